@@ -1,0 +1,83 @@
+"""Localized RI triple coefficients (oracle; test infrastructure).
+
+Sec. II C of the paper:
+* Eqs. expan_coeff_FT1/2: C~_{i(0),j(k)} = sum_R exp(i k.R) C~_{i(0),j(R)}.
+* Eq. AO_triple_split2: the AO triple coefficient of the Bloch product
+  phi_i^{k1*} phi_j^{k2} (k1 = k+q, k2 = k in the paper) is
+      C~^mu_{ij}(k1,k2) = [mu on atom(i)] C~^mu_{i(0),j(k2)}
+                        + [mu on atom(j)] C~^mu_{j(0),i(-k1)}.
+  (The earlier Eq. AO_triple_split has the atom labels of the two sectors
+  interchanged; the split2 form is the one that follows from Eq. local_ri_FT.)
+* Eq. AO_MO_transform: C^mu_{mn}(k1,k2) = sum_ij c*_{im}(k1) c_{jn}(k2) C~^mu_{ij}(k1,k2).
+
+Here the stored real-space block of atom A, L_A(R)[mu][a][b], is the
+coefficient C~^{mu(0)}_{a(0), b(R)} with mu and a on atom A.
+
+The dense AO triple tensor is formed explicitly (N_aux x N_b x N_b per Bloch
+pair), exactly as the equation reads.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def lri_bloch(lri_blocks, R, kfrac):
+    """Eqs. expan_coeff_FT1/2 for every atom block.
+
+    lri_blocks: list over atoms of [nR][naux_A][nb_A][N_b] float64.
+    R: [nR][3] integer lattice coordinates.  kfrac: [nk][3] fractional k.
+    Returns list over atoms of [nk][naux_A][nb_A][N_b] complex128.
+    """
+    phase = np.exp(2j * np.pi * (np.asarray(kfrac, dtype=np.float64) @ np.asarray(R, dtype=np.float64).T))
+    out = []
+    for blk in lri_blocks:
+        nR = blk.shape[0]
+        flat = blk.reshape(nR, -1)
+        out.append((phase @ flat).reshape((phase.shape[0],) + blk.shape[1:]))
+    return out
+
+
+def ao_triple(Lk2, Lmk1, basis_off, aux_off, n_b):
+    """Dense C~^mu_{ij}(k1,k2), Eq. AO_triple_split2.
+
+    Lk2[A]  = C~_{a(0),b(k2)}  for atom A, shape [naux_A][nb_A][N_b]
+    Lmk1[A] = C~_{a(0),b(-k1)} for atom A.
+    Returns [N_aux][N_b][N_b] complex128.
+    """
+    n_atoms = len(Lk2)
+    n_aux = int(aux_off[-1])
+    Ct = np.zeros((n_aux, n_b, n_b), dtype=np.complex128)
+    for A in range(n_atoms):
+        mu = slice(int(aux_off[A]), int(aux_off[A + 1]))
+        a = slice(int(basis_off[A]), int(basis_off[A + 1]))
+        # mu on atom(i): i runs over atom A's functions, j over all
+        Ct[mu, a, :] += Lk2[A]
+        # mu on atom(j): j runs over atom A's functions, i over all
+        Ct[mu, :, a] += np.transpose(Lmk1[A], (0, 2, 1))
+    return Ct
+
+
+def mo_triple(Ct, c1, c2):
+    """Eq. AO_MO_transform: C^mu_{mn} = sum_ij c1*_{im} Ct^mu_{ij} c2_{jn}.
+    c1: [N_b][M] orbitals at the first Bloch vector, c2: [N_b][N]."""
+    return np.einsum("im,uij,jn->umn", c1.conj(), Ct, c2, optimize=True)
+
+
+class TripleBuilder:
+    """Forms C^mu_{mn}(k1,k2) for any pair of grid points of one cell."""
+
+    def __init__(self, sysm, kfrac):
+        self.sys = sysm
+        blocks = [sysm.lri_block(A) for A in range(sysm.spec.n_atoms)]
+        self.Lk = lri_bloch(blocks, sysm.R, kfrac)          # at +k
+        self.Lmk = lri_bloch(blocks, sysm.R, -kfrac)        # at -k (own transform)
+
+    def ao(self, k1, k2):
+        s = self.sys
+        return ao_triple([L[k2] for L in self.Lk], [L[k1] for L in self.Lmk],
+                         s.basis_off, s.aux_off, s.spec.n_b)
+
+    def mo(self, k1, k2, rows, cols):
+        """C^mu_{mn}(k1,k2) for bands m in `rows`, n in `cols` (slices/arrays)."""
+        c = self.sys.evec
+        return mo_triple(self.ao(k1, k2), c[k1][:, rows], c[k2][:, cols])

@@ -1,0 +1,84 @@
+"""The whole imaginary-frequency path for one cell (oracle; test
+infrastructure), following the flowchart of Sec. II C with the q loop outer
+for both the response and the self-energy (a reordering of the finite sums):
+
+  for q:  B(k,q) = C(k,k+q) (occ x unocc)       Eqs. AO_triple_split2, AO_MO_transform
+          chi~(q, i w_j)                         Eq. chi0_matrix
+          W^c(q, i w_j)                          Eqs. symm_dielec_func, screened_W_matr
+                                                 (q = 0: Eq. dielectric_func_gamma)
+          x(k,q) = C(k,k-q) (QP bands x all)
+          Sigma^c_n(k, i w_i) += ...             Eq. GW_selfe_element
+  Pade continuation and the QP equation.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import grids, lri, response, screening, selfenergy, continuation
+
+
+class Oracle:
+    def __init__(self, sysm, n_par=16):
+        self.sys = sysm
+        sp = sysm.spec
+        self.kint, self.kfrac = grids.kgrid(sp.nk)
+        self.kpq, self.kmq, self.minus = grids.kq_tables(sp.nk)
+        self.omega, self.weight = grids.frequency_grid(sp.n_freq, sp.x0)
+        self.tb = lri.TripleBuilder(sysm, self.kfrac)
+        self.occ = slice(0, sp.n_occ)
+        self.unocc = slice(sp.n_occ, sp.n_bands)
+        self.qp = slice(sp.qp_lo, sp.qp_lo + sp.n_qp)
+        self.allb = slice(0, sp.n_bands)
+        self.n_par = min(n_par, sp.n_freq)
+
+    # ---- per-q pieces -------------------------------------------------
+    def B(self, q):
+        """C^mu_{ia}(k,k+q): [N_k][N_aux][N_occ][N_unocc]."""
+        return np.stack([self.tb.mo(k, self.kpq[k, q], self.occ, self.unocc)
+                         for k in range(self.sys.n_k)])
+
+    def x(self, q, ks=None):
+        """C^mu_{nm}(k,k-q) for QP bands n and all m: [len(ks)][N_aux][N_qp][N_bands]."""
+        ks = range(self.sys.n_k) if ks is None else ks
+        return np.stack([self.tb.mo(k, self.kmq[k, q], self.qp, self.allb) for k in ks])
+
+    def chi0(self, q, B=None, omega=None):
+        B = self.B(q) if B is None else B
+        om = self.omega if omega is None else omega
+        return response.chi0_trs(B, self.sys.eig, self.kpq, q, self.sys.n_occ, om)
+
+    def wc(self, q, chi=None, B=None, gamma=True):
+        s = self.sys
+        if q == 0 and gamma:
+            B = self.B(0) if B is None else B
+            return screening.screen_gamma(B, s.eig, s.n_occ, s.p, s.omega_cell, s.V[0], self.omega)[2]
+        chi = self.chi0(q, B) if chi is None else chi
+        return screening.screen(chi, s.V[q])[1]
+
+    def sigma_q(self, q, Wc, ks=None):
+        """Contribution of q to Sigma^c for the k points `ks` (default all)."""
+        ks = list(range(self.sys.n_k)) if ks is None else list(ks)
+        xq = self.x(q, ks)
+        X = selfenergy.pair_weights(xq, Wc)
+        kmq = self.kmq[ks]
+        return selfenergy.sigma_c_q(X, self.sys.eig, kmq, q, self.sys.mu, self.omega, self.weight,
+                                    self.sys.n_k), X
+
+    # ---- whole path ---------------------------------------------------
+    def run(self, ks=None, gamma=True, keep=False):
+        s = self.sys
+        ks = list(range(s.n_k)) if ks is None else list(ks)
+        sigma = np.zeros((len(ks), s.spec.n_qp, len(self.omega)), dtype=np.complex128)
+        kept = {}
+        for q in range(s.n_k):
+            B = self.B(q)
+            chi = self.chi0(q, B)
+            Wc = self.wc(q, chi=chi, B=B, gamma=gamma)
+            sq, X = self.sigma_q(q, Wc, ks)
+            sigma += sq
+            if keep:
+                kept[q] = dict(chi=chi, Wc=Wc, X=X, sigma=sq)
+        eps_qp = s.eig[ks][:, self.qp]
+        nodes = grids.pade_nodes(len(self.omega), self.n_par)
+        E, Z, ok = continuation.qp_energies(sigma, self.omega, eps_qp, s.e_static[ks], s.mu, nodes)
+        return dict(sigma=sigma, E=E, Z=Z, converged=ok, per_q=kept, ks=ks)

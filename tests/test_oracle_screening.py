@@ -1,0 +1,80 @@
+"""Screening pins (oracle): spectral bounds, NSD W^c, Cholesky-factor invariance,
+Gamma-point special cases."""
+import numpy as np
+import pytest
+
+from oracle import screening, response, grids
+from synth.systems import make_config
+
+
+def test_spectral_bounds(c1_oracle):
+    s = c1_oracle.sys
+    for q in (1, 4):
+        chi = c1_oracle.result["per_q"][q]["chi"]
+        eps, Wc = screening.screen(chi, s.V[q])
+        for e, w in zip(eps, Wc):
+            le = np.linalg.eigvalsh(e)
+            assert le.min() >= 1.0 - 1e-12
+            li = np.linalg.eigvalsh(np.linalg.inv(e) - np.eye(len(e)))
+            assert li.min() > -1.0 and li.max() <= 1e-12
+            lw = np.linalg.eigvalsh(w)
+            assert lw.max() <= 1e-12 * np.abs(lw).max()
+
+
+def test_pair_weights_real_nonpositive(c1_oracle):
+    X = c1_oracle.result["per_q"][3]["X"]
+    assert np.max(np.abs(X.imag)) <= 1e-13 * np.max(np.abs(X))
+    assert X.real.max() <= 1e-14 * np.max(np.abs(X))
+
+
+def test_cholesky_factor_gives_same_w(c1_oracle):
+    # W^c = L (eps_L^-1 - I) L^H with V = L L^H, eps_L = I - L^H chi L, equals the
+    # square-root form: eps_L = Q^H eps Q with Q = V^-1/2 L unitary.
+    s = c1_oracle.sys
+    q = 3
+    chi = c1_oracle.result["per_q"][q]["chi"]
+    _, Wc = screening.screen(chi, s.V[q])
+    L = np.linalg.cholesky(s.V[q])
+    eye = np.eye(s.n_aux)
+    for iw in (0, 7, 15):
+        eL = eye - L.conj().T @ chi[iw] @ L
+        W2 = L @ (np.linalg.inv(eL) - eye) @ L.conj().T
+        assert np.linalg.norm(W2 - Wc[iw]) <= 1e-12 * np.linalg.norm(Wc[iw])
+
+
+def test_gamma_zero_momentum_reduces_to_projected_regular_form(c1_oracle):
+    s = c1_oracle.sys
+    o = c1_oracle
+    B0 = o.B(0)
+    p0 = np.zeros_like(s.p)
+    eps_l, eps_mu, Wc = screening.screen_gamma(B0, s.eig, s.n_occ, p0, s.omega_cell, s.V[0], o.omega)
+    v, X = screening.coulomb_eigenbasis(s.V[0])
+    chi = o.chi0(0, B0)
+    Vh = screening.sqrt_hpd(s.V[0])
+    for iw in (0, 5):
+        assert abs(eps_l[iw][0, 0] - 1.0) < 1e-15
+        assert np.max(np.abs(eps_l[iw][0, 1:])) < 1e-15
+        reg = np.eye(s.n_aux) - Vh @ chi[iw] @ Vh
+        reg_l = X.conj().T @ reg @ X
+        assert np.max(np.abs(reg_l[1:, 1:] - eps_l[iw][1:, 1:])) < 1e-11 * np.max(np.abs(reg_l))
+
+
+def test_gamma_single_aux_closed_form():
+    # N_aux = 1: eps = 1 + s/N_k sum_k sum_ia 2D/(D^2+w^2) (4 pi/Omega) |p/D|^2
+    rng = np.random.default_rng(2)
+    nk, no, nu = 3, 2, 3
+    eig = np.sort(np.concatenate([rng.uniform(-0.8, -0.1, (nk, no)), rng.uniform(0.1, 1.5, (nk, nu))], axis=1), axis=1)
+    p = rng.standard_normal((nk, no, nu)) + 1j * rng.standard_normal((nk, no, nu))
+    B0 = rng.standard_normal((nk, 1, no, nu)) + 0j
+    om = np.array([0.1, 1.0, 4.0])
+    Om = 270.0
+    v = 3.7
+    eps_l, eps_mu, Wc = screening.screen_gamma(B0, eig, no, p, Om, np.array([[v + 0j]]), om)
+    for iw, w in enumerate(om):
+        tot = 0.0
+        for k in range(nk):
+            d = eig[k, no:][None, :] - eig[k, :no][:, None]
+            tot += np.sum(2 * d / (d * d + w * w) * (4 * np.pi / Om) * np.abs(p[k] / d) ** 2)
+        e = 1 + 2.0 / nk * tot
+        assert abs(eps_l[iw][0, 0] - e) < 1e-13
+        assert abs(Wc[iw][0, 0] - v * (1 / e - 1)) < 1e-13
