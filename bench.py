@@ -1,0 +1,220 @@
+"""Throughput of the imaginary-frequency LRI-G0W0 path on one MI355X.
+
+One step = the whole path over the Si-like 2-atom cell (N_b = 78, N_aux = 260,
+6x6x6 k grid, 4 occupied bands, 32 frequencies): LRI Bloch/half transform,
+then for every q the response build, chi0, screening to W^c and the Sigma^c
+contribution of every (k, QP band), then Pade + QP.  value = (q, w) pairs per
+second = N_q * N_w * steps / seconds.
+
+Prints one JSON line.  The FP64 oracle is timed on a bounded sample on the
+host cores (cpu_baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0}
+HA_MEV = 27211.386
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "split_bf16"])
+    ap.add_argument("--no-plain", action="store_true", help="skip timing the plain FP64 path")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--n-par", type=int, default=16)
+    return ap.parse_args()
+
+
+class Run:
+    """All device state of one precision form on one cell."""
+
+    def __init__(self, L, sysm, dev, precision, n_par):
+        import torch
+        self.torch = torch
+        self.sysm, self.dev, self.n_par = sysm, dev, n_par
+        self.ctx = L.Context.from_system(sysm, precision=precision)
+        sp = sysm.spec
+        self.H = self.ctx.empty("H")
+        self.sigma = torch.zeros((sysm.n_k, sp.n_qp, sp.n_freq), dtype=torch.complex128, device="cuda")
+        self.e_qp = torch.zeros((sysm.n_k, sp.n_qp), dtype=torch.float64, device="cuda")
+        self.z = torch.zeros_like(self.e_qp)
+
+    def step(self):
+        s, d = self.sysm, self.dev
+        self.ctx.lri_ft(d["lri"], s.R, d["evec"], self.H)
+        return self.ctx.g0w0(self.H, d["evec"], d["eig"], d["V"], d["p"], s.omega_cell, d["e_static"], self.n_par,
+                             self.sigma, self.e_qp, self.z)
+
+    def timed(self, steps, warmup):
+        torch = self.torch
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        self.ctx.reset_timing()
+        self.ctx.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            self.step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        stages = {}
+        for name in ("lri_ft", "build_M", "chi0", "chi0_mfma", "screen", "sigma_c", "sigma_mfma", "qp"):
+            ms, n = self.ctx.stage_ms(name)
+            if n:
+                stages[name] = (ms, n)
+        self.ctx.set_timing(False)
+        return dt, stages
+
+
+def roofline(sysm, stages, precision):
+    """Dominant MFMA kernel: algorithmic flops per launch / average launch time."""
+    sp = sysm.spec
+    n_aux, n_k, nw = sysm.n_aux, sysm.n_k, sp.n_freq
+    K = n_k * sp.n_occ * (sp.n_bands - sp.n_occ)
+    flops = {
+        # chi0: 8 N_aux^2 K real flops per (q, w) pair (full Hermitian count), one launch = one q, all w
+        "chi0_mfma": 8.0 * n_aux * n_aux * K * nw,
+        # Sigma^c: 8 N_aux^2 N_k N_qp N_bands per pair, one launch = one q, all w
+        "sigma_mfma": 8.0 * n_aux * n_aux * n_k * sp.n_qp * sp.n_bands * nw,
+    }
+    best = None
+    for name, f in flops.items():
+        if name not in stages:
+            continue
+        ms, n = stages[name]
+        if best is None or ms > best[1]:
+            best = (name, ms, n, f)
+    name, ms, n, f = best
+    avg_s = ms / n / 1e3
+    achieved = f / avg_s / 1e12
+    peak = PEAK_TFLOPS[precision]
+    return {"bound": "mfma", "kernel": name, "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": None, "avg_launch_ms": round(ms / n, 4),
+            "flops_per_launch": f}
+
+
+def cpu_baseline(sysm):
+    """FP64 oracle on a bounded sample of the same workload: q = 1, 4 of the
+    frequencies, 27 of the k points for the k sums; every k-dependent cost is
+    scaled by N_k / 27, B/x construction is amortised over all N_w frequencies."""
+    from oracle.pipeline import Oracle
+    from oracle import response, screening, selfenergy
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    o = Oracle(sysm)
+    s = sysm
+    q = 1
+    ks = list(range(0, s.n_k, max(1, s.n_k // 27)))[:27]
+    scale = s.n_k / len(ks)
+    wsel = np.array([0, 10, 20, 31]) if s.spec.n_freq > 31 else np.arange(min(4, s.spec.n_freq))
+    om = o.omega[wsel]
+    t0 = time.perf_counter()
+    B = np.stack([o.tb.mo(k, o.kpq[k, q], o.occ, o.unocc) for k in ks])
+    t_b = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    # chi0 restricted to the sampled k (the k sum scales linearly)
+    n_aux = s.n_aux
+    chi = np.zeros((len(om), n_aux, n_aux), dtype=np.complex128)
+    for j, k in enumerate(ks):
+        d = (s.eig[o.kpq[k, q]][s.n_occ:][None, :] - s.eig[k][:s.n_occ][:, None]).reshape(-1)
+        Bk = B[j].reshape(n_aux, -1)
+        for iw, w in enumerate(om):
+            chi[iw] += (Bk * (2 * d / (d * d + w * w))[None, :]) @ Bk.conj().T
+    chi *= -2.0 / s.n_k
+    t_chi = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, Wc = screening.screen(chi, s.V[q])
+    t_scr = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    x = o.x(q, ks)
+    t_x = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    X = selfenergy.pair_weights(x, Wc)
+    t_X = time.perf_counter() - t0
+    nw_all = s.spec.n_freq
+    per_pair = scale * (t_b + t_x) / nw_all + scale * (t_chi + t_X) / len(om) + t_scr / len(om)
+    total = t_b + t_chi + t_scr + t_x + t_X
+    return {"value": round(1.0 / per_pair, 4), "unit": "(q,w)-pairs/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"q=1, {len(om)} of {nw_all} frequencies, {len(ks)} of {s.n_k} k points (k sums scaled by "
+                      f"{scale:.0f}, B/x build amortised over {nw_all} frequencies); {total:.1f} s of CPU work"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in DESIGN.md",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_2011_01400_amd import lrigw as L
+    from synth.systems import make_config
+    L.load()
+    sysm = make_config(args.config)
+    dev = L.device_inputs(sysm)
+    sp = sysm.spec
+    pairs = sysm.n_k * sp.n_freq
+
+    run = Run(L, sysm, dev, args.precision, args.n_par)
+    print(f"# bench: config {args.config} precision {args.precision}: warmup {args.warmup}, steps {args.steps}",
+          file=sys.stderr, flush=True)
+    dt, stages = run.timed(args.steps, args.warmup)
+    value = pairs * args.steps / dt
+    e_form = run.e_qp.cpu().numpy()
+    print(f"# bench: {value:.1f} pairs/s, {dt / args.steps * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+
+    plain = None
+    if not args.no_plain and args.precision != "fp64":
+        prun = Run(L, sysm, dev, "fp64", args.n_par)
+        pdt, pstages = prun.timed(1, 1)
+        e_plain = prun.e_qp.cpu().numpy()
+        plain = {"value": round(pairs / pdt, 2), "ms_per_step": round(pdt * 1e3, 2),
+                 "qp_max_err_mev_vs_plain": float(np.max(np.abs(e_form - e_plain)) * HA_MEV),
+                 "roofline": roofline(sysm, pstages, "fp64")}
+        print(f"# bench: plain fp64 {plain['value']} pairs/s, QP diff {plain['qp_max_err_mev_vs_plain']:.3e} meV",
+              file=sys.stderr, flush=True)
+        prun.ctx.close()
+        del prun
+
+    rl = roofline(sysm, stages, args.precision)
+    out = {
+        "metric": "chi0+Sigma^c (q,w)-pairs/s", "value": round(value, 2), "unit": "(q,w)-pairs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16x3"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"Si-like 2-atom cell (config {args.config}): N_b={sysm.n_b}, N_aux={sysm.n_aux}, "
+                               f"k grid {'x'.join(map(str, sp.nk))}, N_occ={sp.n_occ}, {sp.n_bands} bands, "
+                               f"{sp.n_freq} modified Gauss-Legendre frequencies, QP bands {sp.qp_lo}..{sp.qp_lo + sp.n_qp - 1}",
+                   "precision_form": args.precision, "pairs_per_step": pairs},
+        "stages_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stages.items()},
+        "roofline": rl,
+    }
+    if plain:
+        out["plain_fp64"] = plain
+        out["speedup_vs_plain"] = round(value / plain["value"], 3)
+    if not args.no_cpu:
+        print("# bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(sysm)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

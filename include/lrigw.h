@@ -1,0 +1,201 @@
+/*
+ * lrigw — imaginary-frequency G0W0 screening and self-energy with localized
+ * resolution of the identity (LRI) in a numerical-atomic-orbital basis, on
+ * AMD MI355X (gfx950).
+ *
+ * Method: Ren, Merz, Jiang, Yao, Rampp, Lederer, Blum, Scheffler,
+ * "All-electron periodic G0W0 implementation with numerical atomic orbital
+ * basis functions: algorithm and benchmarks", arXiv:2011.01400.  Section and
+ * equation labels below refer to that paper.
+ *
+ * Conventions for every entry point
+ *  - All array pointers are DEVICE pointers owned by the caller unless marked
+ *    "host".  The library never frees caller memory.  Arrays are row-major;
+ *    complex numbers are interleaved (re, im) as in std::complex / torch.
+ *  - "complex T" means complex128 (two doubles) when the context precision is
+ *    LRIGW_FP64 and complex64 (two floats) for LRIGW_FP32 and
+ *    LRIGW_SPLIT_BF16.  Eigenvalues, eigenvectors, Coulomb matrices, grids,
+ *    Sigma^c and QP energies are always FP64.
+ *  - Calls are asynchronous on the stream given to lrigw_create; outputs are
+ *    valid after that stream is synchronised.  Host "info" outputs are written
+ *    before the call returns (the call synchronises the stream for them).
+ *  - Energies are in Hartree.  Spin-restricted closed shell (spin factor 2).
+ *  - Return value: LRIGW_OK (0), a negative error code, or a positive warning.
+ *    Argument checks happen before any work is queued; no C++ exception
+ *    crosses this interface.
+ *
+ * Index conventions
+ *  - k grid: Gamma-centred n1 x n2 x n3 grid, point (i1,i2,i3) has fractional
+ *    coordinates i_d/n_d and index (i1*n2 + i2)*n3 + i3; the q grid is the k
+ *    grid; weights 1/N_k (Sec. II A).
+ *  - Orbital basis functions are grouped by atom (basis_off), auxiliary
+ *    functions likewise (aux_off).
+ */
+#ifndef LRIGW_H
+#define LRIGW_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LRIGW_OK 0
+#define LRIGW_ERR_ARG (-1)         /* bad argument (sizes, NULL, ordering) */
+#define LRIGW_ERR_OOM (-2)         /* device allocation failed */
+#define LRIGW_ERR_HIP (-3)         /* HIP runtime error */
+#define LRIGW_ERR_NOT_HPD (-4)     /* a matrix that must be Hermitian positive definite is not */
+#define LRIGW_ERR_NOCONV (-5)      /* an iteration did not converge */
+#define LRIGW_WARN_QP_NOCONV 1     /* some QP equations had no root (E = e + e_static returned) */
+#define LRIGW_WARN_PADE_TRUNC 2    /* some Pade fits were truncated at a zero coefficient */
+
+enum lrigw_precision {
+  LRIGW_FP64 = 0,        /* every contraction in FP64 (the plain path) */
+  LRIGW_FP32 = 1,        /* M, chi0 and Sigma^c contractions in FP32 on MFMA, FP32 accumulate */
+  LRIGW_SPLIT_BF16 = 2   /* chi0 and Sigma^c as hi/lo BF16 products on MFMA, FP32 accumulate */
+};
+
+typedef struct {
+  int n_atoms;
+  const int *basis_off;  /* host [n_atoms+1]: orbital basis functions of atom A are basis_off[A]..basis_off[A+1]-1 */
+  const int *aux_off;    /* host [n_atoms+1]: auxiliary functions of atom A likewise */
+  int nk[3];             /* Gamma-centred grid; q grid == k grid */
+  int n_bands;           /* bands kept (columns of the eigenvector matrices) */
+  int n_occ;             /* occupied bands (T = 0, insulator) */
+  int n_freq;            /* imaginary frequencies of the modified Gauss-Legendre grid */
+  double x0;             /* grid scale: omega = x0 (1+t)/(1-t) (Ha) */
+  double mu;             /* chemical potential, inside the gap (Ha) */
+  int qp_lo, n_qp;       /* bands qp_lo..qp_lo+n_qp-1 get Sigma^c and QP energies */
+} lrigw_system;
+
+typedef struct lrigw_ctx lrigw_ctx;
+
+/* Create a context for one cell.  `sys` is copied.  `hip_stream` is a
+ * hipStream_t (NULL = default stream).  Allocates the per-q workspaces.
+ * Errors: ERR_ARG (inconsistent sizes: n_occ < 1, n_occ >= n_bands, qp range
+ * outside the bands, offsets not increasing), ERR_OOM, ERR_HIP. */
+int lrigw_create(lrigw_ctx **out, const lrigw_system *sys, int precision, void *hip_stream);
+int lrigw_destroy(lrigw_ctx *ctx);
+const char *lrigw_strerror(int code);
+
+/* Sizes (in elements) of the caller buffers of the calls below. */
+typedef struct {
+  long long n_k, n_b, n_aux, n_bands, n_freq, nb_max;
+  long long h_elems;      /* lrigw_lri_ft output: N_k * nb_max * n_bands * N_aux complex T */
+  long long m_chi_elems;  /* lrigw_build_M slice 0: N_k * n_occ * (n_bands-n_occ) * N_aux complex T */
+  long long m_sig_elems;  /* lrigw_build_M slice 1: N_k * n_qp * n_bands * N_aux complex T */
+  long long w_elems;      /* chi0 / W^c of one q: n_freq * N_aux * N_aux complex T */
+  long long sigma_elems;  /* Sigma^c: N_k * n_qp * n_freq complex128 */
+} lrigw_sizes;
+int lrigw_get_sizes(const lrigw_ctx *ctx, lrigw_sizes *out /* host */);
+
+/* Grids (Sec. II A; modified Gauss-Legendre frequencies): omega[n_freq] and
+ * weight[n_freq] (FP64, ascending omega) from Gauss-Legendre nodes computed on
+ * the device; kpq[N_k*N_k] and kmq[N_k*N_k] (int32): index of k+q and k-q.
+ * Any output pointer may be NULL.  The context keeps its own copies. */
+int lrigw_grids(lrigw_ctx *ctx, double *omega, double *weight, int *kpq, int *kmq);
+
+/* LRI Bloch transform and half-transform (Sec. II C, Eqs. expan_coeff_FT1/2).
+ *   lri_R: FP64, concatenation over atoms A of [nR][naux_A][nb_A][N_b]:
+ *          C~^{mu(0)}_{a(0), b(R)} with mu and a on atom A (the real-space
+ *          two-centre coefficients; real because the basis functions are).
+ *   R_list: host int [nR][3], lattice coordinates of R.
+ *   evec: complex128 [N_k][N_b][n_bands], KS eigenvectors c_{i n}(k).
+ *   H_out: complex T [N_k][nb_max][n_bands][N_aux]:
+ *          H[k][a][n][mu] = sum_j C~^{mu(0)}_{a(0), j(k)} c_{j n}(k), a the
+ *          a-th function of atom(mu) (rows a >= nb_A of that atom are zero).
+ * Errors: ERR_ARG (nR < 1, NULL), ERR_OOM (temporary for the transform). */
+int lrigw_lri_ft(lrigw_ctx *ctx, const double *lri_R, const int *R_list, int nR, const void *evec, void *H_out);
+
+/* MO triple coefficients (Eqs. AO_triple_split2 and AO_MO_transform) with the
+ * Bloch pair (k, k2), mu on P^{(k-k2)*}:
+ *   C^mu_{rc}(k,k2) = sum_{a on atom(mu)} conj(c_{a r}(k)) H[k2][a][c][mu]
+ *                                      + conj(H[k][a][r][mu]) c_{a c}(k2)
+ * (the second sector uses C~(-k) = conj C~(k), true for real coefficients).
+ *   slice 0 (response):    k2 = k+q, r over occupied, c over unoccupied bands:
+ *       M_out complex T [N_k][n_occ][n_bands-n_occ][N_aux]  (B^mu_ia(k,q))
+ *   slice 1 (self-energy): k2 = k-q, r over the QP bands, c over all bands:
+ *       M_out complex T [N_k][n_qp][n_bands][N_aux]  (C^mu_{nm}(k,k-q))
+ * Errors: ERR_ARG (iq out of range, bad slice, NULL). */
+int lrigw_build_M(lrigw_ctx *ctx, int iq, int slice, const void *H, const void *evec, void *M_out);
+
+/* Independent-particle response, Eq. chi0_matrix (occupation difference
+ * restored, paired with V(q) as the Dyson equation requires; time-reversal
+ * symmetric inputs):
+ *   chi_out[w][mu][nu] = -(2/N_k) sum_{k,i,a} 2D/(D^2 + w^2) B^mu_ia conj(B^nu_ia),
+ *   D = e_a(k+q) - e_i(k),   for every grid frequency w.
+ * M: slice-0 output of lrigw_build_M for this iq.  eig: FP64 [N_k][n_bands].
+ * apply_gamma (iq == 0 only, after lrigw_gamma_prepare): replace, in every
+ * B_ia, the component along the G=0-like eigenvector X_1 of V^cut(0) by the
+ * q->0 limit sqrt(4 pi/Omega) (p_ia.q_hat)/D / sqrt(v_1) (Sec. III B, Eq.
+ * dielectric_func_gamma as a Gram form); the result, screened with V^cut(0),
+ * gives W^cut(0).
+ * chi_out: complex T [n_freq][N_aux][N_aux], Hermitian.
+ * Errors: ERR_ARG (D <= 0: an unoccupied level below an occupied one,
+ * apply_gamma without preparation or with iq != 0). */
+int lrigw_chi0(lrigw_ctx *ctx, int iq, const void *M, const double *eig, int apply_gamma, void *chi_out);
+
+/* q = 0 preparation (Sec. III B): dominant eigenpair (X_1, v_1) of the
+ * truncated Coulomb matrix Vcut0 (complex128 [N_aux][N_aux], Hermitian PD),
+ * by power iteration on the device, X_1 scaled so its largest-magnitude
+ * component is real positive; p: complex128 [N_k][n_occ][n_bands-n_occ],
+ * momentum elements p_ia(k).q_hat; omega_cell: cell volume (bohr^3).
+ * The context keeps X_1, v_1 and the pointer p (which must stay valid).
+ * Errors: ERR_NOCONV (no dominant eigenvalue within 5000 iterations). */
+int lrigw_gamma_prepare(lrigw_ctx *ctx, const void *Vcut0, const void *p, double omega_cell);
+
+/* Screening (Eqs. symm_dielec_func and screened_W_matr), correlation part:
+ *   W^c = V^{1/2} (eps~^{-1} - I) V^{1/2},  eps~ = I - V^{1/2} chi V^{1/2},
+ * computed with the Cholesky factor V = L L^H in place of V^{1/2} (W is
+ * unchanged by that substitution) and eps~^{-1} - I = -eps~^{-1}(eps~ - I)
+ * (no cancellation at weak screening), all in FP64.
+ * chi: complex T [n_freq][N_aux][N_aux] (lrigw_chi0 output); V: complex128
+ * [N_aux][N_aux] (V(q), or V^cut(0) at iq == 0).  Wc_out: complex T, same
+ * shape as chi.  info (host, may be NULL): -1, or the first frequency index
+ * whose eps~ was not positive definite, or -2 if V was not.
+ * Errors: ERR_NOT_HPD. */
+int lrigw_screen(lrigw_ctx *ctx, int iq, const void *chi, const void *V, void *Wc_out, int *info);
+
+/* Correlation self-energy, Eq. GW_selfe_element with W -> W^c and w_q = 1/N_q,
+ * folded onto w' > 0 (W^c is even in w'):
+ *   sigma_acc[k][n][i] += -1/(pi N_q) sum_m sum_j g_j X_nm(k,q,w_j) a/(a^2 + w_j^2),
+ *   a = i w_i + mu - e_m(k-q),  X_nm = sum_{mu nu} x^mu_nm W^c_{mu nu}(w_j) conj(x^nu_nm).
+ * x: slice-1 output of lrigw_build_M for this iq; Wc: lrigw_screen output;
+ * eig: FP64 [N_k][n_bands]; sigma_acc: complex128 [N_k][n_qp][n_freq],
+ * accumulated (zero it before the first q). */
+int lrigw_sigma_c(lrigw_ctx *ctx, int iq, const void *x, const void *Wc, const double *eig, void *sigma_acc);
+
+/* Pade continuation (Thiele continued fraction through n_par grid points
+ * j*(n_freq-1)/(n_par-1) rounded half up) and the quasiparticle equation
+ *   E = e_n + e_static_n + Re P_n(E - mu),  Z = 1/(1 - Re P_n'(E - mu)),
+ * Newton from e_n + e_static_n (|dE| < 1e-10 Ha, <= 50 steps), else the sign
+ * change of the residual nearest to the start within +-1 Ha (1 mHa scan) by
+ * bisection.  sigma: complex128 [N_k][n_qp][n_freq]; eps_qp: FP64
+ * [N_k][n_qp]; e_static: FP64 [N_k][n_qp] or NULL (zero).  e_qp, z: FP64
+ * [N_k][n_qp] outputs.  info (host, may be NULL): number of (k,n) without a
+ * root.  Returns WARN_QP_NOCONV / WARN_PADE_TRUNC when they occur. */
+int lrigw_qp(lrigw_ctx *ctx, const void *sigma, const double *eps_qp, const double *e_static, int n_par,
+             double *e_qp, double *z, int *info);
+
+/* Whole path for one cell, q loop inside the library:
+ *   for q: build_M(0), chi0 (gamma at q = 0 when p != NULL), screen (V[q]; V[0]
+ *   is V^cut(0)), build_M(1), sigma_c;  then qp.
+ * V: complex128 [N_k][N_aux][N_aux]; p: complex128 [N_k][n_occ][n_unocc] or
+ * NULL (no q = 0 head/wings); H: lrigw_lri_ft output.  sigma: complex128
+ * [N_k][n_qp][n_freq] output; e_qp, z: FP64 [N_k][n_qp].  q_first..q_last-1
+ * restricts the q loop (0, N_k for all; QP only when all q were done).
+ * The buffers for M, chi0 and W^c are owned by the context. */
+int lrigw_g0w0(lrigw_ctx *ctx, const void *H, const void *evec, const double *eig, const void *V, const void *p,
+               double omega_cell, const double *e_static, int n_par, int q_first, int q_last,
+               void *sigma, double *e_qp, double *z, int *info);
+
+/* Per-kernel device time (ms, HIP events on the context stream) accumulated
+ * since the last reset, for the named stages "build_M", "chi0", "screen",
+ * "sigma_c", "qp", "lri_ft".  Timing is recorded only after
+ * lrigw_set_timing(ctx, 1).  Returns -1.0 for an unknown stage. */
+int lrigw_set_timing(lrigw_ctx *ctx, int on);
+double lrigw_stage_ms(lrigw_ctx *ctx, const char *stage, long long *launches);
+void lrigw_reset_timing(lrigw_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LRIGW_H */

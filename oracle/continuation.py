@@ -20,10 +20,14 @@ finite; the fraction is then truncated there.
 Quasiparticle equation (variable z = E - mu, as Sigma^c(i w) was defined with
 i w + mu in its denominators):
   E = e_n + e_static_n + Re P_n(E - mu),   Z = 1 / (1 - Re P_n'(E - mu)).
-Newton from E_0 = e_n + e_static_n, |dE| < 1e-10 Ha, at most 50 steps; if that
-fails, scan E_0 +- 1 Ha in 1 mHa steps for sign changes of
-f(E) = E - e_n - e_static_n - Re P(E - mu), take the bracket whose midpoint is
-closest to E_0 and bisect it to 1e-12 Ha.
+With f(E) = E - e_n - e_static_n - Re P(E - mu): Newton from
+E_0 = e_n + e_static_n, |dE| < 1e-10 Ha, at most 50 steps, abandoned as soon as
+f'(E) <= 0 (a quasiparticle root has f' = 1/Z > 0; f' <= 0 means the step
+crossed a pole of the continued fraction, after which Newton wanders).  Then
+scan E_0 +- 1 Ha in 1 mHa steps for increasing sign changes
+f(E_i) < 0 <= f(E_{i+1}) (a pole of P with positive residue gives a decreasing
+change), take the one whose midpoint is closest to E_0 and bisect it to
+1e-12 Ha.  Z = 1 / f'(E).
 """
 from __future__ import annotations
 
@@ -84,19 +88,21 @@ def solve_qp(e0, e_static, mu, z_nodes, a):
     E = target
     for _ in range(50):
         fv, fd = f(E)
-        if not (np.isfinite(fv) and np.isfinite(fd)) or fd == 0.0:
+        if not (np.isfinite(fv) and np.isfinite(fd)) or fd <= 0.0:
             break
         dE = fv / fd
         E = E - dE
         if abs(dE) < 1e-10:
             fv, fd = f(E)
-            return E, 1.0 / fd, True
-    # bracket scan
+            if fd > 0.0:
+                return E, 1.0 / fd, True
+            break
+    # bracket scan: increasing sign changes only
     grid = target + np.arange(-1000, 1001) * 1e-3
     vals = np.array([f(x)[0] for x in grid])
     best = None
     for i in range(len(grid) - 1):
-        if np.isfinite(vals[i]) and np.isfinite(vals[i + 1]) and vals[i] * vals[i + 1] <= 0.0:
+        if np.isfinite(vals[i]) and np.isfinite(vals[i + 1]) and vals[i] < 0.0 <= vals[i + 1]:
             mid = 0.5 * (grid[i] + grid[i + 1])
             if best is None or abs(mid - target) < abs(best[0] - target):
                 best = (mid, i)
@@ -104,16 +110,15 @@ def solve_qp(e0, e_static, mu, z_nodes, a):
         fv, fd = f(target)
         return target, 1.0 / fd, False
     lo, hi = grid[best[1]], grid[best[1] + 1]
-    flo = vals[best[1]]
     for _ in range(200):
         if hi - lo < 1e-12:
             break
         mid = 0.5 * (lo + hi)
         fm = f(mid)[0]
-        if flo * fm <= 0.0:
+        if fm >= 0.0:
             hi = mid
         else:
-            lo, flo = mid, fm
+            lo = mid
     E = 0.5 * (lo + hi)
     return E, 1.0 / f(E)[1], True
 

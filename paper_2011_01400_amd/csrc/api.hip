@@ -1,0 +1,308 @@
+// C interface of the lrigw library: context, validation, driver, timing.
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "lrigw_internal.h"
+
+int lrigw_hip_error(hipError_t e, const char *what, const char *file, int line) {
+  if (getenv("LRIGW_VERBOSE")) fprintf(stderr, "lrigw: %s failed: %s (%s:%d)\n", what, hipGetErrorString(e), file, line);
+  return e == hipErrorOutOfMemory ? LRIGW_ERR_OOM : LRIGW_ERR_HIP;
+}
+
+int lrigw_launch_check(const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return lrigw_hip_error(e, what, __FILE__, __LINE__);
+  return LRIGW_OK;
+}
+
+size_t lrigw_csize(const lrigw_ctx *c) { return c->precision == LRIGW_FP64 ? sizeof(double2) : sizeof(float2); }
+long long lrigw_K(const lrigw_ctx *c) { return (long long)c->d.n_k * c->d.n_occ * c->d.n_unocc; }
+
+void stage_begin(lrigw_ctx *c, const char *name, hipEvent_t *ev) {
+  *ev = nullptr;
+  if (!c->timing) return;
+  if (hipEventCreate(ev) != hipSuccess) { *ev = nullptr; return; }
+  hipEventRecord(*ev, c->stream);
+  (void)name;
+}
+
+void stage_end(lrigw_ctx *c, const char *name, hipEvent_t ev) {
+  if (!c->timing || !ev) return;
+  hipEvent_t e1;
+  if (hipEventCreate(&e1) != hipSuccess) return;
+  hipEventRecord(e1, c->stream);
+  StageTimer &t = c->stages[name];
+  t.pending.push_back({ev, e1});
+  t.launches += 1;
+}
+
+static void free_all(lrigw_ctx *c) {
+  void *ptrs[] = {c->d_aux_atom, c->d_basis_off, c->d_aux_off, c->d_kpq, c->d_kmq, c->d_omega, c->d_weight,
+                  c->d_delta, c->d_part, c->d_X, c->d_LV, c->d_s0, c->d_s1, c->d_s2, c->d_s3, c->d_info,
+                  c->d_bhat, c->d_x1, c->d_M, c->d_x, c->d_chi, c->d_wc};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  for (auto &kv : c->stages)
+    for (auto &pr : kv.second.pending) {
+      hipEventDestroy(pr.first);
+      hipEventDestroy(pr.second);
+    }
+}
+
+extern "C" {
+
+const char *lrigw_strerror(int code) {
+  switch (code) {
+    case LRIGW_OK: return "ok";
+    case LRIGW_ERR_ARG: return "invalid argument";
+    case LRIGW_ERR_OOM: return "device out of memory";
+    case LRIGW_ERR_HIP: return "HIP runtime error";
+    case LRIGW_ERR_NOT_HPD: return "matrix not Hermitian positive definite";
+    case LRIGW_ERR_NOCONV: return "iteration did not converge";
+    case LRIGW_WARN_QP_NOCONV: return "warning: some quasiparticle equations had no root";
+    case LRIGW_WARN_PADE_TRUNC: return "warning: some Pade fits were truncated";
+    default: return "unknown status";
+  }
+}
+
+int lrigw_create(lrigw_ctx **out, const lrigw_system *sys, int precision, void *hip_stream) {
+  (void)hipGetLastError();  // drop a stale error another library left behind
+  if (!out || !sys || !sys->basis_off || !sys->aux_off) return LRIGW_ERR_ARG;
+  *out = nullptr;
+  if (precision < LRIGW_FP64 || precision > LRIGW_SPLIT_BF16) return LRIGW_ERR_ARG;
+  if (sys->n_atoms < 1 || sys->nk[0] < 1 || sys->nk[1] < 1 || sys->nk[2] < 1) return LRIGW_ERR_ARG;
+  if (sys->basis_off[0] != 0 || sys->aux_off[0] != 0) return LRIGW_ERR_ARG;
+  int nb_max = 0;
+  for (int a = 0; a < sys->n_atoms; ++a) {
+    int nb = sys->basis_off[a + 1] - sys->basis_off[a];
+    int na = sys->aux_off[a + 1] - sys->aux_off[a];
+    if (nb < 1 || na < 1) return LRIGW_ERR_ARG;
+    if (nb > nb_max) nb_max = nb;
+  }
+  int n_b = sys->basis_off[sys->n_atoms];
+  int n_aux = sys->aux_off[sys->n_atoms];
+  if (sys->n_bands < 2 || sys->n_bands > n_b) return LRIGW_ERR_ARG;
+  if (sys->n_occ < 1 || sys->n_occ >= sys->n_bands || sys->n_occ > 64) return LRIGW_ERR_ARG;
+  if (sys->n_freq < 1 || sys->n_freq > 4096 || !(sys->x0 > 0.0)) return LRIGW_ERR_ARG;
+  if (sys->qp_lo < 0 || sys->n_qp < 1 || sys->n_qp > 64 || sys->qp_lo + sys->n_qp > sys->n_bands) return LRIGW_ERR_ARG;
+  long long n_k = (long long)sys->nk[0] * sys->nk[1] * sys->nk[2];
+  if (n_k > 65535) return LRIGW_ERR_ARG;
+
+  lrigw_ctx *c = new (std::nothrow) lrigw_ctx();
+  if (!c) return LRIGW_ERR_OOM;
+  Dims &d = c->d;
+  d.n_atoms = sys->n_atoms;
+  for (int i = 0; i < 3; ++i) d.nk[i] = sys->nk[i];
+  d.n_k = (int)n_k;
+  d.n_b = n_b;
+  d.n_aux = n_aux;
+  d.n_bands = sys->n_bands;
+  d.n_occ = sys->n_occ;
+  d.n_unocc = sys->n_bands - sys->n_occ;
+  d.n_freq = sys->n_freq;
+  d.x0 = sys->x0;
+  d.mu = sys->mu;
+  d.qp_lo = sys->qp_lo;
+  d.n_qp = sys->n_qp;
+  d.nb_max = nb_max;
+  c->precision = precision;
+  c->stream = (hipStream_t)hip_stream;
+  c->basis_off.assign(sys->basis_off, sys->basis_off + d.n_atoms + 1);
+  c->aux_off.assign(sys->aux_off, sys->aux_off + d.n_atoms + 1);
+
+  int rc = run_grids(c);
+  if (rc < 0) {
+    free_all(c);
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return LRIGW_OK;
+}
+
+int lrigw_destroy(lrigw_ctx *c) {
+  if (!c) return LRIGW_ERR_ARG;
+  if (c->stream) hipStreamSynchronize(c->stream);
+  else hipDeviceSynchronize();
+  free_all(c);
+  delete c;
+  return LRIGW_OK;
+}
+
+int lrigw_get_sizes(const lrigw_ctx *c, lrigw_sizes *o) {
+  if (!c || !o) return LRIGW_ERR_ARG;
+  const Dims &d = c->d;
+  o->n_k = d.n_k;
+  o->n_b = d.n_b;
+  o->n_aux = d.n_aux;
+  o->n_bands = d.n_bands;
+  o->n_freq = d.n_freq;
+  o->nb_max = d.nb_max;
+  o->h_elems = (long long)d.n_k * d.nb_max * d.n_bands * d.n_aux;
+  o->m_chi_elems = lrigw_K(c) * d.n_aux;
+  o->m_sig_elems = (long long)d.n_k * d.n_qp * d.n_bands * d.n_aux;
+  o->w_elems = (long long)d.n_freq * d.n_aux * d.n_aux;
+  o->sigma_elems = (long long)d.n_k * d.n_qp * d.n_freq;
+  return LRIGW_OK;
+}
+
+int lrigw_grids(lrigw_ctx *c, double *omega, double *weight, int *kpq, int *kmq) {
+  if (!c) return LRIGW_ERR_ARG;
+  const Dims &d = c->d;
+  size_t kk = (size_t)d.n_k * d.n_k * sizeof(int);
+  if (omega) LRIGW_HIP_TRY(hipMemcpyAsync(omega, c->d_omega, d.n_freq * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (weight) LRIGW_HIP_TRY(hipMemcpyAsync(weight, c->d_weight, d.n_freq * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (kpq) LRIGW_HIP_TRY(hipMemcpyAsync(kpq, c->d_kpq, kk, hipMemcpyDeviceToDevice, c->stream));
+  if (kmq) LRIGW_HIP_TRY(hipMemcpyAsync(kmq, c->d_kmq, kk, hipMemcpyDeviceToDevice, c->stream));
+  return LRIGW_OK;
+}
+
+int lrigw_lri_ft(lrigw_ctx *c, const double *lri_R, const int *R_list, int nR, const void *evec, void *H_out) {
+  (void)hipGetLastError();  // drop a stale error another library left behind
+  if (!c || !lri_R || !R_list || nR < 1 || !evec || !H_out) return LRIGW_ERR_ARG;
+  hipEvent_t ev;
+  stage_begin(c, "lri_ft", &ev);
+  int rc = run_lri_ft(c, lri_R, R_list, nR, evec, H_out);
+  stage_end(c, "lri_ft", ev);
+  return rc;
+}
+
+int lrigw_build_M(lrigw_ctx *c, int iq, int slice, const void *H, const void *evec, void *M_out) {
+  (void)hipGetLastError();  // drop a stale error another library left behind
+  if (!c || !H || !evec || !M_out) return LRIGW_ERR_ARG;
+  if (iq < 0 || iq >= c->d.n_k || (slice != 0 && slice != 1)) return LRIGW_ERR_ARG;
+  hipEvent_t ev;
+  stage_begin(c, "build_M", &ev);
+  int rc = run_build_M(c, iq, slice, H, evec, M_out);
+  stage_end(c, "build_M", ev);
+  return rc;
+}
+
+int lrigw_chi0(lrigw_ctx *c, int iq, const void *M, const double *eig, int apply_gamma, void *chi_out) {
+  (void)hipGetLastError();  // drop a stale error another library left behind
+  if (!c || !M || !eig || !chi_out) return LRIGW_ERR_ARG;
+  if (iq < 0 || iq >= c->d.n_k) return LRIGW_ERR_ARG;
+  if (apply_gamma && (iq != 0 || !c->gamma_ready)) return LRIGW_ERR_ARG;
+  return run_chi0(c, iq, M, eig, apply_gamma, chi_out);
+}
+
+int lrigw_gamma_prepare(lrigw_ctx *c, const void *Vcut0, const void *p, double omega_cell) {
+  (void)hipGetLastError();  // drop a stale error another library left behind
+  if (!c || !Vcut0 || !p || !(omega_cell > 0.0)) return LRIGW_ERR_ARG;
+  return run_gamma_prepare(c, Vcut0, p, omega_cell);
+}
+
+int lrigw_screen(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_out, int *info) {
+  (void)hipGetLastError();  // drop a stale error another library left behind
+  if (!c || !chi || !V || !Wc_out) return LRIGW_ERR_ARG;
+  if (iq < 0 || iq >= c->d.n_k) return LRIGW_ERR_ARG;
+  hipEvent_t ev;
+  stage_begin(c, "screen", &ev);
+  int rc = run_screen(c, iq, chi, V, Wc_out, info);
+  stage_end(c, "screen", ev);
+  return rc;
+}
+
+int lrigw_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const double *eig, void *sigma_acc) {
+  (void)hipGetLastError();  // drop a stale error another library left behind
+  if (!c || !x || !Wc || !eig || !sigma_acc) return LRIGW_ERR_ARG;
+  if (iq < 0 || iq >= c->d.n_k) return LRIGW_ERR_ARG;
+  return run_sigma_c(c, iq, x, Wc, eig, sigma_acc);
+}
+
+int lrigw_qp(lrigw_ctx *c, const void *sigma, const double *eps_qp, const double *e_static, int n_par, double *e_qp,
+             double *z, int *info) {
+  (void)hipGetLastError();
+  if (!c || !sigma || !eps_qp || !e_qp || !z) return LRIGW_ERR_ARG;
+  if (n_par < 1 || n_par > 64) return LRIGW_ERR_ARG;
+  hipEvent_t ev;
+  stage_begin(c, "qp", &ev);
+  int rc = run_qp(c, sigma, eps_qp, e_static, n_par, e_qp, z, info);
+  stage_end(c, "qp", ev);
+  return rc;
+}
+
+int lrigw_g0w0(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *p,
+               double omega_cell, const double *e_static, int n_par, int q_first, int q_last, void *sigma,
+               double *e_qp, double *z, int *info) {
+  if (!c || !H || !evec || !eig || !V || !sigma) return LRIGW_ERR_ARG;
+  const Dims &d = c->d;
+  if (q_first < 0 || q_last > d.n_k || q_first >= q_last) return LRIGW_ERR_ARG;
+  bool all_q = (q_first == 0 && q_last == d.n_k);
+  if (all_q && (!e_qp || !z)) return LRIGW_ERR_ARG;
+  size_t cs = lrigw_csize(c);
+  if (!c->d_M) LRIGW_HIP_TRY(hipMalloc(&c->d_M, (size_t)lrigw_K(c) * d.n_aux * cs));
+  if (!c->d_x) LRIGW_HIP_TRY(hipMalloc(&c->d_x, (size_t)d.n_k * d.n_qp * d.n_bands * d.n_aux * cs));
+  if (!c->d_chi) LRIGW_HIP_TRY(hipMalloc(&c->d_chi, (size_t)d.n_freq * d.n_aux * d.n_aux * cs));
+  if (!c->d_wc) LRIGW_HIP_TRY(hipMalloc(&c->d_wc, (size_t)d.n_freq * d.n_aux * d.n_aux * cs));
+  if (p && q_first == 0) LRIGW_TRY(lrigw_gamma_prepare(c, V, p, omega_cell));
+  LRIGW_TRY(zero_fill(c->stream, sigma, (size_t)d.n_k * d.n_qp * d.n_freq * sizeof(double2)));
+  size_t vstride = (size_t)d.n_aux * d.n_aux;
+  for (int q = q_first; q < q_last; ++q) {
+    LRIGW_TRY(lrigw_build_M(c, q, 0, H, evec, c->d_M));
+    LRIGW_TRY(lrigw_chi0(c, q, c->d_M, eig, (p && q == 0) ? 1 : 0, c->d_chi));
+    int sinfo = -1;
+    int rc = lrigw_screen(c, q, c->d_chi, (const double2 *)V + q * vstride, c->d_wc, &sinfo);
+    if (rc < 0) {
+      if (info) *info = q;
+      return rc;
+    }
+    LRIGW_TRY(lrigw_build_M(c, q, 1, H, evec, c->d_x));
+    LRIGW_TRY(lrigw_sigma_c(c, q, c->d_x, c->d_wc, eig, sigma));
+  }
+  if (!all_q) return LRIGW_OK;
+  // QP energies for the QP bands: eps_qp from eig on the device
+  double *eps_qp = nullptr;
+  LRIGW_HIP_TRY(hipMalloc(&eps_qp, (size_t)d.n_k * d.n_qp * sizeof(double)));
+  LRIGW_HIP_TRY(hipMemcpy2DAsync(eps_qp, d.n_qp * sizeof(double), eig + d.qp_lo, d.n_bands * sizeof(double),
+                                 d.n_qp * sizeof(double), d.n_k, hipMemcpyDeviceToDevice, c->stream));
+  int qinfo = 0;
+  int rc = lrigw_qp(c, sigma, eps_qp, e_static, n_par, e_qp, z, &qinfo);
+  hipStreamSynchronize(c->stream);
+  (void)hipFree(eps_qp);
+  if (info) *info = qinfo;
+  return rc;
+}
+
+int lrigw_set_timing(lrigw_ctx *c, int on) {
+  if (!c) return LRIGW_ERR_ARG;
+  c->timing = on != 0;
+  return LRIGW_OK;
+}
+
+double lrigw_stage_ms(lrigw_ctx *c, const char *stage, long long *launches) {
+  if (!c || !stage) return -1.0;
+  auto it = c->stages.find(stage);
+  if (it == c->stages.end()) {
+    if (launches) *launches = 0;
+    return -1.0;
+  }
+  StageTimer &t = it->second;
+  if (!t.pending.empty()) {
+    hipStreamSynchronize(c->stream);
+    for (auto &pr : t.pending) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) t.ms += ms;
+      hipEventDestroy(pr.first);
+      hipEventDestroy(pr.second);
+    }
+    t.pending.clear();
+  }
+  if (launches) *launches = t.launches;
+  return t.ms;
+}
+
+void lrigw_reset_timing(lrigw_ctx *c) {
+  if (!c) return;
+  hipStreamSynchronize(c->stream);
+  for (auto &kv : c->stages)
+    for (auto &pr : kv.second.pending) {
+      hipEventDestroy(pr.first);
+      hipEventDestroy(pr.second);
+    }
+  c->stages.clear();
+}
+
+}  // extern "C"

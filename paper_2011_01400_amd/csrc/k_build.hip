@@ -1,0 +1,294 @@
+// MO triple coefficients (Eqs. AO_triple_split2 and AO_MO_transform) and the
+// q = 0 head/wing preparation (Sec. III B).
+#include <algorithm>
+#include <cmath>
+
+#include "lrigw_internal.h"
+#include "tiles.h"
+
+// M[k][r][c][mu] = sum_{a on atom(mu)} conj(c_{a,r0+r}(k)) H[k2][a][c0+c][mu] + conj(H[k][a][r0+r][mu]) c_{a,c0+c}(k2)
+// k2 = kmap[k][iq].  One thread per (mu, c); NR >= nr accumulators.
+template <typename T, int NR>
+__global__ __launch_bounds__(256) void k_build_M(const typename c2t<T>::type *__restrict__ H, const double2 *__restrict__ evec,
+                                                 int n_bands, int n_b, int n_aux, int nb_max, const int *__restrict__ aux_atom,
+                                                 const int *__restrict__ basis_off, const int *__restrict__ kmap, int iq,
+                                                 int nk, int r0, int nr, int c0, int nc, typename c2t<T>::type *__restrict__ M) {
+  typedef typename c2t<T>::type C;
+  const int mu = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int ci = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int k = blockIdx.z;
+  if (mu >= n_aux || ci >= nc) return;
+  const int A = aux_atom[mu];
+  const int bo = basis_off[A];
+  const int nbA = basis_off[A + 1] - bo;
+  const int k2 = kmap[k * nk + iq];
+  const int cc = c0 + ci;
+  C acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r].x = acc[r].y = (T)0;
+  for (int a = 0; a < nbA; ++a) {
+    const C h2 = H[(((long long)k2 * nb_max + a) * n_bands + cc) * n_aux + mu];
+    const double2 e2d = evec[((long long)k2 * n_b + bo + a) * n_bands + cc];
+    C e2;
+    e2.x = (T)e2d.x;
+    e2.y = (T)e2d.y;
+    const C *h1row = H + (((long long)k * nb_max + a) * n_bands + r0) * n_aux + mu;
+    const double2 *e1row = evec + ((long long)k * n_b + bo + a) * n_bands + r0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      if (r < nr) {
+        double2 e1d = e1row[r];
+        C e1;
+        e1.x = (T)e1d.x;
+        e1.y = (T)e1d.y;
+        C h1 = h1row[(long long)r * n_aux];
+        acc[r] = cadd(acc[r], cadd(ccmul(e1, h2), ccmul(h1, e2)));
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+    if (r < nr) M[(((long long)k * nr + r) * nc + ci) * n_aux + mu] = acc[r];
+}
+
+template <typename T>
+static void launch_build(lrigw_ctx *c, int iq, int r0, int nr, int c0, int nc, const int *kmap, const void *H,
+                         const void *evec, void *M) {
+  typedef typename c2t<T>::type C;
+  const Dims &d = c->d;
+  dim3 grid((d.n_aux + 63) / 64, (nc + 3) / 4, d.n_k);
+#define BM(NRV)                                                                                                   \
+  hipLaunchKernelGGL((k_build_M<T, NRV>), grid, dim3(256), 0, c->stream, (const C *)H, (const double2 *)evec,     \
+                     d.n_bands, d.n_b, d.n_aux, d.nb_max, c->d_aux_atom, c->d_basis_off, kmap, iq, d.n_k, r0, nr, c0, \
+                     nc, (C *)M)
+  if (nr <= 4) BM(4);
+  else if (nr <= 8) BM(8);
+  else if (nr <= 16) BM(16);
+  else if (nr <= 32) BM(32);
+  else BM(64);
+#undef BM
+}
+
+int run_build_M(lrigw_ctx *c, int iq, int slice, const void *H, const void *evec, void *M_out) {
+  const Dims &d = c->d;
+  int r0, nr, c0, nc;
+  const int *kmap;
+  if (slice == 0) {
+    r0 = 0; nr = d.n_occ; c0 = d.n_occ; nc = d.n_unocc; kmap = c->d_kpq;
+  } else {
+    r0 = d.qp_lo; nr = d.n_qp; c0 = 0; nc = d.n_bands; kmap = c->d_kmq;
+  }
+  if (c->precision == LRIGW_FP64) launch_build<double>(c, iq, r0, nr, c0, nc, kmap, H, evec, M_out);
+  else launch_build<float>(c, iq, r0, nr, c0, nc, kmap, H, evec, M_out);
+  return lrigw_launch_check("build_M");
+}
+
+// ---------------------------------------------------------------- q = 0 preparation
+// Dominant eigenpair of a Hermitian positive definite matrix by power
+// iteration (one workgroup, x and V x in LDS).  Stops when
+// ||V x - lambda x|| <= 1e-13 lambda; status[0] = iterations or -1.
+__global__ __launch_bounds__(1024) void k_power_iter(const double2 *__restrict__ V, int n, int max_it, double2 *__restrict__ x_out,
+                                                     double *__restrict__ lam_out, int *__restrict__ status) {
+  extern __shared__ double2 sm[];
+  double2 *x = sm;
+  double2 *y = sm + n;
+  __shared__ double red[32];
+  __shared__ double bcast[4];
+  __shared__ int istart;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  if (tid == 0) {
+    double best = -1.0;
+    int bi = 0;
+    for (int i = 0; i < n; ++i)
+      if (V[(long long)i * n + i].x > best) { best = V[(long long)i * n + i].x; bi = i; }
+    istart = bi;
+  }
+  __syncthreads();
+  // start from the column of the largest diagonal element
+  for (int i = tid; i < n; i += blockDim.x) x[i] = V[(long long)i * n + istart];
+  __syncthreads();
+  auto block_sum = [&](double v) -> double {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < nw; ++i) s += red[i];
+    __syncthreads();
+    return s;
+  };
+  double nrm = 0.0;
+  for (int i = tid; i < n; i += blockDim.x) nrm += x[i].x * x[i].x + x[i].y * x[i].y;
+  nrm = sqrt(block_sum(nrm));
+  for (int i = tid; i < n; i += blockDim.x) { x[i].x /= nrm; x[i].y /= nrm; }
+  __syncthreads();
+  int it = 0, done = 0;
+  double lam = 0.0;
+  for (it = 1; it <= max_it; ++it) {
+    // y = V x, one wavefront per row
+    for (int i = wv; i < n; i += nw) {
+      double sr = 0.0, si = 0.0;
+      const double2 *row = V + (long long)i * n;
+      for (int j = lane; j < n; j += 64) {
+        double2 v = row[j], xv = x[j];
+        sr += v.x * xv.x - v.y * xv.y;
+        si += v.x * xv.y + v.y * xv.x;
+      }
+      for (int o = 32; o > 0; o >>= 1) { sr += __shfl_xor(sr, o); si += __shfl_xor(si, o); }
+      if (lane == 0) y[i] = mkc(sr, si);
+    }
+    __syncthreads();
+    double l = 0.0;
+    for (int i = tid; i < n; i += blockDim.x) l += x[i].x * y[i].x + x[i].y * y[i].y;  // Re x^H y
+    lam = block_sum(l);
+    double r2 = 0.0, y2 = 0.0;
+    for (int i = tid; i < n; i += blockDim.x) {
+      double dr = y[i].x - lam * x[i].x, di = y[i].y - lam * x[i].y;
+      r2 += dr * dr + di * di;
+      y2 += y[i].x * y[i].x + y[i].y * y[i].y;
+    }
+    r2 = block_sum(r2);
+    y2 = block_sum(y2);
+    double ny = sqrt(y2);
+    for (int i = tid; i < n; i += blockDim.x) { x[i].x = y[i].x / ny; x[i].y = y[i].y / ny; }
+    __syncthreads();
+    if (sqrt(r2) <= 1e-13 * fabs(lam)) { done = 1; break; }
+  }
+  // final Rayleigh quotient with the normalised vector, and the phase convention
+  for (int i = wv; i < n; i += nw) {
+    double sr = 0.0, si = 0.0;
+    const double2 *row = V + (long long)i * n;
+    for (int j = lane; j < n; j += 64) {
+      double2 v = row[j], xv = x[j];
+      sr += v.x * xv.x - v.y * xv.y;
+      si += v.x * xv.y + v.y * xv.x;
+    }
+    for (int o = 32; o > 0; o >>= 1) { sr += __shfl_xor(sr, o); si += __shfl_xor(si, o); }
+    if (lane == 0) y[i] = mkc(sr, si);
+  }
+  __syncthreads();
+  double l = 0.0;
+  for (int i = tid; i < n; i += blockDim.x) l += x[i].x * y[i].x + x[i].y * y[i].y;
+  lam = block_sum(l);
+  if (tid == 0) {
+    double best = -1.0;
+    int bi = 0;
+    for (int i = 0; i < n; ++i) {
+      double m = x[i].x * x[i].x + x[i].y * x[i].y;
+      if (m > best) { best = m; bi = i; }
+    }
+    double a = sqrt(best);
+    bcast[0] = x[bi].x / a;   // e^{i phi} of the largest component
+    bcast[1] = x[bi].y / a;
+  }
+  __syncthreads();
+  const double pr = bcast[0], pi = bcast[1];
+  for (int i = tid; i < n; i += blockDim.x) {
+    double2 v = x[i];
+    x_out[i] = mkc(v.x * pr + v.y * pi, v.y * pr - v.x * pi);  // x * conj(phase)
+  }
+  if (tid == 0) {
+    lam_out[0] = lam;
+    status[0] = done ? it : -1;
+  }
+}
+
+int run_gamma_prepare(lrigw_ctx *c, const void *Vcut0, const void *p, double omega_cell) {
+  const Dims &d = c->d;
+  const int n = d.n_aux;
+  if ((size_t)2 * n * sizeof(double2) > 140 * 1024) return LRIGW_ERR_ARG;
+  double *dlam = nullptr;
+  LRIGW_HIP_TRY(hipFuncSetAttribute((const void *)k_power_iter, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)(2 * n * sizeof(double2))));
+  LRIGW_HIP_TRY(hipMalloc(&dlam, sizeof(double)));
+  hipLaunchKernelGGL(k_power_iter, dim3(1), dim3(1024), 2 * n * sizeof(double2), c->stream, (const double2 *)Vcut0, n, 5000,
+                     c->d_x1, dlam, c->d_info);
+  int rc = lrigw_launch_check("power_iter");
+  double lam = 0.0;
+  int st = -1;
+  if (rc == LRIGW_OK) {
+    hipMemcpyAsync(&lam, dlam, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    hipMemcpyAsync(&st, c->d_info, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) rc = lrigw_hip_error(e, "power_iter sync", __FILE__, __LINE__);
+  }
+  (void)hipFree(dlam);
+  if (rc < 0) return rc;
+  if (st < 0 || !(lam > 0.0)) return LRIGW_ERR_NOCONV;
+  c->v1 = lam;
+  c->gamma_p = p;
+  c->omega_cell = omega_cell;
+  if (!c->d_bhat) LRIGW_HIP_TRY(hipMalloc(&c->d_bhat, (size_t)lrigw_K(c) * d.n_aux * lrigw_csize(c)));
+  c->gamma_ready = true;
+  return LRIGW_OK;
+}
+
+// B^[K] = B[K] + X1 (y_K / sqrt(v1) - X1^H B[K]),  y_K = sqrt(4 pi / Omega) p_K / D_K.
+// One wavefront per K; the projection is accumulated in FP64.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gamma_modify(const typename c2t<T>::type *__restrict__ B, const double2 *__restrict__ x1,
+                                                      const double2 *__restrict__ p, const T *__restrict__ delta, long long K,
+                                                      int n, double yscale, typename c2t<T>::type *__restrict__ Bh) {
+  typedef typename c2t<T>::type C;
+  const long long Kidx = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (Kidx >= K) return;
+  const C *b = B + Kidx * n;
+  double sr = 0.0, si = 0.0;
+  for (int m = lane; m < n; m += 64) {
+    double2 xv = x1[m];
+    double2 bv = to_z(b[m]);
+    sr += xv.x * bv.x + xv.y * bv.y;  // conj(x) b
+    si += xv.x * bv.y - xv.y * bv.x;
+  }
+  for (int o = 32; o > 0; o >>= 1) { sr += __shfl_xor(sr, o); si += __shfl_xor(si, o); }
+  const double dl = (double)delta[Kidx];
+  const double2 pk = p[Kidx];
+  const double cr = yscale * pk.x / dl - sr, ci = yscale * pk.y / dl - si;
+  C *o = Bh + Kidx * n;
+  for (int m = lane; m < n; m += 64) {
+    double2 xv = x1[m];
+    double2 bv = to_z(b[m]);
+    o[m] = to_c<T>(mkc(bv.x + xv.x * cr - xv.y * ci, bv.y + xv.x * ci + xv.y * cr));
+  }
+}
+
+// D[K] = e_a(k+q) - e_i(k), K = (k * n_occ + i) * n_unocc + a
+template <typename T>
+__global__ void k_delta(const double *__restrict__ eig, const int *__restrict__ kpq, int iq, int nk, int n_bands, int n_occ,
+                        int n_unocc, T *__restrict__ delta) {
+  long long K = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long tot = (long long)nk * n_occ * n_unocc;
+  if (K >= tot) return;
+  int a = (int)(K % n_unocc);
+  int i = (int)((K / n_unocc) % n_occ);
+  int k = (int)(K / ((long long)n_unocc * n_occ));
+  int k2 = kpq[k * nk + iq];
+  delta[K] = (T)(eig[(long long)k2 * n_bands + n_occ + a] - eig[(long long)k * n_bands + i]);
+}
+
+int launch_delta(lrigw_ctx *c, int iq, const double *eig) {
+  const Dims &d = c->d;
+  long long K = lrigw_K(c);
+  dim3 grid((unsigned)((K + 255) / 256));
+  if (c->precision == LRIGW_FP64)
+    hipLaunchKernelGGL(k_delta<double>, grid, dim3(256), 0, c->stream, eig, c->d_kpq, iq, d.n_k, d.n_bands, d.n_occ, d.n_unocc,
+                       (double *)c->d_delta);
+  else
+    hipLaunchKernelGGL(k_delta<float>, grid, dim3(256), 0, c->stream, eig, c->d_kpq, iq, d.n_k, d.n_bands, d.n_occ, d.n_unocc,
+                       (float *)c->d_delta);
+  return lrigw_launch_check("delta");
+}
+
+int launch_gamma_modify(lrigw_ctx *c, const void *B) {
+  const Dims &d = c->d;
+  long long K = lrigw_K(c);
+  double ys = sqrt(4.0 * M_PI / c->omega_cell) / sqrt(c->v1);
+  dim3 grid((unsigned)((K + 3) / 4));
+  if (c->precision == LRIGW_FP64)
+    hipLaunchKernelGGL(k_gamma_modify<double>, grid, dim3(256), 0, c->stream, (const double2 *)B, c->d_x1,
+                       (const double2 *)c->gamma_p, (const double *)c->d_delta, K, d.n_aux, ys, (double2 *)c->d_bhat);
+  else
+    hipLaunchKernelGGL(k_gamma_modify<float>, grid, dim3(256), 0, c->stream, (const float2 *)B, c->d_x1,
+                       (const double2 *)c->gamma_p, (const float *)c->d_delta, K, d.n_aux, ys, (float2 *)c->d_bhat);
+  return lrigw_launch_check("gamma_modify");
+}

@@ -1,0 +1,107 @@
+// Screening (Eqs. symm_dielec_func, screened_W_matr), correlation part, FP64:
+//   V = L L^H (Cholesky, once per q)
+//   D = -L^H chi L          (eps~ - I, Hermitian positive semidefinite)
+//   E = I + D = L_E L_E^H   (batched over frequencies)
+//   W^c = L (E^{-1} - I) L^H = -L (E^{-1} D) L^H,   E^{-1} D by two triangular solves
+// Using L in place of V^{1/2} leaves W unchanged (L = V^{1/2} Q with Q unitary),
+// and E^{-1} D avoids the cancellation of E^{-1} - I where screening is weak.
+#include <algorithm>
+#include <climits>
+
+#include "lrigw_internal.h"
+#include "tiles.h"
+
+template <typename CIN>
+__global__ void k_widen(const CIN *__restrict__ in, double2 *__restrict__ out, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long st = (long long)gridDim.x * blockDim.x;
+  for (; i < n; i += st) out[i] = to_z(in[i]);
+}
+
+// E = I + D
+__global__ void k_add_identity(const double2 *__restrict__ D, double2 *__restrict__ E, int n, long long stride) {
+  long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)n * n) return;
+  long long o = (long long)blockIdx.y * stride + idx;
+  double2 v = D[o];
+  if (idx / n == idx % n) v.x += 1.0;
+  E[o] = v;
+}
+
+// out = (W + W^H) / 2 in the compute type
+template <typename T>
+__global__ void k_hermitize(const double2 *__restrict__ W, typename c2t<T>::type *__restrict__ out, int n, long long stride) {
+  long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)n * n) return;
+  int r = (int)(idx / n), cc = (int)(idx % n);
+  const double2 *Wb = W + (long long)blockIdx.y * stride;
+  double2 a = Wb[(long long)r * n + cc], b = Wb[(long long)cc * n + r];
+  double2 z = mkc(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+  out[(long long)blockIdx.y * stride + idx] = to_c<T>(z);
+}
+
+static ZGemm mk(int m, int n, int k, int opa, const double2 *A, long long lda, long long sa, int opb, const double2 *B,
+                long long ldb, long long sb, double2 *Cm, long long ldc, long long sc, double2 alpha, int batch) {
+  ZGemm g;
+  g.m = m; g.n = n; g.k = k;
+  g.opa = opa; g.A = A; g.lda = lda; g.sa = sa;
+  g.opb = opb; g.B = B; g.ldb = ldb; g.sb = sb;
+  g.C = Cm; g.ldc = ldc; g.sc = sc;
+  g.alpha = alpha; g.beta = mkc(0.0, 0.0);
+  g.batch = batch; g.lower_only = 0;
+  return g;
+}
+
+int run_screen(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_out, int *info) {
+  (void)iq;
+  const Dims &d = c->d;
+  const int n = d.n_aux, nw = d.n_freq;
+  const long long nn = (long long)n * n;
+  hipStream_t s = c->stream;
+  // L_V
+  LRIGW_HIP_TRY(hipMemcpyAsync(c->d_LV, V, nn * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  LRIGW_TRY(zpotrf_batched(s, c->d_LV, n, n, nn, 1, c->d_info + 1));
+  // chi in FP64
+  const double2 *chiz;
+  if (c->precision == LRIGW_FP64) {
+    chiz = (const double2 *)chi;
+  } else {
+    long long tot = nw * nn;
+    hipLaunchKernelGGL(k_widen<float2>, dim3((unsigned)std::min<long long>((tot + 255) / 256, 16384)), dim3(256), 0, s,
+                       (const float2 *)chi, c->d_s3, tot);
+    chiz = c->d_s3;
+  }
+  const double2 one = mkc(1.0, 0.0), mone = mkc(-1.0, 0.0);
+  // T1 = chi L ; D = -L^H T1
+  LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, chiz, n, nn, OP_N, c->d_LV, n, 0, c->d_s0, n, nn, one, nw)));
+  LRIGW_TRY(zgemm(s, mk(n, n, n, OP_C, c->d_LV, n, 0, OP_N, c->d_s0, n, nn, c->d_s1, n, nn, mone, nw)));
+  // E = I + D, Cholesky
+  dim3 eg((unsigned)((nn + 255) / 256), nw);
+  hipLaunchKernelGGL(k_add_identity, eg, dim3(256), 0, s, c->d_s1, c->d_s2, n, nn);
+  LRIGW_TRY(zpotrf_batched(s, c->d_s2, n, n, nn, nw, c->d_info + 2));
+  // D <- E^{-1} D
+  LRIGW_TRY(ztrsm_left_lower(s, c->d_s2, n, nn, c->d_s1, n, nn, n, n, nw));
+  LRIGW_TRY(ztrsm_left_upper_conj(s, c->d_s2, n, nn, c->d_s1, n, nn, n, n, nw));
+  // W = -L (E^{-1} D) L^H
+  LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_s1, n, nn, OP_C, c->d_LV, n, 0, c->d_s0, n, nn, one, nw)));
+  LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_LV, n, 0, OP_N, c->d_s0, n, nn, c->d_s1, n, nn, mone, nw)));
+  if (c->precision == LRIGW_FP64)
+    hipLaunchKernelGGL(k_hermitize<double>, eg, dim3(256), 0, s, c->d_s1, (double2 *)Wc_out, n, nn);
+  else
+    hipLaunchKernelGGL(k_hermitize<float>, eg, dim3(256), 0, s, c->d_s1, (float2 *)Wc_out, n, nn);
+  LRIGW_TRY(lrigw_launch_check("screen"));
+  // status: V and eps~ must have been positive definite
+  int h[2];
+  LRIGW_HIP_TRY(hipMemcpyAsync(h, c->d_info + 1, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  LRIGW_HIP_TRY(hipStreamSynchronize(s));
+  if (info) *info = -1;
+  if (h[0] != INT_MAX) {
+    if (info) *info = -2;
+    return LRIGW_ERR_NOT_HPD;
+  }
+  if (h[1] != INT_MAX) {
+    if (info) *info = h[1];
+    return LRIGW_ERR_NOT_HPD;
+  }
+  return LRIGW_OK;
+}

@@ -1,0 +1,144 @@
+// Internal declarations of the lrigw HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/lrigw.h"
+
+// ---------------------------------------------------------------- complex helpers
+template <typename T> struct c2t;
+template <> struct c2t<double> { typedef double2 type; };
+template <> struct c2t<float> { typedef float2 type; };
+
+__host__ __device__ inline double2 mkc(double r, double i) { double2 z; z.x = r; z.y = i; return z; }
+__host__ __device__ inline float2 mkcf(float r, float i) { float2 z; z.x = r; z.y = i; return z; }
+template <typename C> __host__ __device__ inline C cmul(C a, C b) { C z; z.x = a.x * b.x - a.y * b.y; z.y = a.x * b.y + a.y * b.x; return z; }
+template <typename C> __host__ __device__ inline C cconj(C a) { a.y = -a.y; return a; }
+template <typename C> __host__ __device__ inline C cadd(C a, C b) { a.x += b.x; a.y += b.y; return a; }
+// a * conj(b)
+template <typename C> __host__ __device__ inline C cmulc(C a, C b) { C z; z.x = a.x * b.x + a.y * b.y; z.y = a.y * b.x - a.x * b.y; return z; }
+// conj(a) * b
+template <typename C> __host__ __device__ inline C ccmul(C a, C b) { C z; z.x = a.x * b.x + a.y * b.y; z.y = a.x * b.y - a.y * b.x; return z; }
+
+template <typename T> __device__ inline typename c2t<T>::type to_c(double2 z);
+template <> __device__ inline double2 to_c<double>(double2 z) { return z; }
+template <> __device__ inline float2 to_c<float>(double2 z) { return mkcf((float)z.x, (float)z.y); }
+__device__ inline double2 to_z(double2 z) { return z; }
+__device__ inline double2 to_z(float2 z) { return mkc(z.x, z.y); }
+
+// ---------------------------------------------------------------- error plumbing
+#define LRIGW_HIP_TRY(expr)                                   \
+  do {                                                        \
+    hipError_t e__ = (expr);                                  \
+    if (e__ != hipSuccess) return lrigw_hip_error(e__, #expr, __FILE__, __LINE__); \
+  } while (0)
+#define LRIGW_TRY(expr)                \
+  do {                                 \
+    int r__ = (expr);                  \
+    if (r__ < 0) return r__;           \
+  } while (0)
+
+int lrigw_hip_error(hipError_t e, const char *what, const char *file, int line);
+int zero_fill(hipStream_t s, void *p, size_t bytes);
+int lrigw_launch_check(const char *what);
+
+// ---------------------------------------------------------------- context
+struct Dims {
+  int n_atoms = 0, n_k = 0, nk[3] = {1, 1, 1};
+  int n_b = 0, n_aux = 0, n_bands = 0, n_occ = 0, n_unocc = 0;
+  int n_freq = 0, qp_lo = 0, n_qp = 0, nb_max = 0;
+  double x0 = 0.5, mu = 0.0;
+};
+
+struct StageTimer {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  double ms = 0.0;
+  long long launches = 0;
+};
+
+struct lrigw_ctx {
+  Dims d;
+  int precision = LRIGW_FP64;
+  hipStream_t stream = nullptr;
+  std::vector<int> basis_off, aux_off;
+  std::vector<int> h_kpq, h_kmq;
+
+  // device tables
+  int *d_aux_atom = nullptr;     // [N_aux] atom of each auxiliary function
+  int *d_basis_off = nullptr;    // [n_atoms+1]
+  int *d_aux_off = nullptr;      // [n_atoms+1]
+  int *d_kpq = nullptr, *d_kmq = nullptr;
+  double *d_omega = nullptr, *d_weight = nullptr;
+  std::vector<double> h_omega, h_weight;
+
+  // per-q workspaces
+  void *d_delta = nullptr;       // [K] transition energies of one q (T)
+  void *d_part = nullptr;        // chi0 split-K partials
+  size_t part_bytes = 0;
+  int chi_splits = 1;
+  void *d_X = nullptr;           // [N_w][N_k*n_qp*n_bands] pair weights (T)
+  double2 *d_LV = nullptr;       // [N][N]
+  double2 *d_s0 = nullptr, *d_s1 = nullptr, *d_s2 = nullptr, *d_s3 = nullptr;  // [N_w][N][N]
+  int *d_info = nullptr;         // device status words
+  void *d_bhat = nullptr;        // q = 0 modified B (T)
+
+  // q = 0 data
+  double2 *d_x1 = nullptr;       // [N_aux]
+  double v1 = 0.0;
+  const void *gamma_p = nullptr;
+  double omega_cell = 0.0;
+  bool gamma_ready = false;
+
+  // driver-owned buffers
+  void *d_M = nullptr, *d_x = nullptr, *d_chi = nullptr, *d_wc = nullptr;
+
+  const double *checked_eig = nullptr;   // eigenvalue array already checked for a gap
+
+  // timing
+  bool timing = false;
+  std::map<std::string, StageTimer> stages;
+};
+
+size_t lrigw_csize(const lrigw_ctx *c);   // bytes of one complex T
+long long lrigw_K(const lrigw_ctx *c);    // N_k * n_occ * n_unocc
+
+// stage timing helpers (no-ops unless timing is on)
+void stage_begin(lrigw_ctx *c, const char *name, hipEvent_t *ev);
+void stage_end(lrigw_ctx *c, const char *name, hipEvent_t ev);
+
+// ---------------------------------------------------------------- kernel entry points (host side)
+int run_grids(lrigw_ctx *c);
+int run_lri_ft(lrigw_ctx *c, const double *lri_R, const int *R_list, int nR, const void *evec, void *H_out);
+int run_build_M(lrigw_ctx *c, int iq, int slice, const void *H, const void *evec, void *M_out);
+int run_chi0(lrigw_ctx *c, int iq, const void *M, const double *eig, int apply_gamma, void *chi_out);
+int run_gamma_prepare(lrigw_ctx *c, const void *Vcut0, const void *p, double omega_cell);
+int run_screen(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_out, int *info);
+int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const double *eig, void *sigma_acc);
+int run_qp(lrigw_ctx *c, const void *sigma, const double *eps_qp, const double *e_static, int n_par, double *e_qp,
+           double *z, int *info);
+
+// dense FP64 complex helpers (k_dense.hip)
+enum { OP_N = 0, OP_T = 1, OP_C = 2 };
+struct ZGemm {
+  int m, n, k;
+  int opa, opb;
+  const double2 *A; long long lda, sa;    // sa: batch stride (elements)
+  const double2 *B; long long ldb, sb;
+  double2 *C; long long ldc, sc;
+  double2 alpha, beta;
+  int batch;
+  int lower_only;                          // skip tiles strictly above the diagonal
+};
+int zgemm(hipStream_t s, const ZGemm &g);
+int zpotrf_batched(hipStream_t s, double2 *A, int n, long long lda, long long stride, int batch, int *d_info);
+int ztrsm_left_lower(hipStream_t s, const double2 *L, long long ldl, long long sl, double2 *Y, long long ldy,
+                     long long sy, int n, int ncols, int batch);
+int ztrsm_left_upper_conj(hipStream_t s, const double2 *L, long long ldl, long long sl, double2 *Y, long long ldy,
+                          long long sy, int n, int ncols, int batch);

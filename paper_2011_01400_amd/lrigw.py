@@ -1,0 +1,255 @@
+"""ctypes binding of liblrigw.so (the HIP library declared in include/lrigw.h).
+
+Argument marshalling only: every call forwards device pointers of torch
+tensors to the C entry point of the same name.  There is no host compute path;
+if the library is not built, loading fails with an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblrigw.so")
+
+LRIGW_OK = 0
+LRIGW_ERR_ARG = -1
+LRIGW_ERR_OOM = -2
+LRIGW_ERR_HIP = -3
+LRIGW_ERR_NOT_HPD = -4
+LRIGW_ERR_NOCONV = -5
+LRIGW_WARN_QP_NOCONV = 1
+LRIGW_WARN_PADE_TRUNC = 2
+
+FP64, FP32, SPLIT_BF16 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "split_bf16": SPLIT_BF16}
+
+# every symbol include/lrigw.h declares
+EXPORTS = ["lrigw_create", "lrigw_destroy", "lrigw_strerror", "lrigw_get_sizes", "lrigw_grids", "lrigw_lri_ft",
+           "lrigw_build_M", "lrigw_chi0", "lrigw_gamma_prepare", "lrigw_screen", "lrigw_sigma_c", "lrigw_qp",
+           "lrigw_g0w0", "lrigw_set_timing", "lrigw_stage_ms", "lrigw_reset_timing"]
+
+
+class LrigwSystem(ctypes.Structure):
+    _fields_ = [("n_atoms", ctypes.c_int), ("basis_off", ctypes.POINTER(ctypes.c_int)),
+                ("aux_off", ctypes.POINTER(ctypes.c_int)), ("nk", ctypes.c_int * 3), ("n_bands", ctypes.c_int),
+                ("n_occ", ctypes.c_int), ("n_freq", ctypes.c_int), ("x0", ctypes.c_double), ("mu", ctypes.c_double),
+                ("qp_lo", ctypes.c_int), ("n_qp", ctypes.c_int)]
+
+
+class LrigwSizes(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_longlong) for n in ("n_k", "n_b", "n_aux", "n_bands", "n_freq", "nb_max", "h_elems",
+                                                  "m_chi_elems", "m_sig_elems", "w_elems", "sigma_elems")]
+
+
+class LrigwError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+_lib = None
+
+
+def load(path: Optional[str] = None):
+    """Load liblrigw.so; raises OSError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    # torch brings its own HIP runtime; it must be the one the library binds to
+    # (a second runtime in the process does not see the device)
+    import torch  # noqa: F401
+    if not os.path.exists(p):
+        raise OSError(f"{p} not found: build it with `python -m paper_2011_01400_amd.build`")
+    lib = ctypes.CDLL(p)
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    ip = ctypes.POINTER(ctypes.c_int)
+    sig = {
+        "lrigw_create": (i, [ctypes.POINTER(vp), ctypes.POINTER(LrigwSystem), i, vp]),
+        "lrigw_destroy": (i, [vp]),
+        "lrigw_strerror": (ctypes.c_char_p, [i]),
+        "lrigw_get_sizes": (i, [vp, ctypes.POINTER(LrigwSizes)]),
+        "lrigw_grids": (i, [vp, vp, vp, vp, vp]),
+        "lrigw_lri_ft": (i, [vp, vp, ip, i, vp, vp]),
+        "lrigw_build_M": (i, [vp, i, i, vp, vp, vp]),
+        "lrigw_chi0": (i, [vp, i, vp, vp, i, vp]),
+        "lrigw_gamma_prepare": (i, [vp, vp, vp, d]),
+        "lrigw_screen": (i, [vp, i, vp, vp, vp, ip]),
+        "lrigw_sigma_c": (i, [vp, i, vp, vp, vp, vp]),
+        "lrigw_qp": (i, [vp, vp, vp, vp, i, vp, vp, ip]),
+        "lrigw_g0w0": (i, [vp, vp, vp, vp, vp, vp, d, vp, i, i, i, vp, vp, vp, ip]),
+        "lrigw_set_timing": (i, [vp, i]),
+        "lrigw_stage_ms": (d, [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_longlong)]),
+        "lrigw_reset_timing": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    try:
+        return load().lrigw_strerror(code).decode()
+    except OSError:
+        return str(code)
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+class Context:
+    """One lrigw context: a cell's dimensions, grids, workspaces and stream."""
+
+    def __init__(self, *, n_atoms, basis_off, aux_off, nk, n_bands, n_occ, n_freq, x0, mu, qp_lo, n_qp,
+                 precision="fp64", stream=None):
+        import torch
+        self.lib = load()
+        self._bo = (ctypes.c_int * (n_atoms + 1))(*[int(v) for v in basis_off])
+        self._ao = (ctypes.c_int * (n_atoms + 1))(*[int(v) for v in aux_off])
+        s = LrigwSystem()
+        s.n_atoms = n_atoms
+        s.basis_off = ctypes.cast(self._bo, ctypes.POINTER(ctypes.c_int))
+        s.aux_off = ctypes.cast(self._ao, ctypes.POINTER(ctypes.c_int))
+        s.nk = (ctypes.c_int * 3)(*[int(v) for v in nk])
+        s.n_bands, s.n_occ, s.n_freq = int(n_bands), int(n_occ), int(n_freq)
+        s.x0, s.mu = float(x0), float(mu)
+        s.qp_lo, s.n_qp = int(qp_lo), int(n_qp)
+        self.sys = s
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = self.lib.lrigw_create(ctypes.byref(h), ctypes.byref(s), self.precision, ctypes.c_void_p(stream.cuda_stream))
+        if rc != LRIGW_OK:
+            raise LrigwError(rc, "lrigw_create")
+        self.h = h
+        sz = LrigwSizes()
+        self._check(self.lib.lrigw_get_sizes(self.h, ctypes.byref(sz)), "lrigw_get_sizes")
+        self.sizes = sz
+        self.cdtype = torch.complex128 if self.precision == FP64 else torch.complex64
+
+    @classmethod
+    def from_system(cls, sysm, precision="fp64", stream=None):
+        sp = sysm.spec
+        return cls(n_atoms=sp.n_atoms, basis_off=sysm.basis_off, aux_off=sysm.aux_off, nk=sp.nk, n_bands=sp.n_bands,
+                   n_occ=sp.n_occ, n_freq=sp.n_freq, x0=sp.x0, mu=sysm.mu, qp_lo=sp.qp_lo, n_qp=sp.n_qp,
+                   precision=precision, stream=stream)
+
+    def _check(self, rc, where, allow_warn=False):
+        if rc < 0 or (rc > 0 and not allow_warn):
+            raise LrigwError(rc, where)
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lrigw_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- buffers ------------------------------------------------------
+    def empty(self, kind):
+        import torch
+        z = self.sizes
+        n = {"H": z.h_elems, "M": z.m_chi_elems, "x": z.m_sig_elems, "W": z.w_elems}[kind]
+        return torch.empty(int(n), dtype=self.cdtype, device="cuda")
+
+    # ---- entry points (same names as the C interface) ------------------
+    def grids(self):
+        import torch
+        n = int(self.sizes.n_freq)
+        nk = int(self.sizes.n_k)
+        om = torch.empty(n, dtype=torch.float64, device="cuda")
+        wt = torch.empty(n, dtype=torch.float64, device="cuda")
+        kpq = torch.empty(nk * nk, dtype=torch.int32, device="cuda")
+        kmq = torch.empty(nk * nk, dtype=torch.int32, device="cuda")
+        self._check(self.lib.lrigw_grids(self.h, _ptr(om), _ptr(wt), _ptr(kpq), _ptr(kmq)), "lrigw_grids")
+        return om, wt, kpq.view(nk, nk), kmq.view(nk, nk)
+
+    def lri_ft(self, lri_R, R_list, evec, H_out):
+        R = np.ascontiguousarray(R_list, dtype=np.int32)
+        rp = R.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        self._check(self.lib.lrigw_lri_ft(self.h, _ptr(lri_R), rp, int(R.shape[0]), _ptr(evec), _ptr(H_out)), "lrigw_lri_ft")
+        return H_out
+
+    def build_M(self, iq, slice_, H, evec, M_out):
+        self._check(self.lib.lrigw_build_M(self.h, int(iq), int(slice_), _ptr(H), _ptr(evec), _ptr(M_out)), "lrigw_build_M")
+        return M_out
+
+    def chi0(self, iq, M, eig, chi_out, apply_gamma=False):
+        self._check(self.lib.lrigw_chi0(self.h, int(iq), _ptr(M), _ptr(eig), int(bool(apply_gamma)), _ptr(chi_out)),
+                    "lrigw_chi0")
+        return chi_out
+
+    def gamma_prepare(self, Vcut0, p, omega_cell):
+        self._check(self.lib.lrigw_gamma_prepare(self.h, _ptr(Vcut0), _ptr(p), float(omega_cell)), "lrigw_gamma_prepare")
+
+    def screen(self, iq, chi, V, Wc_out):
+        info = ctypes.c_int(0)
+        rc = self.lib.lrigw_screen(self.h, int(iq), _ptr(chi), _ptr(V), _ptr(Wc_out), ctypes.byref(info))
+        if rc < 0:
+            e = LrigwError(rc, "lrigw_screen")
+            e.info = info.value
+            raise e
+        return Wc_out
+
+    def sigma_c(self, iq, x, Wc, eig, sigma_acc):
+        self._check(self.lib.lrigw_sigma_c(self.h, int(iq), _ptr(x), _ptr(Wc), _ptr(eig), _ptr(sigma_acc)),
+                    "lrigw_sigma_c")
+        return sigma_acc
+
+    def qp(self, sigma, eps_qp, e_static, n_par, e_qp, z):
+        info = ctypes.c_int(0)
+        rc = self.lib.lrigw_qp(self.h, _ptr(sigma), _ptr(eps_qp), _ptr(e_static), int(n_par), _ptr(e_qp), _ptr(z),
+                               ctypes.byref(info))
+        self._check(rc, "lrigw_qp", allow_warn=True)
+        return rc, info.value
+
+    def g0w0(self, H, evec, eig, V, p, omega_cell, e_static, n_par, sigma, e_qp, z, q_first=0, q_last=None):
+        info = ctypes.c_int(0)
+        q_last = int(self.sizes.n_k) if q_last is None else q_last
+        rc = self.lib.lrigw_g0w0(self.h, _ptr(H), _ptr(evec), _ptr(eig), _ptr(V), _ptr(p), float(omega_cell),
+                                 _ptr(e_static), int(n_par), int(q_first), int(q_last), _ptr(sigma), _ptr(e_qp), _ptr(z),
+                                 ctypes.byref(info))
+        self._check(rc, "lrigw_g0w0", allow_warn=True)
+        return rc, info.value
+
+    def set_timing(self, on=True):
+        self._check(self.lib.lrigw_set_timing(self.h, int(bool(on))), "lrigw_set_timing")
+
+    def stage_ms(self, stage):
+        n = ctypes.c_longlong(0)
+        ms = self.lib.lrigw_stage_ms(self.h, stage.encode(), ctypes.byref(n))
+        return ms, n.value
+
+    def reset_timing(self):
+        self.lib.lrigw_reset_timing(self.h)
+
+
+def device_inputs(sysm, device="cuda"):
+    """Copy the arrays of a synthetic cell to the device (torch tensors)."""
+    import torch
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt)
+    return dict(
+        eig=t(sysm.eig, torch.float64),
+        evec=t(sysm.evec, torch.complex128),
+        lri=t(sysm.lri, torch.float64),
+        V=t(sysm.V, torch.complex128),
+        p=t(sysm.p, torch.complex128),
+        e_static=t(sysm.e_static, torch.float64),
+    )

@@ -50,3 +50,19 @@ def test_qp_no_root_reports_failure():
     E, Z, ok = continuation.solve_qp(0.2, 0.0, 0.0, z, a)
     # Newton solves a linear equation in one step
     assert ok and abs(E - 5.2) < 1e-12
+
+
+def test_qp_ignores_pole_crossings():
+    """f(E) = E - e - Re P(E) with P(z) = r/(z - p): near the pole f jumps from +inf
+    to -inf (a decreasing sign change); the QP root is an increasing crossing."""
+    r, pole, e0 = 0.02, 0.03, 0.0
+    f = lambda zz: r / (zz - pole)
+    z = 1j * np.array([0.05, 0.3, 1.0, 3.0])
+    a, _ = continuation.thiele_coeffs(z, np.array([f(zz) for zz in z]))
+    E, Z, ok = continuation.solve_qp(e0, 0.0, 0.0, z, a)
+    assert ok
+    # roots of E - r/(E - p) = 0: E = (p +- sqrt(p^2 + 4r)) / 2, both increasing crossings
+    roots = [(pole - np.sqrt(pole ** 2 + 4 * r)) / 2, (pole + np.sqrt(pole ** 2 + 4 * r)) / 2]
+    assert min(abs(E - x) for x in roots) < 1e-9
+    fd = 1 + r / (E - pole) ** 2
+    assert Z > 0 and abs(Z - 1 / fd) < 1e-9
