@@ -6,10 +6,12 @@ conventions, not arithmetic of the method):
 * k-point index.  A Gamma-centred n1 x n2 x n3 grid; the point with integer
   coordinates (i1, i2, i3), 0 <= i_d < n_d, has fractional coordinates
   i_d / n_d and index (i1 * n2 + i2) * n3 + i3.  The q-grid is the k-grid.
-* Real-space LRI coefficients (amplitude lri_amp * N(0,1) * exp(-|R|/2 bohr);
-  lri_amp = 0.03 puts the dielectric matrix and Sigma^c in the semiconductor
-  range, eps~ eigenvalues ~1..40 and |Sigma^c| ~ 0.1-0.3 Ha, Z ~ 0.75-0.9,
-  where unit amplitude gives eps~ ~ 4e4 and |Sigma^c| ~ 400 Ha).  For each atom A and lattice vector R (integer
+* Real-space LRI coefficients: amplitude a_L * N(0,1) * exp(-|R|/2 bohr) with
+  a_L = 0.03 * sqrt(48 / (N_occ * N_unocc)).  The static screening per
+  auxiliary function grows with the number of occupied/unoccupied pairs times
+  a_L^2; this normalisation keeps every cell in the semiconductor range (eps~
+  eigenvalues ~1..10 away from q = 0, |Sigma^c| ~ 0.1-0.5 Ha, Z ~ 0.8-0.9),
+  where unit amplitude gives eps~ ~ 4e4 and |Sigma^c| ~ 400 Ha.  For each atom A and lattice vector R (integer
   coordinates in the primitive vectors) a block L_A(R)[mu][a][b] holds the
   two-centre coefficient of the product phi_a(0) phi_b(R) on the auxiliary
   function mu, where mu runs over the auxiliary functions of atom A, a over
@@ -54,7 +56,7 @@ class CellSpec:
     x0: float = 0.5
     rmax: int = 2
     lattice: str = "fcc"
-    lri_amp: float = 0.03
+    lri_amp: Optional[float] = None   # None: 0.03 * sqrt(48 / (N_occ * N_unocc))
 
     @property
     def n_b(self) -> int:
@@ -71,6 +73,12 @@ class CellSpec:
     @property
     def n_bands(self) -> int:
         return self.n_b
+
+    @property
+    def lri_amplitude(self) -> float:
+        if self.lri_amp is not None:
+            return self.lri_amp
+        return 0.03 * math.sqrt(48.0 / (self.n_occ * (self.n_bands - self.n_occ)))
 
 
 def _cell(n_atoms, nb, naux, nk, n_occ, n_freq, n_qp=8, qp_lo=None):
@@ -221,7 +229,7 @@ def make_system(spec: CellSpec, seed: int, *, lri_scale: float = 1.0,
         na = spec.naux_per_atom
         nb = spec.nb_per_atom
         blk = rng_lri.standard_normal((nR, na, nb, n_b))
-        blk *= (amp * (spec.lri_amp * lri_scale))[:, None, None, None]
+        blk *= (amp * (spec.lri_amplitude * lri_scale))[:, None, None, None]
         blocks.append(blk.reshape(-1))
         lri_off.append(lri_off[-1] + blk.size)
     lri = np.concatenate(blocks)

@@ -1,0 +1,96 @@
+"""GPU parity at the full Si-like workload size (N_aux = 260, 216 k points,
+32 frequencies) on outputs sampled by tests/golden/make_c2_golden.py (values
+written by the FP64 oracle), plus properties of the whole pass."""
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLD = os.path.join(HERE, "golden", "c2_sampled.npz")
+HA_MEV = 27211.386
+
+
+@pytest.fixture(scope="module")
+def c2():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2011_01400_amd import lrigw as L
+    from synth.systems import make_config
+    L.load()
+    print("\n[gpu c2] generating the Si-like workload", flush=True)
+    s = make_config(2)
+    g = np.load(GOLD)
+    assert int(g["seed"]) == s.seed
+    return dict(L=L, s=s, dev=L.device_inputs(s), g=g)
+
+
+def relf(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_sampled_q(c2, precision, tol):
+    L, s, dev, g = c2["L"], c2["s"], c2["dev"], c2["g"]
+    print(f"[gpu c2] sampled q, {precision}", flush=True)
+    ctx = L.Context.from_system(s, precision=precision)
+    sp = s.spec
+    n = s.n_aux
+    H = ctx.empty("H")
+    ctx.lri_ft(dev["lri"], s.R, dev["evec"], H)
+    M, x, chi, W = ctx.empty("M"), ctx.empty("x"), ctx.empty("W"), ctx.empty("W")
+    ctx.gamma_prepare(dev["V"][0], dev["p"], s.omega_cell)
+    rows = int(g["ROWS"])
+    widx, kidx = g["W_IDX"], g["K_IDX"]
+    for q in g["Q"]:
+        q = int(q)
+        ctx.build_M(q, 0, H, dev["evec"], M)
+        ctx.chi0(q, M, dev["eig"], chi)
+        c = chi.cpu().numpy().reshape(-1, n, n)[widx, :rows]
+        assert relf(c, g[f"chi_q{q}"]) < tol, (q, relf(c, g[f"chi_q{q}"]))
+        if q == 0:
+            ctx.chi0(0, M, dev["eig"], chi, apply_gamma=True)
+        ctx.screen(q, chi, dev["V"][q], W)
+        w = W.cpu().numpy().reshape(-1, n, n)[widx, :rows]
+        assert relf(w, g[f"wc_q{q}"]) < 10 * tol, (q, relf(w, g[f"wc_q{q}"]))
+        ctx.build_M(q, 1, H, dev["evec"], x)
+        sig = torch.zeros((s.n_k, sp.n_qp, sp.n_freq), dtype=torch.complex128, device="cuda")
+        ctx.sigma_c(q, x, W, dev["eig"], sig)
+        sg = sig.cpu().numpy()[kidx]
+        ref = g[f"sigma_q{q}"]
+        err = np.max(np.abs(sg - ref)) / np.max(np.abs(ref))
+        print(f"  q={q} {precision}: chi {relf(c, g[f'chi_q{q}']):.2e}  Wc {relf(w, g[f'wc_q{q}']):.2e}  "
+              f"Sigma_q {err:.2e}", flush=True)
+        assert err < 10 * tol
+    ctx.close()
+
+
+def test_full_pass_forms_agree(c2):
+    """Whole pass in FP64 and FP32: QP energies of the 8 bands around the gap
+    agree within 1 meV; Sigma^c is finite; Z in (0, 1]."""
+    L, s, dev = c2["L"], c2["s"], c2["dev"]
+    sp = s.spec
+    out = {}
+    for precision in ("fp64", "fp32"):
+        print(f"[gpu c2] full pass {precision}", flush=True)
+        ctx = L.Context.from_system(s, precision=precision)
+        H = ctx.empty("H")
+        ctx.lri_ft(dev["lri"], s.R, dev["evec"], H)
+        sigma = torch.zeros((s.n_k, sp.n_qp, sp.n_freq), dtype=torch.complex128, device="cuda")
+        e = torch.zeros((s.n_k, sp.n_qp), dtype=torch.float64, device="cuda")
+        z = torch.zeros_like(e)
+        rc, info = ctx.g0w0(H, dev["evec"], dev["eig"], dev["V"], dev["p"], s.omega_cell, dev["e_static"], 16, sigma, e, z)
+        out[precision] = (sigma.cpu().numpy(), e.cpu().numpy(), z.cpu().numpy(), rc, info)
+        ctx.close()
+    s64, e64, z64, rc64, _ = out["fp64"]
+    s32, e32, z32, _, _ = out["fp32"]
+    assert np.all(np.isfinite(s64)) and np.all(np.isfinite(e64))
+    d = np.max(np.abs(e64 - e32)) * HA_MEV
+    ds = np.max(np.abs(s64 - s32))
+    print(f"  fp32 vs fp64: max|dSigma| = {ds:.3e} Ha, max|dE_qp| = {d:.3e} meV", flush=True)
+    assert d < 1.0
+    reg = (z64 > 0.2)
+    assert np.all(z64[reg] <= 1.0 + 1e-9)
