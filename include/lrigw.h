@@ -13,8 +13,7 @@
  *    "host".  The library never frees caller memory.  Arrays are row-major;
  *    complex numbers are interleaved (re, im) as in std::complex / torch.
  *  - "complex T" means complex128 (two doubles) when the context precision is
- *    LRIGW_FP64 and complex64 (two floats) for LRIGW_FP32 and
- *    LRIGW_SPLIT_BF16.  Eigenvalues, eigenvectors, Coulomb matrices, grids,
+ *    LRIGW_FP64 and complex64 (two floats) for the other precision forms.  Eigenvalues, eigenvectors, Coulomb matrices, grids,
  *    Sigma^c and QP energies are always FP64.
  *  - Calls are asynchronous on the stream given to lrigw_create; outputs are
  *    valid after that stream is synchronised.  Host "info" outputs are written
@@ -50,7 +49,8 @@ extern "C" {
 enum lrigw_precision {
   LRIGW_FP64 = 0,        /* every contraction in FP64 (the plain path) */
   LRIGW_FP32 = 1,        /* M, chi0 and Sigma^c contractions in FP32 on MFMA, FP32 accumulate */
-  LRIGW_SPLIT_BF16 = 2   /* chi0 and Sigma^c as hi/lo BF16 products on MFMA, FP32 accumulate */
+  LRIGW_SPLIT_BF16 = 2,  /* chi0 and Sigma^c as hi/lo BF16 products on MFMA (hi*hi + hi*lo + lo*hi), FP32 accumulate */
+  LRIGW_SPLIT3_BF16 = 3  /* chi0 and Sigma^c with a three-part BF16 split (six products, FP32-like accuracy) */
 };
 
 typedef struct {

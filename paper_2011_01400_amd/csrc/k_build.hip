@@ -7,31 +7,45 @@
 #include "tiles.h"
 
 // M[k][r][c][mu] = sum_{a on atom(mu)} conj(c_{a,r0+r}(k)) H[k2][a][c0+c][mu] + conj(H[k][a][r0+r][mu]) c_{a,c0+c}(k2)
-// k2 = kmap[k][iq].  One thread per (mu, c); NR >= nr accumulators.
-template <typename T, int NR>
+// k2 = kmap[k][iq].  One thread per (mu, 4 columns c); NR >= nr row accumulators
+// per column, so every H[k][a][r][mu] loaded serves BM_CPT columns
+// (BM_CPT * NR <= 32 keeps the accumulators in registers).
+template <typename T, int NR, int BM_CPT>
 __global__ __launch_bounds__(256) void k_build_M(const typename c2t<T>::type *__restrict__ H, const double2 *__restrict__ evec,
                                                  int n_bands, int n_b, int n_aux, int nb_max, const int *__restrict__ aux_atom,
                                                  const int *__restrict__ basis_off, const int *__restrict__ kmap, int iq,
                                                  int nk, int r0, int nr, int c0, int nc, typename c2t<T>::type *__restrict__ M) {
   typedef typename c2t<T>::type C;
   const int mu = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int ci = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int cb = (blockIdx.y * 4 + (threadIdx.x >> 6)) * BM_CPT;   // first column of this thread
   const int k = blockIdx.z;
-  if (mu >= n_aux || ci >= nc) return;
+  if (mu >= n_aux || cb >= nc) return;
   const int A = aux_atom[mu];
   const int bo = basis_off[A];
   const int nbA = basis_off[A + 1] - bo;
   const int k2 = kmap[k * nk + iq];
-  const int cc = c0 + ci;
-  C acc[NR];
+  const int ncol = min(BM_CPT, nc - cb);
+  C acc[BM_CPT][NR];
 #pragma unroll
-  for (int r = 0; r < NR; ++r) acc[r].x = acc[r].y = (T)0;
+  for (int t = 0; t < BM_CPT; ++t)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[t][r].x = acc[t][r].y = (T)0;
   for (int a = 0; a < nbA; ++a) {
-    const C h2 = H[(((long long)k2 * nb_max + a) * n_bands + cc) * n_aux + mu];
-    const double2 e2d = evec[((long long)k2 * n_b + bo + a) * n_bands + cc];
-    C e2;
-    e2.x = (T)e2d.x;
-    e2.y = (T)e2d.y;
+    C h2[BM_CPT], e2[BM_CPT];
+    const C *h2row = H + (((long long)k2 * nb_max + a) * n_bands + c0 + cb) * n_aux + mu;
+    const double2 *e2row = evec + ((long long)k2 * n_b + bo + a) * n_bands + c0 + cb;
+#pragma unroll
+    for (int t = 0; t < BM_CPT; ++t) {
+      if (t < ncol) {
+        h2[t] = h2row[(long long)t * n_aux];
+        double2 v = e2row[t];
+        e2[t].x = (T)v.x;
+        e2[t].y = (T)v.y;
+      } else {
+        h2[t].x = h2[t].y = (T)0;
+        e2[t].x = e2[t].y = (T)0;
+      }
+    }
     const C *h1row = H + (((long long)k * nb_max + a) * n_bands + r0) * n_aux + mu;
     const double2 *e1row = evec + ((long long)k * n_b + bo + a) * n_bands + r0;
 #pragma unroll
@@ -41,14 +55,18 @@ __global__ __launch_bounds__(256) void k_build_M(const typename c2t<T>::type *__
         C e1;
         e1.x = (T)e1d.x;
         e1.y = (T)e1d.y;
-        C h1 = h1row[(long long)r * n_aux];
-        acc[r] = cadd(acc[r], cadd(ccmul(e1, h2), ccmul(h1, e2)));
+        const C h1 = h1row[(long long)r * n_aux];
+#pragma unroll
+        for (int t = 0; t < BM_CPT; ++t) acc[t][r] = cadd(acc[t][r], cadd(ccmul(e1, h2[t]), ccmul(h1, e2[t])));
       }
     }
   }
 #pragma unroll
-  for (int r = 0; r < NR; ++r)
-    if (r < nr) M[(((long long)k * nr + r) * nc + ci) * n_aux + mu] = acc[r];
+  for (int t = 0; t < BM_CPT; ++t)
+    if (t < ncol)
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        if (r < nr) M[(((long long)k * nr + r) * nc + cb + t) * n_aux + mu] = acc[t][r];
 }
 
 template <typename T>
@@ -56,16 +74,15 @@ static void launch_build(lrigw_ctx *c, int iq, int r0, int nr, int c0, int nc, c
                          const void *evec, void *M) {
   typedef typename c2t<T>::type C;
   const Dims &d = c->d;
-  dim3 grid((d.n_aux + 63) / 64, (nc + 3) / 4, d.n_k);
-#define BM(NRV)                                                                                                   \
-  hipLaunchKernelGGL((k_build_M<T, NRV>), grid, dim3(256), 0, c->stream, (const C *)H, (const double2 *)evec,     \
-                     d.n_bands, d.n_b, d.n_aux, d.nb_max, c->d_aux_atom, c->d_basis_off, kmap, iq, d.n_k, r0, nr, c0, \
-                     nc, (C *)M)
-  if (nr <= 4) BM(4);
-  else if (nr <= 8) BM(8);
-  else if (nr <= 16) BM(16);
-  else if (nr <= 32) BM(32);
-  else BM(64);
+#define BM(NRV, CPT)                                                                                              \
+  hipLaunchKernelGGL((k_build_M<T, NRV, CPT>), dim3((d.n_aux + 63) / 64, (nc + 4 * CPT - 1) / (4 * CPT), d.n_k),   \
+                     dim3(256), 0, c->stream, (const C *)H, (const double2 *)evec, d.n_bands, d.n_b, d.n_aux, d.nb_max, \
+                     c->d_aux_atom, c->d_basis_off, kmap, iq, d.n_k, r0, nr, c0, nc, (C *)M)
+  if (nr <= 4) BM(4, 4);
+  else if (nr <= 8) BM(8, 4);
+  else if (nr <= 16) BM(16, 2);
+  else if (nr <= 32) BM(32, 1);
+  else BM(64, 1);
 #undef BM
 }
 

@@ -158,6 +158,156 @@ __global__ __launch_bounds__(256) void k_chi0_mfma(const typename c2t<T>::type *
   }
 }
 
+// Split-BF16 form of the same update: every FP32 operand is split into NS
+// BF16 parts (x = x_0 + x_1 [+ x_2], x_p = bf16(x - x_0 - ... - x_{p-1})) and
+// the products x_p y_q with p + q < NS are accumulated by the 16x16x32 BF16
+// MFMA in FP32 (NS = 2: hi*hi + hi*lo + lo*hi; NS = 3: six products, FP32-like
+// accuracy).  The unweighted side is split once per LDS tile; the weighted
+// side is kept in FP32 in LDS and weighted and split per frequency in
+// registers.  The split-K chunks are kept short (<= 2048 rows, see
+// chi0_plan_splits) so that FP32 accumulation error stays ~1e-6.
+#define KCB 32
+#define BAP 8    // bf16 padding of an A row in LDS
+#define BBP 2    // complex padding of a B row in LDS
+
+template <int NS>
+__device__ inline void splitn(float v, __bf16 *p) {
+  float r = v;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    p[i] = (__bf16)r;
+    r -= (float)p[i];
+  }
+}
+
+template <int NS>
+__global__ __launch_bounds__(256) void k_chi0_bf16(const float2 *__restrict__ B, const float *__restrict__ delta,
+                                                   const double *__restrict__ omega, long long K, int N, int n_freq,
+                                                   long long Ks, long long ntile, float2 *__restrict__ part) {
+  const int NW = 4;
+  __shared__ __bf16 Ar[NS][TILE][KCB + BAP];   // A side (rows mu), real parts, k contiguous
+  __shared__ __bf16 Ai[NS][TILE][KCB + BAP];
+  __shared__ float2 Bs[TILE][KCB + BBP];        // B side (cols nu), FP32, k contiguous
+  __shared__ float dl[KCB];
+
+  int I, J;
+  tri_decode(blockIdx.x, I, J);
+  const int w0 = blockIdx.y * NW;
+  const long long kb = (long long)blockIdx.z * Ks;
+  const long long ke = min(K, kb + Ks);
+  const int mu0 = I * TILE, nu0 = J * TILE;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1, col = lane & 15, g = lane >> 4;
+
+  float om2[NW];
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    double o = (w0 + w < n_freq) ? omega[w0 + w] : 0.0;
+    om2[w] = (float)(o * o);
+  }
+  f4v re[NW][2][2], im[NW][2][2];
+#pragma unroll
+  for (int w = 0; w < NW; ++w)
+#pragma unroll
+    for (int si = 0; si < 2; ++si)
+#pragma unroll
+      for (int sj = 0; sj < 2; ++sj) re[w][si][sj] = im[w][si][sj] = Mfma<float>::zero();
+  for (long long k0 = kb; k0 < ke; k0 += KCB) {
+#pragma unroll
+    for (int t = 0; t < (KCB * TILE) / 256; ++t) {
+      const int e = tid + 256 * t;
+      const int kk = e / TILE, m = e % TILE;
+      const long long kr = k0 + kk;
+      float2 a = mkcf(0.f, 0.f), b = mkcf(0.f, 0.f);
+      if (kr < ke) {
+        if (mu0 + m < N) a = B[kr * N + mu0 + m];
+        if (nu0 + m < N) b = B[kr * N + nu0 + m];
+      }
+      __bf16 pr[NS], pi[NS];
+      splitn<NS>(a.x, pr);
+      splitn<NS>(a.y, pi);
+#pragma unroll
+      for (int p = 0; p < NS; ++p) {
+        Ar[p][m][kk] = pr[p];
+        Ai[p][m][kk] = pi[p];
+      }
+      Bs[m][kk] = b;
+    }
+    if (tid < KCB) dl[tid] = (k0 + tid < ke) ? delta[k0 + tid] : 1.f;
+    __syncthreads();
+    // A operands (rows 32 wr + 16 si + col, k = 8g..8g+7)
+    bf16x8 ar[2][NS], ai[2][NS], nar[2][NS];
+#pragma unroll
+    for (int si = 0; si < 2; ++si)
+#pragma unroll
+      for (int p = 0; p < NS; ++p) {
+        ar[si][p] = *(const bf16x8 *)&Ar[p][32 * wr + 16 * si + col][8 * g];
+        ai[si][p] = *(const bf16x8 *)&Ai[p][32 * wr + 16 * si + col][8 * g];
+        nar[si][p] = -ar[si][p];
+      }
+    float dd[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) dd[e] = dl[8 * g + e];
+    float2 bv[2][8];
+#pragma unroll
+    for (int sj = 0; sj < 2; ++sj)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) bv[sj][e] = Bs[32 * wc + 16 * sj + col][8 * g + e];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      float wt[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) wt[e] = 2.f * dd[e] / (dd[e] * dd[e] + om2[w]);
+#pragma unroll
+      for (int sj = 0; sj < 2; ++sj) {
+        bf16x8 br[NS], bi[NS];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          __bf16 pr[NS], pi[NS];
+          splitn<NS>(wt[e] * bv[sj][e].x, pr);
+          splitn<NS>(wt[e] * bv[sj][e].y, pi);
+#pragma unroll
+          for (int p = 0; p < NS; ++p) {
+            br[p][e] = pr[p];
+            bi[p][e] = pi[p];
+          }
+        }
+#pragma unroll
+        for (int si = 0; si < 2; ++si) {
+          // a conj(b): re = ar br + ai bi, im = ai br - ar bi
+#pragma unroll
+          for (int p = 0; p < NS; ++p)
+#pragma unroll
+            for (int q = 0; q + p < NS; ++q) {
+              re[w][si][sj] = mfma_bf16(ar[si][p], br[q], re[w][si][sj]);
+              re[w][si][sj] = mfma_bf16(ai[si][p], bi[q], re[w][si][sj]);
+              im[w][si][sj] = mfma_bf16(ai[si][p], br[q], im[w][si][sj]);
+              im[w][si][sj] = mfma_bf16(nar[si][p], bi[q], im[w][si][sj]);
+            }
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    if (w0 + w >= n_freq) continue;
+    float2 *dst = part + (((long long)blockIdx.z * n_freq + w0 + w) * ntile + blockIdx.x) * (TILE * TILE);
+#pragma unroll
+    for (int si = 0; si < 2; ++si)
+#pragma unroll
+      for (int sj = 0; sj < 2; ++sj) {
+        const f4v r = re[w][si][sj], i = im[w][si][sj];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int row = 32 * wr + 16 * si + Mfma<float>::row(lane, q);
+          const int cl = 32 * wc + 16 * sj + col;
+          dst[row * TILE + cl] = mkcf(r[q], i[q]);
+        }
+      }
+  }
+}
+
 // chi[w][mu][nu] = scale * sum_s part[s][w][tile][..]; upper triangle by Hermitian symmetry.
 template <typename T>
 __global__ void k_chi0_reduce(const typename c2t<T>::type *__restrict__ part, int S, int n_freq, long long ntile, int N,
@@ -194,9 +344,10 @@ int chi0_plan_splits(const lrigw_ctx *c, int *splits) {
   long long S = (2048 + units - 1) / units;
   long long maxS = std::max<long long>(1, K / 512);
   S = std::min(S, maxS);
+  if (c->precision == LRIGW_SPLIT_BF16 || c->precision == LRIGW_SPLIT3_BF16) S = std::max(S, (K + 2047) / 2048);
   const size_t cs = lrigw_csize(c);
   const size_t per = (size_t)d.n_freq * ntile * TILE * TILE * cs;
-  while (S > 1 && (size_t)S * per > (size_t)2 << 30) --S;
+  while (S > 1 && (size_t)S * per > (size_t)3 << 30) --S;
   *splits = (int)std::max<long long>(1, S);
   return LRIGW_OK;
 }
@@ -237,7 +388,7 @@ int run_chi0(lrigw_ctx *c, int iq, const void *M, const double *eig, int apply_g
   const int nt = (d.n_aux + TILE - 1) / TILE;
   const long long ntile = (long long)nt * (nt + 1) / 2;
   const int S = c->chi_splits;
-  const long long Ks = ((K + S - 1) / S + KC - 1) / KC * KC;
+  const long long Ks = ((K + S - 1) / S + KCB - 1) / KCB * KCB;
   const double scale = -2.0 / d.n_k;
   hipEvent_t ev;
   stage_begin(c, "chi0_mfma", &ev);
@@ -249,8 +400,15 @@ int run_chi0(lrigw_ctx *c, int iq, const void *M, const double *eig, int apply_g
   } else {
     const int NW = Chi0Cfg<float>::NW;
     dim3 grid((unsigned)ntile, (d.n_freq + NW - 1) / NW, S);
-    hipLaunchKernelGGL(k_chi0_mfma<float>, grid, dim3(256), 0, c->stream, (const float2 *)B, (const float *)c->d_delta,
-                       c->d_omega, K, d.n_aux, d.n_freq, Ks, ntile, (float2 *)c->d_part);
+    if (c->precision == LRIGW_FP32)
+      hipLaunchKernelGGL(k_chi0_mfma<float>, grid, dim3(256), 0, c->stream, (const float2 *)B, (const float *)c->d_delta,
+                         c->d_omega, K, d.n_aux, d.n_freq, Ks, ntile, (float2 *)c->d_part);
+    else if (c->precision == LRIGW_SPLIT_BF16)
+      hipLaunchKernelGGL(k_chi0_bf16<2>, grid, dim3(256), 0, c->stream, (const float2 *)B, (const float *)c->d_delta,
+                         c->d_omega, K, d.n_aux, d.n_freq, Ks, ntile, (float2 *)c->d_part);
+    else
+      hipLaunchKernelGGL(k_chi0_bf16<3>, grid, dim3(256), 0, c->stream, (const float2 *)B, (const float *)c->d_delta,
+                         c->d_omega, K, d.n_aux, d.n_freq, Ks, ntile, (float2 *)c->d_part);
   }
   stage_end(c, "chi0_mfma", ev);
   LRIGW_TRY(lrigw_launch_check("chi0_mfma"));

@@ -1,13 +1,15 @@
-// Dense FP64 complex building blocks: batched GEMM, blocked Cholesky and
-// triangular solves (used by the screening step and the LRI half-transform).
+// Dense FP64 complex building blocks: batched GEMM on FP64 MFMA, blocked
+// Cholesky and triangular solves (screening step, LRI half-transform).
 #include <algorithm>
+#include <climits>
 #include <cmath>
 
 #include "lrigw_internal.h"
 #include "tiles.h"
 
 #define GT 64      // output tile
-#define GK 8       // K step
+#define GK 16      // K rows staged per step
+#define GP (GT + 1)
 
 __device__ inline double2 ldop(const double2 *__restrict__ A, long long ld, int op, long long r, long long cidx) {
   // element (r, cidx) of op(A)
@@ -17,27 +19,32 @@ __device__ inline double2 ldop(const double2 *__restrict__ A, long long ld, int 
   return v;
 }
 
-// C = alpha op(A) op(B) + beta C, 64x64 tile per workgroup, 4x4 outputs per thread.
+// C = alpha op(A) op(B) + beta C; 64x64 tile per workgroup, four waves of
+// 32x32, complex products as four real FP64 MFMA 16x16x4 products.  A
+// workgroup reads all of op(A)'s rows and op(B)'s columns of its tile before it
+// writes the tile, so C may alias A when n <= 64 or B when m <= 64.
 __global__ __launch_bounds__(256) void k_zgemm(ZGemm g) {
-  __shared__ double2 As[GK][GT + 1];
-  __shared__ double2 Bs[GK][GT + 1];
+  typedef Mfma<double> MF;
+  __shared__ double2 As[GK][GP];   // As[k][m] = op(A)(m0+m, k0+k)
+  __shared__ double2 Bs[GK][GP];   // Bs[k][n] = op(B)(k0+k, n0+n)
   const int tm = blockIdx.x, tn = blockIdx.y, b = blockIdx.z;
   const int m0 = tm * GT, n0 = tn * GT;
   if (g.lower_only && n0 > m0 + GT - 1) return;
   const double2 *A = g.A + (long long)b * g.sa;
   const double2 *B = g.B + (long long)b * g.sb;
   double2 *C = g.C + (long long)b * g.sc;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  double cr[4][4], ci[4][4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1, col = lane & 15;
+  d4v cr[2][2], ci[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) cr[i][j] = ci[i][j] = 0.0;
+    for (int j = 0; j < 2; ++j) cr[i][j] = ci[i][j] = MF::zero();
   for (int k0 = 0; k0 < g.k; k0 += GK) {
+    __syncthreads();
 #pragma unroll
     for (int t = 0; t < (GK * GT) / 256; ++t) {
-      int e = tid + 256 * t;
-      // A tile: rows m0..m0+63, cols k0..k0+7 ; choose the mapping that walks memory contiguously
+      const int e = tid + 256 * t;
       int kk, mm;
       if (g.opa == OP_N) { mm = e / GK; kk = e % GK; } else { kk = e / GT; mm = e % GT; }
       double2 v = mkc(0.0, 0.0);
@@ -51,67 +58,79 @@ __global__ __launch_bounds__(256) void k_zgemm(ZGemm g) {
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < GK; ++kk) {
-      double2 a[4], bb[4];
+    for (int ks = 0; ks < GK / 4; ++ks) {
+      const int kk = ks * 4 + (lane >> 4);
+      double2 a[2], bb[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+      for (int s = 0; s < 2; ++s) {
+        a[s] = As[kk][32 * wr + 16 * s + col];
+        bb[s] = Bs[kk][32 * wc + 16 * s + col];
+      }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bb[j] = Bs[kk][tx + 16 * j];
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 2; ++j) {
+          cr[i][j] = MF::mac(a[i].x, bb[j].x, cr[i][j]);
+          ci[i][j] = MF::mac(a[i].x, bb[j].y, ci[i][j]);
+        }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          cr[i][j] += a[i].x * bb[j].x - a[i].y * bb[j].y;
-          ci[i][j] += a[i].x * bb[j].y + a[i].y * bb[j].x;
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          cr[i][j] = MF::mac(-a[i].y, bb[j].y, cr[i][j]);
+          ci[i][j] = MF::mac(a[i].y, bb[j].x, ci[i][j]);
         }
     }
-    __syncthreads();
   }
+  __syncthreads();   // every read of an aliased operand is done before any write
   const bool beta0 = (g.beta.x == 0.0 && g.beta.y == 0.0);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    int r = m0 + ty + 16 * i;
-    if (r >= g.m) continue;
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      int cc = n0 + tx + 16 * j;
-      if (cc >= g.n) continue;
-      if (g.lower_only && cc > r) continue;
-      double2 v = mkc(g.alpha.x * cr[i][j] - g.alpha.y * ci[i][j], g.alpha.x * ci[i][j] + g.alpha.y * cr[i][j]);
-      long long o = (long long)r * g.ldc + cc;
-      if (!beta0) {
-        double2 old = C[o];
-        v.x += g.beta.x * old.x - g.beta.y * old.y;
-        v.y += g.beta.x * old.y + g.beta.y * old.x;
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = m0 + 32 * wr + 16 * i + MF::row(lane, q);
+        const int cc = n0 + 32 * wc + 16 * j + col;
+        if (r >= g.m || cc >= g.n) continue;
+        if (g.lower_only && cc > r) continue;
+        const double xr = cr[i][j][q], xi = ci[i][j][q];
+        double2 v = mkc(g.alpha.x * xr - g.alpha.y * xi, g.alpha.x * xi + g.alpha.y * xr);
+        const long long o = (long long)r * g.ldc + cc;
+        if (!beta0) {
+          const double2 old = C[o];
+          v.x += g.beta.x * old.x - g.beta.y * old.y;
+          v.y += g.beta.x * old.y + g.beta.y * old.x;
+        }
+        C[o] = v;
       }
-      C[o] = v;
-    }
-  }
 }
 
 int zgemm(hipStream_t s, const ZGemm &g) {
   if (g.m <= 0 || g.n <= 0 || g.batch <= 0) return LRIGW_OK;
-  if (g.k <= 0) {
-    // C = beta C: not needed by the callers
-    return LRIGW_ERR_ARG;
-  }
+  if (g.k <= 0) return LRIGW_ERR_ARG;
   dim3 grid((g.m + GT - 1) / GT, (g.n + GT - 1) / GT, g.batch);
   hipLaunchKernelGGL(k_zgemm, grid, dim3(256), 0, s, g);
   return lrigw_launch_check("zgemm");
 }
 
-// ---------------------------------------------------------------- Cholesky
-#define NB 32
+// ---------------------------------------------------------------- Cholesky, NB = 64
+#define NB 64
+#define NBP (NB + 1)
 
-// Factor the jb x jb diagonal block at (j0, j0) of every matrix in LDS.
-__global__ __launch_bounds__(256) void k_potrf_diag(double2 *A, long long lda, long long stride, int j0, int jb, int *info) {
-  __shared__ double2 L[NB][NB + 1];
+// Factor the jb x jb diagonal block at (j0, j0) of every matrix in LDS, write
+// back L_jj (lower, strict upper zeroed) and its inverse into
+// Dinv[batch][blk][NB][NB].  info[0] = smallest failing batch index.
+__global__ __launch_bounds__(256) void k_potrf_diag(double2 *A, long long lda, long long stride, int j0, int jb, double2 *Dinv,
+                                                    long long dstride, int *info) {
+  __shared__ double2 L[NB][NBP];
+  __shared__ double2 X[NB][NBP];
   __shared__ int bad;
   double2 *M = A + (long long)blockIdx.x * stride;
   const int tid = threadIdx.x;
   if (tid == 0) bad = 0;
   for (int e = tid; e < jb * jb; e += blockDim.x) {
-    int r = e / jb, cc = e % jb;
+    const int r = e / jb, cc = e % jb;
     L[r][cc] = M[(long long)(j0 + r) * lda + j0 + cc];
   }
   __syncthreads();
@@ -131,88 +150,86 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double2 *A, long long lda, l
       L[r][cc].y *= dinv;
     }
     __syncthreads();
-    // trailing update of the lower part: L[r][s] -= L[r][cc] conj(L[s][cc]), cc < s <= r
     const int rem = jb - cc - 1;
     for (int e = tid; e < rem * rem; e += blockDim.x) {
-      int r = cc + 1 + e / rem, s2 = cc + 1 + e % rem;
+      const int r = cc + 1 + e / rem, s2 = cc + 1 + e % rem;
       if (s2 <= r) {
-        double2 a = L[r][cc], b = L[s2][cc];
+        const double2 a = L[r][cc], b = L[s2][cc];
         L[r][s2].x -= a.x * b.x + a.y * b.y;
         L[r][s2].y -= a.y * b.x - a.x * b.y;
       }
     }
     __syncthreads();
   }
+  // inverse of the lower-triangular block, one column per thread:
+  // X[i][j] = (delta_ij - sum_{t=j}^{i-1} L[i][t] X[t][j]) / L[i][i]
+  if (tid < jb) {
+    const int j = tid;
+    for (int i = 0; i < j; ++i) X[i][j] = mkc(0.0, 0.0);
+    for (int i = j; i < jb; ++i) {
+      double2 v = mkc(i == j ? 1.0 : 0.0, 0.0);
+      for (int t = j; t < i; ++t) {
+        const double2 l = L[i][t], x = X[t][j];
+        v.x -= l.x * x.x - l.y * x.y;
+        v.y -= l.x * x.y + l.y * x.x;
+      }
+      const double dinv = 1.0 / L[i][i].x;
+      X[i][j] = mkc(v.x * dinv, v.y * dinv);
+    }
+  }
+  __syncthreads();
+  double2 *D = Dinv + (long long)blockIdx.x * dstride + (long long)(j0 / NB) * NB * NB;
   for (int e = tid; e < jb * jb; e += blockDim.x) {
-    int r = e / jb, cc = e % jb;
+    const int r = e / jb, cc = e % jb;
     M[(long long)(j0 + r) * lda + j0 + cc] = (cc <= r) ? L[r][cc] : mkc(0.0, 0.0);
+    D[r * NB + cc] = X[r][cc];
   }
   if (tid == 0 && bad) atomicMin(info + 0, blockIdx.x);
 }
 
-// Panel: A[r][j0..j0+jb) <- A[r][..] L_jj^{-H} for rows r >= j0+jb (one thread per row).
-__global__ __launch_bounds__(256) void k_trsm_panel(double2 *A, long long lda, long long stride, int n, int j0, int jb) {
-  __shared__ double2 L[NB][NB + 1];
-  double2 *M = A + (long long)blockIdx.y * stride;
-  for (int e = threadIdx.x; e < jb * jb; e += blockDim.x) L[e / jb][e % jb] = M[(long long)(j0 + e / jb) * lda + j0 + e % jb];
-  __syncthreads();
-  int r = j0 + jb + blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  double2 x[NB];
-  double2 *row = M + (long long)r * lda + j0;
-  for (int cc = 0; cc < jb; ++cc) {
-    // x L^H = a  ->  x_c = (a_c - sum_{t<c} x_t conj(L[c][t])) / L[c][c]
-    double2 v = row[cc];
-    for (int t = 0; t < cc; ++t) {
-      double2 l = L[cc][t];
-      v.x -= x[t].x * l.x + x[t].y * l.y;
-      v.y -= x[t].y * l.x - x[t].x * l.y;
-    }
-    double dinv = 1.0 / L[cc][cc].x;
-    x[cc] = mkc(v.x * dinv, v.y * dinv);
-  }
-  for (int cc = 0; cc < jb; ++cc) row[cc] = x[cc];
-}
-
 __global__ void k_zero_upper(double2 *A, long long lda, long long stride, int n) {
-  long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long long)n * n) return;
-  int r = (int)(idx / n), cc = (int)(idx % n);
+  const int r = (int)(idx / n), cc = (int)(idx % n);
   if (cc > r) A[(long long)blockIdx.y * stride + (long long)r * lda + cc] = mkc(0.0, 0.0);
 }
 
 __global__ void k_info_init(int *info, int v) { info[threadIdx.x] = v; }
 
-// A = L L^H in place (lower; the strict upper part is zeroed).  d_info[0] = first
-// failing batch index, or INT_MAX.
-int zpotrf_batched(hipStream_t s, double2 *A, int n, long long lda, long long stride, int batch, int *d_info) {
-  hipLaunchKernelGGL(k_info_init, dim3(1), dim3(1), 0, s, d_info, 0x7fffffff);
+static ZGemm mkg(int m, int n, int k, int opa, const double2 *A, long long lda, long long sa, int opb, const double2 *B,
+                 long long ldb, long long sb, double2 *Cm, long long ldc, long long sc, double2 alpha, double2 beta,
+                 int batch, int lower_only) {
+  ZGemm g;
+  g.m = m; g.n = n; g.k = k;
+  g.opa = opa; g.A = A; g.lda = lda; g.sa = sa;
+  g.opb = opb; g.B = B; g.ldb = ldb; g.sb = sb;
+  g.C = Cm; g.ldc = ldc; g.sc = sc;
+  g.alpha = alpha; g.beta = beta;
+  g.batch = batch; g.lower_only = lower_only;
+  return g;
+}
+
+long long zdinv_stride(int n) { return (long long)((n + NB - 1) / NB) * NB * NB; }
+
+// A = L L^H in place (lower; strict upper part zeroed); Dinv receives the
+// inverses of the diagonal blocks (zdinv_stride(n) elements per matrix).
+// d_info[0] = first failing batch index, or INT_MAX.
+int zpotrf_batched(hipStream_t s, double2 *A, int n, long long lda, long long stride, int batch, double2 *Dinv, int *d_info) {
+  const long long ds = zdinv_stride(n);
+  const double2 one = mkc(1.0, 0.0), mone = mkc(-1.0, 0.0), zero = mkc(0.0, 0.0);
+  hipLaunchKernelGGL(k_info_init, dim3(1), dim3(1), 0, s, d_info, INT_MAX);
   for (int j0 = 0; j0 < n; j0 += NB) {
-    int jb = std::min(NB, n - j0);
-    hipLaunchKernelGGL(k_potrf_diag, dim3(batch), dim3(256), 0, s, A, lda, stride, j0, jb, d_info);
-    int rest = n - j0 - jb;
+    const int jb = std::min(NB, n - j0);
+    hipLaunchKernelGGL(k_potrf_diag, dim3(batch), dim3(256), 0, s, A, lda, stride, j0, jb, Dinv, ds, d_info);
+    const int rest = n - j0 - jb;
     if (rest > 0) {
-      hipLaunchKernelGGL(k_trsm_panel, dim3((rest + 255) / 256, batch), dim3(256), 0, s, A, lda, stride, n, j0, jb);
-      ZGemm g;
-      g.m = rest;
-      g.n = rest;
-      g.k = jb;
-      g.opa = OP_N;
-      g.A = A + (long long)(j0 + jb) * lda + j0;
-      g.lda = lda;
-      g.sa = stride;
-      g.opb = OP_C;
-      g.B = A + (long long)(j0 + jb) * lda + j0;
-      g.ldb = lda;
-      g.sb = stride;
-      g.C = A + (long long)(j0 + jb) * lda + j0 + jb;
-      g.ldc = lda;
-      g.sc = stride;
-      g.alpha = mkc(-1.0, 0.0);
-      g.beta = mkc(1.0, 0.0);
-      g.batch = batch;
-      g.lower_only = 1;
-      LRIGW_TRY(zgemm(s, g));
+      double2 *P = A + (long long)(j0 + jb) * lda + j0;
+      const double2 *D = Dinv + (long long)(j0 / NB) * NB * NB;
+      // panel P <- P L_jj^{-H} (in place: one column tile)
+      LRIGW_TRY(zgemm(s, mkg(rest, jb, jb, OP_N, P, lda, stride, OP_C, D, NB, ds, P, lda, stride, one, zero, batch, 0)));
+      // trailing update, lower part: A22 -= P P^H
+      LRIGW_TRY(zgemm(s, mkg(rest, rest, jb, OP_N, P, lda, stride, OP_C, P, lda, stride, P + jb, lda, stride, mone, one,
+                          batch, 1)));
     }
   }
   dim3 zg((unsigned)(((long long)n * n + 255) / 256), batch);
@@ -220,121 +237,41 @@ int zpotrf_batched(hipStream_t s, double2 *A, int n, long long lda, long long st
   return lrigw_launch_check("zpotrf");
 }
 
-// ---------------------------------------------------------------- triangular solves, full right-hand sides
-// rows j0..j0+jb of Y <- L_jj^{-1} rows (forward), one thread per column
-__global__ __launch_bounds__(256) void k_trsm_lower_diag(const double2 *L, long long ldl, long long sl, double2 *Y, long long ldy,
-                                                         long long sy, int j0, int jb, int ncols) {
-  __shared__ double2 Ld[NB][NB + 1];
-  const double2 *Lb = L + (long long)blockIdx.y * sl;
-  for (int e = threadIdx.x; e < jb * jb; e += blockDim.x) Ld[e / jb][e % jb] = Lb[(long long)(j0 + e / jb) * ldl + j0 + e % jb];
-  __syncthreads();
-  int cc = blockIdx.x * blockDim.x + threadIdx.x;
-  if (cc >= ncols) return;
-  double2 *Yb = Y + (long long)blockIdx.y * sy;
-  double2 y[NB];
-  for (int r = 0; r < jb; ++r) {
-    double2 v = Yb[(long long)(j0 + r) * ldy + cc];
-    for (int t = 0; t < r; ++t) {
-      double2 l = Ld[r][t];
-      v.x -= l.x * y[t].x - l.y * y[t].y;
-      v.y -= l.x * y[t].y + l.y * y[t].x;
-    }
-    double dinv = 1.0 / Ld[r][r].x;
-    y[r] = mkc(v.x * dinv, v.y * dinv);
-  }
-  for (int r = 0; r < jb; ++r) Yb[(long long)(j0 + r) * ldy + cc] = y[r];
-}
-
-// rows j0..j0+jb of Y <- L_jj^{-H} rows (backward), one thread per column
-__global__ __launch_bounds__(256) void k_trsm_upperc_diag(const double2 *L, long long ldl, long long sl, double2 *Y, long long ldy,
-                                                          long long sy, int j0, int jb, int ncols) {
-  __shared__ double2 Ld[NB][NB + 1];
-  const double2 *Lb = L + (long long)blockIdx.y * sl;
-  for (int e = threadIdx.x; e < jb * jb; e += blockDim.x) Ld[e / jb][e % jb] = Lb[(long long)(j0 + e / jb) * ldl + j0 + e % jb];
-  __syncthreads();
-  int cc = blockIdx.x * blockDim.x + threadIdx.x;
-  if (cc >= ncols) return;
-  double2 *Yb = Y + (long long)blockIdx.y * sy;
-  double2 y[NB];
-  for (int r = jb - 1; r >= 0; --r) {
-    double2 v = Yb[(long long)(j0 + r) * ldy + cc];
-    for (int t = r + 1; t < jb; ++t) {
-      double2 l = Ld[t][r];  // (L^H)[r][t] = conj(L[t][r])
-      v.x -= l.x * y[t].x + l.y * y[t].y;
-      v.y -= l.x * y[t].y - l.y * y[t].x;
-    }
-    double dinv = 1.0 / Ld[r][r].x;
-    y[r] = mkc(v.x * dinv, v.y * dinv);
-  }
-  for (int r = 0; r < jb; ++r) Yb[(long long)(j0 + r) * ldy + cc] = y[r];
-}
-
-// Y <- L^{-1} Y  (L lower, n x n; Y n x ncols)
-int ztrsm_left_lower(hipStream_t s, const double2 *L, long long ldl, long long sl, double2 *Y, long long ldy, long long sy,
-                     int n, int ncols, int batch) {
+// Y <- L^{-1} Y  (L lower n x n with Dinv from zpotrf_batched; Y n x ncols)
+int ztrsm_left_lower(hipStream_t s, const double2 *L, long long ldl, long long sl, const double2 *Dinv, double2 *Y,
+                     long long ldy, long long sy, int n, int ncols, int batch) {
+  const long long ds = zdinv_stride(n);
+  const double2 one = mkc(1.0, 0.0), mone = mkc(-1.0, 0.0), zero = mkc(0.0, 0.0);
   for (int j0 = 0; j0 < n; j0 += NB) {
-    int jb = std::min(NB, n - j0);
-    if (j0 > 0) {
-      ZGemm g;
-      g.m = jb;
-      g.n = ncols;
-      g.k = j0;
-      g.opa = OP_N;
-      g.A = L + (long long)j0 * ldl;
-      g.lda = ldl;
-      g.sa = sl;
-      g.opb = OP_N;
-      g.B = Y;
-      g.ldb = ldy;
-      g.sb = sy;
-      g.C = Y + (long long)j0 * ldy;
-      g.ldc = ldy;
-      g.sc = sy;
-      g.alpha = mkc(-1.0, 0.0);
-      g.beta = mkc(1.0, 0.0);
-      g.batch = batch;
-      g.lower_only = 0;
-      LRIGW_TRY(zgemm(s, g));
-    }
-    hipLaunchKernelGGL(k_trsm_lower_diag, dim3((ncols + 255) / 256, batch), dim3(256), 0, s, L, ldl, sl, Y, ldy, sy, j0, jb,
-                       ncols);
+    const int jb = std::min(NB, n - j0);
+    double2 *Yj = Y + (long long)j0 * ldy;
+    if (j0 > 0)
+      LRIGW_TRY(zgemm(s, mkg(jb, ncols, j0, OP_N, L + (long long)j0 * ldl, ldl, sl, OP_N, Y, ldy, sy, Yj, ldy, sy, mone,
+                          one, batch, 0)));
+    // Y_j <- L_jj^{-1} Y_j (in place: one row tile)
+    LRIGW_TRY(zgemm(s, mkg(jb, ncols, jb, OP_N, Dinv + (long long)(j0 / NB) * NB * NB, NB, ds, OP_N, Yj, ldy, sy, Yj, ldy,
+                        sy, one, zero, batch, 0)));
   }
-  return lrigw_launch_check("ztrsm_lower");
+  return LRIGW_OK;
 }
 
 // Y <- L^{-H} Y
-int ztrsm_left_upper_conj(hipStream_t s, const double2 *L, long long ldl, long long sl, double2 *Y, long long ldy, long long sy,
-                          int n, int ncols, int batch) {
-  int nblk = (n + NB - 1) / NB;
+int ztrsm_left_upper_conj(hipStream_t s, const double2 *L, long long ldl, long long sl, const double2 *Dinv, double2 *Y,
+                          long long ldy, long long sy, int n, int ncols, int batch) {
+  const long long ds = zdinv_stride(n);
+  const double2 one = mkc(1.0, 0.0), mone = mkc(-1.0, 0.0), zero = mkc(0.0, 0.0);
+  const int nblk = (n + NB - 1) / NB;
   for (int bi = nblk - 1; bi >= 0; --bi) {
-    int j0 = bi * NB;
-    int jb = std::min(NB, n - j0);
-    int rest = n - j0 - jb;
-    if (rest > 0) {
-      // Y[j0..] -= (L[j0+jb.., j0..j0+jb))^H Y[j0+jb..]
-      ZGemm g;
-      g.m = jb;
-      g.n = ncols;
-      g.k = rest;
-      g.opa = OP_C;
-      g.A = L + (long long)(j0 + jb) * ldl + j0;
-      g.lda = ldl;
-      g.sa = sl;
-      g.opb = OP_N;
-      g.B = Y + (long long)(j0 + jb) * ldy;
-      g.ldb = ldy;
-      g.sb = sy;
-      g.C = Y + (long long)j0 * ldy;
-      g.ldc = ldy;
-      g.sc = sy;
-      g.alpha = mkc(-1.0, 0.0);
-      g.beta = mkc(1.0, 0.0);
-      g.batch = batch;
-      g.lower_only = 0;
-      LRIGW_TRY(zgemm(s, g));
-    }
-    hipLaunchKernelGGL(k_trsm_upperc_diag, dim3((ncols + 255) / 256, batch), dim3(256), 0, s, L, ldl, sl, Y, ldy, sy, j0, jb,
-                       ncols);
+    const int j0 = bi * NB;
+    const int jb = std::min(NB, n - j0);
+    const int rest = n - j0 - jb;
+    double2 *Yj = Y + (long long)j0 * ldy;
+    if (rest > 0)
+      LRIGW_TRY(zgemm(s, mkg(jb, ncols, rest, OP_C, L + (long long)(j0 + jb) * ldl + j0, ldl, sl, OP_N,
+                          Y + (long long)(j0 + jb) * ldy, ldy, sy, Yj, ldy, sy, mone, one, batch, 0)));
+    // Y_j <- L_jj^{-H} Y_j
+    LRIGW_TRY(zgemm(s, mkg(jb, ncols, jb, OP_C, Dinv + (long long)(j0 / NB) * NB * NB, NB, ds, OP_N, Yj, ldy, sy, Yj, ldy,
+                        sy, one, zero, batch, 0)));
   }
-  return lrigw_launch_check("ztrsm_upperc");
+  return LRIGW_OK;
 }

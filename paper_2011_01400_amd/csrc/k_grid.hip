@@ -124,12 +124,13 @@ int run_grids(lrigw_ctx *c) {
   size_t ntile = (size_t)nt * (nt + 1) / 2;
   c->part_bytes = (size_t)c->chi_splits * d.n_freq * ntile * TILE * TILE * cs;
   LRIGW_HIP_TRY(hipMalloc(&c->d_part, c->part_bytes));
-  LRIGW_HIP_TRY(hipMalloc(&c->d_X, (size_t)d.n_freq * d.n_k * d.n_qp * d.n_bands * rs));
+  LRIGW_HIP_TRY(hipMalloc(&c->d_X, (size_t)d.n_freq * d.n_k * d.n_qp * d.n_bands * sizeof(double)));
   LRIGW_HIP_TRY(hipMalloc(&c->d_LV, nn * sizeof(double2)));
   LRIGW_HIP_TRY(hipMalloc(&c->d_s0, d.n_freq * nn * sizeof(double2)));
   LRIGW_HIP_TRY(hipMalloc(&c->d_s1, d.n_freq * nn * sizeof(double2)));
   LRIGW_HIP_TRY(hipMalloc(&c->d_s2, d.n_freq * nn * sizeof(double2)));
   LRIGW_HIP_TRY(hipMalloc(&c->d_s3, d.n_freq * nn * sizeof(double2)));
+  LRIGW_HIP_TRY(hipMalloc(&c->d_dinv, (size_t)d.n_freq * zdinv_stride(d.n_aux) * sizeof(double2)));
   LRIGW_HIP_TRY(hipMalloc(&c->d_info, 64 * sizeof(int)));
   LRIGW_HIP_TRY(hipMalloc(&c->d_x1, d.n_aux * sizeof(double2)));
   return LRIGW_OK;

@@ -60,7 +60,7 @@ int run_screen(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_ou
   hipStream_t s = c->stream;
   // L_V
   LRIGW_HIP_TRY(hipMemcpyAsync(c->d_LV, V, nn * sizeof(double2), hipMemcpyDeviceToDevice, s));
-  LRIGW_TRY(zpotrf_batched(s, c->d_LV, n, n, nn, 1, c->d_info + 1));
+  LRIGW_TRY(zpotrf_batched(s, c->d_LV, n, n, nn, 1, c->d_dinv, c->d_info + 1));
   // chi in FP64
   const double2 *chiz;
   if (c->precision == LRIGW_FP64) {
@@ -78,10 +78,10 @@ int run_screen(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_ou
   // E = I + D, Cholesky
   dim3 eg((unsigned)((nn + 255) / 256), nw);
   hipLaunchKernelGGL(k_add_identity, eg, dim3(256), 0, s, c->d_s1, c->d_s2, n, nn);
-  LRIGW_TRY(zpotrf_batched(s, c->d_s2, n, n, nn, nw, c->d_info + 2));
+  LRIGW_TRY(zpotrf_batched(s, c->d_s2, n, n, nn, nw, c->d_dinv, c->d_info + 2));
   // D <- E^{-1} D
-  LRIGW_TRY(ztrsm_left_lower(s, c->d_s2, n, nn, c->d_s1, n, nn, n, n, nw));
-  LRIGW_TRY(ztrsm_left_upper_conj(s, c->d_s2, n, nn, c->d_s1, n, nn, n, n, nw));
+  LRIGW_TRY(ztrsm_left_lower(s, c->d_s2, n, nn, c->d_dinv, c->d_s1, n, nn, n, n, nw));
+  LRIGW_TRY(ztrsm_left_upper_conj(s, c->d_s2, n, nn, c->d_dinv, c->d_s1, n, nn, n, n, nw));
   // W = -L (E^{-1} D) L^H
   LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_s1, n, nn, OP_C, c->d_LV, n, 0, c->d_s0, n, nn, one, nw)));
   LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_LV, n, 0, OP_N, c->d_s0, n, nn, c->d_s1, n, nn, mone, nw)));

@@ -13,120 +13,286 @@
 #include "lrigw_internal.h"
 #include "tiles.h"
 
-#define LP (TILE + 1)   // padded LDS row (complex elements)
+#define SKC 16          // nu rows staged per step
+#define SLP (TILE + 1)  // padded LDS row (complex elements)
 
+// One workgroup = 64 columns c (x rows) and every row mu of W^c.  Rows are
+// taken in groups of 64 aligned to the END of the range (the ragged group is
+// the first and costs the least); wave w owns rows 16w..16w+15 of a group and
+// all 64 columns (4 MFMA column tiles).  The contraction index nu runs in
+// chunks of 16 from 0 to the diagonal (strictly lower part only); LDS is double
+// buffered and the next chunk is fetched into registers while the current one
+// is multiplied.  The reduction over mu is accumulated in FP64.
 template <typename T>
 __global__ __launch_bounds__(256) void k_sigma_mfma(const typename c2t<T>::type *__restrict__ x, const typename c2t<T>::type *__restrict__ Wall,
-                                                    long long Ccols, int N, T *__restrict__ Xall) {
+                                                    long long Ccols, int N, double *__restrict__ Xall) {
   typedef typename c2t<T>::type C;
   typedef Mfma<T> MF;
   typedef typename MF::acc ACC;
-  __shared__ C Wt[TILE][LP];   // Wt[nu][mu] = W[mu][nu] (block I, J)
-  __shared__ C Ut[TILE][LP];   // Ut[nu][c]  = conj(x[c][nu])
-  __shared__ T red[2][TILE];
+  __shared__ C Ws[2][SKC][SLP];   // Ws[b][nu][mu] = W[mu][nu] for the current group
+  __shared__ C Us[2][SKC][SLP];   // Us[b][nu][c]  = conj(x[c][nu])
+  __shared__ double red[4][TILE];
 
   const C *W = Wall + (long long)blockIdx.y * N * N;
-  T *Xout = Xall + (long long)blockIdx.y * Ccols;
+  double *Xout = Xall + (long long)blockIdx.y * Ccols;
   const long long c0 = (long long)blockIdx.x * TILE;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1, col = lane & 15;
-  const int nt = (N + TILE - 1) / TILE;
-  T psum[2] = {(T)0, (T)0};
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15;
+  const int ngroups = (N + TILE - 1) / TILE;
+  const int base = N - ngroups * TILE;        // <= 0
+  double psum[4] = {0.0, 0.0, 0.0, 0.0};
+  // loader mapping: 16 consecutive threads read 16 consecutive nu of one row
+  const int lrow = tid >> 4, lk = tid & 15;    // rows lrow + 16*t, t = 0..3
 
-  for (int I = 0; I < nt; ++I) {
-    const int mu0 = I * TILE;
-    ACC zr[2][2], zi[2][2];
+  for (int I = 0; I < ngroups; ++I) {
+    const int mu0 = base + I * TILE;
+    const int nch = (mu0 + TILE - 2) / SKC + 1;   // chunks covering nu <= mu0 + 62
+    const int r0 = mu0 + 16 * wave;               // this wave's first row
+    const bool active = (r0 + 15 >= 0);
+    const int kcw = active ? (r0 + 14) / SKC + 1 : 0;   // chunks this wave needs (nu <= r0 + 14)
+    ACC zr[4], zi[4];
 #pragma unroll
-    for (int si = 0; si < 2; ++si)
+    for (int j = 0; j < 4; ++j) {
+      zr[j] = MF::zero();
+      zi[j] = MF::zero();
+    }
+    C wreg[4], ureg[4];
+    auto fetch = [&](int ch) {
+      const int nu = ch * SKC + lk;
 #pragma unroll
-      for (int sj = 0; sj < 2; ++sj) {
-        zr[si][sj] = MF::zero();
-        zi[si][sj] = MF::zero();
-      }
-    for (int J = 0; J <= I; ++J) {
-      const int nu0 = J * TILE;
-      const bool diag = (J == I);
-      __syncthreads();
-      // W block rows mu (64) x cols nu (64), 16 consecutive nu per thread group
-#pragma unroll 4
-      for (int t = 0; t < (TILE * TILE) / 256; ++t) {
-        int e = tid + 256 * t;
-        int m = e / TILE, kk = e % TILE;
-        int mu = mu0 + m, nu = nu0 + kk;
+      for (int t = 0; t < 4; ++t) {
+        const int m = lrow + 16 * t;
+        const int mu = mu0 + m;
         C w;
         w.x = w.y = (T)0;
-        if (mu < N && nu < N && (!diag || nu < mu)) w = W[(long long)mu * N + nu];
-        Wt[kk][m] = w;
-        long long cc = c0 + m;
+        if (mu >= 0 && mu < N && nu < mu) w = W[(long long)mu * N + nu];
+        wreg[t] = w;
+        const long long cc = c0 + m;
         C u;
         u.x = u.y = (T)0;
         if (cc < Ccols && nu < N) u = cconj(x[cc * N + nu]);
-        Ut[kk][m] = u;
+        ureg[t] = u;
       }
-      __syncthreads();
-#pragma unroll 4
-      for (int ks = 0; ks < TILE / 4; ++ks) {
-        const int kk = ks * 4 + (lane >> 4);
-        C wv[2], uv[2];
+    };
+    auto stash = [&](int b) {
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-          wv[s] = Wt[kk][32 * wr + 16 * s + col];
-          uv[s] = Ut[kk][32 * wc + 16 * s + col];
+      for (int t = 0; t < 4; ++t) {
+        Ws[b][lk][lrow + 16 * t] = wreg[t];
+        Us[b][lk][lrow + 16 * t] = ureg[t];
+      }
+    };
+    __syncthreads();
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+      const int b = ch & 1;
+      if (ch + 1 < nch) fetch(ch + 1);
+      if (ch < kcw) {
+#pragma unroll
+        for (int ks = 0; ks < SKC / 4; ++ks) {
+          const int kk = ks * 4 + (lane >> 4);
+          const C a = Ws[b][kk][16 * wave + col];
+          C u[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) u[j] = Us[b][kk][16 * j + col];
+          // Z += W u: re = Wr ur - Wi ui, im = Wr ui + Wi ur
+#pragma unroll
+          for (int j = 0; j < 4; ++j) zr[j] = MF::mac(a.x, u[j].x, zr[j]);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) zi[j] = MF::mac(a.x, u[j].y, zi[j]);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) zr[j] = MF::mac(-a.y, u[j].y, zr[j]);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) zi[j] = MF::mac(a.y, u[j].x, zi[j]);
         }
-#pragma unroll
-        for (int si = 0; si < 2; ++si)
-#pragma unroll
-          for (int sj = 0; sj < 2; ++sj) {
-            // Z += W u: re = Wr ur - Wi ui, im = Wr ui + Wi ur
-            zr[si][sj] = MF::mac(wv[si].x, uv[sj].x, zr[si][sj]);
-            zr[si][sj] = MF::mac(-wv[si].y, uv[sj].y, zr[si][sj]);
-            zi[si][sj] = MF::mac(wv[si].x, uv[sj].y, zi[si][sj]);
-            zi[si][sj] = MF::mac(wv[si].y, uv[sj].x, zi[si][sj]);
-          }
       }
+      if (ch + 1 < nch) stash(b ^ 1);
+      __syncthreads();
     }
-    // epilogue of row block I: Ut holds conj(x) of block I (last J == I)
+    // epilogue of the group: X_c += 2 Re(x_mu Z_mu) + Re W_mumu |x_mu|^2 over this wave's rows
+    if (active) {
 #pragma unroll
-    for (int si = 0; si < 2; ++si)
-#pragma unroll
-      for (int sj = 0; sj < 2; ++sj)
+      for (int j = 0; j < 4; ++j) {
+        const long long cc = c0 + 16 * j + col;
+        if (cc >= Ccols) continue;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int ml = 32 * wr + 16 * si + MF::row(lane, q);
-          const int cl = 32 * wc + 16 * sj + col;
-          const int mu = mu0 + ml;
-          if (mu < N) {
-            C u = Ut[ml][cl];                       // conj(x_mu)
-            T xr = u.x, xi = -u.y;                  // x_mu
-            T wdd = (T)W[(long long)mu * N + mu].x;
-            // 2 Re(x Z) + Re W_mumu |x|^2
-            psum[sj] += (T)2 * (xr * zr[si][sj][q] - xi * zi[si][sj][q]) + wdd * (xr * xr + xi * xi);
-          }
+          const int mu = r0 + MF::row(lane, q);
+          if (mu < 0 || mu >= N) continue;
+          const C xv = x[cc * N + mu];
+          const double wdd = (double)W[(long long)mu * N + mu].x;
+          const double xr = (double)xv.x, xi = (double)xv.y;
+          psum[j] += 2.0 * (xr * (double)zr[j][q] - xi * (double)zi[j][q]) + wdd * (xr * xr + xi * xi);
         }
+      }
+    }
   }
   // lanes l, l^16, l^32, l^48 hold the same column
 #pragma unroll
-  for (int sj = 0; sj < 2; ++sj) {
-    T v = psum[sj];
+  for (int j = 0; j < 4; ++j) {
+    double v = psum[j];
     v += __shfl_xor(v, 16);
     v += __shfl_xor(v, 32);
-    psum[sj] = v;
+    psum[j] = v;
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[wave][16 * j + lane] = psum[j];
+  }
+  __syncthreads();
+  if (tid < TILE) {
+    const long long cc = c0 + tid;
+    if (cc < Ccols) Xout[cc] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+  }
+}
+
+// Split-BF16 form: W^c and conj(x) are split into NS BF16 parts when staged in
+// LDS, products of parts p + q < NS are accumulated by the 16x16x32 BF16 MFMA
+// in FP32.  Same work decomposition as k_sigma_mfma, nu chunks of 32.
+#define SKB 32
+#define SBP 8
+
+template <int NS>
+__device__ inline void splitn_s(float v, __bf16 *p) {
+  float r = v;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    p[i] = (__bf16)r;
+    r -= (float)p[i];
+  }
+}
+
+template <int NS>
+__global__ __launch_bounds__(256) void k_sigma_bf16(const float2 *__restrict__ x, const float2 *__restrict__ Wall, long long Ccols,
+                                                    int N, double *__restrict__ Xall) {
+  __shared__ __bf16 Wr[NS][TILE][SKB + SBP], Wi[NS][TILE][SKB + SBP];   // [part][mu][nu]
+  __shared__ __bf16 Ur[NS][TILE][SKB + SBP], Ui[NS][TILE][SKB + SBP];   // [part][c][nu] of conj(x)
+  __shared__ double red[4][TILE];
+  const float2 *W = Wall + (long long)blockIdx.y * N * N;
+  double *Xout = Xall + (long long)blockIdx.y * Ccols;
+  const long long c0 = (long long)blockIdx.x * TILE;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, g = lane >> 4;
+  const int ngroups = (N + TILE - 1) / TILE;
+  const int base = N - ngroups * TILE;
+  double psum[4] = {0.0, 0.0, 0.0, 0.0};
+  const int lrow = tid >> 5, lk = tid & 31;     // 32 consecutive threads read 32 nu of one row; rows lrow + 8 t
+
+  for (int I = 0; I < ngroups; ++I) {
+    const int mu0 = base + I * TILE;
+    const int nch = (mu0 + TILE - 2 >= 0) ? (mu0 + TILE - 2) / SKB + 1 : 1;
+    const int r0 = mu0 + 16 * wave;
+    const bool active = (r0 + 15 >= 0);
+    const int kcw = active ? ((r0 + 14 >= 0) ? (r0 + 14) / SKB + 1 : 1) : 0;
+    f4v zr[4], zi[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) zr[j] = zi[j] = Mfma<float>::zero();
+    float2 wreg[8], ureg[8];
+    auto fetch = [&](int ch) {
+      const int nu = ch * SKB + lk;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int m = lrow + 8 * t;
+        const int mu = mu0 + m;
+        float2 w = mkcf(0.f, 0.f);
+        if (mu >= 0 && mu < N && nu < mu) w = W[(long long)mu * N + nu];
+        wreg[t] = w;
+        const long long cc = c0 + m;
+        float2 u = mkcf(0.f, 0.f);
+        if (cc < Ccols && nu < N) u = cconj(x[cc * N + nu]);
+        ureg[t] = u;
+      }
+    };
+    auto stash = [&]() {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int m = lrow + 8 * t;
+        __bf16 a[NS], b[NS], c[NS], d[NS];
+        splitn_s<NS>(wreg[t].x, a);
+        splitn_s<NS>(wreg[t].y, b);
+        splitn_s<NS>(ureg[t].x, c);
+        splitn_s<NS>(ureg[t].y, d);
+#pragma unroll
+        for (int p = 0; p < NS; ++p) {
+          Wr[p][m][lk] = a[p];
+          Wi[p][m][lk] = b[p];
+          Ur[p][m][lk] = c[p];
+          Ui[p][m][lk] = d[p];
+        }
+      }
+    };
+    fetch(0);
+    for (int ch = 0; ch < nch; ++ch) {
+      __syncthreads();
+      stash();
+      __syncthreads();
+      if (ch + 1 < nch) fetch(ch + 1);
+      if (ch < kcw) {
+        bf16x8 ar[NS], ai[NS], nai[NS];
+#pragma unroll
+        for (int p = 0; p < NS; ++p) {
+          ar[p] = *(const bf16x8 *)&Wr[p][16 * wave + col][8 * g];
+          ai[p] = *(const bf16x8 *)&Wi[p][16 * wave + col][8 * g];
+          nai[p] = -ai[p];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          bf16x8 ur[NS], ui[NS];
+#pragma unroll
+          for (int p = 0; p < NS; ++p) {
+            ur[p] = *(const bf16x8 *)&Ur[p][16 * j + col][8 * g];
+            ui[p] = *(const bf16x8 *)&Ui[p][16 * j + col][8 * g];
+          }
+          // Z += W u: re = Wr ur - Wi ui, im = Wr ui + Wi ur
+#pragma unroll
+          for (int p = 0; p < NS; ++p)
+#pragma unroll
+            for (int q = 0; q + p < NS; ++q) {
+              zr[j] = mfma_bf16(ar[p], ur[q], zr[j]);
+              zr[j] = mfma_bf16(nai[p], ui[q], zr[j]);
+              zi[j] = mfma_bf16(ar[p], ui[q], zi[j]);
+              zi[j] = mfma_bf16(ai[p], ur[q], zi[j]);
+            }
+        }
+      }
+    }
+    if (active) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const long long cc = c0 + 16 * j + col;
+        if (cc >= Ccols) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int mu = r0 + Mfma<float>::row(lane, q);
+          if (mu < 0 || mu >= N) continue;
+          const float2 xv = x[cc * N + mu];
+          const double wdd = (double)W[(long long)mu * N + mu].x;
+          const double xr = (double)xv.x, xi = (double)xv.y;
+          psum[j] += 2.0 * (xr * (double)zr[j][q] - xi * (double)zi[j][q]) + wdd * (xr * xr + xi * xi);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    double v = psum[j];
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    psum[j] = v;
   }
   __syncthreads();
   if (lane < 16) {
 #pragma unroll
-    for (int sj = 0; sj < 2; ++sj) red[wr][32 * wc + 16 * sj + lane] = psum[sj];
+    for (int j = 0; j < 4; ++j) red[wave][16 * j + lane] = psum[j];
   }
   __syncthreads();
   if (tid < TILE) {
-    long long cc = c0 + tid;
-    if (cc < Ccols) Xout[cc] = red[0][tid] + red[1][tid];
+    const long long cc = c0 + tid;
+    if (cc < Ccols) Xout[cc] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
   }
 }
 
 // sigma[k][n][i] += scale * sum_m sum_j g_j X[j][k][n][m] a/(a^2 + w_j^2),  a = i w_i + mu - e_m(k-q)
-template <typename T>
-__global__ void k_sigma_freq(const T *__restrict__ X, const double *__restrict__ eig, const int *__restrict__ kmq, int iq,
+__global__ void k_sigma_freq(const double *__restrict__ X, const double *__restrict__ eig, const int *__restrict__ kmq, int iq,
                              int nk, int n_qp, int n_bands, int n_freq, const double *__restrict__ omega,
                              const double *__restrict__ weight, double mu, double scale, double2 *__restrict__ sigma) {
   long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -142,7 +308,7 @@ __global__ void k_sigma_freq(const T *__restrict__ X, const double *__restrict__
   for (int m = 0; m < n_bands; ++m) {
     const double ar = mu - eig[(long long)k2 * n_bands + m];
     const double ai = wi;
-    const T *xp = X + ((long long)k * n_qp + n) * n_bands + m;
+    const double *xp = X + ((long long)k * n_qp + n) * n_bands + m;
     for (int j = 0; j < n_freq; ++j) {
       const double wj = omega[j];
       const double dr = ar * ar - ai * ai + wj * wj, di = 2.0 * ar * ai;
@@ -170,20 +336,22 @@ int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const doubl
   if (c->precision == LRIGW_FP64)
     hipLaunchKernelGGL(k_sigma_mfma<double>, grid, dim3(256), 0, c->stream, (const double2 *)x, (const double2 *)Wc, Ccols,
                        d.n_aux, (double *)c->d_X);
-  else
+  else if (c->precision == LRIGW_FP32)
     hipLaunchKernelGGL(k_sigma_mfma<float>, grid, dim3(256), 0, c->stream, (const float2 *)x, (const float2 *)Wc, Ccols,
-                       d.n_aux, (float *)c->d_X);
+                       d.n_aux, (double *)c->d_X);
+  else if (c->precision == LRIGW_SPLIT_BF16)
+    hipLaunchKernelGGL(k_sigma_bf16<2>, grid, dim3(256), 0, c->stream, (const float2 *)x, (const float2 *)Wc, Ccols,
+                       d.n_aux, (double *)c->d_X);
+  else
+    hipLaunchKernelGGL(k_sigma_bf16<3>, grid, dim3(256), 0, c->stream, (const float2 *)x, (const float2 *)Wc, Ccols,
+                       d.n_aux, (double *)c->d_X);
   stage_end(c, "sigma_mfma", ev);
   LRIGW_TRY(lrigw_launch_check("sigma_mfma"));
   long long tot = (long long)d.n_k * d.n_qp * d.n_freq;
   dim3 g2((unsigned)((tot + 127) / 128));
   const double scale = -1.0 / (M_PI * d.n_k);
-  if (c->precision == LRIGW_FP64)
-    hipLaunchKernelGGL(k_sigma_freq<double>, g2, dim3(128), 0, c->stream, (const double *)c->d_X, eig, c->d_kmq, iq, d.n_k,
-                       d.n_qp, d.n_bands, d.n_freq, c->d_omega, c->d_weight, d.mu, scale, (double2 *)sigma_acc);
-  else
-    hipLaunchKernelGGL(k_sigma_freq<float>, g2, dim3(128), 0, c->stream, (const float *)c->d_X, eig, c->d_kmq, iq, d.n_k,
-                       d.n_qp, d.n_bands, d.n_freq, c->d_omega, c->d_weight, d.mu, scale, (double2 *)sigma_acc);
+  hipLaunchKernelGGL(k_sigma_freq, g2, dim3(128), 0, c->stream, (const double *)c->d_X, eig, c->d_kmq, iq, d.n_k, d.n_qp,
+                     d.n_bands, d.n_freq, c->d_omega, c->d_weight, d.mu, scale, (double2 *)sigma_acc);
   LRIGW_TRY(lrigw_launch_check("sigma_freq"));
   stage_end(c, "sigma_c", ev_all);
   return LRIGW_OK;

@@ -86,6 +86,7 @@ struct lrigw_ctx {
   void *d_X = nullptr;           // [N_w][N_k*n_qp*n_bands] pair weights (T)
   double2 *d_LV = nullptr;       // [N][N]
   double2 *d_s0 = nullptr, *d_s1 = nullptr, *d_s2 = nullptr, *d_s3 = nullptr;  // [N_w][N][N]
+  double2 *d_dinv = nullptr;     // inverses of 64x64 diagonal Cholesky blocks, [N_w][zdinv_stride(N)]
   int *d_info = nullptr;         // device status words
   void *d_bhat = nullptr;        // q = 0 modified B (T)
 
@@ -137,8 +138,9 @@ struct ZGemm {
   int lower_only;                          // skip tiles strictly above the diagonal
 };
 int zgemm(hipStream_t s, const ZGemm &g);
-int zpotrf_batched(hipStream_t s, double2 *A, int n, long long lda, long long stride, int batch, int *d_info);
-int ztrsm_left_lower(hipStream_t s, const double2 *L, long long ldl, long long sl, double2 *Y, long long ldy,
-                     long long sy, int n, int ncols, int batch);
-int ztrsm_left_upper_conj(hipStream_t s, const double2 *L, long long ldl, long long sl, double2 *Y, long long ldy,
-                          long long sy, int n, int ncols, int batch);
+long long zdinv_stride(int n);
+int zpotrf_batched(hipStream_t s, double2 *A, int n, long long lda, long long stride, int batch, double2 *Dinv, int *d_info);
+int ztrsm_left_lower(hipStream_t s, const double2 *L, long long ldl, long long sl, const double2 *Dinv, double2 *Y,
+                     long long ldy, long long sy, int n, int ncols, int batch);
+int ztrsm_left_upper_conj(hipStream_t s, const double2 *L, long long ldl, long long sl, const double2 *Dinv, double2 *Y,
+                          long long ldy, long long sy, int n, int ncols, int batch);

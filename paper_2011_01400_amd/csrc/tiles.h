@@ -29,3 +29,14 @@ template <> struct Mfma<double> {
   __device__ static inline acc mac(double a, double b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
   __device__ static inline int row(int lane, int r) { return (lane >> 4) + 4 * r; }
 };
+
+// BF16 16x16x32 (gfx950): A lane l holds A[l % 16][8*(l/16) .. 8*(l/16)+7],
+// B lane l holds B[8*(l/16) .. +7][l % 16]; output as FP32 16x16x4.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+__device__ inline f4v mfma_bf16(bf16x8 a, bf16x8 b, f4v c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+
+// x = hi + lo with hi = bf16(x), lo = bf16(x - hi)
+__device__ inline void split_bf16(float x, __bf16 &hi, __bf16 &lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
