@@ -187,6 +187,120 @@ int lrigw_g0w0(lrigw_ctx *ctx, const void *H, const void *evec, const double *ei
                double omega_cell, const double *e_static, int n_par, int q_first, int q_last,
                void *sigma, double *e_qp, double *z, int *info);
 
+/* ---- Learned frequency surrogate of the response (a form the paper does not
+ * have; it evaluates Eq. chi0_matrix at every frequency of the grid).
+ *
+ * Per q the response is computed exactly at n_anchor anchor indices
+ * j (n_freq-1)/(n_anchor-1) (rounded half up) and at one held-out index midway
+ * between the two middle anchors; at every other index t it is predicted as
+ *   chi(w_t) = sum_l C[l][t] chi(w_l) + U R_t U^H,
+ * where C is a least-squares interpolation rule for the transition kernel
+ * 2D/(D^2 + w^2) over D in [d_lo, d_hi] (256 log-spaced D, anchor columns
+ * scaled to unit norm, ridge 1e-12), U (N_aux x rank) is an orthonormal basis
+ * of the dominant eigenspace of -chi(w_anchor0) (4 block subspace-iteration
+ * products from the caller's start block, Cholesky QR after each), and R_t is
+ * the rule's residual on the rank x rank projection U^H chi U, predicted by a
+ * network from the anchor values of each of its rank^2 real series (Re P_ij
+ * for i <= j, Im P_ij for i > j) scaled by s = sign(a_0) |a|:
+ *   h1 = tanh(x W1 + b1), h2 = tanh(h1 W2 + b2), y = h2 W3 + b3,
+ * x = a/s (n_anchor inputs), y = residual/s at the n_out non-anchor indices.
+ * Parameters: FP32 flat vector W1 [n_anchor][H], b1 [H], W2 [H][H], b2 [H],
+ * W3 [H][n_out], b3 [n_out]; the products use the BF16-rounded copy with FP32
+ * activations and accumulation.  If the relative Frobenius error of the
+ * prediction at the held-out index exceeds `threshold`, every other index of
+ * that q is recomputed exactly (decided on the device).  The surrogate serves
+ * every context with the same N_aux, n_freq and x0 as the one it was created
+ * with, and runs on that context's stream. */
+typedef struct lrigw_surrogate lrigw_surrogate;
+
+/* init_params: device FP32 [n_params] (see lrigw_surrogate_info); start:
+ * device FP64 [N_aux][rank] (real); row_capacity: training rows to reserve
+ * (rank^2 per added q).  Errors: ERR_ARG (n_anchor outside 4..16,
+ * n_freq < n_anchor + 2, rank > N_aux or > 256, d_hi <= d_lo or d_lo <= 0),
+ * ERR_OOM. */
+int lrigw_surrogate_create(lrigw_ctx *ctx, int rank, int n_anchor, int hidden, double d_lo, double d_hi,
+                           long long row_capacity, const float *init_params, const double *start,
+                           lrigw_surrogate **out);
+int lrigw_surrogate_destroy(lrigw_surrogate *sg);
+/* ints (host, 6): n_anchor, n_out, held-out grid index, its position among
+ * the n_out non-anchor indices, rank, hidden; n_params (host). */
+int lrigw_surrogate_info(const lrigw_surrogate *sg, int *ints, long long *n_params);
+/* The rule C (device FP64 [n_anchor][n_out]). */
+int lrigw_surrogate_rule(const lrigw_surrogate *sg, double *C);
+/* Copy the FP32 parameters out (get) and/or replace them (set; resets Adam). */
+int lrigw_surrogate_params(lrigw_surrogate *sg, float *get, const float *set);
+/* The basis U (device complex128 [N_aux][rank]) of chi_a0 (complex T
+ * [N_aux][N_aux] of ctx's precision). */
+int lrigw_surrogate_basis(lrigw_surrogate *sg, lrigw_ctx *ctx, const void *chi_a0, void *U_out);
+/* Append the rank^2 training rows of one q from the exact response chi
+ * (complex T [n_freq][N_aux][N_aux]): x = scaled anchor values, target = the
+ * rule's residual at the non-anchor indices in units of s.  Synchronous.
+ * Errors: ERR_ARG (capacity), ERR_NOT_HPD (basis rank-deficient). */
+int lrigw_surrogate_add(lrigw_surrogate *sg, lrigw_ctx *ctx, const void *chi);
+/* Row count (host) and rows first..first+count-1 (device FP32 x
+ * [count][n_anchor], y [count][n_out]; either may be NULL). */
+int lrigw_surrogate_rows(lrigw_surrogate *sg, long long *n_rows, float *x, float *y, long long first, long long count);
+/* Network output y (device FP32 [n_rows][n_out]) for inputs x [n_rows][n_anchor]. */
+int lrigw_surrogate_forward(lrigw_surrogate *sg, const float *x, int n_rows, float *y);
+/* Mean-squared loss (device float[1]) and its gradient (device FP32
+ * [n_params]) for rows x, y; no update. */
+int lrigw_surrogate_grad(lrigw_surrogate *sg, const float *x, const float *y, int n_rows, float *loss, float *grad);
+/* `steps` Adam steps (beta 0.9/0.999, eps 1e-8, learning rate lr) on batches
+ * of the stored rows: step s uses rows order[s*batch .. s*batch+batch-1]
+ * (device int32, order_len >= steps*batch).  loss_hist: device float[steps]
+ * or NULL. */
+int lrigw_surrogate_train(lrigw_surrogate *sg, int steps, int batch, double lr, const int *order, long long order_len,
+                          float *loss_hist);
+/* Response of one q with the surrogate (arguments as lrigw_chi0). */
+int lrigw_chi0_surrogate(lrigw_ctx *ctx, lrigw_surrogate *sg, int iq, const void *M, const double *eig, int apply_gamma,
+                         double threshold, void *chi_out);
+/* Make lrigw_g0w0 use the surrogate for every q (sg = NULL: exact). */
+int lrigw_set_surrogate(lrigw_ctx *ctx, lrigw_surrogate *sg, double threshold);
+/* Calls so far (host), fallbacks (host int), and the held-out errors of the
+ * first max_errors calls (host FP64).  Synchronises the stream. */
+int lrigw_surrogate_stats(lrigw_surrogate *sg, long long *n_calls, int *n_fallback, double *errors, int max_errors);
+int lrigw_surrogate_reset_stats(lrigw_surrogate *sg);
+
+/* ---- Batched form: several cells (uneven basis and auxiliary sizes, each
+ * with its own context and precision) in one hipGraph.  The graph holds the
+ * whole pass of every cell (lrigw_g0w0's q loop and QP step; cells on
+ * separate streams inside the graph); lrigw_batch_run replays it with one
+ * launch.  Everything that needs the host (gap check, q = 0 preparation,
+ * buffers, tuning) is done by lrigw_batch_create.  With autotune != 0 the
+ * response kernel of every cell is timed on one q over its tile choices
+ * (frequencies per workgroup, K split count) and the fastest is kept.
+ * The arrays a cell names must stay valid while the batch exists; inputs may
+ * change between runs (same addresses). */
+typedef struct {
+  lrigw_ctx *ctx;                 /* one context per cell */
+  const void *H, *evec;           /* lrigw_lri_ft output, eigenvectors (device) */
+  const double *eig;              /* FP64 [N_k][n_bands] (device) */
+  const void *V, *p;              /* as lrigw_g0w0; p may be NULL */
+  double omega_cell;
+  const double *e_static;         /* FP64 [N_k][n_qp] or NULL */
+  int n_par;                      /* Pade points (1..64) */
+  void *sigma;                    /* complex128 [N_k][n_qp][n_freq] output */
+  double *e_qp, *z;               /* FP64 [N_k][n_qp] outputs */
+} lrigw_batch_cell;
+typedef struct lrigw_batch lrigw_batch;
+
+/* hip_stream must be a created stream (not the legacy default stream).  A
+ * surrogate attached with lrigw_set_surrogate is captured too (its call
+ * statistics then count the capture, not the replays).
+ * Errors: ERR_ARG (NULL arrays, a context used twice), ERR_NOT_HPD /
+ * ERR_NOCONV from the q = 0 preparation, ERR_HIP (capture). */
+int lrigw_batch_create(lrigw_batch **out, int n_cells, const lrigw_batch_cell *cells, int autotune, void *hip_stream);
+/* One launch of the captured graph on hip_stream (asynchronous). */
+int lrigw_batch_run(lrigw_batch *b);
+/* After a run (synchronises): status[3*i + 0] = first q of cell i whose V or
+ * eps~ was not positive definite, or -1; [3*i + 1] = QP equations without a
+ * root; [3*i + 2] = truncated Pade fits. */
+int lrigw_batch_status(lrigw_batch *b, int *status);
+/* The tuned tile choice of a cell and its measured time (ms, -1 untuned). */
+int lrigw_batch_tuning(const lrigw_batch *b, int cell, int *nw, int *splits, double *ms);
+int lrigw_batch_graph_nodes(const lrigw_batch *b, long long *n_nodes);
+int lrigw_batch_destroy(lrigw_batch *b);
+
 /* Per-kernel device time (ms, HIP events on the context stream) accumulated
  * since the last reset, for the named stages "build_M", "chi0", "screen",
  * "sigma_c", "qp", "lri_ft".  Timing is recorded only after

@@ -1,4 +1,5 @@
 // C interface of the lrigw library: context, validation, driver, timing.
+#include <climits>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -39,9 +40,9 @@ void stage_end(lrigw_ctx *c, const char *name, hipEvent_t ev) {
 }
 
 static void free_all(lrigw_ctx *c) {
-  void *ptrs[] = {c->d_aux_atom, c->d_basis_off, c->d_aux_off, c->d_kpq, c->d_kmq, c->d_omega, c->d_weight,
+  void *ptrs[] = {c->d_aux_atom, c->d_basis_off, c->d_aux_off, c->d_kpq, c->d_kmq, c->d_omega, c->d_weight, c->d_wall,
                   c->d_delta, c->d_part, c->d_X, c->d_LV, c->d_s0, c->d_s1, c->d_s2, c->d_s3, c->d_dinv, c->d_info,
-                  c->d_bhat, c->d_x1, c->d_M, c->d_x, c->d_chi, c->d_wc};
+                  c->d_bhat, c->d_x1, c->d_M, c->d_x, c->d_chi, c->d_wc, c->d_epsqp};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &kv : c->stages)
@@ -49,6 +50,63 @@ static void free_all(lrigw_ctx *c) {
       hipEventDestroy(pr.first);
       hipEventDestroy(pr.second);
     }
+}
+
+// eps_qp[k][n] = eig[k][qp_lo + n]
+__global__ void k_qp_bands(const double *__restrict__ eig, int n_k, int n_bands, int qp_lo, int n_qp, double *__restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_k * n_qp) return;
+  out[i] = eig[(long long)(i / n_qp) * n_bands + qp_lo + i % n_qp];
+}
+
+__global__ void k_set_int(int *p, int v) { p[threadIdx.x] = v; }
+
+int driver_buffers(lrigw_ctx *c) {
+  const Dims &d = c->d;
+  size_t cs = lrigw_csize(c);
+  if (!c->d_M) LRIGW_HIP_TRY(hipMalloc(&c->d_M, (size_t)lrigw_K(c) * d.n_aux * cs));
+  if (!c->d_x) LRIGW_HIP_TRY(hipMalloc(&c->d_x, (size_t)d.n_k * d.n_qp * d.n_bands * d.n_aux * cs));
+  if (!c->d_chi) LRIGW_HIP_TRY(hipMalloc(&c->d_chi, (size_t)d.n_freq * d.n_aux * d.n_aux * cs));
+  if (!c->d_wc) LRIGW_HIP_TRY(hipMalloc(&c->d_wc, (size_t)d.n_freq * d.n_aux * d.n_aux * cs));
+  if (!c->d_epsqp) LRIGW_HIP_TRY(hipMalloc(&c->d_epsqp, (size_t)d.n_k * d.n_qp * sizeof(double)));
+  return LRIGW_OK;
+}
+
+// One pass over q_first..q_last-1 (and the QP step when every q was done).
+// With c->capturing the pass makes no host round trip: the screening status
+// is folded into d_info[16] and the QP flags stay in d_info[8..9].
+int run_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *p, double omega_cell,
+             const double *e_static, int n_par, int q_first, int q_last, void *sigma, double *e_qp, double *z, int *info) {
+  (void)omega_cell;
+  const Dims &d = c->d;
+  const bool all_q = (q_first == 0 && q_last == d.n_k);
+  hipStream_t s = c->stream;
+  LRIGW_TRY(zero_fill(s, sigma, (size_t)d.n_k * d.n_qp * d.n_freq * sizeof(double2)));
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->d_info + 16, INT_MAX);
+  size_t vstride = (size_t)d.n_aux * d.n_aux;
+  for (int q = q_first; q < q_last; ++q) {
+    LRIGW_TRY(lrigw_build_M(c, q, 0, H, evec, c->d_M));
+    const int g = (p && q == 0) ? 1 : 0;
+    if (c->sur) LRIGW_TRY(lrigw_chi0_surrogate(c, c->sur, q, c->d_M, eig, g, c->sur_threshold, c->d_chi));
+    else LRIGW_TRY(lrigw_chi0(c, q, c->d_M, eig, g, c->d_chi));
+    int sinfo = -1;
+    int rc = lrigw_screen(c, q, c->d_chi, (const double2 *)V + q * vstride, c->d_wc, &sinfo);
+    if (rc < 0) {
+      if (info) *info = q;
+      return rc;
+    }
+    LRIGW_TRY(lrigw_build_M(c, q, 1, H, evec, c->d_x));
+    LRIGW_TRY(lrigw_sigma_c(c, q, c->d_x, c->d_wc, eig, sigma));
+  }
+  if (!all_q) return LRIGW_OK;
+  const int nkq = d.n_k * d.n_qp;
+  hipLaunchKernelGGL(k_qp_bands, dim3((nkq + 255) / 256), dim3(256), 0, s, eig, d.n_k, d.n_bands, d.qp_lo, d.n_qp,
+                     c->d_epsqp);
+  LRIGW_TRY(lrigw_launch_check("qp_bands"));
+  int qinfo = 0;
+  int rc = lrigw_qp(c, sigma, c->d_epsqp, e_static, n_par, e_qp, z, &qinfo);
+  if (info) *info = qinfo;
+  return rc;
 }
 
 extern "C" {
@@ -188,6 +246,22 @@ int lrigw_chi0(lrigw_ctx *c, int iq, const void *M, const double *eig, int apply
   return run_chi0(c, iq, M, eig, apply_gamma, chi_out);
 }
 
+int lrigw_chi0_surrogate(lrigw_ctx *c, lrigw_surrogate *sg, int iq, const void *M, const double *eig, int apply_gamma,
+                         double threshold, void *chi_out) {
+  (void)hipGetLastError();  // drop a stale error another library left behind
+  if (!c || !sg || !M || !eig || !chi_out || !(threshold >= 0.0)) return LRIGW_ERR_ARG;
+  if (iq < 0 || iq >= c->d.n_k) return LRIGW_ERR_ARG;
+  if (apply_gamma && (iq != 0 || !c->gamma_ready)) return LRIGW_ERR_ARG;
+  return run_chi0_surrogate(c, sg, iq, M, eig, apply_gamma, threshold, chi_out);
+}
+
+int lrigw_set_surrogate(lrigw_ctx *c, lrigw_surrogate *sg, double threshold) {
+  if (!c || (sg && !(threshold >= 0.0))) return LRIGW_ERR_ARG;
+  c->sur = sg;
+  c->sur_threshold = threshold;
+  return LRIGW_OK;
+}
+
 int lrigw_gamma_prepare(lrigw_ctx *c, const void *Vcut0, const void *p, double omega_cell) {
   (void)hipGetLastError();  // drop a stale error another library left behind
   if (!c || !Vcut0 || !p || !(omega_cell > 0.0)) return LRIGW_ERR_ARG;
@@ -227,43 +301,16 @@ int lrigw_qp(lrigw_ctx *c, const void *sigma, const double *eps_qp, const double
 int lrigw_g0w0(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *p,
                double omega_cell, const double *e_static, int n_par, int q_first, int q_last, void *sigma,
                double *e_qp, double *z, int *info) {
+  (void)hipGetLastError();
   if (!c || !H || !evec || !eig || !V || !sigma) return LRIGW_ERR_ARG;
   const Dims &d = c->d;
   if (q_first < 0 || q_last > d.n_k || q_first >= q_last) return LRIGW_ERR_ARG;
   bool all_q = (q_first == 0 && q_last == d.n_k);
   if (all_q && (!e_qp || !z)) return LRIGW_ERR_ARG;
-  size_t cs = lrigw_csize(c);
-  if (!c->d_M) LRIGW_HIP_TRY(hipMalloc(&c->d_M, (size_t)lrigw_K(c) * d.n_aux * cs));
-  if (!c->d_x) LRIGW_HIP_TRY(hipMalloc(&c->d_x, (size_t)d.n_k * d.n_qp * d.n_bands * d.n_aux * cs));
-  if (!c->d_chi) LRIGW_HIP_TRY(hipMalloc(&c->d_chi, (size_t)d.n_freq * d.n_aux * d.n_aux * cs));
-  if (!c->d_wc) LRIGW_HIP_TRY(hipMalloc(&c->d_wc, (size_t)d.n_freq * d.n_aux * d.n_aux * cs));
+  if (n_par < 1 || n_par > 64) return LRIGW_ERR_ARG;
+  LRIGW_TRY(driver_buffers(c));
   if (p && q_first == 0) LRIGW_TRY(lrigw_gamma_prepare(c, V, p, omega_cell));
-  LRIGW_TRY(zero_fill(c->stream, sigma, (size_t)d.n_k * d.n_qp * d.n_freq * sizeof(double2)));
-  size_t vstride = (size_t)d.n_aux * d.n_aux;
-  for (int q = q_first; q < q_last; ++q) {
-    LRIGW_TRY(lrigw_build_M(c, q, 0, H, evec, c->d_M));
-    LRIGW_TRY(lrigw_chi0(c, q, c->d_M, eig, (p && q == 0) ? 1 : 0, c->d_chi));
-    int sinfo = -1;
-    int rc = lrigw_screen(c, q, c->d_chi, (const double2 *)V + q * vstride, c->d_wc, &sinfo);
-    if (rc < 0) {
-      if (info) *info = q;
-      return rc;
-    }
-    LRIGW_TRY(lrigw_build_M(c, q, 1, H, evec, c->d_x));
-    LRIGW_TRY(lrigw_sigma_c(c, q, c->d_x, c->d_wc, eig, sigma));
-  }
-  if (!all_q) return LRIGW_OK;
-  // QP energies for the QP bands: eps_qp from eig on the device
-  double *eps_qp = nullptr;
-  LRIGW_HIP_TRY(hipMalloc(&eps_qp, (size_t)d.n_k * d.n_qp * sizeof(double)));
-  LRIGW_HIP_TRY(hipMemcpy2DAsync(eps_qp, d.n_qp * sizeof(double), eig + d.qp_lo, d.n_bands * sizeof(double),
-                                 d.n_qp * sizeof(double), d.n_k, hipMemcpyDeviceToDevice, c->stream));
-  int qinfo = 0;
-  int rc = lrigw_qp(c, sigma, eps_qp, e_static, n_par, e_qp, z, &qinfo);
-  hipStreamSynchronize(c->stream);
-  (void)hipFree(eps_qp);
-  if (info) *info = qinfo;
-  return rc;
+  return run_pass(c, H, evec, eig, V, p, omega_cell, e_static, n_par, q_first, q_last, sigma, e_qp, z, info);
 }
 
 int lrigw_set_timing(lrigw_ctx *c, int on) {

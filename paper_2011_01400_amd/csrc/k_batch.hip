@@ -1,0 +1,237 @@
+// Batched form: several cells of uneven basis / auxiliary size, every
+// (cell, q, w) job of a whole pass captured into one hipGraph and replayed
+// with a single launch.  Each cell runs on a stream of its own inside the
+// capture (fork/join through events), so the small kernels of different cells
+// overlap on the device.  Before capture an autotuner times the response
+// kernel of every cell over its tile choices (frequencies per workgroup, K
+// split count) and keeps the fastest.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "lrigw_internal.h"
+
+struct lrigw_batch {
+  std::vector<lrigw_batch_cell> cells;
+  hipStream_t stream = nullptr;
+  std::vector<hipStream_t> cs;
+  std::vector<hipStream_t> saved;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<int> nw, splits;
+  std::vector<double> ms;
+  long long launches = 0;
+};
+
+// Time the response kernel of one q for every (frequencies per workgroup,
+// split) candidate; keep the fastest.  Runs before capture.
+static int autotune_chi0(lrigw_ctx *c, const lrigw_batch_cell &cell, int *nw_out, int *S_out, double *ms_out) {
+  const Dims &d = c->d;
+  hipStream_t s = c->stream;
+  const int q = d.n_k > 1 ? 1 : 0;
+  LRIGW_TRY(run_build_M(c, q, 0, cell.H, cell.evec, c->d_M));
+  const int nw0 = c->chi_nw, S0 = c->chi_splits;
+  std::vector<int> nws = {chi0_default_nw(c->precision), chi0_alt_nw(c->precision)};
+  const int nt = (d.n_aux + 63) / 64;
+  const size_t ntile = (size_t)nt * (nt + 1) / 2;
+  const size_t per = (size_t)d.n_freq * ntile * 64 * 64 * lrigw_csize(c);
+  const long long Smax = std::max<long long>(1, (long long)(c->part_bytes / per));
+  double best = INFINITY;
+  int bnw = nw0, bS = S0;
+  hipEvent_t e0, e1;
+  LRIGW_HIP_TRY(hipEventCreate(&e0));
+  LRIGW_HIP_TRY(hipEventCreate(&e1));
+  const bool timing = c->timing;
+  c->timing = false;
+  for (int nw : nws) {
+    c->chi_nw = nw;
+    int Sp = 1;
+    LRIGW_TRY(chi0_plan_splits(c, &Sp));
+    std::vector<int> Ss = {std::max(1, Sp / 2), Sp, Sp * 2};
+    std::sort(Ss.begin(), Ss.end());
+    Ss.erase(std::unique(Ss.begin(), Ss.end()), Ss.end());
+    for (int S : Ss) {
+      if (S > Smax) continue;
+      if ((long long)S > std::max<long long>(1, lrigw_K(c) / 64)) continue;
+      c->chi_splits = S;
+      // warm-up then timed
+      LRIGW_TRY(run_chi0(c, q, c->d_M, cell.eig, 0, c->d_chi));
+      LRIGW_HIP_TRY(hipEventRecord(e0, s));
+      LRIGW_TRY(run_chi0(c, q, c->d_M, cell.eig, 0, c->d_chi));
+      LRIGW_HIP_TRY(hipEventRecord(e1, s));
+      LRIGW_HIP_TRY(hipEventSynchronize(e1));
+      float t = 0.f;
+      LRIGW_HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+      if (t < best) {
+        best = t;
+        bnw = nw;
+        bS = S;
+      }
+    }
+  }
+  c->timing = timing;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  c->chi_nw = bnw;
+  c->chi_splits = bS;
+  *nw_out = bnw;
+  *S_out = bS;
+  *ms_out = best;
+  return LRIGW_OK;
+}
+
+static void batch_free(lrigw_batch *b) {
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  for (hipStream_t s : b->cs)
+    if (s) hipStreamDestroy(s);
+  if (b->fork) hipEventDestroy(b->fork);
+  for (hipEvent_t e : b->join)
+    if (e) hipEventDestroy(e);
+}
+
+static int batch_capture(lrigw_batch *b) {
+  const int n = (int)b->cells.size();
+  LRIGW_HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  int rc = LRIGW_OK;
+  hipError_t he = hipEventRecord(b->fork, b->stream);
+  for (int i = 0; i < n && rc == LRIGW_OK && he == hipSuccess; ++i) {
+    lrigw_batch_cell &cl = b->cells[i];
+    lrigw_ctx *c = cl.ctx;
+    he = hipStreamWaitEvent(b->cs[i], b->fork, 0);
+    if (he != hipSuccess) break;
+    b->saved[i] = c->stream;
+    c->stream = b->cs[i];
+    c->capturing = true;
+    const bool timing = c->timing;
+    c->timing = false;
+    rc = run_pass(c, cl.H, cl.evec, cl.eig, cl.V, cl.p, cl.omega_cell, cl.e_static, cl.n_par, 0, c->d.n_k, cl.sigma,
+                  cl.e_qp, cl.z, nullptr);
+    c->timing = timing;
+    c->capturing = false;
+    c->stream = b->saved[i];
+    if (rc == LRIGW_OK) he = hipEventRecord(b->join[i], b->cs[i]);
+    if (rc == LRIGW_OK && he == hipSuccess) he = hipStreamWaitEvent(b->stream, b->join[i], 0);
+  }
+  hipGraph_t g = nullptr;
+  hipError_t he2 = hipStreamEndCapture(b->stream, &g);
+  if (rc != LRIGW_OK) {
+    if (g) hipGraphDestroy(g);
+    return rc;
+  }
+  if (he != hipSuccess) {
+    if (g) hipGraphDestroy(g);
+    return lrigw_hip_error(he, "batch capture", __FILE__, __LINE__);
+  }
+  if (he2 != hipSuccess) return lrigw_hip_error(he2, "hipStreamEndCapture", __FILE__, __LINE__);
+  b->graph = g;
+  LRIGW_HIP_TRY(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+  return LRIGW_OK;
+}
+
+extern "C" {
+
+int lrigw_batch_create(lrigw_batch **out, int n_cells, const lrigw_batch_cell *cells, int autotune, void *hip_stream) {
+  (void)hipGetLastError();
+  if (!out || n_cells < 1 || n_cells > 64 || !cells) return LRIGW_ERR_ARG;
+  if (!hip_stream) return LRIGW_ERR_ARG;   // the legacy default stream cannot be captured
+  *out = nullptr;
+  for (int i = 0; i < n_cells; ++i) {
+    const lrigw_batch_cell &c = cells[i];
+    if (!c.ctx || !c.H || !c.evec || !c.eig || !c.V || !c.sigma || !c.e_qp || !c.z) return LRIGW_ERR_ARG;
+    if (c.n_par < 1 || c.n_par > 64) return LRIGW_ERR_ARG;
+    if (c.p && !(c.omega_cell > 0.0)) return LRIGW_ERR_ARG;
+    for (int j = 0; j < i; ++j)
+      if (cells[j].ctx == c.ctx) return LRIGW_ERR_ARG;   // one context per cell
+  }
+  lrigw_batch *b = new (std::nothrow) lrigw_batch();
+  if (!b) return LRIGW_ERR_OOM;
+  b->cells.assign(cells, cells + n_cells);
+  b->stream = (hipStream_t)hip_stream;
+  b->cs.assign(n_cells, nullptr);
+  b->saved.assign(n_cells, nullptr);
+  b->join.assign(n_cells, nullptr);
+  b->nw.assign(n_cells, 0);
+  b->splits.assign(n_cells, 0);
+  b->ms.assign(n_cells, -1.0);
+  int rc = LRIGW_OK;
+  for (int i = 0; i < n_cells && rc == LRIGW_OK; ++i) {
+    lrigw_batch_cell &cl = b->cells[i];
+    lrigw_ctx *c = cl.ctx;
+    // everything that needs the host happens here, before capture
+    if ((rc = driver_buffers(c)) < 0) break;
+    if (cl.p && (rc = lrigw_gamma_prepare(c, cl.V, cl.p, cl.omega_cell)) < 0) break;
+    if ((rc = chi0_check_gap(c, cl.eig)) < 0) break;
+    if (c->sur && (rc = surrogate_prepare(c->sur)) < 0) break;
+    if (autotune) {
+      if ((rc = autotune_chi0(c, cl, &b->nw[i], &b->splits[i], &b->ms[i])) < 0) break;
+    } else {
+      b->nw[i] = c->chi_nw;
+      b->splits[i] = c->chi_splits;
+    }
+    if (hipStreamCreate(&b->cs[i]) != hipSuccess) rc = LRIGW_ERR_HIP;
+    if (rc == LRIGW_OK && hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming) != hipSuccess) rc = LRIGW_ERR_HIP;
+  }
+  if (rc == LRIGW_OK && hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) rc = LRIGW_ERR_HIP;
+  if (rc == LRIGW_OK && hipDeviceSynchronize() != hipSuccess) rc = LRIGW_ERR_HIP;
+  if (rc == LRIGW_OK) rc = batch_capture(b);
+  if (rc != LRIGW_OK) {
+    batch_free(b);
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return LRIGW_OK;
+}
+
+int lrigw_batch_run(lrigw_batch *b) {
+  (void)hipGetLastError();
+  if (!b || !b->exec) return LRIGW_ERR_ARG;
+  LRIGW_HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+  b->launches += 1;
+  return LRIGW_OK;
+}
+
+int lrigw_batch_status(lrigw_batch *b, int *status) {
+  if (!b || !status) return LRIGW_ERR_ARG;
+  LRIGW_HIP_TRY(hipStreamSynchronize(b->stream));
+  for (size_t i = 0; i < b->cells.size(); ++i) {
+    int h[17];
+    LRIGW_HIP_TRY(hipMemcpy(h, b->cells[i].ctx->d_info, 17 * sizeof(int), hipMemcpyDeviceToHost));
+    status[3 * i + 0] = h[16] == INT_MAX ? -1 : h[16];
+    status[3 * i + 1] = h[8];
+    status[3 * i + 2] = h[9];
+  }
+  return LRIGW_OK;
+}
+
+int lrigw_batch_tuning(const lrigw_batch *b, int cell, int *nw, int *splits, double *ms) {
+  if (!b || cell < 0 || cell >= (int)b->cells.size()) return LRIGW_ERR_ARG;
+  if (nw) *nw = b->nw[cell];
+  if (splits) *splits = b->splits[cell];
+  if (ms) *ms = b->ms[cell];
+  return LRIGW_OK;
+}
+
+int lrigw_batch_graph_nodes(const lrigw_batch *b, long long *n_nodes) {
+  if (!b || !n_nodes || !b->graph) return LRIGW_ERR_ARG;
+  size_t n = 0;
+  LRIGW_HIP_TRY(hipGraphGetNodes(b->graph, nullptr, &n));
+  *n_nodes = (long long)n;
+  return LRIGW_OK;
+}
+
+int lrigw_batch_destroy(lrigw_batch *b) {
+  if (!b) return LRIGW_ERR_ARG;
+  if (b->stream) hipStreamSynchronize(b->stream);
+  else hipDeviceSynchronize();
+  batch_free(b);
+  delete b;
+  return LRIGW_OK;
+}
+
+}  // extern "C"

@@ -28,14 +28,19 @@ template <typename T> struct Chi0Cfg;
 template <> struct Chi0Cfg<float> { static const int NW = 4; static const bool two_level = true; };
 template <> struct Chi0Cfg<double> { static const int NW = 2; static const bool two_level = false; };
 
-template <typename T>
+// frequencies per workgroup: the default and the alternative the tuner may pick
+int chi0_default_nw(int precision) { return precision == LRIGW_FP64 ? Chi0Cfg<double>::NW : Chi0Cfg<float>::NW; }
+int chi0_alt_nw(int precision) { return precision == LRIGW_FP64 ? 1 : 2; }
+
+template <typename T, int NW>
 __global__ __launch_bounds__(256) void k_chi0_mfma(const typename c2t<T>::type *__restrict__ B, const T *__restrict__ delta,
-                                                   const double *__restrict__ omega, long long K, int N, int n_freq, long long Ks,
+                                                   const double *__restrict__ omega, const int *__restrict__ wsel,
+                                                   const int *__restrict__ run, long long K, int N, int n_freq, long long Ks,
                                                    long long ntile, typename c2t<T>::type *__restrict__ part) {
+  if (run && *run == 0) return;
   typedef typename c2t<T>::type C;
   typedef Mfma<T> MF;
   typedef typename MF::acc ACC;
-  const int NW = Chi0Cfg<T>::NW;
   __shared__ C As[KC][TILE];
   __shared__ C Bs[KC][TILE];
   __shared__ T dl[KC];
@@ -52,7 +57,7 @@ __global__ __launch_bounds__(256) void k_chi0_mfma(const typename c2t<T>::type *
   T om2[NW];
 #pragma unroll
   for (int w = 0; w < NW; ++w) {
-    double o = (w0 + w < n_freq) ? omega[w0 + w] : 0.0;
+    double o = (w0 + w < n_freq) ? omega[wsel[w0 + w]] : 0.0;
     om2[w] = (T)(o * o);
   }
   ACC re[NW][2][2], im[NW][2][2];
@@ -180,11 +185,12 @@ __device__ inline void splitn(float v, __bf16 *p) {
   }
 }
 
-template <int NS>
+template <int NS, int NW>
 __global__ __launch_bounds__(256) void k_chi0_bf16(const float2 *__restrict__ B, const float *__restrict__ delta,
-                                                   const double *__restrict__ omega, long long K, int N, int n_freq,
+                                                   const double *__restrict__ omega, const int *__restrict__ wsel,
+                                                   const int *__restrict__ run, long long K, int N, int n_freq,
                                                    long long Ks, long long ntile, float2 *__restrict__ part) {
-  const int NW = 4;
+  if (run && *run == 0) return;
   __shared__ __bf16 Ar[NS][TILE][KCB + BAP];   // A side (rows mu), real parts, k contiguous
   __shared__ __bf16 Ai[NS][TILE][KCB + BAP];
   __shared__ float2 Bs[TILE][KCB + BBP];        // B side (cols nu), FP32, k contiguous
@@ -202,7 +208,7 @@ __global__ __launch_bounds__(256) void k_chi0_bf16(const float2 *__restrict__ B,
   float om2[NW];
 #pragma unroll
   for (int w = 0; w < NW; ++w) {
-    double o = (w0 + w < n_freq) ? omega[w0 + w] : 0.0;
+    double o = (w0 + w < n_freq) ? omega[wsel[w0 + w]] : 0.0;
     om2[w] = (float)(o * o);
   }
   f4v re[NW][2][2], im[NW][2][2];
@@ -311,10 +317,12 @@ __global__ __launch_bounds__(256) void k_chi0_bf16(const float2 *__restrict__ B,
 // chi[w][mu][nu] = scale * sum_s part[s][w][tile][..]; upper triangle by Hermitian symmetry.
 template <typename T>
 __global__ void k_chi0_reduce(const typename c2t<T>::type *__restrict__ part, int S, int n_freq, long long ntile, int N,
-                              double scale, typename c2t<T>::type *__restrict__ chi) {
+                              double scale, const int *__restrict__ wsel, const int *__restrict__ run,
+                              typename c2t<T>::type *__restrict__ chi) {
   long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int w = blockIdx.y;
   if (idx >= (long long)N * N) return;
+  if (run && *run == 0) return;
   int mu = (int)(idx / N), nu = (int)(idx % N);
   bool up = nu > mu;
   int a = up ? nu : mu, b = up ? mu : nu;
@@ -330,7 +338,7 @@ __global__ void k_chi0_reduce(const typename c2t<T>::type *__restrict__ part, in
   double2 z = mkc(scale * sr, scale * si);
   if (up) z.y = -z.y;
   if (mu == nu) z.y = 0.0;
-  chi[((long long)w * N + mu) * N + nu] = to_c<T>(z);
+  chi[((long long)wsel[w] * N + mu) * N + nu] = to_c<T>(z);
 }
 
 // Number of K splits: enough workgroups to fill the device, partial buffer <= 2 GiB.
@@ -339,7 +347,7 @@ int chi0_plan_splits(const lrigw_ctx *c, int *splits) {
   const long long K = lrigw_K(c);
   const int nt = (d.n_aux + TILE - 1) / TILE;
   const long long ntile = (long long)nt * (nt + 1) / 2;
-  const int NW = c->precision == LRIGW_FP64 ? Chi0Cfg<double>::NW : Chi0Cfg<float>::NW;
+  const int NW = c->chi_nw;
   const long long units = ntile * ((d.n_freq + NW - 1) / NW);
   long long S = (2048 + units - 1) / units;
   long long maxS = std::max<long long>(1, K / 512);
@@ -349,6 +357,15 @@ int chi0_plan_splits(const lrigw_ctx *c, int *splits) {
   const size_t per = (size_t)d.n_freq * ntile * TILE * TILE * cs;
   while (S > 1 && (size_t)S * per > (size_t)3 << 30) --S;
   *splits = (int)std::max<long long>(1, S);
+  return LRIGW_OK;
+}
+
+static int check_gap(lrigw_ctx *c, const double *eig);
+
+int chi0_check_gap(lrigw_ctx *c, const double *eig) {
+  if (eig == c->checked_eig) return LRIGW_OK;
+  LRIGW_TRY(check_gap(c, eig));
+  c->checked_eig = eig;
   return LRIGW_OK;
 }
 
@@ -370,7 +387,10 @@ static int check_gap(lrigw_ctx *c, const double *eig) {
   return LRIGW_OK;
 }
 
-int run_chi0(lrigw_ctx *c, int iq, const void *M, const double *eig, int apply_gamma, void *chi_out) {
+// chi at the frequencies wsel[0..n_sel) (device indices into the grid); when
+// `run` is non-null the kernels do nothing unless *run != 0 (device flag).
+int run_chi0_sel(lrigw_ctx *c, int iq, const void *M, const double *eig, int apply_gamma, void *chi_out, const int *wsel,
+                 int n_sel, const int *run) {
   const Dims &d = c->d;
   if (eig != c->checked_eig) {
     LRIGW_TRY(check_gap(c, eig));
@@ -392,34 +412,46 @@ int run_chi0(lrigw_ctx *c, int iq, const void *M, const double *eig, int apply_g
   const double scale = -2.0 / d.n_k;
   hipEvent_t ev;
   stage_begin(c, "chi0_mfma", &ev);
+  const int NW = c->chi_nw;
+  dim3 grid((unsigned)ntile, (n_sel + NW - 1) / NW, S);
+#define CHI0_ARGS c->d_omega, wsel, run, K, d.n_aux, n_sel, Ks, ntile
   if (c->precision == LRIGW_FP64) {
-    const int NW = Chi0Cfg<double>::NW;
-    dim3 grid((unsigned)ntile, (d.n_freq + NW - 1) / NW, S);
-    hipLaunchKernelGGL(k_chi0_mfma<double>, grid, dim3(256), 0, c->stream, (const double2 *)B, (const double *)c->d_delta,
-                       c->d_omega, K, d.n_aux, d.n_freq, Ks, ntile, (double2 *)c->d_part);
-  } else {
-    const int NW = Chi0Cfg<float>::NW;
-    dim3 grid((unsigned)ntile, (d.n_freq + NW - 1) / NW, S);
-    if (c->precision == LRIGW_FP32)
-      hipLaunchKernelGGL(k_chi0_mfma<float>, grid, dim3(256), 0, c->stream, (const float2 *)B, (const float *)c->d_delta,
-                         c->d_omega, K, d.n_aux, d.n_freq, Ks, ntile, (float2 *)c->d_part);
-    else if (c->precision == LRIGW_SPLIT_BF16)
-      hipLaunchKernelGGL(k_chi0_bf16<2>, grid, dim3(256), 0, c->stream, (const float2 *)B, (const float *)c->d_delta,
-                         c->d_omega, K, d.n_aux, d.n_freq, Ks, ntile, (float2 *)c->d_part);
+    if (NW == 2)
+      hipLaunchKernelGGL((k_chi0_mfma<double, 2>), grid, dim3(256), 0, c->stream, (const double2 *)B,
+                         (const double *)c->d_delta, CHI0_ARGS, (double2 *)c->d_part);
     else
-      hipLaunchKernelGGL(k_chi0_bf16<3>, grid, dim3(256), 0, c->stream, (const float2 *)B, (const float *)c->d_delta,
-                         c->d_omega, K, d.n_aux, d.n_freq, Ks, ntile, (float2 *)c->d_part);
+      hipLaunchKernelGGL((k_chi0_mfma<double, 1>), grid, dim3(256), 0, c->stream, (const double2 *)B,
+                         (const double *)c->d_delta, CHI0_ARGS, (double2 *)c->d_part);
+  } else {
+    const float2 *Bf = (const float2 *)B;
+    const float *Df = (const float *)c->d_delta;
+    float2 *Pf = (float2 *)c->d_part;
+    if (c->precision == LRIGW_FP32) {
+      if (NW == 4) hipLaunchKernelGGL((k_chi0_mfma<float, 4>), grid, dim3(256), 0, c->stream, Bf, Df, CHI0_ARGS, Pf);
+      else hipLaunchKernelGGL((k_chi0_mfma<float, 2>), grid, dim3(256), 0, c->stream, Bf, Df, CHI0_ARGS, Pf);
+    } else if (c->precision == LRIGW_SPLIT_BF16) {
+      if (NW == 4) hipLaunchKernelGGL((k_chi0_bf16<2, 4>), grid, dim3(256), 0, c->stream, Bf, Df, CHI0_ARGS, Pf);
+      else hipLaunchKernelGGL((k_chi0_bf16<2, 2>), grid, dim3(256), 0, c->stream, Bf, Df, CHI0_ARGS, Pf);
+    } else {
+      if (NW == 4) hipLaunchKernelGGL((k_chi0_bf16<3, 4>), grid, dim3(256), 0, c->stream, Bf, Df, CHI0_ARGS, Pf);
+      else hipLaunchKernelGGL((k_chi0_bf16<3, 2>), grid, dim3(256), 0, c->stream, Bf, Df, CHI0_ARGS, Pf);
+    }
   }
+#undef CHI0_ARGS
   stage_end(c, "chi0_mfma", ev);
   LRIGW_TRY(lrigw_launch_check("chi0_mfma"));
-  dim3 rgrid((unsigned)(((long long)d.n_aux * d.n_aux + 255) / 256), d.n_freq);
+  dim3 rgrid((unsigned)(((long long)d.n_aux * d.n_aux + 255) / 256), n_sel);
   if (c->precision == LRIGW_FP64)
-    hipLaunchKernelGGL(k_chi0_reduce<double>, rgrid, dim3(256), 0, c->stream, (const double2 *)c->d_part, S, d.n_freq, ntile,
-                       d.n_aux, scale, (double2 *)chi_out);
+    hipLaunchKernelGGL(k_chi0_reduce<double>, rgrid, dim3(256), 0, c->stream, (const double2 *)c->d_part, S, n_sel, ntile,
+                       d.n_aux, scale, wsel, run, (double2 *)chi_out);
   else
-    hipLaunchKernelGGL(k_chi0_reduce<float>, rgrid, dim3(256), 0, c->stream, (const float2 *)c->d_part, S, d.n_freq, ntile,
-                       d.n_aux, scale, (float2 *)chi_out);
+    hipLaunchKernelGGL(k_chi0_reduce<float>, rgrid, dim3(256), 0, c->stream, (const float2 *)c->d_part, S, n_sel, ntile,
+                       d.n_aux, scale, wsel, run, (float2 *)chi_out);
   LRIGW_TRY(lrigw_launch_check("chi0_reduce"));
   stage_end(c, "chi0", ev_all);
   return LRIGW_OK;
+}
+
+int run_chi0(lrigw_ctx *c, int iq, const void *M, const double *eig, int apply_gamma, void *chi_out) {
+  return run_chi0_sel(c, iq, M, eig, apply_gamma, chi_out, c->d_wall, c->d.n_freq, nullptr);
 }

@@ -64,8 +64,6 @@ static int kindex(const int nk[3], int a, int b, int c) {
   return (a * nk[1] + b) * nk[2] + c;
 }
 
-int chi0_plan_splits(const lrigw_ctx *c, int *splits);
-
 int run_grids(lrigw_ctx *c) {
   Dims &d = c->d;
   const int nk = d.n_k;
@@ -98,6 +96,7 @@ int run_grids(lrigw_ctx *c) {
   LRIGW_HIP_TRY(hipMalloc(&c->d_aux_off, (d.n_atoms + 1) * sizeof(int)));
   LRIGW_HIP_TRY(hipMalloc(&c->d_omega, d.n_freq * sizeof(double)));
   LRIGW_HIP_TRY(hipMalloc(&c->d_weight, d.n_freq * sizeof(double)));
+  LRIGW_HIP_TRY(hipMalloc(&c->d_wall, d.n_freq * sizeof(int)));
   LRIGW_HIP_TRY(hipMemcpyAsync(c->d_kpq, c->h_kpq.data(), kk, hipMemcpyHostToDevice, c->stream));
   LRIGW_HIP_TRY(hipMemcpyAsync(c->d_kmq, c->h_kmq.data(), kk, hipMemcpyHostToDevice, c->stream));
   LRIGW_HIP_TRY(hipMemcpyAsync(c->d_aux_atom, aux_atom.data(), d.n_aux * sizeof(int), hipMemcpyHostToDevice, c->stream));
@@ -106,6 +105,9 @@ int run_grids(lrigw_ctx *c) {
   hipLaunchKernelGGL(k_gauss_legendre, dim3((d.n_freq + 63) / 64), dim3(64), 0, c->stream, d.n_freq, d.x0, c->d_omega,
                      c->d_weight);
   LRIGW_TRY(lrigw_launch_check("gauss_legendre"));
+  std::vector<int> wall(d.n_freq);
+  for (int i = 0; i < d.n_freq; ++i) wall[i] = i;
+  LRIGW_HIP_TRY(hipMemcpyAsync(c->d_wall, wall.data(), d.n_freq * sizeof(int), hipMemcpyHostToDevice, c->stream));
   c->h_omega.resize(d.n_freq);
   c->h_weight.resize(d.n_freq);
   LRIGW_HIP_TRY(hipMemcpyAsync(c->h_omega.data(), c->d_omega, d.n_freq * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -119,6 +121,7 @@ int run_grids(lrigw_ctx *c) {
   const long long K = lrigw_K(c);
   const size_t nn = (size_t)d.n_aux * d.n_aux;
   LRIGW_HIP_TRY(hipMalloc(&c->d_delta, (size_t)K * rs));
+  c->chi_nw = chi0_default_nw(c->precision);
   LRIGW_TRY(chi0_plan_splits(c, &c->chi_splits));
   int nt = (d.n_aux + TILE - 1) / TILE;
   size_t ntile = (size_t)nt * (nt + 1) / 2;

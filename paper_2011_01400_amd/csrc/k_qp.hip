@@ -158,6 +158,10 @@ int run_qp(lrigw_ctx *c, const void *sigma, const double *eps_qp, const double *
   hipLaunchKernelGGL(k_pade_qp, dim3((nkq + 63) / 64), dim3(64), 0, c->stream, (const double2 *)sigma, nkq, d.n_freq, n_par,
                      c->d_omega, eps_qp, e_static, d.mu, e_qp, z, flags);
   LRIGW_TRY(lrigw_launch_check("pade_qp"));
+  if (c->capturing) {   // flags stay in d_info[8..9]
+    if (info) *info = 0;
+    return LRIGW_OK;
+  }
   int h[2];
   LRIGW_HIP_TRY(hipMemcpyAsync(h, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   LRIGW_HIP_TRY(hipStreamSynchronize(c->stream));

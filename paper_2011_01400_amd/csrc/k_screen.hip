@@ -40,6 +40,13 @@ __global__ void k_hermitize(const double2 *__restrict__ W, typename c2t<T>::type
   out[(long long)blockIdx.y * stride + idx] = to_c<T>(z);
 }
 
+// sticky status of a captured pass: d_info[16] = smallest q whose V or eps~ was
+// not positive definite (INT_MAX: none)
+__global__ void k_fold_status(int *info, int q) {
+  if (threadIdx.x != 0) return;
+  if (info[1] != INT_MAX || info[2] != INT_MAX) info[16] = min(info[16], q);
+}
+
 static ZGemm mk(int m, int n, int k, int opa, const double2 *A, long long lda, long long sa, int opb, const double2 *B,
                 long long ldb, long long sb, double2 *Cm, long long ldc, long long sc, double2 alpha, int batch) {
   ZGemm g;
@@ -53,7 +60,6 @@ static ZGemm mk(int m, int n, int k, int opa, const double2 *A, long long lda, l
 }
 
 int run_screen(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_out, int *info) {
-  (void)iq;
   const Dims &d = c->d;
   const int n = d.n_aux, nw = d.n_freq;
   const long long nn = (long long)n * n;
@@ -90,6 +96,11 @@ int run_screen(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_ou
   else
     hipLaunchKernelGGL(k_hermitize<float>, eg, dim3(256), 0, s, c->d_s1, (float2 *)Wc_out, n, nn);
   LRIGW_TRY(lrigw_launch_check("screen"));
+  if (c->capturing) {
+    hipLaunchKernelGGL(k_fold_status, dim3(1), dim3(1), 0, s, c->d_info, iq);
+    if (info) *info = -1;
+    return lrigw_launch_check("screen_status");
+  }
   // status: V and eps~ must have been positive definite
   int h[2];
   LRIGW_HIP_TRY(hipMemcpyAsync(h, c->d_info + 1, 2 * sizeof(int), hipMemcpyDeviceToHost, s));

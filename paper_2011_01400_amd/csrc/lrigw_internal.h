@@ -76,6 +76,7 @@ struct lrigw_ctx {
   int *d_aux_off = nullptr;      // [n_atoms+1]
   int *d_kpq = nullptr, *d_kmq = nullptr;
   double *d_omega = nullptr, *d_weight = nullptr;
+  int *d_wall = nullptr;         // [N_w] 0, 1, ..., N_w - 1 (every frequency selected)
   std::vector<double> h_omega, h_weight;
 
   // per-q workspaces
@@ -83,6 +84,7 @@ struct lrigw_ctx {
   void *d_part = nullptr;        // chi0 split-K partials
   size_t part_bytes = 0;
   int chi_splits = 1;
+  int chi_nw = 4;                // frequencies per chi0 workgroup
   void *d_X = nullptr;           // [N_w][N_k*n_qp*n_bands] pair weights (T)
   double2 *d_LV = nullptr;       // [N][N]
   double2 *d_s0 = nullptr, *d_s1 = nullptr, *d_s2 = nullptr, *d_s3 = nullptr;  // [N_w][N][N]
@@ -102,6 +104,14 @@ struct lrigw_ctx {
 
   const double *checked_eig = nullptr;   // eigenvalue array already checked for a gap
 
+  // graph capture: no host round trips; screening status folded into d_info[16]
+  bool capturing = false;
+  double *d_epsqp = nullptr;     // [N_k][n_qp] band energies of the QP bands (driver)
+
+  // learned frequency surrogate used by the driver (not owned)
+  lrigw_surrogate *sur = nullptr;
+  double sur_threshold = 0.0;
+
   // timing
   bool timing = false;
   std::map<std::string, StageTimer> stages;
@@ -116,12 +126,24 @@ void stage_end(lrigw_ctx *c, const char *name, hipEvent_t ev);
 
 // ---------------------------------------------------------------- kernel entry points (host side)
 int run_grids(lrigw_ctx *c);
+int chi0_default_nw(int precision);
+int chi0_alt_nw(int precision);
+int chi0_plan_splits(const lrigw_ctx *c, int *splits);
+int chi0_check_gap(lrigw_ctx *c, const double *eig);
 int run_lri_ft(lrigw_ctx *c, const double *lri_R, const int *R_list, int nR, const void *evec, void *H_out);
 int run_build_M(lrigw_ctx *c, int iq, int slice, const void *H, const void *evec, void *M_out);
 int run_chi0(lrigw_ctx *c, int iq, const void *M, const double *eig, int apply_gamma, void *chi_out);
+int run_chi0_sel(lrigw_ctx *c, int iq, const void *M, const double *eig, int apply_gamma, void *chi_out, const int *wsel,
+                 int n_sel, const int *run);
+int surrogate_prepare(lrigw_surrogate *sg);
+int run_chi0_surrogate(lrigw_ctx *c, lrigw_surrogate *sg, int iq, const void *M, const double *eig, int apply_gamma,
+                       double threshold, void *chi_out);
 int run_gamma_prepare(lrigw_ctx *c, const void *Vcut0, const void *p, double omega_cell);
 int run_screen(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_out, int *info);
 int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const double *eig, void *sigma_acc);
+int run_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *p, double omega_cell,
+             const double *e_static, int n_par, int q_first, int q_last, void *sigma, double *e_qp, double *z, int *info);
+int driver_buffers(lrigw_ctx *c);
 int run_qp(lrigw_ctx *c, const void *sigma, const double *eps_qp, const double *e_static, int n_par, double *e_qp,
            double *z, int *info);
 

@@ -30,7 +30,13 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "split_bf16": SPLIT_BF16, "split3_bf16
 # every symbol include/lrigw.h declares
 EXPORTS = ["lrigw_create", "lrigw_destroy", "lrigw_strerror", "lrigw_get_sizes", "lrigw_grids", "lrigw_lri_ft",
            "lrigw_build_M", "lrigw_chi0", "lrigw_gamma_prepare", "lrigw_screen", "lrigw_sigma_c", "lrigw_qp",
-           "lrigw_g0w0", "lrigw_set_timing", "lrigw_stage_ms", "lrigw_reset_timing"]
+           "lrigw_g0w0", "lrigw_set_timing", "lrigw_stage_ms", "lrigw_reset_timing",
+           "lrigw_surrogate_create", "lrigw_surrogate_destroy", "lrigw_surrogate_info", "lrigw_surrogate_rule",
+           "lrigw_surrogate_params", "lrigw_surrogate_basis", "lrigw_surrogate_add", "lrigw_surrogate_rows",
+           "lrigw_surrogate_forward", "lrigw_surrogate_grad", "lrigw_surrogate_train", "lrigw_chi0_surrogate",
+           "lrigw_set_surrogate", "lrigw_surrogate_stats", "lrigw_surrogate_reset_stats",
+           "lrigw_batch_create", "lrigw_batch_run", "lrigw_batch_status", "lrigw_batch_tuning",
+           "lrigw_batch_graph_nodes", "lrigw_batch_destroy"]
 
 
 class LrigwSystem(ctypes.Structure):
@@ -43,6 +49,13 @@ class LrigwSystem(ctypes.Structure):
 class LrigwSizes(ctypes.Structure):
     _fields_ = [(n, ctypes.c_longlong) for n in ("n_k", "n_b", "n_aux", "n_bands", "n_freq", "nb_max", "h_elems",
                                                   "m_chi_elems", "m_sig_elems", "w_elems", "sigma_elems")]
+
+
+class LrigwBatchCell(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p), ("H", ctypes.c_void_p), ("evec", ctypes.c_void_p), ("eig", ctypes.c_void_p),
+                ("V", ctypes.c_void_p), ("p", ctypes.c_void_p), ("omega_cell", ctypes.c_double),
+                ("e_static", ctypes.c_void_p), ("n_par", ctypes.c_int), ("sigma", ctypes.c_void_p),
+                ("e_qp", ctypes.c_void_p), ("z", ctypes.c_void_p)]
 
 
 class LrigwError(RuntimeError):
@@ -68,6 +81,9 @@ def load(path: Optional[str] = None):
     lib = ctypes.CDLL(p)
     vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     ip = ctypes.POINTER(ctypes.c_int)
+    ll = ctypes.c_longlong
+    llp = ctypes.POINTER(ctypes.c_longlong)
+    dp = ctypes.POINTER(ctypes.c_double)
     sig = {
         "lrigw_create": (i, [ctypes.POINTER(vp), ctypes.POINTER(LrigwSystem), i, vp]),
         "lrigw_destroy": (i, [vp]),
@@ -85,6 +101,27 @@ def load(path: Optional[str] = None):
         "lrigw_set_timing": (i, [vp, i]),
         "lrigw_stage_ms": (d, [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_longlong)]),
         "lrigw_reset_timing": (None, [vp]),
+        "lrigw_surrogate_create": (i, [vp, i, i, i, d, d, ll, vp, vp, ctypes.POINTER(vp)]),
+        "lrigw_surrogate_destroy": (i, [vp]),
+        "lrigw_surrogate_info": (i, [vp, ip, llp]),
+        "lrigw_surrogate_rule": (i, [vp, vp]),
+        "lrigw_surrogate_params": (i, [vp, vp, vp]),
+        "lrigw_surrogate_basis": (i, [vp, vp, vp, vp]),
+        "lrigw_surrogate_add": (i, [vp, vp, vp]),
+        "lrigw_surrogate_rows": (i, [vp, llp, vp, vp, ll, ll]),
+        "lrigw_surrogate_forward": (i, [vp, vp, i, vp]),
+        "lrigw_surrogate_grad": (i, [vp, vp, vp, i, vp, vp]),
+        "lrigw_surrogate_train": (i, [vp, i, i, d, vp, ll, vp]),
+        "lrigw_chi0_surrogate": (i, [vp, vp, i, vp, vp, i, d, vp]),
+        "lrigw_set_surrogate": (i, [vp, vp, d]),
+        "lrigw_surrogate_stats": (i, [vp, llp, ip, dp, i]),
+        "lrigw_surrogate_reset_stats": (i, [vp]),
+        "lrigw_batch_create": (i, [ctypes.POINTER(vp), i, ctypes.POINTER(LrigwBatchCell), i, vp]),
+        "lrigw_batch_run": (i, [vp]),
+        "lrigw_batch_status": (i, [vp, ip]),
+        "lrigw_batch_tuning": (i, [vp, i, ip, ip, dp]),
+        "lrigw_batch_graph_nodes": (i, [vp, llp]),
+        "lrigw_batch_destroy": (i, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -229,6 +266,15 @@ class Context:
         self._check(rc, "lrigw_g0w0", allow_warn=True)
         return rc, info.value
 
+    def chi0_surrogate(self, sg, iq, M, eig, chi_out, threshold, apply_gamma=False):
+        self._check(self.lib.lrigw_chi0_surrogate(self.h, sg.h, int(iq), _ptr(M), _ptr(eig), int(bool(apply_gamma)),
+                                                  float(threshold), _ptr(chi_out)), "lrigw_chi0_surrogate")
+        return chi_out
+
+    def set_surrogate(self, sg, threshold=0.0):
+        self._check(self.lib.lrigw_set_surrogate(self.h, sg.h if sg is not None else None, float(threshold)),
+                    "lrigw_set_surrogate")
+
     def set_timing(self, on=True):
         self._check(self.lib.lrigw_set_timing(self.h, int(bool(on))), "lrigw_set_timing")
 
@@ -239,6 +285,168 @@ class Context:
 
     def reset_timing(self):
         self.lib.lrigw_reset_timing(self.h)
+
+
+class Surrogate:
+    """The learned frequency surrogate (lrigw_surrogate_* calls)."""
+
+    def __init__(self, ctx, init_params, start, *, rank, n_anchor=6, hidden=256, d_lo, d_hi, row_capacity=0):
+        self.lib = ctx.lib
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        rc = self.lib.lrigw_surrogate_create(ctx.h, int(rank), int(n_anchor), int(hidden), float(d_lo), float(d_hi),
+                                             int(row_capacity), _ptr(init_params), _ptr(start), ctypes.byref(h))
+        if rc != LRIGW_OK:
+            raise LrigwError(rc, "lrigw_surrogate_create")
+        self.h = h
+        ints = (ctypes.c_int * 6)()
+        n = ctypes.c_longlong(0)
+        self._check(self.lib.lrigw_surrogate_info(self.h, ints, ctypes.byref(n)), "lrigw_surrogate_info")
+        self.n_anchor, self.n_out, self.holdout, self.t_holdout, self.rank, self.hidden = list(ints)
+        self.n_params = n.value
+
+    @staticmethod
+    def n_params_of(n_anchor, hidden, n_out):
+        return (n_anchor + 1) * hidden + (hidden + 1) * hidden + (hidden + 1) * n_out
+
+    def _check(self, rc, where):
+        if rc != LRIGW_OK:
+            raise LrigwError(rc, where)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lrigw_surrogate_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def rule(self):
+        import torch
+        C = torch.empty(self.n_anchor * self.n_out, dtype=torch.float64, device="cuda")
+        self._check(self.lib.lrigw_surrogate_rule(self.h, _ptr(C)), "lrigw_surrogate_rule")
+        return C.view(self.n_anchor, self.n_out)
+
+    def params(self, set_to=None):
+        import torch
+        out = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        self._check(self.lib.lrigw_surrogate_params(self.h, _ptr(out), _ptr(set_to)), "lrigw_surrogate_params")
+        return out
+
+    def basis(self, ctx, chi_a0):
+        import torch
+        U = torch.empty(int(ctx.sizes.n_aux) * self.rank, dtype=torch.complex128, device="cuda")
+        self._check(self.lib.lrigw_surrogate_basis(self.h, ctx.h, _ptr(chi_a0), _ptr(U)), "lrigw_surrogate_basis")
+        return U.view(int(ctx.sizes.n_aux), self.rank)
+
+    def add(self, ctx, chi):
+        self._check(self.lib.lrigw_surrogate_add(self.h, ctx.h, _ptr(chi)), "lrigw_surrogate_add")
+
+    def rows(self, first=0, count=None):
+        import torch
+        n = ctypes.c_longlong(0)
+        self._check(self.lib.lrigw_surrogate_rows(self.h, ctypes.byref(n), None, None, 0, 0), "lrigw_surrogate_rows")
+        count = n.value - first if count is None else count
+        x = torch.empty((count, self.n_anchor), dtype=torch.float32, device="cuda")
+        y = torch.empty((count, self.n_out), dtype=torch.float32, device="cuda")
+        if count > 0:
+            self._check(self.lib.lrigw_surrogate_rows(self.h, ctypes.byref(n), _ptr(x), _ptr(y), int(first), int(count)),
+                        "lrigw_surrogate_rows")
+        return x, y
+
+    def n_rows(self):
+        n = ctypes.c_longlong(0)
+        self._check(self.lib.lrigw_surrogate_rows(self.h, ctypes.byref(n), None, None, 0, 0), "lrigw_surrogate_rows")
+        return n.value
+
+    def forward(self, x):
+        import torch
+        y = torch.empty((x.shape[0], self.n_out), dtype=torch.float32, device="cuda")
+        self._check(self.lib.lrigw_surrogate_forward(self.h, _ptr(x), int(x.shape[0]), _ptr(y)), "lrigw_surrogate_forward")
+        return y
+
+    def grad(self, x, y):
+        import torch
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        g = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        self._check(self.lib.lrigw_surrogate_grad(self.h, _ptr(x), _ptr(y), int(x.shape[0]), _ptr(loss), _ptr(g)),
+                    "lrigw_surrogate_grad")
+        return loss, g
+
+    def train(self, steps, batch, lr, order, loss_hist=None):
+        self._check(self.lib.lrigw_surrogate_train(self.h, int(steps), int(batch), float(lr), _ptr(order), int(order.numel()),
+                                                   _ptr(loss_hist)), "lrigw_surrogate_train")
+        return loss_hist
+
+    def stats(self, max_errors=0):
+        n = ctypes.c_longlong(0)
+        fb = ctypes.c_int(0)
+        errs = (ctypes.c_double * max(1, max_errors))()
+        self._check(self.lib.lrigw_surrogate_stats(self.h, ctypes.byref(n), ctypes.byref(fb), errs, int(max_errors)),
+                    "lrigw_surrogate_stats")
+        return n.value, fb.value, list(errs)[:min(max_errors, n.value)]
+
+    def reset_stats(self):
+        self._check(self.lib.lrigw_surrogate_reset_stats(self.h), "lrigw_surrogate_reset_stats")
+
+
+class Batch:
+    """Several cells in one captured hipGraph (lrigw_batch_* calls).
+    cells: list of dicts with keys ctx, H, evec, eig, V, p, omega_cell,
+    e_static, n_par, sigma, e_qp, z (torch tensors / numbers)."""
+
+    def __init__(self, cells, autotune=True, stream=None):
+        import torch
+        self.lib = load()
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.cells = cells           # keeps the tensors alive
+        arr = (LrigwBatchCell * len(cells))()
+        for i, c in enumerate(cells):
+            arr[i] = LrigwBatchCell(c["ctx"].h.value, _ptr(c["H"]), _ptr(c["evec"]), _ptr(c["eig"]), _ptr(c["V"]),
+                                    _ptr(c.get("p")), float(c.get("omega_cell", 0.0)), _ptr(c.get("e_static")),
+                                    int(c.get("n_par", 16)), _ptr(c["sigma"]), _ptr(c["e_qp"]), _ptr(c["z"]))
+        h = ctypes.c_void_p()
+        rc = self.lib.lrigw_batch_create(ctypes.byref(h), len(cells), arr, int(bool(autotune)),
+                                         ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != LRIGW_OK:
+            raise LrigwError(rc, "lrigw_batch_create")
+        self.h = h
+
+    def run(self):
+        rc = self.lib.lrigw_batch_run(self.h)
+        if rc != LRIGW_OK:
+            raise LrigwError(rc, "lrigw_batch_run")
+
+    def status(self):
+        st = (ctypes.c_int * (3 * len(self.cells)))()
+        rc = self.lib.lrigw_batch_status(self.h, st)
+        if rc != LRIGW_OK:
+            raise LrigwError(rc, "lrigw_batch_status")
+        return [tuple(st[3 * i:3 * i + 3]) for i in range(len(self.cells))]
+
+    def tuning(self, i):
+        nw, sp, ms = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0)
+        self.lib.lrigw_batch_tuning(self.h, int(i), ctypes.byref(nw), ctypes.byref(sp), ctypes.byref(ms))
+        return nw.value, sp.value, ms.value
+
+    def graph_nodes(self):
+        n = ctypes.c_longlong(0)
+        self.lib.lrigw_batch_graph_nodes(self.h, ctypes.byref(n))
+        return n.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lrigw_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def device_inputs(sysm, device="cuda"):

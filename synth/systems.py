@@ -286,3 +286,50 @@ def make_custom(n_atoms=2, nb_per_atom=4, naux_per_atom=6, nk=(2, 1, 1), n_occ=2
 
 def all_cells(config: int) -> List[System]:
     return [make_config(config, c) for c in range(len(CONFIGS[config]))]
+
+
+# ---------------------------------------------------------------- surrogate inputs
+# Random draws of the learned-surrogate form, made here and passed to both the
+# library and the oracle: initial network parameters (values representable in
+# BF16, so that both sides start from the same weights), the start block of
+# the subspace iteration and the order in which training rows are visited.
+
+def bf16_round(a) -> np.ndarray:
+    """Round float values to the nearest BF16 value (ties to even), as float32."""
+    f = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+def surrogate_init(n_in: int, hidden: int, n_out: int, seed: int, out_scale: float = 1.0) -> np.ndarray:
+    """Flat parameters W1 [n_in][H], b1, W2 [H][H], b2, W3 [H][n_out], b3:
+    weights uniform in +-sqrt(6/(fan_in+fan_out)) (W3 times out_scale; the
+    targets are small residuals), biases zero, BF16 values."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for li, (fi, fo) in enumerate(((n_in, hidden), (hidden, hidden), (hidden, n_out))):
+        lim = math.sqrt(6.0 / (fi + fo)) * (out_scale if li == 2 else 1.0)
+        parts.append(rng.uniform(-lim, lim, fi * fo))
+        parts.append(np.zeros(fo))
+    return bf16_round(np.concatenate(parts))
+
+
+def surrogate_start(n_aux: int, rank: int, seed: int) -> np.ndarray:
+    """Start block of the subspace iteration: float64 [n_aux][rank], U(-1,1)."""
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, (n_aux, rank))
+
+
+def surrogate_order(n_rows: int, n_visits: int, seed: int) -> np.ndarray:
+    """Row visiting order for training: concatenated permutations, int32."""
+    rng = np.random.default_rng(seed)
+    reps = (n_visits + n_rows - 1) // n_rows
+    return np.concatenate([rng.permutation(n_rows) for _ in range(reps)])[:n_visits].astype(np.int32)
+
+
+def transition_window(sysm: "System") -> tuple:
+    """Smallest and largest occupied -> unoccupied energy difference over all
+    k, k' (the band gap and the width of the transition spectrum), Ha."""
+    occ = sysm.eig[:, :sysm.n_occ]
+    unocc = sysm.eig[:, sysm.n_occ:]
+    return float(unocc.min() - occ.max()), float(unocc.max() - occ.min())

@@ -1,0 +1,115 @@
+"""GPU: the batched form (several uneven cells in one captured hipGraph,
+lrigw_batch_*) against the per-cell calls and the FP64 oracle; the graph is
+replayed several times with eager work in between, every replay checked."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle.pipeline import Oracle
+from synth.systems import make_config, make_custom
+
+HA_MEV = 27211.386
+
+CELLS = [
+    ("c1", lambda: make_config(1), "fp64"),
+    ("ragged", lambda: make_custom(n_atoms=2, nb_per_atom=7, naux_per_atom=37, nk=(3, 1, 2), n_occ=5, n_freq=10,
+                                   qp_lo=2, n_qp=6, seed=17), "fp32"),
+    ("three_atoms", lambda: make_custom(n_atoms=3, nb_per_atom=6, naux_per_atom=45, nk=(1, 1, 1), n_occ=4, n_freq=8,
+                                        qp_lo=1, n_qp=7, seed=23), "split_bf16"),
+]
+
+
+def _lib():
+    from paper_2011_01400_amd import lrigw as L
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L.load()
+    return L
+
+
+def _cell_inputs(L, s, precision):
+    ctx = L.Context.from_system(s, precision=precision)
+    dev = L.device_inputs(s)
+    H = ctx.empty("H")
+    ctx.lri_ft(dev["lri"], s.R, dev["evec"], H)
+    sp = s.spec
+    out = dict(sigma=torch.zeros((s.n_k, sp.n_qp, sp.n_freq), dtype=torch.complex128, device="cuda"),
+               e_qp=torch.zeros((s.n_k, sp.n_qp), dtype=torch.float64, device="cuda"),
+               z=torch.zeros((s.n_k, sp.n_qp), dtype=torch.float64, device="cuda"))
+    return dict(ctx=ctx, H=H, evec=dev["evec"], eig=dev["eig"], V=dev["V"], p=dev["p"], omega_cell=s.omega_cell,
+                e_static=dev["e_static"], n_par=16, **out)
+
+
+def _eager(L, s, precision):
+    c = _cell_inputs(L, s, precision)
+    c["ctx"].g0w0(c["H"], c["evec"], c["eig"], c["V"], c["p"], c["omega_cell"], c["e_static"], 16, c["sigma"], c["e_qp"],
+                  c["z"])
+    torch.cuda.synchronize()
+    return c["sigma"].cpu().numpy(), c["e_qp"].cpu().numpy(), c["z"].cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def cells():
+    L = _lib()
+    out = []
+    for name, mk, prec in CELLS:
+        print(f"\n[gpu batch] cell {name} ({prec})", flush=True)
+        s = mk()
+        out.append(dict(name=name, s=s, prec=prec, ref=_eager(L, s, prec)))
+    return L, out
+
+
+@pytest.mark.parametrize("autotune", [False, True])
+def test_batch_replays_match_per_cell_calls(cells, autotune):
+    L, cs = cells
+    inputs = [_cell_inputs(L, c["s"], c["prec"]) for c in cs]
+    b = L.Batch(inputs, autotune=autotune)
+    print(f"  autotune={autotune}: graph nodes {b.graph_nodes()}; tuning "
+          + ", ".join(f"{c['name']}: nw={b.tuning(i)[0]} S={b.tuning(i)[1]}" for i, c in enumerate(cs)), flush=True)
+    for rep in range(3):
+        for inp in inputs:
+            inp["sigma"].fill_(float("nan"))
+            inp["e_qp"].zero_()
+        torch.cuda.synchronize()
+        b.run()
+        st = b.status()
+        # eager work on the default stream between replays
+        x = torch.randn(512, 512, device="cuda")
+        (x @ x).sum().item()
+        for i, (c, inp) in enumerate(zip(cs, inputs)):
+            sg, e, z = (inp[k].cpu().numpy() for k in ("sigma", "e_qp", "z"))
+            s_ref, e_ref, z_ref = c["ref"]
+            ds = np.abs(sg - s_ref).max() / np.abs(s_ref).max()
+            de = np.abs(e - e_ref) * HA_MEV
+            reg = (z_ref >= 0.5) & (z_ref <= 1.0)
+            print(f"  replay {rep} {c['name']}: status {st[i]}, max rel dSigma {ds:.2e}, "
+                  f"QP max {de.max():.2e} meV (quasiparticle-like {de[reg].max() if reg.any() else 0:.2e})", flush=True)
+            assert st[i][0] == -1
+            if not autotune:
+                # same tile choices as the per-cell calls: same arithmetic
+                assert ds < 1e-13 and de.max() < 1e-9
+            else:
+                tol_s = {"fp64": 1e-12, "fp32": 1e-5, "split_bf16": 1e-4}[c["prec"]]
+                assert ds < tol_s
+                assert (de[reg].max() if reg.any() else 0.0) < (1e-6 if c["prec"] == "fp64" else 1.0)
+    b.close()
+
+
+def test_batch_fp64_cell_matches_oracle(cells):
+    L, cs = cells
+    c = cs[0]
+    inputs = [_cell_inputs(L, x["s"], x["prec"]) for x in cs]
+    b = L.Batch(inputs, autotune=True)
+    b.run()
+    b.status()
+    ref = Oracle(c["s"]).run()
+    sg = inputs[0]["sigma"].cpu().numpy()
+    e = inputs[0]["e_qp"].cpu().numpy()
+    ds = np.abs(sg - ref["sigma"]).max()
+    de = np.abs(e - ref["E"]).max() * HA_MEV
+    print(f"  c1 in the batch vs oracle: max|dSigma| {ds:.2e} Ha, max|dE| {de:.2e} meV", flush=True)
+    assert ds < 1e-9 and de < 1e-5
+    b.close()
