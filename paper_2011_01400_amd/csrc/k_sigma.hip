@@ -14,6 +14,19 @@
 #include "tiles.h"
 
 #define SKC 16          // nu rows staged per step
+
+// Workgroup -> (column block, frequency block).  Consecutive workgroup ids go
+// to different XCDs (id mod 8); all frequency blocks of one column block are
+// given to the same XCD, back to back, so its x tile is fetched from HBM once
+// and then served by that XCD's L2.
+__device__ inline bool xcd_map(int nfb, long long ncb, long long &cb, int &fb) {
+  const long long b = blockIdx.x;
+  const long long slot = b >> 3;
+  cb = (slot / nfb) * 8 + (b & 7);
+  fb = (int)(slot % nfb);
+  return cb < ncb;
+}
+static inline unsigned xcd_grid(int nfb, long long ncb) { return (unsigned)(((ncb + 7) / 8) * 8 * nfb); }
 #define SLP (TILE + 1)  // padded LDS row (complex elements)
 
 // One workgroup = 64 columns c (x rows) and every row mu of W^c.  Rows are
@@ -25,7 +38,7 @@
 // is multiplied.  The reduction over mu is accumulated in FP64.
 template <typename T>
 __global__ __launch_bounds__(256) void k_sigma_mfma(const typename c2t<T>::type *__restrict__ x, const typename c2t<T>::type *__restrict__ Wall,
-                                                    long long Ccols, int N, double *__restrict__ Xall) {
+                                                    long long Ccols, int N, int n_freq, double *__restrict__ Xall) {
   typedef typename c2t<T>::type C;
   typedef Mfma<T> MF;
   typedef typename MF::acc ACC;
@@ -33,9 +46,12 @@ __global__ __launch_bounds__(256) void k_sigma_mfma(const typename c2t<T>::type 
   __shared__ C Us[2][SKC][SLP];   // Us[b][nu][c]  = conj(x[c][nu])
   __shared__ double red[4][TILE];
 
-  const C *W = Wall + (long long)blockIdx.y * N * N;
-  double *Xout = Xall + (long long)blockIdx.y * Ccols;
-  const long long c0 = (long long)blockIdx.x * TILE;
+  long long cb;
+  int wq;
+  if (!xcd_map(n_freq, (Ccols + TILE - 1) / TILE, cb, wq)) return;
+  const C *W = Wall + (long long)wq * N * N;
+  double *Xout = Xall + (long long)wq * Ccols;
+  const long long c0 = cb * TILE;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15;
   const int ngroups = (N + TILE - 1) / TILE;
   const int base = N - ngroups * TILE;        // <= 0
@@ -146,116 +162,195 @@ __global__ __launch_bounds__(256) void k_sigma_mfma(const typename c2t<T>::type 
   }
 }
 
-// Split-BF16 form: W^c and conj(x) are split into NS BF16 parts when staged in
-// LDS, products of parts p + q < NS are accumulated by the 16x16x32 BF16 MFMA
-// in FP32.  Same work decomposition as k_sigma_mfma, nu chunks of 32.
+// Split-BF16 form.  conj(x) and the strictly lower part of W^c are split once
+// per q into NS BF16 parts (x = sum_p x_p, each part the rounding of what the
+// previous ones left) in zero-padded MFMA-ready arrays:
+//   xs[p][re/im][Cpad][Npad]             (Cpad = 64-multiple, Npad = 32-multiple)
+//   ws[w][p][re/im][Rpad][Npad]          (row r <-> mu = r + N - Rpad, end-aligned
+//                                          64-row groups; zero for nu >= mu)
+// so the main kernel streams operands without per-element work: the x tile of
+// a workgroup (64 columns x 32 nu) goes to LDS with 16-byte copies, double
+// buffered; each wave reads its 16 rows of W straight into MFMA registers;
+// products of parts p + q < NS accumulate in FP32 on the 16x16x32 BF16 MFMA.
+// Two frequencies share every x tile.
 #define SKB 32
 #define SBP 8
+#define SNW 2
+
+typedef unsigned short us16;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <int NS>
-__device__ inline void splitn_s(float v, __bf16 *p) {
+__device__ inline void split_parts(float v, us16 *out) {
   float r = v;
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
-    p[i] = (__bf16)r;
-    r -= (float)p[i];
+    const __bf16 h = (__bf16)r;
+    out[i] = __builtin_bit_cast(us16, h);
+    r -= (float)h;
   }
 }
 
+// xs from x (complex FP32 [C][N]); one thread per (column, 8 nu)
 template <int NS>
-__global__ __launch_bounds__(256) void k_sigma_bf16(const float2 *__restrict__ x, const float2 *__restrict__ Wall, long long Ccols,
-                                                    int N, double *__restrict__ Xall) {
-  __shared__ __bf16 Wr[NS][TILE][SKB + SBP], Wi[NS][TILE][SKB + SBP];   // [part][mu][nu]
-  __shared__ __bf16 Ur[NS][TILE][SKB + SBP], Ui[NS][TILE][SKB + SBP];   // [part][c][nu] of conj(x)
-  __shared__ double red[4][TILE];
-  const float2 *W = Wall + (long long)blockIdx.y * N * N;
-  double *Xout = Xall + (long long)blockIdx.y * Ccols;
-  const long long c0 = (long long)blockIdx.x * TILE;
+__global__ void k_split_x(const float2 *__restrict__ x, long long C, int N, long long Cpad, int Npad, us16 *__restrict__ xs) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int g8 = Npad / 8;
+  if (t >= Cpad * g8) return;
+  const long long c = t / g8;
+  const int k0 = (int)(t % g8) * 8;
+  us16 re[NS][8], im[NS][8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int nu = k0 + e;
+    float2 u = mkcf(0.f, 0.f);
+    if (c < C && nu < N) u = cconj(x[c * N + nu]);
+    us16 a[NS], b[NS];
+    split_parts<NS>(u.x, a);
+    split_parts<NS>(u.y, b);
+#pragma unroll
+    for (int p = 0; p < NS; ++p) {
+      re[p][e] = a[p];
+      im[p][e] = b[p];
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < NS; ++p) {
+    *(u32x4 *)(xs + ((long long)(2 * p) * Cpad + c) * Npad + k0) = *(const u32x4 *)re[p];
+    *(u32x4 *)(xs + ((long long)(2 * p + 1) * Cpad + c) * Npad + k0) = *(const u32x4 *)im[p];
+  }
+}
+
+// ws from W^c (complex FP32 [n_freq][N][N]); one thread per (w, row, 8 nu)
+template <int NS>
+__global__ void k_split_w(const float2 *__restrict__ W, int N, int Npad, int Rpad, int n_freq, us16 *__restrict__ ws) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int g8 = Npad / 8;
+  const long long per = (long long)Rpad * g8;
+  if (t >= per * n_freq) return;
+  const int w = (int)(t / per);
+  const int r = (int)((t % per) / g8);
+  const int k0 = (int)(t % g8) * 8;
+  const int mu = r + N - Rpad;
+  us16 re[NS][8], im[NS][8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int nu = k0 + e;
+    float2 v = mkcf(0.f, 0.f);
+    if (mu >= 0 && nu < mu) v = W[((long long)w * N + mu) * N + nu];
+    us16 a[NS], b[NS];
+    split_parts<NS>(v.x, a);
+    split_parts<NS>(v.y, b);
+#pragma unroll
+    for (int p = 0; p < NS; ++p) {
+      re[p][e] = a[p];
+      im[p][e] = b[p];
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < NS; ++p) {
+    const long long o = (((long long)w * NS + p) * 2) * Rpad;
+    *(u32x4 *)(ws + ((o + r) * Npad) + k0) = *(const u32x4 *)re[p];
+    *(u32x4 *)(ws + ((o + Rpad + r) * Npad) + k0) = *(const u32x4 *)im[p];
+  }
+}
+
+__device__ inline bf16x8 as_bf(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+__device__ inline u32x4 neg_bf(u32x4 v) { return v ^ 0x80008000u; }
+
+template <int NS>
+__global__ __launch_bounds__(256) void k_sigma_bf16(const us16 *__restrict__ xs, const us16 *__restrict__ ws,
+                                                    const float2 *__restrict__ x, const float2 *__restrict__ Wall,
+                                                    long long Ccols, long long Cpad, int N, int Npad, int Rpad, int n_freq,
+                                                    double *__restrict__ Xall) {
+  __shared__ __attribute__((aligned(16))) us16 Bs[2][NS * 2][TILE][SKB + SBP];   // [buf][part*2 + re/im][column][nu]
+  __shared__ double red[4][SNW * TILE];
+  long long cb;
+  int wb;
+  if (!xcd_map((n_freq + SNW - 1) / SNW, (Ccols + TILE - 1) / TILE, cb, wb)) return;
+  const long long c0 = cb * TILE;
+  const int w0 = wb * SNW;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, g = lane >> 4;
-  const int ngroups = (N + TILE - 1) / TILE;
-  const int base = N - ngroups * TILE;
-  double psum[4] = {0.0, 0.0, 0.0, 0.0};
-  const int lrow = tid >> 5, lk = tid & 31;     // 32 consecutive threads read 32 nu of one row; rows lrow + 8 t
+  const int ngroups = Rpad / TILE;
+  const int base = N - Rpad;
+  double psum[SNW][4];
+#pragma unroll
+  for (int v = 0; v < SNW; ++v)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) psum[v][j] = 0.0;
+  // staging map: thread -> (column, 8-nu group) of the 64 x 32 tile
+  const int scol = tid >> 2, sk = (tid & 3) * 8;
 
   for (int I = 0; I < ngroups; ++I) {
     const int mu0 = base + I * TILE;
-    const int nch = (mu0 + TILE - 2 >= 0) ? (mu0 + TILE - 2) / SKB + 1 : 1;
+    const int nch = (mu0 + TILE - 1 > 0) ? (mu0 + TILE - 1 + SKB - 1) / SKB : 0;   // nu < mu0 + 63
+    if (nch == 0) continue;
     const int r0 = mu0 + 16 * wave;
-    const bool active = (r0 + 15 >= 0);
-    const int kcw = active ? ((r0 + 14 >= 0) ? (r0 + 14) / SKB + 1 : 1) : 0;
-    f4v zr[4], zi[4];
+    const int kcw = (r0 + 15 > 0) ? (r0 + 15 + SKB - 1) / SKB : 0;                 // nu < r0 + 15
+    const int wrow = I * TILE + 16 * wave + col;                                     // stored row of this lane
+    f4v zr[SNW][4], zi[SNW][4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) zr[j] = zi[j] = Mfma<float>::zero();
-    float2 wreg[8], ureg[8];
-    auto fetch = [&](int ch) {
-      const int nu = ch * SKB + lk;
+    for (int v = 0; v < SNW; ++v)
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int m = lrow + 8 * t;
-        const int mu = mu0 + m;
-        float2 w = mkcf(0.f, 0.f);
-        if (mu >= 0 && mu < N && nu < mu) w = W[(long long)mu * N + nu];
-        wreg[t] = w;
-        const long long cc = c0 + m;
-        float2 u = mkcf(0.f, 0.f);
-        if (cc < Ccols && nu < N) u = cconj(x[cc * N + nu]);
-        ureg[t] = u;
-      }
-    };
-    auto stash = [&]() {
+      for (int j = 0; j < 4; ++j) zr[v][j] = zi[v][j] = Mfma<float>::zero();
+    u32x4 bpre[NS * 2];
+    const us16 *xsrc = xs + (c0 + scol) * Npad + sk;
+    __syncthreads();
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int m = lrow + 8 * t;
-        __bf16 a[NS], b[NS], c[NS], d[NS];
-        splitn_s<NS>(wreg[t].x, a);
-        splitn_s<NS>(wreg[t].y, b);
-        splitn_s<NS>(ureg[t].x, c);
-        splitn_s<NS>(ureg[t].y, d);
+    for (int pr = 0; pr < NS * 2; ++pr) bpre[pr] = *(const u32x4 *)(xsrc + (long long)pr * Cpad * Npad);
 #pragma unroll
-        for (int p = 0; p < NS; ++p) {
-          Wr[p][m][lk] = a[p];
-          Wi[p][m][lk] = b[p];
-          Ur[p][m][lk] = c[p];
-          Ui[p][m][lk] = d[p];
-        }
-      }
-    };
-    fetch(0);
+    for (int pr = 0; pr < NS * 2; ++pr) *(u32x4 *)&Bs[0][pr][scol][sk] = bpre[pr];
+    __syncthreads();
     for (int ch = 0; ch < nch; ++ch) {
-      __syncthreads();
-      stash();
-      __syncthreads();
-      if (ch + 1 < nch) fetch(ch + 1);
-      if (ch < kcw) {
-        bf16x8 ar[NS], ai[NS], nai[NS];
+      const int b = ch & 1;
+      if (ch + 1 < nch) {
 #pragma unroll
-        for (int p = 0; p < NS; ++p) {
-          ar[p] = *(const bf16x8 *)&Wr[p][16 * wave + col][8 * g];
-          ai[p] = *(const bf16x8 *)&Wi[p][16 * wave + col][8 * g];
-          nai[p] = -ai[p];
+        for (int pr = 0; pr < NS * 2; ++pr) bpre[pr] = *(const u32x4 *)(xsrc + (long long)pr * Cpad * Npad + (ch + 1) * SKB);
+      }
+      if (ch < kcw) {
+        // this wave's 16 rows of W for both frequencies, straight into registers
+        u32x4 acur[SNW][NS * 2];
+#pragma unroll
+        for (int v = 0; v < SNW; ++v) {
+          const int w = min(w0 + v, n_freq - 1);
+#pragma unroll
+          for (int pr = 0; pr < NS * 2; ++pr)
+            acur[v][pr] = *(const u32x4 *)(ws + (((long long)w * NS * 2 + pr) * Rpad + wrow) * Npad + ch * SKB + 8 * g);
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          bf16x8 ur[NS], ui[NS];
+          bf16x8 br[NS], bi[NS];
 #pragma unroll
           for (int p = 0; p < NS; ++p) {
-            ur[p] = *(const bf16x8 *)&Ur[p][16 * j + col][8 * g];
-            ui[p] = *(const bf16x8 *)&Ui[p][16 * j + col][8 * g];
+            br[p] = *(const bf16x8 *)&Bs[b][2 * p][16 * j + col][8 * g];
+            bi[p] = *(const bf16x8 *)&Bs[b][2 * p + 1][16 * j + col][8 * g];
           }
-          // Z += W u: re = Wr ur - Wi ui, im = Wr ui + Wi ur
 #pragma unroll
-          for (int p = 0; p < NS; ++p)
+          for (int v = 0; v < SNW; ++v) {
+            // Z += W u: re = Wr ur - Wi ui, im = Wr ui + Wi ur
 #pragma unroll
-            for (int q = 0; q + p < NS; ++q) {
-              zr[j] = mfma_bf16(ar[p], ur[q], zr[j]);
-              zr[j] = mfma_bf16(nai[p], ui[q], zr[j]);
-              zi[j] = mfma_bf16(ar[p], ui[q], zi[j]);
-              zi[j] = mfma_bf16(ai[p], ur[q], zi[j]);
+            for (int p = 0; p < NS; ++p) {
+              const bf16x8 ar = as_bf(acur[v][2 * p]), ai = as_bf(acur[v][2 * p + 1]);
+              const bf16x8 nai = as_bf(neg_bf(acur[v][2 * p + 1]));
+#pragma unroll
+              for (int q = 0; q + p < NS; ++q) {
+                zr[v][j] = mfma_bf16(ar, br[q], zr[v][j]);
+                zr[v][j] = mfma_bf16(nai, bi[q], zr[v][j]);
+                zi[v][j] = mfma_bf16(ar, bi[q], zi[v][j]);
+                zi[v][j] = mfma_bf16(ai, br[q], zi[v][j]);
+              }
             }
+          }
         }
       }
+      if (ch + 1 < nch) {
+#pragma unroll
+        for (int pr = 0; pr < NS * 2; ++pr) *(u32x4 *)&Bs[b ^ 1][pr][scol][sk] = bpre[pr];
+      }
+      __syncthreads();
     }
-    if (active) {
+    // X_c += 2 Re(x_mu Z_mu) + Re W_mumu |x_mu|^2 over this wave's rows
+    if (r0 + 15 >= 0) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const long long cc = c0 + 16 * j + col;
@@ -265,29 +360,39 @@ __global__ __launch_bounds__(256) void k_sigma_bf16(const float2 *__restrict__ x
           const int mu = r0 + Mfma<float>::row(lane, q);
           if (mu < 0 || mu >= N) continue;
           const float2 xv = x[cc * N + mu];
-          const double wdd = (double)W[(long long)mu * N + mu].x;
           const double xr = (double)xv.x, xi = (double)xv.y;
-          psum[j] += 2.0 * (xr * (double)zr[j][q] - xi * (double)zi[j][q]) + wdd * (xr * xr + xi * xi);
+#pragma unroll
+          for (int v = 0; v < SNW; ++v) {
+            if (w0 + v >= n_freq) continue;
+            const double wdd = (double)Wall[((long long)(w0 + v) * N + mu) * N + mu].x;
+            psum[v][j] += 2.0 * (xr * (double)zr[v][j][q] - xi * (double)zi[v][j][q]) + wdd * (xr * xr + xi * xi);
+          }
         }
       }
     }
   }
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    double v = psum[j];
-    v += __shfl_xor(v, 16);
-    v += __shfl_xor(v, 32);
-    psum[j] = v;
-  }
+  for (int v = 0; v < SNW; ++v)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      double t = psum[v][j];
+      t += __shfl_xor(t, 16);
+      t += __shfl_xor(t, 32);
+      psum[v][j] = t;
+    }
   __syncthreads();
   if (lane < 16) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) red[wave][16 * j + lane] = psum[j];
+    for (int v = 0; v < SNW; ++v)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) red[wave][v * TILE + 16 * j + lane] = psum[v][j];
   }
   __syncthreads();
-  if (tid < TILE) {
-    const long long cc = c0 + tid;
-    if (cc < Ccols) Xout[cc] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+  if (tid < SNW * TILE) {
+    const int v = tid / TILE, cl = tid % TILE;
+    const long long cc = c0 + cl;
+    if (cc < Ccols && w0 + v < n_freq)
+      Xall[(long long)(w0 + v) * Ccols + cc] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
   }
 }
 
@@ -332,19 +437,37 @@ int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const doubl
   hipEvent_t ev_all, ev;
   stage_begin(c, "sigma_c", &ev_all);
   stage_begin(c, "sigma_mfma", &ev);
-  dim3 grid((unsigned)((Ccols + TILE - 1) / TILE), d.n_freq);
+  const long long ncb = (Ccols + TILE - 1) / TILE;
+  dim3 grid(xcd_grid(d.n_freq, ncb));
   if (c->precision == LRIGW_FP64)
     hipLaunchKernelGGL(k_sigma_mfma<double>, grid, dim3(256), 0, c->stream, (const double2 *)x, (const double2 *)Wc, Ccols,
-                       d.n_aux, (double *)c->d_X);
+                       d.n_aux, d.n_freq, (double *)c->d_X);
   else if (c->precision == LRIGW_FP32)
     hipLaunchKernelGGL(k_sigma_mfma<float>, grid, dim3(256), 0, c->stream, (const float2 *)x, (const float2 *)Wc, Ccols,
-                       d.n_aux, (double *)c->d_X);
-  else if (c->precision == LRIGW_SPLIT_BF16)
-    hipLaunchKernelGGL(k_sigma_bf16<2>, grid, dim3(256), 0, c->stream, (const float2 *)x, (const float2 *)Wc, Ccols,
-                       d.n_aux, (double *)c->d_X);
-  else
-    hipLaunchKernelGGL(k_sigma_bf16<3>, grid, dim3(256), 0, c->stream, (const float2 *)x, (const float2 *)Wc, Ccols,
-                       d.n_aux, (double *)c->d_X);
+                       d.n_aux, d.n_freq, (double *)c->d_X);
+  else {
+    const long long Cpad = (Ccols + TILE - 1) / TILE * TILE;
+    const int Npad = (d.n_aux + SKB - 1) / SKB * SKB;
+    const int Rpad = (d.n_aux + TILE - 1) / TILE * TILE;
+    us16 *xs = (us16 *)c->d_xs, *ws = (us16 *)c->d_ws;
+    const long long nx = Cpad * (Npad / 8), nwt = (long long)d.n_freq * Rpad * (Npad / 8);
+    dim3 g2(xcd_grid((d.n_freq + SNW - 1) / SNW, ncb));
+    if (c->precision == LRIGW_SPLIT_BF16) {
+      hipLaunchKernelGGL(k_split_x<2>, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, c->stream, (const float2 *)x, Ccols,
+                         d.n_aux, Cpad, Npad, xs);
+      hipLaunchKernelGGL(k_split_w<2>, dim3((unsigned)((nwt + 255) / 256)), dim3(256), 0, c->stream, (const float2 *)Wc,
+                         d.n_aux, Npad, Rpad, d.n_freq, ws);
+      hipLaunchKernelGGL(k_sigma_bf16<2>, g2, dim3(256), 0, c->stream, xs, ws, (const float2 *)x, (const float2 *)Wc, Ccols,
+                         Cpad, d.n_aux, Npad, Rpad, d.n_freq, (double *)c->d_X);
+    } else {
+      hipLaunchKernelGGL(k_split_x<3>, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, c->stream, (const float2 *)x, Ccols,
+                         d.n_aux, Cpad, Npad, xs);
+      hipLaunchKernelGGL(k_split_w<3>, dim3((unsigned)((nwt + 255) / 256)), dim3(256), 0, c->stream, (const float2 *)Wc,
+                         d.n_aux, Npad, Rpad, d.n_freq, ws);
+      hipLaunchKernelGGL(k_sigma_bf16<3>, g2, dim3(256), 0, c->stream, xs, ws, (const float2 *)x, (const float2 *)Wc, Ccols,
+                         Cpad, d.n_aux, Npad, Rpad, d.n_freq, (double *)c->d_X);
+    }
+  }
   stage_end(c, "sigma_mfma", ev);
   LRIGW_TRY(lrigw_launch_check("sigma_mfma"));
   long long tot = (long long)d.n_k * d.n_qp * d.n_freq;

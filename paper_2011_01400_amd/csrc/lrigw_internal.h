@@ -91,6 +91,8 @@ struct lrigw_ctx {
   double2 *d_dinv = nullptr;     // inverses of 64x64 diagonal Cholesky blocks, [N_w][zdinv_stride(N)]
   int *d_info = nullptr;         // device status words
   void *d_bhat = nullptr;        // q = 0 modified B (T)
+  void *d_xs = nullptr;          // split-BF16 forms: BF16 parts of conj(x), [NS][2][Cpad][Npad]
+  void *d_ws = nullptr;          // split-BF16 forms: BF16 parts of lower W^c, [N_w][NS][2][Rpad][Npad]
 
   // q = 0 data
   double2 *d_x1 = nullptr;       // [N_aux]
