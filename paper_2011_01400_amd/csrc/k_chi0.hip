@@ -185,132 +185,185 @@ __device__ inline void splitn(float v, __bf16 *p) {
   }
 }
 
-template <int NS, int NW>
-__global__ __launch_bounds__(256) void k_chi0_bf16(const float2 *__restrict__ B, const float *__restrict__ delta,
-                                                   const double *__restrict__ omega, const int *__restrict__ wsel,
-                                                   const int *__restrict__ run, long long K, int N, int n_freq,
-                                                   long long Ks, long long ntile, float2 *__restrict__ part) {
-  if (run && *run == 0) return;
-  __shared__ __bf16 Ar[NS][TILE][KCB + BAP];   // A side (rows mu), real parts, k contiguous
-  __shared__ __bf16 Ai[NS][TILE][KCB + BAP];
-  __shared__ float2 Bs[TILE][KCB + BBP];        // B side (cols nu), FP32, k contiguous
-  __shared__ float dl[KCB];
+// Split-BF16 form.  Once per q the response operand B[K][N] is rewritten as
+//   Ap[p][re/im][Npad][Kp]  BF16 parts (row mu, k contiguous, zero padded)
+//   Bt[Npad][Kp]            the FP32 values transposed (row nu, k contiguous)
+// (Npad: 64-multiple, Kp: 32-multiple).  In the main kernel a workgroup owns a
+// 64 x 64 tile (rows mu, columns nu), each wave a 64 x 16 strip: the A
+// fragments (rows) come from a double-buffered LDS tile filled with 16-byte
+// copies of Ap; the B fragments (the wave's 16 columns) are read from Bt
+// straight into registers, weighted by 2D/(D^2 + w^2) and split into NS parts
+// there, once per element and frequency.
+typedef unsigned short us16;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
+template <int NS>
+__device__ inline void split_us(float v, us16 *out) {
+  float r = v;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const __bf16 h = (__bf16)r;
+    out[i] = __builtin_bit_cast(us16, h);
+    r -= (float)h;
+  }
+}
+
+// 32 (k) x 32 (mu) tiles through LDS; block 32 x 8 threads
+template <int NS>
+__global__ __launch_bounds__(256) void k_chi0_presplit(const float2 *__restrict__ B, long long K, int N, long long Kp,
+                                                       int Npad, us16 *__restrict__ Ap, float2 *__restrict__ Bt) {
+  __shared__ float2 t[32][33];
+  const long long k0 = (long long)blockIdx.x * 32;
+  const int m0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int kk = ty + 8 * i;
+    float2 v = mkcf(0.f, 0.f);
+    if (k0 + kk < K && m0 + tx < N) v = B[(k0 + kk) * N + m0 + tx];
+    t[kk][tx] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int mm = ty + 8 * i;
+    const float2 v = t[tx][mm];
+    const long long o = (long long)(m0 + mm) * Kp + k0 + tx;
+    Bt[o] = v;
+    us16 a[NS], b[NS];
+    split_us<NS>(v.x, a);
+    split_us<NS>(v.y, b);
+#pragma unroll
+    for (int p = 0; p < NS; ++p) {
+      Ap[(long long)(2 * p) * Npad * Kp + o] = a[p];
+      Ap[(long long)(2 * p + 1) * Npad * Kp + o] = b[p];
+    }
+  }
+}
+
+template <int NS, int NW>
+__global__ __launch_bounds__(256) void k_chi0_bf16(const us16 *__restrict__ Ap, const float2 *__restrict__ Bt,
+                                                   const float *__restrict__ delta, const double *__restrict__ omega,
+                                                   const int *__restrict__ wsel, const int *__restrict__ run, long long K,
+                                                   long long Kp, int Npad, int n_freq, long long Ks, long long ntile,
+                                                   float2 *__restrict__ part) {
+  if (run && *run == 0) return;
+  __shared__ __attribute__((aligned(16))) us16 As[2][NS * 2][TILE][KCB + BAP];
   int I, J;
   tri_decode(blockIdx.x, I, J);
   const int w0 = blockIdx.y * NW;
   const long long kb = (long long)blockIdx.z * Ks;
   const long long ke = min(K, kb + Ks);
   const int mu0 = I * TILE, nu0 = J * TILE;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1, col = lane & 15, g = lane >> 4;
-
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, g = lane >> 4;
   float om2[NW];
 #pragma unroll
   for (int w = 0; w < NW; ++w) {
-    double o = (w0 + w < n_freq) ? omega[wsel[w0 + w]] : 0.0;
+    const double o = (w0 + w < n_freq) ? omega[wsel[w0 + w]] : 0.0;
     om2[w] = (float)(o * o);
   }
-  f4v re[NW][2][2], im[NW][2][2];
+  f4v re[NW][4], im[NW][4];
 #pragma unroll
   for (int w = 0; w < NW; ++w)
 #pragma unroll
-    for (int si = 0; si < 2; ++si)
+    for (int si = 0; si < 4; ++si) re[w][si] = im[w][si] = Mfma<float>::zero();
+  const int nch = (int)((ke - kb + KCB - 1) / KCB);
+  if (nch <= 0) goto store;
+  {
+    // staging map of the A tile: thread -> (row, 8-k piece)
+    const int arow = tid >> 2, ak = (tid & 3) * 8;
+    const us16 *asrc = Ap + (long long)(mu0 + arow) * Kp + kb + ak;
+    const long long pstride = (long long)Npad * Kp;
+    const float2 *bsrc = Bt + (long long)(nu0 + 16 * wave + col) * Kp + kb + 8 * g;
+    u32x4 apre[NS * 2];
+    float2 bcur[8], bnext[8];
+    float dcur[8], dnext[8];
 #pragma unroll
-      for (int sj = 0; sj < 2; ++sj) re[w][si][sj] = im[w][si][sj] = Mfma<float>::zero();
-  for (long long k0 = kb; k0 < ke; k0 += KCB) {
+    for (int pr = 0; pr < NS * 2; ++pr) apre[pr] = *(const u32x4 *)(asrc + pr * pstride);
 #pragma unroll
-    for (int t = 0; t < (KCB * TILE) / 256; ++t) {
-      const int e = tid + 256 * t;
-      const int kk = e / TILE, m = e % TILE;
-      const long long kr = k0 + kk;
-      float2 a = mkcf(0.f, 0.f), b = mkcf(0.f, 0.f);
-      if (kr < ke) {
-        if (mu0 + m < N) a = B[kr * N + mu0 + m];
-        if (nu0 + m < N) b = B[kr * N + nu0 + m];
-      }
-      __bf16 pr[NS], pi[NS];
-      splitn<NS>(a.x, pr);
-      splitn<NS>(a.y, pi);
-#pragma unroll
-      for (int p = 0; p < NS; ++p) {
-        Ar[p][m][kk] = pr[p];
-        Ai[p][m][kk] = pi[p];
-      }
-      Bs[m][kk] = b;
+    for (int e = 0; e < 8; ++e) {
+      bcur[e] = bsrc[e];
+      const long long k = kb + 8 * g + e;
+      dcur[e] = k < K ? delta[k] : 1.f;
     }
-    if (tid < KCB) dl[tid] = (k0 + tid < ke) ? delta[k0 + tid] : 1.f;
+#pragma unroll
+    for (int pr = 0; pr < NS * 2; ++pr) *(u32x4 *)&As[0][pr][arow][ak] = apre[pr];
     __syncthreads();
-    // A operands (rows 32 wr + 16 si + col, k = 8g..8g+7)
-    bf16x8 ar[2][NS], ai[2][NS], nar[2][NS];
+    for (int ch = 0; ch < nch; ++ch) {
+      const int b = ch & 1;
+      if (ch + 1 < nch) {
+        const long long off = (long long)(ch + 1) * KCB;
 #pragma unroll
-    for (int si = 0; si < 2; ++si)
+        for (int pr = 0; pr < NS * 2; ++pr) apre[pr] = *(const u32x4 *)(asrc + pr * pstride + off);
 #pragma unroll
-      for (int p = 0; p < NS; ++p) {
-        ar[si][p] = *(const bf16x8 *)&Ar[p][32 * wr + 16 * si + col][8 * g];
-        ai[si][p] = *(const bf16x8 *)&Ai[p][32 * wr + 16 * si + col][8 * g];
-        nar[si][p] = -ar[si][p];
+        for (int e = 0; e < 8; ++e) {
+          bnext[e] = bsrc[off + e];
+          const long long k = kb + off + 8 * g + e;
+          dnext[e] = k < K ? delta[k] : 1.f;
+        }
       }
-    float dd[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) dd[e] = dl[8 * g + e];
-    float2 bv[2][8];
-#pragma unroll
-    for (int sj = 0; sj < 2; ++sj)
-#pragma unroll
-      for (int e = 0; e < 8; ++e) bv[sj][e] = Bs[32 * wc + 16 * sj + col][8 * g + e];
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-      float wt[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) wt[e] = 2.f * dd[e] / (dd[e] * dd[e] + om2[w]);
-#pragma unroll
-      for (int sj = 0; sj < 2; ++sj) {
+      for (int w = 0; w < NW; ++w) {
+        // this wave's 16 columns, weighted for frequency w and split
         bf16x8 br[NS], bi[NS];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          __bf16 pr[NS], pi[NS];
-          splitn<NS>(wt[e] * bv[sj][e].x, pr);
-          splitn<NS>(wt[e] * bv[sj][e].y, pi);
+          const float wt = 2.f * dcur[e] / (dcur[e] * dcur[e] + om2[w]);
+          us16 pr_[NS], pi_[NS];
+          split_us<NS>(wt * bcur[e].x, pr_);
+          split_us<NS>(wt * bcur[e].y, pi_);
 #pragma unroll
           for (int p = 0; p < NS; ++p) {
-            br[p][e] = pr[p];
-            bi[p][e] = pi[p];
+            br[p][e] = __builtin_bit_cast(__bf16, pr_[p]);
+            bi[p][e] = __builtin_bit_cast(__bf16, pi_[p]);
           }
         }
 #pragma unroll
-        for (int si = 0; si < 2; ++si) {
-          // a conj(b): re = ar br + ai bi, im = ai br - ar bi
+        for (int si = 0; si < 4; ++si) {
 #pragma unroll
-          for (int p = 0; p < NS; ++p)
+          for (int p = 0; p < NS; ++p) {
+            const u32x4 ur = *(const u32x4 *)&As[b][2 * p][16 * si + col][8 * g];
+            const u32x4 ui = *(const u32x4 *)&As[b][2 * p + 1][16 * si + col][8 * g];
+            const bf16x8 ar = __builtin_bit_cast(bf16x8, ur), ai = __builtin_bit_cast(bf16x8, ui);
+            const bf16x8 nar = __builtin_bit_cast(bf16x8, ur ^ 0x80008000u);
+            // a conj(b): re = ar br + ai bi, im = ai br - ar bi
 #pragma unroll
             for (int q = 0; q + p < NS; ++q) {
-              re[w][si][sj] = mfma_bf16(ar[si][p], br[q], re[w][si][sj]);
-              re[w][si][sj] = mfma_bf16(ai[si][p], bi[q], re[w][si][sj]);
-              im[w][si][sj] = mfma_bf16(ai[si][p], br[q], im[w][si][sj]);
-              im[w][si][sj] = mfma_bf16(nar[si][p], bi[q], im[w][si][sj]);
+              re[w][si] = mfma_bf16(ar, br[q], re[w][si]);
+              re[w][si] = mfma_bf16(ai, bi[q], re[w][si]);
+              im[w][si] = mfma_bf16(ai, br[q], im[w][si]);
+              im[w][si] = mfma_bf16(nar, bi[q], im[w][si]);
             }
+          }
         }
       }
+      if (ch + 1 < nch) {
+#pragma unroll
+        for (int pr = 0; pr < NS * 2; ++pr) *(u32x4 *)&As[b ^ 1][pr][arow][ak] = apre[pr];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          bcur[e] = bnext[e];
+          dcur[e] = dnext[e];
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
+store:
 #pragma unroll
   for (int w = 0; w < NW; ++w) {
     if (w0 + w >= n_freq) continue;
     float2 *dst = part + (((long long)blockIdx.z * n_freq + w0 + w) * ntile + blockIdx.x) * (TILE * TILE);
 #pragma unroll
-    for (int si = 0; si < 2; ++si)
+    for (int si = 0; si < 4; ++si) {
+      const f4v r = re[w][si], i = im[w][si];
 #pragma unroll
-      for (int sj = 0; sj < 2; ++sj) {
-        const f4v r = re[w][si][sj], i = im[w][si][sj];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int row = 32 * wr + 16 * si + Mfma<float>::row(lane, q);
-          const int cl = 32 * wc + 16 * sj + col;
-          dst[row * TILE + cl] = mkcf(r[q], i[q]);
-        }
+      for (int q = 0; q < 4; ++q) {
+        const int row = 16 * si + Mfma<float>::row(lane, q);
+        const int cl = 16 * wave + col;
+        dst[row * TILE + cl] = mkcf(r[q], i[q]);
       }
+    }
   }
 }
 
@@ -429,12 +482,23 @@ int run_chi0_sel(lrigw_ctx *c, int iq, const void *M, const double *eig, int app
     if (c->precision == LRIGW_FP32) {
       if (NW == 4) hipLaunchKernelGGL((k_chi0_mfma<float, 4>), grid, dim3(256), 0, c->stream, Bf, Df, CHI0_ARGS, Pf);
       else hipLaunchKernelGGL((k_chi0_mfma<float, 2>), grid, dim3(256), 0, c->stream, Bf, Df, CHI0_ARGS, Pf);
-    } else if (c->precision == LRIGW_SPLIT_BF16) {
-      if (NW == 4) hipLaunchKernelGGL((k_chi0_bf16<2, 4>), grid, dim3(256), 0, c->stream, Bf, Df, CHI0_ARGS, Pf);
-      else hipLaunchKernelGGL((k_chi0_bf16<2, 2>), grid, dim3(256), 0, c->stream, Bf, Df, CHI0_ARGS, Pf);
     } else {
-      if (NW == 4) hipLaunchKernelGGL((k_chi0_bf16<3, 4>), grid, dim3(256), 0, c->stream, Bf, Df, CHI0_ARGS, Pf);
-      else hipLaunchKernelGGL((k_chi0_bf16<3, 2>), grid, dim3(256), 0, c->stream, Bf, Df, CHI0_ARGS, Pf);
+      const long long Kp = (K + KCB - 1) / KCB * KCB;
+      const int Npad = nt * TILE;
+      us16 *Apd = (us16 *)c->d_ap;
+      float2 *Btd = (float2 *)c->d_bt;
+      dim3 pg((unsigned)(Kp / 32), (unsigned)(Npad / 32));
+#define BF16_ARGS Apd, Btd, Df, c->d_omega, wsel, run, K, Kp, Npad, n_sel, Ks, ntile, Pf
+      if (c->precision == LRIGW_SPLIT_BF16) {
+        hipLaunchKernelGGL(k_chi0_presplit<2>, pg, dim3(256), 0, c->stream, Bf, K, d.n_aux, Kp, Npad, Apd, Btd);
+        if (NW == 4) hipLaunchKernelGGL((k_chi0_bf16<2, 4>), grid, dim3(256), 0, c->stream, BF16_ARGS);
+        else hipLaunchKernelGGL((k_chi0_bf16<2, 2>), grid, dim3(256), 0, c->stream, BF16_ARGS);
+      } else {
+        hipLaunchKernelGGL(k_chi0_presplit<3>, pg, dim3(256), 0, c->stream, Bf, K, d.n_aux, Kp, Npad, Apd, Btd);
+        if (NW == 4) hipLaunchKernelGGL((k_chi0_bf16<3, 4>), grid, dim3(256), 0, c->stream, BF16_ARGS);
+        else hipLaunchKernelGGL((k_chi0_bf16<3, 2>), grid, dim3(256), 0, c->stream, BF16_ARGS);
+      }
+#undef BF16_ARGS
     }
   }
 #undef CHI0_ARGS

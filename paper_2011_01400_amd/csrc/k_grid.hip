@@ -144,6 +144,9 @@ int run_grids(lrigw_ctx *c) {
     const long long Rpad = (d.n_aux + TILE - 1) / TILE * TILE;
     LRIGW_HIP_TRY(hipMalloc(&c->d_xs, (size_t)NS * 2 * Cpad * Npad * 2));
     LRIGW_HIP_TRY(hipMalloc(&c->d_ws, (size_t)d.n_freq * NS * 2 * Rpad * Npad * 2));
+    const long long Kp = (K + 31) / 32 * 32;
+    LRIGW_HIP_TRY(hipMalloc(&c->d_ap, (size_t)NS * 2 * Rpad * Kp * 2));
+    LRIGW_HIP_TRY(hipMalloc(&c->d_bt, (size_t)Rpad * Kp * sizeof(float2)));
   }
   return LRIGW_OK;
 }

@@ -91,6 +91,8 @@ struct lrigw_ctx {
   double2 *d_dinv = nullptr;     // inverses of 64x64 diagonal Cholesky blocks, [N_w][zdinv_stride(N)]
   int *d_info = nullptr;         // device status words
   void *d_bhat = nullptr;        // q = 0 modified B (T)
+  void *d_ap = nullptr;          // split-BF16 forms: BF16 parts of B, [NS][2][Npad][Kp] (k contiguous)
+  void *d_bt = nullptr;          // split-BF16 forms: B transposed, FP32 [Npad][Kp]
   void *d_xs = nullptr;          // split-BF16 forms: BF16 parts of conj(x), [NS][2][Cpad][Npad]
   void *d_ws = nullptr;          // split-BF16 forms: BF16 parts of lower W^c, [N_w][NS][2][Rpad][Npad]
 
