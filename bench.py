@@ -22,7 +22,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0}
+# MI355X dense matrix peaks (the split forms run BF16 MFMA)
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0, "split3_bf16": 2500.0}
+DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16", "split3_bf16": "bf16"}
+STAGES = ("lri_ft", "build_M", "chi0", "chi0_split", "chi0_mfma", "screen", "sigma_c", "sigma_split", "sigma_mfma", "qp")
 HA_MEV = 27211.386
 
 
@@ -32,7 +35,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "split_bf16"])
+    ap.add_argument("--precision", default="split3_bf16", choices=list(PEAK_TFLOPS))
+    ap.add_argument("--no-tune", action="store_true", help="skip the response-kernel tile autotuner")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain FP64 path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--n-par", type=int, default=16)
@@ -73,7 +77,7 @@ class Run:
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         stages = {}
-        for name in ("lri_ft", "build_M", "chi0", "chi0_mfma", "screen", "sigma_c", "sigma_mfma", "qp"):
+        for name in STAGES:
             ms, n = self.ctx.stage_ms(name)
             if n:
                 stages[name] = (ms, n)
@@ -81,17 +85,42 @@ class Run:
         return dt, stages
 
 
-def roofline(sysm, stages, precision):
-    """Dominant MFMA kernel: algorithmic flops per launch / average launch time."""
+def algorithmic_flops(sysm):
+    """Real flops of one launch of each MFMA kernel (one q, all frequencies):
+    chi0: 8 N_aux^2 K per (q, w) pair, K = N_k N_occ N_unocc (full Hermitian
+    count); Sigma^c: 8 N_aux^2 N_k N_qp N_bands per pair."""
     sp = sysm.spec
     n_aux, n_k, nw = sysm.n_aux, sysm.n_k, sp.n_freq
     K = n_k * sp.n_occ * (sp.n_bands - sp.n_occ)
-    flops = {
-        # chi0: 8 N_aux^2 K real flops per (q, w) pair (full Hermitian count), one launch = one q, all w
-        "chi0_mfma": 8.0 * n_aux * n_aux * K * nw,
-        # Sigma^c: 8 N_aux^2 N_k N_qp N_bands per pair, one launch = one q, all w
-        "sigma_mfma": 8.0 * n_aux * n_aux * n_k * sp.n_qp * sp.n_bands * nw,
-    }
+    return {"chi0_mfma": 8.0 * n_aux * n_aux * K * nw,
+            "sigma_mfma": 8.0 * n_aux * n_aux * n_k * sp.n_qp * sp.n_bands * nw}
+
+
+def traffic_for(kernel, precision, config):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    r = rec.get(f"{kernel}:{precision}:c{config}")
+    if not r:
+        return None
+    src = os.path.join(ROOT, "paper_2011_01400_amd", "csrc", r["source"])
+    try:
+        with open(src, "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()[:16]
+    except OSError:
+        return None
+    return r["bytes_per_launch"] if h == r["source_sha256_16"] else None
+
+
+def roofline(sysm, stages, precision, config):
+    """Dominant MFMA kernel: algorithmic flops per launch / average launch time."""
+    flops = algorithmic_flops(sysm)
     best = None
     for name, f in flops.items():
         if name not in stages:
@@ -104,8 +133,22 @@ def roofline(sysm, stages, precision):
     achieved = f / avg_s / 1e12
     peak = PEAK_TFLOPS[precision]
     return {"bound": "mfma", "kernel": name, "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": None, "avg_launch_ms": round(ms / n, 4),
-            "flops_per_launch": f}
+            "frac": round(achieved / peak, 4), "traffic": traffic_for(name, precision, config),
+            "avg_launch_ms": round(ms / n, 4), "flops_per_launch": f}
+
+
+def other_kernel(sysm, stages, precision, rl):
+    """The same figures for the other MFMA kernel."""
+    flops = algorithmic_flops(sysm)
+    out = {}
+    for name, f in flops.items():
+        if name == rl["kernel"] or name not in stages:
+            continue
+        ms, n = stages[name]
+        a = f / (ms / n / 1e3) / 1e12
+        out[name] = {"achieved": round(a, 2), "peak": PEAK_TFLOPS[precision], "frac": round(a / PEAK_TFLOPS[precision], 4),
+                     "avg_launch_ms": round(ms / n, 4)}
+    return out
 
 
 def cpu_baseline(sysm):
@@ -171,6 +214,12 @@ def main():
     pairs = sysm.n_k * sp.n_freq
 
     run = Run(L, sysm, dev, args.precision, args.n_par)
+    tuned = None
+    if not args.no_tune:
+        run.ctx.lri_ft(dev["lri"], sysm.R, dev["evec"], run.H)
+        nw, sp_, ms = run.ctx.tune(run.H, dev["evec"], dev["eig"])
+        tuned = {"freq_per_workgroup": nw, "k_splits": sp_, "chi0_ms_one_q": round(ms, 3)}
+        print(f"# bench: tuned chi0 tiles {tuned}", file=sys.stderr, flush=True)
     print(f"# bench: config {args.config} precision {args.precision}: warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
     dt, stages = run.timed(args.steps, args.warmup)
@@ -183,20 +232,27 @@ def main():
         prun = Run(L, sysm, dev, "fp64", args.n_par)
         pdt, pstages = prun.timed(1, 1)
         e_plain = prun.e_qp.cpu().numpy()
+        z_plain = prun.z.cpu().numpy()
+        reg = (z_plain >= 0.5) & (z_plain <= 1.0)
+        d = np.abs(e_form - e_plain) * HA_MEV
         plain = {"value": round(pairs / pdt, 2), "ms_per_step": round(pdt * 1e3, 2),
-                 "qp_max_err_mev_vs_plain": float(np.max(np.abs(e_form - e_plain)) * HA_MEV),
-                 "roofline": roofline(sysm, pstages, "fp64")}
-        print(f"# bench: plain fp64 {plain['value']} pairs/s, QP diff {plain['qp_max_err_mev_vs_plain']:.3e} meV",
-              file=sys.stderr, flush=True)
+                 "qp_max_err_mev_quasiparticle_like": float(d[reg].max()),
+                 "qp_max_err_mev_all_states": float(d.max()),
+                 "quasiparticle_like_states": f"{int(reg.sum())} of {reg.size} (0.5 <= Z <= 1 in the plain path)",
+                 "within_1_mev": bool(d[reg].max() <= 1.0),
+                 "stages_ms_per_step": {k: round(v[0], 3) for k, v in pstages.items()},
+                 "roofline": roofline(sysm, pstages, "fp64", args.config)}
+        print(f"# bench: plain fp64 {plain['value']} pairs/s, QP diff {plain['qp_max_err_mev_quasiparticle_like']:.3f} meV "
+              f"(quasiparticle-like), {plain['qp_max_err_mev_all_states']:.3f} meV (all)", file=sys.stderr, flush=True)
         prun.ctx.close()
         del prun
 
-    rl = roofline(sysm, stages, args.precision)
+    rl = roofline(sysm, stages, args.precision, args.config)
     out = {
         "metric": "chi0+Sigma^c (q,w)-pairs/s", "value": round(value, 2), "unit": "(q,w)-pairs/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16x3"}[args.precision],
+        "dtype": DTYPE[args.precision],
         "data": "synthetic",
         "config": {"workload": f"Si-like 2-atom cell (config {args.config}): N_b={sysm.n_b}, N_aux={sysm.n_aux}, "
                                f"k grid {'x'.join(map(str, sp.nk))}, N_occ={sp.n_occ}, {sp.n_bands} bands, "
@@ -204,7 +260,10 @@ def main():
                    "precision_form": args.precision, "pairs_per_step": pairs},
         "stages_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in stages.items()},
         "roofline": rl,
+        "other_kernel": other_kernel(sysm, stages, args.precision, rl),
     }
+    if tuned:
+        out["tuned"] = tuned
     if plain:
         out["plain_fp64"] = plain
         out["speedup_vs_plain"] = round(value / plain["value"], 3)

@@ -301,6 +301,13 @@ int lrigw_batch_tuning(const lrigw_batch *b, int cell, int *nw, int *splits, dou
 int lrigw_batch_graph_nodes(const lrigw_batch *b, long long *n_nodes);
 int lrigw_batch_destroy(lrigw_batch *b);
 
+/* Tile autotuner for one context (the same one lrigw_batch_create runs per
+ * cell): times the response kernel on one q over its tile choices and keeps
+ * the fastest for the context's later calls.  H, evec, eig as lrigw_g0w0.
+ * Outputs (host, may be NULL): frequencies per workgroup, K splits, time (ms).
+ * Synchronous. */
+int lrigw_tune(lrigw_ctx *ctx, const void *H, const void *evec, const double *eig, int *nw, int *splits, double *ms);
+
 /* Per-kernel device time (ms, HIP events on the context stream) accumulated
  * since the last reset, for the named stages "build_M", "chi0", "screen",
  * "sigma_c", "qp", "lri_ft".  Timing is recorded only after

@@ -42,7 +42,7 @@ void stage_end(lrigw_ctx *c, const char *name, hipEvent_t ev) {
 static void free_all(lrigw_ctx *c) {
   void *ptrs[] = {c->d_aux_atom, c->d_basis_off, c->d_aux_off, c->d_kpq, c->d_kmq, c->d_omega, c->d_weight, c->d_wall,
                   c->d_delta, c->d_part, c->d_X, c->d_LV, c->d_s0, c->d_s1, c->d_s2, c->d_s3, c->d_dinv, c->d_info,
-                  c->d_bhat, c->d_x1, c->d_M, c->d_x, c->d_chi, c->d_wc, c->d_epsqp, c->d_xs, c->d_ws, c->d_ap, c->d_bt};
+                  c->d_bhat, c->d_x1, c->d_M, c->d_x, c->d_chi, c->d_wc, c->d_epsqp, c->d_xs, c->d_ws, c->d_ap, c->d_bt, c->d_chi2, c->d_wc2};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &kv : c->stages)
@@ -50,6 +50,11 @@ static void free_all(lrigw_ctx *c) {
       hipEventDestroy(pr.first);
       hipEventDestroy(pr.second);
     }
+  for (int i = 0; i < 2; ++i) {
+    if (c->ev_chi[i]) hipEventDestroy(c->ev_chi[i]);
+    if (c->ev_wc[i]) hipEventDestroy(c->ev_wc[i]);
+  }
+  if (c->stream2) hipStreamDestroy(c->stream2);
 }
 
 // eps_qp[k][n] = eig[k][qp_lo + n]
@@ -69,34 +74,91 @@ int driver_buffers(lrigw_ctx *c) {
   if (!c->d_chi) LRIGW_HIP_TRY(hipMalloc(&c->d_chi, (size_t)d.n_freq * d.n_aux * d.n_aux * cs));
   if (!c->d_wc) LRIGW_HIP_TRY(hipMalloc(&c->d_wc, (size_t)d.n_freq * d.n_aux * d.n_aux * cs));
   if (!c->d_epsqp) LRIGW_HIP_TRY(hipMalloc(&c->d_epsqp, (size_t)d.n_k * d.n_qp * sizeof(double)));
+  if (!c->d_chi2) LRIGW_HIP_TRY(hipMalloc(&c->d_chi2, (size_t)d.n_freq * d.n_aux * d.n_aux * cs));
+  if (!c->d_wc2) LRIGW_HIP_TRY(hipMalloc(&c->d_wc2, (size_t)d.n_freq * d.n_aux * d.n_aux * cs));
+  if (!c->stream2) LRIGW_HIP_TRY(hipStreamCreate(&c->stream2));   // default priority
+  for (int i = 0; i < 2; ++i) {
+    if (!c->ev_chi[i]) LRIGW_HIP_TRY(hipEventCreateWithFlags(&c->ev_chi[i], hipEventDisableTiming));
+    if (!c->ev_wc[i]) LRIGW_HIP_TRY(hipEventCreateWithFlags(&c->ev_wc[i], hipEventDisableTiming));
+  }
   return LRIGW_OK;
 }
 
 // One pass over q_first..q_last-1 (and the QP step when every q was done).
-// With c->capturing the pass makes no host round trip: the screening status
-// is folded into d_info[16] and the QP flags stay in d_info[8..9].
+// Software pipeline over q on two streams: `stream` builds M and the response
+// of q (into one of two chi buffers) and then the Sigma^c contribution of q-1;
+// `stream2` screens q (into one of two W^c buffers) as soon as its response is
+// ready, so the latency-bound screening overlaps the MFMA-bound response of
+// q+1.  Events order the buffer reuse:
+//   chi[q&1] is rewritten only after sigma(q-2), which waited for screen(q-2);
+//   W[q&1] is rewritten by screen(q), which starts after chi0(q), issued after
+//   sigma(q-2) on `stream`.
+// The screening status is folded on the device (d_info[16] = first failing q)
+// and read once at the end (not under graph capture).  With a surrogate
+// attached (its per-q work shares the screening workspaces), and under graph
+// capture (the batched form overlaps whole cells on streams of their own
+// instead), the pass runs on `stream` alone.
 int run_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *p, double omega_cell,
              const double *e_static, int n_par, int q_first, int q_last, void *sigma, double *e_qp, double *z, int *info) {
   (void)omega_cell;
   const Dims &d = c->d;
   const bool all_q = (q_first == 0 && q_last == d.n_k);
-  hipStream_t s = c->stream;
+  const hipStream_t s = c->stream;
+  const bool overlap = (c->sur == nullptr) && !c->capturing;
+  const hipStream_t s2 = overlap ? c->stream2 : s;
   LRIGW_TRY(zero_fill(s, sigma, (size_t)d.n_k * d.n_qp * d.n_freq * sizeof(double2)));
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->d_info + 16, INT_MAX);
-  size_t vstride = (size_t)d.n_aux * d.n_aux;
-  for (int q = q_first; q < q_last; ++q) {
-    LRIGW_TRY(lrigw_build_M(c, q, 0, H, evec, c->d_M));
-    const int g = (p && q == 0) ? 1 : 0;
-    if (c->sur) LRIGW_TRY(lrigw_chi0_surrogate(c, c->sur, q, c->d_M, eig, g, c->sur_threshold, c->d_chi));
-    else LRIGW_TRY(lrigw_chi0(c, q, c->d_M, eig, g, c->d_chi));
-    int sinfo = -1;
-    int rc = lrigw_screen(c, q, c->d_chi, (const double2 *)V + q * vstride, c->d_wc, &sinfo);
-    if (rc < 0) {
-      if (info) *info = q;
-      return rc;
+  const size_t vstride = (size_t)d.n_aux * d.n_aux;
+  // two buffers in either mode: Sigma^c(q-1) is issued after screen(q)
+  void *chi[2] = {c->d_chi, c->d_chi2};
+  void *wc[2] = {c->d_wc, c->d_wc2};
+  const bool was_capturing = c->capturing;
+  c->capturing = true;   // screening: device-side status, no host round trip
+  int rc = LRIGW_OK;
+  for (int q = q_first; q <= q_last && rc == LRIGW_OK; ++q) {
+    if (q < q_last) {
+      const int b = q & 1;
+      if ((rc = lrigw_build_M(c, q, 0, H, evec, c->d_M)) < 0) break;
+      const int g = (p && q == 0) ? 1 : 0;
+      if (c->sur) rc = lrigw_chi0_surrogate(c, c->sur, q, c->d_M, eig, g, c->sur_threshold, chi[b]);
+      else rc = lrigw_chi0(c, q, c->d_M, eig, g, chi[b]);
+      if (rc < 0) break;
+      if (overlap) {
+        if (hipEventRecord(c->ev_chi[b], s) != hipSuccess || hipStreamWaitEvent(s2, c->ev_chi[b], 0) != hipSuccess) {
+          rc = LRIGW_ERR_HIP;
+          break;
+        }
+      }
+      c->stream = s2;
+      rc = lrigw_screen(c, q, chi[b], (const double2 *)V + q * vstride, wc[b], nullptr);
+      c->stream = s;
+      if (rc < 0) break;
+      if (overlap && hipEventRecord(c->ev_wc[b], s2) != hipSuccess) {
+        rc = LRIGW_ERR_HIP;
+        break;
+      }
     }
-    LRIGW_TRY(lrigw_build_M(c, q, 1, H, evec, c->d_x));
-    LRIGW_TRY(lrigw_sigma_c(c, q, c->d_x, c->d_wc, eig, sigma));
+    if (q > q_first) {
+      const int pq = q - 1, b = pq & 1;
+      if ((rc = lrigw_build_M(c, pq, 1, H, evec, c->d_x)) < 0) break;
+      if (overlap && hipStreamWaitEvent(s, c->ev_wc[b], 0) != hipSuccess) {
+        rc = LRIGW_ERR_HIP;
+        break;
+      }
+      if ((rc = lrigw_sigma_c(c, pq, c->d_x, wc[b], eig, sigma)) < 0) break;
+    }
+  }
+  c->stream = s;
+  c->capturing = was_capturing;
+  if (rc < 0) return rc;
+  if (!was_capturing) {
+    int h = INT_MAX;
+    LRIGW_HIP_TRY(hipMemcpyAsync(&h, c->d_info + 16, sizeof(int), hipMemcpyDeviceToHost, s));
+    LRIGW_HIP_TRY(hipStreamSynchronize(s));
+    if (h != INT_MAX) {
+      if (info) *info = h;
+      return LRIGW_ERR_NOT_HPD;
+    }
   }
   if (!all_q) return LRIGW_OK;
   const int nkq = d.n_k * d.n_qp;
@@ -104,7 +166,7 @@ int run_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, c
                      c->d_epsqp);
   LRIGW_TRY(lrigw_launch_check("qp_bands"));
   int qinfo = 0;
-  int rc = lrigw_qp(c, sigma, c->d_epsqp, e_static, n_par, e_qp, z, &qinfo);
+  rc = lrigw_qp(c, sigma, c->d_epsqp, e_static, n_par, e_qp, z, &qinfo);
   if (info) *info = qinfo;
   return rc;
 }
@@ -184,6 +246,7 @@ int lrigw_destroy(lrigw_ctx *c) {
   if (!c) return LRIGW_ERR_ARG;
   if (c->stream) hipStreamSynchronize(c->stream);
   else hipDeviceSynchronize();
+  if (c->stream2) hipStreamSynchronize(c->stream2);
   free_all(c);
   delete c;
   return LRIGW_OK;

@@ -188,6 +188,25 @@ int lrigw_batch_create(lrigw_batch **out, int n_cells, const lrigw_batch_cell *c
   return LRIGW_OK;
 }
 
+int lrigw_tune(lrigw_ctx *c, const void *H, const void *evec, const double *eig, int *nw, int *splits, double *ms) {
+  (void)hipGetLastError();
+  if (!c || !H || !evec || !eig) return LRIGW_ERR_ARG;
+  LRIGW_TRY(driver_buffers(c));
+  LRIGW_TRY(chi0_check_gap(c, eig));
+  lrigw_batch_cell cell = {};
+  cell.ctx = c;
+  cell.H = H;
+  cell.evec = evec;
+  cell.eig = eig;
+  int a = 0, b = 0;
+  double t = 0.0;
+  LRIGW_TRY(autotune_chi0(c, cell, &a, &b, &t));
+  if (nw) *nw = a;
+  if (splits) *splits = b;
+  if (ms) *ms = t;
+  return LRIGW_OK;
+}
+
 int lrigw_batch_run(lrigw_batch *b) {
   (void)hipGetLastError();
   if (!b || !b->exec) return LRIGW_ERR_ARG;

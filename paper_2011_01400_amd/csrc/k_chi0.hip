@@ -491,10 +491,14 @@ int run_chi0_sel(lrigw_ctx *c, int iq, const void *M, const double *eig, int app
 #define BF16_ARGS Apd, Btd, Df, c->d_omega, wsel, run, K, Kp, Npad, n_sel, Ks, ntile, Pf
       if (c->precision == LRIGW_SPLIT_BF16) {
         hipLaunchKernelGGL(k_chi0_presplit<2>, pg, dim3(256), 0, c->stream, Bf, K, d.n_aux, Kp, Npad, Apd, Btd);
+        stage_end(c, "chi0_split", ev);
+        stage_begin(c, "chi0_mfma", &ev);
         if (NW == 4) hipLaunchKernelGGL((k_chi0_bf16<2, 4>), grid, dim3(256), 0, c->stream, BF16_ARGS);
         else hipLaunchKernelGGL((k_chi0_bf16<2, 2>), grid, dim3(256), 0, c->stream, BF16_ARGS);
       } else {
         hipLaunchKernelGGL(k_chi0_presplit<3>, pg, dim3(256), 0, c->stream, Bf, K, d.n_aux, Kp, Npad, Apd, Btd);
+        stage_end(c, "chi0_split", ev);
+        stage_begin(c, "chi0_mfma", &ev);
         if (NW == 4) hipLaunchKernelGGL((k_chi0_bf16<3, 4>), grid, dim3(256), 0, c->stream, BF16_ARGS);
         else hipLaunchKernelGGL((k_chi0_bf16<3, 2>), grid, dim3(256), 0, c->stream, BF16_ARGS);
       }

@@ -175,7 +175,6 @@ __global__ __launch_bounds__(256) void k_sigma_mfma(const typename c2t<T>::type 
 // Two frequencies share every x tile.
 #define SKB 32
 #define SBP 8
-#define SNW 2
 
 typedef unsigned short us16;
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -258,7 +257,7 @@ __global__ void k_split_w(const float2 *__restrict__ W, int N, int Npad, int Rpa
 __device__ inline bf16x8 as_bf(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 __device__ inline u32x4 neg_bf(u32x4 v) { return v ^ 0x80008000u; }
 
-template <int NS>
+template <int NS, int SNW>
 __global__ __launch_bounds__(256) void k_sigma_bf16(const us16 *__restrict__ xs, const us16 *__restrict__ ws,
                                                     const float2 *__restrict__ x, const float2 *__restrict__ Wall,
                                                     long long Ccols, long long Cpad, int N, int Npad, int Rpad, int n_freq,
@@ -451,21 +450,24 @@ int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const doubl
     const int Rpad = (d.n_aux + TILE - 1) / TILE * TILE;
     us16 *xs = (us16 *)c->d_xs, *ws = (us16 *)c->d_ws;
     const long long nx = Cpad * (Npad / 8), nwt = (long long)d.n_freq * Rpad * (Npad / 8);
-    dim3 g2(xcd_grid((d.n_freq + SNW - 1) / SNW, ncb));
     if (c->precision == LRIGW_SPLIT_BF16) {
       hipLaunchKernelGGL(k_split_x<2>, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, c->stream, (const float2 *)x, Ccols,
                          d.n_aux, Cpad, Npad, xs);
       hipLaunchKernelGGL(k_split_w<2>, dim3((unsigned)((nwt + 255) / 256)), dim3(256), 0, c->stream, (const float2 *)Wc,
                          d.n_aux, Npad, Rpad, d.n_freq, ws);
-      hipLaunchKernelGGL(k_sigma_bf16<2>, g2, dim3(256), 0, c->stream, xs, ws, (const float2 *)x, (const float2 *)Wc, Ccols,
-                         Cpad, d.n_aux, Npad, Rpad, d.n_freq, (double *)c->d_X);
+      stage_end(c, "sigma_split", ev);
+      stage_begin(c, "sigma_mfma", &ev);
+      hipLaunchKernelGGL((k_sigma_bf16<2, 2>), dim3(xcd_grid((d.n_freq + 1) / 2, ncb)), dim3(256), 0, c->stream, xs, ws,
+                         (const float2 *)x, (const float2 *)Wc, Ccols, Cpad, d.n_aux, Npad, Rpad, d.n_freq, (double *)c->d_X);
     } else {
       hipLaunchKernelGGL(k_split_x<3>, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, c->stream, (const float2 *)x, Ccols,
                          d.n_aux, Cpad, Npad, xs);
       hipLaunchKernelGGL(k_split_w<3>, dim3((unsigned)((nwt + 255) / 256)), dim3(256), 0, c->stream, (const float2 *)Wc,
                          d.n_aux, Npad, Rpad, d.n_freq, ws);
-      hipLaunchKernelGGL(k_sigma_bf16<3>, g2, dim3(256), 0, c->stream, xs, ws, (const float2 *)x, (const float2 *)Wc, Ccols,
-                         Cpad, d.n_aux, Npad, Rpad, d.n_freq, (double *)c->d_X);
+      stage_end(c, "sigma_split", ev);
+      stage_begin(c, "sigma_mfma", &ev);
+      hipLaunchKernelGGL((k_sigma_bf16<3, 1>), dim3(xcd_grid(d.n_freq, ncb)), dim3(256), 0, c->stream, xs, ws,
+                         (const float2 *)x, (const float2 *)Wc, Ccols, Cpad, d.n_aux, Npad, Rpad, d.n_freq, (double *)c->d_X);
     }
   }
   stage_end(c, "sigma_mfma", ev);

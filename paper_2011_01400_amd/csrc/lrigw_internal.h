@@ -103,8 +103,12 @@ struct lrigw_ctx {
   double omega_cell = 0.0;
   bool gamma_ready = false;
 
-  // driver-owned buffers
+  // driver-owned buffers (chi and W^c double buffered: the screening of q runs
+  // on stream2 while the response of q+1 is built on stream)
   void *d_M = nullptr, *d_x = nullptr, *d_chi = nullptr, *d_wc = nullptr;
+  void *d_chi2 = nullptr, *d_wc2 = nullptr;
+  hipStream_t stream2 = nullptr;
+  hipEvent_t ev_chi[2] = {nullptr, nullptr}, ev_wc[2] = {nullptr, nullptr};
 
   const double *checked_eig = nullptr;   // eigenvalue array already checked for a gap
 

@@ -36,7 +36,7 @@ EXPORTS = ["lrigw_create", "lrigw_destroy", "lrigw_strerror", "lrigw_get_sizes",
            "lrigw_surrogate_forward", "lrigw_surrogate_grad", "lrigw_surrogate_train", "lrigw_chi0_surrogate",
            "lrigw_set_surrogate", "lrigw_surrogate_stats", "lrigw_surrogate_reset_stats",
            "lrigw_batch_create", "lrigw_batch_run", "lrigw_batch_status", "lrigw_batch_tuning",
-           "lrigw_batch_graph_nodes", "lrigw_batch_destroy"]
+           "lrigw_batch_graph_nodes", "lrigw_batch_destroy", "lrigw_tune"]
 
 
 class LrigwSystem(ctypes.Structure):
@@ -122,6 +122,7 @@ def load(path: Optional[str] = None):
         "lrigw_batch_tuning": (i, [vp, i, ip, ip, dp]),
         "lrigw_batch_graph_nodes": (i, [vp, llp]),
         "lrigw_batch_destroy": (i, [vp]),
+        "lrigw_tune": (i, [vp, vp, vp, vp, ip, ip, dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -265,6 +266,12 @@ class Context:
                                  ctypes.byref(info))
         self._check(rc, "lrigw_g0w0", allow_warn=True)
         return rc, info.value
+
+    def tune(self, H, evec, eig):
+        nw, sp, ms = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0)
+        self._check(self.lib.lrigw_tune(self.h, _ptr(H), _ptr(evec), _ptr(eig), ctypes.byref(nw), ctypes.byref(sp),
+                                        ctypes.byref(ms)), "lrigw_tune")
+        return nw.value, sp.value, ms.value
 
     def chi0_surrogate(self, sg, iq, M, eig, chi_out, threshold, apply_gamma=False):
         self._check(self.lib.lrigw_chi0_surrogate(self.h, sg.h, int(iq), _ptr(M), _ptr(eig), int(bool(apply_gamma)),

@@ -1,0 +1,126 @@
+"""Short workload for hardware-counter runs (run under rocprofv3).
+
+Runs (1) a plain device-to-device copy of a known size, the calibration for
+the FETCH_SIZE / WRITE_SIZE counters, then (2) one q of the path on the
+Si-like cell in the chosen precision form (the per-launch traffic of every
+kernel is the same for every q except q = 0).  `summarize` turns the counter
+CSVs of two such runs into bytes per launch.
+
+  rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -- python3 -m paper_2011_01400_amd.profile_run
+  python3 -m paper_2011_01400_amd.profile_run --summarize <fetch dir> <write dir>
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+COPY_BYTES = 1 << 30          # calibration copy: 1 GiB read + 1 GiB written
+SOURCES = {"k_sigma_bf16": "k_sigma.hip", "k_sigma_mfma": "k_sigma.hip", "k_chi0_bf16": "k_chi0.hip",
+           "k_chi0_mfma": "k_chi0.hip"}
+
+
+def run(precision: str, config: int, q: int):
+    import torch
+    sys.path.insert(0, ROOT)
+    from paper_2011_01400_amd import lrigw as L
+    from synth.systems import make_config
+    L.load()
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    torch.cuda.synchronize()
+    b.copy_(a)                     # the calibration dispatch
+    torch.cuda.synchronize()
+    del a, b
+    s = make_config(config)
+    dev = L.device_inputs(s)
+    sp = s.spec
+    ctx = L.Context.from_system(s, precision=precision)
+    H = ctx.empty("H")
+    ctx.lri_ft(dev["lri"], s.R, dev["evec"], H)
+    sigma = torch.zeros((s.n_k, sp.n_qp, sp.n_freq), dtype=torch.complex128, device="cuda")
+    e = torch.zeros((s.n_k, sp.n_qp), dtype=torch.float64, device="cuda")
+    z = torch.zeros_like(e)
+    ctx.g0w0(H, dev["evec"], dev["eig"], dev["V"], dev["p"], s.omega_cell, dev["e_static"], 16, sigma, e, z,
+             q_first=q, q_last=q + 1)
+    torch.cuda.synchronize()
+    print(f"profile_run: {precision} config {config} q {q} done", flush=True)
+
+
+def _rows(d):
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    out = []
+    with open(files[0]) as f:
+        for r in csv.DictReader(f):
+            out.append(r)
+    return out
+
+
+def _per_kernel(rows):
+    """{kernel name: [value per dispatch]} (counter value in KiB, summed over the dispatch)."""
+    acc = {}
+    for r in rows:
+        name = r.get("Kernel_Name") or r.get("Kernel-Name") or r.get("KernelName") or ""
+        val = float(r.get("Counter_Value") or r.get("Counter-Value") or 0.0)
+        disp = r.get("Dispatch_Id") or r.get("Dispatch-Id") or r.get("Correlation_Id") or len(acc)
+        acc.setdefault(name, {}).setdefault(disp, 0.0)
+        acc[name][disp] += val
+    return {k: list(v.values()) for k, v in acc.items()}
+
+
+def summarize(fetch_dir, write_dir, precision, config, out_path):
+    res = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        per = _per_kernel(_rows(d))
+        copy = [v for k, v in per.items() if "copy" in k.lower() or "elementwise" in k.lower()]
+        copy = max((x for lst in copy for x in lst), default=None)
+        scale = COPY_BYTES / (copy * 1024.0) if copy else None
+        res[counter] = {"copy_kib": copy, "scale": scale, "kernels": {}}
+        for k, vals in per.items():
+            for short in SOURCES:
+                if short in k:
+                    res[counter]["kernels"][short] = sum(vals) / len(vals)
+    out = {}
+    try:
+        with open(out_path) as f:
+            out = json.load(f)
+    except (OSError, ValueError):
+        pass
+    for short, src in SOURCES.items():
+        f = res["FETCH_SIZE"]["kernels"].get(short)
+        w = res["WRITE_SIZE"]["kernels"].get(short)
+        if f is None or w is None:
+            continue
+        sf, sw = res["FETCH_SIZE"]["scale"], res["WRITE_SIZE"]["scale"]
+        with open(os.path.join(ROOT, "paper_2011_01400_amd", "csrc", src), "rb") as fh:
+            h = hashlib.sha256(fh.read()).hexdigest()[:16]
+        key = ("sigma_mfma" if "sigma" in short else "chi0_mfma") + f":{precision}:c{config}"
+        out[key] = {"kernel": short, "source": src, "source_sha256_16": h,
+                    "fetch_kib_per_launch": f, "write_kib_per_launch": w,
+                    "copy_calibration": {"fetch_scale": sf, "write_scale": sw, "copy_bytes": COPY_BYTES},
+                    "bytes_per_launch": (f * 1024.0 * (sf or 1.0)) + (w * 1024.0 * (sw or 1.0))}
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--precision", default="split3_bf16")
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--q", type=int, default=1)
+    ap.add_argument("--summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    a = ap.parse_args()
+    if a.summarize:
+        summarize(a.summarize[0], a.summarize[1], a.precision, a.config, a.out)
+    else:
+        run(a.precision, a.config, a.q)
