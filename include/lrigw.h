@@ -302,11 +302,15 @@ int lrigw_batch_graph_nodes(const lrigw_batch *b, long long *n_nodes);
 int lrigw_batch_destroy(lrigw_batch *b);
 
 /* Tile autotuner for one context (the same one lrigw_batch_create runs per
- * cell): times the response kernel on one q over its tile choices and keeps
- * the fastest for the context's later calls.  H, evec, eig as lrigw_g0w0.
- * Outputs (host, may be NULL): frequencies per workgroup, K splits, time (ms).
+ * cell): times the response kernel on one q over its tile choices
+ * (frequencies per workgroup, K splits) and, in the split-BF16 forms, the
+ * self-energy kernel over its variants (frequencies per workgroup, W
+ * prefetch), and keeps the fastest for the context's later calls.  H, evec,
+ * eig as lrigw_g0w0.  Outputs (host, may be NULL): the chosen response tiles,
+ * the self-energy variant (0..2) and the response time of one q (ms).
  * Synchronous. */
-int lrigw_tune(lrigw_ctx *ctx, const void *H, const void *evec, const double *eig, int *nw, int *splits, double *ms);
+int lrigw_tune(lrigw_ctx *ctx, const void *H, const void *evec, const double *eig, int *nw, int *splits,
+               int *sigma_variant, double *ms);
 
 /* Per-kernel device time (ms, HIP events on the context stream) accumulated
  * since the last reset, for the named stages "build_M", "chi0", "screen",

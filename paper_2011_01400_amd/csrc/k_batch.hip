@@ -28,7 +28,8 @@ struct lrigw_batch {
 };
 
 // Time the response kernel of one q for every (frequencies per workgroup,
-// split) candidate; keep the fastest.  Runs before capture.
+// split) candidate and, in the split-BF16 forms, the self-energy kernel for
+// every variant; keep the fastest.  Runs before capture.
 static int autotune_chi0(lrigw_ctx *c, const lrigw_batch_cell &cell, int *nw_out, int *S_out, double *ms_out) {
   const Dims &d = c->d;
   hipStream_t s = c->stream;
@@ -73,14 +74,44 @@ static int autotune_chi0(lrigw_ctx *c, const lrigw_batch_cell &cell, int *nw_out
       }
     }
   }
-  c->timing = timing;
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
   c->chi_nw = bnw;
   c->chi_splits = bS;
   *nw_out = bnw;
   *S_out = bS;
   *ms_out = best;
+  // split-BF16 Sigma^c kernel variant (timing does not depend on the values)
+  if (c->precision == LRIGW_SPLIT_BF16 || c->precision == LRIGW_SPLIT3_BF16) {
+    LRIGW_TRY(run_build_M(c, q, 1, cell.H, cell.evec, c->d_x));
+    LRIGW_TRY(zero_fill(s, c->d_wc, (size_t)d.n_freq * d.n_aux * d.n_aux * lrigw_csize(c)));
+    double2 *sg = nullptr;
+    LRIGW_HIP_TRY(hipMalloc(&sg, (size_t)d.n_k * d.n_qp * d.n_freq * sizeof(double2)));
+    double sbest = INFINITY;
+    int bvar = c->sig_var;
+    for (int var = 0; var < 3; ++var) {
+      c->sig_var = var;
+      int rc = run_sigma_c(c, q, c->d_x, c->d_wc, cell.eig, sg);
+      if (rc == LRIGW_OK) rc = hipEventRecord(e0, s) == hipSuccess ? LRIGW_OK : LRIGW_ERR_HIP;
+      if (rc == LRIGW_OK) rc = run_sigma_c(c, q, c->d_x, c->d_wc, cell.eig, sg);
+      if (rc == LRIGW_OK) rc = hipEventRecord(e1, s) == hipSuccess ? LRIGW_OK : LRIGW_ERR_HIP;
+      if (rc == LRIGW_OK) rc = hipEventSynchronize(e1) == hipSuccess ? LRIGW_OK : LRIGW_ERR_HIP;
+      float t = 0.f;
+      if (rc == LRIGW_OK) rc = hipEventElapsedTime(&t, e0, e1) == hipSuccess ? LRIGW_OK : LRIGW_ERR_HIP;
+      if (rc != LRIGW_OK) {
+        (void)hipFree(sg);
+        c->sig_var = bvar;
+        return rc;
+      }
+      if (t < sbest) {
+        sbest = t;
+        bvar = var;
+      }
+    }
+    (void)hipFree(sg);
+    c->sig_var = bvar;
+  }
+  c->timing = timing;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
   return LRIGW_OK;
 }
 
@@ -188,7 +219,8 @@ int lrigw_batch_create(lrigw_batch **out, int n_cells, const lrigw_batch_cell *c
   return LRIGW_OK;
 }
 
-int lrigw_tune(lrigw_ctx *c, const void *H, const void *evec, const double *eig, int *nw, int *splits, double *ms) {
+int lrigw_tune(lrigw_ctx *c, const void *H, const void *evec, const double *eig, int *nw, int *splits, int *sigma_variant,
+               double *ms) {
   (void)hipGetLastError();
   if (!c || !H || !evec || !eig) return LRIGW_ERR_ARG;
   LRIGW_TRY(driver_buffers(c));
@@ -203,6 +235,7 @@ int lrigw_tune(lrigw_ctx *c, const void *H, const void *evec, const double *eig,
   LRIGW_TRY(autotune_chi0(c, cell, &a, &b, &t));
   if (nw) *nw = a;
   if (splits) *splits = b;
+  if (sigma_variant) *sigma_variant = c->sig_var;
   if (ms) *ms = t;
   return LRIGW_OK;
 }

@@ -134,47 +134,68 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double2 *A, long long lda, l
     L[r][cc] = M[(long long)(j0 + r) * lda + j0 + cc];
   }
   __syncthreads();
+  // right-looking LDL^H on the unscaled columns (one barrier per column):
+  // d_cc = L[cc][cc];  L[r][s] -= L[r][cc] conj(L[s][cc]) / d_cc  (cc < s <= r)
+  __shared__ double piv[NB];
   for (int cc = 0; cc < jb; ++cc) {
-    if (tid == 0) {
-      double p = L[cc][cc].x;
-      if (!(p > 0.0) || !isfinite(p)) {
-        bad = 1;
-        p = 1.0;
-      }
-      L[cc][cc] = mkc(sqrt(p), 0.0);
+    double p = L[cc][cc].x;
+    if (!(p > 0.0) || !isfinite(p)) {
+      if (tid == 0) bad = 1;
+      p = 1.0;
     }
-    __syncthreads();
-    const double dinv = 1.0 / L[cc][cc].x;
-    for (int r = cc + 1 + tid; r < jb; r += blockDim.x) {
-      L[r][cc].x *= dinv;
-      L[r][cc].y *= dinv;
-    }
-    __syncthreads();
+    if (tid == 0) piv[cc] = p;
+    const double pinv = 1.0 / p;
     const int rem = jb - cc - 1;
     for (int e = tid; e < rem * rem; e += blockDim.x) {
       const int r = cc + 1 + e / rem, s2 = cc + 1 + e % rem;
       if (s2 <= r) {
         const double2 a = L[r][cc], b = L[s2][cc];
-        L[r][s2].x -= a.x * b.x + a.y * b.y;
-        L[r][s2].y -= a.y * b.x - a.x * b.y;
+        L[r][s2].x -= (a.x * b.x + a.y * b.y) * pinv;
+        L[r][s2].y -= (a.y * b.x - a.x * b.y) * pinv;
       }
     }
     __syncthreads();
   }
-  // inverse of the lower-triangular block, one column per thread:
-  // X[i][j] = (delta_ij - sum_{t=j}^{i-1} L[i][t] X[t][j]) / L[i][i]
-  if (tid < jb) {
-    const int j = tid;
-    for (int i = 0; i < j; ++i) X[i][j] = mkc(0.0, 0.0);
-    for (int i = j; i < jb; ++i) {
-      double2 v = mkc(i == j ? 1.0 : 0.0, 0.0);
-      for (int t = j; t < i; ++t) {
-        const double2 l = L[i][t], x = X[t][j];
-        v.x -= l.x * x.x - l.y * x.y;
-        v.y -= l.x * x.y + l.y * x.x;
+  // Cholesky factor: column cc scaled by 1/sqrt(d_cc), diagonal sqrt(d_cc)
+  for (int e = tid; e < jb * jb; e += blockDim.x) {
+    const int r = e / jb, cc = e % jb;
+    if (cc < r) {
+      const double sinv = 1.0 / sqrt(piv[cc]);
+      L[r][cc].x *= sinv;
+      L[r][cc].y *= sinv;
+    } else if (cc == r) {
+      L[r][r] = mkc(sqrt(piv[r]), 0.0);
+    }
+  }
+  __syncthreads();
+  // inverse of the lower-triangular block by forward substitution, column j
+  // by four adjacent lanes: X[i][j] = (delta_ij - sum_{t=j}^{i-1} L[i][t] X[t][j]) / L[i][i];
+  // lane part sums the t with t = part (mod 4) and writes the rows i = part
+  // (mod 4), so every X entry a lane reads is one it wrote itself.
+  {
+    const int j = tid >> 2, part = tid & 3;
+    const bool act = j < jb;
+    for (int i = 0; i < jb; ++i) {
+      double sr = 0.0, si = 0.0;
+      if (act && i > j) {
+        for (int t = j + ((part - j) & 3); t < i; t += 4) {
+          const double2 l = L[i][t], x = X[t][j];
+          sr += l.x * x.x - l.y * x.y;
+          si += l.x * x.y + l.y * x.x;
+        }
       }
-      const double dinv = 1.0 / L[i][i].x;
-      X[i][j] = mkc(v.x * dinv, v.y * dinv);
+      sr += __shfl_xor(sr, 1);
+      si += __shfl_xor(si, 1);
+      sr += __shfl_xor(sr, 2);
+      si += __shfl_xor(si, 2);
+      if (act && (i & 3) == part) {
+        if (i < j) {
+          X[i][j] = mkc(0.0, 0.0);
+        } else {
+          const double dinv = 1.0 / L[i][i].x;
+          X[i][j] = mkc(((i == j ? 1.0 : 0.0) - sr) * dinv, -si * dinv);
+        }
+      }
     }
   }
   __syncthreads();

@@ -122,6 +122,7 @@ int run_grids(lrigw_ctx *c) {
   const size_t nn = (size_t)d.n_aux * d.n_aux;
   LRIGW_HIP_TRY(hipMalloc(&c->d_delta, (size_t)K * rs));
   c->chi_nw = chi0_default_nw(c->precision);
+  c->sig_var = sigma_default_variant(c->precision);
   LRIGW_TRY(chi0_plan_splits(c, &c->chi_splits));
   int nt = (d.n_aux + TILE - 1) / TILE;
   size_t ntile = (size_t)nt * (nt + 1) / 2;

@@ -16,17 +16,20 @@
 #define SKC 16          // nu rows staged per step
 
 // Workgroup -> (column block, frequency block).  Consecutive workgroup ids go
-// to different XCDs (id mod 8); all frequency blocks of one column block are
-// given to the same XCD, back to back, so its x tile is fetched from HBM once
-// and then served by that XCD's L2.
+// to different XCDs (id mod 8).  Each XCD owns a fixed set of ceil(nfb/8)
+// frequency blocks and walks all column blocks with them, so the W^c of its
+// frequencies (a few MB) stays in that XCD's L2 while x streams through once
+// per XCD; the frequency blocks of one column block run back to back and share
+// the x tile.
 __device__ inline bool xcd_map(int nfb, long long ncb, long long &cb, int &fb) {
   const long long b = blockIdx.x;
   const long long slot = b >> 3;
-  cb = (slot / nfb) * 8 + (b & 7);
-  fb = (int)(slot % nfb);
-  return cb < ncb;
+  const int fpx = (nfb + 7) >> 3;
+  fb = (int)(b & 7) * fpx + (int)(slot % fpx);
+  cb = slot / fpx;
+  return cb < ncb && fb < nfb;
 }
-static inline unsigned xcd_grid(int nfb, long long ncb) { return (unsigned)(((ncb + 7) / 8) * 8 * nfb); }
+static inline unsigned xcd_grid(int nfb, long long ncb) { return (unsigned)(8LL * ((nfb + 7) / 8) * ncb); }
 #define SLP (TILE + 1)  // padded LDS row (complex elements)
 
 // One workgroup = 64 columns c (x rows) and every row mu of W^c.  Rows are
@@ -257,7 +260,7 @@ __global__ void k_split_w(const float2 *__restrict__ W, int N, int Npad, int Rpa
 __device__ inline bf16x8 as_bf(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 __device__ inline u32x4 neg_bf(u32x4 v) { return v ^ 0x80008000u; }
 
-template <int NS, int SNW>
+template <int NS, int SNW, bool PF>
 __global__ __launch_bounds__(256) void k_sigma_bf16(const us16 *__restrict__ xs, const us16 *__restrict__ ws,
                                                     const float2 *__restrict__ x, const float2 *__restrict__ Wall,
                                                     long long Ccols, long long Cpad, int N, int Npad, int Rpad, int n_freq,
@@ -300,22 +303,39 @@ __global__ __launch_bounds__(256) void k_sigma_bf16(const us16 *__restrict__ xs,
 #pragma unroll
     for (int pr = 0; pr < NS * 2; ++pr) *(u32x4 *)&Bs[0][pr][scol][sk] = bpre[pr];
     __syncthreads();
+    // this wave's 16 rows of W (every frequency of the block), straight into
+    // registers, one chunk ahead
+    u32x4 acur[SNW][NS * 2], anext[SNW][NS * 2];
+    const us16 *wsrc[SNW];
+#pragma unroll
+    for (int v = 0; v < SNW; ++v) wsrc[v] = ws + ((long long)min(w0 + v, n_freq - 1) * NS * 2 * Rpad + wrow) * Npad + 8 * g;
+    if (PF && kcw > 0) {
+#pragma unroll
+      for (int v = 0; v < SNW; ++v)
+#pragma unroll
+        for (int pr = 0; pr < NS * 2; ++pr) acur[v][pr] = *(const u32x4 *)(wsrc[v] + (long long)pr * Rpad * Npad);
+    }
     for (int ch = 0; ch < nch; ++ch) {
       const int b = ch & 1;
       if (ch + 1 < nch) {
 #pragma unroll
         for (int pr = 0; pr < NS * 2; ++pr) bpre[pr] = *(const u32x4 *)(xsrc + (long long)pr * Cpad * Npad + (ch + 1) * SKB);
       }
-      if (ch < kcw) {
-        // this wave's 16 rows of W for both frequencies, straight into registers
-        u32x4 acur[SNW][NS * 2];
+      if (PF && ch + 1 < kcw) {
 #pragma unroll
-        for (int v = 0; v < SNW; ++v) {
-          const int w = min(w0 + v, n_freq - 1);
+        for (int v = 0; v < SNW; ++v)
 #pragma unroll
           for (int pr = 0; pr < NS * 2; ++pr)
-            acur[v][pr] = *(const u32x4 *)(ws + (((long long)w * NS * 2 + pr) * Rpad + wrow) * Npad + ch * SKB + 8 * g);
-        }
+            anext[v][pr] = *(const u32x4 *)(wsrc[v] + (long long)pr * Rpad * Npad + (ch + 1) * SKB);
+      }
+      if (!PF && ch < kcw) {
+#pragma unroll
+        for (int v = 0; v < SNW; ++v)
+#pragma unroll
+          for (int pr = 0; pr < NS * 2; ++pr)
+            acur[v][pr] = *(const u32x4 *)(wsrc[v] + (long long)pr * Rpad * Npad + ch * SKB);
+      }
+      if (ch < kcw) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           bf16x8 br[NS], bi[NS];
@@ -345,6 +365,12 @@ __global__ __launch_bounds__(256) void k_sigma_bf16(const us16 *__restrict__ xs,
       if (ch + 1 < nch) {
 #pragma unroll
         for (int pr = 0; pr < NS * 2; ++pr) *(u32x4 *)&Bs[b ^ 1][pr][scol][sk] = bpre[pr];
+      }
+      if (PF && ch + 1 < kcw) {
+#pragma unroll
+        for (int v = 0; v < SNW; ++v)
+#pragma unroll
+          for (int pr = 0; pr < NS * 2; ++pr) acur[v][pr] = anext[v][pr];
       }
       __syncthreads();
     }
@@ -430,6 +456,11 @@ __global__ void k_sigma_freq(const double *__restrict__ X, const double *__restr
   sigma[o] = s;
 }
 
+// split-BF16 kernel variants the tuner chooses from: (frequencies per
+// workgroup, W prefetched one chunk ahead) = (1, yes), (2, no), (1, no)
+int sigma_variant_snw(int var) { return var == 1 ? 2 : 1; }
+int sigma_default_variant(int precision) { return precision == LRIGW_SPLIT_BF16 ? 1 : 0; }
+
 int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const double *eig, void *sigma_acc) {
   const Dims &d = c->d;
   const long long Ccols = (long long)d.n_k * d.n_qp * d.n_bands;
@@ -450,25 +481,34 @@ int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const doubl
     const int Rpad = (d.n_aux + TILE - 1) / TILE * TILE;
     us16 *xs = (us16 *)c->d_xs, *ws = (us16 *)c->d_ws;
     const long long nx = Cpad * (Npad / 8), nwt = (long long)d.n_freq * Rpad * (Npad / 8);
-    if (c->precision == LRIGW_SPLIT_BF16) {
+    const int NS = c->precision == LRIGW_SPLIT_BF16 ? 2 : 3;
+    if (NS == 2) {
       hipLaunchKernelGGL(k_split_x<2>, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, c->stream, (const float2 *)x, Ccols,
                          d.n_aux, Cpad, Npad, xs);
       hipLaunchKernelGGL(k_split_w<2>, dim3((unsigned)((nwt + 255) / 256)), dim3(256), 0, c->stream, (const float2 *)Wc,
                          d.n_aux, Npad, Rpad, d.n_freq, ws);
-      stage_end(c, "sigma_split", ev);
-      stage_begin(c, "sigma_mfma", &ev);
-      hipLaunchKernelGGL((k_sigma_bf16<2, 2>), dim3(xcd_grid((d.n_freq + 1) / 2, ncb)), dim3(256), 0, c->stream, xs, ws,
-                         (const float2 *)x, (const float2 *)Wc, Ccols, Cpad, d.n_aux, Npad, Rpad, d.n_freq, (double *)c->d_X);
     } else {
       hipLaunchKernelGGL(k_split_x<3>, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, c->stream, (const float2 *)x, Ccols,
                          d.n_aux, Cpad, Npad, xs);
       hipLaunchKernelGGL(k_split_w<3>, dim3((unsigned)((nwt + 255) / 256)), dim3(256), 0, c->stream, (const float2 *)Wc,
                          d.n_aux, Npad, Rpad, d.n_freq, ws);
-      stage_end(c, "sigma_split", ev);
-      stage_begin(c, "sigma_mfma", &ev);
-      hipLaunchKernelGGL((k_sigma_bf16<3, 1>), dim3(xcd_grid(d.n_freq, ncb)), dim3(256), 0, c->stream, xs, ws,
-                         (const float2 *)x, (const float2 *)Wc, Ccols, Cpad, d.n_aux, Npad, Rpad, d.n_freq, (double *)c->d_X);
     }
+    stage_end(c, "sigma_split", ev);
+    stage_begin(c, "sigma_mfma", &ev);
+    const int var = c->sig_var;
+    const int snw = sigma_variant_snw(var);
+#define SIG_ARGS xs, ws, (const float2 *)x, (const float2 *)Wc, Ccols, Cpad, d.n_aux, Npad, Rpad, d.n_freq, (double *)c->d_X
+    dim3 gs(xcd_grid((d.n_freq + snw - 1) / snw, ncb));
+    if (NS == 2) {
+      if (var == 0) hipLaunchKernelGGL((k_sigma_bf16<2, 1, true>), gs, dim3(256), 0, c->stream, SIG_ARGS);
+      else if (var == 1) hipLaunchKernelGGL((k_sigma_bf16<2, 2, false>), gs, dim3(256), 0, c->stream, SIG_ARGS);
+      else hipLaunchKernelGGL((k_sigma_bf16<2, 1, false>), gs, dim3(256), 0, c->stream, SIG_ARGS);
+    } else {
+      if (var == 0) hipLaunchKernelGGL((k_sigma_bf16<3, 1, true>), gs, dim3(256), 0, c->stream, SIG_ARGS);
+      else if (var == 1) hipLaunchKernelGGL((k_sigma_bf16<3, 2, false>), gs, dim3(256), 0, c->stream, SIG_ARGS);
+      else hipLaunchKernelGGL((k_sigma_bf16<3, 1, false>), gs, dim3(256), 0, c->stream, SIG_ARGS);
+    }
+#undef SIG_ARGS
   }
   stage_end(c, "sigma_mfma", ev);
   LRIGW_TRY(lrigw_launch_check("sigma_mfma"));

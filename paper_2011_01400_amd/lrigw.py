@@ -122,7 +122,7 @@ def load(path: Optional[str] = None):
         "lrigw_batch_tuning": (i, [vp, i, ip, ip, dp]),
         "lrigw_batch_graph_nodes": (i, [vp, llp]),
         "lrigw_batch_destroy": (i, [vp]),
-        "lrigw_tune": (i, [vp, vp, vp, vp, ip, ip, dp]),
+        "lrigw_tune": (i, [vp, vp, vp, vp, ip, ip, ip, dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -268,10 +268,10 @@ class Context:
         return rc, info.value
 
     def tune(self, H, evec, eig):
-        nw, sp, ms = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0)
+        nw, sp, sv, ms = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0)
         self._check(self.lib.lrigw_tune(self.h, _ptr(H), _ptr(evec), _ptr(eig), ctypes.byref(nw), ctypes.byref(sp),
-                                        ctypes.byref(ms)), "lrigw_tune")
-        return nw.value, sp.value, ms.value
+                                        ctypes.byref(sv), ctypes.byref(ms)), "lrigw_tune")
+        return nw.value, sp.value, sv.value, ms.value
 
     def chi0_surrogate(self, sg, iq, M, eig, chi_out, threshold, apply_gamma=False):
         self._check(self.lib.lrigw_chi0_surrogate(self.h, sg.h, int(iq), _ptr(M), _ptr(eig), int(bool(apply_gamma)),
