@@ -23,8 +23,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # MI355X dense matrix peaks (the split forms run BF16 MFMA)
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0, "split3_bf16": 2500.0}
-DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16", "split3_bf16": "bf16"}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0, "split3_bf16": 2500.0, "split_mixed": 2500.0}
+DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16", "split3_bf16": "bf16", "split_mixed": "bf16"}
 STAGES = ("lri_ft", "build_M", "chi0", "chi0_split", "chi0_mfma", "screen", "sigma_c", "sigma_split", "sigma_mfma", "qp")
 HA_MEV = 27211.386
 

@@ -50,7 +50,8 @@ enum lrigw_precision {
   LRIGW_FP64 = 0,        /* every contraction in FP64 (the plain path) */
   LRIGW_FP32 = 1,        /* M, chi0 and Sigma^c contractions in FP32 on MFMA, FP32 accumulate */
   LRIGW_SPLIT_BF16 = 2,  /* chi0 and Sigma^c as hi/lo BF16 products on MFMA (hi*hi + hi*lo + lo*hi), FP32 accumulate */
-  LRIGW_SPLIT3_BF16 = 3  /* chi0 and Sigma^c with a three-part BF16 split (six products, FP32-like accuracy) */
+  LRIGW_SPLIT3_BF16 = 3, /* chi0 and Sigma^c with a three-part BF16 split (six products, FP32-like accuracy) */
+  LRIGW_SPLIT_MIXED = 4  /* chi0 with the three-part split, Sigma^c with the two-part split */
 };
 
 typedef struct {

@@ -191,7 +191,7 @@ int lrigw_create(lrigw_ctx **out, const lrigw_system *sys, int precision, void *
   (void)hipGetLastError();  // drop a stale error another library left behind
   if (!out || !sys || !sys->basis_off || !sys->aux_off) return LRIGW_ERR_ARG;
   *out = nullptr;
-  if (precision < LRIGW_FP64 || precision > LRIGW_SPLIT3_BF16) return LRIGW_ERR_ARG;
+  if (precision < LRIGW_FP64 || precision > LRIGW_SPLIT_MIXED) return LRIGW_ERR_ARG;
   if (sys->n_atoms < 1 || sys->nk[0] < 1 || sys->nk[1] < 1 || sys->nk[2] < 1) return LRIGW_ERR_ARG;
   if (sys->basis_off[0] != 0 || sys->aux_off[0] != 0) return LRIGW_ERR_ARG;
   int nb_max = 0;

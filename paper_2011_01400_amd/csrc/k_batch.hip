@@ -80,7 +80,7 @@ static int autotune_chi0(lrigw_ctx *c, const lrigw_batch_cell &cell, int *nw_out
   *S_out = bS;
   *ms_out = best;
   // split-BF16 Sigma^c kernel variant (timing does not depend on the values)
-  if (c->precision == LRIGW_SPLIT_BF16 || c->precision == LRIGW_SPLIT3_BF16) {
+  if (ns_sig(c->precision) > 0) {
     LRIGW_TRY(run_build_M(c, q, 1, cell.H, cell.evec, c->d_x));
     LRIGW_TRY(zero_fill(s, c->d_wc, (size_t)d.n_freq * d.n_aux * d.n_aux * lrigw_csize(c)));
     double2 *sg = nullptr;

@@ -405,7 +405,7 @@ int chi0_plan_splits(const lrigw_ctx *c, int *splits) {
   long long S = (2048 + units - 1) / units;
   long long maxS = std::max<long long>(1, K / 512);
   S = std::min(S, maxS);
-  if (c->precision == LRIGW_SPLIT_BF16 || c->precision == LRIGW_SPLIT3_BF16) S = std::max(S, (K + 2047) / 2048);
+  if (ns_chi(c->precision) > 0) S = std::max(S, (K + 2047) / 2048);
   const size_t cs = lrigw_csize(c);
   const size_t per = (size_t)d.n_freq * ntile * TILE * TILE * cs;
   while (S > 1 && (size_t)S * per > (size_t)3 << 30) --S;
@@ -489,7 +489,7 @@ int run_chi0_sel(lrigw_ctx *c, int iq, const void *M, const double *eig, int app
       float2 *Btd = (float2 *)c->d_bt;
       dim3 pg((unsigned)(Kp / 32), (unsigned)(Npad / 32));
 #define BF16_ARGS Apd, Btd, Df, c->d_omega, wsel, run, K, Kp, Npad, n_sel, Ks, ntile, Pf
-      if (c->precision == LRIGW_SPLIT_BF16) {
+      if (ns_chi(c->precision) == 2) {
         hipLaunchKernelGGL(k_chi0_presplit<2>, pg, dim3(256), 0, c->stream, Bf, K, d.n_aux, Kp, Npad, Apd, Btd);
         stage_end(c, "chi0_split", ev);
         stage_begin(c, "chi0_mfma", &ev);

@@ -145,11 +145,11 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double2 *A, long long lda, l
     }
     if (tid == 0) piv[cc] = p;
     const double pinv = 1.0 / p;
-    const int rem = jb - cc - 1;
-    for (int e = tid; e < rem * rem; e += blockDim.x) {
-      const int r = cc + 1 + e / rem, s2 = cc + 1 + e % rem;
-      if (s2 <= r) {
-        const double2 a = L[r][cc], b = L[s2][cc];
+    // 16 x 16 thread grid over the trailing lower triangle
+    for (int r = cc + 1 + (tid >> 4); r < jb; r += 16) {
+      const double2 a = L[r][cc];
+      for (int s2 = cc + 1 + (tid & 15); s2 <= r; s2 += 16) {
+        const double2 b = L[s2][cc];
         L[r][s2].x -= (a.x * b.x + a.y * b.y) * pinv;
         L[r][s2].y -= (a.y * b.x - a.x * b.y) * pinv;
       }

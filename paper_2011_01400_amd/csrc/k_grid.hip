@@ -137,16 +137,16 @@ int run_grids(lrigw_ctx *c) {
   LRIGW_HIP_TRY(hipMalloc(&c->d_dinv, (size_t)d.n_freq * zdinv_stride(d.n_aux) * sizeof(double2)));
   LRIGW_HIP_TRY(hipMalloc(&c->d_info, 64 * sizeof(int)));
   LRIGW_HIP_TRY(hipMalloc(&c->d_x1, d.n_aux * sizeof(double2)));
-  if (c->precision == LRIGW_SPLIT_BF16 || c->precision == LRIGW_SPLIT3_BF16) {
-    const int NS = c->precision == LRIGW_SPLIT_BF16 ? 2 : 3;
+  if (ns_chi(c->precision) > 0) {
+    const int NSS = ns_sig(c->precision), NSC = ns_chi(c->precision);
     const long long Ccols = (long long)d.n_k * d.n_qp * d.n_bands;
     const long long Cpad = (Ccols + TILE - 1) / TILE * TILE;
     const long long Npad = (d.n_aux + 31) / 32 * 32;
     const long long Rpad = (d.n_aux + TILE - 1) / TILE * TILE;
-    LRIGW_HIP_TRY(hipMalloc(&c->d_xs, (size_t)NS * 2 * Cpad * Npad * 2));
-    LRIGW_HIP_TRY(hipMalloc(&c->d_ws, (size_t)d.n_freq * NS * 2 * Rpad * Npad * 2));
+    LRIGW_HIP_TRY(hipMalloc(&c->d_xs, (size_t)NSS * 2 * Cpad * Npad * 2));
+    LRIGW_HIP_TRY(hipMalloc(&c->d_ws, (size_t)d.n_freq * NSS * 2 * Rpad * Npad * 2));
     const long long Kp = (K + 31) / 32 * 32;
-    LRIGW_HIP_TRY(hipMalloc(&c->d_ap, (size_t)NS * 2 * Rpad * Kp * 2));
+    LRIGW_HIP_TRY(hipMalloc(&c->d_ap, (size_t)NSC * 2 * Rpad * Kp * 2));
     LRIGW_HIP_TRY(hipMalloc(&c->d_bt, (size_t)Rpad * Kp * sizeof(float2)));
   }
   return LRIGW_OK;

@@ -459,7 +459,7 @@ __global__ void k_sigma_freq(const double *__restrict__ X, const double *__restr
 // split-BF16 kernel variants the tuner chooses from: (frequencies per
 // workgroup, W prefetched one chunk ahead) = (1, yes), (2, no), (1, no)
 int sigma_variant_snw(int var) { return var == 1 ? 2 : 1; }
-int sigma_default_variant(int precision) { return precision == LRIGW_SPLIT_BF16 ? 1 : 0; }
+int sigma_default_variant(int precision) { return ns_sig(precision) == 2 ? 1 : 0; }
 
 int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const double *eig, void *sigma_acc) {
   const Dims &d = c->d;
@@ -481,7 +481,7 @@ int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const doubl
     const int Rpad = (d.n_aux + TILE - 1) / TILE * TILE;
     us16 *xs = (us16 *)c->d_xs, *ws = (us16 *)c->d_ws;
     const long long nx = Cpad * (Npad / 8), nwt = (long long)d.n_freq * Rpad * (Npad / 8);
-    const int NS = c->precision == LRIGW_SPLIT_BF16 ? 2 : 3;
+    const int NS = ns_sig(c->precision);
     if (NS == 2) {
       hipLaunchKernelGGL(k_split_x<2>, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, c->stream, (const float2 *)x, Ccols,
                          d.n_aux, Cpad, Npad, xs);

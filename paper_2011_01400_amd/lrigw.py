@@ -24,8 +24,9 @@ LRIGW_ERR_NOCONV = -5
 LRIGW_WARN_QP_NOCONV = 1
 LRIGW_WARN_PADE_TRUNC = 2
 
-FP64, FP32, SPLIT_BF16, SPLIT3_BF16 = 0, 1, 2, 3
-PRECISIONS = {"fp64": FP64, "fp32": FP32, "split_bf16": SPLIT_BF16, "split3_bf16": SPLIT3_BF16}
+FP64, FP32, SPLIT_BF16, SPLIT3_BF16, SPLIT_MIXED = 0, 1, 2, 3, 4
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "split_bf16": SPLIT_BF16, "split3_bf16": SPLIT3_BF16,
+              "split_mixed": SPLIT_MIXED}
 
 # every symbol include/lrigw.h declares
 EXPORTS = ["lrigw_create", "lrigw_destroy", "lrigw_strerror", "lrigw_get_sizes", "lrigw_grids", "lrigw_lri_ft",
