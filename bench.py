@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--precision", default="split3_bf16", choices=list(PEAK_TFLOPS))
+    ap.add_argument("--precision", default="split_mixed", choices=list(PEAK_TFLOPS))
     ap.add_argument("--no-tune", action="store_true", help="skip the response-kernel tile autotuner")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain FP64 path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")

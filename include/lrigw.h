@@ -51,7 +51,7 @@ enum lrigw_precision {
   LRIGW_FP32 = 1,        /* M, chi0 and Sigma^c contractions in FP32 on MFMA, FP32 accumulate */
   LRIGW_SPLIT_BF16 = 2,  /* chi0 and Sigma^c as hi/lo BF16 products on MFMA (hi*hi + hi*lo + lo*hi), FP32 accumulate */
   LRIGW_SPLIT3_BF16 = 3, /* chi0 and Sigma^c with a three-part BF16 split (six products, FP32-like accuracy) */
-  LRIGW_SPLIT_MIXED = 4  /* chi0 with the three-part split, Sigma^c with the two-part split */
+  LRIGW_SPLIT_MIXED = 4  /* chi0 with the two-part split, Sigma^c with the three-part split */
 };
 
 typedef struct {
@@ -306,9 +306,10 @@ int lrigw_batch_destroy(lrigw_batch *b);
  * cell): times the response kernel on one q over its tile choices
  * (frequencies per workgroup, K splits) and, in the split-BF16 forms, the
  * self-energy kernel over its variants (frequencies per workgroup, W
- * prefetch), and keeps the fastest for the context's later calls.  H, evec,
- * eig as lrigw_g0w0.  Outputs (host, may be NULL): the chosen response tiles,
- * the self-energy variant (0..2) and the response time of one q (ms).
+ * prefetch, wave tile), and keeps the fastest for the context's later calls.
+ * H, evec, eig as lrigw_g0w0.  Outputs (host, may be NULL): the chosen
+ * response tiles, the self-energy variant (0..4) and the response time of one
+ * q (ms).
  * Synchronous. */
 int lrigw_tune(lrigw_ctx *ctx, const void *H, const void *evec, const double *eig, int *nw, int *splits,
                int *sigma_variant, double *ms);

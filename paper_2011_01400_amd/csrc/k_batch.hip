@@ -87,7 +87,7 @@ static int autotune_chi0(lrigw_ctx *c, const lrigw_batch_cell &cell, int *nw_out
     LRIGW_HIP_TRY(hipMalloc(&sg, (size_t)d.n_k * d.n_qp * d.n_freq * sizeof(double2)));
     double sbest = INFINITY;
     int bvar = c->sig_var;
-    for (int var = 0; var < 3; ++var) {
+    for (int var = 0; var < 5; ++var) {
       c->sig_var = var;
       int rc = run_sigma_c(c, q, c->d_x, c->d_wc, cell.eig, sg);
       if (rc == LRIGW_OK) rc = hipEventRecord(e0, s) == hipSuccess ? LRIGW_OK : LRIGW_ERR_HIP;

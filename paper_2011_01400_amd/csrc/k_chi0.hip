@@ -249,6 +249,7 @@ __global__ __launch_bounds__(256) void k_chi0_bf16(const us16 *__restrict__ Ap, 
                                                    float2 *__restrict__ part) {
   if (run && *run == 0) return;
   __shared__ __attribute__((aligned(16))) us16 As[2][NS * 2][TILE][KCB + BAP];
+  __shared__ __attribute__((aligned(16))) float wtab[2][NW][KCB];   // 2D/(D^2 + w^2) of the chunk
   int I, J;
   tri_decode(blockIdx.x, I, J);
   const int w0 = blockIdx.y * NW;
@@ -277,15 +278,20 @@ __global__ __launch_bounds__(256) void k_chi0_bf16(const us16 *__restrict__ Ap, 
     const float2 *bsrc = Bt + (long long)(nu0 + 16 * wave + col) * Kp + kb + 8 * g;
     u32x4 apre[NS * 2];
     float2 bcur[8], bnext[8];
-    float dcur[8], dnext[8];
+    // the weight table of a chunk is computed once per workgroup: thread t
+    // < NW*KCB owns frequency t / KCB and row t % KCB
+    const int tw = tid / KCB, tk = tid % KCB;
+    float wnext = 0.f;
+    auto weight = [&](long long k0) {
+      const long long k = k0 + tk;
+      const float dd = k < K ? delta[k] : 1.f;
+      return 2.f * dd / (dd * dd + om2[tw < NW ? tw : 0]);
+    };
 #pragma unroll
     for (int pr = 0; pr < NS * 2; ++pr) apre[pr] = *(const u32x4 *)(asrc + pr * pstride);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      bcur[e] = bsrc[e];
-      const long long k = kb + 8 * g + e;
-      dcur[e] = k < K ? delta[k] : 1.f;
-    }
+    for (int e = 0; e < 8; ++e) bcur[e] = bsrc[e];
+    if (tw < NW) wtab[0][tw][tk] = weight(kb);
 #pragma unroll
     for (int pr = 0; pr < NS * 2; ++pr) *(u32x4 *)&As[0][pr][arow][ak] = apre[pr];
     __syncthreads();
@@ -296,19 +302,19 @@ __global__ __launch_bounds__(256) void k_chi0_bf16(const us16 *__restrict__ Ap, 
 #pragma unroll
         for (int pr = 0; pr < NS * 2; ++pr) apre[pr] = *(const u32x4 *)(asrc + pr * pstride + off);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          bnext[e] = bsrc[off + e];
-          const long long k = kb + off + 8 * g + e;
-          dnext[e] = k < K ? delta[k] : 1.f;
-        }
+        for (int e = 0; e < 8; ++e) bnext[e] = bsrc[off + e];
+        if (tw < NW) wnext = weight(kb + off);
       }
 #pragma unroll
       for (int w = 0; w < NW; ++w) {
         // this wave's 16 columns, weighted for frequency w and split
         bf16x8 br[NS], bi[NS];
+        float wt8[8];
+        *(float4 *)&wt8[0] = *(const float4 *)&wtab[b][w][8 * g];
+        *(float4 *)&wt8[4] = *(const float4 *)&wtab[b][w][8 * g + 4];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          const float wt = 2.f * dcur[e] / (dcur[e] * dcur[e] + om2[w]);
+          const float wt = wt8[e];
           us16 pr_[NS], pi_[NS];
           split_us<NS>(wt * bcur[e].x, pr_);
           split_us<NS>(wt * bcur[e].y, pi_);
@@ -341,10 +347,8 @@ __global__ __launch_bounds__(256) void k_chi0_bf16(const us16 *__restrict__ Ap, 
 #pragma unroll
         for (int pr = 0; pr < NS * 2; ++pr) *(u32x4 *)&As[b ^ 1][pr][arow][ak] = apre[pr];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          bcur[e] = bnext[e];
-          dcur[e] = dnext[e];
-        }
+        for (int e = 0; e < 8; ++e) bcur[e] = bnext[e];
+        if (tw < NW) wtab[b ^ 1][tw][tk] = wnext;
       }
       __syncthreads();
     }

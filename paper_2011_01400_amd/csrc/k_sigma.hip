@@ -421,6 +421,153 @@ __global__ __launch_bounds__(256) void k_sigma_bf16(const us16 *__restrict__ xs,
   }
 }
 
+// The same contraction with 32 x 32 wave tiles (waves 2 x 2 over the 64 x 64
+// workgroup tile, one frequency): per chunk a wave reads half as many x
+// fragments from LDS (two column tiles) and twice as many W fragments from
+// L2 (two row tiles, one chunk ahead), for the same MFMA work.
+template <int NS, bool PF>
+__global__ __launch_bounds__(256) void k_sigma_bf16q(const us16 *__restrict__ xs, const us16 *__restrict__ ws,
+                                                     const float2 *__restrict__ x, const float2 *__restrict__ Wall,
+                                                     long long Ccols, long long Cpad, int N, int Npad, int Rpad, int n_freq,
+                                                     double *__restrict__ Xall) {
+  __shared__ __attribute__((aligned(16))) us16 Bs[2][NS * 2][TILE][SKB + SBP];
+  __shared__ double red[2][TILE];
+  long long cb;
+  int w;
+  if (!xcd_map(n_freq, (Ccols + TILE - 1) / TILE, cb, w)) return;
+  const long long c0 = cb * TILE;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, g = lane >> 4;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int ngroups = Rpad / TILE;
+  const int base = N - Rpad;
+  double psum[2] = {0.0, 0.0};
+  const int scol = tid >> 2, sk = (tid & 3) * 8;
+  const us16 *xsrc = xs + (c0 + scol) * Npad + sk;
+  const long long pst = (long long)Rpad * Npad;
+
+  for (int I = 0; I < ngroups; ++I) {
+    const int mu0 = base + I * TILE;
+    const int nch = (mu0 + TILE - 1 > 0) ? (mu0 + TILE - 1 + SKB - 1) / SKB : 0;   // nu < mu0 + 63
+    if (nch == 0) continue;
+    const int r0 = mu0 + 32 * wr;
+    const int kcw = (r0 + 31 > 0) ? (r0 + 31 + SKB - 1) / SKB : 0;                 // nu < r0 + 31
+    f4v zr[2][2], zi[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) zr[i][j] = zi[i][j] = Mfma<float>::zero();
+    u32x4 bpre[NS * 2];
+    __syncthreads();
+#pragma unroll
+    for (int pr = 0; pr < NS * 2; ++pr) bpre[pr] = *(const u32x4 *)(xsrc + (long long)pr * Cpad * Npad);
+#pragma unroll
+    for (int pr = 0; pr < NS * 2; ++pr) *(u32x4 *)&Bs[0][pr][scol][sk] = bpre[pr];
+    __syncthreads();
+    const us16 *wsrc[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      wsrc[i] = ws + ((long long)w * NS * 2 * Rpad + I * TILE + 32 * wr + 16 * i + col) * Npad + 8 * g;
+    u32x4 acur[2][NS * 2], anext[2][NS * 2];
+    if (PF && kcw > 0) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int pr = 0; pr < NS * 2; ++pr) acur[i][pr] = *(const u32x4 *)(wsrc[i] + pr * pst);
+    }
+    for (int ch = 0; ch < nch; ++ch) {
+      const int b = ch & 1;
+      if (ch + 1 < nch) {
+#pragma unroll
+        for (int pr = 0; pr < NS * 2; ++pr) bpre[pr] = *(const u32x4 *)(xsrc + (long long)pr * Cpad * Npad + (ch + 1) * SKB);
+      }
+      if (PF && ch + 1 < kcw) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int pr = 0; pr < NS * 2; ++pr) anext[i][pr] = *(const u32x4 *)(wsrc[i] + pr * pst + (ch + 1) * SKB);
+      }
+      if (!PF && ch < kcw) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int pr = 0; pr < NS * 2; ++pr) acur[i][pr] = *(const u32x4 *)(wsrc[i] + pr * pst + ch * SKB);
+      }
+      if (ch < kcw) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          bf16x8 br[NS], bi[NS];
+#pragma unroll
+          for (int p = 0; p < NS; ++p) {
+            br[p] = *(const bf16x8 *)&Bs[b][2 * p][32 * wc + 16 * j + col][8 * g];
+            bi[p] = *(const bf16x8 *)&Bs[b][2 * p + 1][32 * wc + 16 * j + col][8 * g];
+          }
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+#pragma unroll
+            for (int p = 0; p < NS; ++p) {
+              const bf16x8 ar = as_bf(acur[i][2 * p]), ai = as_bf(acur[i][2 * p + 1]);
+              const bf16x8 nai = as_bf(neg_bf(acur[i][2 * p + 1]));
+#pragma unroll
+              for (int q = 0; q + p < NS; ++q) {
+                zr[i][j] = mfma_bf16(ar, br[q], zr[i][j]);
+                zr[i][j] = mfma_bf16(nai, bi[q], zr[i][j]);
+                zi[i][j] = mfma_bf16(ar, bi[q], zi[i][j]);
+                zi[i][j] = mfma_bf16(ai, br[q], zi[i][j]);
+              }
+            }
+          }
+        }
+      }
+      if (ch + 1 < nch) {
+#pragma unroll
+        for (int pr = 0; pr < NS * 2; ++pr) *(u32x4 *)&Bs[b ^ 1][pr][scol][sk] = bpre[pr];
+      }
+      if (PF && ch + 1 < kcw) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int pr = 0; pr < NS * 2; ++pr) acur[i][pr] = anext[i][pr];
+      }
+      __syncthreads();
+    }
+    if (r0 + 31 >= 0) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const long long cc = c0 + 32 * wc + 16 * j + col;
+        if (cc >= Ccols) continue;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int mu = r0 + 16 * i + Mfma<float>::row(lane, q);
+            if (mu < 0 || mu >= N) continue;
+            const float2 xv = x[cc * N + mu];
+            const double xr = (double)xv.x, xi = (double)xv.y;
+            const double wdd = (double)Wall[((long long)w * N + mu) * N + mu].x;
+            psum[j] += 2.0 * (xr * (double)zr[i][j][q] - xi * (double)zi[i][j][q]) + wdd * (xr * xr + xi * xi);
+          }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    double t = psum[j];
+    t += __shfl_xor(t, 16);
+    t += __shfl_xor(t, 32);
+    psum[j] = t;
+  }
+  __syncthreads();
+  if (lane < 16) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) red[wr][32 * wc + 16 * j + lane] = psum[j];
+  }
+  __syncthreads();
+  if (tid < TILE) {
+    const long long cc = c0 + tid;
+    if (cc < Ccols) Xall[(long long)w * Ccols + cc] = red[0][tid] + red[1][tid];
+  }
+}
+
 // sigma[k][n][i] += scale * sum_m sum_j g_j X[j][k][n][m] a/(a^2 + w_j^2),  a = i w_i + mu - e_m(k-q)
 __global__ void k_sigma_freq(const double *__restrict__ X, const double *__restrict__ eig, const int *__restrict__ kmq, int iq,
                              int nk, int n_qp, int n_bands, int n_freq, const double *__restrict__ omega,
@@ -457,7 +604,9 @@ __global__ void k_sigma_freq(const double *__restrict__ X, const double *__restr
 }
 
 // split-BF16 kernel variants the tuner chooses from: (frequencies per
-// workgroup, W prefetched one chunk ahead) = (1, yes), (2, no), (1, no)
+// workgroup, W prefetched one chunk ahead, wave tile) = (1, yes, 16x64),
+// (2, no, 16x64), (1, no, 16x64), (1, yes, 32x32), (1, no, 32x32)
+#define SIGMA_VARIANTS 5
 int sigma_variant_snw(int var) { return var == 1 ? 2 : 1; }
 int sigma_default_variant(int precision) { return ns_sig(precision) == 2 ? 1 : 0; }
 
@@ -502,11 +651,15 @@ int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const doubl
     if (NS == 2) {
       if (var == 0) hipLaunchKernelGGL((k_sigma_bf16<2, 1, true>), gs, dim3(256), 0, c->stream, SIG_ARGS);
       else if (var == 1) hipLaunchKernelGGL((k_sigma_bf16<2, 2, false>), gs, dim3(256), 0, c->stream, SIG_ARGS);
-      else hipLaunchKernelGGL((k_sigma_bf16<2, 1, false>), gs, dim3(256), 0, c->stream, SIG_ARGS);
+      else if (var == 2) hipLaunchKernelGGL((k_sigma_bf16<2, 1, false>), gs, dim3(256), 0, c->stream, SIG_ARGS);
+      else if (var == 3) hipLaunchKernelGGL((k_sigma_bf16q<2, true>), gs, dim3(256), 0, c->stream, SIG_ARGS);
+      else hipLaunchKernelGGL((k_sigma_bf16q<2, false>), gs, dim3(256), 0, c->stream, SIG_ARGS);
     } else {
       if (var == 0) hipLaunchKernelGGL((k_sigma_bf16<3, 1, true>), gs, dim3(256), 0, c->stream, SIG_ARGS);
       else if (var == 1) hipLaunchKernelGGL((k_sigma_bf16<3, 2, false>), gs, dim3(256), 0, c->stream, SIG_ARGS);
-      else hipLaunchKernelGGL((k_sigma_bf16<3, 1, false>), gs, dim3(256), 0, c->stream, SIG_ARGS);
+      else if (var == 2) hipLaunchKernelGGL((k_sigma_bf16<3, 1, false>), gs, dim3(256), 0, c->stream, SIG_ARGS);
+      else if (var == 3) hipLaunchKernelGGL((k_sigma_bf16q<3, true>), gs, dim3(256), 0, c->stream, SIG_ARGS);
+      else hipLaunchKernelGGL((k_sigma_bf16q<3, false>), gs, dim3(256), 0, c->stream, SIG_ARGS);
     }
 #undef SIG_ARGS
   }

@@ -129,10 +129,10 @@ struct lrigw_ctx {
 size_t lrigw_csize(const lrigw_ctx *c);   // bytes of one complex T
 // BF16 parts of the response / self-energy operands (0: not a split form)
 inline int ns_chi(int precision) {
-  return precision == LRIGW_SPLIT_BF16 ? 2 : (precision == LRIGW_SPLIT3_BF16 || precision == LRIGW_SPLIT_MIXED) ? 3 : 0;
+  return (precision == LRIGW_SPLIT_BF16 || precision == LRIGW_SPLIT_MIXED) ? 2 : precision == LRIGW_SPLIT3_BF16 ? 3 : 0;
 }
 inline int ns_sig(int precision) {
-  return (precision == LRIGW_SPLIT_BF16 || precision == LRIGW_SPLIT_MIXED) ? 2 : precision == LRIGW_SPLIT3_BF16 ? 3 : 0;
+  return precision == LRIGW_SPLIT_BF16 ? 2 : (precision == LRIGW_SPLIT3_BF16 || precision == LRIGW_SPLIT_MIXED) ? 3 : 0;
 }
 long long lrigw_K(const lrigw_ctx *c);    // N_k * n_occ * n_unocc
 

@@ -81,7 +81,8 @@ def test_build_M(case, precision, tol):
         assert relf(X, refx) < tol, (q, relf(X, refx))
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("split_bf16", 1e-5), ("split3_bf16", 1e-5)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("split_bf16", 1e-5), ("split3_bf16", 1e-5),
+                                         ("split_mixed", 1e-5)])
 def test_chi0_and_screen(case, precision, tol):
     s, o, dev = case["sys"], case["o"], case["dev"]
     ctx = _ctx(case, precision)
@@ -115,7 +116,7 @@ def test_chi0_and_screen(case, precision, tol):
 
 
 @pytest.mark.parametrize("precision,tol_s,tol_mev", [("fp64", 1e-9, 1e-5), ("fp32", 2e-5, 10.0), ("split3_bf16", 2e-5, 10.0),
-                                                      ("split_bf16", 2e-4, 30.0)])
+                                                      ("split_bf16", 2e-4, 30.0), ("split_mixed", 2e-4, 30.0)])
 def test_g0w0_end_to_end(case, precision, tol_s, tol_mev):
     s, o, dev = case["sys"], case["o"], case["dev"]
     ctx = _ctx(case, precision)
