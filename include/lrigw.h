@@ -306,9 +306,9 @@ int lrigw_batch_destroy(lrigw_batch *b);
  * cell): times the response kernel on one q over its tile choices
  * (frequencies per workgroup, K splits) and, in the split-BF16 forms, the
  * self-energy kernel over its variants (frequencies per workgroup, W
- * prefetch, wave tile), and keeps the fastest for the context's later calls.
+ * prefetch, wave tile, LDS row padding), and keeps the fastest for the context's later calls.
  * H, evec, eig as lrigw_g0w0.  Outputs (host, may be NULL): the chosen
- * response tiles, the self-energy variant (0..4) and the response time of one
+ * response tiles, the self-energy variant (0..6) and the response time of one
  * q (ms).
  * Synchronous. */
 int lrigw_tune(lrigw_ctx *ctx, const void *H, const void *evec, const double *eig, int *nw, int *splits,

@@ -48,8 +48,13 @@ static int autotune_chi0(lrigw_ctx *c, const lrigw_batch_cell &cell, int *nw_out
   LRIGW_HIP_TRY(hipEventCreate(&e1));
   const bool timing = c->timing;
   c->timing = false;
-  for (int nw : nws) {
+  const bool split = ns_chi(c->precision) > 0;
+  int bpad = c->chi_pad;
+  for (int cand = 0; cand < (split ? 4 : 2); ++cand) {
+    const int nw = nws[cand & 1];
+    const int pad = (cand >> 1) ? 16 : 8;
     c->chi_nw = nw;
+    c->chi_pad = pad;
     int Sp = 1;
     LRIGW_TRY(chi0_plan_splits(c, &Sp));
     std::vector<int> Ss = {std::max(1, Sp / 2), Sp, Sp * 2};
@@ -59,23 +64,29 @@ static int autotune_chi0(lrigw_ctx *c, const lrigw_batch_cell &cell, int *nw_out
       if (S > Smax) continue;
       if ((long long)S > std::max<long long>(1, lrigw_K(c) / 64)) continue;
       c->chi_splits = S;
-      // warm-up then timed
+      // warm-up, then the best of three timed runs
       LRIGW_TRY(run_chi0(c, q, c->d_M, cell.eig, 0, c->d_chi));
-      LRIGW_HIP_TRY(hipEventRecord(e0, s));
-      LRIGW_TRY(run_chi0(c, q, c->d_M, cell.eig, 0, c->d_chi));
-      LRIGW_HIP_TRY(hipEventRecord(e1, s));
-      LRIGW_HIP_TRY(hipEventSynchronize(e1));
-      float t = 0.f;
-      LRIGW_HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+      float t = INFINITY;
+      for (int rep = 0; rep < 3; ++rep) {
+        LRIGW_HIP_TRY(hipEventRecord(e0, s));
+        LRIGW_TRY(run_chi0(c, q, c->d_M, cell.eig, 0, c->d_chi));
+        LRIGW_HIP_TRY(hipEventRecord(e1, s));
+        LRIGW_HIP_TRY(hipEventSynchronize(e1));
+        float tr = 0.f;
+        LRIGW_HIP_TRY(hipEventElapsedTime(&tr, e0, e1));
+        t = std::min(t, tr);
+      }
       if (t < best) {
         best = t;
         bnw = nw;
         bS = S;
+        bpad = pad;
       }
     }
   }
   c->chi_nw = bnw;
   c->chi_splits = bS;
+  c->chi_pad = bpad;
   *nw_out = bnw;
   *S_out = bS;
   *ms_out = best;
@@ -87,15 +98,19 @@ static int autotune_chi0(lrigw_ctx *c, const lrigw_batch_cell &cell, int *nw_out
     LRIGW_HIP_TRY(hipMalloc(&sg, (size_t)d.n_k * d.n_qp * d.n_freq * sizeof(double2)));
     double sbest = INFINITY;
     int bvar = c->sig_var;
-    for (int var = 0; var < 5; ++var) {
+    for (int var = 0; var < sigma_variants(); ++var) {
       c->sig_var = var;
       int rc = run_sigma_c(c, q, c->d_x, c->d_wc, cell.eig, sg);
-      if (rc == LRIGW_OK) rc = hipEventRecord(e0, s) == hipSuccess ? LRIGW_OK : LRIGW_ERR_HIP;
-      if (rc == LRIGW_OK) rc = run_sigma_c(c, q, c->d_x, c->d_wc, cell.eig, sg);
-      if (rc == LRIGW_OK) rc = hipEventRecord(e1, s) == hipSuccess ? LRIGW_OK : LRIGW_ERR_HIP;
-      if (rc == LRIGW_OK) rc = hipEventSynchronize(e1) == hipSuccess ? LRIGW_OK : LRIGW_ERR_HIP;
-      float t = 0.f;
-      if (rc == LRIGW_OK) rc = hipEventElapsedTime(&t, e0, e1) == hipSuccess ? LRIGW_OK : LRIGW_ERR_HIP;
+      float t = INFINITY;
+      for (int rep = 0; rep < 3 && rc == LRIGW_OK; ++rep) {
+        rc = hipEventRecord(e0, s) == hipSuccess ? LRIGW_OK : LRIGW_ERR_HIP;
+        if (rc == LRIGW_OK) rc = run_sigma_c(c, q, c->d_x, c->d_wc, cell.eig, sg);
+        if (rc == LRIGW_OK) rc = hipEventRecord(e1, s) == hipSuccess ? LRIGW_OK : LRIGW_ERR_HIP;
+        if (rc == LRIGW_OK) rc = hipEventSynchronize(e1) == hipSuccess ? LRIGW_OK : LRIGW_ERR_HIP;
+        float tr = 0.f;
+        if (rc == LRIGW_OK) rc = hipEventElapsedTime(&tr, e0, e1) == hipSuccess ? LRIGW_OK : LRIGW_ERR_HIP;
+        t = std::min(t, tr);
+      }
       if (rc != LRIGW_OK) {
         (void)hipFree(sg);
         c->sig_var = bvar;

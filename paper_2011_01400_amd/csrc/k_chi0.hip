@@ -241,14 +241,14 @@ __global__ __launch_bounds__(256) void k_chi0_presplit(const float2 *__restrict_
   }
 }
 
-template <int NS, int NW>
+template <int NS, int NW, int PAD>
 __global__ __launch_bounds__(256) void k_chi0_bf16(const us16 *__restrict__ Ap, const float2 *__restrict__ Bt,
                                                    const float *__restrict__ delta, const double *__restrict__ omega,
                                                    const int *__restrict__ wsel, const int *__restrict__ run, long long K,
                                                    long long Kp, int Npad, int n_freq, long long Ks, long long ntile,
                                                    float2 *__restrict__ part) {
   if (run && *run == 0) return;
-  __shared__ __attribute__((aligned(16))) us16 As[2][NS * 2][TILE][KCB + BAP];
+  __shared__ __attribute__((aligned(16))) us16 As[2][NS * 2][TILE][KCB + PAD];
   __shared__ __attribute__((aligned(16))) float wtab[2][NW][KCB];   // 2D/(D^2 + w^2) of the chunk
   int I, J;
   tri_decode(blockIdx.x, I, J);
@@ -493,18 +493,23 @@ int run_chi0_sel(lrigw_ctx *c, int iq, const void *M, const double *eig, int app
       float2 *Btd = (float2 *)c->d_bt;
       dim3 pg((unsigned)(Kp / 32), (unsigned)(Npad / 32));
 #define BF16_ARGS Apd, Btd, Df, c->d_omega, wsel, run, K, Kp, Npad, n_sel, Ks, ntile, Pf
+      const bool p16 = c->chi_pad == 16;
       if (ns_chi(c->precision) == 2) {
         hipLaunchKernelGGL(k_chi0_presplit<2>, pg, dim3(256), 0, c->stream, Bf, K, d.n_aux, Kp, Npad, Apd, Btd);
         stage_end(c, "chi0_split", ev);
         stage_begin(c, "chi0_mfma", &ev);
-        if (NW == 4) hipLaunchKernelGGL((k_chi0_bf16<2, 4>), grid, dim3(256), 0, c->stream, BF16_ARGS);
-        else hipLaunchKernelGGL((k_chi0_bf16<2, 2>), grid, dim3(256), 0, c->stream, BF16_ARGS);
+        if (NW == 4 && p16) hipLaunchKernelGGL((k_chi0_bf16<2, 4, 16>), grid, dim3(256), 0, c->stream, BF16_ARGS);
+        else if (NW == 4) hipLaunchKernelGGL((k_chi0_bf16<2, 4, 8>), grid, dim3(256), 0, c->stream, BF16_ARGS);
+        else if (p16) hipLaunchKernelGGL((k_chi0_bf16<2, 2, 16>), grid, dim3(256), 0, c->stream, BF16_ARGS);
+        else hipLaunchKernelGGL((k_chi0_bf16<2, 2, 8>), grid, dim3(256), 0, c->stream, BF16_ARGS);
       } else {
         hipLaunchKernelGGL(k_chi0_presplit<3>, pg, dim3(256), 0, c->stream, Bf, K, d.n_aux, Kp, Npad, Apd, Btd);
         stage_end(c, "chi0_split", ev);
         stage_begin(c, "chi0_mfma", &ev);
-        if (NW == 4) hipLaunchKernelGGL((k_chi0_bf16<3, 4>), grid, dim3(256), 0, c->stream, BF16_ARGS);
-        else hipLaunchKernelGGL((k_chi0_bf16<3, 2>), grid, dim3(256), 0, c->stream, BF16_ARGS);
+        if (NW == 4 && p16) hipLaunchKernelGGL((k_chi0_bf16<3, 4, 16>), grid, dim3(256), 0, c->stream, BF16_ARGS);
+        else if (NW == 4) hipLaunchKernelGGL((k_chi0_bf16<3, 4, 8>), grid, dim3(256), 0, c->stream, BF16_ARGS);
+        else if (p16) hipLaunchKernelGGL((k_chi0_bf16<3, 2, 16>), grid, dim3(256), 0, c->stream, BF16_ARGS);
+        else hipLaunchKernelGGL((k_chi0_bf16<3, 2, 8>), grid, dim3(256), 0, c->stream, BF16_ARGS);
       }
 #undef BF16_ARGS
     }

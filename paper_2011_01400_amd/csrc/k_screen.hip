@@ -28,16 +28,29 @@ __global__ void k_add_identity(const double2 *__restrict__ D, double2 *__restric
   E[o] = v;
 }
 
-// out = (W + W^H) / 2 in the compute type
+// out = the Hermitian matrix whose lower triangle (diagonal included) is that
+// of W, in the compute type (the diagonal's imaginary part is dropped)
 template <typename T>
 __global__ void k_hermitize(const double2 *__restrict__ W, typename c2t<T>::type *__restrict__ out, int n, long long stride) {
   long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long long)n * n) return;
   int r = (int)(idx / n), cc = (int)(idx % n);
   const double2 *Wb = W + (long long)blockIdx.y * stride;
-  double2 a = Wb[(long long)r * n + cc], b = Wb[(long long)cc * n + r];
-  double2 z = mkc(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+  double2 z;
+  if (cc < r) z = Wb[(long long)r * n + cc];
+  else if (cc > r) z = cconj(Wb[(long long)cc * n + r]);
+  else z = mkc(Wb[(long long)r * n + r].x, 0.0);
   out[(long long)blockIdx.y * stride + idx] = to_c<T>(z);
+}
+
+// A[cc][r] = conj(A[r][cc]) for cc > r (upper triangle from the lower one)
+__global__ void k_mirror_lower(double2 *A, int n, long long stride) {
+  long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)n * n) return;
+  int r = (int)(idx / n), cc = (int)(idx % n);
+  if (cc <= r) return;
+  double2 *Ab = A + (long long)blockIdx.y * stride;
+  Ab[(long long)r * n + cc] = cconj(Ab[(long long)cc * n + r]);
 }
 
 // sticky status of a captured pass: d_info[16] = smallest q whose V or eps~ was
@@ -78,19 +91,24 @@ int run_screen(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_ou
     chiz = c->d_s3;
   }
   const double2 one = mkc(1.0, 0.0), mone = mkc(-1.0, 0.0);
-  // T1 = chi L ; D = -L^H T1
+  // T1 = chi L ; D = -L^H T1 (Hermitian: lower tiles, then mirrored)
   LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, chiz, n, nn, OP_N, c->d_LV, n, 0, c->d_s0, n, nn, one, nw)));
-  LRIGW_TRY(zgemm(s, mk(n, n, n, OP_C, c->d_LV, n, 0, OP_N, c->d_s0, n, nn, c->d_s1, n, nn, mone, nw)));
-  // E = I + D, Cholesky
+  ZGemm gd = mk(n, n, n, OP_C, c->d_LV, n, 0, OP_N, c->d_s0, n, nn, c->d_s1, n, nn, mone, nw);
+  gd.lower_only = 1;
+  LRIGW_TRY(zgemm(s, gd));
   dim3 eg((unsigned)((nn + 255) / 256), nw);
+  hipLaunchKernelGGL(k_mirror_lower, eg, dim3(256), 0, s, c->d_s1, n, nn);
+  // E = I + D, Cholesky
   hipLaunchKernelGGL(k_add_identity, eg, dim3(256), 0, s, c->d_s1, c->d_s2, n, nn);
   LRIGW_TRY(zpotrf_batched(s, c->d_s2, n, n, nn, nw, c->d_dinv, c->d_info + 2));
   // D <- E^{-1} D
   LRIGW_TRY(ztrsm_left_lower(s, c->d_s2, n, nn, c->d_dinv, c->d_s1, n, nn, n, n, nw));
   LRIGW_TRY(ztrsm_left_upper_conj(s, c->d_s2, n, nn, c->d_dinv, c->d_s1, n, nn, n, n, nw));
-  // W = -L (E^{-1} D) L^H
+  // W = -L (E^{-1} D) L^H (Hermitian: lower tiles; k_hermitize mirrors them)
   LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_s1, n, nn, OP_C, c->d_LV, n, 0, c->d_s0, n, nn, one, nw)));
-  LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_LV, n, 0, OP_N, c->d_s0, n, nn, c->d_s1, n, nn, mone, nw)));
+  ZGemm gw = mk(n, n, n, OP_N, c->d_LV, n, 0, OP_N, c->d_s0, n, nn, c->d_s1, n, nn, mone, nw);
+  gw.lower_only = 1;
+  LRIGW_TRY(zgemm(s, gw));
   if (c->precision == LRIGW_FP64)
     hipLaunchKernelGGL(k_hermitize<double>, eg, dim3(256), 0, s, c->d_s1, (double2 *)Wc_out, n, nn);
   else

@@ -260,12 +260,12 @@ __global__ void k_split_w(const float2 *__restrict__ W, int N, int Npad, int Rpa
 __device__ inline bf16x8 as_bf(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 __device__ inline u32x4 neg_bf(u32x4 v) { return v ^ 0x80008000u; }
 
-template <int NS, int SNW, bool PF>
+template <int NS, int SNW, bool PF, int PAD = SBP>
 __global__ __launch_bounds__(256) void k_sigma_bf16(const us16 *__restrict__ xs, const us16 *__restrict__ ws,
                                                     const float2 *__restrict__ x, const float2 *__restrict__ Wall,
                                                     long long Ccols, long long Cpad, int N, int Npad, int Rpad, int n_freq,
                                                     double *__restrict__ Xall) {
-  __shared__ __attribute__((aligned(16))) us16 Bs[2][NS * 2][TILE][SKB + SBP];   // [buf][part*2 + re/im][column][nu]
+  __shared__ __attribute__((aligned(16))) us16 Bs[2][NS * 2][TILE][SKB + PAD];   // [buf][part*2 + re/im][column][nu]
   __shared__ double red[4][SNW * TILE];
   long long cb;
   int wb;
@@ -605,9 +605,11 @@ __global__ void k_sigma_freq(const double *__restrict__ X, const double *__restr
 
 // split-BF16 kernel variants the tuner chooses from: (frequencies per
 // workgroup, W prefetched one chunk ahead, wave tile) = (1, yes, 16x64),
-// (2, no, 16x64), (1, no, 16x64), (1, yes, 32x32), (1, no, 32x32)
-#define SIGMA_VARIANTS 5
+// (2, no, 16x64), (1, no, 16x64), (1, yes, 32x32), (1, no, 32x32), and the
+// first one with LDS rows padded to 96 and 112 bytes instead of 80
+#define SIGMA_VARIANTS 7
 int sigma_variant_snw(int var) { return var == 1 ? 2 : 1; }
+int sigma_variants() { return SIGMA_VARIANTS; }
 int sigma_default_variant(int precision) { return ns_sig(precision) == 2 ? 1 : 0; }
 
 int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const double *eig, void *sigma_acc) {
@@ -653,13 +655,17 @@ int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const doubl
       else if (var == 1) hipLaunchKernelGGL((k_sigma_bf16<2, 2, false>), gs, dim3(256), 0, c->stream, SIG_ARGS);
       else if (var == 2) hipLaunchKernelGGL((k_sigma_bf16<2, 1, false>), gs, dim3(256), 0, c->stream, SIG_ARGS);
       else if (var == 3) hipLaunchKernelGGL((k_sigma_bf16q<2, true>), gs, dim3(256), 0, c->stream, SIG_ARGS);
-      else hipLaunchKernelGGL((k_sigma_bf16q<2, false>), gs, dim3(256), 0, c->stream, SIG_ARGS);
+      else if (var == 4) hipLaunchKernelGGL((k_sigma_bf16q<2, false>), gs, dim3(256), 0, c->stream, SIG_ARGS);
+      else if (var == 5) hipLaunchKernelGGL((k_sigma_bf16<2, 1, true, 16>), gs, dim3(256), 0, c->stream, SIG_ARGS);
+      else hipLaunchKernelGGL((k_sigma_bf16<2, 1, true, 24>), gs, dim3(256), 0, c->stream, SIG_ARGS);
     } else {
       if (var == 0) hipLaunchKernelGGL((k_sigma_bf16<3, 1, true>), gs, dim3(256), 0, c->stream, SIG_ARGS);
       else if (var == 1) hipLaunchKernelGGL((k_sigma_bf16<3, 2, false>), gs, dim3(256), 0, c->stream, SIG_ARGS);
       else if (var == 2) hipLaunchKernelGGL((k_sigma_bf16<3, 1, false>), gs, dim3(256), 0, c->stream, SIG_ARGS);
       else if (var == 3) hipLaunchKernelGGL((k_sigma_bf16q<3, true>), gs, dim3(256), 0, c->stream, SIG_ARGS);
-      else hipLaunchKernelGGL((k_sigma_bf16q<3, false>), gs, dim3(256), 0, c->stream, SIG_ARGS);
+      else if (var == 4) hipLaunchKernelGGL((k_sigma_bf16q<3, false>), gs, dim3(256), 0, c->stream, SIG_ARGS);
+      else if (var == 5) hipLaunchKernelGGL((k_sigma_bf16<3, 1, true, 16>), gs, dim3(256), 0, c->stream, SIG_ARGS);
+      else hipLaunchKernelGGL((k_sigma_bf16<3, 1, true, 24>), gs, dim3(256), 0, c->stream, SIG_ARGS);
     }
 #undef SIG_ARGS
   }

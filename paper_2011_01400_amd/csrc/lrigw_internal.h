@@ -85,6 +85,7 @@ struct lrigw_ctx {
   size_t part_bytes = 0;
   int chi_splits = 1;
   int chi_nw = 4;                // frequencies per chi0 workgroup
+  int chi_pad = 8;               // split-BF16 chi0: LDS row padding (BF16 elements)
   int sig_var = 0;               // split-BF16 Sigma^c kernel variant
   void *d_X = nullptr;           // [N_w][N_k*n_qp*n_bands] pair weights (T)
   double2 *d_LV = nullptr;       // [N][N]
@@ -147,6 +148,7 @@ int chi0_alt_nw(int precision);
 int chi0_plan_splits(const lrigw_ctx *c, int *splits);
 int chi0_check_gap(lrigw_ctx *c, const double *eig);
 int sigma_variant_snw(int var);
+int sigma_variants();
 int sigma_default_variant(int precision);
 int run_lri_ft(lrigw_ctx *c, const double *lri_R, const int *R_list, int nR, const void *evec, void *H_out);
 int run_build_M(lrigw_ctx *c, int iq, int slice, const void *H, const void *evec, void *M_out);
