@@ -1,10 +1,11 @@
 """Short workload for hardware-counter runs (run under rocprofv3).
 
 Runs (1) a plain device-to-device copy of a known size, the calibration for
-the FETCH_SIZE / WRITE_SIZE counters, then (2) one q of the path on the
-Si-like cell in the chosen precision form (the per-launch traffic of every
-kernel is the same for every q except q = 0).  `summarize` turns the counter
-CSVs of two such runs into bytes per launch.
+the FETCH_SIZE / WRITE_SIZE counters, then (2) the tile tuner and one q of the
+path on the Si-like cell in the chosen precision form (the per-launch traffic
+of every kernel is the same for every q except q = 0).  `summarize` turns the
+counter CSVs of two such runs into bytes per launch, taking for each kernel
+family its last dispatch (the pass's; the tuner's trials come first).
 
   rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -- python3 -m paper_2011_01400_amd.profile_run
   python3 -m paper_2011_01400_amd.profile_run --summarize <fetch dir> <write dir>
@@ -21,8 +22,9 @@ import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY_BYTES = 1 << 30          # calibration copy: 1 GiB read + 1 GiB written
-SOURCES = {"k_sigma_bf16": "k_sigma.hip", "k_sigma_mfma": "k_sigma.hip", "k_chi0_bf16": "k_chi0.hip",
-           "k_chi0_mfma": "k_chi0.hip"}
+# the main kernel of each stage (all its variants) and its source file
+FAMILIES = {"sigma_mfma": (("k_sigma_bf16", "k_sigma_bf16q", "k_sigma_mfma"), "k_sigma.hip"),
+            "chi0_mfma": (("k_chi0_bf16", "k_chi0_mfma"), "k_chi0.hip")}
 
 
 def run(precision: str, config: int, q: int):
@@ -44,6 +46,7 @@ def run(precision: str, config: int, q: int):
     ctx = L.Context.from_system(s, precision=precision)
     H = ctx.empty("H")
     ctx.lri_ft(dev["lri"], s.R, dev["evec"], H)
+    ctx.tune(H, dev["evec"], dev["eig"])           # the kernel variants bench.py runs
     sigma = torch.zeros((s.n_k, sp.n_qp, sp.n_freq), dtype=torch.complex128, device="cuda")
     e = torch.zeros((s.n_k, sp.n_qp), dtype=torch.float64, device="cuda")
     z = torch.zeros_like(e)
@@ -65,45 +68,51 @@ def _rows(d):
 
 
 def _per_kernel(rows):
-    """{kernel name: [value per dispatch]} (counter value in KiB, summed over the dispatch)."""
+    """{kernel name: [(dispatch id, value)]} (counter value in KiB, summed over the dispatch)."""
     acc = {}
     for r in rows:
         name = r.get("Kernel_Name") or r.get("Kernel-Name") or r.get("KernelName") or ""
         val = float(r.get("Counter_Value") or r.get("Counter-Value") or 0.0)
-        disp = r.get("Dispatch_Id") or r.get("Dispatch-Id") or r.get("Correlation_Id") or len(acc)
+        disp = int(r.get("Dispatch_Id") or r.get("Dispatch-Id") or r.get("Correlation_Id") or 0)
         acc.setdefault(name, {}).setdefault(disp, 0.0)
         acc[name][disp] += val
-    return {k: list(v.values()) for k, v in acc.items()}
+    return {k: sorted(v.items()) for k, v in acc.items()}
 
 
 def summarize(fetch_dir, write_dir, precision, config, out_path):
     res = {}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         per = _per_kernel(_rows(d))
-        copy = [v for k, v in per.items() if "copy" in k.lower() or "elementwise" in k.lower()]
-        copy = max((x for lst in copy for x in lst), default=None)
+        copy = [v for k, lst in per.items() if "copy" in k.lower() for _, v in lst]
+        copy = max(copy, default=None)
         scale = COPY_BYTES / (copy * 1024.0) if copy else None
         res[counter] = {"copy_kib": copy, "scale": scale, "kernels": {}}
-        for k, vals in per.items():
-            for short in SOURCES:
-                if short in k:
-                    res[counter]["kernels"][short] = sum(vals) / len(vals)
+        last = {}
+        for k, lst in per.items():
+            name = k.split("(")[0].replace("void ", "").strip()
+            base = name.split("<")[0].strip()
+            for fam, (members, _) in FAMILIES.items():
+                if base in members and (fam not in last or lst[-1][0] > last[fam][0]):
+                    last[fam] = (lst[-1][0], lst[-1][1], name)
+        for fam, (_, v, name) in last.items():
+            res[counter]["kernels"][fam] = (v, name)
     out = {}
     try:
         with open(out_path) as f:
             out = json.load(f)
     except (OSError, ValueError):
         pass
-    for short, src in SOURCES.items():
-        f = res["FETCH_SIZE"]["kernels"].get(short)
-        w = res["WRITE_SIZE"]["kernels"].get(short)
-        if f is None or w is None:
+    for fam, (_, src) in FAMILIES.items():
+        fr = res["FETCH_SIZE"]["kernels"].get(fam)
+        wr = res["WRITE_SIZE"]["kernels"].get(fam)
+        if fr is None or wr is None:
             continue
+        (f, kname), (w, _) = fr, wr
         sf, sw = res["FETCH_SIZE"]["scale"], res["WRITE_SIZE"]["scale"]
         with open(os.path.join(ROOT, "paper_2011_01400_amd", "csrc", src), "rb") as fh:
             h = hashlib.sha256(fh.read()).hexdigest()[:16]
-        key = ("sigma_mfma" if "sigma" in short else "chi0_mfma") + f":{precision}:c{config}"
-        out[key] = {"kernel": short, "source": src, "source_sha256_16": h,
+        key = f"{fam}:{precision}:c{config}"
+        out[key] = {"kernel": kname, "source": src, "source_sha256_16": h,
                     "fetch_kib_per_launch": f, "write_kib_per_launch": w,
                     "copy_calibration": {"fetch_scale": sf, "write_scale": sw, "copy_bytes": COPY_BYTES},
                     "bytes_per_launch": (f * 1024.0 * (sf or 1.0)) + (w * 1024.0 * (sw or 1.0))}
@@ -114,7 +123,7 @@ def summarize(fetch_dir, write_dir, precision, config, out_path):
 
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
-    ap.add_argument("--precision", default="split3_bf16")
+    ap.add_argument("--precision", default="split_mixed")
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--q", type=int, default=1)
     ap.add_argument("--summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
