@@ -23,8 +23,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # MI355X dense matrix peaks (the split forms run BF16 MFMA)
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0, "split3_bf16": 2500.0, "split_mixed": 2500.0}
-DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16", "split3_bf16": "bf16", "split_mixed": "bf16"}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0, "split3_bf16": 2500.0, "split_mixed": 2500.0,
+               "split_f16": 2500.0}
+DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16", "split3_bf16": "bf16", "split_mixed": "bf16",
+         "split_f16": "f16"}
 STAGES = ("lri_ft", "build_M", "chi0", "chi0_split", "chi0_mfma", "screen", "sigma_c", "sigma_split", "sigma_mfma", "qp")
 HA_MEV = 27211.386
 
@@ -35,7 +37,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--precision", default="split_mixed", choices=list(PEAK_TFLOPS))
+    ap.add_argument("--precision", default="split_f16", choices=list(PEAK_TFLOPS))
     ap.add_argument("--no-tune", action="store_true", help="skip the response-kernel tile autotuner")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain FP64 path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")

@@ -51,7 +51,9 @@ enum lrigw_precision {
   LRIGW_FP32 = 1,        /* M, chi0 and Sigma^c contractions in FP32 on MFMA, FP32 accumulate */
   LRIGW_SPLIT_BF16 = 2,  /* chi0 and Sigma^c as hi/lo BF16 products on MFMA (hi*hi + hi*lo + lo*hi), FP32 accumulate */
   LRIGW_SPLIT3_BF16 = 3, /* chi0 and Sigma^c with a three-part BF16 split (six products, FP32-like accuracy) */
-  LRIGW_SPLIT_MIXED = 4  /* chi0 with the two-part split, Sigma^c with the three-part split */
+  LRIGW_SPLIT_MIXED = 4, /* chi0 with the two-part split, Sigma^c with the three-part split */
+  LRIGW_SPLIT_F16 = 5    /* chi0 and Sigma^c as two-part FP16 splits of power-of-two scaled operands (three
+                            products, 22 significand bits), FP32 accumulate */
 };
 
 typedef struct {
@@ -304,15 +306,24 @@ int lrigw_batch_destroy(lrigw_batch *b);
 
 /* Tile autotuner for one context (the same one lrigw_batch_create runs per
  * cell): times the response kernel on one q over its tile choices
- * (frequencies per workgroup, K splits) and, in the split-BF16 forms, the
- * self-energy kernel over its variants (frequencies per workgroup, W
- * prefetch, wave tile, LDS row padding), and keeps the fastest for the context's later calls.
+ * (frequencies per workgroup, K splits, LDS row padding) and, in the split
+ * forms, the self-energy kernel over its variants (frequencies per workgroup,
+ * W prefetch, wave tile, LDS row padding), and keeps the fastest for the
+ * context's later calls.
  * H, evec, eig as lrigw_g0w0.  Outputs (host, may be NULL): the chosen
  * response tiles, the self-energy variant (0..6) and the response time of one
  * q (ms).
  * Synchronous. */
 int lrigw_tune(lrigw_ctx *ctx, const void *H, const void *evec, const double *eig, int *nw, int *splits,
                int *sigma_variant, double *ms);
+
+/* Set the tile choices lrigw_tune would pick, explicitly: nw = frequencies per
+ * response workgroup (the form's default or its alternative: 4/2 in the FP32
+ * and split forms, 2/1 in FP64), splits = K splits (the partial-tile buffer
+ * must hold them), pad = LDS row padding of the split-form response kernel (8
+ * or 16), sigma_variant = split-form self-energy kernel variant (0..6).
+ * Errors: ERR_ARG for a choice outside these sets. */
+int lrigw_set_tiles(lrigw_ctx *ctx, int nw, int splits, int pad, int sigma_variant);
 
 /* Per-kernel device time (ms, HIP events on the context stream) accumulated
  * since the last reset, for the named stages "build_M", "chi0", "screen",

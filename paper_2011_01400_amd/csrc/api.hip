@@ -42,7 +42,8 @@ void stage_end(lrigw_ctx *c, const char *name, hipEvent_t ev) {
 static void free_all(lrigw_ctx *c) {
   void *ptrs[] = {c->d_aux_atom, c->d_basis_off, c->d_aux_off, c->d_kpq, c->d_kmq, c->d_omega, c->d_weight, c->d_wall,
                   c->d_delta, c->d_part, c->d_X, c->d_LV, c->d_s0, c->d_s1, c->d_s2, c->d_s3, c->d_dinv, c->d_info,
-                  c->d_bhat, c->d_x1, c->d_M, c->d_x, c->d_chi, c->d_wc, c->d_epsqp, c->d_xs, c->d_ws, c->d_ap, c->d_bt, c->d_chi2, c->d_wc2};
+                  c->d_bhat, c->d_x1, c->d_M, c->d_x, c->d_chi, c->d_wc, c->d_epsqp, c->d_xs, c->d_ws, c->d_ap, c->d_bt, c->d_chi2, c->d_wc2,
+                  c->d_sx, c->d_wmax, c->d_amax};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &kv : c->stages)
@@ -191,7 +192,7 @@ int lrigw_create(lrigw_ctx **out, const lrigw_system *sys, int precision, void *
   (void)hipGetLastError();  // drop a stale error another library left behind
   if (!out || !sys || !sys->basis_off || !sys->aux_off) return LRIGW_ERR_ARG;
   *out = nullptr;
-  if (precision < LRIGW_FP64 || precision > LRIGW_SPLIT_MIXED) return LRIGW_ERR_ARG;
+  if (precision < LRIGW_FP64 || precision > LRIGW_SPLIT_F16) return LRIGW_ERR_ARG;
   if (sys->n_atoms < 1 || sys->nk[0] < 1 || sys->nk[1] < 1 || sys->nk[2] < 1) return LRIGW_ERR_ARG;
   if (sys->basis_off[0] != 0 || sys->aux_off[0] != 0) return LRIGW_ERR_ARG;
   int nb_max = 0;

@@ -255,6 +255,24 @@ int lrigw_tune(lrigw_ctx *c, const void *H, const void *evec, const double *eig,
   return LRIGW_OK;
 }
 
+int lrigw_set_tiles(lrigw_ctx *c, int nw, int splits, int pad, int sigma_variant) {
+  if (!c) return LRIGW_ERR_ARG;
+  const int dnw = chi0_default_nw(c->precision), anw = chi0_alt_nw(c->precision);
+  if (nw != dnw && nw != anw) return LRIGW_ERR_ARG;
+  if (pad != 8 && pad != 16) return LRIGW_ERR_ARG;
+  if (sigma_variant < 0 || sigma_variant >= sigma_variants()) return LRIGW_ERR_ARG;
+  const Dims &d = c->d;
+  const int nt = (d.n_aux + 63) / 64;
+  const size_t per = (size_t)d.n_freq * ((size_t)nt * (nt + 1) / 2) * 64 * 64 * lrigw_csize(c);
+  if (splits < 1 || (size_t)splits * per > c->part_bytes || (long long)splits > std::max<long long>(1, lrigw_K(c) / 64))
+    return LRIGW_ERR_ARG;
+  c->chi_nw = nw;
+  c->chi_splits = splits;
+  c->chi_pad = pad;
+  c->sig_var = sigma_variant;
+  return LRIGW_OK;
+}
+
 int lrigw_batch_run(lrigw_batch *b) {
   (void)hipGetLastError();
   if (!b || !b->exec) return LRIGW_ERR_ARG;

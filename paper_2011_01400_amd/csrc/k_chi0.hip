@@ -194,24 +194,28 @@ __device__ inline void splitn(float v, __bf16 *p) {
 // copies of Ap; the B fragments (the wave's 16 columns) are read from Bt
 // straight into registers, weighted by 2D/(D^2 + w^2) and split into NS parts
 // there, once per element and frequency.
-typedef unsigned short us16;
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-
-template <int NS>
-__device__ inline void split_us(float v, us16 *out) {
-  float r = v;
-#pragma unroll
-  for (int i = 0; i < NS; ++i) {
-    const __bf16 h = (__bf16)r;
-    out[i] = __builtin_bit_cast(us16, h);
-    r -= (float)h;
+// amax[mu] = max(amax[mu], largest |Re|, |Im| of B[k][mu] over 64 rows k) as
+// float bits; one block per 64 rows of K
+__global__ __launch_bounds__(256) void k_absmax_rows(const float2 *__restrict__ B, long long K, int N, unsigned *__restrict__ amax) {
+  const long long k0 = (long long)blockIdx.x * 64;
+  const long long k1 = k0 + 64 < K ? k0 + 64 : K;
+  for (int mu = threadIdx.x; mu < N; mu += 256) {
+    float m = 0.f;
+    for (long long k = k0; k < k1; ++k) {
+      const float2 v = B[k * N + mu];
+      m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+    }
+    atomicMax(amax + mu, __float_as_uint(m));
   }
 }
 
-// 32 (k) x 32 (mu) tiles through LDS; block 32 x 8 threads
-template <int NS>
+// 32 (k) x 32 (mu) tiles through LDS; block 32 x 8 threads.  FP16 parts (H)
+// and the FP32 copy Bt are taken of row mu times the power of two set by its
+// largest magnitude amax[mu].
+template <int NS, bool H>
 __global__ __launch_bounds__(256) void k_chi0_presplit(const float2 *__restrict__ B, long long K, int N, long long Kp,
-                                                       int Npad, us16 *__restrict__ Ap, float2 *__restrict__ Bt) {
+                                                       int Npad, const unsigned *__restrict__ amax, us16 *__restrict__ Ap,
+                                                       float2 *__restrict__ Bt) {
   __shared__ float2 t[32][33];
   const long long k0 = (long long)blockIdx.x * 32;
   const int m0 = blockIdx.y * 32;
@@ -227,12 +231,17 @@ __global__ __launch_bounds__(256) void k_chi0_presplit(const float2 *__restrict_
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int mm = ty + 8 * i;
-    const float2 v = t[tx][mm];
+    float2 v = t[tx][mm];
+    if (H) {
+      const float inv = m0 + mm < N ? inv_pow2_scale(__uint_as_float(amax[m0 + mm])) : 1.f;
+      v.x *= inv;
+      v.y *= inv;
+    }
     const long long o = (long long)(m0 + mm) * Kp + k0 + tx;
     Bt[o] = v;
     us16 a[NS], b[NS];
-    split_us<NS>(v.x, a);
-    split_us<NS>(v.y, b);
+    split_n<NS, H>(v.x, a);
+    split_n<NS, H>(v.y, b);
 #pragma unroll
     for (int p = 0; p < NS; ++p) {
       Ap[(long long)(2 * p) * Npad * Kp + o] = a[p];
@@ -241,12 +250,15 @@ __global__ __launch_bounds__(256) void k_chi0_presplit(const float2 *__restrict_
   }
 }
 
-template <int NS, int NW, int PAD>
-__global__ __launch_bounds__(256) void k_chi0_bf16(const us16 *__restrict__ Ap, const float2 *__restrict__ Bt,
-                                                   const float *__restrict__ delta, const double *__restrict__ omega,
-                                                   const int *__restrict__ wsel, const int *__restrict__ run, long long K,
-                                                   long long Kp, int Npad, int n_freq, long long Ks, long long ntile,
-                                                   float2 *__restrict__ part) {
+// FP16 parts (H): the weight of frequency w is taken times 2^-e_w with
+// 2^e_w >= 1/w, which bounds |2D/(D^2 + w^2)| by 1, so the weighted, row-scaled
+// B side stays below 2^15; the tile is scaled back by s_mu s_nu 2^e_w.
+template <int NS, int NW, int PAD, bool H>
+__global__ __launch_bounds__(256) void k_chi0_split(const us16 *__restrict__ Ap, const float2 *__restrict__ Bt,
+                                                    const float *__restrict__ delta, const double *__restrict__ omega,
+                                                    const int *__restrict__ wsel, const int *__restrict__ run, long long K,
+                                                    long long Kp, int Npad, int n_freq, long long Ks, long long ntile,
+                                                    const unsigned *__restrict__ amax, int N, float2 *__restrict__ part) {
   if (run && *run == 0) return;
   __shared__ __attribute__((aligned(16))) us16 As[2][NS * 2][TILE][KCB + PAD];
   __shared__ __attribute__((aligned(16))) float wtab[2][NW][KCB];   // 2D/(D^2 + w^2) of the chunk
@@ -257,11 +269,14 @@ __global__ __launch_bounds__(256) void k_chi0_bf16(const us16 *__restrict__ Ap, 
   const long long ke = min(K, kb + Ks);
   const int mu0 = I * TILE, nu0 = J * TILE;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, g = lane >> 4;
-  float om2[NW];
+  float om2[NW], wsc[NW];
 #pragma unroll
   for (int w = 0; w < NW; ++w) {
     const double o = (w0 + w < n_freq) ? omega[wsel[w0 + w]] : 0.0;
     om2[w] = (float)(o * o);
+    int e = 0;
+    if (H && o > 0.0) frexp(1.0 / o, &e);   // 1/o < 2^e
+    wsc[w] = ldexpf(1.f, -e);
   }
   f4v re[NW][4], im[NW][4];
 #pragma unroll
@@ -285,7 +300,8 @@ __global__ __launch_bounds__(256) void k_chi0_bf16(const us16 *__restrict__ Ap, 
     auto weight = [&](long long k0) {
       const long long k = k0 + tk;
       const float dd = k < K ? delta[k] : 1.f;
-      return 2.f * dd / (dd * dd + om2[tw < NW ? tw : 0]);
+      const int w = tw < NW ? tw : 0;
+      return 2.f * dd / (dd * dd + om2[w]) * wsc[w];
     };
 #pragma unroll
     for (int pr = 0; pr < NS * 2; ++pr) apre[pr] = *(const u32x4 *)(asrc + pr * pstride);
@@ -308,7 +324,7 @@ __global__ __launch_bounds__(256) void k_chi0_bf16(const us16 *__restrict__ Ap, 
 #pragma unroll
       for (int w = 0; w < NW; ++w) {
         // this wave's 16 columns, weighted for frequency w and split
-        bf16x8 br[NS], bi[NS];
+        us16 brs[NS][8], bis[NS][8];
         float wt8[8];
         *(float4 *)&wt8[0] = *(const float4 *)&wtab[b][w][8 * g];
         *(float4 *)&wt8[4] = *(const float4 *)&wtab[b][w][8 * g + 4];
@@ -316,29 +332,34 @@ __global__ __launch_bounds__(256) void k_chi0_bf16(const us16 *__restrict__ Ap, 
         for (int e = 0; e < 8; ++e) {
           const float wt = wt8[e];
           us16 pr_[NS], pi_[NS];
-          split_us<NS>(wt * bcur[e].x, pr_);
-          split_us<NS>(wt * bcur[e].y, pi_);
+          split_n<NS, H>(wt * bcur[e].x, pr_);
+          split_n<NS, H>(wt * bcur[e].y, pi_);
 #pragma unroll
           for (int p = 0; p < NS; ++p) {
-            br[p][e] = __builtin_bit_cast(__bf16, pr_[p]);
-            bi[p][e] = __builtin_bit_cast(__bf16, pi_[p]);
+            brs[p][e] = pr_[p];
+            bis[p][e] = pi_[p];
           }
+        }
+        u32x4 br[NS], bi[NS];
+#pragma unroll
+        for (int p = 0; p < NS; ++p) {
+          br[p] = *(const u32x4 *)brs[p];
+          bi[p] = *(const u32x4 *)bis[p];
         }
 #pragma unroll
         for (int si = 0; si < 4; ++si) {
 #pragma unroll
           for (int p = 0; p < NS; ++p) {
-            const u32x4 ur = *(const u32x4 *)&As[b][2 * p][16 * si + col][8 * g];
-            const u32x4 ui = *(const u32x4 *)&As[b][2 * p + 1][16 * si + col][8 * g];
-            const bf16x8 ar = __builtin_bit_cast(bf16x8, ur), ai = __builtin_bit_cast(bf16x8, ui);
-            const bf16x8 nar = __builtin_bit_cast(bf16x8, ur ^ 0x80008000u);
+            const u32x4 ar = *(const u32x4 *)&As[b][2 * p][16 * si + col][8 * g];
+            const u32x4 ai = *(const u32x4 *)&As[b][2 * p + 1][16 * si + col][8 * g];
+            const u32x4 nar = ar ^ 0x80008000u;
             // a conj(b): re = ar br + ai bi, im = ai br - ar bi
 #pragma unroll
             for (int q = 0; q + p < NS; ++q) {
-              re[w][si] = mfma_bf16(ar, br[q], re[w][si]);
-              re[w][si] = mfma_bf16(ai, bi[q], re[w][si]);
-              im[w][si] = mfma_bf16(ai, br[q], im[w][si]);
-              im[w][si] = mfma_bf16(nar, bi[q], im[w][si]);
+              re[w][si] = mfma_p<H>(ar, br[q], re[w][si]);
+              re[w][si] = mfma_p<H>(ai, bi[q], re[w][si]);
+              im[w][si] = mfma_p<H>(ai, br[q], im[w][si]);
+              im[w][si] = mfma_p<H>(nar, bi[q], im[w][si]);
             }
           }
         }
@@ -358,14 +379,16 @@ store:
   for (int w = 0; w < NW; ++w) {
     if (w0 + w >= n_freq) continue;
     float2 *dst = part + (((long long)blockIdx.z * n_freq + w0 + w) * ntile + blockIdx.x) * (TILE * TILE);
+    const int cl = 16 * wave + col;
+    const float fcol = H ? pow2_scale(__uint_as_float(amax[nu0 + cl < N ? nu0 + cl : 0])) / wsc[w] : 1.f;
 #pragma unroll
     for (int si = 0; si < 4; ++si) {
       const f4v r = re[w][si], i = im[w][si];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int row = 16 * si + Mfma<float>::row(lane, q);
-        const int cl = 16 * wave + col;
-        dst[row * TILE + cl] = mkcf(r[q], i[q]);
+        const float f = H ? fcol * pow2_scale(__uint_as_float(amax[mu0 + row < N ? mu0 + row : 0])) : 1.f;
+        dst[row * TILE + cl] = mkcf(r[q] * f, i[q] * f);
       }
     }
   }
@@ -492,25 +515,35 @@ int run_chi0_sel(lrigw_ctx *c, int iq, const void *M, const double *eig, int app
       us16 *Apd = (us16 *)c->d_ap;
       float2 *Btd = (float2 *)c->d_bt;
       dim3 pg((unsigned)(Kp / 32), (unsigned)(Npad / 32));
-#define BF16_ARGS Apd, Btd, Df, c->d_omega, wsel, run, K, Kp, Npad, n_sel, Ks, ntile, Pf
       const bool p16 = c->chi_pad == 16;
-      if (ns_chi(c->precision) == 2) {
-        hipLaunchKernelGGL(k_chi0_presplit<2>, pg, dim3(256), 0, c->stream, Bf, K, d.n_aux, Kp, Npad, Apd, Btd);
-        stage_end(c, "chi0_split", ev);
-        stage_begin(c, "chi0_mfma", &ev);
-        if (NW == 4 && p16) hipLaunchKernelGGL((k_chi0_bf16<2, 4, 16>), grid, dim3(256), 0, c->stream, BF16_ARGS);
-        else if (NW == 4) hipLaunchKernelGGL((k_chi0_bf16<2, 4, 8>), grid, dim3(256), 0, c->stream, BF16_ARGS);
-        else if (p16) hipLaunchKernelGGL((k_chi0_bf16<2, 2, 16>), grid, dim3(256), 0, c->stream, BF16_ARGS);
-        else hipLaunchKernelGGL((k_chi0_bf16<2, 2, 8>), grid, dim3(256), 0, c->stream, BF16_ARGS);
+      const int NS = ns_chi(c->precision);
+      const bool H = split_h(c->precision);
+      if (H) {
+        LRIGW_TRY(zero_fill(c->stream, c->d_amax, (size_t)Npad * sizeof(unsigned)));
+        hipLaunchKernelGGL(k_absmax_rows, dim3((unsigned)((K + 63) / 64)), dim3(256), 0, c->stream, Bf, K, d.n_aux, c->d_amax);
+        hipLaunchKernelGGL((k_chi0_presplit<2, true>), pg, dim3(256), 0, c->stream, Bf, K, d.n_aux, Kp, Npad, c->d_amax, Apd,
+                           Btd);
+      } else if (NS == 2) {
+        hipLaunchKernelGGL((k_chi0_presplit<2, false>), pg, dim3(256), 0, c->stream, Bf, K, d.n_aux, Kp, Npad, nullptr, Apd,
+                           Btd);
       } else {
-        hipLaunchKernelGGL(k_chi0_presplit<3>, pg, dim3(256), 0, c->stream, Bf, K, d.n_aux, Kp, Npad, Apd, Btd);
-        stage_end(c, "chi0_split", ev);
-        stage_begin(c, "chi0_mfma", &ev);
-        if (NW == 4 && p16) hipLaunchKernelGGL((k_chi0_bf16<3, 4, 16>), grid, dim3(256), 0, c->stream, BF16_ARGS);
-        else if (NW == 4) hipLaunchKernelGGL((k_chi0_bf16<3, 4, 8>), grid, dim3(256), 0, c->stream, BF16_ARGS);
-        else if (p16) hipLaunchKernelGGL((k_chi0_bf16<3, 2, 16>), grid, dim3(256), 0, c->stream, BF16_ARGS);
-        else hipLaunchKernelGGL((k_chi0_bf16<3, 2, 8>), grid, dim3(256), 0, c->stream, BF16_ARGS);
+        hipLaunchKernelGGL((k_chi0_presplit<3, false>), pg, dim3(256), 0, c->stream, Bf, K, d.n_aux, Kp, Npad, nullptr, Apd,
+                           Btd);
       }
+      stage_end(c, "chi0_split", ev);
+      stage_begin(c, "chi0_mfma", &ev);
+#define BF16_ARGS Apd, Btd, Df, c->d_omega, wsel, run, K, Kp, Npad, n_sel, Ks, ntile, c->d_amax, d.n_aux, Pf
+#define SPLIT_LAUNCH(NS_, H_)                                                                                            \
+  do {                                                                                                                 \
+    if (NW == 4 && p16) hipLaunchKernelGGL((k_chi0_split<NS_, 4, 16, H_>), grid, dim3(256), 0, c->stream, BF16_ARGS); \
+    else if (NW == 4) hipLaunchKernelGGL((k_chi0_split<NS_, 4, 8, H_>), grid, dim3(256), 0, c->stream, BF16_ARGS);   \
+    else if (p16) hipLaunchKernelGGL((k_chi0_split<NS_, 2, 16, H_>), grid, dim3(256), 0, c->stream, BF16_ARGS);      \
+    else hipLaunchKernelGGL((k_chi0_split<NS_, 2, 8, H_>), grid, dim3(256), 0, c->stream, BF16_ARGS);                \
+  } while (0)
+      if (H) SPLIT_LAUNCH(2, true);
+      else if (NS == 2) SPLIT_LAUNCH(2, false);
+      else SPLIT_LAUNCH(3, false);
+#undef SPLIT_LAUNCH
 #undef BF16_ARGS
     }
   }

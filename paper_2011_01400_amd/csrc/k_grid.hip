@@ -148,6 +148,9 @@ int run_grids(lrigw_ctx *c) {
     const long long Kp = (K + 31) / 32 * 32;
     LRIGW_HIP_TRY(hipMalloc(&c->d_ap, (size_t)NSC * 2 * Rpad * Kp * 2));
     LRIGW_HIP_TRY(hipMalloc(&c->d_bt, (size_t)Rpad * Kp * sizeof(float2)));
+    LRIGW_HIP_TRY(hipMalloc(&c->d_sx, (size_t)Cpad * sizeof(float)));
+    LRIGW_HIP_TRY(hipMalloc(&c->d_wmax, (size_t)d.n_freq * sizeof(unsigned)));
+    LRIGW_HIP_TRY(hipMalloc(&c->d_amax, (size_t)Rpad * sizeof(unsigned)));
   }
   return LRIGW_OK;
 }

@@ -165,35 +165,24 @@ __global__ __launch_bounds__(256) void k_sigma_mfma(const typename c2t<T>::type 
   }
 }
 
-// Split-BF16 form.  conj(x) and the strictly lower part of W^c are split once
-// per q into NS BF16 parts (x = sum_p x_p, each part the rounding of what the
+// Split forms.  conj(x) and the strictly lower part of W^c are split once per
+// q into NS 16-bit parts (x = sum_p x_p, each part the rounding of what the
 // previous ones left) in zero-padded MFMA-ready arrays:
 //   xs[p][re/im][Cpad][Npad]             (Cpad = 64-multiple, Npad = 32-multiple)
 //   ws[w][p][re/im][Rpad][Npad]          (row r <-> mu = r + N - Rpad, end-aligned
 //                                          64-row groups; zero for nu >= mu)
-// so the main kernel streams operands without per-element work: the x tile of
-// a workgroup (64 columns x 32 nu) goes to LDS with 16-byte copies, double
-// buffered; each wave reads its 16 rows of W straight into MFMA registers;
-// products of parts p + q < NS accumulate in FP32 on the 16x16x32 BF16 MFMA.
-// Two frequencies share every x tile.
+// Parts are BF16 (H = false) or FP16 (H = true); FP16 parts are taken of the
+// values times a power of two, one per x column (sx) and one per frequency of
+// W^c (from its largest magnitude, wmax), which the FP64 epilogue undoes
+// exactly.  The main kernel streams operands without per-element work: the x
+// tile of a workgroup (64 columns x 32 nu) goes to LDS with 16-byte copies,
+// double buffered; each wave reads its 16 rows of W straight into MFMA
+// registers; products of parts p + q < NS accumulate in FP32 on the 16x16x32
+// MFMA.
 #define SKB 32
 #define SBP 8
 
-typedef unsigned short us16;
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-
-template <int NS>
-__device__ inline void split_parts(float v, us16 *out) {
-  float r = v;
-#pragma unroll
-  for (int i = 0; i < NS; ++i) {
-    const __bf16 h = (__bf16)r;
-    out[i] = __builtin_bit_cast(us16, h);
-    r -= (float)h;
-  }
-}
-
-// xs from x (complex FP32 [C][N]); one thread per (column, 8 nu)
+// BF16 xs from x (complex FP32 [C][N]); one thread per (column, 8 nu)
 template <int NS>
 __global__ void k_split_x(const float2 *__restrict__ x, long long C, int N, long long Cpad, int Npad, us16 *__restrict__ xs) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -208,8 +197,8 @@ __global__ void k_split_x(const float2 *__restrict__ x, long long C, int N, long
     float2 u = mkcf(0.f, 0.f);
     if (c < C && nu < N) u = cconj(x[c * N + nu]);
     us16 a[NS], b[NS];
-    split_parts<NS>(u.x, a);
-    split_parts<NS>(u.y, b);
+    split_n<NS, false>(u.x, a);
+    split_n<NS, false>(u.y, b);
 #pragma unroll
     for (int p = 0; p < NS; ++p) {
       re[p][e] = a[p];
@@ -223,9 +212,72 @@ __global__ void k_split_x(const float2 *__restrict__ x, long long C, int N, long
   }
 }
 
-// ws from W^c (complex FP32 [n_freq][N][N]); one thread per (w, row, 8 nu)
+// FP16 xs: one wave per column; the column's largest |Re|, |Im| sets its scale
+// sx[c], then the scaled values are split.  Block = 4 columns.
 template <int NS>
-__global__ void k_split_w(const float2 *__restrict__ W, int N, int Npad, int Rpad, int n_freq, us16 *__restrict__ ws) {
+__global__ __launch_bounds__(256) void k_split_x_h(const float2 *__restrict__ x, long long C, int N, long long Cpad, int Npad,
+                                                   us16 *__restrict__ xs, float *__restrict__ sx) {
+  const long long c = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= Cpad) return;
+  float m = 0.f;
+  if (c < C)
+    for (int nu = lane; nu < N; nu += 64) {
+      const float2 u = x[c * N + nu];
+      m = fmaxf(m, fmaxf(fabsf(u.x), fabsf(u.y)));
+    }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  const float inv = inv_pow2_scale(m);
+  if (lane == 0) sx[c] = pow2_scale(m);
+  for (int k0 = 8 * lane; k0 < Npad; k0 += 512) {
+    us16 re[NS][8], im[NS][8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int nu = k0 + e;
+      float2 u = mkcf(0.f, 0.f);
+      if (c < C && nu < N) u = cconj(x[c * N + nu]);
+      us16 a[NS], b[NS];
+      split_n<NS, true>(u.x * inv, a);
+      split_n<NS, true>(u.y * inv, b);
+#pragma unroll
+      for (int p = 0; p < NS; ++p) {
+        re[p][e] = a[p];
+        im[p][e] = b[p];
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < NS; ++p) {
+      *(u32x4 *)(xs + ((long long)(2 * p) * Cpad + c) * Npad + k0) = *(const u32x4 *)re[p];
+      *(u32x4 *)(xs + ((long long)(2 * p + 1) * Cpad + c) * Npad + k0) = *(const u32x4 *)im[p];
+    }
+  }
+}
+
+// out[s] = max(out[s], largest |Re|, |Im| of v[s][0..n_per)) as float bits
+// (non-negative floats order like their bit patterns); grid (blocks, sets)
+__global__ __launch_bounds__(256) void k_absmax_sets(const float2 *__restrict__ v, long long n_per, unsigned *__restrict__ out) {
+  __shared__ float red[4];
+  const float2 *p = v + (long long)blockIdx.y * n_per;
+  float m = 0.f;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n_per; i += (long long)gridDim.x * 256) {
+    const float2 u = p[i];
+    m = fmaxf(m, fmaxf(fabsf(u.x), fabsf(u.y)));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    atomicMax(out + blockIdx.y, __float_as_uint(m));
+  }
+}
+
+// ws from W^c (complex FP32 [n_freq][N][N]); one thread per (w, row, 8 nu)
+template <int NS, bool H>
+__global__ void k_split_w(const float2 *__restrict__ W, int N, int Npad, int Rpad, int n_freq, const unsigned *__restrict__ wmax,
+                          us16 *__restrict__ ws) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int g8 = Npad / 8;
   const long long per = (long long)Rpad * g8;
@@ -234,6 +286,7 @@ __global__ void k_split_w(const float2 *__restrict__ W, int N, int Npad, int Rpa
   const int r = (int)((t % per) / g8);
   const int k0 = (int)(t % g8) * 8;
   const int mu = r + N - Rpad;
+  const float inv = H ? inv_pow2_scale(__uint_as_float(wmax[w])) : 1.f;
   us16 re[NS][8], im[NS][8];
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
@@ -241,8 +294,8 @@ __global__ void k_split_w(const float2 *__restrict__ W, int N, int Npad, int Rpa
     float2 v = mkcf(0.f, 0.f);
     if (mu >= 0 && nu < mu) v = W[((long long)w * N + mu) * N + nu];
     us16 a[NS], b[NS];
-    split_parts<NS>(v.x, a);
-    split_parts<NS>(v.y, b);
+    split_n<NS, H>(v.x * inv, a);
+    split_n<NS, H>(v.y * inv, b);
 #pragma unroll
     for (int p = 0; p < NS; ++p) {
       re[p][e] = a[p];
@@ -257,14 +310,14 @@ __global__ void k_split_w(const float2 *__restrict__ W, int N, int Npad, int Rpa
   }
 }
 
-__device__ inline bf16x8 as_bf(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
-__device__ inline u32x4 neg_bf(u32x4 v) { return v ^ 0x80008000u; }
+__device__ inline u32x4 neg_p(u32x4 v) { return v ^ 0x80008000u; }   // both formats keep the sign in bit 15
 
-template <int NS, int SNW, bool PF, int PAD = SBP>
-__global__ __launch_bounds__(256) void k_sigma_bf16(const us16 *__restrict__ xs, const us16 *__restrict__ ws,
-                                                    const float2 *__restrict__ x, const float2 *__restrict__ Wall,
-                                                    long long Ccols, long long Cpad, int N, int Npad, int Rpad, int n_freq,
-                                                    double *__restrict__ Xall) {
+template <int NS, int SNW, bool PF, int PAD, bool H>
+__global__ __launch_bounds__(256) void k_sigma_split(const us16 *__restrict__ xs, const us16 *__restrict__ ws,
+                                                     const float2 *__restrict__ x, const float2 *__restrict__ Wall,
+                                                     long long Ccols, long long Cpad, int N, int Npad, int Rpad, int n_freq,
+                                                     const float *__restrict__ sx, const unsigned *__restrict__ wmax,
+                                                     double *__restrict__ Xall) {
   __shared__ __attribute__((aligned(16))) us16 Bs[2][NS * 2][TILE][SKB + PAD];   // [buf][part*2 + re/im][column][nu]
   __shared__ double red[4][SNW * TILE];
   long long cb;
@@ -275,11 +328,15 @@ __global__ __launch_bounds__(256) void k_sigma_bf16(const us16 *__restrict__ xs,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, g = lane >> 4;
   const int ngroups = Rpad / TILE;
   const int base = N - Rpad;
-  double psum[SNW][4];
+  double psum[SNW][4], fw[SNW], fx[4];
 #pragma unroll
-  for (int v = 0; v < SNW; ++v)
+  for (int v = 0; v < SNW; ++v) {
+    fw[v] = H ? (double)pow2_scale(__uint_as_float(wmax[min(w0 + v, n_freq - 1)])) : 1.0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) psum[v][j] = 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) fx[j] = H ? (double)sx[c0 + 16 * j + col] : 1.0;
   // staging map: thread -> (column, 8-nu group) of the 64 x 32 tile
   const int scol = tid >> 2, sk = (tid & 3) * 8;
 
@@ -338,25 +395,24 @@ __global__ __launch_bounds__(256) void k_sigma_bf16(const us16 *__restrict__ xs,
       if (ch < kcw) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          bf16x8 br[NS], bi[NS];
+          u32x4 br[NS], bi[NS];
 #pragma unroll
           for (int p = 0; p < NS; ++p) {
-            br[p] = *(const bf16x8 *)&Bs[b][2 * p][16 * j + col][8 * g];
-            bi[p] = *(const bf16x8 *)&Bs[b][2 * p + 1][16 * j + col][8 * g];
+            br[p] = *(const u32x4 *)&Bs[b][2 * p][16 * j + col][8 * g];
+            bi[p] = *(const u32x4 *)&Bs[b][2 * p + 1][16 * j + col][8 * g];
           }
 #pragma unroll
           for (int v = 0; v < SNW; ++v) {
             // Z += W u: re = Wr ur - Wi ui, im = Wr ui + Wi ur
 #pragma unroll
             for (int p = 0; p < NS; ++p) {
-              const bf16x8 ar = as_bf(acur[v][2 * p]), ai = as_bf(acur[v][2 * p + 1]);
-              const bf16x8 nai = as_bf(neg_bf(acur[v][2 * p + 1]));
+              const u32x4 ar = acur[v][2 * p], ai = acur[v][2 * p + 1], nai = neg_p(ai);
 #pragma unroll
               for (int q = 0; q + p < NS; ++q) {
-                zr[v][j] = mfma_bf16(ar, br[q], zr[v][j]);
-                zr[v][j] = mfma_bf16(nai, bi[q], zr[v][j]);
-                zi[v][j] = mfma_bf16(ar, bi[q], zi[v][j]);
-                zi[v][j] = mfma_bf16(ai, br[q], zi[v][j]);
+                zr[v][j] = mfma_p<H>(ar, br[q], zr[v][j]);
+                zr[v][j] = mfma_p<H>(nai, bi[q], zr[v][j]);
+                zi[v][j] = mfma_p<H>(ar, bi[q], zi[v][j]);
+                zi[v][j] = mfma_p<H>(ai, br[q], zi[v][j]);
               }
             }
           }
@@ -390,7 +446,7 @@ __global__ __launch_bounds__(256) void k_sigma_bf16(const us16 *__restrict__ xs,
           for (int v = 0; v < SNW; ++v) {
             if (w0 + v >= n_freq) continue;
             const double wdd = (double)Wall[((long long)(w0 + v) * N + mu) * N + mu].x;
-            psum[v][j] += 2.0 * (xr * (double)zr[v][j][q] - xi * (double)zi[v][j][q]) + wdd * (xr * xr + xi * xi);
+            psum[v][j] += 2.0 * fw[v] * fx[j] * (xr * (double)zr[v][j][q] - xi * (double)zi[v][j][q]) + wdd * (xr * xr + xi * xi);
           }
         }
       }
@@ -425,11 +481,12 @@ __global__ __launch_bounds__(256) void k_sigma_bf16(const us16 *__restrict__ xs,
 // workgroup tile, one frequency): per chunk a wave reads half as many x
 // fragments from LDS (two column tiles) and twice as many W fragments from
 // L2 (two row tiles, one chunk ahead), for the same MFMA work.
-template <int NS, bool PF>
-__global__ __launch_bounds__(256) void k_sigma_bf16q(const us16 *__restrict__ xs, const us16 *__restrict__ ws,
-                                                     const float2 *__restrict__ x, const float2 *__restrict__ Wall,
-                                                     long long Ccols, long long Cpad, int N, int Npad, int Rpad, int n_freq,
-                                                     double *__restrict__ Xall) {
+template <int NS, bool PF, bool H>
+__global__ __launch_bounds__(256) void k_sigma_splitq(const us16 *__restrict__ xs, const us16 *__restrict__ ws,
+                                                      const float2 *__restrict__ x, const float2 *__restrict__ Wall,
+                                                      long long Ccols, long long Cpad, int N, int Npad, int Rpad, int n_freq,
+                                                      const float *__restrict__ sx, const unsigned *__restrict__ wmax,
+                                                      double *__restrict__ Xall) {
   __shared__ __attribute__((aligned(16))) us16 Bs[2][NS * 2][TILE][SKB + SBP];
   __shared__ double red[2][TILE];
   long long cb;
@@ -440,7 +497,10 @@ __global__ __launch_bounds__(256) void k_sigma_bf16q(const us16 *__restrict__ xs
   const int wr = wave >> 1, wc = wave & 1;
   const int ngroups = Rpad / TILE;
   const int base = N - Rpad;
-  double psum[2] = {0.0, 0.0};
+  double psum[2] = {0.0, 0.0}, fx[2];
+  const double fw = H ? (double)pow2_scale(__uint_as_float(wmax[w])) : 1.0;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) fx[j] = H ? (double)sx[c0 + 32 * wc + 16 * j + col] : 1.0;
   const int scol = tid >> 2, sk = (tid & 3) * 8;
   const us16 *xsrc = xs + (c0 + scol) * Npad + sk;
   const long long pst = (long long)Rpad * Npad;
@@ -495,24 +555,23 @@ __global__ __launch_bounds__(256) void k_sigma_bf16q(const us16 *__restrict__ xs
       if (ch < kcw) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-          bf16x8 br[NS], bi[NS];
+          u32x4 br[NS], bi[NS];
 #pragma unroll
           for (int p = 0; p < NS; ++p) {
-            br[p] = *(const bf16x8 *)&Bs[b][2 * p][32 * wc + 16 * j + col][8 * g];
-            bi[p] = *(const bf16x8 *)&Bs[b][2 * p + 1][32 * wc + 16 * j + col][8 * g];
+            br[p] = *(const u32x4 *)&Bs[b][2 * p][32 * wc + 16 * j + col][8 * g];
+            bi[p] = *(const u32x4 *)&Bs[b][2 * p + 1][32 * wc + 16 * j + col][8 * g];
           }
 #pragma unroll
           for (int i = 0; i < 2; ++i) {
 #pragma unroll
             for (int p = 0; p < NS; ++p) {
-              const bf16x8 ar = as_bf(acur[i][2 * p]), ai = as_bf(acur[i][2 * p + 1]);
-              const bf16x8 nai = as_bf(neg_bf(acur[i][2 * p + 1]));
+              const u32x4 ar = acur[i][2 * p], ai = acur[i][2 * p + 1], nai = neg_p(ai);
 #pragma unroll
               for (int q = 0; q + p < NS; ++q) {
-                zr[i][j] = mfma_bf16(ar, br[q], zr[i][j]);
-                zr[i][j] = mfma_bf16(nai, bi[q], zr[i][j]);
-                zi[i][j] = mfma_bf16(ar, bi[q], zi[i][j]);
-                zi[i][j] = mfma_bf16(ai, br[q], zi[i][j]);
+                zr[i][j] = mfma_p<H>(ar, br[q], zr[i][j]);
+                zr[i][j] = mfma_p<H>(nai, bi[q], zr[i][j]);
+                zi[i][j] = mfma_p<H>(ar, bi[q], zi[i][j]);
+                zi[i][j] = mfma_p<H>(ai, br[q], zi[i][j]);
               }
             }
           }
@@ -544,7 +603,7 @@ __global__ __launch_bounds__(256) void k_sigma_bf16q(const us16 *__restrict__ xs
             const float2 xv = x[cc * N + mu];
             const double xr = (double)xv.x, xi = (double)xv.y;
             const double wdd = (double)Wall[((long long)w * N + mu) * N + mu].x;
-            psum[j] += 2.0 * (xr * (double)zr[i][j][q] - xi * (double)zi[i][j][q]) + wdd * (xr * xr + xi * xi);
+            psum[j] += 2.0 * fw * fx[j] * (xr * (double)zr[i][j][q] - xi * (double)zi[i][j][q]) + wdd * (xr * xr + xi * xi);
           }
       }
     }
@@ -603,14 +662,31 @@ __global__ void k_sigma_freq(const double *__restrict__ X, const double *__restr
   sigma[o] = s;
 }
 
-// split-BF16 kernel variants the tuner chooses from: (frequencies per
-// workgroup, W prefetched one chunk ahead, wave tile) = (1, yes, 16x64),
-// (2, no, 16x64), (1, no, 16x64), (1, yes, 32x32), (1, no, 32x32), and the
-// first one with LDS rows padded to 96 and 112 bytes instead of 80
+// split kernel variants the tuner chooses from: (frequencies per workgroup,
+// W prefetched one chunk ahead, wave tile) = (1, yes, 16x64), (2, no, 16x64),
+// (1, no, 16x64), (1, yes, 32x32), (1, no, 32x32), and the first one with LDS
+// rows padded to 96 and 112 bytes instead of 80
 #define SIGMA_VARIANTS 7
 int sigma_variant_snw(int var) { return var == 1 ? 2 : 1; }
 int sigma_variants() { return SIGMA_VARIANTS; }
 int sigma_default_variant(int precision) { return ns_sig(precision) == 2 ? 1 : 0; }
+
+template <int NS, bool H>
+static void launch_sigma_split(int var, dim3 gs, hipStream_t st, const us16 *xs, const us16 *ws, const float2 *x,
+                               const float2 *W, long long Ccols, long long Cpad, int N, int Npad, int Rpad, int n_freq,
+                               const float *sx, const unsigned *wmax, double *X) {
+#define SIG_ARGS xs, ws, x, W, Ccols, Cpad, N, Npad, Rpad, n_freq, sx, wmax, X
+  switch (var) {
+    case 0: hipLaunchKernelGGL((k_sigma_split<NS, 1, true, SBP, H>), gs, dim3(256), 0, st, SIG_ARGS); break;
+    case 1: hipLaunchKernelGGL((k_sigma_split<NS, 2, false, SBP, H>), gs, dim3(256), 0, st, SIG_ARGS); break;
+    case 2: hipLaunchKernelGGL((k_sigma_split<NS, 1, false, SBP, H>), gs, dim3(256), 0, st, SIG_ARGS); break;
+    case 3: hipLaunchKernelGGL((k_sigma_splitq<NS, true, H>), gs, dim3(256), 0, st, SIG_ARGS); break;
+    case 4: hipLaunchKernelGGL((k_sigma_splitq<NS, false, H>), gs, dim3(256), 0, st, SIG_ARGS); break;
+    case 5: hipLaunchKernelGGL((k_sigma_split<NS, 1, true, 16, H>), gs, dim3(256), 0, st, SIG_ARGS); break;
+    default: hipLaunchKernelGGL((k_sigma_split<NS, 1, true, 24, H>), gs, dim3(256), 0, st, SIG_ARGS); break;
+  }
+#undef SIG_ARGS
+}
 
 int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const double *eig, void *sigma_acc) {
   const Dims &d = c->d;
@@ -633,41 +709,39 @@ int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const doubl
     us16 *xs = (us16 *)c->d_xs, *ws = (us16 *)c->d_ws;
     const long long nx = Cpad * (Npad / 8), nwt = (long long)d.n_freq * Rpad * (Npad / 8);
     const int NS = ns_sig(c->precision);
-    if (NS == 2) {
-      hipLaunchKernelGGL(k_split_x<2>, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, c->stream, (const float2 *)x, Ccols,
-                         d.n_aux, Cpad, Npad, xs);
-      hipLaunchKernelGGL(k_split_w<2>, dim3((unsigned)((nwt + 255) / 256)), dim3(256), 0, c->stream, (const float2 *)Wc,
-                         d.n_aux, Npad, Rpad, d.n_freq, ws);
+    const bool H = split_h(c->precision);
+    const float2 *xf = (const float2 *)x, *Wf = (const float2 *)Wc;
+    const dim3 gx((unsigned)((nx + 255) / 256)), gw((unsigned)((nwt + 255) / 256));
+    if (H) {
+      // per-frequency largest |W^c| for the FP16 scales
+      LRIGW_TRY(zero_fill(c->stream, c->d_wmax, (size_t)d.n_freq * sizeof(unsigned)));
+      const long long nn = (long long)d.n_aux * d.n_aux;
+      const unsigned nb = (unsigned)std::min<long long>((nn + 4095) / 4096, 64);
+      hipLaunchKernelGGL(k_absmax_sets, dim3(nb, d.n_freq), dim3(256), 0, c->stream, Wf, nn, c->d_wmax);
+      hipLaunchKernelGGL(k_split_x_h<2>, dim3((unsigned)(Cpad / 4)), dim3(256), 0, c->stream, xf, Ccols, d.n_aux, Cpad, Npad,
+                         xs, c->d_sx);
+      hipLaunchKernelGGL((k_split_w<2, true>), gw, dim3(256), 0, c->stream, Wf, d.n_aux, Npad, Rpad, d.n_freq, c->d_wmax, ws);
+    } else if (NS == 2) {
+      hipLaunchKernelGGL(k_split_x<2>, gx, dim3(256), 0, c->stream, xf, Ccols, d.n_aux, Cpad, Npad, xs);
+      hipLaunchKernelGGL((k_split_w<2, false>), gw, dim3(256), 0, c->stream, Wf, d.n_aux, Npad, Rpad, d.n_freq, nullptr, ws);
     } else {
-      hipLaunchKernelGGL(k_split_x<3>, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, c->stream, (const float2 *)x, Ccols,
-                         d.n_aux, Cpad, Npad, xs);
-      hipLaunchKernelGGL(k_split_w<3>, dim3((unsigned)((nwt + 255) / 256)), dim3(256), 0, c->stream, (const float2 *)Wc,
-                         d.n_aux, Npad, Rpad, d.n_freq, ws);
+      hipLaunchKernelGGL(k_split_x<3>, gx, dim3(256), 0, c->stream, xf, Ccols, d.n_aux, Cpad, Npad, xs);
+      hipLaunchKernelGGL((k_split_w<3, false>), gw, dim3(256), 0, c->stream, Wf, d.n_aux, Npad, Rpad, d.n_freq, nullptr, ws);
     }
     stage_end(c, "sigma_split", ev);
     stage_begin(c, "sigma_mfma", &ev);
     const int var = c->sig_var;
     const int snw = sigma_variant_snw(var);
-#define SIG_ARGS xs, ws, (const float2 *)x, (const float2 *)Wc, Ccols, Cpad, d.n_aux, Npad, Rpad, d.n_freq, (double *)c->d_X
     dim3 gs(xcd_grid((d.n_freq + snw - 1) / snw, ncb));
-    if (NS == 2) {
-      if (var == 0) hipLaunchKernelGGL((k_sigma_bf16<2, 1, true>), gs, dim3(256), 0, c->stream, SIG_ARGS);
-      else if (var == 1) hipLaunchKernelGGL((k_sigma_bf16<2, 2, false>), gs, dim3(256), 0, c->stream, SIG_ARGS);
-      else if (var == 2) hipLaunchKernelGGL((k_sigma_bf16<2, 1, false>), gs, dim3(256), 0, c->stream, SIG_ARGS);
-      else if (var == 3) hipLaunchKernelGGL((k_sigma_bf16q<2, true>), gs, dim3(256), 0, c->stream, SIG_ARGS);
-      else if (var == 4) hipLaunchKernelGGL((k_sigma_bf16q<2, false>), gs, dim3(256), 0, c->stream, SIG_ARGS);
-      else if (var == 5) hipLaunchKernelGGL((k_sigma_bf16<2, 1, true, 16>), gs, dim3(256), 0, c->stream, SIG_ARGS);
-      else hipLaunchKernelGGL((k_sigma_bf16<2, 1, true, 24>), gs, dim3(256), 0, c->stream, SIG_ARGS);
-    } else {
-      if (var == 0) hipLaunchKernelGGL((k_sigma_bf16<3, 1, true>), gs, dim3(256), 0, c->stream, SIG_ARGS);
-      else if (var == 1) hipLaunchKernelGGL((k_sigma_bf16<3, 2, false>), gs, dim3(256), 0, c->stream, SIG_ARGS);
-      else if (var == 2) hipLaunchKernelGGL((k_sigma_bf16<3, 1, false>), gs, dim3(256), 0, c->stream, SIG_ARGS);
-      else if (var == 3) hipLaunchKernelGGL((k_sigma_bf16q<3, true>), gs, dim3(256), 0, c->stream, SIG_ARGS);
-      else if (var == 4) hipLaunchKernelGGL((k_sigma_bf16q<3, false>), gs, dim3(256), 0, c->stream, SIG_ARGS);
-      else if (var == 5) hipLaunchKernelGGL((k_sigma_bf16<3, 1, true, 16>), gs, dim3(256), 0, c->stream, SIG_ARGS);
-      else hipLaunchKernelGGL((k_sigma_bf16<3, 1, true, 24>), gs, dim3(256), 0, c->stream, SIG_ARGS);
-    }
-#undef SIG_ARGS
+    if (H)
+      launch_sigma_split<2, true>(var, gs, c->stream, xs, ws, xf, Wf, Ccols, Cpad, d.n_aux, Npad, Rpad, d.n_freq, c->d_sx,
+                                  c->d_wmax, (double *)c->d_X);
+    else if (NS == 2)
+      launch_sigma_split<2, false>(var, gs, c->stream, xs, ws, xf, Wf, Ccols, Cpad, d.n_aux, Npad, Rpad, d.n_freq, nullptr,
+                                   nullptr, (double *)c->d_X);
+    else
+      launch_sigma_split<3, false>(var, gs, c->stream, xs, ws, xf, Wf, Ccols, Cpad, d.n_aux, Npad, Rpad, d.n_freq, nullptr,
+                                   nullptr, (double *)c->d_X);
   }
   stage_end(c, "sigma_mfma", ev);
   LRIGW_TRY(lrigw_launch_check("sigma_mfma"));

@@ -94,9 +94,12 @@ struct lrigw_ctx {
   int *d_info = nullptr;         // device status words
   void *d_bhat = nullptr;        // q = 0 modified B (T)
   void *d_ap = nullptr;          // split-BF16 forms: BF16 parts of B, [NS][2][Npad][Kp] (k contiguous)
-  void *d_bt = nullptr;          // split-BF16 forms: B transposed, FP32 [Npad][Kp]
-  void *d_xs = nullptr;          // split-BF16 forms: BF16 parts of conj(x), [NS][2][Cpad][Npad]
-  void *d_ws = nullptr;          // split-BF16 forms: BF16 parts of lower W^c, [N_w][NS][2][Rpad][Npad]
+  void *d_bt = nullptr;          // split forms: B transposed (FP16 split: row-scaled), FP32 [Npad][Kp]
+  void *d_xs = nullptr;          // split forms: 16-bit parts of conj(x), [NS][2][Cpad][Npad]
+  void *d_ws = nullptr;          // split forms: 16-bit parts of lower W^c, [N_w][NS][2][Rpad][Npad]
+  float *d_sx = nullptr;         // FP16 split: power-of-two scale of each x column [Cpad]
+  unsigned *d_wmax = nullptr;    // FP16 split: largest |W^c(w)| as float bits [N_w]
+  unsigned *d_amax = nullptr;    // FP16 split: largest |B| of each auxiliary row as float bits [Rpad]
 
   // q = 0 data
   double2 *d_x1 = nullptr;       // [N_aux]
@@ -130,11 +133,17 @@ struct lrigw_ctx {
 size_t lrigw_csize(const lrigw_ctx *c);   // bytes of one complex T
 // BF16 parts of the response / self-energy operands (0: not a split form)
 inline int ns_chi(int precision) {
-  return (precision == LRIGW_SPLIT_BF16 || precision == LRIGW_SPLIT_MIXED) ? 2 : precision == LRIGW_SPLIT3_BF16 ? 3 : 0;
+  return (precision == LRIGW_SPLIT_BF16 || precision == LRIGW_SPLIT_MIXED || precision == LRIGW_SPLIT_F16) ? 2
+         : precision == LRIGW_SPLIT3_BF16                                                                 ? 3
+                                                                                                          : 0;
 }
 inline int ns_sig(int precision) {
-  return precision == LRIGW_SPLIT_BF16 ? 2 : (precision == LRIGW_SPLIT3_BF16 || precision == LRIGW_SPLIT_MIXED) ? 3 : 0;
+  return (precision == LRIGW_SPLIT_BF16 || precision == LRIGW_SPLIT_F16)        ? 2
+         : (precision == LRIGW_SPLIT3_BF16 || precision == LRIGW_SPLIT_MIXED) ? 3
+                                                                             : 0;
 }
+// split parts are FP16 (scaled) rather than BF16
+inline bool split_h(int precision) { return precision == LRIGW_SPLIT_F16; }
 long long lrigw_K(const lrigw_ctx *c);    // N_k * n_occ * n_unocc
 
 // stage timing helpers (no-ops unless timing is on)

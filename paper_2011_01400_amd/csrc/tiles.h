@@ -35,6 +35,57 @@ template <> struct Mfma<double> {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 __device__ inline f4v mfma_bf16(bf16x8 a, bf16x8 b, f4v c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
 
+// Split operands travel as 16-bit patterns (us16, eight to a u32x4 register
+// quad); H selects what they mean: false = BF16 (8-bit significand, FP32
+// range), true = FP16 (11-bit significand, range 2^-24 .. 65504, used with a
+// power-of-two scale that puts the largest magnitude just below 2^15).  The
+// FP16 16x16x32 MFMA has the BF16 operand and output layout.
+typedef unsigned short us16;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+template <bool H>
+__device__ inline f4v mfma_p(u32x4 a, u32x4 b, f4v c) {
+  if constexpr (H)
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// v = sum of NS parts, each the round-to-nearest-even value of what the
+// previous parts left
+template <int NS, bool H>
+__device__ inline void split_n(float v, us16 *out) {
+  float r = v;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    if constexpr (H) {
+      const _Float16 h = (_Float16)r;
+      out[i] = __builtin_bit_cast(us16, h);
+      r -= (float)h;
+    } else {
+      const __bf16 h = (__bf16)r;
+      out[i] = __builtin_bit_cast(us16, h);
+      r -= (float)h;
+    }
+  }
+}
+
+// Power-of-two scale for a block whose largest magnitude is m: m / scale <
+// 2^15 (m = 0 or not finite: 1).  inv_pow2_scale is its exact reciprocal.
+__device__ inline float pow2_scale(float m) {
+  if (!(m > 0.f) || !(m < INFINITY)) return 1.f;
+  int e;
+  frexpf(m, &e);   // m < 2^e
+  return ldexpf(1.f, e - 15);
+}
+__device__ inline float inv_pow2_scale(float m) {
+  if (!(m > 0.f) || !(m < INFINITY)) return 1.f;
+  int e;
+  frexpf(m, &e);
+  return ldexpf(1.f, 15 - e);
+}
+
 // x = hi + lo with hi = bf16(x), lo = bf16(x - hi)
 __device__ inline void split_bf16(float x, __bf16 &hi, __bf16 &lo) {
   hi = (__bf16)x;

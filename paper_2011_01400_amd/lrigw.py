@@ -24,9 +24,9 @@ LRIGW_ERR_NOCONV = -5
 LRIGW_WARN_QP_NOCONV = 1
 LRIGW_WARN_PADE_TRUNC = 2
 
-FP64, FP32, SPLIT_BF16, SPLIT3_BF16, SPLIT_MIXED = 0, 1, 2, 3, 4
+FP64, FP32, SPLIT_BF16, SPLIT3_BF16, SPLIT_MIXED, SPLIT_F16 = 0, 1, 2, 3, 4, 5
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "split_bf16": SPLIT_BF16, "split3_bf16": SPLIT3_BF16,
-              "split_mixed": SPLIT_MIXED}
+              "split_mixed": SPLIT_MIXED, "split_f16": SPLIT_F16}
 
 # every symbol include/lrigw.h declares
 EXPORTS = ["lrigw_create", "lrigw_destroy", "lrigw_strerror", "lrigw_get_sizes", "lrigw_grids", "lrigw_lri_ft",
@@ -37,7 +37,7 @@ EXPORTS = ["lrigw_create", "lrigw_destroy", "lrigw_strerror", "lrigw_get_sizes",
            "lrigw_surrogate_forward", "lrigw_surrogate_grad", "lrigw_surrogate_train", "lrigw_chi0_surrogate",
            "lrigw_set_surrogate", "lrigw_surrogate_stats", "lrigw_surrogate_reset_stats",
            "lrigw_batch_create", "lrigw_batch_run", "lrigw_batch_status", "lrigw_batch_tuning",
-           "lrigw_batch_graph_nodes", "lrigw_batch_destroy", "lrigw_tune"]
+           "lrigw_batch_graph_nodes", "lrigw_batch_destroy", "lrigw_tune", "lrigw_set_tiles"]
 
 
 class LrigwSystem(ctypes.Structure):
@@ -124,6 +124,7 @@ def load(path: Optional[str] = None):
         "lrigw_batch_graph_nodes": (i, [vp, llp]),
         "lrigw_batch_destroy": (i, [vp]),
         "lrigw_tune": (i, [vp, vp, vp, vp, ip, ip, ip, dp]),
+        "lrigw_set_tiles": (i, [vp, i, i, i, i]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -273,6 +274,9 @@ class Context:
         self._check(self.lib.lrigw_tune(self.h, _ptr(H), _ptr(evec), _ptr(eig), ctypes.byref(nw), ctypes.byref(sp),
                                         ctypes.byref(sv), ctypes.byref(ms)), "lrigw_tune")
         return nw.value, sp.value, sv.value, ms.value
+
+    def set_tiles(self, nw, splits, pad, sigma_variant):
+        self._check(self.lib.lrigw_set_tiles(self.h, int(nw), int(splits), int(pad), int(sigma_variant)), "lrigw_set_tiles")
 
     def chi0_surrogate(self, sg, iq, M, eig, chi_out, threshold, apply_gamma=False):
         self._check(self.lib.lrigw_chi0_surrogate(self.h, sg.h, int(iq), _ptr(M), _ptr(eig), int(bool(apply_gamma)),

@@ -23,8 +23,8 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY_BYTES = 1 << 30          # calibration copy: 1 GiB read + 1 GiB written
 # the main kernel of each stage (all its variants) and its source file
-FAMILIES = {"sigma_mfma": (("k_sigma_bf16", "k_sigma_bf16q", "k_sigma_mfma"), "k_sigma.hip"),
-            "chi0_mfma": (("k_chi0_bf16", "k_chi0_mfma"), "k_chi0.hip")}
+FAMILIES = {"sigma_mfma": (("k_sigma_split", "k_sigma_splitq", "k_sigma_mfma"), "k_sigma.hip"),
+            "chi0_mfma": (("k_chi0_split", "k_chi0_mfma"), "k_chi0.hip")}
 
 
 def run(precision: str, config: int, q: int):
@@ -123,7 +123,7 @@ def summarize(fetch_dir, write_dir, precision, config, out_path):
 
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
-    ap.add_argument("--precision", default="split_mixed")
+    ap.add_argument("--precision", default="split_f16")
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--q", type=int, default=1)
     ap.add_argument("--summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))

@@ -32,7 +32,8 @@ def relf(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("split3_bf16", 1e-5), ("split_bf16", 1e-5)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("split3_bf16", 1e-5), ("split_bf16", 1e-5),
+                                           ("split_f16", 1e-5)])
 def test_sampled_q(c2, precision, tol):
     L, s, dev, g = c2["L"], c2["s"], c2["dev"], c2["g"]
     print(f"[gpu c2] sampled q, {precision}", flush=True)
@@ -73,11 +74,11 @@ def test_full_pass_forms_agree(c2):
     energies of quasiparticle-like solutions (0.5 <= Z <= 1; Z near 0 marks a
     root next to a pole of the continued fraction, where the continuation is
     ill-conditioned) agree within 1 meV for the FP32, three-part and mixed BF16
-    forms and within 3 meV for the two-part BF16 form."""
+    and two-part FP16 forms and within 3 meV for the two-part BF16 form."""
     L, s, dev = c2["L"], c2["s"], c2["dev"]
     sp = s.spec
     out = {}
-    for precision in ("fp64", "fp32", "split3_bf16", "split_mixed", "split_bf16"):
+    for precision in ("fp64", "fp32", "split3_bf16", "split_mixed", "split_f16", "split_bf16"):
         print(f"[gpu c2] full pass {precision}", flush=True)
         ctx = L.Context.from_system(s, precision=precision)
         H = ctx.empty("H")
@@ -92,7 +93,8 @@ def test_full_pass_forms_agree(c2):
     assert np.all(np.isfinite(s64)) and np.all(np.isfinite(e64))
     reg = (z64 >= 0.5) & (z64 <= 1.0)
     assert reg.mean() > 0.9
-    for precision, bound in (("fp32", 1.0), ("split3_bf16", 1.0), ("split_mixed", 1.0), ("split_bf16", 3.0)):
+    for precision, bound in (("fp32", 1.0), ("split3_bf16", 1.0), ("split_mixed", 1.0), ("split_f16", 1.0),
+                             ("split_bf16", 3.0)):
         sg, e, z = out[precision]
         d = np.abs(e - e64) * HA_MEV
         print(f"  {precision} vs fp64: max|dSigma| = {np.max(np.abs(sg - s64)):.3e} Ha, QP max {d.max():.3f} meV, "

@@ -82,7 +82,7 @@ def test_build_M(case, precision, tol):
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("split_bf16", 1e-5), ("split3_bf16", 1e-5),
-                                         ("split_mixed", 1e-5)])
+                                         ("split_mixed", 1e-5), ("split_f16", 1e-5)])
 def test_chi0_and_screen(case, precision, tol):
     s, o, dev = case["sys"], case["o"], case["dev"]
     ctx = _ctx(case, precision)
@@ -116,7 +116,8 @@ def test_chi0_and_screen(case, precision, tol):
 
 
 @pytest.mark.parametrize("precision,tol_s,tol_mev", [("fp64", 1e-9, 1e-5), ("fp32", 2e-5, 10.0), ("split3_bf16", 2e-5, 10.0),
-                                                      ("split_bf16", 2e-4, 30.0), ("split_mixed", 2e-4, 30.0)])
+                                                      ("split_bf16", 2e-4, 30.0), ("split_mixed", 2e-4, 30.0),
+                                                      ("split_f16", 2e-5, 10.0)])
 def test_g0w0_end_to_end(case, precision, tol_s, tol_mev):
     s, o, dev = case["sys"], case["o"], case["dev"]
     ctx = _ctx(case, precision)
@@ -167,3 +168,42 @@ def test_sigma_c_accumulates_per_q(case):
     # accumulating twice doubles it
     ctx.sigma_c(q, x, W, dev["eig"], sig)
     assert np.max(np.abs(sig.cpu().numpy() - 2 * ref)) < 2e-10 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("precision", ["split_bf16", "split3_bf16", "split_f16"])
+def test_every_tile_variant(case, precision):
+    """Each tile choice the tuner may pick (response: frequencies per workgroup
+    x LDS padding; self-energy: every variant) gives the oracle's
+    chi0 and Sigma^c contribution within the form's tolerance."""
+    if case["name"] != "ragged":
+        pytest.skip("one cell suffices")
+    s, o, dev = case["sys"], case["o"], case["dev"]
+    L = case["L"]
+    ctx = _ctx(case, precision)
+    H = ctx.empty("H")
+    ctx.lri_ft(dev["lri"], s.R, dev["evec"], H)
+    M, x, chi, W = ctx.empty("M"), ctx.empty("x"), ctx.empty("W"), ctx.empty("W")
+    q = 1
+    ctx.build_M(q, 0, H, dev["evec"], M)
+    ctx.build_M(q, 1, H, dev["evec"], x)
+    ref_chi = o.chi0(q)
+    ref_w = o.wc(q, chi=ref_chi)
+    sq_ref, _ = o.sigma_q(q, ref_w)
+    n = s.n_aux
+    sp = s.spec
+    nw_choices = (4, 2)
+    for var in range(7):
+        # the partial-tile buffer of this small cell holds one K split
+        nw, pad, splits = nw_choices[var % 2], (8, 16)[(var // 2) % 2], 1
+        ctx.set_tiles(nw, splits, pad, var)
+        ctx.chi0(q, M, dev["eig"], chi)
+        c = chi.cpu().numpy().reshape(-1, n, n)
+        ec = relf(c, ref_chi)
+        # W^c from the oracle (complex64) isolates the self-energy kernel
+        W.copy_(torch.from_numpy(ref_w.reshape(-1)).to(device="cuda", dtype=W.dtype))
+        sg = torch.zeros((s.n_k, sp.n_qp, sp.n_freq), dtype=torch.complex128, device="cuda")
+        ctx.sigma_c(q, x, W, dev["eig"], sg)
+        es = np.abs(sg.cpu().numpy() - sq_ref).max() / np.abs(sq_ref).max()
+        print(f"  {precision} variant {var} (nw {nw}, pad {pad}, splits {splits}): chi0 rel {ec:.2e}, sigma rel {es:.2e}",
+              flush=True)
+        assert ec < 1e-5 and es < 2e-5, var
