@@ -308,10 +308,10 @@ int lrigw_batch_destroy(lrigw_batch *b);
  * cell): times the response kernel on one q over its tile choices
  * (frequencies per workgroup, K splits, LDS row padding) and, in the split
  * forms, the self-energy kernel over its variants (frequencies per workgroup,
- * W prefetch, wave tile, LDS row padding), and keeps the fastest for the
- * context's later calls.
+ * W prefetch, wave tile, LDS row padding, x tile resident in LDS), and keeps
+ * the fastest for the context's later calls.
  * H, evec, eig as lrigw_g0w0.  Outputs (host, may be NULL): the chosen
- * response tiles, the self-energy variant (0..6) and the response time of one
+ * response tiles, the self-energy variant (0..8) and the response time of one
  * q (ms).
  * Synchronous. */
 int lrigw_tune(lrigw_ctx *ctx, const void *H, const void *evec, const double *eig, int *nw, int *splits,
@@ -321,8 +321,11 @@ int lrigw_tune(lrigw_ctx *ctx, const void *H, const void *evec, const double *ei
  * response workgroup (the form's default or its alternative: 4/2 in the FP32
  * and split forms, 2/1 in FP64), splits = K splits (the partial-tile buffer
  * must hold them), pad = LDS row padding of the split-form response kernel (8
- * or 16), sigma_variant = split-form self-energy kernel variant (0..6).
- * Errors: ERR_ARG for a choice outside these sets. */
+ * or 16), sigma_variant = split-form self-energy kernel variant (0..8; 7 and 8,
+ * the resident-tile form, need the two-part FP16 split, N_aux <= 288 and at
+ * most 32 frequencies).
+ * Errors: ERR_ARG for a choice outside these sets or a variant the cell does
+ * not admit. */
 int lrigw_set_tiles(lrigw_ctx *ctx, int nw, int splits, int pad, int sigma_variant);
 
 /* Per-kernel device time (ms, HIP events on the context stream) accumulated

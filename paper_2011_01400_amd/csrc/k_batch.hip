@@ -99,6 +99,7 @@ static int autotune_chi0(lrigw_ctx *c, const lrigw_batch_cell &cell, int *nw_out
     double sbest = INFINITY;
     int bvar = c->sig_var;
     for (int var = 0; var < sigma_variants(); ++var) {
+      if (!sigma_variant_ok(c, var)) continue;
       c->sig_var = var;
       int rc = run_sigma_c(c, q, c->d_x, c->d_wc, cell.eig, sg);
       float t = INFINITY;
@@ -260,7 +261,7 @@ int lrigw_set_tiles(lrigw_ctx *c, int nw, int splits, int pad, int sigma_variant
   const int dnw = chi0_default_nw(c->precision), anw = chi0_alt_nw(c->precision);
   if (nw != dnw && nw != anw) return LRIGW_ERR_ARG;
   if (pad != 8 && pad != 16) return LRIGW_ERR_ARG;
-  if (sigma_variant < 0 || sigma_variant >= sigma_variants()) return LRIGW_ERR_ARG;
+  if (!sigma_variant_ok(c, sigma_variant)) return LRIGW_ERR_ARG;
   const Dims &d = c->d;
   const int nt = (d.n_aux + 63) / 64;
   const size_t per = (size_t)d.n_freq * ((size_t)nt * (nt + 1) / 2) * 64 * 64 * lrigw_csize(c);

@@ -151,6 +151,7 @@ int run_grids(lrigw_ctx *c) {
     LRIGW_HIP_TRY(hipMalloc(&c->d_sx, (size_t)Cpad * sizeof(float)));
     LRIGW_HIP_TRY(hipMalloc(&c->d_wmax, (size_t)d.n_freq * sizeof(unsigned)));
     LRIGW_HIP_TRY(hipMalloc(&c->d_amax, (size_t)Rpad * sizeof(unsigned)));
+    LRIGW_TRY(sigma_res_prepare(c));
   }
   return LRIGW_OK;
 }

@@ -8,6 +8,7 @@
 // reduction over mu finishes inside the workgroup (no atomics).  A second
 // kernel contracts X with the folded frequency kernel in FP64.
 #include <algorithm>
+#include <vector>
 #include <cmath>
 
 #include "lrigw_internal.h"
@@ -311,6 +312,11 @@ __global__ void k_split_w(const float2 *__restrict__ W, int N, int Npad, int Rpa
 }
 
 __device__ inline u32x4 neg_p(u32x4 v) { return v ^ 0x80008000u; }   // both formats keep the sign in bit 15
+template <bool H>
+__device__ inline float part_f(us16 v) {
+  if constexpr (H) return (float)__builtin_bit_cast(_Float16, v);
+  else return (float)__builtin_bit_cast(__bf16, v);
+}
 
 template <int NS, int SNW, bool PF, int PAD, bool H>
 __global__ __launch_bounds__(256) void k_sigma_split(const us16 *__restrict__ xs, const us16 *__restrict__ ws,
@@ -627,6 +633,229 @@ __global__ __launch_bounds__(256) void k_sigma_splitq(const us16 *__restrict__ x
   }
 }
 
+// Resident-tile form (two-part FP16 split, N_aux <= RES_NPAD): one workgroup of NWV
+// waves (8: two per SIMD; 4: one per SIMD with the whole register file) per
+// (64 columns, set of F <= RES_F frequencies), the set chosen by the XCD the
+// workgroup runs on.  The split x tile of its columns, every nu, is loaded into
+// LDS once; then NWV/F' waves (F' = F rounded up to 1, 2 or 4) share each
+// frequency, each working through its own list of 32-row tiles (a balanced
+// static assignment built on the host) with its W fragments read one chunk
+// ahead from L2, with no barrier until the final reduction.  The per-wave sums
+// over mu are reduced through LDS in a fixed order.  items[w * (RES_MAXI + 1)]
+// = number of tiles of wave w, then the tiles.
+#define RES_NPAD 288
+#define RES_F 4
+#define RES_MAXI 15
+
+template <int PAD, bool H, int NWV>
+__global__ __launch_bounds__(64 * NWV) void k_sigma_res(const us16 *__restrict__ xs, const us16 *__restrict__ ws,
+                                                   const float2 *__restrict__ x, const float2 *__restrict__ Wall,
+                                                   long long Ccols, long long Cpad, int N, int Npad, int Rpad, int n_freq,
+                                                   int F, const int *__restrict__ items, const float *__restrict__ sx,
+                                                   const unsigned *__restrict__ wmax, double *__restrict__ Xall) {
+  __shared__ __attribute__((aligned(16))) us16 Xs[4][TILE][RES_NPAD + PAD];   // [part*2 + re/im][column][nu]
+  const int fs = blockIdx.x & 7;
+  const long long c0 = (long long)(blockIdx.x >> 3) * TILE;
+  const int f0 = fs * F;
+  if (f0 >= n_freq) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, g = lane >> 4;
+  const int fpad = F <= 1 ? 1 : F <= 2 ? 2 : 4;
+  const int wpf = NWV / fpad;               // waves per frequency
+  const int fl = wave / wpf;
+  const int w = f0 + fl;
+  const int g8 = Npad / 8;
+  {
+    // every load of the tile in flight before the first LDS store
+    constexpr int PER = 4 * TILE * (RES_NPAD / 8) / (64 * NWV);
+    u32x4 v[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int e = tid + k * 64 * NWV;
+      const int pr = e / (TILE * g8), rem = e % (TILE * g8), cl = rem / g8, k8 = rem % g8;
+      if (e < 4 * TILE * g8) v[k] = *(const u32x4 *)(xs + ((long long)pr * Cpad + c0 + cl) * Npad + 8 * k8);
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int e = tid + k * 64 * NWV;
+      const int pr = e / (TILE * g8), rem = e % (TILE * g8), cl = rem / g8, k8 = rem % g8;
+      if (e < 4 * TILE * g8) *(u32x4 *)&Xs[pr][cl][8 * k8] = v[k];
+    }
+  }
+  __syncthreads();
+  const int base = N - Rpad;
+  const long long pst = (long long)Rpad * Npad;
+  const int *it = items + wave * (RES_MAXI + 1);
+  const int nit = (fl < F && w < n_freq) ? it[0] : 0;
+  double psum[4] = {0.0, 0.0, 0.0, 0.0};
+  float fx[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) fx[j] = H ? sx[c0 + 16 * j + col] : 1.f;
+  const float fw = H ? pow2_scale(__uint_as_float(wmax[min(w, n_freq - 1)])) : 1.f;
+  for (int idx = 0; idx < nit; ++idx) {
+    const int t = it[1 + idx];
+    const int r0 = base + 32 * t;
+    const int kcw = (r0 + 31 > 0) ? (r0 + 31 + SKB - 1) / SKB : 0;   // nu < r0 + 31
+    f4v zr[2][4], zi[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) zr[i][j] = zi[i][j] = Mfma<float>::zero();
+    const us16 *wsrc = ws + ((long long)w * 4 * Rpad + 32 * t + col) * Npad + 8 * g;   // row tile i at + 16 i Npad
+    // W fragments of chunk ch into a[i][part*2 + re/im]; the chunk index is
+    // clamped so that every iteration issues the same loads (the two register
+    // sets alternate, so a wait covers only the older set)
+    auto load_a = [&](u32x4 (&a)[2][4], int ch) {
+      const int cc = min(ch, kcw - 1) * SKB;
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int pr = 0; pr < 4; ++pr) a[i][pr] = *(const u32x4 *)(wsrc + pr * pst + 16 * i * Npad + cc);
+    };
+    auto chunk = [&](const u32x4 (&a)[2][4], int ch) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        u32x4 br[2], bi[2];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          br[p] = *(const u32x4 *)&Xs[2 * p][16 * j + col][ch * SKB + 8 * g];
+          bi[p] = *(const u32x4 *)&Xs[2 * p + 1][16 * j + col][ch * SKB + 8 * g];
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          // Z += W u: re = Wr ur - Wi ui, im = Wr ui + Wi ur; parts p + q < 2
+#pragma unroll
+          for (int p = 0; p < 2; ++p) {
+            const u32x4 ar = a[i][2 * p], ai = a[i][2 * p + 1], nai = neg_p(ai);
+#pragma unroll
+            for (int q = 0; q + p < 2; ++q) {
+              zr[i][j] = mfma_p<H>(ar, br[q], zr[i][j]);
+              zr[i][j] = mfma_p<H>(nai, bi[q], zr[i][j]);
+              zi[i][j] = mfma_p<H>(ar, bi[q], zi[i][j]);
+              zi[i][j] = mfma_p<H>(ai, br[q], zi[i][j]);
+            }
+          }
+        }
+      }
+    };
+    if (kcw > 0) {
+      // an odd first chunk is taken alone, so the paired loop has no branch
+      // (a conditional second half would pull its loads in behind the branch)
+      u32x4 a0[2][4], a1[2][4];
+      int ch = kcw & 1;
+      if (ch) load_a(a1, 0);
+      load_a(a0, ch);
+      if (ch) chunk(a1, 0);
+      // the scheduling barriers keep each prefetch ahead of the chunk it
+      // overlaps (the scheduler would otherwise sink the loads to their use)
+      for (; ch < kcw; ch += 2) {
+        load_a(a1, ch + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        chunk(a0, ch);
+        load_a(a0, ch + 2);
+        __builtin_amdgcn_sched_barrier(0);
+        chunk(a1, ch + 1);
+      }
+    }
+    // X_c += 2 Re(x_mu Z_mu) + Re W_mumu |x_mu|^2 over the tile's rows, with
+    // x_mu from the resident tile (the sum of its parts: the same x as in Z),
+    // in units of the column scale
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int mu = r0 + 16 * i + Mfma<float>::row(lane, q);
+        if (mu < 0 || mu >= N) continue;
+        const double wdd = (double)Wall[((long long)w * N + mu) * N + mu].x;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int cl = 16 * j + col;
+          // the tile holds conj(x) / sx
+          const double xr = (double)(part_f<H>(Xs[0][cl][mu]) + part_f<H>(Xs[2][cl][mu]));
+          const double xi = -(double)(part_f<H>(Xs[1][cl][mu]) + part_f<H>(Xs[3][cl][mu]));
+          psum[j] += 2.0 * (double)fw * (xr * (double)zr[i][j][q] - xi * (double)zi[i][j][q]) + wdd * (xr * xr + xi * xi);
+        }
+      }
+  }
+  // x = sx x' and Z = sW sx Z': both terms carry sx^2
+#pragma unroll
+  for (int j = 0; j < 4; ++j) psum[j] *= (double)fx[j] * (double)fx[j];
+  // lanes l, l^16, l^32, l^48 hold the same column
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    double v = psum[j];
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    psum[j] = v;
+  }
+  __syncthreads();   // the x tile is no longer read: its space takes the partial sums
+  double *red = (double *)&Xs[0][0][0];   // [wave][column]
+  if (lane < 16) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[wave * TILE + 16 * j + lane] = psum[j];
+  }
+  __syncthreads();
+  const int nf = min(F, n_freq - f0);
+  if (tid < nf * TILE) {
+    const int f = tid / TILE, cl = tid % TILE;
+    double sum = 0.0;
+    for (int v = 0; v < wpf; ++v) sum += red[(f * wpf + v) * TILE + cl];
+    const long long cc = c0 + cl;
+    if (cc < Ccols) Xall[(long long)(f0 + f) * Ccols + cc] = sum;
+  }
+}
+
+// Tile lists of the resident-tile form: the 32-row tiles with work are shared
+// by the NWV/F' waves of a frequency, largest first to the least loaded wave
+// (cost = number of nu chunks); every frequency slot gets the same lists.
+static bool sigma_res_plan(int N, int n_freq, int NWV, std::vector<int> &table, int &F) {
+  const int Npad = (N + SKB - 1) / SKB * SKB, Rpad = (N + TILE - 1) / TILE * TILE;
+  F = (n_freq + 7) / 8;
+  if (Npad > RES_NPAD || F > RES_F) return false;
+  const int fpad = F <= 1 ? 1 : F <= 2 ? 2 : 4;
+  const int wpf = NWV / fpad;
+  const int base = N - Rpad;
+  std::vector<std::pair<int, int>> its;   // (cost, tile)
+  for (int t = 0; t < Rpad / 32; ++t) {
+    const int r0 = base + 32 * t;
+    const int kcw = (r0 + 31 > 0) ? (r0 + 31 + SKB - 1) / SKB : 0;
+    if (kcw > 0) its.push_back({kcw, t});
+  }
+  std::stable_sort(its.begin(), its.end(), [](const std::pair<int, int> &a, const std::pair<int, int> &b) { return a.first > b.first; });
+  std::vector<std::vector<int>> lists(wpf);
+  std::vector<int> load(wpf, 0);
+  for (const auto &pr : its) {
+    int wv = 0;
+    for (int v = 1; v < wpf; ++v)
+      if (load[v] < load[wv]) wv = v;
+    load[wv] += pr.first;
+    lists[wv].push_back(pr.second);
+  }
+  table.assign(NWV * (RES_MAXI + 1), 0);
+  for (int wave = 0; wave < NWV; ++wave) {
+    const std::vector<int> &l = lists[wave % wpf];
+    if ((int)l.size() > RES_MAXI) return false;
+    table[wave * (RES_MAXI + 1)] = (int)l.size();
+    for (size_t i = 0; i < l.size(); ++i) table[wave * (RES_MAXI + 1) + 1 + i] = l[i];
+  }
+  return true;
+}
+
+int sigma_res_prepare(lrigw_ctx *c) {
+  c->sig_res_ok = false;
+  // the epilogue takes x from the split tile: 22 significand bits with FP16
+  // parts, too few with BF16 ones
+  if (ns_sig(c->precision) != 2 || !split_h(c->precision)) return LRIGW_OK;
+  std::vector<int> t8, t4;
+  int F = 0;
+  if (!sigma_res_plan(c->d.n_aux, c->d.n_freq, 8, t8, F) || !sigma_res_plan(c->d.n_aux, c->d.n_freq, 4, t4, F)) return LRIGW_OK;
+  t8.insert(t8.end(), t4.begin(), t4.end());   // the 8-wave lists, then the 4-wave ones
+  LRIGW_HIP_TRY(hipMalloc(&c->d_sitems, t8.size() * sizeof(int)));
+  LRIGW_HIP_TRY(hipMemcpy(c->d_sitems, t8.data(), t8.size() * sizeof(int), hipMemcpyHostToDevice));
+  c->sig_res_F = F;
+  c->sig_res_ok = true;
+  return LRIGW_OK;
+}
+
 // sigma[k][n][i] += scale * sum_m sum_j g_j X[j][k][n][m] a/(a^2 + w_j^2),  a = i w_i + mu - e_m(k-q)
 __global__ void k_sigma_freq(const double *__restrict__ X, const double *__restrict__ eig, const int *__restrict__ kmq, int iq,
                              int nk, int n_qp, int n_bands, int n_freq, const double *__restrict__ omega,
@@ -664,12 +893,17 @@ __global__ void k_sigma_freq(const double *__restrict__ X, const double *__restr
 
 // split kernel variants the tuner chooses from: (frequencies per workgroup,
 // W prefetched one chunk ahead, wave tile) = (1, yes, 16x64), (2, no, 16x64),
-// (1, no, 16x64), (1, yes, 32x32), (1, no, 32x32), and the first one with LDS
-// rows padded to 96 and 112 bytes instead of 80
-#define SIGMA_VARIANTS 7
+// (1, no, 16x64), (1, yes, 32x32), (1, no, 32x32), the first one with LDS rows
+// padded to 96 and 112 bytes instead of 80, and the resident-tile form with 8
+// and 4 waves per workgroup (two-part FP16 split, N_aux <= 288 only)
+#define SIGMA_VARIANTS 9
 int sigma_variant_snw(int var) { return var == 1 ? 2 : 1; }
 int sigma_variants() { return SIGMA_VARIANTS; }
 int sigma_default_variant(int precision) { return ns_sig(precision) == 2 ? 1 : 0; }
+bool sigma_variant_ok(const lrigw_ctx *c, int var) {
+  if (var < 0 || var >= SIGMA_VARIANTS) return false;
+  return var < 7 || c->sig_res_ok;
+}
 
 template <int NS, bool H>
 static void launch_sigma_split(int var, dim3 gs, hipStream_t st, const us16 *xs, const us16 *ws, const float2 *x,
@@ -733,7 +967,15 @@ int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const doubl
     const int var = c->sig_var;
     const int snw = sigma_variant_snw(var);
     dim3 gs(xcd_grid((d.n_freq + snw - 1) / snw, ncb));
-    if (H)
+    if (var >= 7) {
+      if (!c->sig_res_ok) return LRIGW_ERR_ARG;
+      const dim3 gr((unsigned)(8 * ncb));
+      const int *t8 = c->d_sitems, *t4 = c->d_sitems + 8 * (RES_MAXI + 1);
+#define RES_ARGS xs, ws, xf, Wf, Ccols, Cpad, d.n_aux, Npad, Rpad, d.n_freq, c->sig_res_F
+      if (var == 7) hipLaunchKernelGGL((k_sigma_res<8, true, 8>), gr, dim3(512), 0, c->stream, RES_ARGS, t8, c->d_sx, c->d_wmax, (double *)c->d_X);
+      else hipLaunchKernelGGL((k_sigma_res<8, true, 4>), gr, dim3(256), 0, c->stream, RES_ARGS, t4, c->d_sx, c->d_wmax, (double *)c->d_X);
+#undef RES_ARGS
+    } else if (H)
       launch_sigma_split<2, true>(var, gs, c->stream, xs, ws, xf, Wf, Ccols, Cpad, d.n_aux, Npad, Rpad, d.n_freq, c->d_sx,
                                   c->d_wmax, (double *)c->d_X);
     else if (NS == 2)

@@ -100,6 +100,9 @@ struct lrigw_ctx {
   float *d_sx = nullptr;         // FP16 split: power-of-two scale of each x column [Cpad]
   unsigned *d_wmax = nullptr;    // FP16 split: largest |W^c(w)| as float bits [N_w]
   unsigned *d_amax = nullptr;    // FP16 split: largest |B| of each auxiliary row as float bits [Rpad]
+  int *d_sitems = nullptr;       // resident-tile Sigma^c form: per-wave item lists
+  int sig_res_F = 0;             // resident-tile Sigma^c form: frequencies per workgroup
+  bool sig_res_ok = false;       // resident-tile Sigma^c form applies to this cell
 
   // q = 0 data
   double2 *d_x1 = nullptr;       // [N_aux]
@@ -158,6 +161,8 @@ int chi0_plan_splits(const lrigw_ctx *c, int *splits);
 int chi0_check_gap(lrigw_ctx *c, const double *eig);
 int sigma_variant_snw(int var);
 int sigma_variants();
+bool sigma_variant_ok(const lrigw_ctx *c, int var);
+int sigma_res_prepare(lrigw_ctx *c);
 int sigma_default_variant(int precision);
 int run_lri_ft(lrigw_ctx *c, const double *lri_R, const int *R_list, int nR, const void *evec, void *H_out);
 int run_build_M(lrigw_ctx *c, int iq, int slice, const void *H, const void *evec, void *M_out);

@@ -83,6 +83,9 @@ def test_full_pass_forms_agree(c2):
         ctx = L.Context.from_system(s, precision=precision)
         H = ctx.empty("H")
         ctx.lri_ft(dev["lri"], s.R, dev["evec"], H)
+        if precision != "fp64":
+            # the tile and kernel choices the benchmark runs with
+            print(f"  tuned: {ctx.tune(H, dev['evec'], dev['eig'])}", flush=True)
         sigma = torch.zeros((s.n_k, sp.n_qp, sp.n_freq), dtype=torch.complex128, device="cuda")
         e = torch.zeros((s.n_k, sp.n_qp), dtype=torch.float64, device="cuda")
         z = torch.zeros_like(e)
