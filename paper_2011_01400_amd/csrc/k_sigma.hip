@@ -758,23 +758,28 @@ __global__ __launch_bounds__(64 * NWV) void k_sigma_res(const us16 *__restrict__
     }
     // X_c += 2 Re(x_mu Z_mu) + Re W_mumu |x_mu|^2 over the tile's rows, with
     // x_mu from the resident tile (the sum of its parts: the same x as in Z),
-    // in units of the column scale
+    // in units of the column scale; the tile's eight terms per lane are summed
+    // in FP32 (products of FP32 values), the tiles in FP64
+    float tz[4] = {0.f, 0.f, 0.f, 0.f}, td[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int mu = r0 + 16 * i + Mfma<float>::row(lane, q);
         if (mu < 0 || mu >= N) continue;
-        const double wdd = (double)Wall[((long long)w * N + mu) * N + mu].x;
+        const float wdd = Wall[((long long)w * N + mu) * N + mu].x;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int cl = 16 * j + col;
-          // the tile holds conj(x) / sx
-          const double xr = (double)(part_f<H>(Xs[0][cl][mu]) + part_f<H>(Xs[2][cl][mu]));
-          const double xi = -(double)(part_f<H>(Xs[1][cl][mu]) + part_f<H>(Xs[3][cl][mu]));
-          psum[j] += 2.0 * (double)fw * (xr * (double)zr[i][j][q] - xi * (double)zi[i][j][q]) + wdd * (xr * xr + xi * xi);
+          // the tile holds conj(x) / sx = xr - i xi' with xi' = -Im(x) / sx
+          const float xr = part_f<H>(Xs[0][cl][mu]) + part_f<H>(Xs[2][cl][mu]);
+          const float xc = part_f<H>(Xs[1][cl][mu]) + part_f<H>(Xs[3][cl][mu]);
+          tz[j] = fmaf(xr, zr[i][j][q], fmaf(xc, zi[i][j][q], tz[j]));   // Re(x Z)
+          td[j] = fmaf(wdd, fmaf(xr, xr, xc * xc), td[j]);
         }
       }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) psum[j] += 2.0 * (double)fw * (double)tz[j] + (double)td[j];
   }
   // x = sx x' and Z = sW sx Z': both terms carry sx^2
 #pragma unroll
