@@ -756,18 +756,17 @@ __global__ __launch_bounds__(64 * NWV) void k_sigma_res(const us16 *__restrict__
         chunk(a1, ch + 1);
       }
     }
-    // X_c += 2 Re(x_mu Z_mu) + Re W_mumu |x_mu|^2 over the tile's rows, with
-    // x_mu from the resident tile (the sum of its parts: the same x as in Z),
-    // in units of the column scale; the tile's eight terms per lane are summed
-    // in FP32 (products of FP32 values), the tiles in FP64
-    float tz[4] = {0.f, 0.f, 0.f, 0.f}, td[4] = {0.f, 0.f, 0.f, 0.f};
+    // X_c += 2 Re(x_mu Z_mu) over the tile's rows (the diagonal term is
+    // already in X, from the exact x), with x_mu from the resident tile (the
+    // sum of its parts: the same x as in Z), in units of the column scale; the
+    // tile's eight terms per lane are summed in FP32, the tiles in FP64
+    float tz[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int mu = r0 + 16 * i + Mfma<float>::row(lane, q);
         if (mu < 0 || mu >= N) continue;
-        const float wdd = Wall[((long long)w * N + mu) * N + mu].x;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int cl = 16 * j + col;
@@ -775,13 +774,12 @@ __global__ __launch_bounds__(64 * NWV) void k_sigma_res(const us16 *__restrict__
           const float xr = part_f<H>(Xs[0][cl][mu]) + part_f<H>(Xs[2][cl][mu]);
           const float xc = part_f<H>(Xs[1][cl][mu]) + part_f<H>(Xs[3][cl][mu]);
           tz[j] = fmaf(xr, zr[i][j][q], fmaf(xc, zi[i][j][q], tz[j]));   // Re(x Z)
-          td[j] = fmaf(wdd, fmaf(xr, xr, xc * xc), td[j]);
         }
       }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) psum[j] += 2.0 * (double)fw * (double)tz[j] + (double)td[j];
+    for (int j = 0; j < 4; ++j) psum[j] += 2.0 * (double)fw * (double)tz[j];
   }
-  // x = sx x' and Z = sW sx Z': both terms carry sx^2
+  // x = sx x' and Z = sW sx Z': sx^2
 #pragma unroll
   for (int j = 0; j < 4; ++j) psum[j] *= (double)fx[j] * (double)fx[j];
   // lanes l, l^16, l^32, l^48 hold the same column
@@ -805,8 +803,39 @@ __global__ __launch_bounds__(64 * NWV) void k_sigma_res(const us16 *__restrict__
     double sum = 0.0;
     for (int v = 0; v < wpf; ++v) sum += red[(f * wpf + v) * TILE + cl];
     const long long cc = c0 + cl;
-    if (cc < Ccols) Xall[(long long)(f0 + f) * Ccols + cc] = sum;
+    if (cc < Ccols) Xall[(long long)(f0 + f) * Ccols + cc] += sum;
   }
+}
+
+// The diagonal term of the pair weights, exactly: X[w][c] = sum_mu Re W^c_mumu(w)
+// |x_c^mu|^2 in FP64 from the FP32 x, for the resident-tile form (which adds
+// the off-diagonal part).  wd[mu][w] = Re W^c_mumu(w) (RES_WMAX frequencies
+// per row, zero beyond n_freq); one thread per column c.
+#define RES_WMAX 32
+__global__ void k_wdiag(const float2 *__restrict__ W, int N, int n_freq, float *__restrict__ wd) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * RES_WMAX) return;
+  const int mu = t / RES_WMAX, w = t % RES_WMAX;
+  wd[t] = w < n_freq ? W[((long long)w * N + mu) * N + mu].x : 0.f;
+}
+
+__global__ __launch_bounds__(256) void k_pair_diag(const float2 *__restrict__ x, long long C, int N, int n_freq,
+                                                   const float *__restrict__ wd, double *__restrict__ Xall) {
+  const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (c >= C) return;
+  double acc[RES_WMAX];
+#pragma unroll
+  for (int w = 0; w < RES_WMAX; ++w) acc[w] = 0.0;
+  for (int mu = 0; mu < N; ++mu) {
+    const float2 v = x[c * N + mu];
+    const double a2 = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+    const float *row = wd + mu * RES_WMAX;
+#pragma unroll
+    for (int w = 0; w < RES_WMAX; ++w) acc[w] += (double)row[w] * a2;
+  }
+#pragma unroll
+  for (int w = 0; w < RES_WMAX; ++w)
+    if (w < n_freq) Xall[(long long)w * C + c] = acc[w];
 }
 
 // Tile lists of the resident-tile form: the 32-row tiles with work are shared
@@ -852,7 +881,9 @@ int sigma_res_prepare(lrigw_ctx *c) {
   if (ns_sig(c->precision) != 2 || !split_h(c->precision)) return LRIGW_OK;
   std::vector<int> t8, t4;
   int F = 0;
+  if (c->d.n_freq > RES_WMAX) return LRIGW_OK;
   if (!sigma_res_plan(c->d.n_aux, c->d.n_freq, 8, t8, F) || !sigma_res_plan(c->d.n_aux, c->d.n_freq, 4, t4, F)) return LRIGW_OK;
+  LRIGW_HIP_TRY(hipMalloc(&c->d_wd, (size_t)c->d.n_aux * RES_WMAX * sizeof(float)));
   t8.insert(t8.end(), t4.begin(), t4.end());   // the 8-wave lists, then the 4-wave ones
   LRIGW_HIP_TRY(hipMalloc(&c->d_sitems, t8.size() * sizeof(int)));
   LRIGW_HIP_TRY(hipMemcpy(c->d_sitems, t8.data(), t8.size() * sizeof(int), hipMemcpyHostToDevice));
@@ -976,6 +1007,11 @@ int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const doubl
       if (!c->sig_res_ok) return LRIGW_ERR_ARG;
       const dim3 gr((unsigned)(8 * ncb));
       const int *t8 = c->d_sitems, *t4 = c->d_sitems + 8 * (RES_MAXI + 1);
+      // the exact diagonal term first; the resident kernel adds the rest
+      hipLaunchKernelGGL(k_wdiag, dim3((unsigned)((d.n_aux * RES_WMAX + 255) / 256)), dim3(256), 0, c->stream, Wf, d.n_aux,
+                         d.n_freq, c->d_wd);
+      hipLaunchKernelGGL(k_pair_diag, dim3((unsigned)((Ccols + 255) / 256)), dim3(256), 0, c->stream, xf, Ccols, d.n_aux,
+                         d.n_freq, c->d_wd, (double *)c->d_X);
 #define RES_ARGS xs, ws, xf, Wf, Ccols, Cpad, d.n_aux, Npad, Rpad, d.n_freq, c->sig_res_F
       if (var == 7) hipLaunchKernelGGL((k_sigma_res<8, true, 8>), gr, dim3(512), 0, c->stream, RES_ARGS, t8, c->d_sx, c->d_wmax, (double *)c->d_X);
       else hipLaunchKernelGGL((k_sigma_res<8, true, 4>), gr, dim3(256), 0, c->stream, RES_ARGS, t4, c->d_sx, c->d_wmax, (double *)c->d_X);
