@@ -77,7 +77,9 @@ int driver_buffers(lrigw_ctx *c) {
   if (!c->d_epsqp) LRIGW_HIP_TRY(hipMalloc(&c->d_epsqp, (size_t)d.n_k * d.n_qp * sizeof(double)));
   if (!c->d_chi2) LRIGW_HIP_TRY(hipMalloc(&c->d_chi2, (size_t)d.n_freq * d.n_aux * d.n_aux * cs));
   if (!c->d_wc2) LRIGW_HIP_TRY(hipMalloc(&c->d_wc2, (size_t)d.n_freq * d.n_aux * d.n_aux * cs));
-  if (!c->stream2) LRIGW_HIP_TRY(hipStreamCreate(&c->stream2));   // default priority
+  // non-blocking: the context stream may be the legacy default stream, which
+  // would otherwise serialize with it (default priority)
+  if (!c->stream2) LRIGW_HIP_TRY(hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
   for (int i = 0; i < 2; ++i) {
     if (!c->ev_chi[i]) LRIGW_HIP_TRY(hipEventCreateWithFlags(&c->ev_chi[i], hipEventDisableTiming));
     if (!c->ev_wc[i]) LRIGW_HIP_TRY(hipEventCreateWithFlags(&c->ev_wc[i], hipEventDisableTiming));
