@@ -998,20 +998,22 @@ int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const doubl
       hipLaunchKernelGGL(k_split_x<3>, gx, dim3(256), 0, c->stream, xf, Ccols, d.n_aux, Cpad, Npad, xs);
       hipLaunchKernelGGL((k_split_w<3, false>), gw, dim3(256), 0, c->stream, Wf, d.n_aux, Npad, Rpad, d.n_freq, nullptr, ws);
     }
-    stage_end(c, "sigma_split", ev);
-    stage_begin(c, "sigma_mfma", &ev);
     const int var = c->sig_var;
-    const int snw = sigma_variant_snw(var);
-    dim3 gs(xcd_grid((d.n_freq + snw - 1) / snw, ncb));
     if (var >= 7) {
       if (!c->sig_res_ok) return LRIGW_ERR_ARG;
-      const dim3 gr((unsigned)(8 * ncb));
-      const int *t8 = c->d_sitems, *t4 = c->d_sitems + 8 * (RES_MAXI + 1);
       // the exact diagonal term first; the resident kernel adds the rest
       hipLaunchKernelGGL(k_wdiag, dim3((unsigned)((d.n_aux * RES_WMAX + 255) / 256)), dim3(256), 0, c->stream, Wf, d.n_aux,
                          d.n_freq, c->d_wd);
       hipLaunchKernelGGL(k_pair_diag, dim3((unsigned)((Ccols + 255) / 256)), dim3(256), 0, c->stream, xf, Ccols, d.n_aux,
                          d.n_freq, c->d_wd, (double *)c->d_X);
+    }
+    stage_end(c, "sigma_split", ev);
+    stage_begin(c, "sigma_mfma", &ev);
+    const int snw = sigma_variant_snw(var);
+    dim3 gs(xcd_grid((d.n_freq + snw - 1) / snw, ncb));
+    if (var >= 7) {
+      const dim3 gr((unsigned)(8 * ncb));
+      const int *t8 = c->d_sitems, *t4 = c->d_sitems + 8 * (RES_MAXI + 1);
 #define RES_ARGS xs, ws, xf, Wf, Ccols, Cpad, d.n_aux, Npad, Rpad, d.n_freq, c->sig_res_F
       if (var == 7) hipLaunchKernelGGL((k_sigma_res<8, true, 8>), gr, dim3(512), 0, c->stream, RES_ARGS, t8, c->d_sx, c->d_wmax, (double *)c->d_X);
       else hipLaunchKernelGGL((k_sigma_res<8, true, 4>), gr, dim3(256), 0, c->stream, RES_ARGS, t4, c->d_sx, c->d_wmax, (double *)c->d_X);

@@ -23,7 +23,7 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY_BYTES = 1 << 30          # calibration copy: 1 GiB read + 1 GiB written
 # the main kernel of each stage (all its variants) and its source file
-FAMILIES = {"sigma_mfma": (("k_sigma_split", "k_sigma_splitq", "k_sigma_mfma"), "k_sigma.hip"),
+FAMILIES = {"sigma_mfma": (("k_sigma_res", "k_sigma_split", "k_sigma_splitq", "k_sigma_mfma"), "k_sigma.hip"),
             "chi0_mfma": (("k_chi0_split", "k_chi0_mfma"), "k_chi0.hip")}
 
 
