@@ -821,18 +821,33 @@ __global__ void k_wdiag(const float2 *__restrict__ W, int N, int n_freq, float *
 
 __global__ __launch_bounds__(256) void k_pair_diag(const float2 *__restrict__ x, long long C, int N, int n_freq,
                                                    const float *__restrict__ wd, double *__restrict__ Xall) {
-  const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (c >= C) return;
+  // 16 mu of 256 columns per step through LDS (coalesced loads, padded rows)
+  __shared__ float2 xs[256][17];
+  const long long c0 = (long long)blockIdx.x * 256;
+  const long long c = c0 + threadIdx.x;
   double acc[RES_WMAX];
 #pragma unroll
   for (int w = 0; w < RES_WMAX; ++w) acc[w] = 0.0;
-  for (int mu = 0; mu < N; ++mu) {
-    const float2 v = x[c * N + mu];
-    const double a2 = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
-    const float *row = wd + mu * RES_WMAX;
+  for (int m0 = 0; m0 < N; m0 += 16) {
+    __syncthreads();
 #pragma unroll
-    for (int w = 0; w < RES_WMAX; ++w) acc[w] += (double)row[w] * a2;
+    for (int e = 0; e < 16; ++e) {
+      const int idx = e * 256 + threadIdx.x, cl = idx / 16, mm = idx % 16;
+      float2 v = mkcf(0.f, 0.f);
+      if (c0 + cl < C && m0 + mm < N) v = x[(c0 + cl) * N + m0 + mm];
+      xs[cl][mm] = v;
+    }
+    __syncthreads();
+    const int mn = min(16, N - m0);
+    for (int mm = 0; mm < mn; ++mm) {
+      const float2 v = xs[threadIdx.x][mm];
+      const double a2 = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+      const float *row = wd + (m0 + mm) * RES_WMAX;
+#pragma unroll
+      for (int w = 0; w < RES_WMAX; ++w) acc[w] += (double)row[w] * a2;
+    }
   }
+  if (c >= C) return;
 #pragma unroll
   for (int w = 0; w < RES_WMAX; ++w)
     if (w < n_freq) Xall[(long long)w * C + c] = acc[w];
@@ -893,38 +908,72 @@ int sigma_res_prepare(lrigw_ctx *c) {
 }
 
 // sigma[k][n][i] += scale * sum_m sum_j g_j X[j][k][n][m] a/(a^2 + w_j^2),  a = i w_i + mu - e_m(k-q)
-__global__ void k_sigma_freq(const double *__restrict__ X, const double *__restrict__ eig, const int *__restrict__ kmq, int iq,
-                             int nk, int n_qp, int n_bands, int n_freq, const double *__restrict__ omega,
-                             const double *__restrict__ weight, double mu, double scale, double2 *__restrict__ sigma) {
-  long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  long long tot = (long long)nk * n_qp * n_freq;
-  if (idx >= tot) return;
-  const int i = (int)(idx % n_freq);
-  const int n = (int)((idx / n_freq) % n_qp);
-  const int k = (int)(idx / ((long long)n_freq * n_qp));
+// One wave per (k, SF_I frequencies i, SF_N bands n): lanes run over the pairs
+// (m, j), m fastest (coalesced X), so each kernel value g_j a/(a^2 + w_j^2) is
+// formed once and serves every n; the lane sums are reduced through LDS in a
+// fixed order (one output per lane).
+#define SF_I 4
+#define SF_N 8
+__global__ __launch_bounds__(64) void k_sigma_freq(const double *__restrict__ X, const double *__restrict__ eig,
+                                                   const int *__restrict__ kmq, int iq, int nk, int n_qp, int n_bands,
+                                                   int n_freq, const double *__restrict__ omega, const double *__restrict__ weight,
+                                                   double mu, double scale, double2 *__restrict__ sigma) {
+  __shared__ double red[2 * SF_I * SF_N][65];
+  const int k = blockIdx.x, i0 = blockIdx.y * SF_I, n0 = blockIdx.z * SF_N, lane = threadIdx.x;
   const int k2 = kmq[k * nk + iq];
-  const double wi = omega[i];
   const long long cstride = (long long)nk * n_qp * n_bands;
-  double sr = 0.0, si = 0.0;
-  for (int m = 0; m < n_bands; ++m) {
+  double wi[SF_I];
+#pragma unroll
+  for (int ii = 0; ii < SF_I; ++ii) wi[ii] = i0 + ii < n_freq ? omega[i0 + ii] : 1.0;
+  double accr[SF_I][SF_N], acci[SF_I][SF_N];
+#pragma unroll
+  for (int ii = 0; ii < SF_I; ++ii)
+#pragma unroll
+    for (int n = 0; n < SF_N; ++n) accr[ii][n] = acci[ii][n] = 0.0;
+  const int np = n_bands * n_freq;
+  for (int p = lane; p < np; p += 64) {
+    const int j = p / n_bands, m = p % n_bands;
     const double ar = mu - eig[(long long)k2 * n_bands + m];
-    const double ai = wi;
-    const double *xp = X + ((long long)k * n_qp + n) * n_bands + m;
-    for (int j = 0; j < n_freq; ++j) {
-      const double wj = omega[j];
+    const double wj = omega[j], gj = weight[j];
+    const double *xp = X + (long long)j * cstride + ((long long)k * n_qp + n0) * n_bands + m;
+    double x[SF_N];
+#pragma unroll
+    for (int n = 0; n < SF_N; ++n) x[n] = n0 + n < n_qp ? gj * xp[(long long)n * n_bands] : 0.0;
+#pragma unroll
+    for (int ii = 0; ii < SF_I; ++ii) {
+      const double ai = wi[ii];
       const double dr = ar * ar - ai * ai + wj * wj, di = 2.0 * ar * ai;
       const double inv = 1.0 / (dr * dr + di * di);
       const double kr = (ar * dr + ai * di) * inv, ki = (ai * dr - ar * di) * inv;
-      const double gx = weight[j] * (double)xp[(long long)j * cstride];
-      sr += gx * kr;
-      si += gx * ki;
+#pragma unroll
+      for (int n = 0; n < SF_N; ++n) {
+        accr[ii][n] += x[n] * kr;
+        acci[ii][n] += x[n] * ki;
+      }
     }
   }
-  const long long o = ((long long)k * n_qp + n) * n_freq + i;
-  double2 s = sigma[o];
-  s.x += scale * sr;
-  s.y += scale * si;
-  sigma[o] = s;
+#pragma unroll
+  for (int ii = 0; ii < SF_I; ++ii)
+#pragma unroll
+    for (int n = 0; n < SF_N; ++n) {
+      red[2 * (ii * SF_N + n)][lane] = accr[ii][n];
+      red[2 * (ii * SF_N + n) + 1][lane] = acci[ii][n];
+    }
+  __syncthreads();
+  if (lane >= SF_I * SF_N) return;
+  const int ii = lane / SF_N, n = lane % SF_N;   // one output per lane
+  double sr = 0.0, si = 0.0;
+  for (int l = 0; l < 64; ++l) {
+    sr += red[2 * lane][l];
+    si += red[2 * lane + 1][l];
+  }
+  if (i0 + ii < n_freq && n0 + n < n_qp) {
+    const long long o = ((long long)k * n_qp + n0 + n) * n_freq + i0 + ii;
+    double2 s = sigma[o];
+    s.x += scale * sr;
+    s.y += scale * si;
+    sigma[o] = s;
+  }
 }
 
 // split kernel variants the tuner chooses from: (frequencies per workgroup,
@@ -1030,10 +1079,9 @@ int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const doubl
   }
   stage_end(c, "sigma_mfma", ev);
   LRIGW_TRY(lrigw_launch_check("sigma_mfma"));
-  long long tot = (long long)d.n_k * d.n_qp * d.n_freq;
-  dim3 g2((unsigned)((tot + 127) / 128));
+  dim3 g2((unsigned)d.n_k, (unsigned)((d.n_freq + SF_I - 1) / SF_I), (unsigned)((d.n_qp + SF_N - 1) / SF_N));
   const double scale = -1.0 / (M_PI * d.n_k);
-  hipLaunchKernelGGL(k_sigma_freq, g2, dim3(128), 0, c->stream, (const double *)c->d_X, eig, c->d_kmq, iq, d.n_k, d.n_qp,
+  hipLaunchKernelGGL(k_sigma_freq, g2, dim3(64), 0, c->stream, (const double *)c->d_X, eig, c->d_kmq, iq, d.n_k, d.n_qp,
                      d.n_bands, d.n_freq, c->d_omega, c->d_weight, d.mu, scale, (double2 *)sigma_acc);
   LRIGW_TRY(lrigw_launch_check("sigma_freq"));
   stage_end(c, "sigma_c", ev_all);
