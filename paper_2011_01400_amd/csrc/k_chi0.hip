@@ -296,31 +296,41 @@ __global__ __launch_bounds__(256) void k_chi0_split(const us16 *__restrict__ Ap,
     // the weight table of a chunk is computed once per workgroup: thread t
     // < NW*KCB owns frequency t / KCB and row t % KCB
     const int tw = tid / KCB, tk = tid % KCB;
-    float wnext = 0.f;
-    auto weight = [&](long long k0) {
+    // D of the chunk's row tk (the weights are formed from it after the
+    // chunk's products, so no wait on the prefetches comes before them)
+    auto dload = [&](long long k0) -> float {
       const long long k = k0 + tk;
-      const float dd = k < K ? delta[k] : 1.f;
+      return (tw < NW && k < K) ? delta[k] : 1.f;
+    };
+    auto weight = [&](float dd) {
       const int w = tw < NW ? tw : 0;
       return 2.f * dd / (dd * dd + om2[w]) * wsc[w];
     };
+    float dnext = 1.f;
 #pragma unroll
     for (int pr = 0; pr < NS * 2; ++pr) apre[pr] = *(const u32x4 *)(asrc + pr * pstride);
 #pragma unroll
     for (int e = 0; e < 8; ++e) bcur[e] = bsrc[e];
-    if (tw < NW) wtab[0][tw][tk] = weight(kb);
+    if (tw < NW) wtab[0][tw][tk] = weight(dload(kb));
 #pragma unroll
     for (int pr = 0; pr < NS * 2; ++pr) *(u32x4 *)&As[0][pr][arow][ak] = apre[pr];
+    // every load of the first chunk done: the loop then carries no pending
+    // load into its first iteration, and its own waits cover only what it
+    // issued itself
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     for (int ch = 0; ch < nch; ++ch) {
       const int b = ch & 1;
-      if (ch + 1 < nch) {
-        const long long off = (long long)(ch + 1) * KCB;
+      {
+        // next chunk, clamped so that every iteration issues the same loads
+        const long long off = (long long)min(ch + 1, nch - 1) * KCB;
 #pragma unroll
         for (int pr = 0; pr < NS * 2; ++pr) apre[pr] = *(const u32x4 *)(asrc + pr * pstride + off);
 #pragma unroll
         for (int e = 0; e < 8; ++e) bnext[e] = bsrc[off + e];
-        if (tw < NW) wnext = weight(kb + off);
+        dnext = dload(kb + off);
       }
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int w = 0; w < NW; ++w) {
         // this wave's 16 columns, weighted for frequency w and split
@@ -369,7 +379,7 @@ __global__ __launch_bounds__(256) void k_chi0_split(const us16 *__restrict__ Ap,
         for (int pr = 0; pr < NS * 2; ++pr) *(u32x4 *)&As[b ^ 1][pr][arow][ak] = apre[pr];
 #pragma unroll
         for (int e = 0; e < 8; ++e) bcur[e] = bnext[e];
-        if (tw < NW) wtab[b ^ 1][tw][tk] = wnext;
+        if (tw < NW) wtab[b ^ 1][tw][tk] = weight(dnext);
       }
       __syncthreads();
     }
