@@ -9,16 +9,24 @@
 // M[k][r][c][mu] = sum_{a on atom(mu)} conj(c_{a,r0+r}(k)) H[k2][a][c0+c][mu] + conj(H[k][a][r0+r][mu]) c_{a,c0+c}(k2)
 // k2 = kmap[k][iq].  One thread per (mu, 4 columns c); NR >= nr row accumulators
 // per column, so every H[k][a][r][mu] loaded serves BM_CPT columns
-// (BM_CPT * NR <= 32 keeps the accumulators in registers).
+// (BM_CPT * NR <= 32 keeps the accumulators in registers).  Workgroup ->
+// (mu block, column block, k): each XCD (workgroup id mod 8) takes a
+// contiguous range of the work items, column block fastest, so the column
+// blocks of one (mu block, k) share the row panel H[k][.][r][mu] in that XCD's
+// L2 instead of fetching it once per column block.
 template <typename T, int NR, int BM_CPT>
 __global__ __launch_bounds__(256) void k_build_M(const typename c2t<T>::type *__restrict__ H, const double2 *__restrict__ evec,
                                                  int n_bands, int n_b, int n_aux, int nb_max, const int *__restrict__ aux_atom,
                                                  const int *__restrict__ basis_off, const int *__restrict__ kmap, int iq,
                                                  int nk, int r0, int nr, int c0, int nc, typename c2t<T>::type *__restrict__ M) {
   typedef typename c2t<T>::type C;
-  const int mu = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int cb = (blockIdx.y * 4 + (threadIdx.x >> 6)) * BM_CPT;   // first column of this thread
-  const int k = blockIdx.z;
+  const int nmb = (n_aux + 63) / 64, ncb = (nc + 4 * BM_CPT - 1) / (4 * BM_CPT);
+  const long long total = (long long)nmb * ncb * nk, per = (total + 7) / 8;
+  const long long w = (long long)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (w >= total) return;
+  const int yb = (int)(w % ncb), xb = (int)((w / ncb) % nmb), k = (int)(w / ((long long)ncb * nmb));
+  const int mu = xb * 64 + (threadIdx.x & 63);
+  const int cb = (yb * 4 + (threadIdx.x >> 6)) * BM_CPT;   // first column of this thread
   if (mu >= n_aux || cb >= nc) return;
   const int A = aux_atom[mu];
   const int bo = basis_off[A];
@@ -75,7 +83,8 @@ static void launch_build(lrigw_ctx *c, int iq, int r0, int nr, int c0, int nc, c
   typedef typename c2t<T>::type C;
   const Dims &d = c->d;
 #define BM(NRV, CPT)                                                                                              \
-  hipLaunchKernelGGL((k_build_M<T, NRV, CPT>), dim3((d.n_aux + 63) / 64, (nc + 4 * CPT - 1) / (4 * CPT), d.n_k),   \
+  hipLaunchKernelGGL((k_build_M<T, NRV, CPT>),                                                                     \
+                     dim3((unsigned)(8 * ((((long long)(d.n_aux + 63) / 64) * ((nc + 4 * CPT - 1) / (4 * CPT)) * d.n_k + 7) / 8))), \
                      dim3(256), 0, c->stream, (const C *)H, (const double2 *)evec, d.n_bands, d.n_b, d.n_aux, d.nb_max, \
                      c->d_aux_atom, c->d_basis_off, kmap, iq, d.n_k, r0, nr, c0, nc, (C *)M)
   if (nr <= 4) BM(4, 4);
