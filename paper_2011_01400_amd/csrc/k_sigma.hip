@@ -665,20 +665,24 @@ __global__ __launch_bounds__(64 * NWV) void k_sigma_res(const us16 *__restrict__
   const int w = f0 + fl;
   const int g8 = Npad / 8;
   {
-    // every load of the tile in flight before the first LDS store
-    constexpr int PER = 4 * TILE * (RES_NPAD / 8) / (64 * NWV);
-    u32x4 v[PER];
+    // 4 x 64 rows of g8 <= RES_NPAD/8 16-byte pieces: wave w takes rows
+    // w, w + NWV, ..., lane = piece (no index division); all loads of a batch
+    // in flight before its LDS stores
+    constexpr int ROWS = 4 * TILE / NWV, BATCH = 8;
+    const bool lact = lane < g8;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int e = tid + k * 64 * NWV;
-      const int pr = e / (TILE * g8), rem = e % (TILE * g8), cl = rem / g8, k8 = rem % g8;
-      if (e < 4 * TILE * g8) v[k] = *(const u32x4 *)(xs + ((long long)pr * Cpad + c0 + cl) * Npad + 8 * k8);
-    }
+    for (int r0b = 0; r0b < ROWS; r0b += BATCH) {
+      u32x4 v[BATCH];
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int e = tid + k * 64 * NWV;
-      const int pr = e / (TILE * g8), rem = e % (TILE * g8), cl = rem / g8, k8 = rem % g8;
-      if (e < 4 * TILE * g8) *(u32x4 *)&Xs[pr][cl][8 * k8] = v[k];
+      for (int t = 0; t < BATCH; ++t) {
+        const int row = wave + NWV * (r0b + t);   // = part plane * 64 + column
+        if (lact) v[t] = *(const u32x4 *)(xs + ((long long)(row >> 6) * Cpad + c0 + (row & 63)) * Npad + 8 * lane);
+      }
+#pragma unroll
+      for (int t = 0; t < BATCH; ++t) {
+        const int row = wave + NWV * (r0b + t);
+        if (lact) *(u32x4 *)&Xs[row >> 6][row & 63][8 * lane] = v[t];
+      }
     }
   }
   __syncthreads();
