@@ -18,7 +18,8 @@ template <typename T, int NR, int BM_CPT>
 __global__ __launch_bounds__(256) void k_build_M(const typename c2t<T>::type *__restrict__ H, const double2 *__restrict__ evec,
                                                  int n_bands, int n_b, int n_aux, int nb_max, const int *__restrict__ aux_atom,
                                                  const int *__restrict__ basis_off, const int *__restrict__ kmap, int iq,
-                                                 int nk, int r0, int nr, int c0, int nc, typename c2t<T>::type *__restrict__ M) {
+                                                 int nk, int r0, int nr, int c0, int nc, int rr0, int nr_tot,
+                                                 typename c2t<T>::type *__restrict__ M) {
   typedef typename c2t<T>::type C;
   const int nmb = (n_aux + 63) / 64, ncb = (nc + 4 * BM_CPT - 1) / (4 * BM_CPT);
   const long long total = (long long)nmb * ncb * nk, per = (total + 7) / 8;
@@ -38,43 +39,49 @@ __global__ __launch_bounds__(256) void k_build_M(const typename c2t<T>::type *__
   for (int t = 0; t < BM_CPT; ++t)
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[t][r].x = acc[t][r].y = (T)0;
+  // padded columns (t >= ncol) and rows (r >= nr) repeat a valid one: their
+  // accumulators are never stored, and with no guard around them the loads of
+  // a basis function are all in flight together
   for (int a = 0; a < nbA; ++a) {
-    C h2[BM_CPT], e2[BM_CPT];
+    C h2[BM_CPT], e2[BM_CPT], h1[NR], e1[NR];
     const C *h2row = H + (((long long)k2 * nb_max + a) * n_bands + c0 + cb) * n_aux + mu;
     const double2 *e2row = evec + ((long long)k2 * n_b + bo + a) * n_bands + c0 + cb;
-#pragma unroll
-    for (int t = 0; t < BM_CPT; ++t) {
-      if (t < ncol) {
-        h2[t] = h2row[(long long)t * n_aux];
-        double2 v = e2row[t];
-        e2[t].x = (T)v.x;
-        e2[t].y = (T)v.y;
-      } else {
-        h2[t].x = h2[t].y = (T)0;
-        e2[t].x = e2[t].y = (T)0;
-      }
-    }
     const C *h1row = H + (((long long)k * nb_max + a) * n_bands + r0) * n_aux + mu;
     const double2 *e1row = evec + ((long long)k * n_b + bo + a) * n_bands + r0;
+    double2 e2d[BM_CPT], e1d[NR];
+#pragma unroll
+    for (int t = 0; t < BM_CPT; ++t) {
+      const int tt = min(t, ncol - 1);
+      h2[t] = h2row[(long long)tt * n_aux];
+      e2d[t] = e2row[tt];
+    }
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      if (r < nr) {
-        double2 e1d = e1row[r];
-        C e1;
-        e1.x = (T)e1d.x;
-        e1.y = (T)e1d.y;
-        const C h1 = h1row[(long long)r * n_aux];
-#pragma unroll
-        for (int t = 0; t < BM_CPT; ++t) acc[t][r] = cadd(acc[t][r], cadd(ccmul(e1, h2[t]), ccmul(h1, e2[t])));
-      }
+      const int rr = min(r, nr - 1);
+      h1[r] = h1row[(long long)rr * n_aux];
+      e1d[r] = e1row[rr];
     }
+#pragma unroll
+    for (int t = 0; t < BM_CPT; ++t) {
+      e2[t].x = (T)e2d[t].x;
+      e2[t].y = (T)e2d[t].y;
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      e1[r].x = (T)e1d[r].x;
+      e1[r].y = (T)e1d[r].y;
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int t = 0; t < BM_CPT; ++t) acc[t][r] = cadd(acc[t][r], cadd(ccmul(e1[r], h2[t]), ccmul(h1[r], e2[t])));
   }
 #pragma unroll
   for (int t = 0; t < BM_CPT; ++t)
     if (t < ncol)
 #pragma unroll
       for (int r = 0; r < NR; ++r)
-        if (r < nr) M[(((long long)k * nr + r) * nc + cb + t) * n_aux + mu] = acc[t][r];
+        if (r < nr) M[(((long long)k * nr_tot + rr0 + r) * nc + cb + t) * n_aux + mu] = acc[t][r];
 }
 
 template <typename T>
@@ -86,12 +93,18 @@ static void launch_build(lrigw_ctx *c, int iq, int r0, int nr, int c0, int nc, c
   hipLaunchKernelGGL((k_build_M<T, NRV, CPT>),                                                                     \
                      dim3((unsigned)(8 * ((((long long)(d.n_aux + 63) / 64) * ((nc + 4 * CPT - 1) / (4 * CPT)) * d.n_k + 7) / 8))), \
                      dim3(256), 0, c->stream, (const C *)H, (const double2 *)evec, d.n_bands, d.n_b, d.n_aux, d.nb_max, \
-                     c->d_aux_atom, c->d_basis_off, kmap, iq, d.n_k, r0, nr, c0, nc, (C *)M)
-  if (nr <= 4) BM(4, 4);
-  else if (nr <= 8) BM(8, 4);
-  else if (nr <= 16) BM(16, 2);
-  else if (nr <= 32) BM(32, 1);
-  else BM(64, 1);
+                     c->d_aux_atom, c->d_basis_off, kmap, iq, d.n_k, r0 + rb, nrl, c0, nc, rb, nr, (C *)M)
+  // rows in blocks of at most 8 (one launch each)
+  for (int rb = 0; rb < nr; rb += 8) {
+    const int nrl = std::min(8, nr - rb);
+    if constexpr (sizeof(T) == 4) {
+      if (nrl <= 4) BM(4, 4);
+      else BM(8, 4);
+    } else {
+      if (nrl <= 4) BM(4, 4);
+      else BM(8, 2);
+    }
+  }
 #undef BM
 }
 
