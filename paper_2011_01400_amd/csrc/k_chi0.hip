@@ -250,11 +250,13 @@ __global__ __launch_bounds__(256) void k_chi0_presplit(const float2 *__restrict_
   }
 }
 
+// With NW = 2 the kernel is held to two waves per SIMD (249 registers), so
+// one wave's weighting and splitting overlaps the other's products.
 // FP16 parts (H): the weight of frequency w is taken times 2^-e_w with
 // 2^e_w >= 1/w, which bounds |2D/(D^2 + w^2)| by 1, so the weighted, row-scaled
 // B side stays below 2^15; the tile is scaled back by s_mu s_nu 2^e_w.
 template <int NS, int NW, int PAD, bool H>
-__global__ __launch_bounds__(256) void k_chi0_split(const us16 *__restrict__ Ap, const float2 *__restrict__ Bt,
+__global__ __launch_bounds__(256, NW == 2 ? 2 : 1) void k_chi0_split(const us16 *__restrict__ Ap, const float2 *__restrict__ Bt,
                                                     const float *__restrict__ delta, const double *__restrict__ omega,
                                                     const int *__restrict__ wsel, const int *__restrict__ run, long long K,
                                                     long long Kp, int Npad, int n_freq, long long Ks, long long ntile,
