@@ -19,6 +19,9 @@ CELLS = [
                                    qp_lo=2, n_qp=6, seed=17), "fp32"),
     ("three_atoms", lambda: make_custom(n_atoms=3, nb_per_atom=6, naux_per_atom=45, nk=(1, 1, 1), n_occ=4, n_freq=8,
                                         qp_lo=1, n_qp=7, seed=23), "split_bf16"),
+    # FP16 form: the scale kernels and (with the tuner) the resident-tile self-energy kernel inside the graph
+    ("three_atoms_f16", lambda: make_custom(n_atoms=3, nb_per_atom=6, naux_per_atom=45, nk=(2, 1, 1), n_occ=4, n_freq=8,
+                                            qp_lo=1, n_qp=7, seed=29), "split_f16"),
 ]
 
 
@@ -92,7 +95,7 @@ def test_batch_replays_match_per_cell_calls(cells, autotune):
                 # same tile choices as the per-cell calls: same arithmetic
                 assert ds < 1e-13 and de.max() < 1e-9
             else:
-                tol_s = {"fp64": 1e-12, "fp32": 1e-5, "split_bf16": 1e-4}[c["prec"]]
+                tol_s = {"fp64": 1e-12, "fp32": 1e-5, "split_bf16": 1e-4, "split_f16": 1e-5}[c["prec"]]
                 assert ds < tol_s
                 assert (de[reg].max() if reg.any() else 0.0) < (1e-6 if c["prec"] == "fp64" else 1.0)
     b.close()
@@ -113,3 +116,35 @@ def test_batch_fp64_cell_matches_oracle(cells):
     print(f"  c1 in the batch vs oracle: max|dSigma| {ds:.2e} Ha, max|dE| {de:.2e} meV", flush=True)
     assert ds < 1e-9 and de < 1e-5
     b.close()
+
+
+def test_batch_resident_tile_f16():
+    """The FP16 form with the resident-tile self-energy kernel (variant 7,
+    forced) inside a captured graph: every replay equals the eager pass with
+    the same tile choices."""
+    L = _lib()
+    s = make_custom(n_atoms=3, nb_per_atom=6, naux_per_atom=45, nk=(2, 1, 1), n_occ=4, n_freq=8, qp_lo=1, n_qp=7, seed=29)
+    ref = _cell_inputs(L, s, "split_f16")
+    ref["ctx"].set_tiles(4, 1, 8, 7)
+    ref["ctx"].g0w0(ref["H"], ref["evec"], ref["eig"], ref["V"], ref["p"], ref["omega_cell"], ref["e_static"], 16,
+                    ref["sigma"], ref["e_qp"], ref["z"])
+    torch.cuda.synchronize()
+    s_ref, e_ref = ref["sigma"].cpu().numpy(), ref["e_qp"].cpu().numpy()
+    inp = _cell_inputs(L, s, "split_f16")
+    inp["ctx"].set_tiles(4, 1, 8, 7)
+    b = L.Batch([inp], autotune=False)
+    for rep in range(3):
+        inp["sigma"].fill_(float("nan"))
+        torch.cuda.synchronize()
+        b.run()
+        st = b.status()
+        x = torch.randn(256, 256, device="cuda")
+        (x @ x).sum().item()
+        sg, e = inp["sigma"].cpu().numpy(), inp["e_qp"].cpu().numpy()
+        ds = np.abs(sg - s_ref).max() / np.abs(s_ref).max()
+        print(f"  replay {rep}: status {st[0]}, max rel dSigma {ds:.2e}, max dE {np.abs(e - e_ref).max() * HA_MEV:.2e} meV",
+              flush=True)
+        assert st[0][0] == -1
+        assert ds < 1e-13 and np.abs(e - e_ref).max() * HA_MEV < 1e-9
+    b.close()
+    ref["ctx"].close()
