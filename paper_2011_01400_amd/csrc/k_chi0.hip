@@ -201,9 +201,13 @@ __global__ __launch_bounds__(256) void k_absmax_rows(const float2 *__restrict__ 
   const long long k1 = k0 + 64 < K ? k0 + 64 : K;
   for (int mu = threadIdx.x; mu < N; mu += 256) {
     float m = 0.f;
-    for (long long k = k0; k < k1; ++k) {
-      const float2 v = B[k * N + mu];
-      m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+    // 64 rows in blocks of 16 loads in flight (rows past K repeat row k0)
+    for (long long kb = k0; kb < k1; kb += 16) {
+      float2 v[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) v[t] = B[(kb + t < k1 ? kb + t : k0) * N + mu];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) m = fmaxf(m, fmaxf(fabsf(v[t].x), fabsf(v[t].y)));
     }
     atomicMax(amax + mu, __float_as_uint(m));
   }
@@ -223,8 +227,7 @@ __global__ __launch_bounds__(256) void k_chi0_presplit(const float2 *__restrict_
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int kk = ty + 8 * i;
-    float2 v = mkcf(0.f, 0.f);
-    if (k0 + kk < K && m0 + tx < N) v = B[(k0 + kk) * N + m0 + tx];
+    const float2 v = ld_or(B, (k0 + kk) * N + m0 + tx, k0 + kk < K && m0 + tx < N, mkcf(0.f, 0.f));
     t[kk][tx] = v;
   }
   __syncthreads();

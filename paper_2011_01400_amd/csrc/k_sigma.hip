@@ -195,8 +195,7 @@ __global__ void k_split_x(const float2 *__restrict__ x, long long C, int N, long
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     const int nu = k0 + e;
-    float2 u = mkcf(0.f, 0.f);
-    if (c < C && nu < N) u = cconj(x[c * N + nu]);
+    const float2 u = cconj(ld_or(x, c * N + nu, c < C && nu < N, mkcf(0.f, 0.f)));
     us16 a[NS], b[NS];
     split_n<NS, false>(u.x, a);
     split_n<NS, false>(u.y, b);
@@ -236,8 +235,7 @@ __global__ __launch_bounds__(256) void k_split_x_h(const float2 *__restrict__ x,
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int nu = k0 + e;
-      float2 u = mkcf(0.f, 0.f);
-      if (c < C && nu < N) u = cconj(x[c * N + nu]);
+      const float2 u = cconj(ld_or(x, c * N + nu, c < C && nu < N, mkcf(0.f, 0.f)));
       us16 a[NS], b[NS];
       split_n<NS, true>(u.x * inv, a);
       split_n<NS, true>(u.y * inv, b);
@@ -292,8 +290,7 @@ __global__ void k_split_w(const float2 *__restrict__ W, int N, int Npad, int Rpa
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     const int nu = k0 + e;
-    float2 v = mkcf(0.f, 0.f);
-    if (mu >= 0 && nu < mu) v = W[((long long)w * N + mu) * N + nu];
+    const float2 v = ld_or(W, ((long long)w * N + mu) * N + nu, mu >= 0 && nu < mu, mkcf(0.f, 0.f));
     us16 a[NS], b[NS];
     split_n<NS, H>(v.x * inv, a);
     split_n<NS, H>(v.y * inv, b);
@@ -837,8 +834,7 @@ __global__ __launch_bounds__(256) void k_pair_diag(const float2 *__restrict__ x,
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int idx = e * 256 + threadIdx.x, cl = idx / 16, mm = idx % 16;
-      float2 v = mkcf(0.f, 0.f);
-      if (c0 + cl < C && m0 + mm < N) v = x[(c0 + cl) * N + m0 + mm];
+      const float2 v = ld_or(x, (c0 + cl) * N + m0 + mm, c0 + cl < C && m0 + mm < N, mkcf(0.f, 0.f));
       xs[cl][mm] = v;
     }
     __syncthreads();
@@ -942,7 +938,7 @@ __global__ __launch_bounds__(64) void k_sigma_freq(const double *__restrict__ X,
     const double *xp = X + (long long)j * cstride + ((long long)k * n_qp + n0) * n_bands + m;
     double x[SF_N];
 #pragma unroll
-    for (int n = 0; n < SF_N; ++n) x[n] = n0 + n < n_qp ? gj * xp[(long long)n * n_bands] : 0.0;
+    for (int n = 0; n < SF_N; ++n) x[n] = gj * ld_or(xp, (long long)n * n_bands, n0 + n < n_qp, 0.0);
 #pragma unroll
     for (int ii = 0; ii < SF_I; ++ii) {
       const double ai = wi[ii];

@@ -22,6 +22,13 @@ __host__ __device__ inline float2 mkcf(float r, float i) { float2 z; z.x = r; z.
 template <typename C> __host__ __device__ inline C cmul(C a, C b) { C z; z.x = a.x * b.x - a.y * b.y; z.y = a.x * b.y + a.y * b.x; return z; }
 template <typename C> __host__ __device__ inline C cconj(C a) { a.y = -a.y; return a; }
 template <typename C> __host__ __device__ inline C cadd(C a, C b) { a.x += b.x; a.y += b.y; return a; }
+// p[i] if ok, else z: the load always happens (from index 0 when !ok, which
+// must be valid), so a run of these issues all its loads before any wait; a
+// branch around each load would serialise them
+template <typename V> __device__ inline V ld_or(const V *__restrict__ p, long long i, bool ok, V z) {
+  const V v = p[ok ? i : 0];
+  return ok ? v : z;
+}
 // a * conj(b)
 template <typename C> __host__ __device__ inline C cmulc(C a, C b) { C z; z.x = a.x * b.x + a.y * b.y; z.y = a.y * b.x - a.x * b.y; return z; }
 // conj(a) * b
