@@ -11,18 +11,15 @@
 #define GK 16      // K rows staged per step
 #define GP (GT + 1)
 
-__device__ inline double2 ldop(const double2 *__restrict__ A, long long ld, int op, long long r, long long cidx) {
-  // element (r, cidx) of op(A)
-  if (op == OP_N) return A[r * ld + cidx];
-  double2 v = A[cidx * ld + r];
-  if (op == OP_C) v.y = -v.y;
-  return v;
-}
-
 // C = alpha op(A) op(B) + beta C; 64x64 tile per workgroup, four waves of
-// 32x32, complex products as four real FP64 MFMA 16x16x4 products.  A
-// workgroup reads all of op(A)'s rows and op(B)'s columns of its tile before it
-// writes the tile, so C may alias A when n <= 64 or B when m <= 64.
+// 32x32, complex products as four real FP64 MFMA 16x16x4 products.  The ops
+// are template parameters, so the staging loads have no branches: elements
+// outside the matrices come from index 0 and are replaced by zero after the
+// load, and the next K step is fetched into registers while the current one
+// is multiplied.  A workgroup reads all of op(A)'s rows and op(B)'s columns of
+// its tile before it writes the tile, so C may alias A when n <= 64 or B when
+// m <= 64.
+template <int OPA, int OPB>
 __global__ __launch_bounds__(256) void k_zgemm(ZGemm g) {
   typedef Mfma<double> MF;
   __shared__ double2 As[GK][GP];   // As[k][m] = op(A)(m0+m, k0+k)
@@ -35,28 +32,52 @@ __global__ __launch_bounds__(256) void k_zgemm(ZGemm g) {
   double2 *C = g.C + (long long)b * g.sc;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1, col = lane & 15;
+  const double2 zero = mkc(0.0, 0.0);
   d4v cr[2][2], ci[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) cr[i][j] = ci[i][j] = MF::zero();
-  for (int k0 = 0; k0 < g.k; k0 += GK) {
-    __syncthreads();
+  // staging map: along the contiguous index of each operand
+  double2 ra[4], rb[4];
+  auto fetch = [&](int k0) {
 #pragma unroll
     for (int t = 0; t < (GK * GT) / 256; ++t) {
       const int e = tid + 256 * t;
-      int kk, mm;
-      if (g.opa == OP_N) { mm = e / GK; kk = e % GK; } else { kk = e / GT; mm = e % GT; }
-      double2 v = mkc(0.0, 0.0);
-      if (m0 + mm < g.m && k0 + kk < g.k) v = ldop(A, g.lda, g.opa, m0 + mm, k0 + kk);
-      As[kk][mm] = v;
-      int nn;
-      if (g.opb == OP_N) { kk = e / GT; nn = e % GT; } else { nn = e / GK; kk = e % GK; }
-      double2 u = mkc(0.0, 0.0);
-      if (n0 + nn < g.n && k0 + kk < g.k) u = ldop(B, g.ldb, g.opb, k0 + kk, n0 + nn);
-      Bs[kk][nn] = u;
+      {
+        const int mm = OPA == OP_N ? e / GK : e % GT, kk = OPA == OP_N ? e % GK : e / GT;
+        const bool ok = m0 + mm < g.m && k0 + kk < g.k;
+        const long long idx = OPA == OP_N ? (long long)(m0 + mm) * g.lda + k0 + kk : (long long)(k0 + kk) * g.lda + m0 + mm;
+        double2 v = ld_or(A, idx, ok, zero);
+        if (OPA == OP_C) v.y = -v.y;
+        ra[t] = v;
+      }
+      {
+        const int nn = OPB == OP_N ? e % GT : e / GK, kk = OPB == OP_N ? e / GT : e % GK;
+        const bool ok = n0 + nn < g.n && k0 + kk < g.k;
+        const long long idx = OPB == OP_N ? (long long)(k0 + kk) * g.ldb + n0 + nn : (long long)(n0 + nn) * g.ldb + k0 + kk;
+        double2 u = ld_or(B, idx, ok, zero);
+        if (OPB == OP_C) u.y = -u.y;
+        rb[t] = u;
+      }
     }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int t = 0; t < (GK * GT) / 256; ++t) {
+      const int e = tid + 256 * t;
+      const int mm = OPA == OP_N ? e / GK : e % GT, ka = OPA == OP_N ? e % GK : e / GT;
+      As[ka][mm] = ra[t];
+      const int nn = OPB == OP_N ? e % GT : e / GK, kb = OPB == OP_N ? e / GT : e % GK;
+      Bs[kb][nn] = rb[t];
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < g.k; k0 += GK) {
     __syncthreads();
+    stash();
+    __syncthreads();
+    fetch(k0 + GK);   // past the end: all zero, harmless
 #pragma unroll
     for (int ks = 0; ks < GK / 4; ++ks) {
       const int kk = ks * 4 + (lane >> 4);
@@ -109,8 +130,14 @@ __global__ __launch_bounds__(256) void k_zgemm(ZGemm g) {
 int zgemm(hipStream_t s, const ZGemm &g) {
   if (g.m <= 0 || g.n <= 0 || g.batch <= 0) return LRIGW_OK;
   if (g.k <= 0) return LRIGW_ERR_ARG;
+  if (g.opa < OP_N || g.opa > OP_C || g.opb < OP_N || g.opb > OP_C) return LRIGW_ERR_ARG;
   dim3 grid((g.m + GT - 1) / GT, (g.n + GT - 1) / GT, g.batch);
-  hipLaunchKernelGGL(k_zgemm, grid, dim3(256), 0, s, g);
+#define ZG(OA, OB) \
+  if (g.opa == OA && g.opb == OB) hipLaunchKernelGGL((k_zgemm<OA, OB>), grid, dim3(256), 0, s, g);
+  ZG(OP_N, OP_N) ZG(OP_N, OP_T) ZG(OP_N, OP_C)
+  ZG(OP_T, OP_N) ZG(OP_T, OP_T) ZG(OP_T, OP_C)
+  ZG(OP_C, OP_N) ZG(OP_C, OP_T) ZG(OP_C, OP_C)
+#undef ZG
   return lrigw_launch_check("zgemm");
 }
 
