@@ -258,6 +258,11 @@ __global__ __launch_bounds__(256) void k_chi0_presplit(const float2 *__restrict_
 // FP16 parts (H): the weight of frequency w is taken times 2^-e_w with
 // 2^e_w >= 1/w, which bounds |2D/(D^2 + w^2)| by 1, so the weighted, row-scaled
 // B side stays below 2^15; the tile is scaled back by s_mu s_nu 2^e_w.
+// A tile of the last tile row whose rows past N_aux fill whole 16-row blocks
+// runs a copy of the chunk loop without those blocks' products (their
+// partial-tile rows are never read).
+template <int V> struct IntC { static constexpr int value = V; };
+
 template <int NS, int NW, int PAD, bool H>
 __global__ __launch_bounds__(256, NW == 2 ? 2 : 1) void k_chi0_split(const us16 *__restrict__ Ap, const float2 *__restrict__ Bt,
                                                     const float *__restrict__ delta, const double *__restrict__ omega,
@@ -324,6 +329,8 @@ __global__ __launch_bounds__(256, NW == 2 ? 2 : 1) void k_chi0_split(const us16 
     // issued itself
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    auto loop = [&](auto nsi_c) {
+    constexpr int NSI = decltype(nsi_c)::value;
     for (int ch = 0; ch < nch; ++ch) {
       const int b = ch & 1;
       {
@@ -362,7 +369,7 @@ __global__ __launch_bounds__(256, NW == 2 ? 2 : 1) void k_chi0_split(const us16 
           bi[p] = *(const u32x4 *)bis[p];
         }
 #pragma unroll
-        for (int si = 0; si < 4; ++si) {
+        for (int si = 0; si < NSI; ++si) {
 #pragma unroll
           for (int p = 0; p < NS; ++p) {
             const u32x4 ar = *(const u32x4 *)&As[b][2 * p][16 * si + col][8 * g];
@@ -388,6 +395,11 @@ __global__ __launch_bounds__(256, NW == 2 ? 2 : 1) void k_chi0_split(const us16 
       }
       __syncthreads();
     }
+    };
+    const int rem = N - mu0;
+    if (rem > 2 * 16) loop(IntC<4>());
+    else if (rem > 16) loop(IntC<2>());
+    else loop(IntC<1>());
   }
 store:
 #pragma unroll
@@ -398,6 +410,7 @@ store:
     const float fcol = H ? pow2_scale(__uint_as_float(amax[nu0 + cl < N ? nu0 + cl : 0])) / wsc[w] : 1.f;
 #pragma unroll
     for (int si = 0; si < 4; ++si) {
+      if (16 * si >= N - mu0) break;
       const f4v r = re[w][si], i = im[w][si];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -411,29 +424,59 @@ store:
 
 // chi[w][mu][nu] = scale * sum_s part[s][w][tile][..]; upper triangle by Hermitian symmetry.
 template <typename T>
-__global__ void k_chi0_reduce(const typename c2t<T>::type *__restrict__ part, int S, int n_freq, long long ntile, int N,
-                              double scale, const int *__restrict__ wsel, const int *__restrict__ run,
-                              typename c2t<T>::type *__restrict__ chi) {
-  long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int w = blockIdx.y;
-  if (idx >= (long long)N * N) return;
+__global__ __launch_bounds__(256) void k_chi0_reduce(const typename c2t<T>::type *__restrict__ part, int S, int n_freq,
+                                                     long long ntile, int N, double scale, const int *__restrict__ wsel,
+                                                     const int *__restrict__ run, typename c2t<T>::type *__restrict__ chi) {
+  // one workgroup per (lower tile, frequency): the K-split partial tiles are
+  // summed in FP64 along the tile's rows; the lower half of chi is written
+  // along those rows, the mirrored upper half (conjugated) along the tile's
+  // columns through an LDS transpose; the diagonal is made real
+  using CT = typename c2t<T>::type;
+  constexpr int E = TILE * TILE / 256;
+  __shared__ CT tr[TILE][TILE + 1];
   if (run && *run == 0) return;
-  int mu = (int)(idx / N), nu = (int)(idx % N);
-  bool up = nu > mu;
-  int a = up ? nu : mu, b = up ? mu : nu;
-  int I = a / TILE, J = b / TILE;
-  long long t = (long long)I * (I + 1) / 2 + J;
-  long long off = (long long)(a % TILE) * TILE + (b % TILE);
-  double sr = 0.0, si = 0.0;
+  const int t = blockIdx.x, w = blockIdx.y, tid = threadIdx.x;
+  int I, J;
+  tri_decode(t, I, J);
+  const int mu0 = I * TILE, nu0 = J * TILE;
+  double sr[E], si[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) sr[e] = si[e] = 0.0;
+  const CT *src = part + ((long long)w * ntile + t) * (TILE * TILE);
+  const long long sstride = (long long)n_freq * ntile * TILE * TILE;
+  CT zero;
+  zero.x = zero.y = 0;
   for (int s = 0; s < S; ++s) {
-    auto v = part[(((long long)s * n_freq + w) * ntile + t) * (TILE * TILE) + off];
-    sr += (double)v.x;
-    si += (double)v.y;
+    const CT *ps = src + s * sstride;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int idx = e * 256 + tid;
+      const CT v = ld_or(ps, idx, mu0 + (idx >> 6) < N && nu0 + (idx & 63) < N, zero);
+      sr[e] += (double)v.x;
+      si[e] += (double)v.y;
+    }
   }
-  double2 z = mkc(scale * sr, scale * si);
-  if (up) z.y = -z.y;
-  if (mu == nu) z.y = 0.0;
-  chi[((long long)wsel[w] * N + mu) * N + nu] = to_c<T>(z);
+  CT *dst = chi + (long long)wsel[w] * N * N;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int idx = e * 256 + tid, r = idx >> 6, cc = idx & 63;
+    double2 z = mkc(scale * sr[e], scale * si[e]);
+    if (I == J && r == cc) z.y = 0.0;
+    const CT v = to_c<T>(z);
+    tr[r][cc] = v;
+    if (mu0 + r < N && nu0 + cc < N && (I != J || cc <= r)) dst[(long long)(mu0 + r) * N + nu0 + cc] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    // output row nu0 + r2, column mu0 + c2 (upper half): conj of tile[c2][r2]
+    const int idx = e * 256 + tid, r2 = idx >> 6, c2 = idx & 63;
+    if (nu0 + r2 < N && mu0 + c2 < N && (I != J || c2 > r2)) {
+      CT v = tr[c2][r2];
+      v.y = -v.y;
+      dst[(long long)(nu0 + r2) * N + mu0 + c2] = v;
+    }
+  }
 }
 
 // Number of K splits: enough workgroups to fill the device, partial buffer <= 2 GiB.
@@ -565,7 +608,7 @@ int run_chi0_sel(lrigw_ctx *c, int iq, const void *M, const double *eig, int app
 #undef CHI0_ARGS
   stage_end(c, "chi0_mfma", ev);
   LRIGW_TRY(lrigw_launch_check("chi0_mfma"));
-  dim3 rgrid((unsigned)(((long long)d.n_aux * d.n_aux + 255) / 256), n_sel);
+  dim3 rgrid((unsigned)ntile, n_sel);
   if (c->precision == LRIGW_FP64)
     hipLaunchKernelGGL(k_chi0_reduce<double>, rgrid, dim3(256), 0, c->stream, (const double2 *)c->d_part, S, n_sel, ntile,
                        d.n_aux, scale, wsel, run, (double2 *)chi_out);

@@ -813,22 +813,30 @@ __global__ __launch_bounds__(64 * NWV) void k_sigma_res(const us16 *__restrict__
 // the off-diagonal part).  wd[mu][w] = Re W^c_mumu(w) (RES_WMAX frequencies
 // per row, zero beyond n_freq); one thread per column c.
 #define RES_WMAX 32
-__global__ void k_wdiag(const float2 *__restrict__ W, int N, int n_freq, float *__restrict__ wd) {
+__global__ void k_wdiag(const float2 *__restrict__ W, int N, int n_freq, double *__restrict__ wd) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= N * RES_WMAX) return;
   const int mu = t / RES_WMAX, w = t % RES_WMAX;
-  wd[t] = w < n_freq ? W[((long long)w * N + mu) * N + mu].x : 0.f;
+  wd[t] = w < n_freq ? (double)W[((long long)w * N + mu) * N + mu].x : 0.0;
 }
-
 __global__ __launch_bounds__(256) void k_pair_diag(const float2 *__restrict__ x, long long C, int N, int n_freq,
-                                                   const float *__restrict__ wd, double *__restrict__ Xall) {
-  // 16 mu of 256 columns per step through LDS (coalesced loads, padded rows)
+                                                   const double *__restrict__ wd, double *__restrict__ Xall) {
+  // 16 mu of 256 columns per step through LDS (coalesced loads, padded rows);
+  // the row of W^c_mumu(w) is the same for every thread, so the products
+  // take it from scalar registers
   __shared__ float2 xs[256][17];
   const long long c0 = (long long)blockIdx.x * 256;
   const long long c = c0 + threadIdx.x;
   double acc[RES_WMAX];
 #pragma unroll
   for (int w = 0; w < RES_WMAX; ++w) acc[w] = 0.0;
+  auto term = [&](int m0, int mm) {
+    const float2 v = xs[threadIdx.x][mm];
+    const double a2 = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+    const double *row = wd + (m0 + mm) * RES_WMAX;
+#pragma unroll
+    for (int w = 0; w < RES_WMAX; ++w) acc[w] = fma(row[w], a2, acc[w]);
+  };
   for (int m0 = 0; m0 < N; m0 += 16) {
     __syncthreads();
 #pragma unroll
@@ -838,13 +846,11 @@ __global__ __launch_bounds__(256) void k_pair_diag(const float2 *__restrict__ x,
       xs[cl][mm] = v;
     }
     __syncthreads();
-    const int mn = min(16, N - m0);
-    for (int mm = 0; mm < mn; ++mm) {
-      const float2 v = xs[threadIdx.x][mm];
-      const double a2 = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
-      const float *row = wd + (m0 + mm) * RES_WMAX;
-#pragma unroll
-      for (int w = 0; w < RES_WMAX; ++w) acc[w] += (double)row[w] * a2;
+    if (m0 + 16 <= N) {
+#pragma unroll 4
+      for (int mm = 0; mm < 16; ++mm) term(m0, mm);
+    } else {
+      for (int mm = 0; mm < N - m0; ++mm) term(m0, mm);
     }
   }
   if (c >= C) return;
@@ -898,7 +904,7 @@ int sigma_res_prepare(lrigw_ctx *c) {
   int F = 0;
   if (c->d.n_freq > RES_WMAX) return LRIGW_OK;
   if (!sigma_res_plan(c->d.n_aux, c->d.n_freq, 8, t8, F) || !sigma_res_plan(c->d.n_aux, c->d.n_freq, 4, t4, F)) return LRIGW_OK;
-  LRIGW_HIP_TRY(hipMalloc(&c->d_wd, (size_t)c->d.n_aux * RES_WMAX * sizeof(float)));
+  LRIGW_HIP_TRY(hipMalloc(&c->d_wd, (size_t)c->d.n_aux * RES_WMAX * sizeof(double)));
   t8.insert(t8.end(), t4.begin(), t4.end());   // the 8-wave lists, then the 4-wave ones
   LRIGW_HIP_TRY(hipMalloc(&c->d_sitems, t8.size() * sizeof(int)));
   LRIGW_HIP_TRY(hipMemcpy(c->d_sitems, t8.data(), t8.size() * sizeof(int), hipMemcpyHostToDevice));

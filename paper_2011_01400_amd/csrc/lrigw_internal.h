@@ -108,7 +108,7 @@ struct lrigw_ctx {
   unsigned *d_wmax = nullptr;    // FP16 split: largest |W^c(w)| as float bits [N_w]
   unsigned *d_amax = nullptr;    // FP16 split: largest |B| of each auxiliary row as float bits [Rpad]
   int *d_sitems = nullptr;       // resident-tile Sigma^c form: per-wave item lists
-  float *d_wd = nullptr;         // resident-tile Sigma^c form: Re W^c_mumu(w), [N_aux][32]
+  double *d_wd = nullptr;        // resident-tile Sigma^c form: Re W^c_mumu(w), [N_aux][32]
   int sig_res_F = 0;             // resident-tile Sigma^c form: frequencies per workgroup
   bool sig_res_ok = false;       // resident-tile Sigma^c form applies to this cell
 
