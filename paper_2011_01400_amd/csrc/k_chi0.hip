@@ -446,16 +446,29 @@ __global__ __launch_bounds__(256) void k_chi0_reduce(const typename c2t<T>::type
   const long long sstride = (long long)n_freq * ntile * TILE * TILE;
   CT zero;
   zero.x = zero.y = 0;
-  for (int s = 0; s < S; ++s) {
-    const CT *ps = src + s * sstride;
+  bool ok[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int idx = e * 256 + tid;
-      const CT v = ld_or(ps, idx, mu0 + (idx >> 6) < N && nu0 + (idx & 63) < N, zero);
-      sr[e] += (double)v.x;
-      si[e] += (double)v.y;
-    }
-  }
+  for (int e = 0; e < E; ++e) ok[e] = mu0 + ((e * 256 + tid) >> 6) < N && nu0 + (tid & 63) < N;
+  // every load of a step is issued before the first sum uses one
+  auto step = [&](auto nsl_c, int s) {
+    constexpr int NSL = decltype(nsl_c)::value;
+    CT v[NSL][E];
+#pragma unroll
+    for (int l = 0; l < NSL; ++l)
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[l][e] = ld_or(src + (s + l) * sstride, e * 256 + tid, ok[e], zero);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int l = 0; l < NSL; ++l)
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        sr[e] += (double)v[l][e].x;
+        si[e] += (double)v[l][e].y;
+      }
+  };
+  int s = 0;
+  for (; s + 2 <= S; s += 2) step(IntC<2>(), s);
+  if (s < S) step(IntC<1>(), s);
   CT *dst = chi + (long long)wsel[w] * N * N;
 #pragma unroll
   for (int e = 0; e < E; ++e) {

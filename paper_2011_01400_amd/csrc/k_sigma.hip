@@ -819,44 +819,47 @@ __global__ void k_wdiag(const float2 *__restrict__ W, int N, int n_freq, double 
   const int mu = t / RES_WMAX, w = t % RES_WMAX;
   wd[t] = w < n_freq ? (double)W[((long long)w * N + mu) * N + mu].x : 0.0;
 }
+// D[w][c] = sum_mu Re W^c_mumu(w) |x_mu(c)|^2 as an FP64 matrix product on the
+// 16x16x4 MFMA (A = W^c_mumu, 16 frequencies x 4 mu; B = |x|^2, 4 mu x 16
+// columns, so each output row is 16 consecutive columns): a wave takes 16
+// columns and all RES_WMAX frequencies (two accumulators); in the k-th product
+// of a 16-mu chunk, lane l holds mu = m0 + 4 (l / 16) + k for frequency l % 16
+// (A) and column l % 16 (B).  Entries past N or C load as zero.  No LDS, no
+// barrier: a wave past the last column leaves at once.
+static_assert(RES_WMAX == 32, "two 16-frequency accumulators");
 __global__ __launch_bounds__(256) void k_pair_diag(const float2 *__restrict__ x, long long C, int N, int n_freq,
                                                    const double *__restrict__ wd, double *__restrict__ Xall) {
-  // 16 mu of 256 columns per step through LDS (coalesced loads, padded rows);
-  // the row of W^c_mumu(w) is the same for every thread, so the products
-  // take it from scalar registers
-  __shared__ float2 xs[256][17];
-  const long long c0 = (long long)blockIdx.x * 256;
-  const long long c = c0 + threadIdx.x;
-  double acc[RES_WMAX];
-#pragma unroll
-  for (int w = 0; w < RES_WMAX; ++w) acc[w] = 0.0;
-  auto term = [&](int m0, int mm) {
-    const float2 v = xs[threadIdx.x][mm];
-    const double a2 = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
-    const double *row = wd + (m0 + mm) * RES_WMAX;
-#pragma unroll
-    for (int w = 0; w < RES_WMAX; ++w) acc[w] = fma(row[w], a2, acc[w]);
-  };
+  const int lane = threadIdx.x & 63;
+  const long long cb = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  if (cb >= C) return;
+  const long long c = cb + (lane & 15);
+  const bool cok = c < C;
+  const int kq = 4 * (lane >> 4), wl = lane & 15;
+  Mfma<double>::acc a0 = Mfma<double>::zero(), a1 = Mfma<double>::zero();
   for (int m0 = 0; m0 < N; m0 += 16) {
-    __syncthreads();
+    float2 xv[4];
+    double w0[4], w1[4];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int idx = e * 256 + threadIdx.x, cl = idx / 16, mm = idx % 16;
-      const float2 v = ld_or(x, (c0 + cl) * N + m0 + mm, c0 + cl < C && m0 + mm < N, mkcf(0.f, 0.f));
-      xs[cl][mm] = v;
+    for (int k = 0; k < 4; ++k) {
+      const int mu = m0 + kq + k;
+      xv[k] = ld_or(x, c * N + mu, cok && mu < N, mkcf(0.f, 0.f));
+      w0[k] = ld_or(wd, (long long)mu * RES_WMAX + wl, mu < N, 0.0);
+      w1[k] = ld_or(wd, (long long)mu * RES_WMAX + 16 + wl, mu < N, 0.0);
     }
-    __syncthreads();
-    if (m0 + 16 <= N) {
-#pragma unroll 4
-      for (int mm = 0; mm < 16; ++mm) term(m0, mm);
-    } else {
-      for (int mm = 0; mm < N - m0; ++mm) term(m0, mm);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double a2 = (double)xv[k].x * (double)xv[k].x + (double)xv[k].y * (double)xv[k].y;
+      a0 = Mfma<double>::mac(w0[k], a2, a0);
+      a1 = Mfma<double>::mac(w1[k], a2, a1);
     }
   }
-  if (c >= C) return;
+  if (!cok) return;
 #pragma unroll
-  for (int w = 0; w < RES_WMAX; ++w)
-    if (w < n_freq) Xall[(long long)w * C + c] = acc[w];
+  for (int r = 0; r < 4; ++r) {
+    const int w = Mfma<double>::row(lane, r);
+    if (w < n_freq) Xall[(long long)w * C + c] = a0[r];
+    if (16 + w < n_freq) Xall[(long long)(16 + w) * C + c] = a1[r];
+  }
 }
 
 // Tile lists of the resident-tile form: the 32-row tiles with work are shared
@@ -1059,7 +1062,7 @@ int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const doubl
       // the exact diagonal term first; the resident kernel adds the rest
       hipLaunchKernelGGL(k_wdiag, dim3((unsigned)((d.n_aux * RES_WMAX + 255) / 256)), dim3(256), 0, c->stream, Wf, d.n_aux,
                          d.n_freq, c->d_wd);
-      hipLaunchKernelGGL(k_pair_diag, dim3((unsigned)((Ccols + 255) / 256)), dim3(256), 0, c->stream, xf, Ccols, d.n_aux,
+      hipLaunchKernelGGL(k_pair_diag, dim3((unsigned)((Ccols + 63) / 64)), dim3(256), 0, c->stream, xf, Ccols, d.n_aux,
                          d.n_freq, c->d_wd, (double *)c->d_X);
     }
     stage_end(c, "sigma_split", ev);
