@@ -84,28 +84,148 @@ __global__ __launch_bounds__(256) void k_build_M(const typename c2t<T>::type *__
         if (r < nr) M[(((long long)k * nr_tot + rr0 + r) * nc + cb + t) * n_aux + mu] = acc[t][r];
 }
 
+// The same sums with the eigenvector rows the workgroup needs held in LDS in
+// the compute type (E1[b][r] = c_{b,r0+r}(k), E2[b][t] = c_{b,c0+colb+t}(k2)
+// for every basis function b): a wave then loads only H, and the H values of
+// basis function a + 1 are fetched into a second register set while those of
+// a are used.  Lanes of one wave may belong to different atoms (loop lengths
+// differ per lane; no barrier follows the staging one).
+template <typename T, int NR, int CPT>
+__global__ __launch_bounds__(256) void k_build_M_lds(const typename c2t<T>::type *__restrict__ H, const double2 *__restrict__ evec,
+                                                     int n_bands, int n_b, int n_aux, int nb_max, const int *__restrict__ aux_atom,
+                                                     const int *__restrict__ basis_off, const int *__restrict__ kmap, int iq,
+                                                     int nk, int r0, int nr, int c0, int nc, int rr0, int nr_tot,
+                                                     typename c2t<T>::type *__restrict__ M) {
+  typedef typename c2t<T>::type C;
+  constexpr int BC = 4 * CPT;   // columns per workgroup
+  extern __shared__ __attribute__((aligned(16))) unsigned char bm_smem[];
+  C *E1s = (C *)bm_smem;        // [n_b][NR]
+  C *E2s = E1s + n_b * NR;      // [n_b][BC]
+  const int nmb = (n_aux + 63) / 64, ncb = (nc + BC - 1) / BC;
+  const long long total = (long long)nmb * ncb * nk, per = (total + 7) / 8;
+  const long long w = (long long)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (w >= total) return;
+  const int yb = (int)(w % ncb), xb = (int)((w / ncb) % nmb), k = (int)(w / ((long long)ncb * nmb));
+  const int k2 = kmap[k * nk + iq];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int colb = yb * BC;
+  for (int e = tid; e < n_b * NR; e += 256) {
+    const int b = e / NR, r = min(e % NR, nr - 1);
+    const double2 v = evec[((long long)k * n_b + b) * n_bands + r0 + r];
+    E1s[e].x = (T)v.x;
+    E1s[e].y = (T)v.y;
+  }
+  for (int e = tid; e < n_b * BC; e += 256) {
+    const int b = e / BC, t = min(colb + e % BC, nc - 1);
+    const double2 v = evec[((long long)k2 * n_b + b) * n_bands + c0 + t];
+    E2s[e].x = (T)v.x;
+    E2s[e].y = (T)v.y;
+  }
+  __syncthreads();
+  const int mu = xb * 64 + lane;
+  const int cb = colb + wave * CPT;   // first column of this wave
+  if (mu >= n_aux || cb >= nc) return;
+  const int A = aux_atom[mu];
+  const int bo = basis_off[A];
+  const int nbA = basis_off[A + 1] - bo;
+  const int ncol = min(CPT, nc - cb);
+  const long long astr = (long long)n_bands * n_aux;
+  const C *h2base = H + ((long long)k2 * nb_max * n_bands + c0 + cb) * n_aux + mu;
+  const C *h1base = H + ((long long)k * nb_max * n_bands + r0) * n_aux + mu;
+  C acc[CPT][NR];
+#pragma unroll
+  for (int t = 0; t < CPT; ++t)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[t][r].x = acc[t][r].y = (T)0;
+  // padded columns (t >= ncol) and rows (r >= nr) repeat a valid one; their
+  // accumulators are never stored
+  auto ld = [&](C (&x2)[CPT], C (&x1)[NR], int a) {
+#pragma unroll
+    for (int t = 0; t < CPT; ++t) x2[t] = h2base[a * astr + (long long)min(t, ncol - 1) * n_aux];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) x1[r] = h1base[a * astr + (long long)min(r, nr - 1) * n_aux];
+  };
+  auto step = [&](const C (&x2)[CPT], const C (&x1)[NR], int a) {
+    const C *e1 = E1s + (bo + a) * NR;
+    const C *e2 = E2s + (bo + a) * BC + wave * CPT;
+    C ev1[NR], ev2[CPT];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) ev1[r] = e1[r];
+#pragma unroll
+    for (int t = 0; t < CPT; ++t) ev2[t] = e2[t];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int t = 0; t < CPT; ++t) acc[t][r] = cadd(acc[t][r], cadd(ccmul(ev1[r], x2[t]), ccmul(x1[r], ev2[t])));
+  };
+  if (nbA > 0) {
+    // an odd first basis function is taken alone, so the paired loop has no
+    // branch; the scheduling barriers keep each prefetch ahead of the step it
+    // overlaps
+    C h2[CPT], h1[NR], n2[CPT], n1[NR];
+    int a = nbA & 1;
+    if (a) ld(n2, n1, 0);
+    ld(h2, h1, a);
+    if (a) step(n2, n1, 0);
+    for (; a < nbA; a += 2) {
+      ld(n2, n1, a + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      step(h2, h1, a);
+      ld(h2, h1, min(a + 2, nbA - 1));
+      __builtin_amdgcn_sched_barrier(0);
+      step(n2, n1, a + 1);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < CPT; ++t)
+    if (t < ncol)
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        if (r < nr) M[(((long long)k * nr_tot + rr0 + r) * nc + cb + t) * n_aux + mu] = acc[t][r];
+}
+
+// LDS of the staged eigenvector rows (bytes); above this the direct-load form runs
+#define BM_LDS_MAX (64 * 1024)
+
 template <typename T>
 static void launch_build(lrigw_ctx *c, int iq, int r0, int nr, int c0, int nc, const int *kmap, const void *H,
                          const void *evec, void *M) {
   typedef typename c2t<T>::type C;
   const Dims &d = c->d;
-#define BM(NRV, CPT)                                                                                              \
-  hipLaunchKernelGGL((k_build_M<T, NRV, CPT>),                                                                     \
-                     dim3((unsigned)(8 * ((((long long)(d.n_aux + 63) / 64) * ((nc + 4 * CPT - 1) / (4 * CPT)) * d.n_k + 7) / 8))), \
-                     dim3(256), 0, c->stream, (const C *)H, (const double2 *)evec, d.n_bands, d.n_b, d.n_aux, d.nb_max, \
-                     c->d_aux_atom, c->d_basis_off, kmap, iq, d.n_k, r0 + rb, nrl, c0, nc, rb, nr, (C *)M)
+  const long long nmb = (d.n_aux + 63) / 64;
+#define BM_GRID(CPT) dim3((unsigned)(8 * ((nmb * ((nc + 4 * CPT - 1) / (4 * CPT)) * d.n_k + 7) / 8)))
+#define BM_ARGS(NRV) (const C *)H, (const double2 *)evec, d.n_bands, d.n_b, d.n_aux, d.nb_max, c->d_aux_atom, c->d_basis_off, \
+                     kmap, iq, d.n_k, r0 + rb, nrl, c0, nc, rb, nr, (C *)M
+#define BM(NRV, CPT) hipLaunchKernelGGL((k_build_M<T, NRV, CPT>), BM_GRID(CPT), dim3(256), 0, c->stream, BM_ARGS(NRV))
+#define BML(NRV, CPT)                                                                                               \
+  hipLaunchKernelGGL((k_build_M_lds<T, NRV, CPT>), BM_GRID(CPT), dim3(256),                                         \
+                     (size_t)d.n_b * (NRV + 4 * CPT) * sizeof(C), c->stream, BM_ARGS(NRV))
   // rows in blocks of at most 8 (one launch each)
   for (int rb = 0; rb < nr; rb += 8) {
     const int nrl = std::min(8, nr - rb);
+    const bool lds = (size_t)d.n_b * (8 + 16) * sizeof(C) <= BM_LDS_MAX;
     if constexpr (sizeof(T) == 4) {
-      if (nrl <= 4) BM(4, 4);
-      else BM(8, 4);
+      if (lds) {
+        if (nrl <= 4) BML(4, 4);
+        else BML(8, 4);
+      } else {
+        if (nrl <= 4) BM(4, 4);
+        else BM(8, 4);
+      }
     } else {
-      if (nrl <= 4) BM(4, 4);
-      else BM(8, 2);
+      if (lds) {
+        if (nrl <= 4) BML(4, 2);
+        else BML(8, 2);
+      } else {
+        if (nrl <= 4) BM(4, 4);
+        else BM(8, 2);
+      }
     }
   }
+#undef BML
 #undef BM
+#undef BM_ARGS
+#undef BM_GRID
 }
 
 int run_build_M(lrigw_ctx *c, int iq, int slice, const void *H, const void *evec, void *M_out) {
