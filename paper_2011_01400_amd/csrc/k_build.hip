@@ -129,7 +129,9 @@ __global__ __launch_bounds__(256) void k_build_M_lds(const typename c2t<T>::type
   const int bo = basis_off[A];
   const int nbA = basis_off[A + 1] - bo;
   const int ncol = min(CPT, nc - cb);
-  const long long astr = (long long)n_bands * n_aux;
+  // offsets inside one k point's H block (nb_max * n_bands * n_aux elements)
+  // in 32 bits
+  const int astr = n_bands * n_aux;
   const C *h2base = H + ((long long)k2 * nb_max * n_bands + c0 + cb) * n_aux + mu;
   const C *h1base = H + ((long long)k * nb_max * n_bands + r0) * n_aux + mu;
   C acc[CPT][NR];
@@ -141,9 +143,9 @@ __global__ __launch_bounds__(256) void k_build_M_lds(const typename c2t<T>::type
   // accumulators are never stored
   auto ld = [&](C (&x2)[CPT], C (&x1)[NR], int a) {
 #pragma unroll
-    for (int t = 0; t < CPT; ++t) x2[t] = h2base[a * astr + (long long)min(t, ncol - 1) * n_aux];
+    for (int t = 0; t < CPT; ++t) x2[t] = h2base[a * astr + min(t, ncol - 1) * n_aux];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) x1[r] = h1base[a * astr + (long long)min(r, nr - 1) * n_aux];
+    for (int r = 0; r < NR; ++r) x1[r] = h1base[a * astr + min(r, nr - 1) * n_aux];
   };
   auto step = [&](const C (&x2)[CPT], const C (&x1)[NR], int a) {
     const C *e1 = E1s + (bo + a) * NR;
