@@ -761,22 +761,53 @@ __global__ __launch_bounds__(64 * NWV) void k_sigma_res(const us16 *__restrict__
     // already in X, from the exact x), with x_mu from the resident tile (the
     // sum of its parts: the same x as in Z), in units of the column scale; the
     // tile's eight terms per lane are summed in FP32, the tiles in FP64
+    // the tile holds conj(x) / sx = xr - i xi' with xi' = -Im(x) / sx
     float tz[4] = {0.f, 0.f, 0.f, 0.f};
+    if ((N & 3) == 0) {
+      // a lane's four rows 16 i + 4 (lane / 16) + q are consecutive and, with
+      // N = 0 (mod 4), start on a multiple of 4 (tiles end at row N - 1): one
+      // 8-byte read per plane; a group above row 0 reads row 0 and adds zero
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int mu = r0 + 16 * i + Mfma<float>::row(lane, q);
-        if (mu < 0 || mu >= N) continue;
+      for (int i = 0; i < 2; ++i) {
+        const int m0 = r0 + 16 * i + 4 * g;
+        const bool ok = m0 >= 0;
+        const int ma = ok ? m0 : 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int cl = 16 * j + col;
-          // the tile holds conj(x) / sx = xr - i xi' with xi' = -Im(x) / sx
-          const float xr = part_f<H>(Xs[0][cl][mu]) + part_f<H>(Xs[2][cl][mu]);
-          const float xc = part_f<H>(Xs[1][cl][mu]) + part_f<H>(Xs[3][cl][mu]);
-          tz[j] = fmaf(xr, zr[i][j][q], fmaf(xc, zi[i][j][q], tz[j]));   // Re(x Z)
+          uint2 pv[4];
+#pragma unroll
+          for (int pl = 0; pl < 4; ++pl) pv[pl] = *(const uint2 *)&Xs[pl][cl][ma];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            float xp[4];
+#pragma unroll
+            for (int pl = 0; pl < 4; ++pl) {
+              const unsigned wv = (q < 2) ? pv[pl].x : pv[pl].y;
+              xp[pl] = part_f<H>((us16)((q & 1) ? (wv >> 16) : (wv & 0xffffu)));
+            }
+            const float xr = ok ? xp[0] + xp[2] : 0.f;
+            const float xc = ok ? xp[1] + xp[3] : 0.f;
+            tz[j] = fmaf(xr, zr[i][j][q], fmaf(xc, zi[i][j][q], tz[j]));   // Re(x Z)
+          }
         }
       }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int mu = r0 + 16 * i + Mfma<float>::row(lane, q);
+          if (mu < 0 || mu >= N) continue;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int cl = 16 * j + col;
+            const float xr = part_f<H>(Xs[0][cl][mu]) + part_f<H>(Xs[2][cl][mu]);
+            const float xc = part_f<H>(Xs[1][cl][mu]) + part_f<H>(Xs[3][cl][mu]);
+            tz[j] = fmaf(xr, zr[i][j][q], fmaf(xc, zi[i][j][q], tz[j]));   // Re(x Z)
+          }
+        }
+    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) psum[j] += 2.0 * (double)fw * (double)tz[j];
   }
