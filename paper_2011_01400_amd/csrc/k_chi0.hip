@@ -362,11 +362,12 @@ __global__ __launch_bounds__(256, NW == 2 ? 2 : 1) void k_chi0_split(const us16 
             bis[p][e] = pi_[p];
           }
         }
-        u32x4 br[NS], bi[NS];
+        u32x4 br[NS], bi[NS], nbi[NS];
 #pragma unroll
         for (int p = 0; p < NS; ++p) {
           br[p] = *(const u32x4 *)brs[p];
           bi[p] = *(const u32x4 *)bis[p];
+          nbi[p] = bi[p] ^ 0x80008000u;   // the sign is taken on this wave's own side
         }
 #pragma unroll
         for (int si = 0; si < NSI; ++si) {
@@ -374,14 +375,13 @@ __global__ __launch_bounds__(256, NW == 2 ? 2 : 1) void k_chi0_split(const us16 
           for (int p = 0; p < NS; ++p) {
             const u32x4 ar = *(const u32x4 *)&As[b][2 * p][16 * si + col][8 * g];
             const u32x4 ai = *(const u32x4 *)&As[b][2 * p + 1][16 * si + col][8 * g];
-            const u32x4 nar = ar ^ 0x80008000u;
             // a conj(b): re = ar br + ai bi, im = ai br - ar bi
 #pragma unroll
             for (int q = 0; q + p < NS; ++q) {
               re[w][si] = mfma_p<H>(ar, br[q], re[w][si]);
               re[w][si] = mfma_p<H>(ai, bi[q], re[w][si]);
               im[w][si] = mfma_p<H>(ai, br[q], im[w][si]);
-              im[w][si] = mfma_p<H>(nar, bi[q], im[w][si]);
+              im[w][si] = mfma_p<H>(ar, nbi[q], im[w][si]);
             }
           }
         }
