@@ -268,14 +268,25 @@ __global__ __launch_bounds__(256, NW == 2 ? 2 : 1) void k_chi0_split(const us16 
                                                     const float *__restrict__ delta, const double *__restrict__ omega,
                                                     const int *__restrict__ wsel, const int *__restrict__ run, long long K,
                                                     long long Kp, int Npad, int n_freq, long long Ks, long long ntile,
-                                                    const unsigned *__restrict__ amax, int N, float2 *__restrict__ part) {
+                                                    const unsigned *__restrict__ amax, int N, float2 *__restrict__ part,
+                                                    int nsplit) {
   if (run && *run == 0) return;
   __shared__ __attribute__((aligned(16))) us16 As[2][NS * 2][TILE][KCB + PAD];
   __shared__ __attribute__((aligned(16))) float wtab[2][NW][KCB];   // 2D/(D^2 + w^2) of the chunk
+  // work item (K split s, tile, frequency group fg), fg fastest: each XCD
+  // (workgroup id mod 8) takes a contiguous range, so the frequency groups
+  // that read the same A and B slabs run back to back in one L2
+  const int nfg = (n_freq + NW - 1) / NW;
+  const long long total = (long long)nfg * ntile * nsplit, per = (total + 7) / 8;
+  const long long wi = (long long)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (wi >= total) return;
+  const int fgi = (int)(wi % nfg);
+  const int tile = (int)((wi / nfg) % ntile);
+  const int ks = (int)(wi / ((long long)nfg * ntile));
   int I, J;
-  tri_decode(blockIdx.x, I, J);
-  const int w0 = blockIdx.y * NW;
-  const long long kb = (long long)blockIdx.z * Ks;
+  tri_decode(tile, I, J);
+  const int w0 = fgi * NW;
+  const long long kb = (long long)ks * Ks;
   const long long ke = min(K, kb + Ks);
   const int mu0 = I * TILE, nu0 = J * TILE;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, g = lane >> 4;
@@ -405,7 +416,7 @@ store:
 #pragma unroll
   for (int w = 0; w < NW; ++w) {
     if (w0 + w >= n_freq) continue;
-    float2 *dst = part + (((long long)blockIdx.z * n_freq + w0 + w) * ntile + blockIdx.x) * (TILE * TILE);
+    float2 *dst = part + (((long long)ks * n_freq + w0 + w) * ntile + tile) * (TILE * TILE);
     const int cl = 16 * wave + col;
     const float fcol = H ? pow2_scale(__uint_as_float(amax[nu0 + cl < N ? nu0 + cl : 0])) / wsc[w] : 1.f;
 #pragma unroll
@@ -603,13 +614,16 @@ int run_chi0_sel(lrigw_ctx *c, int iq, const void *M, const double *eig, int app
       }
       stage_end(c, "chi0_split", ev);
       stage_begin(c, "chi0_mfma", &ev);
-#define BF16_ARGS Apd, Btd, Df, c->d_omega, wsel, run, K, Kp, Npad, n_sel, Ks, ntile, c->d_amax, d.n_aux, Pf
+      // 1D over (K split, tile, frequency group), split over the XCDs
+      const long long sitems = (long long)((n_sel + NW - 1) / NW) * ntile * S;
+      const dim3 sgrid((unsigned)(8 * ((sitems + 7) / 8)));
+#define BF16_ARGS Apd, Btd, Df, c->d_omega, wsel, run, K, Kp, Npad, n_sel, Ks, ntile, c->d_amax, d.n_aux, Pf, S
 #define SPLIT_LAUNCH(NS_, H_)                                                                                            \
   do {                                                                                                                 \
-    if (NW == 4 && p16) hipLaunchKernelGGL((k_chi0_split<NS_, 4, 16, H_>), grid, dim3(256), 0, c->stream, BF16_ARGS); \
-    else if (NW == 4) hipLaunchKernelGGL((k_chi0_split<NS_, 4, 8, H_>), grid, dim3(256), 0, c->stream, BF16_ARGS);   \
-    else if (p16) hipLaunchKernelGGL((k_chi0_split<NS_, 2, 16, H_>), grid, dim3(256), 0, c->stream, BF16_ARGS);      \
-    else hipLaunchKernelGGL((k_chi0_split<NS_, 2, 8, H_>), grid, dim3(256), 0, c->stream, BF16_ARGS);                \
+    if (NW == 4 && p16) hipLaunchKernelGGL((k_chi0_split<NS_, 4, 16, H_>), sgrid, dim3(256), 0, c->stream, BF16_ARGS); \
+    else if (NW == 4) hipLaunchKernelGGL((k_chi0_split<NS_, 4, 8, H_>), sgrid, dim3(256), 0, c->stream, BF16_ARGS);   \
+    else if (p16) hipLaunchKernelGGL((k_chi0_split<NS_, 2, 16, H_>), sgrid, dim3(256), 0, c->stream, BF16_ARGS);      \
+    else hipLaunchKernelGGL((k_chi0_split<NS_, 2, 8, H_>), sgrid, dim3(256), 0, c->stream, BF16_ARGS);                \
   } while (0)
       if (H) SPLIT_LAUNCH(2, true);
       else if (NS == 2) SPLIT_LAUNCH(2, false);
