@@ -357,29 +357,43 @@ __global__ __launch_bounds__(256, NW == 2 ? 2 : 1) void k_chi0_split(const us16 
 #pragma unroll
       for (int w = 0; w < NW; ++w) {
         // this wave's 16 columns, weighted for frequency w and split
-        us16 brs[NS][8], bis[NS][8];
         float wt8[8];
         *(float4 *)&wt8[0] = *(const float4 *)&wtab[b][w][8 * g];
         *(float4 *)&wt8[4] = *(const float4 *)&wtab[b][w][8 * g + 4];
+        u32x4 br[NS], bi[NS], nbi[NS];
+        if constexpr (H && NS == 2) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const float wt = wt8[e];
-          us16 pr_[NS], pi_[NS];
-          split_n<NS, H>(wt * bcur[e].x, pr_);
-          split_n<NS, H>(wt * bcur[e].y, pi_);
+          for (int e = 0; e < 8; e += 2) {
+            unsigned h, l;
+            split2_h_pair(wt8[e], bcur[e].x, wt8[e + 1], bcur[e + 1].x, h, l);
+            br[0][e / 2] = h;
+            br[1][e / 2] = l;
+            split2_h_pair(wt8[e], bcur[e].y, wt8[e + 1], bcur[e + 1].y, h, l);
+            bi[0][e / 2] = h;
+            bi[1][e / 2] = l;
+          }
+        } else {
+          us16 brs[NS][8], bis[NS][8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const float wt = wt8[e];
+            us16 pr_[NS], pi_[NS];
+            split_n<NS, H>(wt * bcur[e].x, pr_);
+            split_n<NS, H>(wt * bcur[e].y, pi_);
+#pragma unroll
+            for (int p = 0; p < NS; ++p) {
+              brs[p][e] = pr_[p];
+              bis[p][e] = pi_[p];
+            }
+          }
 #pragma unroll
           for (int p = 0; p < NS; ++p) {
-            brs[p][e] = pr_[p];
-            bis[p][e] = pi_[p];
+            br[p] = *(const u32x4 *)brs[p];
+            bi[p] = *(const u32x4 *)bis[p];
           }
         }
-        u32x4 br[NS], bi[NS], nbi[NS];
 #pragma unroll
-        for (int p = 0; p < NS; ++p) {
-          br[p] = *(const u32x4 *)brs[p];
-          bi[p] = *(const u32x4 *)bis[p];
-          nbi[p] = bi[p] ^ 0x80008000u;   // the sign is taken on this wave's own side
-        }
+        for (int p = 0; p < NS; ++p) nbi[p] = bi[p] ^ 0x80008000u;   // the sign is taken on this wave's own side
 #pragma unroll
         for (int si = 0; si < NSI; ++si) {
 #pragma unroll

@@ -71,6 +71,24 @@ __device__ inline void split_n(float v, us16 *out) {
   }
 }
 
+// Two-part FP16 split of the products a0 b0 and a1 b1, packed (element 0 in
+// the low half): hi = f16(a b) and lo = f16(a b - hi), each from the exact
+// product in one mixed-precision FMA (v_fma_mixlo/mixhi_f16 write one half of
+// the destination and keep the other), two instructions per value.
+__device__ inline void split2_h_pair(float a0, float b0, float a1, float b1, unsigned &hi, unsigned &lo) {
+  unsigned h, l;
+  asm("v_fma_mixlo_f16 %0, %1, %2, 0\n\t"
+      "v_fma_mixhi_f16 %0, %3, %4, 0"
+      : "=&v"(h)
+      : "v"(a0), "v"(b0), "v"(a1), "v"(b1));
+  asm("v_fma_mixlo_f16 %0, %2, %3, -%1 op_sel_hi:[0,0,1]\n\t"
+      "v_fma_mixhi_f16 %0, %4, %5, -%1 op_sel:[0,0,1] op_sel_hi:[0,0,1]"
+      : "=&v"(l)
+      : "v"(h), "v"(a0), "v"(b0), "v"(a1), "v"(b1));
+  hi = h;
+  lo = l;
+}
+
 // Power-of-two scale for a block whose largest magnitude is m: m / scale <
 // 2^15 (m = 0 or not finite: 1).  inv_pow2_scale is its exact reciprocal.
 __device__ inline float pow2_scale(float m) {
