@@ -786,9 +786,10 @@ __global__ __launch_bounds__(64 * NWV) void k_sigma_res(const us16 *__restrict__
               const unsigned wv = (q < 2) ? pv[pl].x : pv[pl].y;
               xp[pl] = part_f<H>((us16)((q & 1) ? (wv >> 16) : (wv & 0xffffu)));
             }
-            const float xr = ok ? xp[0] + xp[2] : 0.f;
-            const float xc = ok ? xp[1] + xp[3] : 0.f;
-            tz[j] = fmaf(xr, zr[i][j][q], fmaf(xc, zi[i][j][q], tz[j]));   // Re(x Z)
+            // Re(x Z), each part taken on its own (the FP16 parts enter the
+            // FMAs directly, with no separate conversion and sum)
+            const float zrv = ok ? zr[i][j][q] : 0.f, ziv = ok ? zi[i][j][q] : 0.f;
+            tz[j] = fmaf(xp[3], ziv, fmaf(xp[1], ziv, fmaf(xp[2], zrv, fmaf(xp[0], zrv, tz[j]))));
           }
         }
       }
