@@ -665,7 +665,7 @@ __global__ __launch_bounds__(64 * NWV) void k_sigma_res(const us16 *__restrict__
     // 4 x 64 rows of g8 <= RES_NPAD/8 16-byte pieces: wave w takes rows
     // w, w + NWV, ..., lane = piece (no index division); all loads of a batch
     // in flight before its LDS stores
-    constexpr int ROWS = 4 * TILE / NWV, BATCH = 8;
+    constexpr int ROWS = 4 * TILE / NWV, BATCH = ROWS;
     const bool lact = lane < g8;
 #pragma unroll
     for (int r0b = 0; r0b < ROWS; r0b += BATCH) {
