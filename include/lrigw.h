@@ -328,10 +328,14 @@ int lrigw_tune(lrigw_ctx *ctx, const void *H, const void *evec, const double *ei
  * not admit. */
 int lrigw_set_tiles(lrigw_ctx *ctx, int nw, int splits, int pad, int sigma_variant);
 
-/* Per-kernel device time (ms, HIP events on the context stream) accumulated
- * since the last reset, for the named stages "build_M", "chi0", "screen",
- * "sigma_c", "qp", "lri_ft".  Timing is recorded only after
- * lrigw_set_timing(ctx, 1).  Returns -1.0 for an unknown stage. */
+/* Per-kernel device time (ms, HIP events on the stream each stage runs on)
+ * accumulated since the last reset, for the named stages "lri_ft", "build_M",
+ * "chi0" (with its parts "chi0_split" and "chi0_mfma"), "screen", "sigma_c"
+ * (with "sigma_split" and "sigma_mfma") and "qp".  lrigw_set_timing(ctx, on):
+ * on = 0 records nothing, 1 every stage, 2 only the two MFMA kernel stages
+ * "chi0_mfma" and "sigma_mfma" (two events per launch, nothing recorded
+ * between the other kernels of a pass); other values return LRIGW_ERR_ARG.
+ * lrigw_stage_ms returns -1.0 for an unknown stage. */
 int lrigw_set_timing(lrigw_ctx *ctx, int on);
 double lrigw_stage_ms(lrigw_ctx *ctx, const char *stage, long long *launches);
 void lrigw_reset_timing(lrigw_ctx *ctx);

@@ -21,16 +21,23 @@ int lrigw_launch_check(const char *what) {
 size_t lrigw_csize(const lrigw_ctx *c) { return c->precision == LRIGW_FP64 ? sizeof(double2) : sizeof(float2); }
 long long lrigw_K(const lrigw_ctx *c) { return (long long)c->d.n_k * c->d.n_occ * c->d.n_unocc; }
 
+// timing mode 2 records only the two MFMA kernel stages (two events per
+// launch, nothing between the other kernels of a pass)
+static bool stage_timed(const lrigw_ctx *c, const char *name) {
+  if (c->timing == 0) return false;
+  if (c->timing == 1) return true;
+  return std::strcmp(name, "chi0_mfma") == 0 || std::strcmp(name, "sigma_mfma") == 0;
+}
+
 void stage_begin(lrigw_ctx *c, const char *name, hipEvent_t *ev) {
   *ev = nullptr;
-  if (!c->timing) return;
+  if (!stage_timed(c, name)) return;
   if (hipEventCreate(ev) != hipSuccess) { *ev = nullptr; return; }
   hipEventRecord(*ev, c->stream);
-  (void)name;
 }
 
 void stage_end(lrigw_ctx *c, const char *name, hipEvent_t ev) {
-  if (!c->timing || !ev) return;
+  if (!ev || !stage_timed(c, name)) return;
   hipEvent_t e1;
   if (hipEventCreate(&e1) != hipSuccess) return;
   hipEventRecord(e1, c->stream);
@@ -381,7 +388,8 @@ int lrigw_g0w0(lrigw_ctx *c, const void *H, const void *evec, const double *eig,
 
 int lrigw_set_timing(lrigw_ctx *c, int on) {
   if (!c) return LRIGW_ERR_ARG;
-  c->timing = on != 0;
+  if (on < 0 || on > 2) return LRIGW_ERR_ARG;
+  c->timing = on;
   return LRIGW_OK;
 }
 

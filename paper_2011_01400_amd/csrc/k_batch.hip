@@ -46,8 +46,8 @@ static int autotune_chi0(lrigw_ctx *c, const lrigw_batch_cell &cell, int *nw_out
   hipEvent_t e0, e1;
   LRIGW_HIP_TRY(hipEventCreate(&e0));
   LRIGW_HIP_TRY(hipEventCreate(&e1));
-  const bool timing = c->timing;
-  c->timing = false;
+  const int timing = c->timing;
+  c->timing = 0;
   const bool split = ns_chi(c->precision) > 0;
   int bpad = c->chi_pad;
   for (int cand = 0; cand < (split ? 4 : 2); ++cand) {
@@ -154,8 +154,8 @@ static int batch_capture(lrigw_batch *b) {
     b->saved[i] = c->stream;
     c->stream = b->cs[i];
     c->capturing = true;
-    const bool timing = c->timing;
-    c->timing = false;
+    const int timing = c->timing;
+    c->timing = 0;
     rc = run_pass(c, cl.H, cl.evec, cl.eig, cl.V, cl.p, cl.omega_cell, cl.e_static, cl.n_par, 0, c->d.n_k, cl.sigma,
                   cl.e_qp, cl.z, nullptr);
     c->timing = timing;

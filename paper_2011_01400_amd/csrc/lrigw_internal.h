@@ -137,7 +137,7 @@ struct lrigw_ctx {
   double sur_threshold = 0.0;
 
   // timing
-  bool timing = false;
+  int timing = 0;   // 0 off, 1 every stage, 2 the two MFMA kernel stages only
   std::map<std::string, StageTimer> stages;
 };
 

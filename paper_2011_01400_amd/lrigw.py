@@ -287,8 +287,10 @@ class Context:
         self._check(self.lib.lrigw_set_surrogate(self.h, sg.h if sg is not None else None, float(threshold)),
                     "lrigw_set_surrogate")
 
-    def set_timing(self, on=True):
-        self._check(self.lib.lrigw_set_timing(self.h, int(bool(on))), "lrigw_set_timing")
+    def set_timing(self, on=True, kernels_only=False):
+        """on: record stage times; kernels_only: only the two MFMA kernel stages."""
+        mode = (2 if kernels_only else 1) if on else 0
+        self._check(self.lib.lrigw_set_timing(self.h, mode), "lrigw_set_timing")
 
     def stage_ms(self, stage):
         n = ctypes.c_longlong(0)
