@@ -97,18 +97,28 @@ __global__ __launch_bounds__(256) void k_build_M_lds(const typename c2t<T>::type
                                                      int nk, int r0, int nr, int c0, int nc, int rr0, int nr_tot,
                                                      typename c2t<T>::type *__restrict__ M) {
   typedef typename c2t<T>::type C;
-  constexpr int BC = 4 * CPT;   // columns per workgroup
+  // thread <-> one entry of the flattened (column group of CPT columns, mu)
+  // space of one k point, mu fastest, 256 entries per workgroup: a wave may
+  // straddle two column groups, and no wave is left with a few lanes of a
+  // last mu block.  Each XCD (workgroup id mod 8) takes a contiguous range of
+  // workgroups, so those of one k share its row panel in one L2.
+  const int ngr = (nc + CPT - 1) / CPT;
+  const long long per_k = (long long)ngr * n_aux;
+  const int wgk = (int)((per_k + 255) / 256);
+  const long long total = (long long)wgk * nk, per = (total + 7) / 8;
+  const long long w = (long long)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (w >= total) return;
+  const int k = (int)(w / wgk);
+  const long long f0 = (w % wgk) * 256;
+  const int g0 = (int)(f0 / n_aux);                        // first column group of the workgroup
+  const int g1 = (int)min((long long)ngr - 1, (f0 + 255) / n_aux);
+  const int BC = (g1 - g0 + 1) * CPT;                      // columns staged
   extern __shared__ __attribute__((aligned(16))) unsigned char bm_smem[];
   C *E1s = (C *)bm_smem;        // [n_b][NR]
   C *E2s = E1s + n_b * NR;      // [n_b][BC]
-  const int nmb = (n_aux + 63) / 64, ncb = (nc + BC - 1) / BC;
-  const long long total = (long long)nmb * ncb * nk, per = (total + 7) / 8;
-  const long long w = (long long)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  if (w >= total) return;
-  const int yb = (int)(w % ncb), xb = (int)((w / ncb) % nmb), k = (int)(w / ((long long)ncb * nmb));
   const int k2 = kmap[k * nk + iq];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int colb = yb * BC;
+  const int tid = threadIdx.x;
+  const int colb = g0 * CPT;
   for (int e = tid; e < n_b * NR; e += 256) {
     const int b = e / NR, r = min(e % NR, nr - 1);
     const double2 v = evec[((long long)k * n_b + b) * n_bands + r0 + r];
@@ -122,9 +132,11 @@ __global__ __launch_bounds__(256) void k_build_M_lds(const typename c2t<T>::type
     E2s[e].y = (T)v.y;
   }
   __syncthreads();
-  const int mu = xb * 64 + lane;
-  const int cb = colb + wave * CPT;   // first column of this wave
-  if (mu >= n_aux || cb >= nc) return;
+  const long long f = f0 + tid;
+  if (f >= per_k) return;
+  const int gi = (int)(f / n_aux), mu = (int)(f - (long long)gi * n_aux);
+  const int cb = gi * CPT;          // first column of this thread
+  const int lcol = cb - colb;       // its offset among the staged columns
   const int A = aux_atom[mu];
   const int bo = basis_off[A];
   const int nbA = basis_off[A + 1] - bo;
@@ -149,7 +161,7 @@ __global__ __launch_bounds__(256) void k_build_M_lds(const typename c2t<T>::type
   };
   auto step = [&](const C (&x2)[CPT], const C (&x1)[NR], int a) {
     const C *e1 = E1s + (bo + a) * NR;
-    const C *e2 = E2s + (bo + a) * BC + wave * CPT;
+    const C *e2 = E2s + (bo + a) * BC + lcol;
     C ev1[NR], ev2[CPT];
 #pragma unroll
     for (int r = 0; r < NR; ++r) ev1[r] = e1[r];
@@ -196,16 +208,21 @@ static void launch_build(lrigw_ctx *c, int iq, int r0, int nr, int c0, int nc, c
   const Dims &d = c->d;
   const long long nmb = (d.n_aux + 63) / 64;
 #define BM_GRID(CPT) dim3((unsigned)(8 * ((nmb * ((nc + 4 * CPT - 1) / (4 * CPT)) * d.n_k + 7) / 8)))
+  // flattened form: 256 (column group, mu) entries per workgroup, staging the
+  // eigenvector columns of at most 256 / n_aux + 2 column groups
+#define BML_WGK(CPT) ((((long long)(nc + CPT - 1) / CPT) * d.n_aux + 255) / 256)
+#define BML_GRID(CPT) dim3((unsigned)(8 * ((BML_WGK(CPT) * d.n_k + 7) / 8)))
+#define BML_GROUPS(CPT) std::min<long long>((nc + CPT - 1) / CPT, 256 / d.n_aux + 2)
 #define BM_ARGS(NRV) (const C *)H, (const double2 *)evec, d.n_bands, d.n_b, d.n_aux, d.nb_max, c->d_aux_atom, c->d_basis_off, \
                      kmap, iq, d.n_k, r0 + rb, nrl, c0, nc, rb, nr, (C *)M
 #define BM(NRV, CPT) hipLaunchKernelGGL((k_build_M<T, NRV, CPT>), BM_GRID(CPT), dim3(256), 0, c->stream, BM_ARGS(NRV))
 #define BML(NRV, CPT)                                                                                               \
-  hipLaunchKernelGGL((k_build_M_lds<T, NRV, CPT>), BM_GRID(CPT), dim3(256),                                         \
-                     (size_t)d.n_b * (NRV + 4 * CPT) * sizeof(C), c->stream, BM_ARGS(NRV))
+  hipLaunchKernelGGL((k_build_M_lds<T, NRV, CPT>), BML_GRID(CPT), dim3(256),                                        \
+                     (size_t)d.n_b * (NRV + BML_GROUPS(CPT) * CPT) * sizeof(C), c->stream, BM_ARGS(NRV))
   // rows in blocks of at most 8 (one launch each)
   for (int rb = 0; rb < nr; rb += 8) {
     const int nrl = std::min(8, nr - rb);
-    const bool lds = (size_t)d.n_b * (8 + 16) * sizeof(C) <= BM_LDS_MAX;
+    const bool lds = (size_t)d.n_b * (8 + BML_GROUPS(4) * 4) * sizeof(C) <= BM_LDS_MAX;
     if constexpr (sizeof(T) == 4) {
       if (lds) {
         if (nrl <= 4) BML(4, 4);
@@ -227,6 +244,9 @@ static void launch_build(lrigw_ctx *c, int iq, int r0, int nr, int c0, int nc, c
 #undef BML
 #undef BM
 #undef BM_ARGS
+#undef BML_GROUPS
+#undef BML_GRID
+#undef BML_WGK
 #undef BM_GRID
 }
 
