@@ -9,6 +9,8 @@ for both the response and the self-energy (a reordering of the finite sums):
           x(k,q) = C(k,k-q) (QP bands x all)
           Sigma^c_n(k, i w_i) += ...             Eq. GW_selfe_element
   Pade continuation and the QP equation.
+The exchange self-energy (the bare-Coulomb term of Eq. GW_selfe_element) is
+`sigma_x`, from the pairs of QP bands at k and occupied bands at k-q.
 """
 from __future__ import annotations
 
@@ -41,6 +43,19 @@ class Oracle:
         """C^mu_{nm}(k,k-q) for QP bands n and all m: [len(ks)][N_aux][N_qp][N_bands]."""
         ks = range(self.sys.n_k) if ks is None else ks
         return np.stack([self.tb.mo(k, self.kmq[k, q], self.qp, self.allb) for k in ks])
+
+    def x_occ(self, q, ks=None):
+        """C^mu_{nm}(k,k-q) for QP bands n and occupied m: [len(ks)][N_aux][N_qp][N_occ]."""
+        ks = range(self.sys.n_k) if ks is None else ks
+        return np.stack([self.tb.mo(k, self.kmq[k, q], self.qp, self.occ) for k in ks])
+
+    def sigma_x_q(self, q, ks=None):
+        """Contribution of q to Sigma^x for the k points `ks` (default all)."""
+        return selfenergy.sigma_x_q(self.x_occ(q, ks), self.sys.V[q], self.sys.n_k)
+
+    def sigma_x(self, ks=None):
+        """Sigma^x_n(k) [len(ks)][N_qp], summed over every q."""
+        return sum(self.sigma_x_q(q, ks) for q in range(self.sys.n_k))
 
     def chi0(self, q, B=None, omega=None):
         B = self.B(q) if B is None else B

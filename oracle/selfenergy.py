@@ -15,6 +15,15 @@ the whole axis folds onto (0, inf):
 
 with (w_j, g_j) the frequency grid.  `sigma_c_unfolded` evaluates the same
 integral with both signs of w' kept separately; the two must agree.
+
+The exchange part is the bare-Coulomb term of the same equation (W_0 = V +
+W^c).  V does not depend on w', and the frequency integral of the Green's
+function taken with the equal-time convergence factor of the exchange term
+gives 2 pi for an occupied band and 0 otherwise, so
+
+  Sigma^x_n(k) = -sum_q w_q sum_{m occ} sum_{mu nu} C^mu_{nm}(k,k-q) V_{mu nu}(q) C^nu_{mn}(k-q,k),
+
+static, with V(0) the truncated Coulomb matrix as in the screening (Sec. III B).
 """
 from __future__ import annotations
 
@@ -64,3 +73,14 @@ def sigma_c_unfolded(X, eig, kmq, q, mu, omega, weight, n_q):
                 den = 1j * w - 1j * sgn * omega[None, :] + mu - em[:, None]     # [nb][nw]
                 sig[k, :, i] += np.einsum("nmj,mj->n", X[k] * weight[None, None, :], 1.0 / den)
     return -(1.0 / (2.0 * np.pi)) * sig / n_q
+
+
+def sigma_x_q(x_occ, V, n_q):
+    """Contribution of one q to the exchange self-energy.
+
+    x_occ: [N_k][N_aux][N_qp][N_occ] = C^mu_{nm}(k,k-q) for occupied m.
+    V: [N_aux][N_aux] Coulomb matrix of this q.  Returns float64 [N_k][N_qp]:
+    -(1/N_q) sum_{m occ} X_nm with X from `pair_weights` (V as its one frequency).
+    """
+    X = pair_weights(x_occ, V[None])[..., 0]
+    return -X.real.sum(axis=2) / n_q
