@@ -168,6 +168,29 @@ def other_kernel(sysm, stages, precision, rl):
     return out
 
 
+def sigma_x_timing(run, sysm, dev, reps=3):
+    """Exchange self-energy over every q (lrigw_sigma_x_pass: the exchange
+    pairs of each q and their FP64 quadratic form with V(q)), outside the timed
+    region of the metric.  Algorithmic flops per pass: 8 N_aux^2 per pair,
+    N_k N_qp N_occ pairs per q, on the FP64 MFMA GEMM."""
+    torch = run.torch
+    sp = sysm.spec
+    sx = torch.zeros((sysm.n_k, sp.n_qp), dtype=torch.float64, device="cuda")
+    run.ctx.sigma_x_pass(run.H, dev["evec"], dev["V"], sx)   # first call allocates its workspace
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        run.ctx.sigma_x_pass(run.H, dev["evec"], dev["V"], sx)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    flops = 8.0 * sysm.n_aux ** 2 * sysm.n_k * sp.n_qp * sp.n_occ * sysm.n_k
+    a = flops / dt / 1e12
+    v = sx.cpu().numpy()
+    return {"ms_per_pass": round(dt * 1e3, 3), "bound": "mfma", "achieved": round(a, 2), "peak": PEAK_TFLOPS["fp64"],
+            "unit": "TFLOP/s", "frac": round(a / PEAK_TFLOPS["fp64"], 4), "flops_per_pass": flops,
+            "range_ha": [round(float(v.min()), 6), round(float(v.max()), 6)]}
+
+
 def cpu_baseline(sysm):
     """FP64 oracle on a bounded sample of the same workload: one q (q = 1), all
     N_w frequencies, all k points of chi0 and Sigma^c; the
@@ -342,6 +365,7 @@ def main():
     }
     if tuned:
         out["tuned"] = tuned
+    out["sigma_x"] = sigma_x_timing(run, sysm, dev)
     if plain:
         out["plain_fp64"] = plain
         out["speedup_vs_plain"] = round(value / plain["value"], 3)

@@ -87,6 +87,7 @@ typedef struct {
   long long m_sig_elems;  /* lrigw_build_M slice 1: N_k * n_qp * n_bands * N_aux complex T */
   long long w_elems;      /* chi0 / W^c of one q: n_freq * N_aux * N_aux complex T */
   long long sigma_elems;  /* Sigma^c: N_k * n_qp * n_freq complex128 */
+  long long m_x_elems;    /* lrigw_build_M slice 2: N_k * n_qp * n_occ * N_aux complex T */
 } lrigw_sizes;
 int lrigw_get_sizes(const lrigw_ctx *ctx, lrigw_sizes *out /* host */);
 
@@ -117,7 +118,9 @@ int lrigw_lri_ft(lrigw_ctx *ctx, const double *lri_R, const int *R_list, int nR,
  *       M_out complex T [N_k][n_occ][n_bands-n_occ][N_aux]  (B^mu_ia(k,q))
  *   slice 1 (self-energy): k2 = k-q, r over the QP bands, c over all bands:
  *       M_out complex T [N_k][n_qp][n_bands][N_aux]  (C^mu_{nm}(k,k-q))
- * Errors: ERR_ARG (iq out of range, bad slice, NULL). */
+ *   slice 2 (exchange):    k2 = k-q, r over the QP bands, c over the occupied bands:
+ *       M_out complex T [N_k][n_qp][n_occ][N_aux]
+ * Errors: ERR_ARG (iq out of range, slice not 0, 1 or 2, NULL). */
 int lrigw_build_M(lrigw_ctx *ctx, int iq, int slice, const void *H, const void *evec, void *M_out);
 
 /* Independent-particle response, Eq. chi0_matrix (occupation difference
@@ -165,6 +168,28 @@ int lrigw_screen(lrigw_ctx *ctx, int iq, const void *chi, const void *V, void *W
  * eig: FP64 [N_k][n_bands]; sigma_acc: complex128 [N_k][n_qp][n_freq],
  * accumulated (zero it before the first q). */
 int lrigw_sigma_c(lrigw_ctx *ctx, int iq, const void *x, const void *Wc, const double *eig, void *sigma_acc);
+
+/* Exchange self-energy: the bare-Coulomb term of Eq. GW_selfe_element
+ * (W_0 = V + W^c).  V is static, and with the equal-time convergence factor
+ * of the exchange term the frequency integral keeps the occupied bands:
+ *   sigma_x[k][n] += -1/N_q sum_{m occ} sum_{mu nu} x^mu_nm V_{mu nu}(q) conj(x^nu_nm)
+ * (the pairing of lrigw_sigma_c with W^c -> V; real since V is Hermitian),
+ * computed in FP64 (the pairs are widened from the compute type).
+ * xo: slice-2 output of lrigw_build_M for this iq; V: complex128
+ * [N_aux][N_aux], V(q) (V(0) the truncated matrix of Sec. III B, as passed
+ * to lrigw_screen); sigma_x: FP64 [N_k][n_qp] on the device, accumulated
+ * (zero it before the first q).  A workspace of 2 * N_k*n_qp*n_occ*N_aux
+ * complex128 is allocated at the first call and kept by the context.
+ * Errors: ERR_ARG (iq out of range, NULL), ERR_OOM. */
+int lrigw_sigma_x(lrigw_ctx *ctx, int iq, const void *xo, const void *V, double *sigma_x);
+
+/* Sigma^x over every q: sigma_x (FP64 [N_k][n_qp], device) is set to the sum
+ * over q of lrigw_sigma_x, with the pairs built by lrigw_build_M slice 2 into a
+ * context buffer.  H: lrigw_lri_ft output; evec as for lrigw_lri_ft; V:
+ * complex128 [N_k][N_aux][N_aux] (V[0] the truncated matrix).  Together with
+ * the caller's V^xc it gives the static term of lrigw_qp:
+ * e_static = sigma_x - V^xc.  Errors: ERR_ARG (NULL), ERR_OOM. */
+int lrigw_sigma_x_pass(lrigw_ctx *ctx, const void *H, const void *evec, const void *V, double *sigma_x);
 
 /* Pade continuation (Thiele continued fraction through n_par grid points
  * j*(n_freq-1)/(n_par-1) rounded half up) and the quasiparticle equation

@@ -50,7 +50,7 @@ static void free_all(lrigw_ctx *c) {
   void *ptrs[] = {c->d_aux_atom, c->d_basis_off, c->d_aux_off, c->d_kpq, c->d_kmq, c->d_omega, c->d_weight, c->d_wall,
                   c->d_delta, c->d_part, c->d_X, c->d_LV, c->d_s0, c->d_s1, c->d_s2, c->d_s3, c->d_dinv, c->d_info,
                   c->d_bhat, c->d_x1, c->d_M, c->d_x, c->d_chi, c->d_wc, c->d_epsqp, c->d_xs, c->d_ws, c->d_ap, c->d_bt, c->d_chi2, c->d_wc2,
-                  c->d_sx, c->d_wmax, c->d_amax, c->d_sitems, c->d_wd};
+                  c->d_sx, c->d_wmax, c->d_amax, c->d_sitems, c->d_wd, c->d_xo, c->d_sxa, c->d_sxz};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &kv : c->stages)
@@ -274,6 +274,7 @@ int lrigw_get_sizes(const lrigw_ctx *c, lrigw_sizes *o) {
   o->h_elems = (long long)d.n_k * d.nb_max * d.n_bands * d.n_aux;
   o->m_chi_elems = lrigw_K(c) * d.n_aux;
   o->m_sig_elems = (long long)d.n_k * d.n_qp * d.n_bands * d.n_aux;
+  o->m_x_elems = (long long)d.n_k * d.n_qp * d.n_occ * d.n_aux;
   o->w_elems = (long long)d.n_freq * d.n_aux * d.n_aux;
   o->sigma_elems = (long long)d.n_k * d.n_qp * d.n_freq;
   return LRIGW_OK;
@@ -303,7 +304,7 @@ int lrigw_lri_ft(lrigw_ctx *c, const double *lri_R, const int *R_list, int nR, c
 int lrigw_build_M(lrigw_ctx *c, int iq, int slice, const void *H, const void *evec, void *M_out) {
   (void)hipGetLastError();  // drop a stale error another library left behind
   if (!c || !H || !evec || !M_out) return LRIGW_ERR_ARG;
-  if (iq < 0 || iq >= c->d.n_k || (slice != 0 && slice != 1)) return LRIGW_ERR_ARG;
+  if (iq < 0 || iq >= c->d.n_k || slice < 0 || slice > 2) return LRIGW_ERR_ARG;
   hipEvent_t ev;
   stage_begin(c, "build_M", &ev);
   int rc = run_build_M(c, iq, slice, H, evec, M_out);
@@ -357,6 +358,27 @@ int lrigw_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const dou
   if (!c || !x || !Wc || !eig || !sigma_acc) return LRIGW_ERR_ARG;
   if (iq < 0 || iq >= c->d.n_k) return LRIGW_ERR_ARG;
   return run_sigma_c(c, iq, x, Wc, eig, sigma_acc);
+}
+
+int lrigw_sigma_x(lrigw_ctx *c, int iq, const void *xo, const void *V, double *sigma_x) {
+  (void)hipGetLastError();
+  if (!c || !xo || !V || !sigma_x) return LRIGW_ERR_ARG;
+  if (iq < 0 || iq >= c->d.n_k) return LRIGW_ERR_ARG;
+  return run_sigma_x(c, iq, xo, V, sigma_x);
+}
+
+int lrigw_sigma_x_pass(lrigw_ctx *c, const void *H, const void *evec, const void *V, double *sigma_x) {
+  (void)hipGetLastError();
+  if (!c || !H || !evec || !V || !sigma_x) return LRIGW_ERR_ARG;
+  const Dims &d = c->d;
+  if (!c->d_xo) LRIGW_HIP_TRY(hipMalloc(&c->d_xo, (size_t)d.n_k * d.n_qp * d.n_occ * d.n_aux * lrigw_csize(c)));
+  LRIGW_TRY(zero_fill(c->stream, sigma_x, (size_t)d.n_k * d.n_qp * sizeof(double)));
+  const size_t vstride = (size_t)d.n_aux * d.n_aux;
+  for (int q = 0; q < d.n_k; ++q) {
+    LRIGW_TRY(run_build_M(c, q, 2, H, evec, c->d_xo));
+    LRIGW_TRY(run_sigma_x(c, q, c->d_xo, (const double2 *)V + q * vstride, sigma_x));
+  }
+  return LRIGW_OK;
 }
 
 int lrigw_qp(lrigw_ctx *c, const void *sigma, const double *eps_qp, const double *e_static, int n_par, double *e_qp,

@@ -256,8 +256,10 @@ int run_build_M(lrigw_ctx *c, int iq, int slice, const void *H, const void *evec
   const int *kmap;
   if (slice == 0) {
     r0 = 0; nr = d.n_occ; c0 = d.n_occ; nc = d.n_unocc; kmap = c->d_kpq;
-  } else {
+  } else if (slice == 1) {
     r0 = d.qp_lo; nr = d.n_qp; c0 = 0; nc = d.n_bands; kmap = c->d_kmq;
+  } else {
+    r0 = d.qp_lo; nr = d.n_qp; c0 = 0; nc = d.n_occ; kmap = c->d_kmq;
   }
   if (c->precision == LRIGW_FP64) launch_build<double>(c, iq, r0, nr, c0, nc, kmap, H, evec, M_out);
   else launch_build<float>(c, iq, r0, nr, c0, nc, kmap, H, evec, M_out);

@@ -109,6 +109,9 @@ struct lrigw_ctx {
   unsigned *d_amax = nullptr;    // FP16 split: largest |B| of each auxiliary row as float bits [Rpad]
   int *d_sitems = nullptr;       // resident-tile Sigma^c form: per-wave item lists
   double *d_wd = nullptr;        // resident-tile Sigma^c form: Re W^c_mumu(w), [N_aux][32]
+  void *d_xo = nullptr;          // exchange pairs of one q (build_M slice 2), compute type
+  void *d_sxa = nullptr;         // the same pairs in FP64 (reduced-precision forms)
+  void *d_sxz = nullptr;         // V x of those pairs, FP64
   int sig_res_F = 0;             // resident-tile Sigma^c form: frequencies per workgroup
   bool sig_res_ok = false;       // resident-tile Sigma^c form applies to this cell
 
@@ -183,6 +186,7 @@ int run_chi0_surrogate(lrigw_ctx *c, lrigw_surrogate *sg, int iq, const void *M,
 int run_gamma_prepare(lrigw_ctx *c, const void *Vcut0, const void *p, double omega_cell);
 int run_screen(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_out, int *info);
 int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const double *eig, void *sigma_acc);
+int run_sigma_x(lrigw_ctx *c, int iq, const void *xo, const void *V, double *sigma_x);
 int run_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *p, double omega_cell,
              const double *e_static, int n_par, int q_first, int q_last, void *sigma, double *e_qp, double *z, int *info);
 int driver_buffers(lrigw_ctx *c);

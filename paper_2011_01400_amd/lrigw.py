@@ -30,7 +30,8 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "split_bf16": SPLIT_BF16, "split3_bf16
 
 # every symbol include/lrigw.h declares
 EXPORTS = ["lrigw_create", "lrigw_destroy", "lrigw_strerror", "lrigw_get_sizes", "lrigw_grids", "lrigw_lri_ft",
-           "lrigw_build_M", "lrigw_chi0", "lrigw_gamma_prepare", "lrigw_screen", "lrigw_sigma_c", "lrigw_qp",
+           "lrigw_build_M", "lrigw_chi0", "lrigw_gamma_prepare", "lrigw_screen", "lrigw_sigma_c", "lrigw_sigma_x",
+           "lrigw_sigma_x_pass", "lrigw_qp",
            "lrigw_g0w0", "lrigw_set_timing", "lrigw_stage_ms", "lrigw_reset_timing",
            "lrigw_surrogate_create", "lrigw_surrogate_destroy", "lrigw_surrogate_info", "lrigw_surrogate_rule",
            "lrigw_surrogate_params", "lrigw_surrogate_basis", "lrigw_surrogate_add", "lrigw_surrogate_rows",
@@ -49,7 +50,8 @@ class LrigwSystem(ctypes.Structure):
 
 class LrigwSizes(ctypes.Structure):
     _fields_ = [(n, ctypes.c_longlong) for n in ("n_k", "n_b", "n_aux", "n_bands", "n_freq", "nb_max", "h_elems",
-                                                  "m_chi_elems", "m_sig_elems", "w_elems", "sigma_elems")]
+                                                  "m_chi_elems", "m_sig_elems", "w_elems", "sigma_elems",
+                                                  "m_x_elems")]
 
 
 class LrigwBatchCell(ctypes.Structure):
@@ -97,6 +99,8 @@ def load(path: Optional[str] = None):
         "lrigw_gamma_prepare": (i, [vp, vp, vp, d]),
         "lrigw_screen": (i, [vp, i, vp, vp, vp, ip]),
         "lrigw_sigma_c": (i, [vp, i, vp, vp, vp, vp]),
+        "lrigw_sigma_x": (i, [vp, i, vp, vp, vp]),
+        "lrigw_sigma_x_pass": (i, [vp, vp, vp, vp, vp]),
         "lrigw_qp": (i, [vp, vp, vp, vp, i, vp, vp, ip]),
         "lrigw_g0w0": (i, [vp, vp, vp, vp, vp, vp, d, vp, i, i, i, vp, vp, vp, ip]),
         "lrigw_set_timing": (i, [vp, i]),
@@ -206,7 +210,7 @@ class Context:
     def empty(self, kind):
         import torch
         z = self.sizes
-        n = {"H": z.h_elems, "M": z.m_chi_elems, "x": z.m_sig_elems, "W": z.w_elems}[kind]
+        n = {"H": z.h_elems, "M": z.m_chi_elems, "x": z.m_sig_elems, "xo": z.m_x_elems, "W": z.w_elems}[kind]
         return torch.empty(int(n), dtype=self.cdtype, device="cuda")
 
     # ---- entry points (same names as the C interface) ------------------
@@ -252,6 +256,15 @@ class Context:
         self._check(self.lib.lrigw_sigma_c(self.h, int(iq), _ptr(x), _ptr(Wc), _ptr(eig), _ptr(sigma_acc)),
                     "lrigw_sigma_c")
         return sigma_acc
+
+    def sigma_x(self, iq, xo, V, sigma_x):
+        self._check(self.lib.lrigw_sigma_x(self.h, int(iq), _ptr(xo), _ptr(V), _ptr(sigma_x)), "lrigw_sigma_x")
+        return sigma_x
+
+    def sigma_x_pass(self, H, evec, V, sigma_x):
+        self._check(self.lib.lrigw_sigma_x_pass(self.h, _ptr(H), _ptr(evec), _ptr(V), _ptr(sigma_x)),
+                    "lrigw_sigma_x_pass")
+        return sigma_x
 
     def qp(self, sigma, eps_qp, e_static, n_par, e_qp, z):
         info = ctypes.c_int(0)
