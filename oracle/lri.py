@@ -81,3 +81,19 @@ class TripleBuilder:
         """C^mu_{mn}(k1,k2) for bands m in `rows`, n in `cols` (slices/arrays)."""
         c = self.sys.evec
         return mo_triple(self.ao(k1, k2), c[k1][:, rows], c[k2][:, cols])
+
+
+def fit_two_centre(T, V, n_keep):
+    """Eq. two_center_coeff_determination: the two-centre coefficients of the
+    orbital products of one atom pair (I in the home cell, J in cell R), from
+    minimising the Coulomb self-repulsion of the expansion error:
+
+        C~^{mu(0)}_{i(0),j(R)} = sum_{nu in {I, J(R)}} (i(0),j(R)|nu) (V^{IJ})^{-1}_{nu mu},   mu on I.
+
+    T: [n][nrhs], (ij|nu) for the auxiliary functions nu of I (the first
+    n_keep) and of J(R), one column per product (i, j); V: [n][n], the
+    Coulomb matrix of those functions (symmetric positive definite; for I = J
+    and R = 0 the set is I's functions alone).  Returns [n_keep][nrhs].
+    """
+    X = np.linalg.solve(V, T)          # (V^-1)_{nu mu} = (V^-1)_{mu nu}: the rows of V^-1 T
+    return X[:n_keep]

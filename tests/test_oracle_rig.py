@@ -153,7 +153,8 @@ def build_rig():
     sysm = System(spec=spec, basis_off=basis_off, aux_off=aux_off, lattice=np.eye(3), R=R, lri=lri_flat,
                   lri_off=lri_off, eig=eig, evec=evec, V=Vq, p=np.zeros((NK, N_OCC, n_b - N_OCC), complex),
                   omega_cell=1.0, mu=mu, e_static=np.zeros((NK, n_b)), seed=0)
-    return dict(sys=sysm, psi=psi, v=v, Pq=Pq, kfrac=kfrac, n_tot=n_tot, naux=int(aux_off[-1]))
+    return dict(sys=sysm, psi=psi, v=v, Pq=Pq, kfrac=kfrac, n_tot=n_tot, naux=int(aux_off[-1]), orb=orb, abf=abf,
+                naux_atoms=naux, lri_blocks=lri_blocks, Rs=Rs, basis_off=basis_off)
 
 
 def _oracle(rig):
@@ -274,3 +275,29 @@ def test_rig_detects_swapped_sectors(rig, monkeypatch):
     lhs = psi[1].conj()[:, None, :] * psi[0][None, :, :]
     rhs = np.einsum("umn,ux->mnx", C, Pq[1].conj())
     assert np.max(np.abs(lhs - rhs)) > 1e-3
+
+
+def test_coulomb_metric_fit_recovers_rig_coefficients(rig):
+    """Eq. two_center_coeff_determination on the rig: every orbital product lies
+    in the span of its pair's auxiliary functions, so the Coulomb-metric fit
+    must return the rig's exact coefficients (those of its minimum-norm fit);
+    for an on-site pair the fit on I's functions alone gives twice the stored
+    block (the two sectors share one coefficient)."""
+    from oracle import lri
+    v, orb, abf = rig["v"], rig["orb"], rig["abf"]
+    naux, blocks, Rs, boff = rig["naux_atoms"], rig["lri_blocks"], rig["Rs"], rig["basis_off"]
+    for A in range(2):
+        for B in range(2):
+            for ir, R in enumerate(Rs):
+                onsite = A == B and R == 0
+                funcs = [abf(A, m, 0) for m in range(naux[A])]
+                if not onsite:
+                    funcs += [abf(B, m, R) for m in range(naux[B])]
+                P = np.array(funcs)                               # [n][x]
+                Vm = P @ v @ P.T
+                prods = np.array([orb(A, a, 0) * orb(B, b, R) for a in range(NB_ATOM) for b in range(NB_ATOM)])
+                T = P @ v @ prods.T                               # [n][(a, b)]
+                C = lri.fit_two_centre(T, Vm, naux[A]).reshape(naux[A], NB_ATOM, NB_ATOM)
+                stored = blocks[A][ir][:, :, boff[B]:boff[B] + NB_ATOM]
+                want = 2.0 * stored if onsite else stored
+                assert np.max(np.abs(C - want)) < 1e-9 * max(1.0, np.max(np.abs(want))), (A, B, R)
