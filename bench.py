@@ -191,6 +191,38 @@ def sigma_x_timing(run, sysm, dev, reps=3):
             "range_ha": [round(float(v.min()), 6), round(float(v.max()), 6)]}
 
 
+def lri_fit_timing(run, sysm, reps=2):
+    """Two-centre coefficient fit (lrigw_lri_fit) at the Si-like cell's shape:
+    every off-site pair (I, J(R)) of its 2 atoms and 125 lattice vectors,
+    n = 2 x 130 auxiliary functions, 130 kept, 39 x 39 products, on seeded
+    synthetic SPD Coulomb blocks.  Algorithmic FP64 flops per pair: the
+    Cholesky factor (n^3/3) and two triangular solves (2 n^2 nrhs)."""
+    torch = run.torch
+    n_at, n_r = sysm.spec.n_atoms, int(sysm.R.shape[0])
+    nb = sysm.n_b // n_at
+    na = sysm.n_aux // n_at
+    batch, n, keep, nrhs = n_at * n_at * n_r, 2 * na, na, nb * nb
+    g = torch.Generator(device="cuda").manual_seed(2011)
+    A = torch.randn((batch, n, n), generator=g, dtype=torch.float64, device="cuda") / n ** 0.5
+    V = torch.bmm(A, A.transpose(1, 2).contiguous()) + 0.5 * torch.eye(n, dtype=torch.float64, device="cuda")
+    del A
+    T = torch.randn((batch, n, nrhs), generator=g, dtype=torch.float64, device="cuda")
+    C = torch.empty((batch, keep, nrhs), dtype=torch.float64, device="cuda")
+    run.ctx.lri_fit(V, T, keep, C)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        run.ctx.lri_fit(V, T, keep, C)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    flops = batch * (n ** 3 / 3.0 + 2.0 * n * n * nrhs)
+    a = flops / dt / 1e12
+    del V, T, C
+    return {"ms": round(dt * 1e3, 3), "pairs": batch, "n": n, "kept": keep, "products": nrhs, "bound": "mfma",
+            "achieved": round(a, 2), "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s", "frac": round(a / PEAK_TFLOPS["fp64"], 4),
+            "flops": flops}
+
+
 def cpu_baseline(sysm):
     """FP64 oracle on a bounded sample of the same workload: one q (q = 1), all
     N_w frequencies, all k points of chi0 and Sigma^c; the
@@ -366,6 +398,7 @@ def main():
     if tuned:
         out["tuned"] = tuned
     out["sigma_x"] = sigma_x_timing(run, sysm, dev)
+    out["lri_fit"] = lri_fit_timing(run, sysm)
     if plain:
         out["plain_fp64"] = plain
         out["speedup_vs_plain"] = round(value / plain["value"], 3)

@@ -109,6 +109,28 @@ int lrigw_grids(lrigw_ctx *ctx, double *omega, double *weight, int *kpq, int *km
  * Errors: ERR_ARG (nR < 1, NULL), ERR_OOM (temporary for the transform). */
 int lrigw_lri_ft(lrigw_ctx *ctx, const double *lri_R, const int *R_list, int nR, const void *evec, void *H_out);
 
+/* Two-centre LRI coefficients, Eq. two_center_coeff_determination: the
+ * expansion of the orbital products of an atom pair (I in the home cell, J in
+ * cell R) that minimises the Coulomb self-repulsion of its error,
+ *   C~^{mu(0)}_{i(0),j(R)} = sum_{nu in {I, J(R)}} (i(0),j(R)|nu) (V^{IJ})^{-1}_{nu mu},  mu on I,
+ * for `batch` pairs of one shape at once (the step that produces lri_R):
+ *   V: FP64 [batch][n][n], the Coulomb matrix of the pair's n auxiliary
+ *      functions, I's n_keep first (for I = J, R = 0 only I's); symmetric
+ *      positive definite;
+ *   T: FP64 [batch][n][nrhs], (ij|nu), one column per product (i, j);
+ *   C: FP64 [batch][n_keep][nrhs] output, scale * (rows 0..n_keep-1 of
+ *      V^{-1} T), i.e. C~^{mu}_{i(0),j(R)} in the [mu][(i, j)] order of an
+ *      lri_R block; scale = 1, or 1/2 for an on-site pair (the two sectors of
+ *      Eq. AO_triple_split2 then share the coefficient).
+ * All device pointers, caller-owned; workspace of batch*(n*n + n*nrhs)
+ * complex128 is allocated and freed inside the call, which synchronises the
+ * context stream.  info (host, may be NULL): -1, or the first pair whose V was
+ * not positive definite (then ERR_NOT_HPD).
+ * Errors: ERR_ARG (batch outside 1..65535, n < 1, n_keep outside 1..n,
+ * nrhs < 1, NULL), ERR_OOM, ERR_NOT_HPD. */
+int lrigw_lri_fit(lrigw_ctx *ctx, int batch, int n, int n_keep, int nrhs, const double *V, const double *T, double scale,
+                  double *C, int *info);
+
 /* MO triple coefficients (Eqs. AO_triple_split2 and AO_MO_transform) with the
  * Bloch pair (k, k2), mu on P^{(k-k2)*}:
  *   C^mu_{rc}(k,k2) = sum_{a on atom(mu)} conj(c_{a r}(k)) H[k2][a][c][mu]

@@ -381,6 +381,15 @@ int lrigw_sigma_x_pass(lrigw_ctx *c, const void *H, const void *evec, const void
   return LRIGW_OK;
 }
 
+int lrigw_lri_fit(lrigw_ctx *c, int batch, int n, int n_keep, int nrhs, const double *V, const double *T, double scale,
+                  double *C, int *info) {
+  (void)hipGetLastError();
+  if (info) *info = -1;
+  if (!c || !V || !T || !C) return LRIGW_ERR_ARG;
+  if (batch < 1 || batch > 65535 || n < 1 || n_keep < 1 || n_keep > n || nrhs < 1) return LRIGW_ERR_ARG;
+  return run_lri_fit(c, batch, n, n_keep, nrhs, V, T, scale, C, info);
+}
+
 int lrigw_qp(lrigw_ctx *c, const void *sigma, const double *eps_qp, const double *e_static, int n_par, double *e_qp,
              double *z, int *info) {
   (void)hipGetLastError();

@@ -187,6 +187,8 @@ int run_gamma_prepare(lrigw_ctx *c, const void *Vcut0, const void *p, double ome
 int run_screen(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_out, int *info);
 int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const double *eig, void *sigma_acc);
 int run_sigma_x(lrigw_ctx *c, int iq, const void *xo, const void *V, double *sigma_x);
+int run_lri_fit(lrigw_ctx *c, int batch, int n, int n_keep, int nrhs, const double *V, const double *T, double scale,
+                double *C, int *info);
 int run_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *p, double omega_cell,
              const double *e_static, int n_par, int q_first, int q_last, void *sigma, double *e_qp, double *z, int *info);
 int driver_buffers(lrigw_ctx *c);

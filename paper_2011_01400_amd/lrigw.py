@@ -31,7 +31,7 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "split_bf16": SPLIT_BF16, "split3_bf16
 # every symbol include/lrigw.h declares
 EXPORTS = ["lrigw_create", "lrigw_destroy", "lrigw_strerror", "lrigw_get_sizes", "lrigw_grids", "lrigw_lri_ft",
            "lrigw_build_M", "lrigw_chi0", "lrigw_gamma_prepare", "lrigw_screen", "lrigw_sigma_c", "lrigw_sigma_x",
-           "lrigw_sigma_x_pass", "lrigw_qp",
+           "lrigw_sigma_x_pass", "lrigw_lri_fit", "lrigw_qp",
            "lrigw_g0w0", "lrigw_set_timing", "lrigw_stage_ms", "lrigw_reset_timing",
            "lrigw_surrogate_create", "lrigw_surrogate_destroy", "lrigw_surrogate_info", "lrigw_surrogate_rule",
            "lrigw_surrogate_params", "lrigw_surrogate_basis", "lrigw_surrogate_add", "lrigw_surrogate_rows",
@@ -101,6 +101,7 @@ def load(path: Optional[str] = None):
         "lrigw_sigma_c": (i, [vp, i, vp, vp, vp, vp]),
         "lrigw_sigma_x": (i, [vp, i, vp, vp, vp]),
         "lrigw_sigma_x_pass": (i, [vp, vp, vp, vp, vp]),
+        "lrigw_lri_fit": (i, [vp, i, i, i, i, vp, vp, d, vp, ip]),
         "lrigw_qp": (i, [vp, vp, vp, vp, i, vp, vp, ip]),
         "lrigw_g0w0": (i, [vp, vp, vp, vp, vp, vp, d, vp, i, i, i, vp, vp, vp, ip]),
         "lrigw_set_timing": (i, [vp, i]),
@@ -265,6 +266,16 @@ class Context:
         self._check(self.lib.lrigw_sigma_x_pass(self.h, _ptr(H), _ptr(evec), _ptr(V), _ptr(sigma_x)),
                     "lrigw_sigma_x_pass")
         return sigma_x
+
+    def lri_fit(self, V, T, n_keep, C, scale=1.0):
+        """V: FP64 [batch][n][n], T: FP64 [batch][n][nrhs], C: FP64 [batch][n_keep][nrhs] (device)."""
+        batch, n, _ = V.shape
+        nrhs = T.shape[2]
+        info = ctypes.c_int(0)
+        rc = self.lib.lrigw_lri_fit(self.h, int(batch), int(n), int(n_keep), int(nrhs), _ptr(V), _ptr(T), float(scale),
+                                    _ptr(C), ctypes.byref(info))
+        self._check(rc, "lrigw_lri_fit")
+        return C
 
     def qp(self, sigma, eps_qp, e_static, n_par, e_qp, z):
         info = ctypes.c_int(0)
