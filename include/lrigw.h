@@ -356,7 +356,10 @@ int lrigw_batch_destroy(lrigw_batch *b);
  * (frequencies per workgroup, K splits, LDS row padding) and, in the split
  * forms, the self-energy kernel over its variants (frequencies per workgroup,
  * W prefetch, wave tile, LDS row padding, x tile resident in LDS), and keeps
- * the fastest for the context's later calls.
+ * the fastest for the context's later calls; candidates are tried in a fixed
+ * order and a later one replaces the best so far only if it is at least 2%
+ * faster, so near-ties resolve the same way each time (the K split count
+ * changes the order of the FP32 sums).
  * H, evec, eig as lrigw_g0w0.  Outputs (host, may be NULL): the chosen
  * response tiles, the self-energy variant (0..8) and the response time of one
  * q (ms).
