@@ -271,7 +271,7 @@ def cpu_baseline(sysm):
 
 
 def batched(args):
-    """Six uneven cells (config 3) in one captured hipGraph: value = total
+    """Six uneven Si-like cells (2 to 8 atoms) in one captured hipGraph: value = total
     (q, w) pairs of all cells per second; compared with the same cells run one
     after the other through lrigw_g0w0."""
     import torch
@@ -317,7 +317,7 @@ def batched(args):
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[args.precision],
            "data": "synthetic",
-           "config": {"workload": "six uneven cells (config 3): " + ", ".join(
+           "config": {"workload": "six uneven Si-like cells: " + ", ".join(
                f"{s.spec.n_atoms} atoms/N_aux {s.n_aux}/{'x'.join(map(str, s.spec.nk))} k" for s in cells)
                + f", {cells[0].spec.n_freq} frequencies, one captured hipGraph", "precision_form": args.precision,
                "pairs_per_step": pairs},
@@ -387,7 +387,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": DTYPE[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"Si-like 2-atom cell (config {args.config}): N_b={sysm.n_b}, N_aux={sysm.n_aux}, "
+        "config": {"workload": f"Si-like 2-atom cell: N_b={sysm.n_b}, N_aux={sysm.n_aux}, "
                                f"k grid {'x'.join(map(str, sp.nk))}, N_occ={sp.n_occ}, {sp.n_bands} bands, "
                                f"{sp.n_freq} modified Gauss-Legendre frequencies, QP bands {sp.qp_lo}..{sp.qp_lo + sp.n_qp - 1}",
                    "precision_form": args.precision, "pairs_per_step": pairs},
