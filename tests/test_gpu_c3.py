@@ -1,0 +1,113 @@
+"""GPU, full size: the six uneven Si-like cells (2, 2, 4, 4, 6, 8 atoms; N_aux
+260 to 1040; 4x4x4 and 3x3x3 k; 32 frequencies) in one captured hipGraph,
+FP16 form with the tile autotuner, as `bench.py --workload batched` runs them.
+Checked: every cell's status; each cell's batched result equals its own
+lrigw_g0w0 on the same tuned context; and on the smallest cell one q's Sigma^c
+contribution at sampled k points equals the FP64 oracle's.
+
+Sigma^c(k) = Sigma^c(-k) is not checked here: the q -> 0 head and wings are
+taken along one direction q_hat, the wings are odd in p.q_hat, and with these
+inputs (no crystal symmetry to cancel them) W^c(0) is complex, so the q = 0
+term differs between k and -k (by 1e-4 relative in the FP64 oracle as well;
+without the Gamma correction the oracle is symmetric to rounding)."""
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle.pipeline import Oracle
+from synth.systems import all_cells
+
+
+def _lib():
+    from paper_2011_01400_amd import lrigw as L
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L.load()
+    return L
+
+
+@pytest.fixture(scope="module")
+def batched():
+    L = _lib()
+    t0 = time.perf_counter()
+    cells = all_cells(3)
+    print(f"\n[gpu c3] inputs of {len(cells)} cells in {time.perf_counter() - t0:.1f} s", flush=True)
+    stream = torch.cuda.Stream()
+    items = []
+    with torch.cuda.stream(stream):
+        for s in cells:
+            dev = L.device_inputs(s)
+            ctx = L.Context.from_system(s, precision="split_f16")
+            H = ctx.empty("H")
+            ctx.lri_ft(dev["lri"], s.R, dev["evec"], H)
+            sp = s.spec
+            items.append(dict(ctx=ctx, H=H, evec=dev["evec"], eig=dev["eig"], V=dev["V"], p=dev["p"],
+                              omega_cell=s.omega_cell, e_static=dev["e_static"], n_par=16,
+                              sigma=torch.zeros((s.n_k, sp.n_qp, sp.n_freq), dtype=torch.complex128, device="cuda"),
+                              e_qp=torch.zeros((s.n_k, sp.n_qp), dtype=torch.float64, device="cuda"),
+                              z=torch.zeros((s.n_k, sp.n_qp), dtype=torch.float64, device="cuda")))
+    torch.cuda.synchronize()
+    b = L.Batch(items, autotune=True, stream=stream)
+    for rep in range(2):
+        b.run()
+        st = b.status()
+        print(f"[gpu c3] graph replay {rep}: status {st}", flush=True)
+    torch.cuda.synchronize()
+    return L, cells, items, b, st
+
+
+def test_status(batched):
+    L, cells, items, b, st = batched
+    for i, (s, it) in enumerate(zip(cells, items)):
+        assert st[i][0] == -1 and st[i][1] == 0, (i, st[i])
+        assert np.all(np.isfinite(it["sigma"].cpu().numpy()))
+        assert np.all(np.isfinite(it["e_qp"].cpu().numpy()))
+        z = it["z"].cpu().numpy()
+        print(f"  cell {i} ({s.spec.n_atoms} atoms, N_aux {s.n_aux}, {s.n_k} k): Z in [{z.min():.3f}, {z.max():.3f}]",
+              flush=True)
+
+
+def test_batched_equals_per_cell_pass(batched):
+    L, cells, items, b, st = batched
+    for i, (s, it) in enumerate(zip(cells, items)):
+        sp = s.spec
+        sg = torch.zeros_like(it["sigma"])
+        e = torch.zeros_like(it["e_qp"])
+        z = torch.zeros_like(it["z"])
+        it["ctx"].g0w0(it["H"], it["evec"], it["eig"], it["V"], it["p"], it["omega_cell"], it["e_static"], 16, sg, e, z)
+        torch.cuda.synchronize()
+        ds = np.max(np.abs(sg.cpu().numpy() - it["sigma"].cpu().numpy()))
+        de = np.max(np.abs(e.cpu().numpy() - it["e_qp"].cpu().numpy())) * 27211.386
+        print(f"  cell {i}: batched vs own pass max|dSigma| {ds:.1e} Ha, max|dE| {de:.1e} meV", flush=True)
+        assert ds < 1e-12 and de < 1e-6
+
+
+def test_smallest_cell_one_q_against_oracle(batched):
+    L, cells, items, b, st = batched
+    i = min(range(len(cells)), key=lambda j: cells[j].n_aux * cells[j].n_k)
+    s, it = cells[i], items[i]
+    sp = s.spec
+    ctx = it["ctx"]
+    q = 1
+    dev = L.device_inputs(s)
+    M, x, chi, W = ctx.empty("M"), ctx.empty("x"), ctx.empty("W"), ctx.empty("W")
+    ctx.build_M(q, 0, it["H"], it["evec"], M)
+    ctx.chi0(q, M, it["eig"], chi)
+    ctx.screen(q, chi, dev["V"][q], W)
+    ctx.build_M(q, 1, it["H"], it["evec"], x)
+    sg = torch.zeros((s.n_k, sp.n_qp, sp.n_freq), dtype=torch.complex128, device="cuda")
+    ctx.sigma_c(q, x, W, it["eig"], sg)
+    ks = [0, 5, s.n_k - 1]
+    t0 = time.perf_counter()
+    o = Oracle(s)
+    ref, _ = o.sigma_q(q, o.wc(q, gamma=False), ks)
+    got = sg.cpu().numpy()[ks]
+    e = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    print(f"  cell {i} (N_aux {s.n_aux}, {s.n_k} k) q={q}: sampled Sigma^c rel {e:.1e} "
+          f"(oracle {time.perf_counter() - t0:.1f} s)", flush=True)
+    assert e < 2e-5
