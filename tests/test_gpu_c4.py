@@ -1,0 +1,86 @@
+"""GPU, full size, by properties: the 8-atom cell of the surrogate workload
+(N_b 312, N_aux 1040, 4x4x4 k, 16 occupied bands, 40 frequencies) in the
+default FP16 form with the tile autotuner.  At this size the oracle cannot
+build the triple coefficients in reasonable time, so the checks are
+properties that hold at any size: the response is Hermitian and negative
+semidefinite, W^c = L (eps~^-1 - I) L^H is negative semidefinite, Sigma^x is
+negative, and the whole pass finishes with every screening positive definite
+and finite quasiparticle energies."""
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from synth.systems import make_config
+
+
+@pytest.fixture(scope="module")
+def c4():
+    from paper_2011_01400_amd import lrigw as L
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L.load()
+    t0 = time.perf_counter()
+    s = make_config(4)
+    print(f"\n[gpu c4] inputs (N_aux {s.n_aux}, {s.n_k} k, {s.spec.n_freq} w) in {time.perf_counter() - t0:.1f} s",
+          flush=True)
+    dev = L.device_inputs(s)
+    ctx = L.Context.from_system(s, precision="split_f16")
+    H = ctx.empty("H")
+    ctx.lri_ft(dev["lri"], s.R, dev["evec"], H)
+    print(f"  tuned {ctx.tune(H, dev['evec'], dev['eig'])}", flush=True)
+    return L, s, dev, ctx, H
+
+
+def _top_eig(m):
+    return np.linalg.eigvalsh(0.5 * (m + m.conj().T))
+
+
+def test_response_and_screening_properties(c4):
+    L, s, dev, ctx, H = c4
+    n = s.n_aux
+    q = 5
+    M, chi, W = ctx.empty("M"), ctx.empty("W"), ctx.empty("W")
+    ctx.build_M(q, 0, H, dev["evec"], M)
+    ctx.chi0(q, M, dev["eig"], chi)
+    ctx.screen(q, chi, dev["V"][q], W)
+    c = chi.cpu().numpy().reshape(-1, n, n)
+    w = W.cpu().numpy().reshape(-1, n, n)
+    for j in (0, s.spec.n_freq // 2, s.spec.n_freq - 1):
+        herm = np.linalg.norm(c[j] - c[j].conj().T) / np.linalg.norm(c[j])
+        ec, ew = _top_eig(c[j].astype(np.complex128)), _top_eig(w[j].astype(np.complex128))
+        print(f"  q={q} w{j}: |chi - chi^H|/|chi| {herm:.1e}, chi eig [{ec[0]:.3e}, {ec[-1]:.3e}], "
+              f"W^c eig [{ew[0]:.3e}, {ew[-1]:.3e}]", flush=True)
+        assert herm < 1e-6
+        assert ec[-1] < 1e-5 * abs(ec[0])
+        assert ew[-1] < 1e-5 * abs(ew[0])
+
+
+def test_exchange_negative(c4):
+    L, s, dev, ctx, H = c4
+    sx = torch.zeros((s.n_k, s.spec.n_qp), dtype=torch.float64, device="cuda")
+    ctx.sigma_x_pass(H, dev["evec"], dev["V"], sx)
+    v = sx.cpu().numpy()
+    print(f"  Sigma^x in [{v.min():.4f}, {v.max():.4f}] Ha", flush=True)
+    assert np.all(v < 0.0)
+
+
+def test_whole_pass(c4):
+    L, s, dev, ctx, H = c4
+    sp = s.spec
+    sg = torch.zeros((s.n_k, sp.n_qp, sp.n_freq), dtype=torch.complex128, device="cuda")
+    e = torch.zeros((s.n_k, sp.n_qp), dtype=torch.float64, device="cuda")
+    z = torch.zeros_like(e)
+    t0 = time.perf_counter()
+    rc, info = ctx.g0w0(H, dev["evec"], dev["eig"], dev["V"], dev["p"], s.omega_cell, dev["e_static"], 16, sg, e, z)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ev, zv = e.cpu().numpy(), z.cpu().numpy()
+    print(f"  pass {dt:.2f} s ({s.n_k * sp.n_freq / dt:.0f} pairs/s), rc {rc}, info {info}, "
+          f"Z in [{zv.min():.3f}, {zv.max():.3f}]", flush=True)
+    assert rc >= 0
+    assert np.all(np.isfinite(sg.cpu().numpy())) and np.all(np.isfinite(ev))
