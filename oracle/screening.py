@@ -24,8 +24,10 @@ Omega as the crystal volume N_k * Omega_cell makes all three consistent).  The
 body is exactly the regular formula in the eigenbasis.  The result is
 transformed back with X and W^c(0) = X sqrt(v) (eps~_lam^{-1} - I) sqrt(v) X^H,
 V^cut entering the numerator.  The sign of the real eigenvector X_1 is fixed
-so that its largest-magnitude component is positive.  Parity of the head and
-wing terms is unpinned beyond the special cases p = 0 and N_aux = 1.
+so that its largest-magnitude component is positive.  The head is pinned
+against the printed band-pair sum of the equation (every pair with its
+occupation difference, Omega the crystal volume); parity of the wing terms
+is unpinned beyond the special cases p = 0 and N_aux = 1.
 """
 from __future__ import annotations
 

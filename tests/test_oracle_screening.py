@@ -78,3 +78,33 @@ def test_gamma_single_aux_closed_form():
         e = 1 + 2.0 / nk * tot
         assert abs(eps_l[iw][0, 0] - e) < 1e-13
         assert abs(Wc[iw][0, 0] - v * (1 / e - 1)) < 1e-13
+
+
+def test_gamma_head_matches_printed_band_pair_sum(c1_oracle):
+    # The head of Eq. dielectric_func_gamma as printed (insulator: no intraband
+    # term): 1 - (4 pi / Omega) sum_{k, sigma} sum_{m<n} 2 (f_m - f_n) |p_mn|^2 /
+    # ([(e_m - e_n)^2 + w^2] (e_m - e_n)), summed over every band pair with its
+    # occupation difference and signed denominator, Omega the crystal volume
+    # N_k * Omega_cell and two spin channels, against the oracle's Gram form
+    # over (occupied, unoccupied) pairs for the full auxiliary set
+    s, o = c1_oracle.sys, c1_oracle
+    rng = np.random.default_rng(11)
+    p = rng.standard_normal(s.p.shape) + 1j * rng.standard_normal(s.p.shape)
+    eps_l, _, _ = screening.screen_gamma(o.B(0), s.eig, s.n_occ, p, s.omega_cell, s.V[0], o.omega)
+    nb = s.spec.n_bands
+    f = np.zeros(nb)
+    f[:s.n_occ] = 1.0
+    omega_crystal = s.n_k * s.omega_cell
+    for iw in (0, 7, len(o.omega) - 1):
+        w = o.omega[iw]
+        tot = 0.0
+        for k in range(s.n_k):
+            for m in range(nb):
+                for n in range(m + 1, nb):
+                    if f[m] == f[n]:
+                        continue
+                    pmn = p[k, m, n - s.n_occ]
+                    d = s.eig[k, m] - s.eig[k, n]
+                    tot += 2.0 * (f[m] - f[n]) * abs(pmn) ** 2 / ((d * d + w * w) * d)
+        head = 1.0 - (4.0 * np.pi / omega_crystal) * 2.0 * tot
+        assert abs(eps_l[iw][0, 0] - head) < 1e-12 * abs(head)
