@@ -34,6 +34,11 @@ CASES = {
     # three atoms, N_aux = 3*45 = 135 (three tiles), one k point
     "three_atoms": lambda: make_custom(n_atoms=3, nb_per_atom=6, naux_per_atom=45, nk=(1, 1, 1), n_occ=4, n_freq=8,
                                        qp_lo=1, n_qp=7, seed=23),
+    # edges: one atom, N_aux = 19 (less than one tile), one occupied band, one
+    # k point, an odd number of frequencies (a last frequency group of one,
+    # empty XCD frequency sets), a single QP band
+    "edge": lambda: make_custom(n_atoms=1, nb_per_atom=5, naux_per_atom=19, nk=(1, 1, 1), n_occ=1, n_freq=7,
+                                qp_lo=0, n_qp=1, seed=41),
 }
 
 
