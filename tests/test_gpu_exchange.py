@@ -31,6 +31,9 @@ CASES = {
                                   qp_lo=2, n_qp=6, seed=17),
     "three_atoms": lambda: make_custom(n_atoms=3, nb_per_atom=6, naux_per_atom=45, nk=(1, 1, 1), n_occ=4, n_freq=8,
                                        qp_lo=1, n_qp=7, seed=23),
+    # one occupied band, N_aux below one tile, a single QP band
+    "edge": lambda: make_custom(n_atoms=1, nb_per_atom=5, naux_per_atom=19, nk=(1, 1, 1), n_occ=1, n_freq=7,
+                                qp_lo=0, n_qp=1, seed=41),
 }
 # FP64: rounding only; reduced-precision forms: the pairs are FP32 (relative
 # 6e-8 per element), the quadratic form is taken in FP64

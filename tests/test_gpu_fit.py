@@ -25,7 +25,8 @@ def _spd_batch(rng, batch, n):
     return np.einsum("bij,bkj->bik", A, A) + 0.5 * np.eye(n)[None]
 
 
-@pytest.mark.parametrize("batch,n,n_keep,nrhs", [(1, 60, 30, 9), (3, 74, 37, 49), (5, 135, 45, 36), (2, 260, 130, 1521)])
+@pytest.mark.parametrize("batch,n,n_keep,nrhs", [(1, 1, 1, 1), (4, 19, 19, 5), (1, 60, 30, 9), (3, 74, 37, 49),
+                                               (5, 135, 45, 36), (2, 260, 130, 1521)])
 def test_fit_matches_oracle(batch, n, n_keep, nrhs):
     L, ctx = _ctx()
     rng = np.random.default_rng(1000 + n)
