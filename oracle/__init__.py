@@ -21,6 +21,8 @@ Modules
                  the Coulomb eigenbasis (Eq. dielectric_func_gamma)
   selfenergy     correlation self-energy (Eq. GW_selfe_element with W -> W^c)
   continuation   Thiele Pade continued fraction and the quasiparticle equation
+  contour        Sigma^c at real energies by contour deformation (imaginary-axis
+                 integral plus residues, W^c below the smallest transition)
   pipeline       the whole path for one synthetic cell
 
 Pins live in tests/test_oracle_*.py.  Functions without an independent pin

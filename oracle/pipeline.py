@@ -11,12 +11,15 @@ for both the response and the self-energy (a reordering of the finite sums):
   Pade continuation and the QP equation.
 The exchange self-energy (the bare-Coulomb term of Eq. GW_selfe_element) is
 `sigma_x`, from the pairs of QP bands at k and occupied bands at k-q.
+`sigma_cd` evaluates Sigma^c at real energies by contour deformation
+(`contour`), from W^c on the imaginary grid and on a real grid below the
+smallest transition energy.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from . import grids, lri, response, screening, selfenergy, continuation
+from . import grids, lri, response, screening, selfenergy, continuation, contour
 
 
 class Oracle:
@@ -78,6 +81,40 @@ class Oracle:
         kmq = self.kmq[ks]
         return selfenergy.sigma_c_q(X, self.sys.eig, kmq, q, self.sys.mu, self.omega, self.weight,
                                     self.sys.n_k), X
+
+    # ---- real energies by contour deformation ---------------------------
+    def chi0_real(self, q, omega_r, B=None):
+        """chi~(q, w) at real w below the smallest transition energy."""
+        B = self.B(q) if B is None else B
+        return response.chi0_trs(B, self.sys.eig, self.kpq, q, self.sys.n_occ, omega_r, real_axis=True)
+
+    def wc_real(self, q, omega_r, chi=None, B=None, gamma=True):
+        s = self.sys
+        if q == 0 and gamma:
+            B = self.B(0) if B is None else B
+            return screening.screen_gamma(B, s.eig, s.n_occ, s.p, s.omega_cell, s.V[0], omega_r, real_axis=True)[2]
+        chi = self.chi0_real(q, omega_r, B) if chi is None else chi
+        return screening.screen(chi, s.V[q])[1]
+
+    def sigma_cd_q(self, q, Wc, Wr, h, E, ks=None):
+        """Contribution of q to Sigma^c at the real energies E [n_e][len(ks)][N_qp]."""
+        ks = list(range(self.sys.n_k)) if ks is None else list(ks)
+        xq = self.x(q, ks)
+        Xi = selfenergy.pair_weights(xq, Wc)
+        Xr = selfenergy.pair_weights(xq, Wr)
+        return contour.sigma_cd_q(Xi, Xr, self.sys.eig, self.kmq[ks], q, self.sys.n_occ, self.omega, self.weight,
+                                  h, E, self.sys.n_k)
+
+    def sigma_cd(self, n_r, omega_max, E, ks=None, gamma=True):
+        """Sigma^c_n(k, E) summed over q at the real energies E."""
+        omega_r, h = contour.real_grid(n_r, omega_max)
+        out = np.zeros(E.shape)
+        for q in range(self.sys.n_k):
+            B = self.B(q)
+            Wc = self.wc(q, B=B, gamma=gamma)
+            Wr = self.wc_real(q, omega_r, B=B, gamma=gamma)
+            out += self.sigma_cd_q(q, Wc, Wr, h, E, ks)
+        return out
 
     # ---- whole path ---------------------------------------------------
     def run(self, ks=None, gamma=True, keep=False):

@@ -31,17 +31,22 @@ import numpy as np
 SPIN = 2.0
 
 
-def chi0_trs(B, eig, kpq, q, n_occ, omega, s=SPIN):
-    """B: [N_k][N_aux][N_occ][N_unocc] = C^mu_{ia}(k,k+q); returns [N_w][N_aux][N_aux]."""
+def chi0_trs(B, eig, kpq, q, n_occ, omega, s=SPIN, real_axis=False):
+    """B: [N_k][N_aux][N_occ][N_unocc] = C^mu_{ia}(k,k+q); returns [N_w][N_aux][N_aux].
+
+    real_axis: the frequencies are real, w -> -i w in the denominators, so the
+    weight is 2D/(D^2 - w^2); meant for 0 <= w < min D, where it stays finite
+    and positive (the response below the first transition)."""
     n_k = B.shape[0]
     n_aux = B.shape[1]
+    sgn = -1.0 if real_axis else 1.0
     out = np.zeros((len(omega), n_aux, n_aux), dtype=np.complex128)
     for k in range(n_k):
         kq = kpq[k, q]
         delta = eig[kq][n_occ:][None, :] - eig[k][:n_occ][:, None]     # [occ][unocc]
         Bk = B[k].reshape(n_aux, -1)
         for iw, w in enumerate(omega):
-            wt = (2.0 * delta / (delta * delta + w * w)).reshape(-1)
+            wt = (2.0 * delta / (delta * delta + sgn * w * w)).reshape(-1)
             out[iw] += (Bk * wt[None, :]) @ Bk.conj().T
     return -(s / n_k) * out
 

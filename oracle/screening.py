@@ -68,12 +68,15 @@ def coulomb_eigenbasis(Vcut0):
     return v, X
 
 
-def screen_gamma(B0, eig, n_occ, p, omega_cell, Vcut0, omega, s=SPIN):
+def screen_gamma(B0, eig, n_occ, p, omega_cell, Vcut0, omega, s=SPIN, real_axis=False):
     """q = 0 dielectric matrix in the Coulomb eigenbasis and W^c(0).
 
     B0: [N_k][N_aux][N_occ][N_unocc] = C^mu_{ia}(k,k); p: [N_k][N_occ][N_unocc].
+    real_axis: real frequencies below the smallest transition, weight
+    2D/(D^2 - w^2) (as in `response.chi0_trs`).
     Returns (eps~_lambda, eps~_mu, W^c) per frequency.
     """
+    sgn = -1.0 if real_axis else 1.0
     n_k, n_aux = B0.shape[0], B0.shape[1]
     v, X = coulomb_eigenbasis(Vcut0)
     if v[-1] <= 0.0:
@@ -86,7 +89,7 @@ def screen_gamma(B0, eig, n_occ, p, omega_cell, Vcut0, omega, s=SPIN):
         Y = sv[:, None] * (X.conj().T @ B0[k].reshape(n_aux, -1))          # [lam][ia]
         Y[0, :] = np.sqrt(4.0 * np.pi / omega_cell) * p[k].reshape(-1) / delta
         for iw, w in enumerate(omega):
-            wt = 2.0 * delta / (delta * delta + w * w)
+            wt = 2.0 * delta / (delta * delta + sgn * w * w)
             eps_l[iw] += (s / n_k) * (Y * wt[None, :]) @ Y.conj().T
     eps_mu = np.empty_like(eps_l)
     Wc = np.empty_like(eps_l)
