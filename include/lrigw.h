@@ -45,6 +45,7 @@ extern "C" {
 #define LRIGW_ERR_NOCONV (-5)      /* an iteration did not converge */
 #define LRIGW_WARN_QP_NOCONV 1     /* some QP equations had no root (E = e + e_static returned) */
 #define LRIGW_WARN_PADE_TRUNC 2    /* some Pade fits were truncated at a zero coefficient */
+#define LRIGW_WARN_CD_RANGE 3      /* some contour-deformation residues lie beyond the real grid (NaN there) */
 
 enum lrigw_precision {
   LRIGW_FP64 = 0,        /* every contraction in FP64 (the plain path) */
@@ -236,6 +237,72 @@ int lrigw_qp(lrigw_ctx *ctx, const void *sigma, const double *eps_qp, const doub
 int lrigw_g0w0(lrigw_ctx *ctx, const void *H, const void *evec, const double *eig, const void *V, const void *p,
                double omega_cell, const double *e_static, int n_par, int q_first, int q_last,
                void *sigma, double *e_qp, double *z, int *info);
+
+/* ---- Sigma^c at real energies by contour deformation (the alternative to
+ * analytic continuation named in Sec. II A, after Eq. chi_0_realspace).
+ *
+ * Moving the real-axis frequency integral onto the imaginary axis leaves two
+ * terms, with z = E - e_m(k-q) and X_nm(w) = x^T W^c(q,w) conj(x) the pair
+ * weight of Eq. GW_selfe_element:
+ *   Sigma^c_n(k,E) = 1/N_q sum_q sum_m [ -(1/pi) int_0^inf X_nm(iw) z/(z^2+w^2) dw
+ *                                        + theta_m(E) X_nm(|z|) ]
+ * The first is the imaginary-axis integral; the second collects the residues
+ * of the Green-function poles passed over.  theta = +1 for an unoccupied m
+ * below E, -1 for an occupied m above E, half of that at E = e_m, else 0.
+ *
+ * W^c on the real axis is formed below the smallest transition energy D_min
+ * only.  There the response weight is 2D/(D^2 - w^2), chi~ is Hermitian and
+ * eps~ positive definite.  This serves states near the band edges, whose
+ * residues come from levels between mu and E.
+ *
+ * Discretisation:
+ *  - Real planes: the uniform grid w_r = r h, r < n_r.  X between nodes is
+ *    the 4-point Lagrange interpolant, with the stencil reflected at w = 0.
+ *  - Imaginary-axis integral: the response grid, with X(0) (the first real
+ *    plane) subtracted and its integral (pi/2) sgn(z) X(0) added in closed
+ *    form.
+ *  - A residue frequency above (n_r - 1) h makes that output NaN. */
+
+/* Define the real grid: 4 <= n_r <= n_freq planes, w_r = r omega_max/(n_r-1).
+ * Allocates the context's real-axis buffers (2 n_r N_aux^2 complex of the
+ * compute type, n_r N_k n_qp n_bands doubles) and waits for the stream.
+ * Errors: ERR_ARG (n_r or omega_max out of range), ERR_OOM. */
+int lrigw_set_real_grid(lrigw_ctx *ctx, int n_r, double omega_max);
+
+/* chi~(q, w_r) at the n_r real frequencies: as lrigw_chi0 (same M, eig,
+ * apply_gamma and output layout [n_r][N_aux][N_aux]), weight 2D/(D^2 - w^2).
+ * Errors: ERR_ARG (no real grid, or omega_max >= the smallest transition
+ * energy of eig, where the response has a pole), as lrigw_chi0 otherwise. */
+int lrigw_chi0_real(lrigw_ctx *ctx, int iq, const void *M, const double *eig, int apply_gamma, void *chi_out);
+
+/* W^c(q, w_r) from lrigw_chi0_real's output: lrigw_screen over n_r planes. */
+int lrigw_screen_real(lrigw_ctx *ctx, int iq, const void *chi, const void *V, void *Wc_out, int *info);
+
+/* Contribution of q to Sigma^c_n(k, E) at n_e (1..4) sets of real energies.
+ * x: slice-1 output of lrigw_build_M; Wc: lrigw_screen output (n_freq
+ * planes); Wr: lrigw_screen_real output (n_r planes); E: FP64 [n_e][N_k][n_qp]
+ * absolute energies (Ha) on the device; sigma_e: FP64 [n_e][N_k][n_qp],
+ * accumulated.  Pair weights in the compute type, the combination in FP64. */
+int lrigw_sigma_cd(lrigw_ctx *ctx, int iq, const void *x, const void *Wc, const void *Wr, const double *eig, int n_e,
+                   const double *E, double *sigma_e);
+
+/* lrigw_sigma_cd summed over every q.  The per-q response and W^c come from
+ * the exact response on both grids, with the q = 0 head and wings when p !=
+ * NULL.  Arguments are as for lrigw_g0w0; sigma_e is set (not accumulated).
+ * n_bad (host, may be NULL) receives the number of NaN outputs.
+ * Returns WARN_CD_RANGE when there are any. */
+int lrigw_sigma_cd_pass(lrigw_ctx *ctx, const void *H, const void *evec, const double *eig, const void *V, const void *p,
+                        double omega_cell, int n_e, const double *E, double *sigma_e, int *n_bad);
+
+/* Linearised quasiparticle energies from contour deformation:
+ *   Sigma^c at e_n - delta, e_n, e_n + delta (e_n the band energies of the QP bands),
+ *   E_n = e_n + Z (Sigma^c(e_n) + e_static_n),
+ *   Z = 1 / (1 - (Sigma^c(e_n + delta) - Sigma^c(e_n - delta)) / (2 delta)).
+ * sigma3: FP64 [3][N_k][n_qp] output or NULL; e_qp, z: FP64 [N_k][n_qp]
+ * outputs; e_static may be NULL.  Returns WARN_CD_RANGE as lrigw_sigma_cd_pass. */
+int lrigw_g0w0_cd(lrigw_ctx *ctx, const void *H, const void *evec, const double *eig, const void *V, const void *p,
+                  double omega_cell, const double *e_static, double delta, double *sigma3, double *e_qp, double *z,
+                  int *n_bad);
 
 /* ---- Learned frequency surrogate of the response (a form the paper does not
  * have; it evaluates Eq. chi0_matrix at every frequency of the grid).

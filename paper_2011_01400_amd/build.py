@@ -13,7 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "liblrigw.so")
 SOURCES = ["api.hip", "k_grid.hip", "k_lri.hip", "k_build.hip", "k_chi0.hip", "k_sigma.hip", "k_dense.hip",
-           "k_screen.hip", "k_qp.hip", "k_surrogate.hip", "k_batch.hip", "k_exchange.hip", "k_fit.hip"]
+           "k_screen.hip", "k_qp.hip", "k_surrogate.hip", "k_batch.hip", "k_exchange.hip", "k_fit.hip",
+           "k_contour.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -1,5 +1,6 @@
 // C interface of the lrigw library: context, validation, driver, timing.
 #include <climits>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -50,7 +51,8 @@ static void free_all(lrigw_ctx *c) {
   void *ptrs[] = {c->d_aux_atom, c->d_basis_off, c->d_aux_off, c->d_kpq, c->d_kmq, c->d_omega, c->d_weight, c->d_wall,
                   c->d_delta, c->d_part, c->d_X, c->d_LV, c->d_s0, c->d_s1, c->d_s2, c->d_s3, c->d_dinv, c->d_info,
                   c->d_bhat, c->d_x1, c->d_M, c->d_x, c->d_chi, c->d_wc, c->d_epsqp, c->d_xs, c->d_ws, c->d_ap, c->d_bt, c->d_chi2, c->d_wc2,
-                  c->d_sx, c->d_wmax, c->d_amax, c->d_sitems, c->d_wd, c->d_xo, c->d_sxa, c->d_sxz};
+                  c->d_sx, c->d_wmax, c->d_amax, c->d_sitems, c->d_wd, c->d_xo, c->d_sxa, c->d_sxz, c->d_om2,
+                  c->d_wsc, c->d_chir, c->d_wr, c->d_Xr, c->d_cdE, c->d_cdS, c->d_cdbad};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &kv : c->stages)
@@ -181,6 +183,35 @@ int run_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, c
   return rc;
 }
 
+// Sigma^c at real energies over every q by contour deformation: per q the
+// response and W^c on the imaginary grid and on the real grid, the pairs of
+// the QP bands, and the combination at the n_e energy sets.  Runs on
+// `stream` alone; the exact response is used (an attached surrogate is not).
+int run_cd_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *p,
+                double omega_cell, int n_e, const double *E, double *sigma_e, int *n_bad) {
+  const Dims &d = c->d;
+  LRIGW_TRY(driver_buffers(c));
+  if (p) LRIGW_TRY(lrigw_gamma_prepare(c, V, p, omega_cell));
+  LRIGW_TRY(zero_fill(c->stream, sigma_e, (size_t)n_e * d.n_k * d.n_qp * sizeof(double)));
+  const size_t vstride = (size_t)d.n_aux * d.n_aux;
+  for (int q = 0; q < d.n_k; ++q) {
+    const double2 *Vq = (const double2 *)V + q * vstride;
+    const int g = (p && q == 0) ? 1 : 0;
+    int info = -1;
+    LRIGW_TRY(lrigw_build_M(c, q, 0, H, evec, c->d_M));
+    LRIGW_TRY(run_chi0(c, q, c->d_M, eig, g, c->d_chi));
+    LRIGW_TRY(run_screen(c, q, c->d_chi, Vq, c->d_wc, &info));
+    LRIGW_TRY(run_chi0_real(c, q, c->d_M, eig, g, c->d_chir));
+    LRIGW_TRY(run_screen_n(c, q, c->d_chir, Vq, c->d_wr, &info, c->n_real));
+    LRIGW_TRY(lrigw_build_M(c, q, 1, H, evec, c->d_x));
+    LRIGW_TRY(run_sigma_cd(c, q, c->d_x, c->d_wc, c->d_wr, eig, n_e, E, sigma_e));
+  }
+  int bad = 0;
+  LRIGW_TRY(cd_count_nan(c, sigma_e, n_e * d.n_k * d.n_qp, &bad));
+  if (n_bad) *n_bad = bad;
+  return bad ? LRIGW_WARN_CD_RANGE : LRIGW_OK;
+}
+
 extern "C" {
 
 const char *lrigw_strerror(int code) {
@@ -193,6 +224,7 @@ const char *lrigw_strerror(int code) {
     case LRIGW_ERR_NOCONV: return "iteration did not converge";
     case LRIGW_WARN_QP_NOCONV: return "warning: some quasiparticle equations had no root";
     case LRIGW_WARN_PADE_TRUNC: return "warning: some Pade fits were truncated";
+    case LRIGW_WARN_CD_RANGE: return "warning: some residue frequencies lie beyond the real grid (NaN returned)";
     default: return "unknown status";
   }
 }
@@ -399,6 +431,69 @@ int lrigw_qp(lrigw_ctx *c, const void *sigma, const double *eps_qp, const double
   stage_begin(c, "qp", &ev);
   int rc = run_qp(c, sigma, eps_qp, e_static, n_par, e_qp, z, info);
   stage_end(c, "qp", ev);
+  return rc;
+}
+
+int lrigw_set_real_grid(lrigw_ctx *c, int n_r, double omega_max) {
+  (void)hipGetLastError();
+  if (!c) return LRIGW_ERR_ARG;
+  return run_set_real_grid(c, n_r, omega_max);
+}
+
+int lrigw_chi0_real(lrigw_ctx *c, int iq, const void *M, const double *eig, int apply_gamma, void *chi_out) {
+  (void)hipGetLastError();
+  if (!c || !M || !eig || !chi_out) return LRIGW_ERR_ARG;
+  if (iq < 0 || iq >= c->d.n_k) return LRIGW_ERR_ARG;
+  if (apply_gamma && (iq != 0 || !c->gamma_ready)) return LRIGW_ERR_ARG;
+  hipEvent_t ev;
+  stage_begin(c, "chi0_real", &ev);
+  int rc = run_chi0_real(c, iq, M, eig, apply_gamma, chi_out);
+  stage_end(c, "chi0_real", ev);
+  return rc;
+}
+
+int lrigw_screen_real(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_out, int *info) {
+  (void)hipGetLastError();
+  if (!c || !chi || !V || !Wc_out) return LRIGW_ERR_ARG;
+  if (iq < 0 || iq >= c->d.n_k || c->n_real < 4) return LRIGW_ERR_ARG;
+  hipEvent_t ev;
+  stage_begin(c, "screen_real", &ev);
+  int rc = run_screen_n(c, iq, chi, V, Wc_out, info, c->n_real);
+  stage_end(c, "screen_real", ev);
+  return rc;
+}
+
+int lrigw_sigma_cd(lrigw_ctx *c, int iq, const void *x, const void *Wc, const void *Wr, const double *eig, int n_e,
+                   const double *E, double *sigma_e) {
+  (void)hipGetLastError();
+  if (!c || !x || !Wc || !Wr || !eig || !E || !sigma_e) return LRIGW_ERR_ARG;
+  if (iq < 0 || iq >= c->d.n_k) return LRIGW_ERR_ARG;
+  return run_sigma_cd(c, iq, x, Wc, Wr, eig, n_e, E, sigma_e);
+}
+
+int lrigw_sigma_cd_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *p,
+                        double omega_cell, int n_e, const double *E, double *sigma_e, int *n_bad) {
+  (void)hipGetLastError();
+  if (n_bad) *n_bad = 0;
+  if (!c || !H || !evec || !eig || !V || !E || !sigma_e) return LRIGW_ERR_ARG;
+  if (c->n_real < 4 || n_e < 1 || n_e > 4) return LRIGW_ERR_ARG;
+  if (p && !(omega_cell > 0.0)) return LRIGW_ERR_ARG;
+  return run_cd_pass(c, H, evec, eig, V, p, omega_cell, n_e, E, sigma_e, n_bad);
+}
+
+int lrigw_g0w0_cd(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *p,
+                  double omega_cell, const double *e_static, double delta, double *sigma3, double *e_qp, double *z,
+                  int *n_bad) {
+  (void)hipGetLastError();
+  if (n_bad) *n_bad = 0;
+  if (!c || !H || !evec || !eig || !V || !e_qp || !z) return LRIGW_ERR_ARG;
+  if (c->n_real < 4 || !(delta > 0.0) || !std::isfinite(delta)) return LRIGW_ERR_ARG;
+  if (p && !(omega_cell > 0.0)) return LRIGW_ERR_ARG;
+  double *S = sigma3 ? sigma3 : c->d_cdS;
+  LRIGW_TRY(cd_energies(c, eig, delta));
+  const int rc = run_cd_pass(c, H, evec, eig, V, p, omega_cell, 3, c->d_cdE, S, n_bad);
+  if (rc < 0) return rc;
+  LRIGW_TRY(cd_qp_linear(c, S, e_static, delta, e_qp, z));
   return rc;
 }
 

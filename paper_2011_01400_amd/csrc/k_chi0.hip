@@ -34,7 +34,7 @@ int chi0_alt_nw(int precision) { return precision == LRIGW_FP64 ? 1 : 2; }
 
 template <typename T, int NW>
 __global__ __launch_bounds__(256) void k_chi0_mfma(const typename c2t<T>::type *__restrict__ B, const T *__restrict__ delta,
-                                                   const double *__restrict__ omega, const int *__restrict__ wsel,
+                                                   const double *__restrict__ om2tab, const int *__restrict__ wsel,
                                                    const int *__restrict__ run, long long K, int N, int n_freq, long long Ks,
                                                    long long ntile, typename c2t<T>::type *__restrict__ part) {
   if (run && *run == 0) return;
@@ -56,10 +56,7 @@ __global__ __launch_bounds__(256) void k_chi0_mfma(const typename c2t<T>::type *
 
   T om2[NW];
 #pragma unroll
-  for (int w = 0; w < NW; ++w) {
-    double o = (w0 + w < n_freq) ? omega[wsel[w0 + w]] : 0.0;
-    om2[w] = (T)(o * o);
-  }
+  for (int w = 0; w < NW; ++w) om2[w] = (T)((w0 + w < n_freq) ? om2tab[wsel[w0 + w]] : 0.0);
   ACC re[NW][2][2], im[NW][2][2];
   ACC re2[NW][2][2], im2[NW][2][2];
 #pragma unroll
@@ -265,8 +262,8 @@ template <int V> struct IntC { static constexpr int value = V; };
 
 template <int NS, int NW, int PAD, bool H>
 __global__ __launch_bounds__(256, NW == 2 ? 2 : 1) void k_chi0_split(const us16 *__restrict__ Ap, const float2 *__restrict__ Bt,
-                                                    const float *__restrict__ delta, const double *__restrict__ omega,
-                                                    const int *__restrict__ wsel, const int *__restrict__ run, long long K,
+                                                    const float *__restrict__ delta, const double *__restrict__ om2tab,
+                                                    const float *__restrict__ wsctab, const int *__restrict__ wsel, const int *__restrict__ run, long long K,
                                                     long long Kp, int Npad, int n_freq, long long Ks, long long ntile,
                                                     const unsigned *__restrict__ amax, int N, float2 *__restrict__ part,
                                                     int nsplit) {
@@ -293,11 +290,9 @@ __global__ __launch_bounds__(256, NW == 2 ? 2 : 1) void k_chi0_split(const us16 
   float om2[NW], wsc[NW];
 #pragma unroll
   for (int w = 0; w < NW; ++w) {
-    const double o = (w0 + w < n_freq) ? omega[wsel[w0 + w]] : 0.0;
-    om2[w] = (float)(o * o);
-    int e = 0;
-    if (H && o > 0.0) frexp(1.0 / o, &e);   // 1/o < 2^e
-    wsc[w] = ldexpf(1.f, -e);
+    const bool in = w0 + w < n_freq;
+    om2[w] = in ? (float)om2tab[wsel[w0 + w]] : 0.f;
+    wsc[w] = (H && in) ? wsctab[wsel[w0 + w]] : 1.f;   // power of two, weight * wsc < 1
   }
   f4v re[NW][4], im[NW][4];
 #pragma unroll
@@ -560,14 +555,18 @@ static int check_gap(lrigw_ctx *c, const double *eig) {
       else cbm = std::min(cbm, e);
     }
   if (!(cbm > vbm)) return LRIGW_ERR_ARG;
+  c->gap_min = cbm - vbm;
   return LRIGW_OK;
 }
 
 // chi at the frequencies wsel[0..n_sel) (device indices into the grid); when
 // `run` is non-null the kernels do nothing unless *run != 0 (device flag).
 int run_chi0_sel(lrigw_ctx *c, int iq, const void *M, const double *eig, int apply_gamma, void *chi_out, const int *wsel,
-                 int n_sel, const int *run) {
+                 int n_sel, const int *run, bool real_axis) {
   const Dims &d = c->d;
+  // per-plane tables: imaginary planes first, then the real-axis ones
+  const double *om2t = c->d_om2 + (real_axis ? d.n_freq : 0);
+  const float *wsct = c->d_wsc + (real_axis ? d.n_freq : 0);
   if (eig != c->checked_eig) {
     LRIGW_TRY(check_gap(c, eig));
     c->checked_eig = eig;
@@ -590,7 +589,7 @@ int run_chi0_sel(lrigw_ctx *c, int iq, const void *M, const double *eig, int app
   stage_begin(c, "chi0_mfma", &ev);
   const int NW = c->chi_nw;
   dim3 grid((unsigned)ntile, (n_sel + NW - 1) / NW, S);
-#define CHI0_ARGS c->d_omega, wsel, run, K, d.n_aux, n_sel, Ks, ntile
+#define CHI0_ARGS om2t, wsel, run, K, d.n_aux, n_sel, Ks, ntile
   if (c->precision == LRIGW_FP64) {
     if (NW == 2)
       hipLaunchKernelGGL((k_chi0_mfma<double, 2>), grid, dim3(256), 0, c->stream, (const double2 *)B,
@@ -631,7 +630,7 @@ int run_chi0_sel(lrigw_ctx *c, int iq, const void *M, const double *eig, int app
       // 1D over (K split, tile, frequency group), split over the XCDs
       const long long sitems = (long long)((n_sel + NW - 1) / NW) * ntile * S;
       const dim3 sgrid((unsigned)(8 * ((sitems + 7) / 8)));
-#define BF16_ARGS Apd, Btd, Df, c->d_omega, wsel, run, K, Kp, Npad, n_sel, Ks, ntile, c->d_amax, d.n_aux, Pf, S
+#define BF16_ARGS Apd, Btd, Df, om2t, wsct, wsel, run, K, Kp, Npad, n_sel, Ks, ntile, c->d_amax, d.n_aux, Pf, S
 #define SPLIT_LAUNCH(NS_, H_)                                                                                            \
   do {                                                                                                                 \
     if (NW == 4 && p16) hipLaunchKernelGGL((k_chi0_split<NS_, 4, 16, H_>), sgrid, dim3(256), 0, c->stream, BF16_ARGS); \

@@ -113,6 +113,22 @@ int run_grids(lrigw_ctx *c) {
   LRIGW_HIP_TRY(hipMemcpyAsync(c->h_omega.data(), c->d_omega, d.n_freq * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   LRIGW_HIP_TRY(hipMemcpyAsync(c->h_weight.data(), c->d_weight, d.n_freq * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   LRIGW_HIP_TRY(hipStreamSynchronize(c->stream));
+  // response tables of the imaginary planes (the real-axis half is filled when
+  // a real grid is set): w^2, and the FP16 split's scale 2^-e with
+  // 2D/(D^2 + w^2) <= 1/w < 2^e
+  c->h_om2.assign(2 * (size_t)d.n_freq, 0.0);
+  c->h_wsc.assign(2 * (size_t)d.n_freq, 1.f);
+  for (int i = 0; i < d.n_freq; ++i) {
+    const double o = c->h_omega[i];
+    c->h_om2[i] = o * o;
+    int e = 0;
+    if (o > 0.0) frexp(1.0 / o, &e);
+    c->h_wsc[i] = ldexpf(1.f, -e);
+  }
+  LRIGW_HIP_TRY(hipMalloc(&c->d_om2, c->h_om2.size() * sizeof(double)));
+  LRIGW_HIP_TRY(hipMalloc(&c->d_wsc, c->h_wsc.size() * sizeof(float)));
+  LRIGW_HIP_TRY(hipMemcpy(c->d_om2, c->h_om2.data(), c->h_om2.size() * sizeof(double), hipMemcpyHostToDevice));
+  LRIGW_HIP_TRY(hipMemcpy(c->d_wsc, c->h_wsc.data(), c->h_wsc.size() * sizeof(float), hipMemcpyHostToDevice));
 
   // workspaces
   const bool f64 = c->precision == LRIGW_FP64;

@@ -73,8 +73,13 @@ static ZGemm mk(int m, int n, int k, int opa, const double2 *A, long long lda, l
 }
 
 int run_screen(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_out, int *info) {
+  return run_screen_n(c, iq, chi, V, Wc_out, info, c->d.n_freq);
+}
+
+// the first nw <= N_w planes of chi (the workspaces hold N_w)
+int run_screen_n(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_out, int *info, int nw) {
   const Dims &d = c->d;
-  const int n = d.n_aux, nw = d.n_freq;
+  const int n = d.n_aux;
   const long long nn = (long long)n * n;
   hipStream_t s = c->stream;
   // L_V

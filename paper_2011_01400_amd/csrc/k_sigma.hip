@@ -1048,78 +1048,88 @@ static void launch_sigma_split(int var, dim3 gs, hipStream_t st, const us16 *xs,
 #undef SIG_ARGS
 }
 
-int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const double *eig, void *sigma_acc) {
+// X[j][k][n][m] = Re x_nm^T W^c(w_j) conj(x_nm) for the first nw <= N_w
+// planes of Wc (the split workspaces hold N_w)
+int run_pair_weights(lrigw_ctx *c, const void *x, const void *Wc, int nw, double *X) {
   const Dims &d = c->d;
   const long long Ccols = (long long)d.n_k * d.n_qp * d.n_bands;
-  hipEvent_t ev_all, ev;
-  stage_begin(c, "sigma_c", &ev_all);
+  hipEvent_t ev;
   stage_begin(c, "sigma_mfma", &ev);
   const long long ncb = (Ccols + TILE - 1) / TILE;
-  dim3 grid(xcd_grid(d.n_freq, ncb));
+  dim3 grid(xcd_grid(nw, ncb));
   if (c->precision == LRIGW_FP64)
     hipLaunchKernelGGL(k_sigma_mfma<double>, grid, dim3(256), 0, c->stream, (const double2 *)x, (const double2 *)Wc, Ccols,
-                       d.n_aux, d.n_freq, (double *)c->d_X);
+                       d.n_aux, nw, X);
   else if (c->precision == LRIGW_FP32)
     hipLaunchKernelGGL(k_sigma_mfma<float>, grid, dim3(256), 0, c->stream, (const float2 *)x, (const float2 *)Wc, Ccols,
-                       d.n_aux, d.n_freq, (double *)c->d_X);
+                       d.n_aux, nw, X);
   else {
     const long long Cpad = (Ccols + TILE - 1) / TILE * TILE;
     const int Npad = (d.n_aux + SKB - 1) / SKB * SKB;
     const int Rpad = (d.n_aux + TILE - 1) / TILE * TILE;
     us16 *xs = (us16 *)c->d_xs, *ws = (us16 *)c->d_ws;
-    const long long nx = Cpad * (Npad / 8), nwt = (long long)d.n_freq * Rpad * (Npad / 8);
+    const long long nx = Cpad * (Npad / 8), nwt = (long long)nw * Rpad * (Npad / 8);
     const int NS = ns_sig(c->precision);
     const bool H = split_h(c->precision);
     const float2 *xf = (const float2 *)x, *Wf = (const float2 *)Wc;
     const dim3 gx((unsigned)((nx + 255) / 256)), gw((unsigned)((nwt + 255) / 256));
     if (H) {
       // per-frequency largest |W^c| for the FP16 scales
-      LRIGW_TRY(zero_fill(c->stream, c->d_wmax, (size_t)d.n_freq * sizeof(unsigned)));
+      LRIGW_TRY(zero_fill(c->stream, c->d_wmax, (size_t)nw * sizeof(unsigned)));
       const long long nn = (long long)d.n_aux * d.n_aux;
       const unsigned nb = (unsigned)std::min<long long>((nn + 4095) / 4096, 64);
-      hipLaunchKernelGGL(k_absmax_sets, dim3(nb, d.n_freq), dim3(256), 0, c->stream, Wf, nn, c->d_wmax);
+      hipLaunchKernelGGL(k_absmax_sets, dim3(nb, nw), dim3(256), 0, c->stream, Wf, nn, c->d_wmax);
       hipLaunchKernelGGL(k_split_x_h<2>, dim3((unsigned)(Cpad / 4)), dim3(256), 0, c->stream, xf, Ccols, d.n_aux, Cpad, Npad,
                          xs, c->d_sx);
-      hipLaunchKernelGGL((k_split_w<2, true>), gw, dim3(256), 0, c->stream, Wf, d.n_aux, Npad, Rpad, d.n_freq, c->d_wmax, ws);
+      hipLaunchKernelGGL((k_split_w<2, true>), gw, dim3(256), 0, c->stream, Wf, d.n_aux, Npad, Rpad, nw, c->d_wmax, ws);
     } else if (NS == 2) {
       hipLaunchKernelGGL(k_split_x<2>, gx, dim3(256), 0, c->stream, xf, Ccols, d.n_aux, Cpad, Npad, xs);
-      hipLaunchKernelGGL((k_split_w<2, false>), gw, dim3(256), 0, c->stream, Wf, d.n_aux, Npad, Rpad, d.n_freq, nullptr, ws);
+      hipLaunchKernelGGL((k_split_w<2, false>), gw, dim3(256), 0, c->stream, Wf, d.n_aux, Npad, Rpad, nw, nullptr, ws);
     } else {
       hipLaunchKernelGGL(k_split_x<3>, gx, dim3(256), 0, c->stream, xf, Ccols, d.n_aux, Cpad, Npad, xs);
-      hipLaunchKernelGGL((k_split_w<3, false>), gw, dim3(256), 0, c->stream, Wf, d.n_aux, Npad, Rpad, d.n_freq, nullptr, ws);
+      hipLaunchKernelGGL((k_split_w<3, false>), gw, dim3(256), 0, c->stream, Wf, d.n_aux, Npad, Rpad, nw, nullptr, ws);
     }
-    const int var = c->sig_var;
+    // the resident-tile form is planned for all N_w planes
+    const int var = (c->sig_var >= 7 && nw != d.n_freq) ? sigma_default_variant(c->precision) : c->sig_var;
     if (var >= 7) {
       if (!c->sig_res_ok) return LRIGW_ERR_ARG;
       // the exact diagonal term first; the resident kernel adds the rest
       hipLaunchKernelGGL(k_wdiag, dim3((unsigned)((d.n_aux * RES_WMAX + 255) / 256)), dim3(256), 0, c->stream, Wf, d.n_aux,
-                         d.n_freq, c->d_wd);
+                         nw, c->d_wd);
       hipLaunchKernelGGL(k_pair_diag, dim3((unsigned)((Ccols + 63) / 64)), dim3(256), 0, c->stream, xf, Ccols, d.n_aux,
-                         d.n_freq, c->d_wd, (double *)c->d_X);
+                         nw, c->d_wd, X);
     }
     stage_end(c, "sigma_split", ev);
     stage_begin(c, "sigma_mfma", &ev);
     const int snw = sigma_variant_snw(var);
-    dim3 gs(xcd_grid((d.n_freq + snw - 1) / snw, ncb));
+    dim3 gs(xcd_grid((nw + snw - 1) / snw, ncb));
     if (var >= 7) {
       const dim3 gr((unsigned)(8 * ncb));
       const int *t8 = c->d_sitems, *t4 = c->d_sitems + 8 * (RES_MAXI + 1);
-#define RES_ARGS xs, ws, xf, Wf, Ccols, Cpad, d.n_aux, Npad, Rpad, d.n_freq, c->sig_res_F
-      if (var == 7) hipLaunchKernelGGL((k_sigma_res<8, true, 8>), gr, dim3(512), 0, c->stream, RES_ARGS, t8, c->d_sx, c->d_wmax, (double *)c->d_X);
-      else hipLaunchKernelGGL((k_sigma_res<8, true, 4>), gr, dim3(256), 0, c->stream, RES_ARGS, t4, c->d_sx, c->d_wmax, (double *)c->d_X);
+#define RES_ARGS xs, ws, xf, Wf, Ccols, Cpad, d.n_aux, Npad, Rpad, nw, c->sig_res_F
+      if (var == 7) hipLaunchKernelGGL((k_sigma_res<8, true, 8>), gr, dim3(512), 0, c->stream, RES_ARGS, t8, c->d_sx, c->d_wmax, X);
+      else hipLaunchKernelGGL((k_sigma_res<8, true, 4>), gr, dim3(256), 0, c->stream, RES_ARGS, t4, c->d_sx, c->d_wmax, X);
 #undef RES_ARGS
     } else if (H)
-      launch_sigma_split<2, true>(var, gs, c->stream, xs, ws, xf, Wf, Ccols, Cpad, d.n_aux, Npad, Rpad, d.n_freq, c->d_sx,
-                                  c->d_wmax, (double *)c->d_X);
+      launch_sigma_split<2, true>(var, gs, c->stream, xs, ws, xf, Wf, Ccols, Cpad, d.n_aux, Npad, Rpad, nw, c->d_sx,
+                                  c->d_wmax, X);
     else if (NS == 2)
-      launch_sigma_split<2, false>(var, gs, c->stream, xs, ws, xf, Wf, Ccols, Cpad, d.n_aux, Npad, Rpad, d.n_freq, nullptr,
-                                   nullptr, (double *)c->d_X);
+      launch_sigma_split<2, false>(var, gs, c->stream, xs, ws, xf, Wf, Ccols, Cpad, d.n_aux, Npad, Rpad, nw, nullptr,
+                                   nullptr, X);
     else
-      launch_sigma_split<3, false>(var, gs, c->stream, xs, ws, xf, Wf, Ccols, Cpad, d.n_aux, Npad, Rpad, d.n_freq, nullptr,
-                                   nullptr, (double *)c->d_X);
+      launch_sigma_split<3, false>(var, gs, c->stream, xs, ws, xf, Wf, Ccols, Cpad, d.n_aux, Npad, Rpad, nw, nullptr,
+                                   nullptr, X);
   }
   stage_end(c, "sigma_mfma", ev);
   LRIGW_TRY(lrigw_launch_check("sigma_mfma"));
+  return LRIGW_OK;
+}
+
+int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const double *eig, void *sigma_acc) {
+  const Dims &d = c->d;
+  hipEvent_t ev_all;
+  stage_begin(c, "sigma_c", &ev_all);
+  LRIGW_TRY(run_pair_weights(c, x, Wc, d.n_freq, (double *)c->d_X));
   dim3 g2((unsigned)d.n_k, (unsigned)((d.n_freq + SF_I - 1) / SF_I), (unsigned)((d.n_qp + SF_N - 1) / SF_N));
   const double scale = -1.0 / (M_PI * d.n_k);
   hipLaunchKernelGGL(k_sigma_freq, g2, dim3(64), 0, c->stream, (const double *)c->d_X, eig, c->d_kmq, iq, d.n_k, d.n_qp,

@@ -85,6 +85,23 @@ struct lrigw_ctx {
   double *d_omega = nullptr, *d_weight = nullptr;
   int *d_wall = nullptr;         // [N_w] 0, 1, ..., N_w - 1 (every frequency selected)
   std::vector<double> h_omega, h_weight;
+  // per-plane tables of the response kernels, [2 N_w]: the imaginary planes,
+  // then the real-axis planes.  om2 is the signed square (+w^2 on the
+  // imaginary axis, -w^2 on the real axis, so the weight 2D/(D^2 + om2) is
+  // the one of either axis); wsc the FP16 split's power-of-two weight scale.
+  double *d_om2 = nullptr;
+  float *d_wsc = nullptr;
+  std::vector<double> h_om2;
+  std::vector<float> h_wsc;
+  double gap_min = 0.0;          // smallest transition energy of the checked eigenvalues
+  // real-axis grid w_r = r h, r < n_real (0: none); its buffers
+  int n_real = 0;
+  double real_h = 0.0, real_wsc_gap = -1.0;
+  void *d_chir = nullptr, *d_wr = nullptr;   // [n_real][N][N] response / W^c (compute type)
+  double *d_Xr = nullptr;        // [n_real][N_k*n_qp*n_bands] pair weights on the real grid
+  double *d_cdE = nullptr;       // [3][N_k][n_qp] evaluation energies of the linearised QP
+  double *d_cdS = nullptr;       // [3][N_k][n_qp] Sigma^c at those energies
+  int *d_cdbad = nullptr;        // count of (e, k, n) whose residues passed the grid's top
 
   // per-q workspaces
   void *d_delta = nullptr;       // [K] transition energies of one q (T)
@@ -179,13 +196,24 @@ int run_lri_ft(lrigw_ctx *c, const double *lri_R, const int *R_list, int nR, con
 int run_build_M(lrigw_ctx *c, int iq, int slice, const void *H, const void *evec, void *M_out);
 int run_chi0(lrigw_ctx *c, int iq, const void *M, const double *eig, int apply_gamma, void *chi_out);
 int run_chi0_sel(lrigw_ctx *c, int iq, const void *M, const double *eig, int apply_gamma, void *chi_out, const int *wsel,
-                 int n_sel, const int *run);
+                 int n_sel, const int *run, bool real_axis = false);
 int surrogate_prepare(lrigw_surrogate *sg);
 int run_chi0_surrogate(lrigw_ctx *c, lrigw_surrogate *sg, int iq, const void *M, const double *eig, int apply_gamma,
                        double threshold, void *chi_out);
 int run_gamma_prepare(lrigw_ctx *c, const void *Vcut0, const void *p, double omega_cell);
 int run_screen(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_out, int *info);
+int run_screen_n(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_out, int *info, int nw);
 int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const double *eig, void *sigma_acc);
+int run_pair_weights(lrigw_ctx *c, const void *x, const void *Wc, int nw, double *X);
+int run_set_real_grid(lrigw_ctx *c, int n_r, double omega_max);
+int run_chi0_real(lrigw_ctx *c, int iq, const void *M, const double *eig, int apply_gamma, void *chi_out);
+int run_sigma_cd(lrigw_ctx *c, int iq, const void *x, const void *Wc, const void *Wr, const double *eig, int n_e,
+                 const double *E, double *sigma_e);
+int cd_energies(lrigw_ctx *c, const double *eig, double delta);
+int cd_qp_linear(lrigw_ctx *c, const double *S, const double *e_static, double delta, double *e_qp, double *z);
+int cd_count_nan(lrigw_ctx *c, const double *v, int n, int *out);
+int run_cd_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *p,
+                double omega_cell, int n_e, const double *E, double *sigma_e, int *n_bad);
 int run_sigma_x(lrigw_ctx *c, int iq, const void *xo, const void *V, double *sigma_x);
 int run_lri_fit(lrigw_ctx *c, int batch, int n, int n_keep, int nrhs, const double *V, const double *T, double scale,
                 double *C, int *info);

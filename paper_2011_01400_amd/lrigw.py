@@ -23,6 +23,7 @@ LRIGW_ERR_NOT_HPD = -4
 LRIGW_ERR_NOCONV = -5
 LRIGW_WARN_QP_NOCONV = 1
 LRIGW_WARN_PADE_TRUNC = 2
+LRIGW_WARN_CD_RANGE = 3
 
 FP64, FP32, SPLIT_BF16, SPLIT3_BF16, SPLIT_MIXED, SPLIT_F16 = 0, 1, 2, 3, 4, 5
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "split_bf16": SPLIT_BF16, "split3_bf16": SPLIT3_BF16,
@@ -32,7 +33,8 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "split_bf16": SPLIT_BF16, "split3_bf16
 EXPORTS = ["lrigw_create", "lrigw_destroy", "lrigw_strerror", "lrigw_get_sizes", "lrigw_grids", "lrigw_lri_ft",
            "lrigw_build_M", "lrigw_chi0", "lrigw_gamma_prepare", "lrigw_screen", "lrigw_sigma_c", "lrigw_sigma_x",
            "lrigw_sigma_x_pass", "lrigw_lri_fit", "lrigw_qp",
-           "lrigw_g0w0", "lrigw_set_timing", "lrigw_stage_ms", "lrigw_reset_timing",
+           "lrigw_set_real_grid", "lrigw_chi0_real", "lrigw_screen_real", "lrigw_sigma_cd", "lrigw_sigma_cd_pass",
+           "lrigw_g0w0_cd", "lrigw_g0w0", "lrigw_set_timing", "lrigw_stage_ms", "lrigw_reset_timing",
            "lrigw_surrogate_create", "lrigw_surrogate_destroy", "lrigw_surrogate_info", "lrigw_surrogate_rule",
            "lrigw_surrogate_params", "lrigw_surrogate_basis", "lrigw_surrogate_add", "lrigw_surrogate_rows",
            "lrigw_surrogate_forward", "lrigw_surrogate_grad", "lrigw_surrogate_train", "lrigw_chi0_surrogate",
@@ -103,6 +105,12 @@ def load(path: Optional[str] = None):
         "lrigw_sigma_x_pass": (i, [vp, vp, vp, vp, vp]),
         "lrigw_lri_fit": (i, [vp, i, i, i, i, vp, vp, d, vp, ip]),
         "lrigw_qp": (i, [vp, vp, vp, vp, i, vp, vp, ip]),
+        "lrigw_set_real_grid": (i, [vp, i, d]),
+        "lrigw_chi0_real": (i, [vp, i, vp, vp, i, vp]),
+        "lrigw_screen_real": (i, [vp, i, vp, vp, vp, ip]),
+        "lrigw_sigma_cd": (i, [vp, i, vp, vp, vp, vp, i, vp, vp]),
+        "lrigw_sigma_cd_pass": (i, [vp, vp, vp, vp, vp, vp, d, i, vp, vp, ip]),
+        "lrigw_g0w0_cd": (i, [vp, vp, vp, vp, vp, vp, d, vp, d, vp, vp, vp, ip]),
         "lrigw_g0w0": (i, [vp, vp, vp, vp, vp, vp, d, vp, i, i, i, vp, vp, vp, ip]),
         "lrigw_set_timing": (i, [vp, i]),
         "lrigw_stage_ms": (d, [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_longlong)]),
@@ -283,6 +291,51 @@ class Context:
                                ctypes.byref(info))
         self._check(rc, "lrigw_qp", allow_warn=True)
         return rc, info.value
+
+    # ---- contour deformation (real energies) ---------------------------
+    def set_real_grid(self, n_r, omega_max):
+        self._check(self.lib.lrigw_set_real_grid(self.h, int(n_r), float(omega_max)), "lrigw_set_real_grid")
+        self.n_real = int(n_r)
+
+    def empty_real(self):
+        """[n_r][N_aux][N_aux] buffer of the compute type (real-axis response or W^c)."""
+        import torch
+        n = int(self.sizes.n_aux)
+        return torch.empty(self.n_real * n * n, dtype=self.cdtype, device="cuda")
+
+    def chi0_real(self, iq, M, eig, chi_out, apply_gamma=False):
+        self._check(self.lib.lrigw_chi0_real(self.h, int(iq), _ptr(M), _ptr(eig), int(bool(apply_gamma)),
+                                             _ptr(chi_out)), "lrigw_chi0_real")
+        return chi_out
+
+    def screen_real(self, iq, chi, V, Wc_out):
+        info = ctypes.c_int(0)
+        rc = self.lib.lrigw_screen_real(self.h, int(iq), _ptr(chi), _ptr(V), _ptr(Wc_out), ctypes.byref(info))
+        if rc < 0:
+            e = LrigwError(rc, "lrigw_screen_real")
+            e.info = info.value
+            raise e
+        return Wc_out
+
+    def sigma_cd(self, iq, x, Wc, Wr, eig, E, sigma_e):
+        """E, sigma_e: FP64 [n_e][N_k][n_qp] (device); sigma_e accumulated."""
+        self._check(self.lib.lrigw_sigma_cd(self.h, int(iq), _ptr(x), _ptr(Wc), _ptr(Wr), _ptr(eig), int(E.shape[0]),
+                                            _ptr(E), _ptr(sigma_e)), "lrigw_sigma_cd")
+        return sigma_e
+
+    def sigma_cd_pass(self, H, evec, eig, V, p, omega_cell, E, sigma_e):
+        bad = ctypes.c_int(0)
+        rc = self.lib.lrigw_sigma_cd_pass(self.h, _ptr(H), _ptr(evec), _ptr(eig), _ptr(V), _ptr(p), float(omega_cell),
+                                          int(E.shape[0]), _ptr(E), _ptr(sigma_e), ctypes.byref(bad))
+        self._check(rc, "lrigw_sigma_cd_pass", allow_warn=True)
+        return rc, bad.value
+
+    def g0w0_cd(self, H, evec, eig, V, p, omega_cell, e_static, delta, e_qp, z, sigma3=None):
+        bad = ctypes.c_int(0)
+        rc = self.lib.lrigw_g0w0_cd(self.h, _ptr(H), _ptr(evec), _ptr(eig), _ptr(V), _ptr(p), float(omega_cell),
+                                    _ptr(e_static), float(delta), _ptr(sigma3), _ptr(e_qp), _ptr(z), ctypes.byref(bad))
+        self._check(rc, "lrigw_g0w0_cd", allow_warn=True)
+        return rc, bad.value
 
     def g0w0(self, H, evec, eig, V, p, omega_cell, e_static, n_par, sigma, e_qp, z, q_first=0, q_last=None):
         info = ctypes.c_int(0)
