@@ -191,6 +191,38 @@ def sigma_x_timing(run, sysm, dev, reps=3):
             "range_ha": [round(float(v.min()), 6), round(float(v.max()), 6)]}
 
 
+def contour_timing(run, sysm, dev, n_r=16, reps=1):
+    """Quasiparticle energies by contour deformation (lrigw_g0w0_cd) on the
+    same cell and form, outside the timed region of the metric: per q the
+    response and W^c on the imaginary grid and on n_r real frequencies up to
+    0.6 of the smallest transition energy, Sigma^c at e_n and e_n -+ 2 mHa,
+    then the linearised QP step.  States whose residue frequencies pass the
+    real grid (those far from the band edges) come back as NaN."""
+    torch = run.torch
+    sp = sysm.spec
+    occ, un = sysm.eig[:, :sysm.n_occ], sysm.eig[:, sysm.n_occ:]
+    dmin = float(un.min() - occ.max())
+    wmax = 0.6 * dmin
+    run.ctx.set_real_grid(n_r, wmax)
+    e = torch.zeros((sysm.n_k, sp.n_qp), dtype=torch.float64, device="cuda")
+    z = torch.zeros_like(e)
+    args = (run.H, dev["evec"], dev["eig"], dev["V"], dev["p"], sysm.omega_cell, dev["e_static"], 0.002, e, z)
+    run.ctx.g0w0_cd(*args)   # first call allocates its workspaces
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        rc, bad = run.ctx.g0w0_cd(*args)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    ev = e.cpu().numpy()
+    ok = np.isfinite(ev)
+    return {"ms_per_pass": round(dt * 1e3, 3), "n_real": n_r, "omega_max_ha": round(wmax, 6),
+            "pairs_per_s": round(sysm.n_k * (sp.n_freq + n_r) / dt, 1),
+            "states_evaluated": int(ok.sum()), "states": int(ok.size), "nan_outputs": int(bad),
+            "z_range": [round(float(z.cpu().numpy()[ok].min()), 4), round(float(z.cpu().numpy()[ok].max()), 4)]
+            if ok.any() else None}
+
+
 def lri_fit_timing(run, sysm, reps=2):
     """Two-centre coefficient fit (lrigw_lri_fit) at the Si-like cell's shape:
     every off-site pair (I, J(R)) of its 2 atoms and 125 lattice vectors,
@@ -399,6 +431,8 @@ def main():
         out["tuned"] = tuned
     out["sigma_x"] = sigma_x_timing(run, sysm, dev)
     out["lri_fit"] = lri_fit_timing(run, sysm)
+    print("# bench: contour-deformation pass", file=sys.stderr, flush=True)
+    out["contour_deformation"] = contour_timing(run, sysm, dev)
     if plain:
         out["plain_fp64"] = plain
         out["speedup_vs_plain"] = round(value / plain["value"], 3)

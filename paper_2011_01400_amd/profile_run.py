@@ -56,6 +56,33 @@ def run(precision: str, config: int, q: int):
     print(f"profile_run: {precision} config {config} q {q} done", flush=True)
 
 
+def run_contour(precision: str, config: int, n_r: int = 16):
+    """The tile tuner, then one whole contour-deformation pass (lrigw_g0w0_cd,
+    n_r real frequencies up to 0.6 of the smallest transition energy), the
+    workload of bench.py's contour-deformation figures."""
+    import numpy as np
+    import torch
+    sys.path.insert(0, ROOT)
+    from paper_2011_01400_amd import lrigw as L
+    from synth.systems import make_config
+    L.load()
+    s = make_config(config)
+    dev = L.device_inputs(s)
+    sp = s.spec
+    ctx = L.Context.from_system(s, precision=precision)
+    H = ctx.empty("H")
+    ctx.lri_ft(dev["lri"], s.R, dev["evec"], H)
+    ctx.tune(H, dev["evec"], dev["eig"])
+    dmin = float(s.eig[:, s.n_occ:].min() - s.eig[:, :s.n_occ].max())
+    ctx.set_real_grid(n_r, 0.6 * dmin)
+    e = torch.zeros((s.n_k, sp.n_qp), dtype=torch.float64, device="cuda")
+    z = torch.zeros_like(e)
+    rc, bad = ctx.g0w0_cd(H, dev["evec"], dev["eig"], dev["V"], dev["p"], s.omega_cell, dev["e_static"], 0.002, e, z)
+    torch.cuda.synchronize()
+    print(f"profile_run: contour pass {precision} config {config}: rc {rc}, "
+          f"{int(np.isfinite(e.cpu().numpy()).sum())} states evaluated", flush=True)
+
+
 def _rows(d):
     files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
     if not files:
@@ -127,9 +154,12 @@ if __name__ == "__main__":
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--q", type=int, default=1)
     ap.add_argument("--summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--contour", action="store_true", help="one contour-deformation pass instead of one q")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "traffic.json"))
     a = ap.parse_args()
     if a.summarize:
         summarize(a.summarize[0], a.summarize[1], a.precision, a.config, a.out)
+    elif a.contour:
+        run_contour(a.precision, a.config)
     else:
         run(a.precision, a.config, a.q)
