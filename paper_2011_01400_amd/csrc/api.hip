@@ -52,7 +52,7 @@ static void free_all(lrigw_ctx *c) {
                   c->d_delta, c->d_part, c->d_X, c->d_LV, c->d_s0, c->d_s1, c->d_s2, c->d_s3, c->d_dinv, c->d_info,
                   c->d_bhat, c->d_x1, c->d_M, c->d_x, c->d_chi, c->d_wc, c->d_epsqp, c->d_xs, c->d_ws, c->d_ap, c->d_bt, c->d_chi2, c->d_wc2,
                   c->d_sx, c->d_wmax, c->d_amax, c->d_sitems, c->d_wd, c->d_xo, c->d_sxa, c->d_sxz, c->d_om2,
-                  c->d_wsc, c->d_chir, c->d_wr, c->d_Xr, c->d_cdE, c->d_cdS, c->d_cdbad};
+                  c->d_wsc, c->d_chir, c->d_wr, c->d_Xr, c->d_cdE, c->d_cdS, c->d_cdbad, c->d_sitems_r};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &kv : c->stages)

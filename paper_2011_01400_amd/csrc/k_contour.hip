@@ -159,6 +159,7 @@ int run_set_real_grid(lrigw_ctx *c, int n_r, double omega_max) {
   if (!c->d_cdE) LRIGW_HIP_TRY(hipMalloc(&c->d_cdE, 3 * (size_t)d.n_k * d.n_qp * sizeof(double)));
   if (!c->d_cdS) LRIGW_HIP_TRY(hipMalloc(&c->d_cdS, 3 * (size_t)d.n_k * d.n_qp * sizeof(double)));
   if (!c->d_cdbad) LRIGW_HIP_TRY(hipMalloc(&c->d_cdbad, sizeof(int)));
+  LRIGW_TRY(sigma_res_prepare_real(c, n_r));
   c->n_real = n_r;
   c->real_h = h;
   c->real_wsc_gap = -1.0;   // the FP16 scales depend on the gap: set at the next response

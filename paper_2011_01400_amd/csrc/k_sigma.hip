@@ -948,6 +948,22 @@ int sigma_res_prepare(lrigw_ctx *c) {
   return LRIGW_OK;
 }
 
+// the same lists for a second plane count (the real-axis planes of contour
+// deformation); without them those planes run in the tuner-free split form
+int sigma_res_prepare_real(lrigw_ctx *c, int n_r) {
+  c->sig_res_nr = 0;
+  if (!c->sig_res_ok || n_r > RES_WMAX) return LRIGW_OK;
+  std::vector<int> t8, t4;
+  int F = 0;
+  if (!sigma_res_plan(c->d.n_aux, n_r, 8, t8, F) || !sigma_res_plan(c->d.n_aux, n_r, 4, t4, F)) return LRIGW_OK;
+  t8.insert(t8.end(), t4.begin(), t4.end());
+  if (!c->d_sitems_r) LRIGW_HIP_TRY(hipMalloc(&c->d_sitems_r, t8.size() * sizeof(int)));   // fixed size per cell
+  LRIGW_HIP_TRY(hipMemcpy(c->d_sitems_r, t8.data(), t8.size() * sizeof(int), hipMemcpyHostToDevice));
+  c->sig_res_Fr = F;
+  c->sig_res_nr = n_r;
+  return LRIGW_OK;
+}
+
 // sigma[k][n][i] += scale * sum_m sum_j g_j X[j][k][n][m] a/(a^2 + w_j^2),  a = i w_i + mu - e_m(k-q)
 // One wave per (k, SF_I frequencies i, SF_N bands n): lanes run over the pairs
 // (m, j), m fastest (coalesced X), so each kernel value g_j a/(a^2 + w_j^2) is
@@ -1089,8 +1105,12 @@ int run_pair_weights(lrigw_ctx *c, const void *x, const void *Wc, int nw, double
       hipLaunchKernelGGL(k_split_x<3>, gx, dim3(256), 0, c->stream, xf, Ccols, d.n_aux, Cpad, Npad, xs);
       hipLaunchKernelGGL((k_split_w<3, false>), gw, dim3(256), 0, c->stream, Wf, d.n_aux, Npad, Rpad, nw, nullptr, ws);
     }
-    // the resident-tile form is planned for all N_w planes
-    const int var = (c->sig_var >= 7 && nw != d.n_freq) ? sigma_default_variant(c->precision) : c->sig_var;
+    // the resident-tile form has plans for the N_w imaginary planes and for
+    // the real-axis grid; any other plane count takes the default split form
+    const bool plan_w = nw == d.n_freq, plan_r = !plan_w && nw == c->sig_res_nr;
+    const int var = (c->sig_var >= 7 && !plan_w && !plan_r) ? sigma_default_variant(c->precision) : c->sig_var;
+    const int *items = plan_w ? c->d_sitems : c->d_sitems_r;
+    const int Fres = plan_w ? c->sig_res_F : c->sig_res_Fr;
     if (var >= 7) {
       if (!c->sig_res_ok) return LRIGW_ERR_ARG;
       // the exact diagonal term first; the resident kernel adds the rest
@@ -1105,8 +1125,8 @@ int run_pair_weights(lrigw_ctx *c, const void *x, const void *Wc, int nw, double
     dim3 gs(xcd_grid((nw + snw - 1) / snw, ncb));
     if (var >= 7) {
       const dim3 gr((unsigned)(8 * ncb));
-      const int *t8 = c->d_sitems, *t4 = c->d_sitems + 8 * (RES_MAXI + 1);
-#define RES_ARGS xs, ws, xf, Wf, Ccols, Cpad, d.n_aux, Npad, Rpad, nw, c->sig_res_F
+      const int *t8 = items, *t4 = items + 8 * (RES_MAXI + 1);
+#define RES_ARGS xs, ws, xf, Wf, Ccols, Cpad, d.n_aux, Npad, Rpad, nw, Fres
       if (var == 7) hipLaunchKernelGGL((k_sigma_res<8, true, 8>), gr, dim3(512), 0, c->stream, RES_ARGS, t8, c->d_sx, c->d_wmax, X);
       else hipLaunchKernelGGL((k_sigma_res<8, true, 4>), gr, dim3(256), 0, c->stream, RES_ARGS, t4, c->d_sx, c->d_wmax, X);
 #undef RES_ARGS

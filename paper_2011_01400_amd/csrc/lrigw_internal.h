@@ -131,6 +131,8 @@ struct lrigw_ctx {
   void *d_sxz = nullptr;         // V x of those pairs, FP64
   int sig_res_F = 0;             // resident-tile Sigma^c form: frequencies per workgroup
   bool sig_res_ok = false;       // resident-tile Sigma^c form applies to this cell
+  int *d_sitems_r = nullptr;     // resident-tile form: item lists for the real-axis planes (contour deformation)
+  int sig_res_Fr = 0, sig_res_nr = 0;   // their frequencies per workgroup and plane count (0: no plan)
 
   // q = 0 data
   double2 *d_x1 = nullptr;       // [N_aux]
@@ -205,6 +207,7 @@ int run_screen(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_ou
 int run_screen_n(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_out, int *info, int nw);
 int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const double *eig, void *sigma_acc);
 int run_pair_weights(lrigw_ctx *c, const void *x, const void *Wc, int nw, double *X);
+int sigma_res_prepare_real(lrigw_ctx *c, int n_r);
 int run_set_real_grid(lrigw_ctx *c, int n_r, double omega_max);
 int run_chi0_real(lrigw_ctx *c, int iq, const void *M, const double *eig, int apply_gamma, void *chi_out);
 int run_sigma_cd(lrigw_ctx *c, int iq, const void *x, const void *Wc, const void *Wr, const double *eig, int n_e,

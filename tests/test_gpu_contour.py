@@ -142,6 +142,41 @@ def test_sigma_cd_per_q_and_pass(case, precision):
     assert e < tol
 
 
+@pytest.mark.parametrize("var", [7, 8])
+def test_sigma_cd_resident_variants(case, var):
+    """The FP16 form's resident-tile self-energy kernel (8 and 4 waves per
+    workgroup) on both plane sets: the imaginary grid and the real grid, which
+    has item lists of its own."""
+    s, o, dev = case["sys"], case["o"], case["dev"]
+    sp = s.spec
+    ctx, H = _ctx(case, "split_f16")
+    ctx.set_tiles(4, 1, 8, var)
+    n_r, wmax = _grid(s)
+    omr, h = contour.real_grid(n_r, wmax)
+    E = case["E"]
+    Ed = torch.from_numpy(E).cuda()
+    q = 1 % s.n_k
+    B = o.B(q)
+    M, x = ctx.empty("M"), ctx.empty("x")
+    chi, W, chir, Wr = ctx.empty("W"), ctx.empty("W"), ctx.empty_real(), ctx.empty_real()
+    ctx.build_M(q, 0, H, dev["evec"], M)
+    ctx.chi0(q, M, dev["eig"], chi)
+    ctx.screen(q, chi, dev["V"][q], W)
+    ctx.chi0_real(q, M, dev["eig"], chir)
+    ctx.screen_real(q, chir, dev["V"][q], Wr)
+    ctx.build_M(q, 1, H, dev["evec"], x)
+    acc = torch.zeros((3, s.n_k, sp.n_qp), dtype=torch.float64, device="cuda")
+    ctx.sigma_cd(q, x, W, Wr, dev["eig"], Ed, acc)
+    ref = o.sigma_cd_q(q, o.wc(q, B=B, gamma=False), o.wc_real(q, omr, B=B, gamma=False), h, E)
+    e = np.max(np.abs(acc.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    out = torch.zeros((3, s.n_k, sp.n_qp), dtype=torch.float64, device="cuda")
+    rc, bad = ctx.sigma_cd_pass(H, dev["evec"], dev["eig"], dev["V"], dev["p"], s.omega_cell, Ed, out)
+    refp = o.sigma_cd(n_r, wmax, E)
+    ep = np.max(np.abs(out.cpu().numpy() - refp)) / np.max(np.abs(refp))
+    print(f"  {case['name']} variant {var}: q={q} Sigma^c(E) rel {e:.1e}, pass rel {ep:.1e}", flush=True)
+    assert e < 2e-5 and ep < 2e-5 and rc == 0 and bad == 0
+
+
 @pytest.mark.parametrize("precision,tol_mev", [("fp64", 1e-5), ("split_f16", 1.0)])
 def test_linearised_qp(case, precision, tol_mev):
     s, o, dev = case["sys"], case["o"], case["dev"]
