@@ -52,7 +52,7 @@ static void free_all(lrigw_ctx *c) {
                   c->d_delta, c->d_part, c->d_X, c->d_LV, c->d_s0, c->d_s1, c->d_s2, c->d_s3, c->d_dinv, c->d_info,
                   c->d_bhat, c->d_x1, c->d_M, c->d_x, c->d_chi, c->d_wc, c->d_epsqp, c->d_xs, c->d_ws, c->d_ap, c->d_bt, c->d_chi2, c->d_wc2,
                   c->d_sx, c->d_wmax, c->d_amax, c->d_sitems, c->d_wd, c->d_xo, c->d_sxa, c->d_sxz, c->d_om2,
-                  c->d_wsc, c->d_chir, c->d_wr, c->d_Xr, c->d_cdE, c->d_cdS, c->d_cdbad, c->d_sitems_r};
+                  c->d_wsc, c->d_chir, c->d_wr, c->d_Xr, c->d_cdE, c->d_cdS, c->d_cdbad, c->d_sitems_r, c->d_chir2, c->d_wr2};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &kv : c->stages)
@@ -185,27 +185,62 @@ int run_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, c
 
 // Sigma^c at real energies over every q by contour deformation: per q the
 // response and W^c on the imaginary grid and on the real grid, the pairs of
-// the QP bands, and the combination at the n_e energy sets.  Runs on
-// `stream` alone; the exact response is used (an attached surrogate is not).
+// the QP bands, and the combination at the n_e energy sets.  As in run_pass,
+// `stream2` screens q (both plane sets, into one of two buffer pairs) while
+// the responses of q+1 are built on `stream`; the same events order the
+// buffer reuse, and the screening status is folded on the device.  The
+// exact response is used (an attached surrogate is not).
 int run_cd_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *p,
                 double omega_cell, int n_e, const double *E, double *sigma_e, int *n_bad) {
   const Dims &d = c->d;
   LRIGW_TRY(driver_buffers(c));
   if (p) LRIGW_TRY(lrigw_gamma_prepare(c, V, p, omega_cell));
-  LRIGW_TRY(zero_fill(c->stream, sigma_e, (size_t)n_e * d.n_k * d.n_qp * sizeof(double)));
+  const hipStream_t s = c->stream, s2 = c->stream2;
+  LRIGW_TRY(zero_fill(s, sigma_e, (size_t)n_e * d.n_k * d.n_qp * sizeof(double)));
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->d_info + 16, INT_MAX);
   const size_t vstride = (size_t)d.n_aux * d.n_aux;
-  for (int q = 0; q < d.n_k; ++q) {
-    const double2 *Vq = (const double2 *)V + q * vstride;
-    const int g = (p && q == 0) ? 1 : 0;
-    int info = -1;
-    LRIGW_TRY(lrigw_build_M(c, q, 0, H, evec, c->d_M));
-    LRIGW_TRY(run_chi0(c, q, c->d_M, eig, g, c->d_chi));
-    LRIGW_TRY(run_screen(c, q, c->d_chi, Vq, c->d_wc, &info));
-    LRIGW_TRY(run_chi0_real(c, q, c->d_M, eig, g, c->d_chir));
-    LRIGW_TRY(run_screen_n(c, q, c->d_chir, Vq, c->d_wr, &info, c->n_real));
-    LRIGW_TRY(lrigw_build_M(c, q, 1, H, evec, c->d_x));
-    LRIGW_TRY(run_sigma_cd(c, q, c->d_x, c->d_wc, c->d_wr, eig, n_e, E, sigma_e));
+  void *chi[2] = {c->d_chi, c->d_chi2}, *wc[2] = {c->d_wc, c->d_wc2};
+  void *chir[2] = {c->d_chir, c->d_chir2}, *wr[2] = {c->d_wr, c->d_wr2};
+  c->capturing = true;   // screening: device-side status, no host round trip
+  int rc = LRIGW_OK;
+  for (int q = 0; q <= d.n_k && rc == LRIGW_OK; ++q) {
+    if (q < d.n_k) {
+      const int b = q & 1, g = (p && q == 0) ? 1 : 0;
+      const double2 *Vq = (const double2 *)V + q * vstride;
+      if ((rc = lrigw_build_M(c, q, 0, H, evec, c->d_M)) < 0) break;
+      if ((rc = run_chi0(c, q, c->d_M, eig, g, chi[b])) < 0) break;
+      if ((rc = run_chi0_real(c, q, c->d_M, eig, g, chir[b])) < 0) break;
+      if (hipEventRecord(c->ev_chi[b], s) != hipSuccess || hipStreamWaitEvent(s2, c->ev_chi[b], 0) != hipSuccess) {
+        rc = LRIGW_ERR_HIP;
+        break;
+      }
+      c->stream = s2;
+      rc = run_screen(c, q, chi[b], Vq, wc[b], nullptr);
+      if (rc == LRIGW_OK) rc = run_screen_n(c, q, chir[b], Vq, wr[b], nullptr, c->n_real);
+      c->stream = s;
+      if (rc < 0) break;
+      if (hipEventRecord(c->ev_wc[b], s2) != hipSuccess) {
+        rc = LRIGW_ERR_HIP;
+        break;
+      }
+    }
+    if (q > 0) {
+      const int pq = q - 1, b = pq & 1;
+      if ((rc = lrigw_build_M(c, pq, 1, H, evec, c->d_x)) < 0) break;
+      if (hipStreamWaitEvent(s, c->ev_wc[b], 0) != hipSuccess) {
+        rc = LRIGW_ERR_HIP;
+        break;
+      }
+      rc = run_sigma_cd(c, pq, c->d_x, wc[b], wr[b], eig, n_e, E, sigma_e);
+    }
   }
+  c->stream = s;
+  c->capturing = false;
+  if (rc < 0) return rc;
+  int h = INT_MAX;
+  LRIGW_HIP_TRY(hipMemcpyAsync(&h, c->d_info + 16, sizeof(int), hipMemcpyDeviceToHost, s));
+  LRIGW_HIP_TRY(hipStreamSynchronize(s));
+  if (h != INT_MAX) return LRIGW_ERR_NOT_HPD;
   int bad = 0;
   LRIGW_TRY(cd_count_nan(c, sigma_e, n_e * d.n_k * d.n_qp, &bad));
   if (n_bad) *n_bad = bad;
@@ -476,7 +511,7 @@ int lrigw_sigma_cd_pass(lrigw_ctx *c, const void *H, const void *evec, const dou
   (void)hipGetLastError();
   if (n_bad) *n_bad = 0;
   if (!c || !H || !evec || !eig || !V || !E || !sigma_e) return LRIGW_ERR_ARG;
-  if (c->n_real < 4 || n_e < 1 || n_e > 4) return LRIGW_ERR_ARG;
+  if (c->n_real < 4 || n_e < 1 || n_e > 4 || c->capturing) return LRIGW_ERR_ARG;
   if (p && !(omega_cell > 0.0)) return LRIGW_ERR_ARG;
   return run_cd_pass(c, H, evec, eig, V, p, omega_cell, n_e, E, sigma_e, n_bad);
 }
@@ -487,7 +522,7 @@ int lrigw_g0w0_cd(lrigw_ctx *c, const void *H, const void *evec, const double *e
   (void)hipGetLastError();
   if (n_bad) *n_bad = 0;
   if (!c || !H || !evec || !eig || !V || !e_qp || !z) return LRIGW_ERR_ARG;
-  if (c->n_real < 4 || !(delta > 0.0) || !std::isfinite(delta)) return LRIGW_ERR_ARG;
+  if (c->n_real < 4 || !(delta > 0.0) || !std::isfinite(delta) || c->capturing) return LRIGW_ERR_ARG;
   if (p && !(omega_cell > 0.0)) return LRIGW_ERR_ARG;
   double *S = sigma3 ? sigma3 : c->d_cdS;
   LRIGW_TRY(cd_energies(c, eig, delta));

@@ -145,15 +145,17 @@ int run_set_real_grid(lrigw_ctx *c, int n_r, double omega_max) {
   LRIGW_HIP_TRY(hipMemcpy(c->d_om2 + d.n_freq, c->h_om2.data() + d.n_freq, d.n_freq * sizeof(double),
                           hipMemcpyHostToDevice));
   if (n_r != c->n_real) {
-    void *bufs[] = {c->d_chir, c->d_wr, c->d_Xr};
+    void *bufs[] = {c->d_chir, c->d_wr, c->d_chir2, c->d_wr2, c->d_Xr};
     for (void *p : bufs)
       if (p) (void)hipFree(p);
-    c->d_chir = c->d_wr = nullptr;
+    c->d_chir = c->d_wr = c->d_chir2 = c->d_wr2 = nullptr;
     c->d_Xr = nullptr;
     c->n_real = 0;
     const size_t plane = (size_t)d.n_aux * d.n_aux * lrigw_csize(c);
     LRIGW_HIP_TRY(hipMalloc(&c->d_chir, n_r * plane));
     LRIGW_HIP_TRY(hipMalloc(&c->d_wr, n_r * plane));
+    LRIGW_HIP_TRY(hipMalloc(&c->d_chir2, n_r * plane));
+    LRIGW_HIP_TRY(hipMalloc(&c->d_wr2, n_r * plane));
     LRIGW_HIP_TRY(hipMalloc(&c->d_Xr, (size_t)n_r * d.n_k * d.n_qp * d.n_bands * sizeof(double)));
   }
   if (!c->d_cdE) LRIGW_HIP_TRY(hipMalloc(&c->d_cdE, 3 * (size_t)d.n_k * d.n_qp * sizeof(double)));

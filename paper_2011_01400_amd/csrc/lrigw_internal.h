@@ -98,6 +98,7 @@ struct lrigw_ctx {
   int n_real = 0;
   double real_h = 0.0, real_wsc_gap = -1.0;
   void *d_chir = nullptr, *d_wr = nullptr;   // [n_real][N][N] response / W^c (compute type)
+  void *d_chir2 = nullptr, *d_wr2 = nullptr; // second pair (the pass screens q while building q+1)
   double *d_Xr = nullptr;        // [n_real][N_k*n_qp*n_bands] pair weights on the real grid
   double *d_cdE = nullptr;       // [3][N_k][n_qp] evaluation energies of the linearised QP
   double *d_cdS = nullptr;       // [3][N_k][n_qp] Sigma^c at those energies
