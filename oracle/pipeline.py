@@ -35,6 +35,8 @@ class Oracle:
         self.qp = slice(sp.qp_lo, sp.qp_lo + sp.n_qp)
         self.allb = slice(0, sp.n_bands)
         self.n_par = min(n_par, sp.n_freq)
+        # q -> 0 averaged over directions: (p . q_hat_d [n_dir][N_k][N_occ][N_unocc], w_d), or None
+        self.gamma_dirs = None
 
     # ---- per-q pieces -------------------------------------------------
     def B(self, q):
@@ -69,6 +71,9 @@ class Oracle:
         s = self.sys
         if q == 0 and gamma:
             B = self.B(0) if B is None else B
+            if self.gamma_dirs is not None:
+                return screening.screen_gamma_average(B, s.eig, s.n_occ, *self.gamma_dirs, s.omega_cell, s.V[0],
+                                                      self.omega)
             return screening.screen_gamma(B, s.eig, s.n_occ, s.p, s.omega_cell, s.V[0], self.omega)[2]
         chi = self.chi0(q, B) if chi is None else chi
         return screening.screen(chi, s.V[q])[1]
@@ -92,6 +97,9 @@ class Oracle:
         s = self.sys
         if q == 0 and gamma:
             B = self.B(0) if B is None else B
+            if self.gamma_dirs is not None:
+                return screening.screen_gamma_average(B, s.eig, s.n_occ, *self.gamma_dirs, s.omega_cell, s.V[0],
+                                                      omega_r, real_axis=True)
             return screening.screen_gamma(B, s.eig, s.n_occ, s.p, s.omega_cell, s.V[0], omega_r, real_axis=True)[2]
         chi = self.chi0_real(q, omega_r, B) if chi is None else chi
         return screening.screen(chi, s.V[q])[1]

@@ -97,3 +97,13 @@ def screen_gamma(B0, eig, n_occ, p, omega_cell, Vcut0, omega, s=SPIN, real_axis=
         eps_mu[iw] = X @ eps_l[iw] @ X.conj().T
         Wc[iw] = (X * sv[None, :]) @ (np.linalg.inv(eps_l[iw]) - eye) @ (sv[:, None] * X.conj().T)
     return eps_l, eps_mu, Wc
+
+
+def screen_gamma_average(B0, eig, n_occ, p_dirs, weights, omega_cell, Vcut0, omega, s=SPIN, real_axis=False):
+    """W^c(q -> 0) averaged over directions q_hat_d: sum_d w_d W^c(q_hat_d), each
+    from `screen_gamma` with p_ia . q_hat_d (p_dirs: [n_dir][N_k][N_occ][N_unocc]).
+    The paper notes that head and wings depend on the direction of approach
+    and gives no averaging scheme; this weighted mean is the reading."""
+    return sum(w * screen_gamma(B0, eig, n_occ, pd, omega_cell, Vcut0, omega, s=s, real_axis=real_axis)[2]
+               for pd, w in zip(p_dirs, weights))
+

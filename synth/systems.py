@@ -267,6 +267,39 @@ def make_system(spec: CellSpec, seed: int, *, lri_scale: float = 1.0,
                   omega_cell=omega_cell, mu=float(mu), e_static=e_static, seed=seed)
 
 
+def momentum_vectors(sysm: System) -> np.ndarray:
+    """Cartesian momentum matrix elements p_ia(k), complex [3][N_k][N_occ][N_unocc],
+    for averaging the q -> 0 treatment over directions.  Drawn like
+    `System.p` (time reversal: p(-k) = -conj(p(k)), purely imaginary at the
+    invariant points), from a generator of their own seeded by the cell's seed."""
+    rng = np.random.default_rng([sysm.seed, 3])
+    sp = sysm.spec
+    n_k, n_occ, n_un = sysm.n_k, sp.n_occ, sp.n_bands - sp.n_occ
+    minus = _kidx(-_kint(sp.nk), sp.nk)
+    p3 = np.empty((3, n_k, n_occ, n_un), dtype=np.complex128)
+    for k in range(n_k):
+        mk = minus[k]
+        if mk < k:
+            p3[:, k] = -np.conj(p3[:, mk])
+        elif mk == k:
+            p3[:, k] = 1j * rng.normal(0.0, 0.5, (3, n_occ, n_un))
+        else:
+            p3[:, k] = (rng.normal(0.0, math.sqrt(0.125), (3, n_occ, n_un))
+                        + 1j * rng.normal(0.0, math.sqrt(0.125), (3, n_occ, n_un)))
+    return p3
+
+
+def cartesian_directions():
+    """The six half-axes +-x, +-y, +-z, equal weights."""
+    q = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], dtype=np.float64)
+    return q, np.full(6, 1.0 / 6.0)
+
+
+def project_momentum(p3, qhat) -> np.ndarray:
+    """p_ia(k) . q_hat for each direction: complex [n_dir][N_k][N_occ][N_unocc]."""
+    return np.einsum("c...,dc->d...", p3, np.asarray(qhat, dtype=np.float64))
+
+
 def make_config(config: int, cell: int = 0, **kw) -> System:
     """Cell `cell` of workload `config`; seed = 1000 * config + cell."""
     return make_system(CONFIGS[config][cell], 1000 * config + cell, **kw)
