@@ -238,6 +238,23 @@ int lrigw_g0w0(lrigw_ctx *ctx, const void *H, const void *evec, const double *ei
                double omega_cell, const double *e_static, int n_par, int q_first, int q_last,
                void *sigma, double *e_qp, double *z, int *info);
 
+/* Average the q -> 0 screening over directions of approach.  The head and
+ * wings of Eq. dielectric_func_gamma depend on the direction q_hat along which
+ * q -> 0 (Sec. III B); the paper gives no averaging scheme.  With n_dir > 0,
+ * the whole passes (lrigw_g0w0, lrigw_sigma_cd_pass, lrigw_g0w0_cd) take
+ * W^c(0) = sum_d weights[d] W^c(0; q_hat_d).  Each term is
+ * the exact q = 0 response with p . q_hat_d and its screening, on the
+ * context's stream; the surrogate is not used at q = 0.  The p argument of
+ * those calls must still be non-NULL (it selects the q = 0 treatment).
+ * p_dirs: device complex128 [n_dir][N_k][n_occ][n_unocc], p_ia(k) . q_hat_d.
+ * It stays owned by the caller and must outlive the passes.  weights: host
+ * double[n_dir], copied.  A set closed under q_hat -> -q_hat (e.g. the six
+ * Cartesian half-axes, equal weights) removes the wing terms from W^c(0), and
+ * with them the difference between Sigma^c(k) and Sigma^c(-k).  n_dir = 0
+ * returns to the single direction.  Errors: ERR_ARG (n_dir outside 0..64,
+ * NULL, non-finite weight). */
+int lrigw_set_gamma_directions(lrigw_ctx *ctx, int n_dir, const void *p_dirs, const double *weights);
+
 /* ---- Sigma^c at real energies by contour deformation (the alternative to
  * analytic continuation named in Sec. II A, after Eq. chi_0_realspace).
  *

@@ -132,6 +132,15 @@ int run_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, c
       const int b = q & 1;
       if ((rc = lrigw_build_M(c, q, 0, H, evec, c->d_M)) < 0) break;
       const int g = (p && q == 0) ? 1 : 0;
+      if (g && c->n_gdir > 0) {
+        // W^c(0) averaged over the directions, on `stream` (exact response;
+        // the other buffer, first used by q = 1, is the scratch)
+        if ((rc = run_gamma_average(c, eig, V, false, chi[b], wc[1 - b], wc[b])) < 0) break;
+        if (overlap && hipEventRecord(c->ev_wc[b], s) != hipSuccess) {
+          rc = LRIGW_ERR_HIP;
+          break;
+        }
+      } else {
       if (c->sur) rc = lrigw_chi0_surrogate(c, c->sur, q, c->d_M, eig, g, c->sur_threshold, chi[b]);
       else rc = lrigw_chi0(c, q, c->d_M, eig, g, chi[b]);
       if (rc < 0) break;
@@ -148,6 +157,7 @@ int run_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, c
       if (overlap && hipEventRecord(c->ev_wc[b], s2) != hipSuccess) {
         rc = LRIGW_ERR_HIP;
         break;
+      }
       }
     }
     if (q > q_first) {
@@ -208,6 +218,16 @@ int run_cd_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig
       const int b = q & 1, g = (p && q == 0) ? 1 : 0;
       const double2 *Vq = (const double2 *)V + q * vstride;
       if ((rc = lrigw_build_M(c, q, 0, H, evec, c->d_M)) < 0) break;
+      if (g && c->n_gdir > 0) {
+        // both plane sets of W^c(0) averaged over the directions, on `stream`
+        if ((rc = run_gamma_average(c, eig, Vq, false, chi[b], wc[1 - b], wc[b])) < 0) break;
+        if ((rc = run_gamma_average(c, eig, Vq, true, chir[b], wr[1 - b], wr[b])) < 0) break;
+        if (hipEventRecord(c->ev_wc[b], s) != hipSuccess) {
+          rc = LRIGW_ERR_HIP;
+          break;
+        }
+        continue;
+      }
       if ((rc = run_chi0(c, q, c->d_M, eig, g, chi[b])) < 0) break;
       if ((rc = run_chi0_real(c, q, c->d_M, eig, g, chir[b])) < 0) break;
       if (hipEventRecord(c->ev_chi[b], s) != hipSuccess || hipStreamWaitEvent(s2, c->ev_chi[b], 0) != hipSuccess) {
@@ -407,6 +427,23 @@ int lrigw_gamma_prepare(lrigw_ctx *c, const void *Vcut0, const void *p, double o
   (void)hipGetLastError();  // drop a stale error another library left behind
   if (!c || !Vcut0 || !p || !(omega_cell > 0.0)) return LRIGW_ERR_ARG;
   return run_gamma_prepare(c, Vcut0, p, omega_cell);
+}
+
+int lrigw_set_gamma_directions(lrigw_ctx *c, int n_dir, const void *p_dirs, const double *weights) {
+  if (!c || n_dir < 0 || n_dir > 64) return LRIGW_ERR_ARG;
+  if (n_dir == 0) {
+    c->n_gdir = 0;
+    c->gdir_p = nullptr;
+    c->gdir_w.clear();
+    return LRIGW_OK;
+  }
+  if (!p_dirs || !weights) return LRIGW_ERR_ARG;
+  for (int i = 0; i < n_dir; ++i)
+    if (!std::isfinite(weights[i])) return LRIGW_ERR_ARG;
+  c->gdir_w.assign(weights, weights + n_dir);
+  c->gdir_p = p_dirs;
+  c->n_gdir = n_dir;
+  return LRIGW_OK;
 }
 
 int lrigw_screen(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_out, int *info) {

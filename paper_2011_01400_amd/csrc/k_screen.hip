@@ -139,3 +139,46 @@ int run_screen_n(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_
   }
   return LRIGW_OK;
 }
+
+// out = tmp * w (first direction) or out + tmp * w
+template <typename C>
+__global__ void k_waccum(C *__restrict__ out, const C *__restrict__ tmp, long long n, double w, int first) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long st = (long long)gridDim.x * blockDim.x;
+  for (; i < n; i += st) {
+    C t = tmp[i], o = first ? C{0, 0} : out[i];
+    o.x += w * t.x;
+    o.y += w * t.y;
+    out[i] = o;
+  }
+}
+
+// W^c(q -> 0) averaged over the context's directions: per direction the q = 0
+// response with that direction's head and wings (M already built for q = 0),
+// its screening into tmp, and out = sum_d w_d tmp_d.  Runs on c->stream; the
+// screening status follows c->capturing as in run_screen.
+int run_gamma_average(lrigw_ctx *c, const double *eig, const void *V0, bool real_axis, void *chi, void *tmp, void *out) {
+  const Dims &d = c->d;
+  const int nw = real_axis ? c->n_real : d.n_freq;
+  const long long n = (long long)nw * d.n_aux * d.n_aux;
+  const size_t per = (size_t)lrigw_K(c);
+  const void *saved = c->gamma_p;
+  const unsigned nb = (unsigned)std::min<long long>((n + 255) / 256, 16384);
+  int rc = LRIGW_OK;
+  for (int g = 0; g < c->n_gdir && rc == LRIGW_OK; ++g) {
+    c->gamma_p = (const double2 *)c->gdir_p + g * per;
+    rc = real_axis ? run_chi0_real(c, 0, c->d_M, eig, 1, chi) : run_chi0(c, 0, c->d_M, eig, 1, chi);
+    if (rc == LRIGW_OK) rc = run_screen_n(c, 0, chi, V0, tmp, nullptr, nw);
+    if (rc != LRIGW_OK) break;
+    if (c->precision == LRIGW_FP64)
+      hipLaunchKernelGGL(k_waccum<double2>, dim3(nb), dim3(256), 0, c->stream, (double2 *)out, (const double2 *)tmp, n,
+                         c->gdir_w[g], g == 0 ? 1 : 0);
+    else
+      hipLaunchKernelGGL(k_waccum<float2>, dim3(nb), dim3(256), 0, c->stream, (float2 *)out, (const float2 *)tmp, n,
+                         c->gdir_w[g], g == 0 ? 1 : 0);
+    rc = lrigw_launch_check("gamma_average");
+  }
+  c->gamma_p = saved;
+  return rc;
+}
+

@@ -141,6 +141,10 @@ struct lrigw_ctx {
   const void *gamma_p = nullptr;
   double omega_cell = 0.0;
   bool gamma_ready = false;
+  // q -> 0 averaged over directions (n_gdir = 0: the single direction gamma_p)
+  int n_gdir = 0;
+  const void *gdir_p = nullptr;  // caller's complex128 [n_gdir][N_k][n_occ][n_unocc], p . q_hat_d
+  std::vector<double> gdir_w;
 
   // driver-owned buffers (chi and W^c double buffered: the screening of q runs
   // on stream2 while the response of q+1 is built on stream)
@@ -216,6 +220,7 @@ int run_sigma_cd(lrigw_ctx *c, int iq, const void *x, const void *Wc, const void
 int cd_energies(lrigw_ctx *c, const double *eig, double delta);
 int cd_qp_linear(lrigw_ctx *c, const double *S, const double *e_static, double delta, double *e_qp, double *z);
 int cd_count_nan(lrigw_ctx *c, const double *v, int n, int *out);
+int run_gamma_average(lrigw_ctx *c, const double *eig, const void *V0, bool real_axis, void *chi, void *tmp, void *out);
 int run_cd_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *p,
                 double omega_cell, int n_e, const double *E, double *sigma_e, int *n_bad);
 int run_sigma_x(lrigw_ctx *c, int iq, const void *xo, const void *V, double *sigma_x);

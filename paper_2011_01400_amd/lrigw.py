@@ -34,7 +34,7 @@ EXPORTS = ["lrigw_create", "lrigw_destroy", "lrigw_strerror", "lrigw_get_sizes",
            "lrigw_build_M", "lrigw_chi0", "lrigw_gamma_prepare", "lrigw_screen", "lrigw_sigma_c", "lrigw_sigma_x",
            "lrigw_sigma_x_pass", "lrigw_lri_fit", "lrigw_qp",
            "lrigw_set_real_grid", "lrigw_chi0_real", "lrigw_screen_real", "lrigw_sigma_cd", "lrigw_sigma_cd_pass",
-           "lrigw_g0w0_cd", "lrigw_g0w0", "lrigw_set_timing", "lrigw_stage_ms", "lrigw_reset_timing",
+           "lrigw_g0w0_cd", "lrigw_set_gamma_directions", "lrigw_g0w0", "lrigw_set_timing", "lrigw_stage_ms", "lrigw_reset_timing",
            "lrigw_surrogate_create", "lrigw_surrogate_destroy", "lrigw_surrogate_info", "lrigw_surrogate_rule",
            "lrigw_surrogate_params", "lrigw_surrogate_basis", "lrigw_surrogate_add", "lrigw_surrogate_rows",
            "lrigw_surrogate_forward", "lrigw_surrogate_grad", "lrigw_surrogate_train", "lrigw_chi0_surrogate",
@@ -106,6 +106,7 @@ def load(path: Optional[str] = None):
         "lrigw_lri_fit": (i, [vp, i, i, i, i, vp, vp, d, vp, ip]),
         "lrigw_qp": (i, [vp, vp, vp, vp, i, vp, vp, ip]),
         "lrigw_set_real_grid": (i, [vp, i, d]),
+        "lrigw_set_gamma_directions": (i, [vp, i, vp, dp]),
         "lrigw_chi0_real": (i, [vp, i, vp, vp, i, vp]),
         "lrigw_screen_real": (i, [vp, i, vp, vp, vp, ip]),
         "lrigw_sigma_cd": (i, [vp, i, vp, vp, vp, vp, i, vp, vp]),
@@ -291,6 +292,19 @@ class Context:
                                ctypes.byref(info))
         self._check(rc, "lrigw_qp", allow_warn=True)
         return rc, info.value
+
+    def set_gamma_directions(self, p_dirs, weights):
+        """p_dirs: complex128 [n_dir][N_k][n_occ][n_unocc] on the device (kept
+        alive here), weights: n_dir floats; p_dirs None: one direction."""
+        if p_dirs is None:
+            self._check(self.lib.lrigw_set_gamma_directions(self.h, 0, None, None), "lrigw_set_gamma_directions")
+            self._gdirs = None
+            return
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        self._check(self.lib.lrigw_set_gamma_directions(self.h, int(w.shape[0]), _ptr(p_dirs),
+                                                        w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                    "lrigw_set_gamma_directions")
+        self._gdirs = p_dirs
 
     # ---- contour deformation (real energies) ---------------------------
     def set_real_grid(self, n_r, omega_max):

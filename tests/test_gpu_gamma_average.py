@@ -1,0 +1,118 @@
+"""GPU parity of the direction-averaged q -> 0 screening
+(lrigw_set_gamma_directions) with the six Cartesian half-axes: the whole pass
+and the contour-deformation pass against the oracle with the same average,
+and time reversal, Sigma^c(k) = Sigma^c(-k), restored on grids with
+non-invariant k points (the Si-like cell among them)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle.pipeline import Oracle
+from synth.systems import cartesian_directions, make_config, make_custom, momentum_vectors, project_momentum
+
+
+def _lib():
+    from paper_2011_01400_amd import lrigw as L
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L.load()
+    return L
+
+
+CASES = {
+    "c1": lambda: make_config(1),
+    "ragged": lambda: make_custom(n_atoms=2, nb_per_atom=7, naux_per_atom=37, nk=(3, 1, 2), n_occ=5, n_freq=10,
+                                  qp_lo=2, n_qp=6, seed=17),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    L = _lib()
+    print(f"\n[gpu gamma average] case={request.param}", flush=True)
+    s = CASES[request.param]()
+    q, w = cartesian_directions()
+    pd = project_momentum(momentum_vectors(s), q)
+    o = Oracle(s)
+    o.gamma_dirs = (pd, w)
+    return dict(name=request.param, sys=s, o=o, dev=L.device_inputs(s), L=L, pd=pd, w=w)
+
+
+def _trs(a, minus):
+    return np.max(np.abs(a - a[minus])) / np.max(np.abs(a))
+
+
+@pytest.mark.parametrize("precision,tol_s,tol_trs", [("fp64", 1e-9, 1e-12), ("split_f16", 2e-5, 1e-6)])
+def test_pass_with_directions(case, precision, tol_s, tol_trs):
+    s, o, dev, L = case["sys"], case["o"], case["dev"], case["L"]
+    sp = s.spec
+    ctx = L.Context.from_system(s, precision=precision)
+    H = ctx.empty("H")
+    ctx.lri_ft(dev["lri"], s.R, dev["evec"], H)
+    pd = torch.from_numpy(case["pd"]).cuda()
+    ctx.set_gamma_directions(pd, case["w"])
+    sg = torch.zeros((s.n_k, sp.n_qp, sp.n_freq), dtype=torch.complex128, device="cuda")
+    e = torch.zeros((s.n_k, sp.n_qp), dtype=torch.float64, device="cuda")
+    z = torch.zeros_like(e)
+    ctx.g0w0(H, dev["evec"], dev["eig"], dev["V"], dev["p"], s.omega_cell, dev["e_static"], 16, sg, e, z)
+    got = sg.cpu().numpy()
+    ref = o.run()["sigma"]
+    err = np.max(np.abs(got - ref))
+    trs = _trs(got, o.minus)
+    print(f"  {case['name']} {precision}: max|dSigma| {err:.1e} Ha, |Sigma(k) - Sigma(-k)| rel {trs:.1e}", flush=True)
+    assert err < tol_s and trs < tol_trs
+    # back to one direction: the pass equals the oracle's single-direction pass
+    ctx.set_gamma_directions(None, None)
+    ctx.g0w0(H, dev["evec"], dev["eig"], dev["V"], dev["p"], s.omega_cell, dev["e_static"], 16, sg, e, z)
+    o1 = Oracle(s)
+    assert np.max(np.abs(sg.cpu().numpy() - o1.run()["sigma"])) < tol_s
+
+
+def test_contour_pass_with_directions(case):
+    s, o, dev, L = case["sys"], case["o"], case["dev"], case["L"]
+    sp = s.spec
+    ctx = L.Context.from_system(s, precision="fp64")
+    H = ctx.empty("H")
+    ctx.lri_ft(dev["lri"], s.R, dev["evec"], H)
+    ctx.set_gamma_directions(torch.from_numpy(case["pd"]).cuda(), case["w"])
+    vbm, cbm = s.eig[:, :s.n_occ].max(), s.eig[:, s.n_occ:].min()
+    dmin = cbm - vbm
+    n_r = min(12, sp.n_freq)
+    ctx.set_real_grid(n_r, 0.6 * dmin)
+    E = np.random.default_rng(11).uniform(vbm - 0.45 * dmin, cbm + 0.45 * dmin, (2, s.n_k, sp.n_qp))
+    out = torch.zeros((2, s.n_k, sp.n_qp), dtype=torch.float64, device="cuda")
+    rc, bad = ctx.sigma_cd_pass(H, dev["evec"], dev["eig"], dev["V"], dev["p"], s.omega_cell, torch.from_numpy(E).cuda(),
+                                out)
+    ref = o.sigma_cd(n_r, 0.6 * dmin, E)
+    e = np.max(np.abs(out.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    print(f"  {case['name']}: contour pass with directions rel {e:.1e}", flush=True)
+    assert rc == 0 and bad == 0 and e < 1e-10
+
+
+def test_si_like_time_reversal():
+    """Si-like cell (6x6x6 k), FP16 form: one direction leaves Sigma^c(k) and
+    Sigma^c(-k) apart by the q = 0 wing terms; the six half-axes bring them
+    together to the form's rounding."""
+    L = _lib()
+    s = make_config(2)
+    sp = s.spec
+    dev = L.device_inputs(s)
+    ctx = L.Context.from_system(s, precision="split_f16")
+    H = ctx.empty("H")
+    ctx.lri_ft(dev["lri"], s.R, dev["evec"], H)
+    o = Oracle(s)
+    sg = torch.zeros((s.n_k, sp.n_qp, sp.n_freq), dtype=torch.complex128, device="cuda")
+    e = torch.zeros((s.n_k, sp.n_qp), dtype=torch.float64, device="cuda")
+    z = torch.zeros_like(e)
+    ctx.g0w0(H, dev["evec"], dev["eig"], dev["V"], dev["p"], s.omega_cell, dev["e_static"], 16, sg, e, z)
+    one = _trs(sg.cpu().numpy(), o.minus)
+    q, w = cartesian_directions()
+    pd = torch.from_numpy(project_momentum(momentum_vectors(s), q)).cuda()
+    ctx.set_gamma_directions(pd, w)
+    ctx.g0w0(H, dev["evec"], dev["eig"], dev["V"], dev["p"], s.omega_cell, dev["e_static"], 16, sg, e, z)
+    avg = _trs(sg.cpu().numpy(), o.minus)
+    print(f"  si-like: |Sigma(k) - Sigma(-k)| rel {one:.1e} with one direction, {avg:.1e} averaged", flush=True)
+    assert avg < 1e-6 < one
