@@ -84,3 +84,40 @@ def test_whole_pass(c4):
           f"Z in [{zv.min():.3f}, {zv.max():.3f}]", flush=True)
     assert rc >= 0
     assert np.all(np.isfinite(sg.cpu().numpy())) and np.all(np.isfinite(ev))
+
+
+def test_contour_deformation_against_pade(c4):
+    """Sigma^c(e_n) of the band-edge states from contour deformation (16 real
+    planes, streaming self-energy kernels at this N_aux) against the Pade
+    continuation of the same path's Sigma^c(i w), evaluated on the host."""
+    from oracle import continuation, grids
+    L, s, dev, ctx, H = c4
+    sp = s.spec
+    sg = torch.zeros((s.n_k, sp.n_qp, sp.n_freq), dtype=torch.complex128, device="cuda")
+    e = torch.zeros((s.n_k, sp.n_qp), dtype=torch.float64, device="cuda")
+    z = torch.zeros_like(e)
+    ctx.g0w0(H, dev["evec"], dev["eig"], dev["V"], dev["p"], s.omega_cell, dev["e_static"], 16, sg, e, z)
+    dmin = float(s.eig[:, s.n_occ:].min() - s.eig[:, :s.n_occ].max())
+    ctx.set_real_grid(16, 0.6 * dmin)
+    S3 = torch.zeros((3, s.n_k, sp.n_qp), dtype=torch.float64, device="cuda")
+    ecd, zcd = torch.zeros_like(e), torch.zeros_like(e)
+    t0 = time.perf_counter()
+    rc, bad = ctx.g0w0_cd(H, dev["evec"], dev["eig"], dev["V"], dev["p"], s.omega_cell, dev["e_static"], 0.002, ecd, zcd,
+                          sigma3=S3)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    cd = S3.cpu().numpy()[1]
+    ok = np.isfinite(cd)
+    nodes = grids.pade_nodes(sp.n_freq, 16)
+    om, _ = grids.frequency_grid(sp.n_freq, sp.x0)
+    zn = 1j * om[nodes]
+    eps = s.eig[:, sp.qp_lo:sp.qp_lo + sp.n_qp]
+    sgh = sg.cpu().numpy()
+    d = []
+    for k, n in zip(*np.nonzero(ok)):
+        a, _ = continuation.thiele_coeffs(zn, sgh[k, n, nodes])
+        d.append(abs(continuation.thiele_eval(zn, a, eps[k, n] - s.mu)[0].real - cd[k, n]))
+    d = np.array(d) * 27211.386
+    print(f"  contour pass {dt:.1f} s, {ok.sum()} band-edge states: |Sigma_CD - Sigma_Pade| median {np.median(d):.3f} "
+          f"meV, max {d.max():.3f} meV", flush=True)
+    assert rc >= 0 and ok.sum() > 0 and d.max() < 5.0
