@@ -241,8 +241,8 @@ int lrigw_g0w0(lrigw_ctx *ctx, const void *H, const void *evec, const double *ei
 /* Average the q -> 0 screening over directions of approach.  The head and
  * wings of Eq. dielectric_func_gamma depend on the direction q_hat along which
  * q -> 0 (Sec. III B); the paper gives no averaging scheme.  With n_dir > 0,
- * the whole passes (lrigw_g0w0, lrigw_sigma_cd_pass, lrigw_g0w0_cd) take
- * W^c(0) = sum_d weights[d] W^c(0; q_hat_d).  Each term is
+ * the whole passes (lrigw_g0w0, the batched graph, lrigw_sigma_cd_pass,
+ * lrigw_g0w0_cd) take W^c(0) = sum_d weights[d] W^c(0; q_hat_d).  Each term is
  * the exact q = 0 response with p . q_hat_d and its screening, on the
  * context's stream; the surrogate is not used at q = 0.  The p argument of
  * those calls must still be non-NULL (it selects the q = 0 treatment).

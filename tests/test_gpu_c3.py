@@ -5,11 +5,13 @@ Checked: every cell's status; each cell's batched result equals its own
 lrigw_g0w0 on the same tuned context; and on the smallest cell one q's Sigma^c
 contribution at sampled k points equals the FP64 oracle's.
 
-Sigma^c(k) = Sigma^c(-k) is not checked here: the q -> 0 head and wings are
-taken along one direction q_hat, the wings are odd in p.q_hat, and with these
-inputs (no crystal symmetry to cancel them) W^c(0) is complex, so the q = 0
-term differs between k and -k (by 1e-4 relative in the FP64 oracle as well;
-without the Gamma correction the oracle is symmetric to rounding)."""
+Sigma^c(k) = Sigma^c(-k) does not hold with one direction q_hat. The q -> 0
+head and wings are taken along q_hat, and the wings are odd in p.q_hat. These
+inputs have no crystal symmetry to cancel them, so W^c(0) is complex and the
+q = 0 term differs between k and -k: by 1e-4 relative in the FP64 oracle as
+well, while without the Gamma correction the oracle is symmetric to rounding.
+With the six Cartesian half-axes set on every context, the second graph of
+the last test restores the symmetry."""
 import time
 
 import numpy as np
@@ -111,3 +113,39 @@ def test_smallest_cell_one_q_against_oracle(batched):
     print(f"  cell {i} (N_aux {s.n_aux}, {s.n_k} k) q={q}: sampled Sigma^c rel {e:.1e} "
           f"(oracle {time.perf_counter() - t0:.1f} s)", flush=True)
     assert e < 2e-5
+
+
+def test_batched_with_directions_restores_time_reversal(batched):
+    """The six Cartesian half-axes set on every cell's context and the cells
+    captured in a second graph: each cell's Sigma^c(k) equals Sigma^c(-k) to
+    the form's rounding, and equals its own direction-averaged pass."""
+    from oracle import grids as og
+    from synth.systems import cartesian_directions, momentum_vectors, project_momentum
+    L, cells, items, b, st = batched
+    q, w = cartesian_directions()
+    items2 = []
+    for s, it in zip(cells, items):
+        pd = torch.from_numpy(project_momentum(momentum_vectors(s), q)).cuda()
+        it["ctx"].set_gamma_directions(pd, w)
+        items2.append(dict(it, sigma=torch.zeros_like(it["sigma"]), e_qp=torch.zeros_like(it["e_qp"]),
+                           z=torch.zeros_like(it["z"])))
+    try:
+        b2 = L.Batch(items2, autotune=False, stream=b.stream)
+        b2.run()
+        torch.cuda.synchronize()
+        st2 = b2.status()
+        for i, (s, it) in enumerate(zip(cells, items2)):
+            assert st2[i][0] == -1 and st2[i][1] == 0, (i, st2[i])
+            minus = og.kq_tables(s.spec.nk)[2]
+            a = it["sigma"].cpu().numpy()
+            trs = np.max(np.abs(a - a[minus])) / np.max(np.abs(a))
+            sg, e, z = torch.zeros_like(it["sigma"]), torch.zeros_like(it["e_qp"]), torch.zeros_like(it["z"])
+            it["ctx"].g0w0(it["H"], it["evec"], it["eig"], it["V"], it["p"], it["omega_cell"], it["e_static"], 16, sg, e, z)
+            torch.cuda.synchronize()
+            ds = np.max(np.abs(sg.cpu().numpy() - a))
+            print(f"  cell {i} with directions: |Sigma(k) - Sigma(-k)| rel {trs:.1e}, batched vs own pass {ds:.1e} Ha",
+                  flush=True)
+            assert trs < 1e-6 and ds < 1e-12
+    finally:
+        for it in items:
+            it["ctx"].set_gamma_directions(None, None)
