@@ -206,7 +206,8 @@ def contour_timing(run, sysm, dev, n_r=16, reps=1):
     run.ctx.set_real_grid(n_r, wmax)
     e = torch.zeros((sysm.n_k, sp.n_qp), dtype=torch.float64, device="cuda")
     z = torch.zeros_like(e)
-    args = (run.H, dev["evec"], dev["eig"], dev["V"], dev["p"], sysm.omega_cell, dev["e_static"], 0.002, e, z)
+    S3 = torch.zeros((3, sysm.n_k, sp.n_qp), dtype=torch.float64, device="cuda")
+    args = (run.H, dev["evec"], dev["eig"], dev["V"], dev["p"], sysm.omega_cell, dev["e_static"], 0.002, e, z, S3)
     run.ctx.g0w0_cd(*args)   # first call allocates its workspaces
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -216,7 +217,17 @@ def contour_timing(run, sysm, dev, n_r=16, reps=1):
     dt = (time.perf_counter() - t0) / reps
     ev = e.cpu().numpy()
     ok = np.isfinite(ev)
+    # Sigma^c(e_n) against the Pade continuation of the timed steps' Sigma^c(i w)
+    # (lrigw_pade_eval), on the states contour deformation evaluated
+    Ee = torch.from_numpy(np.ascontiguousarray(sysm.eig[None, :, sp.qp_lo:sp.qp_lo + sp.n_qp])).cuda()
+    pv = torch.zeros((1, sysm.n_k, sp.n_qp), dtype=torch.complex128, device="cuda")
+    run.ctx.pade_eval(run.sigma, run.n_par, Ee, pv)
+    s0 = S3.cpu().numpy()[1]
+    m = np.isfinite(s0)
+    dp = np.abs(pv.cpu().numpy()[0].real[m] - s0[m]) * 27211.386
     return {"ms_per_pass": round(dt * 1e3, 3), "n_real": n_r, "omega_max_ha": round(wmax, 6),
+            "sigma_vs_pade_mev": {"states": int(m.sum()), "median": round(float(np.median(dp)), 4),
+                                  "max": round(float(dp.max()), 4)} if m.any() else None,
             "pairs_per_s": round(sysm.n_k * (sp.n_freq + n_r) / dt, 1),
             "states_evaluated": int(ok.sum()), "states": int(ok.size), "nan_outputs": int(bad),
             "z_range": [round(float(z.cpu().numpy()[ok].min()), 4), round(float(z.cpu().numpy()[ok].max()), 4)]

@@ -226,6 +226,14 @@ int lrigw_sigma_x_pass(lrigw_ctx *ctx, const void *H, const void *evec, const vo
 int lrigw_qp(lrigw_ctx *ctx, const void *sigma, const double *eps_qp, const double *e_static, int n_par,
              double *e_qp, double *z, int *info);
 
+/* The continuation of lrigw_qp evaluated at real energies: out[e][k][n] =
+ * P_{kn}(E[e][k][n] - mu), the same nodes and continued fraction (Sigma^c on
+ * the real axis, e.g. for spectral functions or beside contour deformation).
+ * sigma: complex128 [N_k][n_qp][n_freq]; E: FP64 [n_e][N_k][n_qp] absolute
+ * energies (Ha); out: complex128 [n_e][N_k][n_qp]; all on the device.
+ * Errors: ERR_ARG (NULL, n_par outside 1..64, n_e < 1). */
+int lrigw_pade_eval(lrigw_ctx *ctx, const void *sigma, int n_par, int n_e, const double *E, void *out);
+
 /* Whole path for one cell, q loop inside the library:
  *   for q: build_M(0), chi0 (gamma at q = 0 when p != NULL), screen (V[q]; V[0]
  *   is V^cut(0)), build_M(1), sigma_c;  then qp.

@@ -569,6 +569,12 @@ int lrigw_g0w0_cd(lrigw_ctx *c, const void *H, const void *evec, const double *e
   return rc;
 }
 
+int lrigw_pade_eval(lrigw_ctx *c, const void *sigma, int n_par, int n_e, const double *E, void *out) {
+  (void)hipGetLastError();
+  if (!c || !sigma || !E || !out || n_par < 1 || n_par > 64 || n_e < 1) return LRIGW_ERR_ARG;
+  return run_pade_eval(c, sigma, n_par, n_e, E, out);
+}
+
 int lrigw_g0w0(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *p,
                double omega_cell, const double *e_static, int n_par, int q_first, int q_last, void *sigma,
                double *e_qp, double *z, int *info) {

@@ -45,36 +45,58 @@ __device__ inline void cf_eval(const double2 *a, const double2 *zn, int na, doub
   der = zdiv(num, cmul(B1, B1));
 }
 
+// nodes z_j = i w_node(j) (n_par grid points j (n_freq-1)/(n_par-1), rounded
+// half up) and the continued-fraction coefficients of one (k, n) row of
+// sigma, by inverse differences; returns the number of coefficients kept
+// (the fraction is truncated at a zero or non-finite one)
+__device__ inline int pade_coeffs(const double2 *__restrict__ row, int n_freq, int n_par, const double *__restrict__ omega,
+                                  double2 *zn, double2 *a) {
+  double2 g[NPMAX];
+  for (int j = 0; j < n_par; ++j) {
+    int node = (n_par == 1) ? 0 : (int)((2LL * j * (n_freq - 1) + (n_par - 1)) / (2LL * (n_par - 1)));
+    zn[j] = mkc(0.0, omega[node]);
+    g[j] = row[node];
+  }
+  int na = n_par;
+  a[0] = g[0];
+  if (!(zfinite(a[0]) && zabs(a[0]) >= PADE_TINY)) return 0;
+  for (int p = 1; p < n_par; ++p) {
+    for (int j = n_par - 1; j >= p; --j) {
+      double2 num = mkc(g[p - 1].x - g[j].x, g[p - 1].y - g[j].y);
+      double2 den = cmul(mkc(zn[j].x - zn[p - 1].x, zn[j].y - zn[p - 1].y), g[j]);
+      g[j] = zdiv(num, den);
+    }
+    a[p] = g[p];
+    if (!zfinite(a[p]) || zabs(a[p]) < PADE_TINY) {
+      na = p;
+      break;
+    }
+  }
+  return na;
+}
+
+// P(E - mu) at n_e sets of real energies: out[e][k][n] = P_{kn}(E[e][k][n] - mu)
+__global__ void k_pade_eval(const double2 *__restrict__ sigma, int nkq, int n_freq, int n_par,
+                            const double *__restrict__ omega, double mu, int n_e, const double *__restrict__ E,
+                            double2 *__restrict__ out) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nkq) return;
+  double2 zn[NPMAX], a[NPMAX];
+  const int na = pade_coeffs(sigma + (long long)idx * n_freq, n_freq, n_par, omega, zn, a);
+  for (int e = 0; e < n_e; ++e) {
+    double2 v, dv;
+    cf_eval(a, zn, na, E[(long long)e * nkq + idx] - mu, v, dv);
+    out[(long long)e * nkq + idx] = v;
+  }
+}
+
 __global__ void k_pade_qp(const double2 *__restrict__ sigma, int nkq, int n_freq, int n_par, const double *__restrict__ omega,
                           const double *__restrict__ eps_qp, const double *__restrict__ e_static, double mu,
                           double *__restrict__ e_qp, double *__restrict__ zf, int *__restrict__ flags) {
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nkq) return;
-  double2 zn[NPMAX], g[NPMAX], a[NPMAX];
-  for (int j = 0; j < n_par; ++j) {
-    int node = (n_par == 1) ? 0 : (int)((2LL * j * (n_freq - 1) + (n_par - 1)) / (2LL * (n_par - 1)));
-    zn[j] = mkc(0.0, omega[node]);
-    g[j] = sigma[(long long)idx * n_freq + node];
-  }
-  // inverse differences
-  int na = n_par;
-  a[0] = g[0];
-  if (!(zfinite(a[0]) && zabs(a[0]) >= PADE_TINY)) {
-    na = 0;
-  } else {
-    for (int p = 1; p < n_par; ++p) {
-      for (int j = n_par - 1; j >= p; --j) {
-        double2 num = mkc(g[p - 1].x - g[j].x, g[p - 1].y - g[j].y);
-        double2 den = cmul(mkc(zn[j].x - zn[p - 1].x, zn[j].y - zn[p - 1].y), g[j]);
-        g[j] = zdiv(num, den);
-      }
-      a[p] = g[p];
-      if (!zfinite(a[p]) || zabs(a[p]) < PADE_TINY) {
-        na = p;
-        break;
-      }
-    }
-  }
+  double2 zn[NPMAX], a[NPMAX];
+  const int na = pade_coeffs(sigma + (long long)idx * n_freq, n_freq, n_par, omega, zn, a);
   if (na < n_par) atomicAdd(flags + 1, 1);
   const double target = eps_qp[idx] + (e_static ? e_static[idx] : 0.0);
   double2 v, dv;
@@ -170,3 +192,14 @@ int run_qp(lrigw_ctx *c, const void *sigma, const double *eps_qp, const double *
   if (h[1] > 0) return LRIGW_WARN_PADE_TRUNC;
   return LRIGW_OK;
 }
+
+int run_pade_eval(lrigw_ctx *c, const void *sigma, int n_par, int n_e, const double *E, void *out) {
+  const Dims &d = c->d;
+  if (n_par > d.n_freq) n_par = d.n_freq;
+  if (n_par < 1 || n_par > NPMAX) return LRIGW_ERR_ARG;
+  const int nkq = d.n_k * d.n_qp;
+  hipLaunchKernelGGL(k_pade_eval, dim3((nkq + 63) / 64), dim3(64), 0, c->stream, (const double2 *)sigma, nkq, d.n_freq, n_par,
+                     c->d_omega, d.mu, n_e, E, (double2 *)out);
+  return lrigw_launch_check("pade_eval");
+}
+

@@ -220,6 +220,7 @@ int run_sigma_cd(lrigw_ctx *c, int iq, const void *x, const void *Wc, const void
 int cd_energies(lrigw_ctx *c, const double *eig, double delta);
 int cd_qp_linear(lrigw_ctx *c, const double *S, const double *e_static, double delta, double *e_qp, double *z);
 int cd_count_nan(lrigw_ctx *c, const double *v, int n, int *out);
+int run_pade_eval(lrigw_ctx *c, const void *sigma, int n_par, int n_e, const double *E, void *out);
 int run_gamma_average(lrigw_ctx *c, const double *eig, const void *V0, bool real_axis, void *chi, void *tmp, void *out);
 int run_cd_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *p,
                 double omega_cell, int n_e, const double *E, double *sigma_e, int *n_bad);

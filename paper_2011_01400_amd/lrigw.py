@@ -34,7 +34,7 @@ EXPORTS = ["lrigw_create", "lrigw_destroy", "lrigw_strerror", "lrigw_get_sizes",
            "lrigw_build_M", "lrigw_chi0", "lrigw_gamma_prepare", "lrigw_screen", "lrigw_sigma_c", "lrigw_sigma_x",
            "lrigw_sigma_x_pass", "lrigw_lri_fit", "lrigw_qp",
            "lrigw_set_real_grid", "lrigw_chi0_real", "lrigw_screen_real", "lrigw_sigma_cd", "lrigw_sigma_cd_pass",
-           "lrigw_g0w0_cd", "lrigw_set_gamma_directions", "lrigw_g0w0", "lrigw_set_timing", "lrigw_stage_ms", "lrigw_reset_timing",
+           "lrigw_g0w0_cd", "lrigw_set_gamma_directions", "lrigw_pade_eval", "lrigw_g0w0", "lrigw_set_timing", "lrigw_stage_ms", "lrigw_reset_timing",
            "lrigw_surrogate_create", "lrigw_surrogate_destroy", "lrigw_surrogate_info", "lrigw_surrogate_rule",
            "lrigw_surrogate_params", "lrigw_surrogate_basis", "lrigw_surrogate_add", "lrigw_surrogate_rows",
            "lrigw_surrogate_forward", "lrigw_surrogate_grad", "lrigw_surrogate_train", "lrigw_chi0_surrogate",
@@ -107,6 +107,7 @@ def load(path: Optional[str] = None):
         "lrigw_qp": (i, [vp, vp, vp, vp, i, vp, vp, ip]),
         "lrigw_set_real_grid": (i, [vp, i, d]),
         "lrigw_set_gamma_directions": (i, [vp, i, vp, dp]),
+        "lrigw_pade_eval": (i, [vp, vp, i, i, vp, vp]),
         "lrigw_chi0_real": (i, [vp, i, vp, vp, i, vp]),
         "lrigw_screen_real": (i, [vp, i, vp, vp, vp, ip]),
         "lrigw_sigma_cd": (i, [vp, i, vp, vp, vp, vp, i, vp, vp]),
@@ -350,6 +351,12 @@ class Context:
                                     _ptr(e_static), float(delta), _ptr(sigma3), _ptr(e_qp), _ptr(z), ctypes.byref(bad))
         self._check(rc, "lrigw_g0w0_cd", allow_warn=True)
         return rc, bad.value
+
+    def pade_eval(self, sigma, n_par, E, out):
+        """E: FP64 [n_e][N_k][n_qp], out: complex128 [n_e][N_k][n_qp] (device)."""
+        self._check(self.lib.lrigw_pade_eval(self.h, _ptr(sigma), int(n_par), int(E.shape[0]), _ptr(E), _ptr(out)),
+                    "lrigw_pade_eval")
+        return out
 
     def g0w0(self, H, evec, eig, V, p, omega_cell, e_static, n_par, sigma, e_qp, z, q_first=0, q_last=None):
         info = ctypes.c_int(0)
