@@ -453,7 +453,7 @@ int lrigw_batch_destroy(lrigw_batch *b);
  * faster, so near-ties resolve the same way each time (the K split count
  * changes the order of the FP32 sums).
  * H, evec, eig as lrigw_g0w0.  Outputs (host, may be NULL): the chosen
- * response tiles, the self-energy variant (0..8) and the response time of one
+ * response tiles, the self-energy variant (0..10) and the response time of one
  * q (ms).
  * Synchronous. */
 int lrigw_tune(lrigw_ctx *ctx, const void *H, const void *evec, const double *eig, int *nw, int *splits,
@@ -463,9 +463,9 @@ int lrigw_tune(lrigw_ctx *ctx, const void *H, const void *evec, const double *ei
  * response workgroup (the form's default or its alternative: 4/2 in the FP32
  * and split forms, 2/1 in FP64), splits = K splits (the partial-tile buffer
  * must hold them), pad = LDS row padding of the split-form response kernel (8
- * or 16), sigma_variant = split-form self-energy kernel variant (0..8; 7 and 8,
- * the resident-tile form, need the two-part FP16 split, N_aux <= 288 and at
- * most 32 frequencies).
+ * or 16), sigma_variant = split-form self-energy kernel variant (0..10; 7 to
+ * 10, the resident-tile form with 8 or 4 waves and LDS rows padded by 8 or
+ * 16, need the two-part FP16 split, N_aux <= 288 and at most 32 frequencies).
  * Errors: ERR_ARG for a choice outside these sets or a variant the cell does
  * not admit. */
 int lrigw_set_tiles(lrigw_ctx *ctx, int nw, int splits, int pad, int sigma_variant);

@@ -1037,8 +1037,9 @@ __global__ __launch_bounds__(64) void k_sigma_freq(const double *__restrict__ X,
 // W prefetched one chunk ahead, wave tile) = (1, yes, 16x64), (2, no, 16x64),
 // (1, no, 16x64), (1, yes, 32x32), (1, no, 32x32), the first one with LDS rows
 // padded to 96 and 112 bytes instead of 80, and the resident-tile form with 8
-// and 4 waves per workgroup (two-part FP16 split, N_aux <= 288 only)
-#define SIGMA_VARIANTS 9
+// and 4 waves per workgroup and LDS rows padded by 8 or 16 elements (two-part
+// FP16 split, N_aux <= 288 only)
+#define SIGMA_VARIANTS 11
 int sigma_variant_snw(int var) { return var == 1 ? 2 : 1; }
 int sigma_variants() { return SIGMA_VARIANTS; }
 int sigma_default_variant(int precision) { return ns_sig(precision) == 2 ? 1 : 0; }
@@ -1128,7 +1129,9 @@ int run_pair_weights(lrigw_ctx *c, const void *x, const void *Wc, int nw, double
       const int *t8 = items, *t4 = items + 8 * (RES_MAXI + 1);
 #define RES_ARGS xs, ws, xf, Wf, Ccols, Cpad, d.n_aux, Npad, Rpad, nw, Fres
       if (var == 7) hipLaunchKernelGGL((k_sigma_res<8, true, 8>), gr, dim3(512), 0, c->stream, RES_ARGS, t8, c->d_sx, c->d_wmax, X);
-      else hipLaunchKernelGGL((k_sigma_res<8, true, 4>), gr, dim3(256), 0, c->stream, RES_ARGS, t4, c->d_sx, c->d_wmax, X);
+      else if (var == 8) hipLaunchKernelGGL((k_sigma_res<8, true, 4>), gr, dim3(256), 0, c->stream, RES_ARGS, t4, c->d_sx, c->d_wmax, X);
+      else if (var == 9) hipLaunchKernelGGL((k_sigma_res<16, true, 8>), gr, dim3(512), 0, c->stream, RES_ARGS, t8, c->d_sx, c->d_wmax, X);
+      else hipLaunchKernelGGL((k_sigma_res<16, true, 4>), gr, dim3(256), 0, c->stream, RES_ARGS, t4, c->d_sx, c->d_wmax, X);
 #undef RES_ARGS
     } else if (H)
       launch_sigma_split<2, true>(var, gs, c->stream, xs, ws, xf, Wf, Ccols, Cpad, d.n_aux, Npad, Rpad, nw, c->d_sx,

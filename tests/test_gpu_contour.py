@@ -142,7 +142,7 @@ def test_sigma_cd_per_q_and_pass(case, precision):
     assert e < tol
 
 
-@pytest.mark.parametrize("var", [7, 8])
+@pytest.mark.parametrize("var", [7, 8, 9, 10])
 def test_sigma_cd_resident_variants(case, var):
     """The FP16 form's resident-tile self-energy kernel (8 and 4 waves per
     workgroup) on both plane sets: the imaginary grid and the real grid, which
