@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--precision", default="split_f16", choices=list(PEAK_TFLOPS))
     ap.add_argument("--no-tune", action="store_true", help="skip the response-kernel tile autotuner")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain FP64 path")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the exchange, coefficient-fit and contour-deformation legs (kernel profiles of the metric)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--n-par", type=int, default=16)
     ap.add_argument("--workload", default="cell", choices=["cell", "batched"],
@@ -440,10 +442,11 @@ def main():
     }
     if tuned:
         out["tuned"] = tuned
-    out["sigma_x"] = sigma_x_timing(run, sysm, dev)
-    out["lri_fit"] = lri_fit_timing(run, sysm)
-    print("# bench: contour-deformation pass", file=sys.stderr, flush=True)
-    out["contour_deformation"] = contour_timing(run, sysm, dev)
+    if not args.no_extras:
+        out["sigma_x"] = sigma_x_timing(run, sysm, dev)
+        out["lri_fit"] = lri_fit_timing(run, sysm)
+        print("# bench: contour-deformation pass", file=sys.stderr, flush=True)
+        out["contour_deformation"] = contour_timing(run, sysm, dev)
     if plain:
         out["plain_fp64"] = plain
         out["speedup_vs_plain"] = round(value / plain["value"], 3)
