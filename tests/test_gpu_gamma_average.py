@@ -116,3 +116,22 @@ def test_si_like_time_reversal():
     avg = _trs(sg.cpu().numpy(), o.minus)
     print(f"  si-like: |Sigma(k) - Sigma(-k)| rel {one:.1e} with one direction, {avg:.1e} averaged", flush=True)
     assert avg < 1e-6 < one
+
+
+def test_argument_errors():
+    L = _lib()
+    s = make_config(1)
+    sp = s.spec
+    ctx = L.Context.from_system(s, precision="fp64")
+    pd = torch.zeros((65, s.n_k, sp.n_occ, sp.n_bands - sp.n_occ), dtype=torch.complex128, device="cuda")
+    for args in ((pd, np.ones(65)), (pd[:2], np.array([0.5, np.nan]))):
+        with pytest.raises(L.LrigwError) as e:
+            ctx.set_gamma_directions(*args)
+        assert e.value.code == L.LRIGW_ERR_ARG
+    sg = torch.zeros((s.n_k, sp.n_qp, sp.n_freq), dtype=torch.complex128, device="cuda")
+    E = torch.zeros((1, s.n_k, sp.n_qp), dtype=torch.float64, device="cuda")
+    out = torch.zeros((1, s.n_k, sp.n_qp), dtype=torch.complex128, device="cuda")
+    for n_par in (0, 65):
+        with pytest.raises(L.LrigwError) as e:
+            ctx.pade_eval(sg, n_par, E, out)
+        assert e.value.code == L.LRIGW_ERR_ARG

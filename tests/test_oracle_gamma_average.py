@@ -55,3 +55,18 @@ def test_symmetric_direction_set_restores_time_reversal():
     rel = lambda a: np.max(np.abs(a - a[m])) / np.max(np.abs(a))
     assert rel(avg) < 1e-12
     assert rel(one) > 1e-8
+
+
+def test_momentum_vectors_time_reversal():
+    """The synthetic Cartesian momenta obey p(-k) = -conj(p(k)) and are purely
+    imaginary at the time-reversal-invariant points; the projection is linear."""
+    from oracle import grids
+    s = _cell()
+    p3 = momentum_vectors(s)
+    _, _, minus = grids.kq_tables(s.spec.nk)
+    assert np.max(np.abs(p3 + np.conj(p3[:, minus]))) == 0.0
+    inv = [k for k in range(s.n_k) if minus[k] == k]
+    assert inv and np.max(np.abs(p3[:, inv].real)) == 0.0
+    q, _ = cartesian_directions()
+    pd = project_momentum(p3, q)
+    assert np.array_equal(pd[0], p3[0]) and np.array_equal(pd[1], -p3[0]) and np.array_equal(pd[5], -p3[2])
