@@ -307,7 +307,8 @@ int lrigw_screen_real(lrigw_ctx *ctx, int iq, const void *chi, const void *V, vo
  * x: slice-1 output of lrigw_build_M; Wc: lrigw_screen output (n_freq
  * planes); Wr: lrigw_screen_real output (n_r planes); E: FP64 [n_e][N_k][n_qp]
  * absolute energies (Ha) on the device; sigma_e: FP64 [n_e][N_k][n_qp],
- * accumulated.  Pair weights in the compute type, the combination in FP64. */
+ * accumulated.  Pair weights in the compute type, the combination in FP64.
+ * Errors: ERR_ARG (NULL, iq out of range, no real grid, n_e outside 1..4). */
 int lrigw_sigma_cd(lrigw_ctx *ctx, int iq, const void *x, const void *Wc, const void *Wr, const double *eig, int n_e,
                    const double *E, double *sigma_e);
 
@@ -315,7 +316,11 @@ int lrigw_sigma_cd(lrigw_ctx *ctx, int iq, const void *x, const void *Wc, const 
  * the exact response on both grids, with the q = 0 head and wings when p !=
  * NULL.  Arguments are as for lrigw_g0w0; sigma_e is set (not accumulated).
  * n_bad (host, may be NULL) receives the number of NaN outputs.
- * Returns WARN_CD_RANGE when there are any. */
+ * Returns WARN_CD_RANGE when there are any.  Screens q on the context's second
+ * stream while the responses of q+1 are built (as lrigw_g0w0) and waits for
+ * the stream at the end; not for graph capture.  Errors: ERR_ARG (NULL, no
+ * real grid, n_e outside 1..4, p without omega_cell > 0, called while the
+ * context captures a graph), ERR_NOT_HPD (a screening failed). */
 int lrigw_sigma_cd_pass(lrigw_ctx *ctx, const void *H, const void *evec, const double *eig, const void *V, const void *p,
                         double omega_cell, int n_e, const double *E, double *sigma_e, int *n_bad);
 
@@ -324,7 +329,9 @@ int lrigw_sigma_cd_pass(lrigw_ctx *ctx, const void *H, const void *evec, const d
  *   E_n = e_n + Z (Sigma^c(e_n) + e_static_n),
  *   Z = 1 / (1 - (Sigma^c(e_n + delta) - Sigma^c(e_n - delta)) / (2 delta)).
  * sigma3: FP64 [3][N_k][n_qp] output or NULL; e_qp, z: FP64 [N_k][n_qp]
- * outputs; e_static may be NULL.  Returns WARN_CD_RANGE as lrigw_sigma_cd_pass. */
+ * outputs; e_static may be NULL.  Returns WARN_CD_RANGE as lrigw_sigma_cd_pass;
+ * states with a NaN among their three values get NaN energies.  Errors: as
+ * lrigw_sigma_cd_pass, and ERR_ARG for delta <= 0. */
 int lrigw_g0w0_cd(lrigw_ctx *ctx, const void *H, const void *evec, const double *eig, const void *V, const void *p,
                   double omega_cell, const double *e_static, double delta, double *sigma3, double *e_qp, double *z,
                   int *n_bad);
