@@ -132,6 +132,23 @@ int lrigw_lri_ft(lrigw_ctx *ctx, const double *lri_R, const int *R_list, int nR,
 int lrigw_lri_fit(lrigw_ctx *ctx, int batch, int n, int n_keep, int nrhs, const double *V, const double *T, double scale,
                   double *C, int *info);
 
+/* lrigw_lri_fit without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same arguments, kernels and results, with the
+ * workspace taken from a fixed array of LRIGW_FIT_SCRATCH_BYTES in the
+ * library's device memory instead of hipMalloc.  Each device holds its own
+ * array until the process ends (its address is looked up at lrigw_create).
+ * Calls on one device share that array: calls that overlap on one device (two
+ * streams, two threads) race and must be serialised by the caller.  Nothing
+ * carries over between calls.  The call synchronises the context stream for
+ * `info`, like lrigw_lri_fit.
+ * Size limit: 256 + batch*n*n*16 + batch*n*nrhs*16 + batch*ceil(n/64)*64*64*16
+ * bytes (each term rounded up to 256) must not exceed LRIGW_FIT_SCRATCH_BYTES.
+ * Errors: as lrigw_lri_fit; ERR_ARG also when the shape exceeds the limit. */
+#define LRIGW_FIT_SCRATCH_BYTES (64ull << 20)
+int lrigw_lri_fit_noalloc(lrigw_ctx *ctx, int batch, int n, int n_keep, int nrhs, const double *V, const double *T,
+                          double scale, double *C, int *info);
+
 /* MO triple coefficients (Eqs. AO_triple_split2 and AO_MO_transform) with the
  * Bloch pair (k, k2), mu on P^{(k-k2)*}:
  *   C^mu_{rc}(k,k2) = sum_{a on atom(mu)} conj(c_{a r}(k)) H[k2][a][c][mu]

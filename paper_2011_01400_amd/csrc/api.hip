@@ -326,10 +326,16 @@ int lrigw_create(lrigw_ctx **out, const lrigw_system *sys, int precision, void *
   d.nb_max = nb_max;
   c->precision = precision;
   c->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return LRIGW_ERR_HIP;
+  }
   c->basis_off.assign(sys->basis_off, sys->basis_off + d.n_atoms + 1);
   c->aux_off.assign(sys->aux_off, sys->aux_off + d.n_atoms + 1);
 
   int rc = run_grids(c);
+  // device address of the allocation-free fit's fixed workspace, once per device
+  if (rc >= 0) rc = fit_scratch_prepare(c->device);
   if (rc < 0) {
     free_all(c);
     delete c;
@@ -492,6 +498,15 @@ int lrigw_lri_fit(lrigw_ctx *c, int batch, int n, int n_keep, int nrhs, const do
   if (!c || !V || !T || !C) return LRIGW_ERR_ARG;
   if (batch < 1 || batch > 65535 || n < 1 || n_keep < 1 || n_keep > n || nrhs < 1) return LRIGW_ERR_ARG;
   return run_lri_fit(c, batch, n, n_keep, nrhs, V, T, scale, C, info);
+}
+
+int lrigw_lri_fit_noalloc(lrigw_ctx *c, int batch, int n, int n_keep, int nrhs, const double *V, const double *T,
+                          double scale, double *C, int *info) {
+  (void)hipGetLastError();
+  if (info) *info = -1;
+  if (!c || !V || !T || !C) return LRIGW_ERR_ARG;
+  if (batch < 1 || batch > 65535 || n < 1 || n_keep < 1 || n_keep > n || nrhs < 1) return LRIGW_ERR_ARG;
+  return run_lri_fit_noalloc(c, batch, n, n_keep, nrhs, V, T, scale, C, info);
 }
 
 int lrigw_qp(lrigw_ctx *c, const void *sigma, const double *eps_qp, const double *e_static, int n_par, double *e_qp,

@@ -73,6 +73,7 @@ struct StageTimer {
 struct lrigw_ctx {
   Dims d;
   int precision = LRIGW_FP64;
+  int device = 0;                // HIP device current at lrigw_create
   hipStream_t stream = nullptr;
   std::vector<int> basis_off, aux_off;
   std::vector<int> h_kpq, h_kmq;
@@ -227,6 +228,12 @@ int run_cd_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig
 int run_sigma_x(lrigw_ctx *c, int iq, const void *xo, const void *V, double *sigma_x);
 int run_lri_fit(lrigw_ctx *c, int batch, int n, int n_keep, int nrhs, const double *V, const double *T, double scale,
                 double *C, int *info);
+// allocation-free fit: workspace in a fixed per-device array of LRIGW_FIT_SCRATCH_BYTES
+#define LRIGW_MAX_DEVICES 64
+int fit_scratch_prepare(int dev);
+size_t fit_scratch_bytes(int batch, int n, int nrhs);
+int run_lri_fit_noalloc(lrigw_ctx *c, int batch, int n, int n_keep, int nrhs, const double *V, const double *T,
+                        double scale, double *C, int *info);
 int run_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *p, double omega_cell,
              const double *e_static, int n_par, int q_first, int q_last, void *sigma, double *e_qp, double *z, int *info);
 int driver_buffers(lrigw_ctx *c);

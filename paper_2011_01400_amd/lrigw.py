@@ -24,6 +24,7 @@ LRIGW_ERR_NOCONV = -5
 LRIGW_WARN_QP_NOCONV = 1
 LRIGW_WARN_PADE_TRUNC = 2
 LRIGW_WARN_CD_RANGE = 3
+FIT_SCRATCH_BYTES = 64 << 20   # LRIGW_FIT_SCRATCH_BYTES: workspace limit of lrigw_lri_fit_noalloc
 
 FP64, FP32, SPLIT_BF16, SPLIT3_BF16, SPLIT_MIXED, SPLIT_F16 = 0, 1, 2, 3, 4, 5
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "split_bf16": SPLIT_BF16, "split3_bf16": SPLIT3_BF16,
@@ -32,7 +33,7 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "split_bf16": SPLIT_BF16, "split3_bf16
 # every symbol include/lrigw.h declares
 EXPORTS = ["lrigw_create", "lrigw_destroy", "lrigw_strerror", "lrigw_get_sizes", "lrigw_grids", "lrigw_lri_ft",
            "lrigw_build_M", "lrigw_chi0", "lrigw_gamma_prepare", "lrigw_screen", "lrigw_sigma_c", "lrigw_sigma_x",
-           "lrigw_sigma_x_pass", "lrigw_lri_fit", "lrigw_qp",
+           "lrigw_sigma_x_pass", "lrigw_lri_fit", "lrigw_lri_fit_noalloc", "lrigw_qp",
            "lrigw_set_real_grid", "lrigw_chi0_real", "lrigw_screen_real", "lrigw_sigma_cd", "lrigw_sigma_cd_pass",
            "lrigw_g0w0_cd", "lrigw_set_gamma_directions", "lrigw_pade_eval", "lrigw_g0w0", "lrigw_set_timing", "lrigw_stage_ms", "lrigw_reset_timing",
            "lrigw_surrogate_create", "lrigw_surrogate_destroy", "lrigw_surrogate_info", "lrigw_surrogate_rule",
@@ -104,6 +105,7 @@ def load(path: Optional[str] = None):
         "lrigw_sigma_x": (i, [vp, i, vp, vp, vp]),
         "lrigw_sigma_x_pass": (i, [vp, vp, vp, vp, vp]),
         "lrigw_lri_fit": (i, [vp, i, i, i, i, vp, vp, d, vp, ip]),
+        "lrigw_lri_fit_noalloc": (i, [vp, i, i, i, i, vp, vp, d, vp, ip]),
         "lrigw_qp": (i, [vp, vp, vp, vp, i, vp, vp, ip]),
         "lrigw_set_real_grid": (i, [vp, i, d]),
         "lrigw_set_gamma_directions": (i, [vp, i, vp, dp]),
@@ -286,6 +288,17 @@ class Context:
                                     _ptr(C), ctypes.byref(info))
         self._check(rc, "lrigw_lri_fit")
         return C
+
+    def lri_fit_noalloc(self, V, T, n_keep, C, scale=1.0):
+        """lri_fit with the library's fixed device workspace (no allocation);
+        returns (rc, info) without raising, so callers can see ERR_ARG for a
+        shape beyond the workspace."""
+        batch, n, _ = V.shape
+        nrhs = T.shape[2]
+        info = ctypes.c_int(0)
+        rc = self.lib.lrigw_lri_fit_noalloc(self.h, int(batch), int(n), int(n_keep), int(nrhs), _ptr(V), _ptr(T),
+                                            float(scale), _ptr(C), ctypes.byref(info))
+        return rc, info.value
 
     def qp(self, sigma, eps_qp, e_static, n_par, e_qp, z):
         info = ctypes.c_int(0)
