@@ -175,7 +175,9 @@ int lrigw_build_M(lrigw_ctx *ctx, int iq, int slice, const void *H, const void *
  * dielectric_func_gamma as a Gram form); the result, screened with V^cut(0),
  * gives W^cut(0).
  * chi_out: complex T [n_freq][N_aux][N_aux], Hermitian.
- * Errors: ERR_ARG (D <= 0: an unoccupied level below an occupied one,
+ * Errors: ERR_ARG (D <= 0: an unoccupied level below an occupied one, or a
+ * non-finite eigenvalue; the eigenvalues are read on every call, one small
+ * copy to the host, so new contents at the same address are checked too;
  * apply_gamma without preparation or with iq != 0). */
 int lrigw_chi0(lrigw_ctx *ctx, int iq, const void *M, const double *eig, int apply_gamma, void *chi_out);
 
@@ -436,7 +438,9 @@ int lrigw_surrogate_reset_stats(lrigw_surrogate *sg);
  * response kernel of every cell is timed on one q over its tile choices
  * (frequencies per workgroup, K split count) and the fastest is kept.
  * The arrays a cell names must stay valid while the batch exists; inputs may
- * change between runs (same addresses). */
+ * change between runs (same addresses).  The eigenvalues are checked for a
+ * gap (every unoccupied level above every occupied one) at create only: the
+ * graph does not re-check them, so new eigenvalues must keep that order. */
 typedef struct {
   lrigw_ctx *ctx;                 /* one context per cell */
   const void *H, *evec;           /* lrigw_lri_ft output, eigenvectors (device) */
@@ -486,13 +490,17 @@ int lrigw_tune(lrigw_ctx *ctx, const void *H, const void *evec, const double *ei
 /* Set the tile choices lrigw_tune would pick, explicitly: nw = frequencies per
  * response workgroup (the form's default or its alternative: 4/2 in the FP32
  * and split forms, 2/1 in FP64), splits = K splits (the partial-tile buffer
- * must hold them), pad = LDS row padding of the split-form response kernel (8
+ * must hold them; in the split forms at least ceil(K/4096), K = N_k n_occ
+ * n_unocc, so no workgroup sums more than 4096 rows in FP32), pad = LDS row padding of the split-form response kernel (8
  * or 16), sigma_variant = split-form self-energy kernel variant (0..10; 7 to
  * 10, the resident-tile form with 8 or 4 waves and LDS rows padded by 8 or
  * 16, need the two-part FP16 split, N_aux <= 288 and at most 32 frequencies).
  * Errors: ERR_ARG for a choice outside these sets or a variant the cell does
  * not admit. */
 int lrigw_set_tiles(lrigw_ctx *ctx, int nw, int splits, int pad, int sigma_variant);
+/* The current tile choices (host outputs, any may be NULL) and the number of
+ * self-energy kernel variants (valid ones are 0..n_variants-1). */
+int lrigw_get_tiles(const lrigw_ctx *ctx, int *nw, int *splits, int *pad, int *sigma_variant, int *n_variants);
 
 /* Per-kernel device time (ms, HIP events on the stream each stage runs on)
  * accumulated since the last reset, for the named stages "lri_ft", "build_M",

@@ -114,6 +114,8 @@ int run_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, c
              const double *e_static, int n_par, int q_first, int q_last, void *sigma, double *e_qp, double *z, int *info) {
   (void)omega_cell;
   const Dims &d = c->d;
+  if (c->gap_trusted == 0) LRIGW_TRY(chi0_check_gap(c, eig));
+  GapScope gap_scope(c);
   const bool all_q = (q_first == 0 && q_last == d.n_k);
   const hipStream_t s = c->stream;
   const bool overlap = (c->sur == nullptr) && !c->capturing;
@@ -205,6 +207,8 @@ int run_cd_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig
   const Dims &d = c->d;
   LRIGW_TRY(driver_buffers(c));
   if (p) LRIGW_TRY(lrigw_gamma_prepare(c, V, p, omega_cell));
+  LRIGW_TRY(chi0_check_gap(c, eig));
+  GapScope gap_scope(c);
   const hipStream_t s = c->stream, s2 = c->stream2;
   LRIGW_TRY(zero_fill(s, sigma_e, (size_t)n_e * d.n_k * d.n_qp * sizeof(double)));
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->d_info + 16, INT_MAX);

@@ -65,6 +65,7 @@ static int autotune_chi0(lrigw_ctx *c, const lrigw_batch_cell &cell, int *nw_out
     Ss.erase(std::unique(Ss.begin(), Ss.end()), Ss.end());
     for (int S : Ss) {
       if (S > Smax) continue;
+      if ((long long)S < chi0_min_splits(c, lrigw_K(c))) continue;
       if ((long long)S > std::max<long long>(1, lrigw_K(c) / 64)) continue;
       c->chi_splits = S;
       // warm-up, then the best of three timed runs
@@ -162,8 +163,11 @@ static int batch_capture(lrigw_batch *b) {
     c->capturing = true;
     const int timing = c->timing;
     c->timing = 0;
-    rc = run_pass(c, cl.H, cl.evec, cl.eig, cl.V, cl.p, cl.omega_cell, cl.e_static, cl.n_par, 0, c->d.n_k, cl.sigma,
-                  cl.e_qp, cl.z, nullptr);
+    {
+      GapScope gap_scope(c);   // checked in lrigw_batch_create; no host round trip under capture
+      rc = run_pass(c, cl.H, cl.evec, cl.eig, cl.V, cl.p, cl.omega_cell, cl.e_static, cl.n_par, 0, c->d.n_k, cl.sigma,
+                    cl.e_qp, cl.z, nullptr);
+    }
     c->timing = timing;
     c->capturing = false;
     c->stream = b->saved[i];
@@ -221,6 +225,7 @@ int lrigw_batch_create(lrigw_batch **out, int n_cells, const lrigw_batch_cell *c
     if ((rc = chi0_check_gap(c, cl.eig)) < 0) break;
     if (c->sur && (rc = surrogate_prepare(c->sur)) < 0) break;
     if (autotune) {
+      GapScope gap_scope(c);
       if ((rc = autotune_chi0(c, cl, &b->nw[i], &b->splits[i], &b->ms[i])) < 0) break;
     } else {
       b->nw[i] = c->chi_nw;
@@ -247,6 +252,7 @@ int lrigw_tune(lrigw_ctx *c, const void *H, const void *evec, const double *eig,
   if (!c || !H || !evec || !eig) return LRIGW_ERR_ARG;
   LRIGW_TRY(driver_buffers(c));
   LRIGW_TRY(chi0_check_gap(c, eig));
+  GapScope gap_scope(c);
   lrigw_batch_cell cell = {};
   cell.ctx = c;
   cell.H = H;
@@ -271,12 +277,23 @@ int lrigw_set_tiles(lrigw_ctx *c, int nw, int splits, int pad, int sigma_variant
   const Dims &d = c->d;
   const int nt = (d.n_aux + 63) / 64;
   const size_t per = (size_t)d.n_freq * ((size_t)nt * (nt + 1) / 2) * 64 * 64 * lrigw_csize(c);
-  if (splits < 1 || (size_t)splits * per > c->part_bytes || (long long)splits > std::max<long long>(1, lrigw_K(c) / 64))
+  if (splits < 1 || (size_t)splits * per > c->part_bytes || (long long)splits > std::max<long long>(1, lrigw_K(c) / 64) ||
+      (long long)splits < chi0_min_splits(c, lrigw_K(c)))
     return LRIGW_ERR_ARG;
   c->chi_nw = nw;
   c->chi_splits = splits;
   c->chi_pad = pad;
   c->sig_var = sigma_variant;
+  return LRIGW_OK;
+}
+
+int lrigw_get_tiles(const lrigw_ctx *c, int *nw, int *splits, int *pad, int *sigma_variant, int *n_variants) {
+  if (!c) return LRIGW_ERR_ARG;
+  if (nw) *nw = c->chi_nw;
+  if (splits) *splits = c->chi_splits;
+  if (pad) *pad = c->chi_pad;
+  if (sigma_variant) *sigma_variant = c->sig_var;
+  if (n_variants) *n_variants = sigma_variants();
   return LRIGW_OK;
 }
 

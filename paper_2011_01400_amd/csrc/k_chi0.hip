@@ -166,8 +166,9 @@ __global__ __launch_bounds__(256) void k_chi0_mfma(const typename c2t<T>::type *
 // MFMA in FP32 (NS = 2: hi*hi + hi*lo + lo*hi; NS = 3: six products, FP32-like
 // accuracy).  The unweighted side is split once per LDS tile; the weighted
 // side is kept in FP32 in LDS and weighted and split per frequency in
-// registers.  The split-K chunks are kept short (<= 2048 rows, see
-// chi0_plan_splits) so that FP32 accumulation error stays ~1e-6.
+// registers.  The split-K chunks are kept short (<= 2048 rows by default, see
+// chi0_plan_splits; the tuner and lrigw_set_tiles allow at most
+// CHI0_SPLIT_MAX_ROWS) so that FP32 accumulation error stays ~1e-6.
 #define KCB 32
 #define BAP 8    // bf16 padding of an A row in LDS
 #define BBP 2    // complex padding of a B row in LDS
@@ -533,12 +534,9 @@ int chi0_plan_splits(const lrigw_ctx *c, int *splits) {
 
 static int check_gap(lrigw_ctx *c, const double *eig);
 
-int chi0_check_gap(lrigw_ctx *c, const double *eig) {
-  if (eig == c->checked_eig) return LRIGW_OK;
-  LRIGW_TRY(check_gap(c, eig));
-  c->checked_eig = eig;
-  return LRIGW_OK;
-}
+// every call reads the eigenvalues (new contents at the same address are
+// checked too); the whole passes call it once and then open a GapScope
+int chi0_check_gap(lrigw_ctx *c, const double *eig) { return check_gap(c, eig); }
 
 static int check_gap(lrigw_ctx *c, const double *eig) {
   // insulator: every unoccupied level above every occupied level (D > 0)
@@ -567,10 +565,7 @@ int run_chi0_sel(lrigw_ctx *c, int iq, const void *M, const double *eig, int app
   // per-plane tables: imaginary planes first, then the real-axis ones
   const double *om2t = c->d_om2 + (real_axis ? d.n_freq : 0);
   const float *wsct = c->d_wsc + (real_axis ? d.n_freq : 0);
-  if (eig != c->checked_eig) {
-    LRIGW_TRY(check_gap(c, eig));
-    c->checked_eig = eig;
-  }
+  if (c->gap_trusted == 0) LRIGW_TRY(check_gap(c, eig));
   hipEvent_t ev_all;
   stage_begin(c, "chi0", &ev_all);
   LRIGW_TRY(launch_delta(c, iq, eig));

@@ -171,7 +171,7 @@ int run_set_real_grid(lrigw_ctx *c, int n_r, double omega_max) {
 int run_chi0_real(lrigw_ctx *c, int iq, const void *M, const double *eig, int apply_gamma, void *chi_out) {
   const Dims &d = c->d;
   if (c->n_real < 4) return LRIGW_ERR_ARG;
-  LRIGW_TRY(chi0_check_gap(c, eig));
+  if (c->gap_trusted == 0) LRIGW_TRY(chi0_check_gap(c, eig));
   const double gap = c->gap_min;
   if (!((c->n_real - 1) * c->real_h < gap)) return LRIGW_ERR_ARG;   // a pole of the response on the grid
   if (c->real_wsc_gap != gap) {

@@ -906,6 +906,8 @@ int surrogate_prepare(lrigw_surrogate *sg) { return ensure_batch(sg, sg->rank * 
 int run_chi0_surrogate(lrigw_ctx *c, lrigw_surrogate *sg, int iq, const void *M, const double *eig, int apply_gamma,
                        double threshold, void *chi_out) {
   if (!same_shape(sg, c)) return LRIGW_ERR_ARG;
+  if (c->gap_trusted == 0) LRIGW_TRY(chi0_check_gap(c, eig));
+  GapScope gap_scope(c);
   hipStream_t s = c->stream;
   const int N = sg->n_aux, r = sg->rank, na = sg->n_anchor, no = sg->n_out;
   const long long nn = (long long)N * N, rr = (long long)r * r;

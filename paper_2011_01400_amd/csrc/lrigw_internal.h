@@ -154,7 +154,9 @@ struct lrigw_ctx {
   hipStream_t stream2 = nullptr;
   hipEvent_t ev_chi[2] = {nullptr, nullptr}, ev_wc[2] = {nullptr, nullptr};
 
-  const double *checked_eig = nullptr;   // eigenvalue array already checked for a gap
+  // > 0 while a whole pass (or a captured graph) runs whose eigenvalues were
+  // checked for a gap at its start: the per-q response calls skip the check
+  int gap_trusted = 0;
 
   // graph capture: no host round trips; screening status folded into d_info[16]
   bool capturing = false;
@@ -170,6 +172,14 @@ struct lrigw_ctx {
 };
 
 size_t lrigw_csize(const lrigw_ctx *c);   // bytes of one complex T
+// marks the eigenvalues as checked for the lifetime of the scope
+struct GapScope {
+  lrigw_ctx *c;
+  explicit GapScope(lrigw_ctx *ctx) : c(ctx) { ++c->gap_trusted; }
+  ~GapScope() { --c->gap_trusted; }
+  GapScope(const GapScope &) = delete;
+  GapScope &operator=(const GapScope &) = delete;
+};
 // BF16 parts of the response / self-energy operands (0: not a split form)
 inline int ns_chi(int precision) {
   return (precision == LRIGW_SPLIT_BF16 || precision == LRIGW_SPLIT_MIXED || precision == LRIGW_SPLIT_F16) ? 2
@@ -194,6 +204,12 @@ int run_grids(lrigw_ctx *c);
 int chi0_default_nw(int precision);
 int chi0_alt_nw(int precision);
 int chi0_plan_splits(const lrigw_ctx *c, int *splits);
+// split forms: the longest K chunk one workgroup may sum in FP32 (the tuner
+// and lrigw_set_tiles keep splits >= ceil(K / CHI0_SPLIT_MAX_ROWS))
+#define CHI0_SPLIT_MAX_ROWS 4096
+inline long long chi0_min_splits(const lrigw_ctx *c, long long K) {
+  return ns_chi(c->precision) > 0 ? (K + CHI0_SPLIT_MAX_ROWS - 1) / CHI0_SPLIT_MAX_ROWS : 1;
+}
 int chi0_check_gap(lrigw_ctx *c, const double *eig);
 int sigma_variant_snw(int var);
 int sigma_variants();

@@ -41,7 +41,7 @@ EXPORTS = ["lrigw_create", "lrigw_destroy", "lrigw_strerror", "lrigw_get_sizes",
            "lrigw_surrogate_forward", "lrigw_surrogate_grad", "lrigw_surrogate_train", "lrigw_chi0_surrogate",
            "lrigw_set_surrogate", "lrigw_surrogate_stats", "lrigw_surrogate_reset_stats",
            "lrigw_batch_create", "lrigw_batch_run", "lrigw_batch_status", "lrigw_batch_tuning",
-           "lrigw_batch_graph_nodes", "lrigw_batch_destroy", "lrigw_tune", "lrigw_set_tiles"]
+           "lrigw_batch_graph_nodes", "lrigw_batch_destroy", "lrigw_tune", "lrigw_set_tiles", "lrigw_get_tiles"]
 
 
 class LrigwSystem(ctypes.Structure):
@@ -142,6 +142,7 @@ def load(path: Optional[str] = None):
         "lrigw_batch_destroy": (i, [vp]),
         "lrigw_tune": (i, [vp, vp, vp, vp, ip, ip, ip, dp]),
         "lrigw_set_tiles": (i, [vp, i, i, i, i]),
+        "lrigw_get_tiles": (i, [vp, ip, ip, ip, ip, ip]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -388,6 +389,16 @@ class Context:
 
     def set_tiles(self, nw, splits, pad, sigma_variant):
         self._check(self.lib.lrigw_set_tiles(self.h, int(nw), int(splits), int(pad), int(sigma_variant)), "lrigw_set_tiles")
+
+    def get_tiles(self):
+        """(nw, splits, pad, sigma_variant, n_variants) of the context."""
+        v = [ctypes.c_int(0) for _ in range(5)]
+        self._check(self.lib.lrigw_get_tiles(self.h, *[ctypes.byref(x) for x in v]), "lrigw_get_tiles")
+        return tuple(x.value for x in v)
+
+    @property
+    def tiles(self):
+        return self.get_tiles()[:4]
 
     def chi0_surrogate(self, sg, iq, M, eig, chi_out, threshold, apply_gamma=False):
         self._check(self.lib.lrigw_chi0_surrogate(self.h, sg.h, int(iq), _ptr(M), _ptr(eig), int(bool(apply_gamma)),

@@ -32,12 +32,11 @@ def relf(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("split3_bf16", 1e-5), ("split_bf16", 1e-5),
-                                           ("split_f16", 1e-5)])
-def test_sampled_q(c2, precision, tol):
+def _sampled(c2, ctx, tol, label, variants=None):
+    """chi0, W^c and the Sigma^c contribution of the sampled q against the
+    oracle's values; with `variants`, the Sigma^c contribution of every listed
+    self-energy kernel variant (response tiles unchanged) as well."""
     L, s, dev, g = c2["L"], c2["s"], c2["dev"], c2["g"]
-    print(f"[gpu c2] sampled q, {precision}", flush=True)
-    ctx = L.Context.from_system(s, precision=precision)
     sp = s.spec
     n = s.n_aux
     H = ctx.empty("H")
@@ -58,14 +57,63 @@ def test_sampled_q(c2, precision, tol):
         w = W.cpu().numpy().reshape(-1, n, n)[widx, :rows]
         assert relf(w, g[f"wc_q{q}"]) < 10 * tol, (q, relf(w, g[f"wc_q{q}"]))
         ctx.build_M(q, 1, H, dev["evec"], x)
-        sig = torch.zeros((s.n_k, sp.n_qp, sp.n_freq), dtype=torch.complex128, device="cuda")
-        ctx.sigma_c(q, x, W, dev["eig"], sig)
-        sg = sig.cpu().numpy()[kidx]
         ref = g[f"sigma_q{q}"]
-        err = np.max(np.abs(sg - ref)) / np.max(np.abs(ref))
-        print(f"  q={q} {precision}: chi {relf(c, g[f'chi_q{q}']):.2e}  Wc {relf(w, g[f'wc_q{q}']):.2e}  "
-              f"Sigma_q {err:.2e}", flush=True)
-        assert err < 10 * tol
+        for var in (variants or [None]):
+            if var is not None:
+                ctx.set_tiles(ctx.tiles[0], ctx.tiles[1], ctx.tiles[2], var)
+            sig = torch.zeros((s.n_k, sp.n_qp, sp.n_freq), dtype=torch.complex128, device="cuda")
+            ctx.sigma_c(q, x, W, dev["eig"], sig)
+            sg = sig.cpu().numpy()[kidx]
+            err = np.max(np.abs(sg - ref)) / np.max(np.abs(ref))
+            print(f"  q={q} {label} variant {var}: chi {relf(c, g[f'chi_q{q}']):.2e}  Wc {relf(w, g[f'wc_q{q}']):.2e}  "
+                  f"Sigma_q {err:.2e}", flush=True)
+            assert err < 10 * tol, (q, var, err)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("split3_bf16", 1e-5), ("split_bf16", 1e-5),
+                                           ("split_f16", 1e-5)])
+def test_sampled_q(c2, precision, tol):
+    """Default tiles (untuned context)."""
+    L, s = c2["L"], c2["s"]
+    print(f"[gpu c2] sampled q, {precision}", flush=True)
+    ctx = L.Context.from_system(s, precision=precision)
+    _sampled(c2, ctx, tol, precision)
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_f16", "split_mixed"])
+def test_sampled_q_tuned(c2, precision):
+    """The tile and kernel choices the benchmark runs with (the tuner's K
+    split count sets how many rows each workgroup sums in FP32)."""
+    L, s, dev = c2["L"], c2["s"], c2["dev"]
+    print(f"[gpu c2] sampled q, {precision}, tuned", flush=True)
+    ctx = L.Context.from_system(s, precision=precision)
+    H = ctx.empty("H")
+    ctx.lri_ft(dev["lri"], s.R, dev["evec"], H)
+    print(f"  tuned: {ctx.tune(H, dev['evec'], dev['eig'])}", flush=True)
+    _sampled(c2, ctx, 1e-5, precision + " tuned")
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["split_f16", "split_bf16", "split3_bf16"])
+def test_sampled_q_every_sigma_variant(c2, precision):
+    """Every self-energy kernel variant the cell admits (the resident-tile
+    kernel the tuner picks for the FP16 form among them) against the
+    oracle's Sigma^c contribution of each sampled q."""
+    L, s = c2["L"], c2["s"]
+    print(f"[gpu c2] sampled q, {precision}, every Sigma^c variant", flush=True)
+    ctx = L.Context.from_system(s, precision=precision)
+    ok = []
+    for var in range(ctx.get_tiles()[4]):
+        try:
+            ctx.set_tiles(ctx.tiles[0], ctx.tiles[1], ctx.tiles[2], var)
+            ok.append(var)
+        except L.LrigwError:
+            pass
+    print(f"  variants admitted: {ok}", flush=True)
+    if precision == "split_f16":
+        assert {7, 8, 9, 10} <= set(ok)
+    _sampled(c2, ctx, 1e-5, precision, variants=ok)
     ctx.close()
 
 
