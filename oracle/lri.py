@@ -13,8 +13,13 @@ Sec. II C of the paper:
 Here the stored real-space block of atom A, L_A(R)[mu][a][b], is the
 coefficient C~^{mu(0)}_{a(0), b(R)} with mu and a on atom A.
 
-The dense AO triple tensor is formed explicitly (N_aux x N_b x N_b per Bloch
-pair), exactly as the equation reads.
+`mo_triple` forms the dense AO triple tensor explicitly (N_aux x N_b x N_b
+per Bloch pair), exactly as the equation reads.  `mo_triple_per_atom` takes
+the same two equations one auxiliary atom at a time without forming the dense
+tensor (for cells where it would not fit in memory): an auxiliary function on
+atom A couples only to the orbital functions of A in either sector, so
+    C^mu_{mn} = sum_{a in A} c*_{am}(k1) [sum_j C~^mu_{a(0),j(k2)} c_{jn}(k2)]
+              + sum_{b in A} [sum_i c*_{im}(k1) C~^mu_{b(0),i(-k1)}] c_{bn}(k2).
 """
 from __future__ import annotations
 
@@ -63,11 +68,29 @@ def mo_triple(Ct, c1, c2):
     return np.einsum("im,uij,jn->umn", c1.conj(), Ct, c2, optimize=True)
 
 
+def mo_triple_per_atom(Lk2, Lmk1, basis_off, aux_off, c1, c2):
+    """Eq. AO_triple_split2 followed by Eq. AO_MO_transform, one auxiliary atom
+    at a time (no dense AO tensor).  Arguments as `ao_triple` and `mo_triple`;
+    returns [N_aux][M][N] complex128."""
+    n_aux = int(aux_off[-1])
+    out = np.empty((n_aux, c1.shape[1], c2.shape[1]), dtype=np.complex128)
+    for A in range(len(Lk2)):
+        mu = slice(int(aux_off[A]), int(aux_off[A + 1]))
+        a = slice(int(basis_off[A]), int(basis_off[A + 1]))
+        # sector mu on atom(i): i = a on A, j over every function
+        t1 = np.einsum("am,uaj,jn->umn", c1[a].conj(), Lk2[A], c2, optimize=True)
+        # sector mu on atom(j): j = b on A, i over every function (C~_{b(0),i(-k1)})
+        t2 = np.einsum("im,ubi,bn->umn", c1.conj(), Lmk1[A], c2[a], optimize=True)
+        out[mu] = t1 + t2
+    return out
+
+
 class TripleBuilder:
     """Forms C^mu_{mn}(k1,k2) for any pair of grid points of one cell."""
 
-    def __init__(self, sysm, kfrac):
+    def __init__(self, sysm, kfrac, per_atom=False):
         self.sys = sysm
+        self.per_atom = per_atom
         blocks = [sysm.lri_block(A) for A in range(sysm.spec.n_atoms)]
         self.Lk = lri_bloch(blocks, sysm.R, kfrac)          # at +k
         self.Lmk = lri_bloch(blocks, sysm.R, -kfrac)        # at -k (own transform)
@@ -80,6 +103,10 @@ class TripleBuilder:
     def mo(self, k1, k2, rows, cols):
         """C^mu_{mn}(k1,k2) for bands m in `rows`, n in `cols` (slices/arrays)."""
         c = self.sys.evec
+        if self.per_atom:
+            s = self.sys
+            return mo_triple_per_atom([L[k2] for L in self.Lk], [L[k1] for L in self.Lmk], s.basis_off, s.aux_off,
+                                      c[k1][:, rows], c[k2][:, cols])
         return mo_triple(self.ao(k1, k2), c[k1][:, rows], c[k2][:, cols])
 
 

@@ -23,13 +23,15 @@ from . import grids, lri, response, screening, selfenergy, continuation, contour
 
 
 class Oracle:
-    def __init__(self, sysm, n_par=16):
+    def __init__(self, sysm, n_par=16, per_atom=False):
         self.sys = sysm
         sp = sysm.spec
         self.kint, self.kfrac = grids.kgrid(sp.nk)
         self.kpq, self.kmq, self.minus = grids.kq_tables(sp.nk)
         self.omega, self.weight = grids.frequency_grid(sp.n_freq, sp.x0)
-        self.tb = lri.TripleBuilder(sysm, self.kfrac)
+        # per_atom: triples one auxiliary atom at a time (cells too large for
+        # the dense AO tensor); the dense form otherwise
+        self.tb = lri.TripleBuilder(sysm, self.kfrac, per_atom=per_atom)
         self.occ = slice(0, sp.n_occ)
         self.unocc = slice(sp.n_occ, sp.n_bands)
         self.qp = slice(sp.qp_lo, sp.qp_lo + sp.n_qp)

@@ -24,10 +24,26 @@ Omega as the crystal volume N_k * Omega_cell makes all three consistent).  The
 body is exactly the regular formula in the eigenbasis.  The result is
 transformed back with X and W^c(0) = X sqrt(v) (eps~_lam^{-1} - I) sqrt(v) X^H,
 V^cut entering the numerator.  The sign of the real eigenvector X_1 is fixed
-so that its largest-magnitude component is positive.  The head is pinned
-against the printed band-pair sum of the equation (every pair with its
-occupation difference, Omega the crystal volume); parity of the wing terms
-is unpinned beyond the special cases p = 0 and N_aux = 1.
+so that its largest-magnitude component is positive.
+
+What is pinned: the head against the printed band-pair sum of the equation
+(every pair with its occupation difference, Omega the crystal volume); the
+body against the regular formula (p = 0); the Gram structure (eigenvalues of
+eps~ >= 1) and the N_aux = 1 closed form; the wings' oddness in q_hat (a set
+closed under q_hat -> -q_hat removes them).  PARITY UNPINNED for the phase of
+the wings: they carry the phase of p_ia relative to the triple coefficients
+B_ia(k,0), which is fixed by how the momentum elements are defined (psi_i^k
+on the left, the convention that makes y_1 the q -> 0 limit of the G = 0-like
+component of B(k,q)), and synthetic momentum elements carry no such relation
+to B.  Two plausible errors therefore pass every pin here:
+  * a wing of the wrong sign (or any constant phase on p): it changes W^c(0)
+    of one direction only through the wing blocks, and the average over a
+    set closed under q_hat -> -q_hat is unchanged by it;
+  * conjugated momentum elements (p_ai in place of p_ia): head and body of
+    eps~ are unchanged, but the wing differs in more than a phase, and W^c(0)
+    moves even after the average (relative 5e-4 on the small cell), since the
+    wings enter the head and body of eps~^{-1} at second order.
+Both are checked to pass the pins in tests/test_oracle_screening.py.
 """
 from __future__ import annotations
 

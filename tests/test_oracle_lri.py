@@ -112,3 +112,44 @@ def test_time_reversal_of_outputs():
     assert np.max(np.abs(r1["sigma"][1] - r1["sigma"][o1.minus[1]])) > 1e-8   # wings break k <-> -k
     for k in range(s1.n_k):
         assert np.max(np.abs(r1["sigma"][k] - r2["sigma"][o1.minus[k]])) < 1e-13
+
+
+@pytest.mark.parametrize("cell", ["c1", "ragged", "nontrim"])
+def test_per_atom_triples_equal_dense(c1_system, cell):
+    """The per-atom evaluation of Eqs. AO_triple_split2 / AO_MO_transform (no
+    dense AO tensor; the form the oracle uses for large cells) against the
+    dense tensor, every Bloch pair and band block."""
+    if cell == "c1":
+        s = c1_system
+    elif cell == "ragged":
+        s = make_custom(n_atoms=3, nb_per_atom=5, naux_per_atom=7, nk=(2, 2, 1), n_occ=3, n_freq=6, seed=41)
+    else:
+        s = make_custom(n_atoms=2, nb_per_atom=4, naux_per_atom=9, nk=(3, 1, 2), n_occ=2, n_freq=6, seed=43)
+    _, kfrac = grids.kgrid(s.spec.nk)
+    dense = lri.TripleBuilder(s, kfrac)
+    pa = lri.TripleBuilder(s, kfrac, per_atom=True)
+    nb, no = s.spec.n_bands, s.spec.n_occ
+    blocks = [(slice(0, no), slice(no, nb)), (slice(0, nb), slice(0, nb)), (np.array([no - 1, no]), slice(0, no))]
+    for k1 in range(s.n_k):
+        for k2 in range(s.n_k):
+            for rows, cols in blocks:
+                a = dense.mo(k1, k2, rows, cols)
+                b = pa.mo(k1, k2, rows, cols)
+                assert np.max(np.abs(a - b)) < 1e-14 * max(1.0, np.max(np.abs(a)))
+
+
+def test_per_atom_triples_expand_rig_products_exactly():
+    """On the real-space rig (atoms with different numbers of auxiliary
+    functions), the per-atom triples reproduce every Bloch product exactly."""
+    from tests.test_oracle_rig import NK, build_rig
+    rig = build_rig()
+    s = rig["sys"]
+    pa = lri.TripleBuilder(s, rig["kfrac"], per_atom=True)
+    psi, Pq = rig["psi"], rig["Pq"]
+    nb = psi.shape[1]
+    for k1 in range(NK):
+        for k2 in range(NK):
+            C = pa.mo(k1, k2, slice(0, nb), slice(0, nb))
+            lhs = psi[k1].conj()[:, None, :] * psi[k2][None, :, :]
+            rhs = np.einsum("umn,ux->mnx", C, Pq[(k1 - k2) % NK].conj())
+            assert np.max(np.abs(lhs - rhs)) < 1e-13

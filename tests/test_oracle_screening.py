@@ -108,3 +108,35 @@ def test_gamma_head_matches_printed_band_pair_sum(c1_oracle):
                     tot += 2.0 * (f[m] - f[n]) * abs(pmn) ** 2 / ((d * d + w * w) * d)
         head = 1.0 - (4.0 * np.pi / omega_crystal) * 2.0 * tot
         assert abs(eps_l[iw][0, 0] - head) < 1e-12 * abs(head)
+
+
+def test_gamma_wing_phase_is_the_unpinned_convention(c1_oracle):
+    """The limit of the Gamma pins: a constant phase on the momentum elements
+    (a sign error of the wing is one) changes only the wing blocks of
+    eps~_lambda, so the head, the body and the eigenvalue bound hold for
+    either phase, and the average over +-q_hat is the same for both.
+    Conjugated momentum elements also keep head, body and bound, but change
+    the averaged W^c(0): that error would pass the pins and move results."""
+    s, o = c1_oracle.sys, c1_oracle
+    B0 = o.B(0)
+    rng = np.random.default_rng(5)
+    p = rng.standard_normal(s.p.shape) + 1j * rng.standard_normal(s.p.shape)
+    e1, _, _ = screening.screen_gamma(B0, s.eig, s.n_occ, p, s.omega_cell, s.V[0], o.omega)
+    e2, _, _ = screening.screen_gamma(B0, s.eig, s.n_occ, np.exp(0.7j) * p, s.omega_cell, s.V[0], o.omega)
+    assert np.max(np.abs(e1[:, 0, 0] - e2[:, 0, 0])) < 1e-13
+    assert np.max(np.abs(e1[:, 1:, 1:] - e2[:, 1:, 1:])) < 1e-13
+    assert np.max(np.abs(e1[:, 0, 1:] - e2[:, 0, 1:])) > 1e-3 * np.max(np.abs(e1[:, 0, 1:]))
+    for e in (e1, e2):
+        assert min(np.linalg.eigvalsh(m).min() for m in e) >= 1.0 - 1e-12
+    w = np.array([0.5, 0.5])
+    a1 = screening.screen_gamma_average(B0, s.eig, s.n_occ, np.stack([p, -p]), w, s.omega_cell, s.V[0], o.omega)
+    a2 = screening.screen_gamma_average(B0, s.eig, s.n_occ, np.stack([p.conj(), -p.conj()]), w, s.omega_cell,
+                                        s.V[0], o.omega)
+    a3 = screening.screen_gamma_average(B0, s.eig, s.n_occ, np.stack([np.exp(0.7j) * p, -np.exp(0.7j) * p]), w,
+                                        s.omega_cell, s.V[0], o.omega)
+    assert np.linalg.norm(a1 - a3) < 1e-12 * np.linalg.norm(a1)
+    e3, _, _ = screening.screen_gamma(B0, s.eig, s.n_occ, p.conj(), s.omega_cell, s.V[0], o.omega)
+    assert np.max(np.abs(e1[:, 0, 0] - e3[:, 0, 0])) < 1e-13
+    assert np.max(np.abs(e1[:, 1:, 1:] - e3[:, 1:, 1:])) < 1e-13
+    assert min(np.linalg.eigvalsh(m).min() for m in e3) >= 1.0 - 1e-12
+    assert np.linalg.norm(a1 - a2) > 1e-6 * np.linalg.norm(a1)
