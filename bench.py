@@ -269,33 +269,24 @@ def lri_fit_timing(run, sysm, reps=2):
 
 
 def cpu_baseline(sysm):
-    """FP64 oracle on a bounded sample of the same workload: one q (q = 1), all
-    N_w frequencies, all k points of chi0 and Sigma^c; the
-    k-dependent time is scaled by N_k / n_sample."""
+    """FP64 oracle as it stands on a bounded sample of the same workload: one q
+    (q = 1), all N_w frequencies, all k points, through the oracle's own
+    functions (triples, chi0, screening, pair weights, Sigma^c).  cores: the
+    host threads this process may run on (its affinity mask), which NumPy's
+    BLAS uses."""
     from oracle.pipeline import Oracle
-    from oracle import screening, selfenergy
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    except Exception:
-        threads = os.cpu_count() or 1
+    from oracle import screening, selfenergy, response
+    cores = len(os.sched_getaffinity(0))
     o = Oracle(sysm)
     s = sysm
     q = 1
     ks = list(range(0, s.n_k, 1))
     scale = s.n_k / len(ks)
     t0 = time.perf_counter()
-    B = np.stack([o.tb.mo(k, o.kpq[k, q], o.occ, o.unocc) for k in ks])
+    B = o.B(q)
     t_b = time.perf_counter() - t0
     t0 = time.perf_counter()
-    n_aux = s.n_aux
-    chi = np.zeros((len(o.omega), n_aux, n_aux), dtype=np.complex128)
-    for j, k in enumerate(ks):
-        d = (s.eig[o.kpq[k, q]][s.n_occ:][None, :] - s.eig[k][:s.n_occ][:, None]).reshape(-1)
-        Bk = B[j].reshape(n_aux, -1)
-        for iw, w in enumerate(o.omega):
-            chi[iw] += (Bk * (2 * d / (d * d + w * w))[None, :]) @ Bk.conj().T
-    chi *= -2.0 / s.n_k
+    chi = response.chi0_trs(B, s.eig, o.kpq, q, s.n_occ, o.omega)
     t_chi = time.perf_counter() - t0
     t0 = time.perf_counter()
     _, Wc = screening.screen(chi, s.V[q])
@@ -310,9 +301,30 @@ def cpu_baseline(sysm):
     nw = len(o.omega)
     per_q = scale * (t_b + t_chi + t_x + t_X) + t_scr
     total = t_b + t_chi + t_scr + t_x + t_X
-    return {"value": round(nw / per_q, 4), "unit": "(q,w)-pairs/s", "cores": int(threads), "kind": "oracle",
+    return {"value": round(nw / per_q, 4), "unit": "(q,w)-pairs/s", "cores": int(cores), "kind": "oracle",
             "sample": f"one q (q=1) of {s.n_k}, all {nw} frequencies, all {len(ks)} k points: {nw} of "
                       f"{s.n_k * nw} (q,w) pairs; {total:.1f} s of CPU work"}
+
+
+def qp_against_oracle(sysm, config, e_form, e_plain):
+    """QP energies of the timed form (and of the plain FP64 path) against the
+    FP64 oracle's whole pass over the same seeded cell, per state, when that
+    pass is on file (tests/golden/c2_qp.npz, written by an oracle-only script)."""
+    path = os.path.join(ROOT, "tests", "golden", f"c{config}_qp.npz")
+    if not os.path.exists(path):
+        return None
+    g = np.load(path)
+    if int(g["seed"]) != sysm.seed:
+        return None
+    E, Z = g["E"], g["Z"]
+    out = {"states": int(E.size)}
+    for name, e in (("form", e_form), ("plain_fp64", e_plain)):
+        if e is None:
+            continue
+        d = np.abs(e - E) * HA_MEV
+        out[name] = {"max_mev": round(float(d.max()), 4), "median_mev": round(float(np.median(d)), 5),
+                     "within_1_mev": bool(d.max() <= 1.0), "states_over_1_mev": int((d > 1.0).sum())}
+    return out
 
 
 def batched(args):
@@ -414,16 +426,18 @@ def main():
         reg = (z_plain >= 0.5) & (z_plain <= 1.0)
         d = np.abs(e_form - e_plain) * HA_MEV
         plain = {"value": round(pairs / pdt, 2), "ms_per_step": round(pdt * 1e3, 2),
-                 "qp_max_err_mev_quasiparticle_like": float(d[reg].max()),
                  "qp_max_err_mev_all_states": float(d.max()),
+                 "within_1_mev": bool(d.max() <= 1.0),
+                 "qp_max_err_mev_quasiparticle_like": float(d[reg].max()),
                  "quasiparticle_like_states": f"{int(reg.sum())} of {reg.size} (0.5 <= Z <= 1 in the plain path)",
-                 "within_1_mev": bool(d[reg].max() <= 1.0),
+                 "within_1_mev_quasiparticle_like": bool(d[reg].max() <= 1.0),
                  "stages_ms_per_step": {k: round(v[0], 3) for k, v in pstages.items()},
                  "roofline": roofline(sysm, pkern, "fp64", args.config)}
         print(f"# bench: plain fp64 {plain['value']} pairs/s, QP diff {plain['qp_max_err_mev_quasiparticle_like']:.3f} meV "
               f"(quasiparticle-like), {plain['qp_max_err_mev_all_states']:.3f} meV (all)", file=sys.stderr, flush=True)
         prun.ctx.close()
         del prun
+    oracle_qp = qp_against_oracle(sysm, args.config, e_form, e_plain if plain else None)
 
     rl = roofline(sysm, kern, args.precision, args.config)
     out = {
@@ -434,7 +448,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"Si-like 2-atom cell: N_b={sysm.n_b}, N_aux={sysm.n_aux}, "
                                f"k grid {'x'.join(map(str, sp.nk))}, N_occ={sp.n_occ}, {sp.n_bands} bands, "
-                               f"{sp.n_freq} modified Gauss-Legendre frequencies, QP bands {sp.qp_lo}..{sp.qp_lo + sp.n_qp - 1}",
+                               f"{sp.n_freq} modified Gauss-Legendre frequencies, QP bands {sp.qp_lo}..{sp.qp_lo + sp.n_qp - 1}, "
+                               f"LRI amplitude a_L={sp.lri_amplitude:.4g} x N(0,1) exp(-|R|/2 bohr)",
                    "precision_form": args.precision, "pairs_per_step": pairs},
         "stages_ms_per_step": {k: round(v[0], 3) for k, v in stages.items()},
         "roofline": rl,
@@ -450,6 +465,8 @@ def main():
     if plain:
         out["plain_fp64"] = plain
         out["speedup_vs_plain"] = round(value / plain["value"], 3)
+    if oracle_qp:
+        out["qp_vs_oracle"] = oracle_qp
     if not args.no_cpu:
         print("# bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sysm)

@@ -7,8 +7,8 @@ of every kernel is the same for every q except q = 0).  `summarize` turns the
 counter CSVs of two such runs into bytes per launch, taking for each kernel
 family its last dispatch (the pass's; the tuner's trials come first).
 
-  rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -- python3 -m paper_2011_01400_amd.profile_run
-  python3 -m paper_2011_01400_amd.profile_run --summarize <fetch dir> <write dir>
+  rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -- python3 profile_run.py
+  python3 profile_run.py --summarize <fetch dir> <write dir>
 """
 from __future__ import annotations
 
@@ -20,7 +20,7 @@ import json
 import os
 import sys
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ROOT = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 1 << 30          # calibration copy: 1 GiB read + 1 GiB written
 # the main kernel of each stage (all its variants) and its source file
 FAMILIES = {"sigma_mfma": (("k_sigma_res", "k_sigma_split", "k_sigma_splitq", "k_sigma_mfma"), "k_sigma.hip"),
@@ -148,16 +148,70 @@ def summarize(fetch_dir, write_dir, precision, config, out_path):
     print(json.dumps(out, indent=1))
 
 
+def _per_kernel_counters(rows):
+    """{kernel name: {dispatch id: {counter: value}}} from one counter CSV."""
+    acc = {}
+    for r in rows:
+        name = r.get("Kernel_Name") or r.get("Kernel-Name") or r.get("KernelName") or ""
+        cname = r.get("Counter_Name") or r.get("Counter-Name") or ""
+        val = float(r.get("Counter_Value") or r.get("Counter-Value") or 0.0)
+        disp = int(r.get("Dispatch_Id") or r.get("Dispatch-Id") or r.get("Correlation_Id") or 0)
+        d = acc.setdefault(name, {}).setdefault(disp, {})
+        d[cname] = d.get(cname, 0.0) + val
+    return acc
+
+
+def summarize_counters(dirs, title):
+    """Markdown table of every counter in the given runs for the last dispatch
+    of each kernel family (the pass's launch; the tuner's trials come first),
+    with MFMA busy as a share of the SIMD cycles of the dispatch."""
+    vals = {}
+    names = {}
+    for d in dirs:
+        per = _per_kernel_counters(_rows(d))
+        for k, disp in per.items():
+            base = k.split("(")[0].replace("void ", "").strip().split("<")[0].strip()
+            for fam, (members, _) in FAMILIES.items():
+                if base in members:
+                    last = max(disp)
+                    if fam not in names or last >= names[fam][0]:
+                        names[fam] = (last, k.split("(")[0].replace("void ", "").strip())
+                        vals.setdefault(fam, {}).update(disp[last])
+    lines = [f"## {title}", "", "| counter | " + " | ".join(f"{fam} (`{names[fam][1]}`)" for fam in vals) + " |",
+             "|---|" + "---:|" * len(vals)]
+    counters = sorted({c for v in vals.values() for c in v})
+    for c in counters:
+        lines.append(f"| {c} | " + " | ".join(f"{vals[f].get(c, float('nan')):.6g}" for f in vals) + " |")
+    derived = []
+    for f, v in vals.items():
+        if "SQ_INSTS_MFMA" in v and "SQ_INSTS_VALU" in v and v["SQ_INSTS_MFMA"] > 0:
+            derived.append(f"- {f}: VALU instructions per MFMA instruction "
+                           f"{(v['SQ_INSTS_VALU'] - v['SQ_INSTS_MFMA']) / v['SQ_INSTS_MFMA']:.3f} "
+                           "(SQ_INSTS_VALU counts the MFMA instructions too)")
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in v and "GRBM_GUI_ACTIVE" in v and v["GRBM_GUI_ACTIVE"] > 0:
+            derived.append(f"- {f}: MFMA busy {100.0 * v['SQ_VALU_MFMA_BUSY_CYCLES'] / (v['GRBM_GUI_ACTIVE'] / 8 * 256 * 4):.1f}% "
+                           "of SIMD cycles (SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / 8 XCDs x 256 CUs x 4 SIMDs))")
+        if "SQ_LDS_BANK_CONFLICT" in v and "SQ_LDS_IDX_ACTIVE" in v and v["SQ_LDS_IDX_ACTIVE"] > 0:
+            derived.append(f"- {f}: LDS bank-conflict cycles per LDS-active cycle "
+                           f"{v['SQ_LDS_BANK_CONFLICT'] / v['SQ_LDS_IDX_ACTIVE']:.3f}")
+    if derived:
+        lines += ["", *derived]
+    print("\n".join(lines))
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--precision", default="split_f16")
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--q", type=int, default=1)
     ap.add_argument("--summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--counters", nargs="+", metavar="PMC_DIR", help="markdown table of the counters of these runs")
     ap.add_argument("--contour", action="store_true", help="one contour-deformation pass instead of one q")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "traffic.json"))
     a = ap.parse_args()
-    if a.summarize:
+    if a.counters:
+        summarize_counters(a.counters, f"{a.precision}, config {a.config}")
+    elif a.summarize:
         summarize(a.summarize[0], a.summarize[1], a.precision, a.config, a.out)
     elif a.contour:
         run_contour(a.precision, a.config)
