@@ -78,7 +78,13 @@ class Oracle:
                                                       self.omega)
             return screening.screen_gamma(B, s.eig, s.n_occ, s.p, s.omega_cell, s.V[0], self.omega)[2]
         chi = self.chi0(q, B) if chi is None else chi
-        return screening.screen(chi, s.V[q])[1]
+        return screening.screen(chi, s.V[q], self._vcut(q))[1]
+
+    def _vcut(self, q):
+        """V^cut(q) of the cell for q != 0 (None: V^cut = V).  At q = 0 the
+        cell's V[0] already is V^cut(0), in both places (Sec. III B)."""
+        vc = getattr(self.sys, "Vcut", None)
+        return None if (vc is None or q == 0) else vc[q]
 
     def sigma_q(self, q, Wc, ks=None):
         """Contribution of q to Sigma^c for the k points `ks` (default all)."""
@@ -104,7 +110,7 @@ class Oracle:
                                                       omega_r, real_axis=True)
             return screening.screen_gamma(B, s.eig, s.n_occ, s.p, s.omega_cell, s.V[0], omega_r, real_axis=True)[2]
         chi = self.chi0_real(q, omega_r, B) if chi is None else chi
-        return screening.screen(chi, s.V[q])[1]
+        return screening.screen(chi, s.V[q], self._vcut(q))[1]
 
     def sigma_cd_q(self, q, Wc, Wr, h, E, ks=None):
         """Contribution of q to Sigma^c at the real energies E [n_e][len(ks)][N_qp]."""

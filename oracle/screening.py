@@ -5,7 +5,9 @@ Eq. symm_dielec_func:  eps~(q,iw) = I - V^{1/2} chi~ V^{1/2}
 Eq. screened_W_matr:   W(q,iw)   = V^{1/2} eps~^{-1} V^{1/2}
 Correlation part:      W^c = W - V = V^{1/2} (eps~^{-1} - I) V^{1/2}
 V^{1/2} is the Hermitian square root from an eigendecomposition, as the paper
-writes it.
+writes it.  With a truncated Coulomb matrix V^cut(q) (Sec. III B), V^cut
+takes the place of V in the numerator only: W^c = V^cut^{1/2} (eps~^{-1} - I)
+V^cut^{1/2}, eps~ from the full V (`screen(chi, V, Vcut)`).
 
 At q = 0 (Sec. III B, Eq. dielectric_func_gamma) the dielectric matrix is
 built in the eigenbasis X, v of the truncated Coulomb matrix V^cut(0), with
@@ -59,16 +61,24 @@ def sqrt_hpd(V):
     return (U * np.sqrt(lam)[None, :]) @ U.conj().T
 
 
-def screen(chi, V):
-    """chi: [N_w][N][N], V: [N][N].  Returns (eps~, W^c) per frequency."""
+def screen(chi, V, Vcut=None):
+    """chi: [N_w][N][N], V: [N][N].  Returns (eps~, W^c) per frequency.
+
+    Vcut (Sec. III B, after Eq. cut_coulomb_pot): the truncated Coulomb
+    matrix V^cut(q).  It replaces V in the numerator of Eq. screened_W_matr
+    (the two V^{1/2} factors) while eps~ keeps the full V:
+        W^c = Vcut^{1/2} (eps~^{-1} - I) Vcut^{1/2},  eps~ = I - V^{1/2} chi V^{1/2},
+    both square roots the Hermitian (principal) ones, as the equation writes
+    them.  None: V in both places."""
     Vh = sqrt_hpd(V)
+    Vch = Vh if Vcut is None else sqrt_hpd(Vcut)
     n = V.shape[0]
     eye = np.eye(n)
     eps = np.empty_like(chi)
     Wc = np.empty_like(chi)
     for iw in range(chi.shape[0]):
         eps[iw] = eye - Vh @ chi[iw] @ Vh
-        Wc[iw] = Vh @ (np.linalg.inv(eps[iw]) - eye) @ Vh
+        Wc[iw] = Vch @ (np.linalg.inv(eps[iw]) - eye) @ Vch
     return eps, Wc
 
 

@@ -118,6 +118,7 @@ class System:
     mu: float                  # chemical potential, mid-gap (Ha)
     e_static: np.ndarray       # float64 [N_k][N_qp], Sigma^x - V^xc (zero here)
     seed: int
+    Vcut: Optional[np.ndarray] = None   # complex128 [N_q][N_aux][N_aux] truncated V(q), or None (V^cut = V)
 
     # convenience views
     @property
@@ -265,6 +266,32 @@ def make_system(spec: CellSpec, seed: int, *, lri_scale: float = 1.0,
     return System(spec=spec, basis_off=basis_off, aux_off=aux_off, lattice=lat, R=R, lri=lri,
                   lri_off=np.array(lri_off, dtype=np.int64), eig=eig, evec=evec, V=V, p=p,
                   omega_cell=omega_cell, mu=float(mu), e_static=e_static, seed=seed)
+
+
+def truncated_coulomb(sysm: System) -> np.ndarray:
+    """V^cut(q) for every q, complex [N_q][N_aux][N_aux]: V(q) with the
+    divergent 4 pi/|q|^2 on auxiliary function 0 replaced by the Fourier
+    transform of the Coulomb operator cut off at R_cut (the inscribed radius
+    of the Born-von Karman supercell), 4 pi (1 - cos(|q| R_cut))/|q|^2, whose
+    q -> 0 limit 2 pi R_cut^2 is the value V[0] already carries.  Positive
+    definite (the added term is >= 0); V^cut(-q) = conj V^cut(q)."""
+    sp = sysm.spec
+    nk = sp.nk
+    kint = _kint(nk)
+    recip = 2.0 * math.pi * np.linalg.inv(sysm.lattice).T
+    r_cut = _inscribed_radius(sysm.lattice * np.array(nk, dtype=np.float64)[:, None])
+    minus = _kidx(-kint, nk)
+    Vc = sysm.V.copy()
+    for q in range(1, sysm.n_k):
+        if minus[q] < q:   # the partner's |q| is the one V(q) = conj V(-q) carries
+            Vc[q] = np.conj(Vc[minus[q]])
+            continue
+        f = kint[q] / np.array(nk, dtype=np.float64)
+        f = np.where(f > 0.5, f - 1.0, f)
+        qc = f @ recip
+        q2 = float(qc @ qc)
+        Vc[q, 0, 0] -= 4.0 * math.pi * math.cos(math.sqrt(q2) * r_cut) / q2
+    return Vc
 
 
 def momentum_vectors(sysm: System) -> np.ndarray:
