@@ -199,8 +199,17 @@ int lrigw_gamma_prepare(lrigw_ctx *ctx, const void *Vcut0, const void *p, double
  * [N_aux][N_aux] (V(q), or V^cut(0) at iq == 0).  Wc_out: complex T, same
  * shape as chi.  info (host, may be NULL): -1, or the first frequency index
  * whose eps~ was not positive definite, or -2 if V was not.
- * Errors: ERR_NOT_HPD. */
-int lrigw_screen(lrigw_ctx *ctx, int iq, const void *chi, const void *V, void *Wc_out, int *info);
+ * Vcut: complex128 [N_aux][N_aux] truncated Coulomb matrix V^cut(q) (Sec. III
+ * B, Eq. cut_coulomb_pot), or NULL (= V).  It replaces V in the numerator
+ * only, W^c = V^cut^{1/2} (eps~^{-1} - I) V^cut^{1/2} with eps~ from the full
+ * V, both roots the Hermitian ones: computed as T (eps~_L^{-1} - I) T^H with
+ * T = V^cut^{1/2} V^{1/2} L^{-H}, the roots by a fixed number of coupled
+ * Newton-Schulz steps on the device (exact to rounding for
+ * |V|_F / lambda_min(V) up to 1e10; about 2 x 108 FP64 N_aux^3 GEMMs per
+ * call).  A workspace of 13 N_aux^2 complex128 is allocated at the first such
+ * call and kept by the context.
+ * Errors: ERR_NOT_HPD, ERR_OOM. */
+int lrigw_screen(lrigw_ctx *ctx, int iq, const void *chi, const void *V, const void *Vcut, void *Wc_out, int *info);
 
 /* Correlation self-energy, Eq. GW_selfe_element with W -> W^c and w_q = 1/N_q,
  * folded onto w' > 0 (W^c is even in w'):
@@ -260,9 +269,12 @@ int lrigw_pade_eval(lrigw_ctx *ctx, const void *sigma, int n_par, int n_e, const
  * NULL (no q = 0 head/wings); H: lrigw_lri_ft output.  sigma: complex128
  * [N_k][n_qp][n_freq] output; e_qp, z: FP64 [N_k][n_qp].  q_first..q_last-1
  * restricts the q loop (0, N_k for all; QP only when all q were done).
+ * Vcut: complex128 [N_k][N_aux][N_aux] truncated Coulomb matrices V^cut(q) for
+ * the numerator of the screening at q != 0 (lrigw_screen), or NULL (V^cut =
+ * V); Vcut[0] is not read (V[0] is V^cut(0), used in both places at q = 0).
  * The buffers for M, chi0 and W^c are owned by the context. */
-int lrigw_g0w0(lrigw_ctx *ctx, const void *H, const void *evec, const double *eig, const void *V, const void *p,
-               double omega_cell, const double *e_static, int n_par, int q_first, int q_last,
+int lrigw_g0w0(lrigw_ctx *ctx, const void *H, const void *evec, const double *eig, const void *V, const void *Vcut,
+               const void *p, double omega_cell, const double *e_static, int n_par, int q_first, int q_last,
                void *sigma, double *e_qp, double *z, int *info);
 
 /* Average the q -> 0 screening over directions of approach.  The head and
@@ -319,8 +331,9 @@ int lrigw_set_real_grid(lrigw_ctx *ctx, int n_r, double omega_max);
  * energy of eig, where the response has a pole), as lrigw_chi0 otherwise. */
 int lrigw_chi0_real(lrigw_ctx *ctx, int iq, const void *M, const double *eig, int apply_gamma, void *chi_out);
 
-/* W^c(q, w_r) from lrigw_chi0_real's output: lrigw_screen over n_r planes. */
-int lrigw_screen_real(lrigw_ctx *ctx, int iq, const void *chi, const void *V, void *Wc_out, int *info);
+/* W^c(q, w_r) from lrigw_chi0_real's output: lrigw_screen over n_r planes
+ * (Vcut as there). */
+int lrigw_screen_real(lrigw_ctx *ctx, int iq, const void *chi, const void *V, const void *Vcut, void *Wc_out, int *info);
 
 /* Contribution of q to Sigma^c_n(k, E) at n_e (1..4) sets of real energies.
  * x: slice-1 output of lrigw_build_M; Wc: lrigw_screen output (n_freq
@@ -333,15 +346,15 @@ int lrigw_sigma_cd(lrigw_ctx *ctx, int iq, const void *x, const void *Wc, const 
 
 /* lrigw_sigma_cd summed over every q.  The per-q response and W^c come from
  * the exact response on both grids, with the q = 0 head and wings when p !=
- * NULL.  Arguments are as for lrigw_g0w0; sigma_e is set (not accumulated).
+ * NULL.  Arguments are as for lrigw_g0w0 (V^cut included); sigma_e is set (not accumulated).
  * n_bad (host, may be NULL) receives the number of NaN outputs.
  * Returns WARN_CD_RANGE when there are any.  Screens q on the context's second
  * stream while the responses of q+1 are built (as lrigw_g0w0) and waits for
  * the stream at the end; not for graph capture.  Errors: ERR_ARG (NULL, no
  * real grid, n_e outside 1..4, p without omega_cell > 0, called while the
  * context captures a graph), ERR_NOT_HPD (a screening failed). */
-int lrigw_sigma_cd_pass(lrigw_ctx *ctx, const void *H, const void *evec, const double *eig, const void *V, const void *p,
-                        double omega_cell, int n_e, const double *E, double *sigma_e, int *n_bad);
+int lrigw_sigma_cd_pass(lrigw_ctx *ctx, const void *H, const void *evec, const double *eig, const void *V, const void *Vcut,
+                        const void *p, double omega_cell, int n_e, const double *E, double *sigma_e, int *n_bad);
 
 /* Linearised quasiparticle energies from contour deformation:
  *   Sigma^c at e_n - delta, e_n, e_n + delta (e_n the band energies of the QP bands),
@@ -351,9 +364,9 @@ int lrigw_sigma_cd_pass(lrigw_ctx *ctx, const void *H, const void *evec, const d
  * outputs; e_static may be NULL.  Returns WARN_CD_RANGE as lrigw_sigma_cd_pass;
  * states with a NaN among their three values get NaN energies.  Errors: as
  * lrigw_sigma_cd_pass, and ERR_ARG for delta <= 0. */
-int lrigw_g0w0_cd(lrigw_ctx *ctx, const void *H, const void *evec, const double *eig, const void *V, const void *p,
-                  double omega_cell, const double *e_static, double delta, double *sigma3, double *e_qp, double *z,
-                  int *n_bad);
+int lrigw_g0w0_cd(lrigw_ctx *ctx, const void *H, const void *evec, const double *eig, const void *V, const void *Vcut,
+                  const void *p, double omega_cell, const double *e_static, double delta, double *sigma3, double *e_qp,
+                  double *z, int *n_bad);
 
 /* ---- Learned frequency surrogate of the response (a form the paper does not
  * have; it evaluates Eq. chi0_matrix at every frequency of the grid).
@@ -445,7 +458,7 @@ typedef struct {
   lrigw_ctx *ctx;                 /* one context per cell */
   const void *H, *evec;           /* lrigw_lri_ft output, eigenvectors (device) */
   const double *eig;              /* FP64 [N_k][n_bands] (device) */
-  const void *V, *p;              /* as lrigw_g0w0; p may be NULL */
+  const void *V, *Vcut, *p;       /* as lrigw_g0w0; Vcut and p may be NULL */
   double omega_cell;
   const double *e_static;         /* FP64 [N_k][n_qp] or NULL */
   int n_par;                      /* Pade points (1..64) */

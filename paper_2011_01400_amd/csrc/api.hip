@@ -52,7 +52,7 @@ static void free_all(lrigw_ctx *c) {
                   c->d_delta, c->d_part, c->d_X, c->d_LV, c->d_s0, c->d_s1, c->d_s2, c->d_s3, c->d_dinv, c->d_info,
                   c->d_bhat, c->d_x1, c->d_M, c->d_x, c->d_chi, c->d_wc, c->d_epsqp, c->d_xs, c->d_ws, c->d_ap, c->d_bt, c->d_chi2, c->d_wc2,
                   c->d_sx, c->d_wmax, c->d_amax, c->d_sitems, c->d_wd, c->d_xo, c->d_sxa, c->d_sxz, c->d_om2,
-                  c->d_wsc, c->d_chir, c->d_wr, c->d_Xr, c->d_cdE, c->d_cdS, c->d_cdbad, c->d_sitems_r, c->d_chir2, c->d_wr2};
+                  c->d_wsc, c->d_chir, c->d_wr, c->d_Xr, c->d_cdE, c->d_cdS, c->d_cdbad, c->d_sitems_r, c->d_chir2, c->d_wr2, c->d_cut};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &kv : c->stages)
@@ -110,8 +110,9 @@ int driver_buffers(lrigw_ctx *c) {
 // attached (its per-q work shares the screening workspaces), and under graph
 // capture (the batched form overlaps whole cells on streams of their own
 // instead), the pass runs on `stream` alone.
-int run_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *p, double omega_cell,
-             const double *e_static, int n_par, int q_first, int q_last, void *sigma, double *e_qp, double *z, int *info) {
+int run_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *Vcut,
+             const void *p, double omega_cell, const double *e_static, int n_par, int q_first, int q_last, void *sigma,
+             double *e_qp, double *z, int *info) {
   (void)omega_cell;
   const Dims &d = c->d;
   if (c->gap_trusted == 0) LRIGW_TRY(chi0_check_gap(c, eig));
@@ -153,7 +154,9 @@ int run_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, c
         }
       }
       c->stream = s2;
-      rc = lrigw_screen(c, q, chi[b], (const double2 *)V + q * vstride, wc[b], nullptr);
+      // V^cut(q) in the numerator for q != 0; V[0] already is V^cut(0)
+      const void *Vcq = (Vcut && q > 0) ? (const void *)((const double2 *)Vcut + q * vstride) : nullptr;
+      rc = lrigw_screen(c, q, chi[b], (const double2 *)V + q * vstride, Vcq, wc[b], nullptr);
       c->stream = s;
       if (rc < 0) break;
       if (overlap && hipEventRecord(c->ev_wc[b], s2) != hipSuccess) {
@@ -202,8 +205,8 @@ int run_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, c
 // the responses of q+1 are built on `stream`; the same events order the
 // buffer reuse, and the screening status is folded on the device.  The
 // exact response is used (an attached surrogate is not).
-int run_cd_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *p,
-                double omega_cell, int n_e, const double *E, double *sigma_e, int *n_bad) {
+int run_cd_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *Vcut,
+                const void *p, double omega_cell, int n_e, const double *E, double *sigma_e, int *n_bad) {
   const Dims &d = c->d;
   LRIGW_TRY(driver_buffers(c));
   if (p) LRIGW_TRY(lrigw_gamma_prepare(c, V, p, omega_cell));
@@ -239,8 +242,9 @@ int run_cd_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig
         break;
       }
       c->stream = s2;
-      rc = run_screen(c, q, chi[b], Vq, wc[b], nullptr);
-      if (rc == LRIGW_OK) rc = run_screen_n(c, q, chir[b], Vq, wr[b], nullptr, c->n_real);
+      const void *Vcq = (Vcut && q > 0) ? (const void *)((const double2 *)Vcut + q * vstride) : nullptr;
+      rc = run_screen(c, q, chi[b], Vq, Vcq, wc[b], nullptr);
+      if (rc == LRIGW_OK) rc = run_screen_n(c, q, chir[b], Vq, Vcq, wr[b], nullptr, c->n_real);
       c->stream = s;
       if (rc < 0) break;
       if (hipEventRecord(c->ev_wc[b], s2) != hipSuccess) {
@@ -456,13 +460,13 @@ int lrigw_set_gamma_directions(lrigw_ctx *c, int n_dir, const void *p_dirs, cons
   return LRIGW_OK;
 }
 
-int lrigw_screen(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_out, int *info) {
+int lrigw_screen(lrigw_ctx *c, int iq, const void *chi, const void *V, const void *Vcut, void *Wc_out, int *info) {
   (void)hipGetLastError();  // drop a stale error another library left behind
   if (!c || !chi || !V || !Wc_out) return LRIGW_ERR_ARG;
   if (iq < 0 || iq >= c->d.n_k) return LRIGW_ERR_ARG;
   hipEvent_t ev;
   stage_begin(c, "screen", &ev);
-  int rc = run_screen(c, iq, chi, V, Wc_out, info);
+  int rc = run_screen(c, iq, chi, V, Vcut, Wc_out, info);
   stage_end(c, "screen", ev);
   return rc;
 }
@@ -543,13 +547,13 @@ int lrigw_chi0_real(lrigw_ctx *c, int iq, const void *M, const double *eig, int 
   return rc;
 }
 
-int lrigw_screen_real(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_out, int *info) {
+int lrigw_screen_real(lrigw_ctx *c, int iq, const void *chi, const void *V, const void *Vcut, void *Wc_out, int *info) {
   (void)hipGetLastError();
   if (!c || !chi || !V || !Wc_out) return LRIGW_ERR_ARG;
   if (iq < 0 || iq >= c->d.n_k || c->n_real < 4) return LRIGW_ERR_ARG;
   hipEvent_t ev;
   stage_begin(c, "screen_real", &ev);
-  int rc = run_screen_n(c, iq, chi, V, Wc_out, info, c->n_real);
+  int rc = run_screen_n(c, iq, chi, V, Vcut, Wc_out, info, c->n_real);
   stage_end(c, "screen_real", ev);
   return rc;
 }
@@ -562,19 +566,19 @@ int lrigw_sigma_cd(lrigw_ctx *c, int iq, const void *x, const void *Wc, const vo
   return run_sigma_cd(c, iq, x, Wc, Wr, eig, n_e, E, sigma_e);
 }
 
-int lrigw_sigma_cd_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *p,
-                        double omega_cell, int n_e, const double *E, double *sigma_e, int *n_bad) {
+int lrigw_sigma_cd_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *Vcut,
+                        const void *p, double omega_cell, int n_e, const double *E, double *sigma_e, int *n_bad) {
   (void)hipGetLastError();
   if (n_bad) *n_bad = 0;
   if (!c || !H || !evec || !eig || !V || !E || !sigma_e) return LRIGW_ERR_ARG;
   if (c->n_real < 4 || n_e < 1 || n_e > 4 || c->capturing) return LRIGW_ERR_ARG;
   if (p && !(omega_cell > 0.0)) return LRIGW_ERR_ARG;
-  return run_cd_pass(c, H, evec, eig, V, p, omega_cell, n_e, E, sigma_e, n_bad);
+  return run_cd_pass(c, H, evec, eig, V, Vcut, p, omega_cell, n_e, E, sigma_e, n_bad);
 }
 
-int lrigw_g0w0_cd(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *p,
-                  double omega_cell, const double *e_static, double delta, double *sigma3, double *e_qp, double *z,
-                  int *n_bad) {
+int lrigw_g0w0_cd(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *Vcut,
+                  const void *p, double omega_cell, const double *e_static, double delta, double *sigma3, double *e_qp,
+                  double *z, int *n_bad) {
   (void)hipGetLastError();
   if (n_bad) *n_bad = 0;
   if (!c || !H || !evec || !eig || !V || !e_qp || !z) return LRIGW_ERR_ARG;
@@ -582,7 +586,7 @@ int lrigw_g0w0_cd(lrigw_ctx *c, const void *H, const void *evec, const double *e
   if (p && !(omega_cell > 0.0)) return LRIGW_ERR_ARG;
   double *S = sigma3 ? sigma3 : c->d_cdS;
   LRIGW_TRY(cd_energies(c, eig, delta));
-  const int rc = run_cd_pass(c, H, evec, eig, V, p, omega_cell, 3, c->d_cdE, S, n_bad);
+  const int rc = run_cd_pass(c, H, evec, eig, V, Vcut, p, omega_cell, 3, c->d_cdE, S, n_bad);
   if (rc < 0) return rc;
   LRIGW_TRY(cd_qp_linear(c, S, e_static, delta, e_qp, z));
   return rc;
@@ -594,8 +598,8 @@ int lrigw_pade_eval(lrigw_ctx *c, const void *sigma, int n_par, int n_e, const d
   return run_pade_eval(c, sigma, n_par, n_e, E, out);
 }
 
-int lrigw_g0w0(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *p,
-               double omega_cell, const double *e_static, int n_par, int q_first, int q_last, void *sigma,
+int lrigw_g0w0(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *Vcut,
+               const void *p, double omega_cell, const double *e_static, int n_par, int q_first, int q_last, void *sigma,
                double *e_qp, double *z, int *info) {
   (void)hipGetLastError();
   if (!c || !H || !evec || !eig || !V || !sigma) return LRIGW_ERR_ARG;
@@ -606,7 +610,7 @@ int lrigw_g0w0(lrigw_ctx *c, const void *H, const void *evec, const double *eig,
   if (n_par < 1 || n_par > 64) return LRIGW_ERR_ARG;
   LRIGW_TRY(driver_buffers(c));
   if (p && q_first == 0) LRIGW_TRY(lrigw_gamma_prepare(c, V, p, omega_cell));
-  return run_pass(c, H, evec, eig, V, p, omega_cell, e_static, n_par, q_first, q_last, sigma, e_qp, z, info);
+  return run_pass(c, H, evec, eig, V, Vcut, p, omega_cell, e_static, n_par, q_first, q_last, sigma, e_qp, z, info);
 }
 
 int lrigw_set_timing(lrigw_ctx *c, int on) {

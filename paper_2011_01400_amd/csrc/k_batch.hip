@@ -165,8 +165,8 @@ static int batch_capture(lrigw_batch *b) {
     c->timing = 0;
     {
       GapScope gap_scope(c);   // checked in lrigw_batch_create; no host round trip under capture
-      rc = run_pass(c, cl.H, cl.evec, cl.eig, cl.V, cl.p, cl.omega_cell, cl.e_static, cl.n_par, 0, c->d.n_k, cl.sigma,
-                    cl.e_qp, cl.z, nullptr);
+      rc = run_pass(c, cl.H, cl.evec, cl.eig, cl.V, cl.Vcut, cl.p, cl.omega_cell, cl.e_static, cl.n_par, 0, c->d.n_k,
+                    cl.sigma, cl.e_qp, cl.z, nullptr);
     }
     c->timing = timing;
     c->capturing = false;

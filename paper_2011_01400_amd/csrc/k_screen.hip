@@ -5,6 +5,17 @@
 //   W^c = L (E^{-1} - I) L^H = -L (E^{-1} D) L^H,   E^{-1} D by two triangular solves
 // Using L in place of V^{1/2} leaves W unchanged (L = V^{1/2} Q with Q unitary),
 // and E^{-1} D avoids the cancellation of E^{-1} - I where screening is weak.
+//
+// Truncated Coulomb matrix (Sec. III B): V^cut replaces V in the numerator
+// only, W^c = S_c (eps~^{-1} - I) S_c with S = V^{1/2}, S_c = V^cut^{1/2} the
+// Hermitian roots and eps~ from the full V.  Since eps~^{-1} - I =
+// S L^{-H} (E^{-1} - I) L^{-1} S, this is T (E^{-1} - I) T^H with
+// T = S_c S L^{-H}; the screening keeps its Cholesky steps and takes T in
+// place of L in the last two products (T = L when V^cut = V).  The two roots
+// come from the coupled Newton-Schulz iteration on the FP64 MFMA GEMM,
+// Y <- Y M, Z <- M Z, M = (3I - Z Y)/2 from Y = A/|A|_F, Z = I
+// (Y -> (A/|A|_F)^{1/2}; a fixed NS_ITERS steps reach FP64 rounding for
+// |A|_F / lambda_min up to 1e10).
 #include <algorithm>
 #include <climits>
 
@@ -60,6 +71,58 @@ __global__ void k_fold_status(int *info, int q) {
   if (info[1] != INT_MAX || info[2] != INT_MAX) info[16] = min(info[16], q);
 }
 
+// nrm[b] = Frobenius norm of matrix b (one workgroup per matrix, FP64 sum)
+__global__ __launch_bounds__(256) void k_fro_norm(const double2 *__restrict__ A, long long nn, double *__restrict__ nrm) {
+  __shared__ double red[256];
+  const double2 *a = A + (long long)blockIdx.x * nn;
+  double s = 0.0;
+  for (long long i = threadIdx.x; i < nn; i += 256) s += a[i].x * a[i].x + a[i].y * a[i].y;
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) nrm[blockIdx.x] = sqrt(red[0]);
+}
+
+// Y = A / nrm, Z = I (batch element blockIdx.y)
+__global__ void k_ns_init(const double2 *__restrict__ A, const double *__restrict__ nrm, double2 *__restrict__ Y,
+                          double2 *__restrict__ Z, int n) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long nn = (long long)n * n;
+  if (idx >= nn) return;
+  const long long o = (long long)blockIdx.y * nn + idx;
+  const double f = 1.0 / nrm[blockIdx.y];
+  const double2 a = A[o];
+  Y[o] = mkc(a.x * f, a.y * f);
+  Z[o] = mkc(idx / n == idx % n ? 1.0 : 0.0, 0.0);
+}
+
+// G <- 1.5 I - 0.5 G
+__global__ void k_ns_step(double2 *__restrict__ G, int n) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long nn = (long long)n * n;
+  if (idx >= nn) return;
+  const long long o = (long long)blockIdx.y * nn + idx;
+  double2 g = G[o];
+  g.x = (idx / n == idx % n ? 1.5 : 0.0) - 0.5 * g.x;
+  g.y = -0.5 * g.y;
+  G[o] = g;
+}
+
+// out = sqrt(nrm) Y
+__global__ void k_ns_finish(const double2 *__restrict__ Y, const double *__restrict__ nrm, double2 *__restrict__ out, int n) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long nn = (long long)n * n;
+  if (idx >= nn) return;
+  const long long o = (long long)blockIdx.y * nn + idx;
+  const double f = sqrt(nrm[blockIdx.y]);
+  out[o] = mkc(Y[o].x * f, Y[o].y * f);
+}
+
+#define NS_ITERS 36
+
 static ZGemm mk(int m, int n, int k, int opa, const double2 *A, long long lda, long long sa, int opb, const double2 *B,
                 long long ldb, long long sb, double2 *Cm, long long ldc, long long sc, double2 alpha, int batch) {
   ZGemm g;
@@ -72,19 +135,64 @@ static ZGemm mk(int m, int n, int k, int opa, const double2 *A, long long lda, l
   return g;
 }
 
-int run_screen(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_out, int *info) {
-  return run_screen_n(c, iq, chi, V, Wc_out, info, c->d.n_freq);
+// Hermitian square roots of the `batch` HPD matrices A[b] (n x n, contiguous)
+// into out[b], by the coupled Newton-Schulz iteration; w: 4 batch n^2 + 64
+// doubles of workspace (Y, Z, G and a second Y/Z pair; norms at the end).
+static int zsqrt_hpd_batched(hipStream_t s, const double2 *A, int n, int batch, double2 *out, double2 *w) {
+  const long long nn = (long long)n * n;
+  double2 *Y = w, *Z = w + batch * nn, *G = w + 2 * batch * nn, *Y2 = w + 3 * batch * nn, *Z2 = out;
+  double *nrm = (double *)(w + 4 * batch * nn);
+  const double2 one = mkc(1.0, 0.0);
+  hipLaunchKernelGGL(k_fro_norm, dim3(batch), dim3(256), 0, s, A, nn, nrm);
+  dim3 eg((unsigned)((nn + 255) / 256), batch);
+  hipLaunchKernelGGL(k_ns_init, eg, dim3(256), 0, s, A, nrm, Y, Z, n);
+  for (int it = 0; it < NS_ITERS; ++it) {
+    LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, Z, n, nn, OP_N, Y, n, nn, G, n, nn, one, batch)));
+    hipLaunchKernelGGL(k_ns_step, eg, dim3(256), 0, s, G, n);
+    LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, Y, n, nn, OP_N, G, n, nn, Y2, n, nn, one, batch)));
+    LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, G, n, nn, OP_N, Z, n, nn, Z2, n, nn, one, batch)));
+    std::swap(Y, Y2);
+    std::swap(Z, Z2);
+  }
+  // after an even number of steps Z is back in the workspace and `out` is free
+  static_assert(NS_ITERS % 2 == 0, "the last Z must not sit in out");
+  hipLaunchKernelGGL(k_ns_finish, eg, dim3(256), 0, s, Y, nrm, out, n);
+  return lrigw_launch_check("zsqrt_hpd");
+}
+
+// c->d_cut[0] = L^{-1} S S_c (= T^H), with L the Cholesky factor of V in c->d_LV
+// and its diagonal-block inverses in c->d_dinv (batch element 0)
+static int cut_factor(lrigw_ctx *c, const void *V, const void *Vcut) {
+  const int n = c->d.n_aux;
+  const long long nn = (long long)n * n;
+  hipStream_t s = c->stream;
+  // T^H, [V, V^cut], their roots, the root iteration's workspace (8 n^2 + norms)
+  if (!c->d_cut) LRIGW_HIP_TRY(hipMalloc(&c->d_cut, (size_t)(13 * nn + 64) * sizeof(double2)));
+  double2 *A = c->d_cut + nn, *R = A + 2 * nn, *w = R + 2 * nn;   // [V, V^cut], their roots, workspace
+  LRIGW_HIP_TRY(hipMemcpyAsync(A, V, nn * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  LRIGW_HIP_TRY(hipMemcpyAsync(A + nn, Vcut, nn * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  LRIGW_TRY(zsqrt_hpd_batched(s, A, n, 2, R, w));
+  // S S_c, then L^{-1} (S S_c)
+  LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, R, n, 0, OP_N, R + nn, n, 0, c->d_cut, n, 0, mkc(1.0, 0.0), 1)));
+  return ztrsm_left_lower(s, c->d_LV, n, nn, c->d_dinv, c->d_cut, n, nn, n, n, 1);
+}
+
+int run_screen(lrigw_ctx *c, int iq, const void *chi, const void *V, const void *Vcut, void *Wc_out, int *info) {
+  return run_screen_n(c, iq, chi, V, Vcut, Wc_out, info, c->d.n_freq);
 }
 
 // the first nw <= N_w planes of chi (the workspaces hold N_w)
-int run_screen_n(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_out, int *info, int nw) {
+int run_screen_n(lrigw_ctx *c, int iq, const void *chi, const void *V, const void *Vcut, void *Wc_out, int *info, int nw) {
   const Dims &d = c->d;
   const int n = d.n_aux;
   const long long nn = (long long)n * n;
   hipStream_t s = c->stream;
+  const bool cut = Vcut != nullptr && Vcut != V;
   // L_V
   LRIGW_HIP_TRY(hipMemcpyAsync(c->d_LV, V, nn * sizeof(double2), hipMemcpyDeviceToDevice, s));
   LRIGW_TRY(zpotrf_batched(s, c->d_LV, n, n, nn, 1, c->d_dinv, c->d_info + 1));
+  // T^H = L^{-1} V^{1/2} V^cut^{1/2} (before the dielectric Cholesky reuses d_dinv)
+  if (cut) LRIGW_TRY(cut_factor(c, V, Vcut));
   // chi in FP64
   const double2 *chiz;
   if (c->precision == LRIGW_FP64) {
@@ -109,9 +217,12 @@ int run_screen_n(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_
   // D <- E^{-1} D
   LRIGW_TRY(ztrsm_left_lower(s, c->d_s2, n, nn, c->d_dinv, c->d_s1, n, nn, n, n, nw));
   LRIGW_TRY(ztrsm_left_upper_conj(s, c->d_s2, n, nn, c->d_dinv, c->d_s1, n, nn, n, n, nw));
-  // W = -L (E^{-1} D) L^H (Hermitian: lower tiles; k_hermitize mirrors them)
-  LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_s1, n, nn, OP_C, c->d_LV, n, 0, c->d_s0, n, nn, one, nw)));
-  ZGemm gw = mk(n, n, n, OP_N, c->d_LV, n, 0, OP_N, c->d_s0, n, nn, c->d_s1, n, nn, mone, nw);
+  // W = -L (E^{-1} D) L^H (Hermitian: lower tiles; k_hermitize mirrors them);
+  // with V^cut, T = (T^H)^H in place of L
+  if (cut) LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_s1, n, nn, OP_N, c->d_cut, n, 0, c->d_s0, n, nn, one, nw)));
+  else LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_s1, n, nn, OP_C, c->d_LV, n, 0, c->d_s0, n, nn, one, nw)));
+  ZGemm gw = cut ? mk(n, n, n, OP_C, c->d_cut, n, 0, OP_N, c->d_s0, n, nn, c->d_s1, n, nn, mone, nw)
+                 : mk(n, n, n, OP_N, c->d_LV, n, 0, OP_N, c->d_s0, n, nn, c->d_s1, n, nn, mone, nw);
   gw.lower_only = 1;
   LRIGW_TRY(zgemm(s, gw));
   if (c->precision == LRIGW_FP64)
@@ -168,7 +279,7 @@ int run_gamma_average(lrigw_ctx *c, const double *eig, const void *V0, bool real
   for (int g = 0; g < c->n_gdir && rc == LRIGW_OK; ++g) {
     c->gamma_p = (const double2 *)c->gdir_p + g * per;
     rc = real_axis ? run_chi0_real(c, 0, c->d_M, eig, 1, chi) : run_chi0(c, 0, c->d_M, eig, 1, chi);
-    if (rc == LRIGW_OK) rc = run_screen_n(c, 0, chi, V0, tmp, nullptr, nw);
+    if (rc == LRIGW_OK) rc = run_screen_n(c, 0, chi, V0, nullptr, tmp, nullptr, nw);
     if (rc != LRIGW_OK) break;
     if (c->precision == LRIGW_FP64)
       hipLaunchKernelGGL(k_waccum<double2>, dim3(nb), dim3(256), 0, c->stream, (double2 *)out, (const double2 *)tmp, n,

@@ -115,6 +115,7 @@ struct lrigw_ctx {
   int sig_var = 0;               // split-BF16 Sigma^c kernel variant
   void *d_X = nullptr;           // [N_w][N_k*n_qp*n_bands] pair weights (T)
   double2 *d_LV = nullptr;       // [N][N]
+  double2 *d_cut = nullptr;      // truncated-Coulomb screening: L^{-1} V^{1/2} V^cut^{1/2} and workspace (13 N^2)
   double2 *d_s0 = nullptr, *d_s1 = nullptr, *d_s2 = nullptr, *d_s3 = nullptr;  // [N_w][N][N]
   double2 *d_dinv = nullptr;     // inverses of 64x64 diagonal Cholesky blocks, [N_w][zdinv_stride(N)]
   int *d_info = nullptr;         // device status words
@@ -225,8 +226,9 @@ int surrogate_prepare(lrigw_surrogate *sg);
 int run_chi0_surrogate(lrigw_ctx *c, lrigw_surrogate *sg, int iq, const void *M, const double *eig, int apply_gamma,
                        double threshold, void *chi_out);
 int run_gamma_prepare(lrigw_ctx *c, const void *Vcut0, const void *p, double omega_cell);
-int run_screen(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_out, int *info);
-int run_screen_n(lrigw_ctx *c, int iq, const void *chi, const void *V, void *Wc_out, int *info, int nw);
+// Vcut: the truncated Coulomb matrix of the numerator (nullptr or V: V itself)
+int run_screen(lrigw_ctx *c, int iq, const void *chi, const void *V, const void *Vcut, void *Wc_out, int *info);
+int run_screen_n(lrigw_ctx *c, int iq, const void *chi, const void *V, const void *Vcut, void *Wc_out, int *info, int nw);
 int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const double *eig, void *sigma_acc);
 int run_pair_weights(lrigw_ctx *c, const void *x, const void *Wc, int nw, double *X);
 int sigma_res_prepare_real(lrigw_ctx *c, int n_r);
@@ -239,8 +241,8 @@ int cd_qp_linear(lrigw_ctx *c, const double *S, const double *e_static, double d
 int cd_count_nan(lrigw_ctx *c, const double *v, int n, int *out);
 int run_pade_eval(lrigw_ctx *c, const void *sigma, int n_par, int n_e, const double *E, void *out);
 int run_gamma_average(lrigw_ctx *c, const double *eig, const void *V0, bool real_axis, void *chi, void *tmp, void *out);
-int run_cd_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *p,
-                double omega_cell, int n_e, const double *E, double *sigma_e, int *n_bad);
+int run_cd_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *Vcut,
+                const void *p, double omega_cell, int n_e, const double *E, double *sigma_e, int *n_bad);
 int run_sigma_x(lrigw_ctx *c, int iq, const void *xo, const void *V, double *sigma_x);
 int run_lri_fit(lrigw_ctx *c, int batch, int n, int n_keep, int nrhs, const double *V, const double *T, double scale,
                 double *C, int *info);
@@ -250,8 +252,9 @@ int fit_scratch_prepare(int dev);
 size_t fit_scratch_bytes(int batch, int n, int nrhs);
 int run_lri_fit_noalloc(lrigw_ctx *c, int batch, int n, int n_keep, int nrhs, const double *V, const double *T,
                         double scale, double *C, int *info);
-int run_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *p, double omega_cell,
-             const double *e_static, int n_par, int q_first, int q_last, void *sigma, double *e_qp, double *z, int *info);
+int run_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *Vcut,
+             const void *p, double omega_cell, const double *e_static, int n_par, int q_first, int q_last, void *sigma,
+             double *e_qp, double *z, int *info);
 int driver_buffers(lrigw_ctx *c);
 int run_qp(lrigw_ctx *c, const void *sigma, const double *eps_qp, const double *e_static, int n_par, double *e_qp,
            double *z, int *info);

@@ -59,7 +59,7 @@ class LrigwSizes(ctypes.Structure):
 
 class LrigwBatchCell(ctypes.Structure):
     _fields_ = [("ctx", ctypes.c_void_p), ("H", ctypes.c_void_p), ("evec", ctypes.c_void_p), ("eig", ctypes.c_void_p),
-                ("V", ctypes.c_void_p), ("p", ctypes.c_void_p), ("omega_cell", ctypes.c_double),
+                ("V", ctypes.c_void_p), ("Vcut", ctypes.c_void_p), ("p", ctypes.c_void_p), ("omega_cell", ctypes.c_double),
                 ("e_static", ctypes.c_void_p), ("n_par", ctypes.c_int), ("sigma", ctypes.c_void_p),
                 ("e_qp", ctypes.c_void_p), ("z", ctypes.c_void_p)]
 
@@ -100,7 +100,7 @@ def load(path: Optional[str] = None):
         "lrigw_build_M": (i, [vp, i, i, vp, vp, vp]),
         "lrigw_chi0": (i, [vp, i, vp, vp, i, vp]),
         "lrigw_gamma_prepare": (i, [vp, vp, vp, d]),
-        "lrigw_screen": (i, [vp, i, vp, vp, vp, ip]),
+        "lrigw_screen": (i, [vp, i, vp, vp, vp, vp, ip]),
         "lrigw_sigma_c": (i, [vp, i, vp, vp, vp, vp]),
         "lrigw_sigma_x": (i, [vp, i, vp, vp, vp]),
         "lrigw_sigma_x_pass": (i, [vp, vp, vp, vp, vp]),
@@ -111,11 +111,11 @@ def load(path: Optional[str] = None):
         "lrigw_set_gamma_directions": (i, [vp, i, vp, dp]),
         "lrigw_pade_eval": (i, [vp, vp, i, i, vp, vp]),
         "lrigw_chi0_real": (i, [vp, i, vp, vp, i, vp]),
-        "lrigw_screen_real": (i, [vp, i, vp, vp, vp, ip]),
+        "lrigw_screen_real": (i, [vp, i, vp, vp, vp, vp, ip]),
         "lrigw_sigma_cd": (i, [vp, i, vp, vp, vp, vp, i, vp, vp]),
-        "lrigw_sigma_cd_pass": (i, [vp, vp, vp, vp, vp, vp, d, i, vp, vp, ip]),
-        "lrigw_g0w0_cd": (i, [vp, vp, vp, vp, vp, vp, d, vp, d, vp, vp, vp, ip]),
-        "lrigw_g0w0": (i, [vp, vp, vp, vp, vp, vp, d, vp, i, i, i, vp, vp, vp, ip]),
+        "lrigw_sigma_cd_pass": (i, [vp, vp, vp, vp, vp, vp, vp, d, i, vp, vp, ip]),
+        "lrigw_g0w0_cd": (i, [vp, vp, vp, vp, vp, vp, vp, d, vp, d, vp, vp, vp, ip]),
+        "lrigw_g0w0": (i, [vp, vp, vp, vp, vp, vp, vp, d, vp, i, i, i, vp, vp, vp, ip]),
         "lrigw_set_timing": (i, [vp, i]),
         "lrigw_stage_ms": (d, [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_longlong)]),
         "lrigw_reset_timing": (None, [vp]),
@@ -257,9 +257,9 @@ class Context:
     def gamma_prepare(self, Vcut0, p, omega_cell):
         self._check(self.lib.lrigw_gamma_prepare(self.h, _ptr(Vcut0), _ptr(p), float(omega_cell)), "lrigw_gamma_prepare")
 
-    def screen(self, iq, chi, V, Wc_out):
+    def screen(self, iq, chi, V, Wc_out, Vcut=None):
         info = ctypes.c_int(0)
-        rc = self.lib.lrigw_screen(self.h, int(iq), _ptr(chi), _ptr(V), _ptr(Wc_out), ctypes.byref(info))
+        rc = self.lib.lrigw_screen(self.h, int(iq), _ptr(chi), _ptr(V), _ptr(Vcut), _ptr(Wc_out), ctypes.byref(info))
         if rc < 0:
             e = LrigwError(rc, "lrigw_screen")
             e.info = info.value
@@ -337,9 +337,10 @@ class Context:
                                              _ptr(chi_out)), "lrigw_chi0_real")
         return chi_out
 
-    def screen_real(self, iq, chi, V, Wc_out):
+    def screen_real(self, iq, chi, V, Wc_out, Vcut=None):
         info = ctypes.c_int(0)
-        rc = self.lib.lrigw_screen_real(self.h, int(iq), _ptr(chi), _ptr(V), _ptr(Wc_out), ctypes.byref(info))
+        rc = self.lib.lrigw_screen_real(self.h, int(iq), _ptr(chi), _ptr(V), _ptr(Vcut), _ptr(Wc_out),
+                                        ctypes.byref(info))
         if rc < 0:
             e = LrigwError(rc, "lrigw_screen_real")
             e.info = info.value
@@ -352,17 +353,18 @@ class Context:
                                             _ptr(E), _ptr(sigma_e)), "lrigw_sigma_cd")
         return sigma_e
 
-    def sigma_cd_pass(self, H, evec, eig, V, p, omega_cell, E, sigma_e):
+    def sigma_cd_pass(self, H, evec, eig, V, p, omega_cell, E, sigma_e, Vcut=None):
         bad = ctypes.c_int(0)
-        rc = self.lib.lrigw_sigma_cd_pass(self.h, _ptr(H), _ptr(evec), _ptr(eig), _ptr(V), _ptr(p), float(omega_cell),
-                                          int(E.shape[0]), _ptr(E), _ptr(sigma_e), ctypes.byref(bad))
+        rc = self.lib.lrigw_sigma_cd_pass(self.h, _ptr(H), _ptr(evec), _ptr(eig), _ptr(V), _ptr(Vcut), _ptr(p),
+                                          float(omega_cell), int(E.shape[0]), _ptr(E), _ptr(sigma_e), ctypes.byref(bad))
         self._check(rc, "lrigw_sigma_cd_pass", allow_warn=True)
         return rc, bad.value
 
-    def g0w0_cd(self, H, evec, eig, V, p, omega_cell, e_static, delta, e_qp, z, sigma3=None):
+    def g0w0_cd(self, H, evec, eig, V, p, omega_cell, e_static, delta, e_qp, z, sigma3=None, Vcut=None):
         bad = ctypes.c_int(0)
-        rc = self.lib.lrigw_g0w0_cd(self.h, _ptr(H), _ptr(evec), _ptr(eig), _ptr(V), _ptr(p), float(omega_cell),
-                                    _ptr(e_static), float(delta), _ptr(sigma3), _ptr(e_qp), _ptr(z), ctypes.byref(bad))
+        rc = self.lib.lrigw_g0w0_cd(self.h, _ptr(H), _ptr(evec), _ptr(eig), _ptr(V), _ptr(Vcut), _ptr(p),
+                                    float(omega_cell), _ptr(e_static), float(delta), _ptr(sigma3), _ptr(e_qp), _ptr(z),
+                                    ctypes.byref(bad))
         self._check(rc, "lrigw_g0w0_cd", allow_warn=True)
         return rc, bad.value
 
@@ -372,10 +374,10 @@ class Context:
                     "lrigw_pade_eval")
         return out
 
-    def g0w0(self, H, evec, eig, V, p, omega_cell, e_static, n_par, sigma, e_qp, z, q_first=0, q_last=None):
+    def g0w0(self, H, evec, eig, V, p, omega_cell, e_static, n_par, sigma, e_qp, z, q_first=0, q_last=None, Vcut=None):
         info = ctypes.c_int(0)
         q_last = int(self.sizes.n_k) if q_last is None else q_last
-        rc = self.lib.lrigw_g0w0(self.h, _ptr(H), _ptr(evec), _ptr(eig), _ptr(V), _ptr(p), float(omega_cell),
+        rc = self.lib.lrigw_g0w0(self.h, _ptr(H), _ptr(evec), _ptr(eig), _ptr(V), _ptr(Vcut), _ptr(p), float(omega_cell),
                                  _ptr(e_static), int(n_par), int(q_first), int(q_last), _ptr(sigma), _ptr(e_qp), _ptr(z),
                                  ctypes.byref(info))
         self._check(rc, "lrigw_g0w0", allow_warn=True)
@@ -542,7 +544,7 @@ class Batch:
         arr = (LrigwBatchCell * len(cells))()
         for i, c in enumerate(cells):
             arr[i] = LrigwBatchCell(c["ctx"].h.value, _ptr(c["H"]), _ptr(c["evec"]), _ptr(c["eig"]), _ptr(c["V"]),
-                                    _ptr(c.get("p")), float(c.get("omega_cell", 0.0)), _ptr(c.get("e_static")),
+                                    _ptr(c.get("Vcut")), _ptr(c.get("p")), float(c.get("omega_cell", 0.0)), _ptr(c.get("e_static")),
                                     int(c.get("n_par", 16)), _ptr(c["sigma"]), _ptr(c["e_qp"]), _ptr(c["z"]))
         h = ctypes.c_void_p()
         rc = self.lib.lrigw_batch_create(ctypes.byref(h), len(cells), arr, int(bool(autotune)),
@@ -589,7 +591,7 @@ def device_inputs(sysm, device="cuda"):
     """Copy the arrays of a synthetic cell to the device (torch tensors)."""
     import torch
     t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt)
-    return dict(
+    out = dict(
         eig=t(sysm.eig, torch.float64),
         evec=t(sysm.evec, torch.complex128),
         lri=t(sysm.lri, torch.float64),
@@ -597,3 +599,6 @@ def device_inputs(sysm, device="cuda"):
         p=t(sysm.p, torch.complex128),
         e_static=t(sysm.e_static, torch.float64),
     )
+    if getattr(sysm, "Vcut", None) is not None:
+        out["Vcut"] = t(sysm.Vcut, torch.complex128)
+    return out

@@ -327,6 +327,12 @@ def project_momentum(p3, qhat) -> np.ndarray:
     return np.einsum("c...,dc->d...", p3, np.asarray(qhat, dtype=np.float64))
 
 
+def training_cells(config: int, n: int, **kw) -> List[System]:
+    """n further seeded cells of workload `config`'s (first) shape, cells
+    1..n of the seed convention (seed = 1000 * config + cell)."""
+    return [make_system(CONFIGS[config][0], 1000 * config + 1 + i, **kw) for i in range(n)]
+
+
 def make_config(config: int, cell: int = 0, **kw) -> System:
     """Cell `cell` of workload `config`; seed = 1000 * config + cell."""
     return make_system(CONFIGS[config][cell], 1000 * config + cell, **kw)
