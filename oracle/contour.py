@@ -39,6 +39,19 @@ Readings (the paper gives no scheme):
  * QP energies from these values are linearised about e_n:
    E = e_n + Z (Sigma^c(e_n) + e_n^static), with Z = 1/(1 - dSigma^c/dE) from
    the central difference at e_n -+ delta.
+ * Every state (residues above Delta_min): W^c is taken at the complex
+   frequencies w_r + i eta of the real grid (the response weight
+   2D/(D^2 - (w + i eta)^2) is complex, chi~ and eps~ are not Hermitian, the
+   screening is the general inverse).  Only Re Sigma^c enters the QP
+   equation, and Re X(w + i eta) is even in w (X(conj z) = conj X(z), W^c even
+   in z), so the same reflection applies at w = 0; the imaginary-axis term is
+   unchanged and its subtracted constant is Re X(i eta), whose closed-form
+   integral is added back exactly.  eta is the broadening of the time-ordered
+   W^c's poles: with a finite k grid the RPA spectrum is discrete, and eta
+   smooths Sigma^c(E) over it; the grid step must resolve eta.
+ * QP energies for every state: Newton steps on E - e_n - e_static - Re
+   Sigma^c(E) from E_0 = e_n, the slope from the central difference at
+   E -+ delta (the first step is the linearised energy).
 """
 from __future__ import annotations
 

@@ -96,20 +96,22 @@ class Oracle:
                                     self.sys.n_k), X
 
     # ---- real energies by contour deformation ---------------------------
-    def chi0_real(self, q, omega_r, B=None):
-        """chi~(q, w) at real w below the smallest transition energy."""
+    def chi0_real(self, q, omega_r, B=None, eta=0.0):
+        """chi~(q, w) at real w below the smallest transition energy, or at
+        w + i eta at any w (eta > 0)."""
         B = self.B(q) if B is None else B
-        return response.chi0_trs(B, self.sys.eig, self.kpq, q, self.sys.n_occ, omega_r, real_axis=True)
+        return response.chi0_trs(B, self.sys.eig, self.kpq, q, self.sys.n_occ, omega_r, real_axis=True, eta=eta)
 
-    def wc_real(self, q, omega_r, chi=None, B=None, gamma=True):
+    def wc_real(self, q, omega_r, chi=None, B=None, gamma=True, eta=0.0):
         s = self.sys
         if q == 0 and gamma:
             B = self.B(0) if B is None else B
             if self.gamma_dirs is not None:
                 return screening.screen_gamma_average(B, s.eig, s.n_occ, *self.gamma_dirs, s.omega_cell, s.V[0],
-                                                      omega_r, real_axis=True)
-            return screening.screen_gamma(B, s.eig, s.n_occ, s.p, s.omega_cell, s.V[0], omega_r, real_axis=True)[2]
-        chi = self.chi0_real(q, omega_r, B) if chi is None else chi
+                                                      omega_r, real_axis=True, eta=eta)
+            return screening.screen_gamma(B, s.eig, s.n_occ, s.p, s.omega_cell, s.V[0], omega_r, real_axis=True,
+                                          eta=eta)[2]
+        chi = self.chi0_real(q, omega_r, B, eta=eta) if chi is None else chi
         return screening.screen(chi, s.V[q], self._vcut(q))[1]
 
     def sigma_cd_q(self, q, Wc, Wr, h, E, ks=None):
@@ -121,16 +123,33 @@ class Oracle:
         return contour.sigma_cd_q(Xi, Xr, self.sys.eig, self.kmq[ks], q, self.sys.n_occ, self.omega, self.weight,
                                   h, E, self.sys.n_k)
 
-    def sigma_cd(self, n_r, omega_max, E, ks=None, gamma=True):
-        """Sigma^c_n(k, E) summed over q at the real energies E."""
+    def sigma_cd(self, n_r, omega_max, E, ks=None, gamma=True, eta=0.0):
+        """Sigma^c_n(k, E) summed over q at the real energies E (the real part,
+        with the residues of the broadened W^c at w + i eta when eta > 0)."""
         omega_r, h = contour.real_grid(n_r, omega_max)
         out = np.zeros(E.shape)
         for q in range(self.sys.n_k):
             B = self.B(q)
             Wc = self.wc(q, B=B, gamma=gamma)
-            Wr = self.wc_real(q, omega_r, B=B, gamma=gamma)
+            Wr = self.wc_real(q, omega_r, B=B, gamma=gamma, eta=eta)
             out += self.sigma_cd_q(q, Wc, Wr, h, E, ks)
         return out
+
+    def qp_cd(self, n_r, omega_max, eta, n_iter, delta=0.002, ks=None, gamma=True):
+        """Quasiparticle energies from contour deformation: Newton steps on
+        f(E) = E - e_n - e_static_n - Re Sigma^c(E) from E_0 = e_n, the slope
+        from Sigma^c at E -+ delta (the first step is the linearised QP
+        energy).  Returns (E [N_k][N_qp], Z, Sigma^c at the last E)."""
+        s = self.sys
+        ks = list(range(s.n_k)) if ks is None else list(ks)
+        eps = s.eig[ks][:, self.qp]
+        est = s.e_static[ks]
+        E = eps.copy()
+        for _ in range(n_iter):
+            S3 = self.sigma_cd(n_r, omega_max, np.stack([E - delta, E, E + delta]), ks, gamma, eta)
+            Z = 1.0 / (1.0 - (S3[2] - S3[0]) / (2.0 * delta))
+            E = E + Z * (eps + est + S3[1] - E)
+        return E, Z, S3[1]
 
     # ---- whole path ---------------------------------------------------
     def run(self, ks=None, gamma=True, keep=False):

@@ -31,22 +31,38 @@ import numpy as np
 SPIN = 2.0
 
 
-def chi0_trs(B, eig, kpq, q, n_occ, omega, s=SPIN, real_axis=False):
+def weight(delta, w, real_axis=False, eta=0.0):
+    """The transition weight 2D/(D^2 - z^2) at z = i w (imaginary axis:
+    2D/(D^2 + w^2)), at real z = w (real_axis), or at z = w + i eta
+    (real_axis, eta > 0: complex)."""
+    if not real_axis:
+        return 2.0 * delta / (delta * delta + w * w)
+    if eta == 0.0:
+        return 2.0 * delta / (delta * delta - w * w)
+    z = w + 1j * eta
+    return 2.0 * delta / (delta * delta - z * z)
+
+
+def chi0_trs(B, eig, kpq, q, n_occ, omega, s=SPIN, real_axis=False, eta=0.0):
     """B: [N_k][N_aux][N_occ][N_unocc] = C^mu_{ia}(k,k+q); returns [N_w][N_aux][N_aux].
 
     real_axis: the frequencies are real, w -> -i w in the denominators, so the
-    weight is 2D/(D^2 - w^2); meant for 0 <= w < min D, where it stays finite
-    and positive (the response below the first transition)."""
+    weight is 2D/(D^2 - w^2); with eta = 0 meant for 0 <= w < min D, where it
+    stays finite and positive (the response below the first transition).
+    eta > 0: the response at the complex frequencies w + i eta, at any w: the
+    complex weight makes it a sum of two Hermitian parts, Re and i Im of the
+    weight, not Hermitian itself (the broadened response above the first
+    transition)."""
     n_k = B.shape[0]
     n_aux = B.shape[1]
-    sgn = -1.0 if real_axis else 1.0
+    cplx = real_axis and eta != 0.0
     out = np.zeros((len(omega), n_aux, n_aux), dtype=np.complex128)
     for k in range(n_k):
         kq = kpq[k, q]
         delta = eig[kq][n_occ:][None, :] - eig[k][:n_occ][:, None]     # [occ][unocc]
         Bk = B[k].reshape(n_aux, -1)
         for iw, w in enumerate(omega):
-            wt = (2.0 * delta / (delta * delta + sgn * w * w)).reshape(-1)
+            wt = weight(delta, w, real_axis, eta).reshape(-1)
             out[iw] += (Bk * wt[None, :]) @ Bk.conj().T
     return -(s / n_k) * out
 

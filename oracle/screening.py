@@ -52,6 +52,7 @@ from __future__ import annotations
 import numpy as np
 
 from .response import SPIN
+from .response import weight as response_weight
 
 
 def sqrt_hpd(V):
@@ -94,15 +95,14 @@ def coulomb_eigenbasis(Vcut0):
     return v, X
 
 
-def screen_gamma(B0, eig, n_occ, p, omega_cell, Vcut0, omega, s=SPIN, real_axis=False):
+def screen_gamma(B0, eig, n_occ, p, omega_cell, Vcut0, omega, s=SPIN, real_axis=False, eta=0.0):
     """q = 0 dielectric matrix in the Coulomb eigenbasis and W^c(0).
 
     B0: [N_k][N_aux][N_occ][N_unocc] = C^mu_{ia}(k,k); p: [N_k][N_occ][N_unocc].
     real_axis: real frequencies below the smallest transition, weight
-    2D/(D^2 - w^2) (as in `response.chi0_trs`).
+    2D/(D^2 - w^2); with eta > 0 at w + i eta (as in `response.chi0_trs`).
     Returns (eps~_lambda, eps~_mu, W^c) per frequency.
     """
-    sgn = -1.0 if real_axis else 1.0
     n_k, n_aux = B0.shape[0], B0.shape[1]
     v, X = coulomb_eigenbasis(Vcut0)
     if v[-1] <= 0.0:
@@ -115,7 +115,7 @@ def screen_gamma(B0, eig, n_occ, p, omega_cell, Vcut0, omega, s=SPIN, real_axis=
         Y = sv[:, None] * (X.conj().T @ B0[k].reshape(n_aux, -1))          # [lam][ia]
         Y[0, :] = np.sqrt(4.0 * np.pi / omega_cell) * p[k].reshape(-1) / delta
         for iw, w in enumerate(omega):
-            wt = 2.0 * delta / (delta * delta + sgn * w * w)
+            wt = response_weight(delta, w, real_axis, eta)
             eps_l[iw] += (s / n_k) * (Y * wt[None, :]) @ Y.conj().T
     eps_mu = np.empty_like(eps_l)
     Wc = np.empty_like(eps_l)
@@ -125,11 +125,11 @@ def screen_gamma(B0, eig, n_occ, p, omega_cell, Vcut0, omega, s=SPIN, real_axis=
     return eps_l, eps_mu, Wc
 
 
-def screen_gamma_average(B0, eig, n_occ, p_dirs, weights, omega_cell, Vcut0, omega, s=SPIN, real_axis=False):
+def screen_gamma_average(B0, eig, n_occ, p_dirs, weights, omega_cell, Vcut0, omega, s=SPIN, real_axis=False, eta=0.0):
     """W^c(q -> 0) averaged over directions q_hat_d: sum_d w_d W^c(q_hat_d), each
     from `screen_gamma` with p_ia . q_hat_d (p_dirs: [n_dir][N_k][N_occ][N_unocc]).
     The paper notes that head and wings depend on the direction of approach
     and gives no averaging scheme; this weighted mean is the reading."""
-    return sum(w * screen_gamma(B0, eig, n_occ, pd, omega_cell, Vcut0, omega, s=s, real_axis=real_axis)[2]
+    return sum(w * screen_gamma(B0, eig, n_occ, pd, omega_cell, Vcut0, omega, s=s, real_axis=real_axis, eta=eta)[2]
                for pd, w in zip(p_dirs, weights))
 

@@ -327,6 +327,29 @@ def project_momentum(p3, qhat) -> np.ndarray:
     return np.einsum("c...,dc->d...", p3, np.asarray(qhat, dtype=np.float64))
 
 
+def eigenvalues_of(spec: CellSpec, seed: int) -> np.ndarray:
+    """The eigenvalues make_system(spec, seed) draws, [N_k][N_bands], from the
+    same generator stream (without drawing the other arrays)."""
+    rng_eig = np.random.default_rng(seed).spawn(6)[0]
+    kint = _kint(spec.nk)
+    minus = _kidx(-kint, spec.nk)
+    n_unocc = spec.n_bands - spec.n_occ
+    eig = np.empty((spec.n_k, spec.n_bands))
+    for k in range(spec.n_k):
+        if minus[k] < k:
+            eig[k] = eig[minus[k]]
+            continue
+        occ = np.sort(rng_eig.uniform(-0.8, -0.05, spec.n_occ))
+        unocc = np.sort(rng_eig.uniform(0.05, 2.0, n_unocc))
+        eig[k] = np.concatenate([occ, unocc])
+    return eig
+
+
+def window_of(eig: np.ndarray, n_occ: int) -> tuple:
+    """transition_window from eigenvalues alone."""
+    return float(eig[:, n_occ:].min() - eig[:, :n_occ].max()), float(eig[:, n_occ:].max() - eig[:, :n_occ].min())
+
+
 def training_cells(config: int, n: int, **kw) -> List[System]:
     """n further seeded cells of workload `config`'s (first) shape, cells
     1..n of the seed convention (seed = 1000 * config + cell)."""

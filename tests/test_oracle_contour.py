@@ -192,3 +192,88 @@ def test_linearised_qp():
     E, Z = contour.qp_linear(S(eps - 0.01), S(eps), S(eps + 0.01), 0.01, eps, np.array([0.1, 0.0]))
     assert np.allclose(Z, 1.0 / 1.25)
     assert np.allclose(E - eps, S(E) + np.array([0.1, 0.0]))
+
+
+def _exact_broadened(o, E, eta, gamma):
+    """Re Sigma^c of contour deformation with the residues of W^c taken at
+    w + i eta, in closed form from the pole decomposition: the eta = 0 pole
+    sum plus sum_m theta_m Re[X_nm(|z| + i eta) - X_nm(|z|)], with
+    X(w) = -sum_s |x^T v_s|^2 / (Omega_s^2 - w^2) for any complex w (the
+    imaginary-axis integral does not depend on eta)."""
+    s = o.sys
+    out = _exact_sigma(o, E, gamma).real
+    occ = np.arange(s.n_bands) < s.n_occ
+    for q in range(s.n_k):
+        Om, v = _poles(o, q, gamma)
+        x = o.x(q)
+        c2 = np.abs(np.einsum("kanm,as->knms", x, v)) ** 2
+        for k in range(s.n_k):
+            em = s.eig[o.kmq[k, q]]
+            for n in range(x.shape[2]):
+                z = E[..., k, n][..., None] - em                         # [..., m]
+                th = contour.residue_sign(z, occ)
+                w = np.abs(z)[..., None]
+                Xb = -np.sum(c2[k, n][None] / (Om ** 2 - (w + 1j * eta) ** 2), -1)
+                X0 = -np.sum(c2[k, n][None] / (Om ** 2 - w ** 2), -1)
+                out[..., k, n] += np.sum(th * (Xb.real - X0), -1) / s.n_k
+    return out
+
+
+@pytest.mark.parametrize("gamma", [False, True])
+def test_broadened_screening_is_the_pole_form(gamma):
+    """W^c at w + i eta from the complex-weight response and the general
+    (non-Hermitian) screening equals the analytic pole form
+    -sum_s v_s v_s^H / (Omega_s^2 - (w + i eta)^2) above the first transition
+    as well as below it."""
+    s = _tiny(8)
+    o = Oracle(s)
+    omr = np.linspace(0.0, 3.0, 13)
+    eta = 0.05
+    for q in (0, 1):
+        Om, v = _poles(o, q, gamma)
+        W = o.wc_real(q, omr, gamma=gamma, eta=eta)
+        z = omr + 1j * eta
+        ref = -np.einsum("as,ws,bs->wab", v, 1.0 / (Om[None, :] ** 2 - z[:, None] ** 2), v.conj())
+        assert np.max(np.abs(W - ref)) < 1e-11 * np.max(np.abs(ref)), q
+        assert np.max(np.abs(W[3] - W[3].conj().T)) > 1e-6 * np.max(np.abs(W[3]))   # not Hermitian
+
+
+@pytest.mark.parametrize("gamma", [False, True])
+def test_broadened_contour_deformation_every_state(gamma):
+    """Re Sigma^c by contour deformation with the broadened real grid, for
+    energies across the whole band range (residues far above the first
+    transition), against the closed form; the interpolation error falls with
+    the grid step."""
+    s = _tiny()
+    o = Oracle(s)
+    eta = 0.05
+    E = np.random.default_rng(2).uniform(s.eig.min() - 0.1, s.eig.max() + 0.1, (2, s.n_k, s.spec.n_qp))
+    top = float(np.max(np.abs(E[..., None] - s.eig[:, None, None, :]))) + 0.01
+    ex = _exact_broadened(o, E, eta, gamma)
+    errs = []
+    for h in (eta / 4, eta / 8):
+        n_r = int(np.ceil(top / h)) + 1
+        got = o.sigma_cd(n_r, (n_r - 1) * h, E, gamma=gamma, eta=eta)
+        assert np.all(np.isfinite(got))
+        errs.append(np.max(np.abs(got - ex)) / np.max(np.abs(ex)))
+    assert errs[1] < 2e-4 and errs[1] < errs[0] / 4, errs
+
+
+def test_qp_iteration_solves_the_qp_equation():
+    """Newton steps on E - e - Re Sigma^c(E) from e: after four the QP equation
+    holds to 1e-9 Ha for every state, and the first step is the linearised
+    energy."""
+    s = _tiny()
+    o = Oracle(s)
+    eta = 0.05
+    top = float(s.eig.max() - s.eig.min()) + 1.0
+    h = eta / 4
+    n_r = int(np.ceil(top / h)) + 1
+    E1, Z1, _ = o.qp_cd(n_r, (n_r - 1) * h, eta, 1)
+    eps = s.eig[:, o.qp]
+    S3 = o.sigma_cd(n_r, (n_r - 1) * h, np.stack([eps - 0.002, eps, eps + 0.002]), eta=eta)
+    El, Zl = contour.qp_linear(S3[0], S3[1], S3[2], 0.002, eps, s.e_static)
+    assert np.max(np.abs(E1 - El)) < 1e-13
+    E, Z, S = o.qp_cd(n_r, (n_r - 1) * h, eta, 4)
+    res = E - eps - s.e_static - o.sigma_cd(n_r, (n_r - 1) * h, E[None], eta=eta)[0]
+    assert np.max(np.abs(res)) < 1e-9
