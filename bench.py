@@ -408,17 +408,19 @@ def surrogate_leg(args):
     switched off (the interpolation rule alone)."""
     import torch
     from paper_2011_01400_amd import lrigw as L
-    from synth.systems import (make_config, surrogate_init, surrogate_order, surrogate_start, training_cells,
-                               transition_window)
+    from synth.systems import (CONFIGS, eigenvalues_of, make_config, make_system, surrogate_init, surrogate_order,
+                               surrogate_start, transition_window, window_of)
     L.load()
     t_start = time.perf_counter()
     cfg = 4
+    print("# bench surrogate: generating the 8-atom cell", file=sys.stderr, flush=True)
     s = make_config(cfg)
     sp = s.spec
     rank, hidden = 48, 256
-    print("# bench surrogate: generating 4 training cells", file=sys.stderr, flush=True)
-    train = training_cells(cfg, 4)
-    wins = [transition_window(c) for c in train + [s]]
+    # the training cells (seeds 1000 config + 1..4), one at a time: their
+    # transition windows first (eigenvalues only), then the rows
+    train_seeds = [1000 * cfg + 1 + i for i in range(4)]
+    wins = [transition_window(s)] + [window_of(eigenvalues_of(CONFIGS[cfg][0], sd), sp.n_occ) for sd in train_seeds]
     lo, hi = min(w[0] for w in wins), max(w[1] for w in wins)
     ctx = L.Context.from_system(s, precision=args.precision)
     omega = ctx.grids()[0].cpu().numpy()
@@ -429,7 +431,9 @@ def surrogate_leg(args):
     sg = L.Surrogate(ctx, torch.from_numpy(th).cuda(),
                      torch.from_numpy(surrogate_start(s.n_aux, rank, 2)).cuda(), rank=rank, n_anchor=n_anchor,
                      hidden=hidden, d_lo=lo, d_hi=hi, row_capacity=len(train) * len(qs_train) * rank * rank)
-    for i, c in enumerate(train):
+    for i, sd in enumerate(train_seeds):
+        print(f"# bench surrogate: generating training cell seed {sd}", file=sys.stderr, flush=True)
+        c = make_system(CONFIGS[cfg][0], sd)
         cx = L.Context.from_system(c, precision=args.precision)
         dv = L.device_inputs(c)
         H = cx.empty("H")
@@ -440,7 +444,7 @@ def surrogate_leg(args):
             cx.chi0(q, M, dv["eig"], chi)
             sg.add(cx, chi)
         cx.close()
-        del dv, H, M, chi
+        del dv, H, M, chi, c
         torch.cuda.empty_cache()
         print(f"# bench surrogate: training cell {i + 1} added ({sg.n_rows()} rows)", file=sys.stderr, flush=True)
     n_rows = sg.n_rows()
@@ -518,7 +522,7 @@ def surrogate_leg(args):
                                   f"rank {rank}, network 3x{hidden}, {n_anchor} anchors + 1 held-out",
                       "precision_form": args.precision, "pairs_per_step": pairs},
            "exact_pass": {"ms": round(dt_exact * 1e3, 1), "pairs_per_s": round(pairs / dt_exact, 1), "tuned": tuned},
-           "training": {"cells": 4, "q_per_cell": len(qs_train), "samples": 4 * len(qs_train) * sp.n_freq,
+           "training": {"cells": 4, "seeds": train_seeds, "q_per_cell": len(qs_train), "samples": 4 * len(qs_train) * sp.n_freq,
                         "rows": n_rows, "steps": int(len(h)), "seconds": round(t_train, 1),
                         "loss_first": float(h[:20].mean()), "loss_last": float(h[-100:].mean()),
                         "series_rms_rule": r_rule, "series_rms_network": r_net},

@@ -319,11 +319,25 @@ int lrigw_set_gamma_directions(lrigw_ctx *ctx, int n_dir, const void *p_dirs, co
  *    form.
  *  - A residue frequency above (n_r - 1) h makes that output NaN. */
 
-/* Define the real grid: 4 <= n_r <= n_freq planes, w_r = r omega_max/(n_r-1).
- * Allocates the context's real-axis buffers (2 n_r N_aux^2 complex of the
- * compute type, n_r N_k n_qp n_bands doubles) and waits for the stream.
- * Errors: ERR_ARG (n_r or omega_max out of range), ERR_OOM. */
-int lrigw_set_real_grid(lrigw_ctx *ctx, int n_r, double omega_max);
+/* Define the real grid w_r = r omega_max/(n_r-1).
+ * eta = 0: 4 <= n_r <= n_freq planes below the smallest transition energy
+ *   (exact, Hermitian W^c); allocates the context's real-axis buffers
+ *   (4 n_r N_aux^2 complex of the compute type, n_r N_k n_qp n_bands doubles).
+ * eta > 0: the broadened grid for every state, 4 <= n_r <= 65536 nodes at any
+ *   height: W^c is taken at w_r + i eta (the poles of the time-ordered W^c
+ *   broadened by eta; the grid step should resolve eta, e.g. eta/4).  The
+ *   response of each node is the Re-weight plane plus i times the Im-weight
+ *   plane of 2D/(D^2 - (w_r + i eta)^2); eps~ is then not Hermitian and is
+ *   solved through its normal equations (E^H E) X = E^H D on the Cholesky
+ *   path; the residues use Re X_nm, the quadratic form of the Hermitian part
+ *   of W^c, which is what Re Sigma^c takes.  Used by lrigw_sigma_cd_pass,
+ *   lrigw_g0w0_cd and lrigw_qp_cd (in chunks of n_freq/2 nodes, on the
+ *   context stream alone; not with the direction average at q = 0); the
+ *   single-q calls lrigw_chi0_real, lrigw_screen_real and lrigw_sigma_cd
+ *   return ERR_ARG with it.  Allocates n_r N_k n_qp n_bands doubles.
+ * Waits for the stream.  Errors: ERR_ARG (n_r, omega_max or eta out of
+ * range; eta > 0 with n_freq < 2), ERR_OOM. */
+int lrigw_set_real_grid(lrigw_ctx *ctx, int n_r, double omega_max, double eta);
 
 /* chi~(q, w_r) at the n_r real frequencies: as lrigw_chi0 (same M, eig,
  * apply_gamma and output layout [n_r][N_aux][N_aux]), weight 2D/(D^2 - w^2).
@@ -367,6 +381,19 @@ int lrigw_sigma_cd_pass(lrigw_ctx *ctx, const void *H, const void *evec, const d
 int lrigw_g0w0_cd(lrigw_ctx *ctx, const void *H, const void *evec, const double *eig, const void *V, const void *Vcut,
                   const void *p, double omega_cell, const double *e_static, double delta, double *sigma3, double *e_qp,
                   double *z, int *n_bad);
+
+/* Quasiparticle energies from contour deformation by Newton steps on
+ *   f(E) = E - e_n - e_static_n - Sigma^c(E),  E_0 = e_n,
+ *   E <- E + Z (e_n + e_static_n + Sigma^c(E) - E),
+ *   Z = 1 / (1 - (Sigma^c(E + delta) - Sigma^c(E - delta)) / (2 delta)),
+ * n_iter (1..64) steps, each one whole contour-deformation pass at the three
+ * energies of every state (n_iter = 1 is lrigw_g0w0_cd).  With the broadened
+ * grid (lrigw_set_real_grid, eta > 0) every state is evaluated.  Arguments
+ * and errors as lrigw_g0w0_cd; sigma3 holds the last pass's three values,
+ * z the Z of the last step. */
+int lrigw_qp_cd(lrigw_ctx *ctx, const void *H, const void *evec, const double *eig, const void *V, const void *Vcut,
+                const void *p, double omega_cell, const double *e_static, double delta, int n_iter, double *sigma3,
+                double *e_qp, double *z, int *n_bad);
 
 /* ---- Learned frequency surrogate of the response (a form the paper does not
  * have; it evaluates Eq. chi0_matrix at every frequency of the grid).
@@ -505,12 +532,14 @@ int lrigw_tune(lrigw_ctx *ctx, const void *H, const void *evec, const double *ei
  * and split forms, 2/1 in FP64), splits = K splits (the partial-tile buffer
  * must hold them; in the split forms at least ceil(K/4096), K = N_k n_occ
  * n_unocc, so no workgroup sums more than 4096 rows in FP32), pad = LDS row padding of the split-form response kernel (8
- * or 16), sigma_variant = split-form self-energy kernel variant (0..10; 7 to
- * 10, the resident-tile form with 8 or 4 waves and LDS rows padded by 8 or
- * 16, need the two-part FP16 split, N_aux <= 288 and at most 32 frequencies).
+ * or 16), sigma_variant = split-form self-energy kernel variant (0..12; 7 to
+ * 12, the resident-tile form with 8 or 4 waves and LDS rows padded by 8 or
+ * 16, or (11, 12) the per-tile sum taking x from global memory, need the
+ * two-part FP16 split, N_aux <= 288 and at most 32 frequencies).
  * Errors: ERR_ARG for a choice outside these sets or a variant the cell does
  * not admit. */
 int lrigw_set_tiles(lrigw_ctx *ctx, int nw, int splits, int pad, int sigma_variant);
+
 /* The current tile choices (host outputs, any may be NULL) and the number of
  * self-energy kernel variants (valid ones are 0..n_variants-1). */
 int lrigw_get_tiles(const lrigw_ctx *ctx, int *nw, int *splits, int *pad, int *sigma_variant, int *n_variants);

@@ -52,7 +52,7 @@ static void free_all(lrigw_ctx *c) {
                   c->d_delta, c->d_part, c->d_X, c->d_LV, c->d_s0, c->d_s1, c->d_s2, c->d_s3, c->d_dinv, c->d_info,
                   c->d_bhat, c->d_x1, c->d_M, c->d_x, c->d_chi, c->d_wc, c->d_epsqp, c->d_xs, c->d_ws, c->d_ap, c->d_bt, c->d_chi2, c->d_wc2,
                   c->d_sx, c->d_wmax, c->d_amax, c->d_sitems, c->d_wd, c->d_xo, c->d_sxa, c->d_sxz, c->d_om2,
-                  c->d_wsc, c->d_chir, c->d_wr, c->d_Xr, c->d_cdE, c->d_cdS, c->d_cdbad, c->d_sitems_r, c->d_chir2, c->d_wr2, c->d_cut};
+                  c->d_wsc, c->d_chir, c->d_wr, c->d_Xr, c->d_cdE, c->d_cdS, c->d_cdbad, c->d_sitems_r, c->d_chir2, c->d_wr2, c->d_cut, c->d_bom2, c->d_bcpl, c->d_bwsc};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &kv : c->stages)
@@ -529,10 +529,10 @@ int lrigw_qp(lrigw_ctx *c, const void *sigma, const double *eps_qp, const double
   return rc;
 }
 
-int lrigw_set_real_grid(lrigw_ctx *c, int n_r, double omega_max) {
+int lrigw_set_real_grid(lrigw_ctx *c, int n_r, double omega_max, double eta) {
   (void)hipGetLastError();
   if (!c) return LRIGW_ERR_ARG;
-  return run_set_real_grid(c, n_r, omega_max);
+  return run_set_real_grid(c, n_r, omega_max, eta);
 }
 
 int lrigw_chi0_real(lrigw_ctx *c, int iq, const void *M, const double *eig, int apply_gamma, void *chi_out) {
@@ -540,6 +540,7 @@ int lrigw_chi0_real(lrigw_ctx *c, int iq, const void *M, const double *eig, int 
   if (!c || !M || !eig || !chi_out) return LRIGW_ERR_ARG;
   if (iq < 0 || iq >= c->d.n_k) return LRIGW_ERR_ARG;
   if (apply_gamma && (iq != 0 || !c->gamma_ready)) return LRIGW_ERR_ARG;
+  if (c->real_eta > 0.0) return LRIGW_ERR_ARG;   // the broadened grid is for the passes only
   hipEvent_t ev;
   stage_begin(c, "chi0_real", &ev);
   int rc = run_chi0_real(c, iq, M, eig, apply_gamma, chi_out);
@@ -550,7 +551,7 @@ int lrigw_chi0_real(lrigw_ctx *c, int iq, const void *M, const double *eig, int 
 int lrigw_screen_real(lrigw_ctx *c, int iq, const void *chi, const void *V, const void *Vcut, void *Wc_out, int *info) {
   (void)hipGetLastError();
   if (!c || !chi || !V || !Wc_out) return LRIGW_ERR_ARG;
-  if (iq < 0 || iq >= c->d.n_k || c->n_real < 4) return LRIGW_ERR_ARG;
+  if (iq < 0 || iq >= c->d.n_k || c->n_real < 4 || c->real_eta > 0.0) return LRIGW_ERR_ARG;
   hipEvent_t ev;
   stage_begin(c, "screen_real", &ev);
   int rc = run_screen_n(c, iq, chi, V, Vcut, Wc_out, info, c->n_real);
@@ -562,7 +563,7 @@ int lrigw_sigma_cd(lrigw_ctx *c, int iq, const void *x, const void *Wc, const vo
                    const double *E, double *sigma_e) {
   (void)hipGetLastError();
   if (!c || !x || !Wc || !Wr || !eig || !E || !sigma_e) return LRIGW_ERR_ARG;
-  if (iq < 0 || iq >= c->d.n_k) return LRIGW_ERR_ARG;
+  if (iq < 0 || iq >= c->d.n_k || c->real_eta > 0.0) return LRIGW_ERR_ARG;
   return run_sigma_cd(c, iq, x, Wc, Wr, eig, n_e, E, sigma_e);
 }
 
@@ -573,6 +574,7 @@ int lrigw_sigma_cd_pass(lrigw_ctx *c, const void *H, const void *evec, const dou
   if (!c || !H || !evec || !eig || !V || !E || !sigma_e) return LRIGW_ERR_ARG;
   if (c->n_real < 4 || n_e < 1 || n_e > 4 || c->capturing) return LRIGW_ERR_ARG;
   if (p && !(omega_cell > 0.0)) return LRIGW_ERR_ARG;
+  if (c->real_eta > 0.0) return run_cd_pass_broadened(c, H, evec, eig, V, Vcut, p, omega_cell, n_e, E, sigma_e, n_bad);
   return run_cd_pass(c, H, evec, eig, V, Vcut, p, omega_cell, n_e, E, sigma_e, n_bad);
 }
 
@@ -586,9 +588,33 @@ int lrigw_g0w0_cd(lrigw_ctx *c, const void *H, const void *evec, const double *e
   if (p && !(omega_cell > 0.0)) return LRIGW_ERR_ARG;
   double *S = sigma3 ? sigma3 : c->d_cdS;
   LRIGW_TRY(cd_energies(c, eig, delta));
-  const int rc = run_cd_pass(c, H, evec, eig, V, Vcut, p, omega_cell, 3, c->d_cdE, S, n_bad);
+  const int rc = c->real_eta > 0.0
+                     ? run_cd_pass_broadened(c, H, evec, eig, V, Vcut, p, omega_cell, 3, c->d_cdE, S, n_bad)
+                     : run_cd_pass(c, H, evec, eig, V, Vcut, p, omega_cell, 3, c->d_cdE, S, n_bad);
   if (rc < 0) return rc;
   LRIGW_TRY(cd_qp_linear(c, S, e_static, delta, e_qp, z));
+  return rc;
+}
+
+int lrigw_qp_cd(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *Vcut,
+                const void *p, double omega_cell, const double *e_static, double delta, int n_iter, double *sigma3,
+                double *e_qp, double *z, int *n_bad) {
+  (void)hipGetLastError();
+  if (n_bad) *n_bad = 0;
+  if (!c || !H || !evec || !eig || !V || !e_qp || !z) return LRIGW_ERR_ARG;
+  if (c->n_real < 4 || !(delta > 0.0) || !std::isfinite(delta) || c->capturing || n_iter < 1 || n_iter > 64)
+    return LRIGW_ERR_ARG;
+  if (p && !(omega_cell > 0.0)) return LRIGW_ERR_ARG;
+  double *S = sigma3 ? sigma3 : c->d_cdS;
+  int rc = LRIGW_OK;
+  for (int it = 0; it < n_iter; ++it) {
+    // energies E - delta, E, E + delta of the current iterate (E_0 = e_n)
+    LRIGW_TRY(cd_newton(c, eig, nullptr, nullptr, delta, e_qp, nullptr, it == 0));
+    rc = c->real_eta > 0.0 ? run_cd_pass_broadened(c, H, evec, eig, V, Vcut, p, omega_cell, 3, c->d_cdE, S, n_bad)
+                           : run_cd_pass(c, H, evec, eig, V, Vcut, p, omega_cell, 3, c->d_cdE, S, n_bad);
+    if (rc < 0) return rc;
+    LRIGW_TRY(cd_newton(c, eig, S, e_static, delta, e_qp, z, 0));
+  }
   return rc;
 }
 

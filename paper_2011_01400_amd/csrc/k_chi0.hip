@@ -32,9 +32,15 @@ template <> struct Chi0Cfg<double> { static const int NW = 2; static const bool 
 int chi0_default_nw(int precision) { return precision == LRIGW_FP64 ? Chi0Cfg<double>::NW : Chi0Cfg<float>::NW; }
 int chi0_alt_nw(int precision) { return precision == LRIGW_FP64 ? 1 : 2; }
 
+// Complex-frequency planes (cpltab != nullptr): plane w holds, for
+// z^2 = -om2 + i s (z = w_r + i eta: om2 = eta^2 - w_r^2, s = 2 w_r eta), the real
+// (cpltab[w].y == 0) or imaginary part of the weight 2D/(D^2 - z^2):
+//   2D a/(a^2 + s^2)  or  2D s/(a^2 + s^2),  a = D^2 + om2,   s = cpltab[w].x;
+// the response at z is then the Re plane plus i times the Im plane.
 template <typename T, int NW>
 __global__ __launch_bounds__(256) void k_chi0_mfma(const typename c2t<T>::type *__restrict__ B, const T *__restrict__ delta,
-                                                   const double *__restrict__ om2tab, const int *__restrict__ wsel,
+                                                   const double *__restrict__ om2tab, const double2 *__restrict__ cpltab,
+                                                   const int *__restrict__ wsel,
                                                    const int *__restrict__ run, long long K, int N, int n_freq, long long Ks,
                                                    long long ntile, typename c2t<T>::type *__restrict__ part) {
   if (run && *run == 0) return;
@@ -54,9 +60,17 @@ __global__ __launch_bounds__(256) void k_chi0_mfma(const typename c2t<T>::type *
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1, col = lane & 15;
 
-  T om2[NW];
+  T om2[NW], csv[NW];
+  bool cim[NW];
+  const bool cplx = cpltab != nullptr;
 #pragma unroll
-  for (int w = 0; w < NW; ++w) om2[w] = (T)((w0 + w < n_freq) ? om2tab[wsel[w0 + w]] : 0.0);
+  for (int w = 0; w < NW; ++w) {
+    const bool in = w0 + w < n_freq;
+    om2[w] = (T)(in ? om2tab[wsel[w0 + w]] : 0.0);
+    const double2 cp = (cplx && in) ? cpltab[wsel[w0 + w]] : mkc(0.0, 0.0);
+    csv[w] = (T)cp.x;
+    cim[w] = cp.y != 0.0;
+  }
   ACC re[NW][2][2], im[NW][2][2];
   ACC re2[NW][2][2], im2[NW][2][2];
 #pragma unroll
@@ -102,7 +116,13 @@ __global__ __launch_bounds__(256) void k_chi0_mfma(const typename c2t<T>::type *
       const T d = dl[kk];
 #pragma unroll
       for (int w = 0; w < NW; ++w) {
-        const T wt = (T)2 * d / (d * d + om2[w]);
+        T wt;
+        if (cplx) {
+          const T a = d * d + om2[w];
+          wt = (T)2 * d * (cim[w] ? csv[w] : a) / (a * a + csv[w] * csv[w]);
+        } else {
+          wt = (T)2 * d / (d * d + om2[w]);
+        }
 #pragma unroll
         for (int sj = 0; sj < 2; ++sj) {
           const T br = wt * bv[sj].x, bi = wt * bv[sj].y;
@@ -264,7 +284,7 @@ template <int V> struct IntC { static constexpr int value = V; };
 template <int NS, int NW, int PAD, bool H>
 __global__ __launch_bounds__(256, NW == 2 ? 2 : 1) void k_chi0_split(const us16 *__restrict__ Ap, const float2 *__restrict__ Bt,
                                                     const float *__restrict__ delta, const double *__restrict__ om2tab,
-                                                    const float *__restrict__ wsctab, const int *__restrict__ wsel, const int *__restrict__ run, long long K,
+                                                    const double2 *__restrict__ cpltab, const float *__restrict__ wsctab, const int *__restrict__ wsel, const int *__restrict__ run, long long K,
                                                     long long Kp, int Npad, int n_freq, long long Ks, long long ntile,
                                                     const unsigned *__restrict__ amax, int N, float2 *__restrict__ part,
                                                     int nsplit) {
@@ -288,12 +308,17 @@ __global__ __launch_bounds__(256, NW == 2 ? 2 : 1) void k_chi0_split(const us16 
   const long long ke = min(K, kb + Ks);
   const int mu0 = I * TILE, nu0 = J * TILE;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, g = lane >> 4;
-  float om2[NW], wsc[NW];
+  float om2[NW], wsc[NW], csv[NW];
+  bool cim[NW];
+  const bool cplx = cpltab != nullptr;
 #pragma unroll
   for (int w = 0; w < NW; ++w) {
     const bool in = w0 + w < n_freq;
     om2[w] = in ? (float)om2tab[wsel[w0 + w]] : 0.f;
     wsc[w] = (H && in) ? wsctab[wsel[w0 + w]] : 1.f;   // power of two, weight * wsc < 1
+    const double2 cp = (cplx && in) ? cpltab[wsel[w0 + w]] : mkc(0.0, 0.0);
+    csv[w] = (float)cp.x;
+    cim[w] = cp.y != 0.0;
   }
   f4v re[NW][4], im[NW][4];
 #pragma unroll
@@ -321,6 +346,10 @@ __global__ __launch_bounds__(256, NW == 2 ? 2 : 1) void k_chi0_split(const us16 
     };
     auto weight = [&](float dd) {
       const int w = tw < NW ? tw : 0;
+      if (cplx) {
+        const float a = dd * dd + om2[w];
+        return 2.f * dd * (cim[w] ? csv[w] : a) / (a * a + csv[w] * csv[w]) * wsc[w];
+      }
       return 2.f * dd / (dd * dd + om2[w]) * wsc[w];
     };
     float dnext = 1.f;
@@ -554,6 +583,14 @@ static int check_gap(lrigw_ctx *c, const double *eig) {
     }
   if (!(cbm > vbm)) return LRIGW_ERR_ARG;
   c->gap_min = cbm - vbm;
+  double omax = -INFINITY, umax = -INFINITY, omin = INFINITY;
+  for (int k = 0; k < d.n_k; ++k)
+    for (int n = 0; n < d.n_bands; ++n) {
+      const double e = h[(size_t)k * d.n_bands + n];
+      if (n < d.n_occ) omin = std::min(omin, e), omax = std::max(omax, e);
+      else umax = std::max(umax, e);
+    }
+  c->gap_max = umax - omin;
   return LRIGW_OK;
 }
 
@@ -563,8 +600,20 @@ int run_chi0_sel(lrigw_ctx *c, int iq, const void *M, const double *eig, int app
                  int n_sel, const int *run, bool real_axis) {
   const Dims &d = c->d;
   // per-plane tables: imaginary planes first, then the real-axis ones
-  const double *om2t = c->d_om2 + (real_axis ? d.n_freq : 0);
-  const float *wsct = c->d_wsc + (real_axis ? d.n_freq : 0);
+  PlaneTab tab;
+  tab.om2 = c->d_om2 + (real_axis ? d.n_freq : 0);
+  tab.wsc = c->d_wsc + (real_axis ? d.n_freq : 0);
+  tab.cpl = nullptr;
+  return run_chi0_tab(c, iq, M, eig, apply_gamma, chi_out, wsel, n_sel, run, tab);
+}
+
+// chi at the planes wsel[0..n_sel) of the given per-plane tables
+int run_chi0_tab(lrigw_ctx *c, int iq, const void *M, const double *eig, int apply_gamma, void *chi_out, const int *wsel,
+                 int n_sel, const int *run, const PlaneTab &tab) {
+  const Dims &d = c->d;
+  const double *om2t = tab.om2;
+  const float *wsct = tab.wsc;
+  const double2 *cplt = tab.cpl;
   if (c->gap_trusted == 0) LRIGW_TRY(check_gap(c, eig));
   hipEvent_t ev_all;
   stage_begin(c, "chi0", &ev_all);
@@ -584,7 +633,7 @@ int run_chi0_sel(lrigw_ctx *c, int iq, const void *M, const double *eig, int app
   stage_begin(c, "chi0_mfma", &ev);
   const int NW = c->chi_nw;
   dim3 grid((unsigned)ntile, (n_sel + NW - 1) / NW, S);
-#define CHI0_ARGS om2t, wsel, run, K, d.n_aux, n_sel, Ks, ntile
+#define CHI0_ARGS om2t, cplt, wsel, run, K, d.n_aux, n_sel, Ks, ntile
   if (c->precision == LRIGW_FP64) {
     if (NW == 2)
       hipLaunchKernelGGL((k_chi0_mfma<double, 2>), grid, dim3(256), 0, c->stream, (const double2 *)B,
@@ -625,7 +674,7 @@ int run_chi0_sel(lrigw_ctx *c, int iq, const void *M, const double *eig, int app
       // 1D over (K split, tile, frequency group), split over the XCDs
       const long long sitems = (long long)((n_sel + NW - 1) / NW) * ntile * S;
       const dim3 sgrid((unsigned)(8 * ((sitems + 7) / 8)));
-#define BF16_ARGS Apd, Btd, Df, om2t, wsct, wsel, run, K, Kp, Npad, n_sel, Ks, ntile, c->d_amax, d.n_aux, Pf, S
+#define BF16_ARGS Apd, Btd, Df, om2t, cplt, wsct, wsel, run, K, Kp, Npad, n_sel, Ks, ntile, c->d_amax, d.n_aux, Pf, S
 #define SPLIT_LAUNCH(NS_, H_)                                                                                            \
   do {                                                                                                                 \
     if (NW == 4 && p16) hipLaunchKernelGGL((k_chi0_split<NS_, 4, 16, H_>), sgrid, dim3(256), 0, c->stream, BF16_ARGS); \

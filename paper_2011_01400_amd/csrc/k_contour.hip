@@ -20,7 +20,10 @@
 // the response's own grid with X(0) subtracted and its integral,
 // (pi/2) sgn(z) X(0), added in closed form.  X(0) is the real grid's first
 // plane.  A residue frequency beyond the grid's top gives NaN.
+#include <algorithm>
+#include <climits>
 #include <cmath>
+#include <vector>
 
 #include "lrigw_internal.h"
 
@@ -133,8 +136,12 @@ __global__ void k_count_nan(const double *__restrict__ v, int n, int *__restrict
   }
 }
 
-int run_set_real_grid(lrigw_ctx *c, int n_r, double omega_max) {
+static int set_real_grid_broadened(lrigw_ctx *c, int n_r, double omega_max, double eta);
+
+int run_set_real_grid(lrigw_ctx *c, int n_r, double omega_max, double eta) {
   const Dims &d = c->d;
+  if (!(eta >= 0.0) || !std::isfinite(eta)) return LRIGW_ERR_ARG;
+  if (eta > 0.0) return set_real_grid_broadened(c, n_r, omega_max, eta);
   if (n_r < 4 || n_r > d.n_freq || !(omega_max > 0.0) || !std::isfinite(omega_max)) return LRIGW_ERR_ARG;
   LRIGW_HIP_TRY(hipStreamSynchronize(c->stream));   // no kernel still reads the old tables or buffers
   const double h = omega_max / (n_r - 1);
@@ -144,7 +151,7 @@ int run_set_real_grid(lrigw_ctx *c, int n_r, double omega_max) {
   }
   LRIGW_HIP_TRY(hipMemcpy(c->d_om2 + d.n_freq, c->h_om2.data() + d.n_freq, d.n_freq * sizeof(double),
                           hipMemcpyHostToDevice));
-  if (n_r != c->n_real) {
+  if (n_r != c->n_real || c->real_eta > 0.0 || !c->d_chir) {
     void *bufs[] = {c->d_chir, c->d_wr, c->d_chir2, c->d_wr2, c->d_Xr};
     for (void *p : bufs)
       if (p) (void)hipFree(p);
@@ -161,10 +168,93 @@ int run_set_real_grid(lrigw_ctx *c, int n_r, double omega_max) {
   if (!c->d_cdE) LRIGW_HIP_TRY(hipMalloc(&c->d_cdE, 3 * (size_t)d.n_k * d.n_qp * sizeof(double)));
   if (!c->d_cdS) LRIGW_HIP_TRY(hipMalloc(&c->d_cdS, 3 * (size_t)d.n_k * d.n_qp * sizeof(double)));
   if (!c->d_cdbad) LRIGW_HIP_TRY(hipMalloc(&c->d_cdbad, sizeof(int)));
+  c->real_eta = 0.0;
   LRIGW_TRY(sigma_res_prepare_real(c, n_r));
   c->n_real = n_r;
   c->real_h = h;
   c->real_wsc_gap = -1.0;   // the FP16 scales depend on the gap: set at the next response
+  return LRIGW_OK;
+}
+
+// Broadened grid: nodes w_r = r h at any height, W^c taken at w_r + i eta.
+// The response of node r is built from two weight planes (Re and Im of
+// 2D/(D^2 - z^2)); the pass works through the nodes in chunks of n_freq/2,
+// which reuse the per-q buffers of the imaginary planes.
+static int set_real_grid_broadened(lrigw_ctx *c, int n_r, double omega_max, double eta) {
+  const Dims &d = c->d;
+  if (n_r < 4 || n_r > 65536 || !(omega_max > 0.0) || !std::isfinite(omega_max) || d.n_freq < 2) return LRIGW_ERR_ARG;
+  LRIGW_HIP_TRY(hipStreamSynchronize(c->stream));
+  void *bufs[] = {c->d_chir, c->d_wr, c->d_chir2, c->d_wr2, c->d_Xr, c->d_bom2, c->d_bcpl, c->d_bwsc};
+  for (void *p : bufs)
+    if (p) (void)hipFree(p);
+  c->d_chir = c->d_wr = c->d_chir2 = c->d_wr2 = nullptr;
+  c->d_Xr = nullptr;
+  c->d_bom2 = nullptr;
+  c->d_bcpl = nullptr;
+  c->d_bwsc = nullptr;
+  c->n_real = 0;
+  const double h = omega_max / (n_r - 1);
+  std::vector<double> om2(2 * (size_t)n_r);
+  std::vector<double2> cpl(2 * (size_t)n_r);
+  for (int r = 0; r < n_r; ++r) {
+    const double w = r * h;
+    om2[2 * r] = om2[2 * r + 1] = eta * eta - w * w;
+    cpl[2 * r] = mkc(2.0 * w * eta, 0.0);
+    cpl[2 * r + 1] = mkc(2.0 * w * eta, 1.0);
+  }
+  LRIGW_HIP_TRY(hipMalloc(&c->d_Xr, (size_t)n_r * d.n_k * d.n_qp * d.n_bands * sizeof(double)));
+  LRIGW_HIP_TRY(hipMalloc(&c->d_bom2, om2.size() * sizeof(double)));
+  LRIGW_HIP_TRY(hipMalloc(&c->d_bcpl, cpl.size() * sizeof(double2)));
+  LRIGW_HIP_TRY(hipMalloc(&c->d_bwsc, om2.size() * sizeof(float)));
+  LRIGW_HIP_TRY(hipMemcpy(c->d_bom2, om2.data(), om2.size() * sizeof(double), hipMemcpyHostToDevice));
+  LRIGW_HIP_TRY(hipMemcpy(c->d_bcpl, cpl.data(), cpl.size() * sizeof(double2), hipMemcpyHostToDevice));
+  c->h_bwsc.assign(om2.size(), 1.f);
+  LRIGW_HIP_TRY(hipMemcpy(c->d_bwsc, c->h_bwsc.data(), c->h_bwsc.size() * sizeof(float), hipMemcpyHostToDevice));
+  if (!c->d_cdE) LRIGW_HIP_TRY(hipMalloc(&c->d_cdE, 3 * (size_t)d.n_k * d.n_qp * sizeof(double)));
+  if (!c->d_cdS) LRIGW_HIP_TRY(hipMalloc(&c->d_cdS, 3 * (size_t)d.n_k * d.n_qp * sizeof(double)));
+  if (!c->d_cdbad) LRIGW_HIP_TRY(hipMalloc(&c->d_cdbad, sizeof(int)));
+  c->sig_res_nr = 0;   // the chunks take the imaginary planes' self-energy plans or the default form
+  c->sig_res_Fr = 0;
+  c->n_real = n_r;
+  c->real_h = h;
+  c->real_eta = eta;
+  c->bwsc_gap = c->bwsc_gmax = -1.0;
+  return LRIGW_OK;
+}
+
+// FP16 split scales of the broadened planes: the largest |Re| and |Im| of
+// 2D/(D^2 - z^2) over D in the transition window, sampled on 4096 log-spaced
+// D plus the resonance D^2 = Re z^2, times 5/4, below 2^e
+static int broadened_scales(lrigw_ctx *c) {
+  if (!split_h(c->precision)) return LRIGW_OK;
+  if (c->bwsc_gap == c->gap_min && c->bwsc_gmax == c->gap_max) return LRIGW_OK;
+  const double lo = c->gap_min, hi = std::max(c->gap_max, c->gap_min * 1.000001), eta = c->real_eta;
+  for (int r = 0; r < c->n_real; ++r) {
+    const double w = r * c->real_h, p = w * w - eta * eta, sv = 2.0 * w * eta;
+    double mr = 0.0, mi = 0.0;
+    auto probe = [&](double D) {
+      if (!(D >= lo && D <= hi)) return;
+      const double a = D * D - p, den = a * a + sv * sv;
+      mr = std::max(mr, std::fabs(2.0 * D * a / den));
+      mi = std::max(mi, std::fabs(2.0 * D * sv / den));
+    };
+    for (int t = 0; t < 4096; ++t) probe(lo * std::pow(hi / lo, t / 4095.0));
+    if (p > 0.0) {
+      probe(std::sqrt(p));
+      if (p > sv) probe(std::sqrt(p - sv));
+      probe(std::sqrt(p + sv));
+    }
+    int e = 0;
+    frexp(1.25 * std::max(mr, 1e-30), &e);
+    c->h_bwsc[2 * r] = ldexpf(1.f, -e);
+    frexp(1.25 * std::max(mi, 1e-30), &e);
+    c->h_bwsc[2 * r + 1] = mi > 0.0 ? ldexpf(1.f, -e) : 1.f;
+  }
+  LRIGW_HIP_TRY(hipMemcpyAsync(c->d_bwsc, c->h_bwsc.data(), c->h_bwsc.size() * sizeof(float), hipMemcpyHostToDevice,
+                               c->stream));
+  LRIGW_HIP_TRY(hipStreamSynchronize(c->stream));
+  c->bwsc_gap = c->gap_min;
+  c->bwsc_gmax = c->gap_max;
   return LRIGW_OK;
 }
 
@@ -229,4 +319,102 @@ int cd_count_nan(lrigw_ctx *c, const double *v, int n, int *out) {
   LRIGW_HIP_TRY(hipMemcpyAsync(out, c->d_cdbad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   LRIGW_HIP_TRY(hipStreamSynchronize(c->stream));
   return LRIGW_OK;
+}
+
+__global__ void k_cd_set_int(int *p, int v) { p[threadIdx.x] = v; }
+
+// Contour deformation over every q with the broadened real grid: per q the
+// imaginary planes as in the exact pass, then the real nodes in chunks of
+// n_freq/2 (the Re- and Im-weight responses of a chunk fill the n_freq planes
+// of the second response buffer; their complex screening the second W^c
+// buffer), the pair weights of each chunk into its rows of the real-grid
+// array, and the combination at the n_e energy sets.  One stream; the
+// screening status is folded on the device and read at the end.
+int run_cd_pass_broadened(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V,
+                          const void *Vcut, const void *p, double omega_cell, int n_e, const double *E, double *sigma_e,
+                          int *n_bad) {
+  const Dims &d = c->d;
+  if (c->n_gdir > 0) return LRIGW_ERR_ARG;   // the direction average is not taken on the broadened grid
+  LRIGW_TRY(driver_buffers(c));
+  if (p) LRIGW_TRY(lrigw_gamma_prepare(c, V, p, omega_cell));
+  LRIGW_TRY(chi0_check_gap(c, eig));
+  GapScope gap_scope(c);
+  LRIGW_TRY(broadened_scales(c));
+  const hipStream_t s = c->stream;
+  LRIGW_TRY(zero_fill(s, sigma_e, (size_t)n_e * d.n_k * d.n_qp * sizeof(double)));
+  hipLaunchKernelGGL(k_cd_set_int, dim3(1), dim3(1), 0, s, c->d_info + 16, INT_MAX);
+  const size_t vstride = (size_t)d.n_aux * d.n_aux;
+  const long long C = (long long)d.n_k * d.n_qp * d.n_bands;
+  const int P = d.n_freq / 2;
+  const bool was = c->capturing;
+  c->capturing = true;   // screening: device-side status, no host round trip
+  int rc = LRIGW_OK;
+  for (int q = 0; q < d.n_k && rc == LRIGW_OK; ++q) {
+    const int g = (p && q == 0) ? 1 : 0;
+    const void *Vq = (const double2 *)V + q * vstride;
+    const void *Vcq = (Vcut && q > 0) ? (const void *)((const double2 *)Vcut + q * vstride) : nullptr;
+    if ((rc = run_build_M(c, q, 0, H, evec, c->d_M)) < 0) break;
+    if ((rc = run_chi0(c, q, c->d_M, eig, g, c->d_chi)) < 0) break;
+    if ((rc = run_screen(c, q, c->d_chi, Vq, Vcq, c->d_wc, nullptr)) < 0) break;
+    if ((rc = run_build_M(c, q, 1, H, evec, c->d_x)) < 0) break;
+    if ((rc = run_pair_weights(c, c->d_x, c->d_wc, d.n_freq, (double *)c->d_X)) < 0) break;
+    for (int r0 = 0; r0 < c->n_real && rc == LRIGW_OK; r0 += P) {
+      const int np = std::min(P, c->n_real - r0);
+      PlaneTab tab;
+      tab.om2 = c->d_bom2 + 2 * r0;
+      tab.wsc = c->d_bwsc + 2 * r0;
+      tab.cpl = c->d_bcpl + 2 * r0;
+      if ((rc = run_chi0_tab(c, q, c->d_M, eig, g, c->d_chi2, c->d_wall, 2 * np, nullptr, tab)) < 0) break;
+      if ((rc = run_screen_cplx(c, q, c->d_chi2, Vq, Vcq, c->d_wc2, nullptr, np)) < 0) break;
+      rc = run_pair_weights(c, c->d_x, c->d_wc2, np, c->d_Xr + (long long)r0 * C);
+    }
+    if (rc < 0) break;
+    hipLaunchKernelGGL(k_sigma_cd, dim3((unsigned)(d.n_k * d.n_qp)), dim3(64), 0, s, (const double *)c->d_X, c->d_Xr,
+                       eig, c->d_kmq, q, d.n_k, d.n_qp, d.n_bands, d.n_occ, d.n_freq, c->d_omega, c->d_weight, c->n_real,
+                       c->real_h, n_e, E, 1.0 / d.n_k, sigma_e);
+    rc = lrigw_launch_check("sigma_cd_broadened");
+  }
+  c->capturing = was;
+  if (rc < 0) return rc;
+  int h = INT_MAX;
+  LRIGW_HIP_TRY(hipMemcpyAsync(&h, c->d_info + 16, sizeof(int), hipMemcpyDeviceToHost, s));
+  LRIGW_HIP_TRY(hipStreamSynchronize(s));
+  if (h != INT_MAX) return LRIGW_ERR_NOT_HPD;
+  int bad = 0;
+  LRIGW_TRY(cd_count_nan(c, sigma_e, n_e * d.n_k * d.n_qp, &bad));
+  if (n_bad) *n_bad = bad;
+  return bad ? LRIGW_WARN_CD_RANGE : LRIGW_OK;
+}
+
+// Newton steps on f(E) = E - e_n - e_static - Sigma^c(E).  mode 0: set the
+// three energy sets E - delta, E, E + delta of the iterate (first: E = e_n);
+// mode 1: E <- E + Z (e_n + e_static + S(E) - E), Z = 1/(1 - (S(E+delta) - S(E-delta))/(2 delta))
+__global__ void k_cd_newton(const double *__restrict__ eig, int nk, int n_bands, int qp_lo, int n_qp,
+                            const double *__restrict__ S, const double *__restrict__ e_static, double delta, int mode,
+                            int first, double *__restrict__ Ecur, double *__restrict__ z, double *__restrict__ Eset) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nkq = nk * n_qp;
+  if (i >= nkq) return;
+  const double eps = eig[(long long)(i / n_qp) * n_bands + qp_lo + i % n_qp];
+  if (mode == 0) {
+    const double E = first ? eps : Ecur[i];
+    if (first) Ecur[i] = eps;
+    Eset[i] = E - delta;
+    Eset[nkq + i] = E;
+    Eset[2 * nkq + i] = E + delta;
+    return;
+  }
+  const double E = Ecur[i];
+  const double Z = 1.0 / (1.0 - (S[2 * nkq + i] - S[i]) / (2.0 * delta));
+  Ecur[i] = E + Z * (eps + (e_static ? e_static[i] : 0.0) + S[nkq + i] - E);
+  if (z) z[i] = Z;
+}
+
+int cd_newton(lrigw_ctx *c, const double *eig, const double *S, const double *e_static, double delta, double *e_cur,
+              double *z, int first) {
+  const Dims &d = c->d;
+  const int nkq = d.n_k * d.n_qp;
+  hipLaunchKernelGGL(k_cd_newton, dim3((nkq + 255) / 256), dim3(256), 0, c->stream, eig, d.n_k, d.n_bands, d.qp_lo, d.n_qp,
+                     S, e_static, delta, S ? 1 : 0, first, e_cur, z, c->d_cdE);
+  return lrigw_launch_check("cd_newton");
 }

@@ -251,6 +251,97 @@ int run_screen_n(lrigw_ctx *c, int iq, const void *chi, const void *V, const voi
   return LRIGW_OK;
 }
 
+// ---------------------------------------------------------------- complex frequencies
+// out[p] = chi[2p] + i chi[2p+1] in FP64 (the Re- and Im-weight planes of the
+// response at w_r + i eta, each a Hermitian matrix)
+template <typename C>
+__global__ void k_combine_planes(const C *__restrict__ chi, double2 *__restrict__ out, long long nn) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nn) return;
+  const int p = blockIdx.y;
+  const double2 a = to_z(chi[(2LL * p) * nn + idx]), b = to_z(chi[(2LL * p + 1) * nn + idx]);
+  out[(long long)p * nn + idx] = mkc(a.x - b.y, a.y + b.x);
+}
+
+// out = (W + W^H)/2 in the compute type
+template <typename T>
+__global__ void k_herm_part(const double2 *__restrict__ W, typename c2t<T>::type *__restrict__ out, int n, long long stride) {
+  long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)n * n) return;
+  const int r = (int)(idx / n), cc = (int)(idx % n);
+  const double2 *Wb = W + (long long)blockIdx.y * stride;
+  const double2 a = Wb[(long long)r * n + cc], b = Wb[(long long)cc * n + r];
+  double2 z = mkc(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+  if (r == cc) z.y = 0.0;
+  out[(long long)blockIdx.y * stride + idx] = to_c<T>(z);
+}
+
+// Screening at complex frequencies z_p = w_p + i eta, p < np: chi holds 2 np
+// planes (the Re- and Im-weight responses of each z_p, compute type).  eps~ is
+// not Hermitian there: with D = -L^H chi L and E = I + D (general), E^{-1} D
+// comes from the Hermitian positive definite normal equations
+// (E^H E) X = E^H D, on the batched Cholesky and triangular solves (in FP64 the
+// squared condition number of E, ~1/eta^2 near a resonance, leaves ~1e-10);
+// W^c = -L X L^H (or T with V^cut), and Wh_out receives its Hermitian part
+// (W + W^H)/2, whose quadratic forms are Re X_nm (the part Re Sigma^c takes).
+int run_screen_cplx(lrigw_ctx *c, int iq, const void *chi, const void *V, const void *Vcut, void *Wh_out, int *info,
+                    int np) {
+  const Dims &d = c->d;
+  const int n = d.n_aux;
+  const long long nn = (long long)n * n;
+  hipStream_t s = c->stream;
+  if (np < 1 || np > d.n_freq) return LRIGW_ERR_ARG;
+  const bool cut = Vcut != nullptr && Vcut != V;
+  LRIGW_HIP_TRY(hipMemcpyAsync(c->d_LV, V, nn * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  LRIGW_TRY(zpotrf_batched(s, c->d_LV, n, n, nn, 1, c->d_dinv, c->d_info + 1));
+  if (cut) LRIGW_TRY(cut_factor(c, V, Vcut));
+  dim3 eg((unsigned)((nn + 255) / 256), np);
+  if (c->precision == LRIGW_FP64)
+    hipLaunchKernelGGL(k_combine_planes<double2>, eg, dim3(256), 0, s, (const double2 *)chi, c->d_s3, nn);
+  else
+    hipLaunchKernelGGL(k_combine_planes<float2>, eg, dim3(256), 0, s, (const float2 *)chi, c->d_s3, nn);
+  const double2 one = mkc(1.0, 0.0), mone = mkc(-1.0, 0.0);
+  // T1 = chi L; D = -L^H T1 (full: not Hermitian)
+  LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_s3, n, nn, OP_N, c->d_LV, n, 0, c->d_s0, n, nn, one, np)));
+  LRIGW_TRY(zgemm(s, mk(n, n, n, OP_C, c->d_LV, n, 0, OP_N, c->d_s0, n, nn, c->d_s1, n, nn, mone, np)));
+  // E = I + D; G = E^H E, R = E^H D
+  hipLaunchKernelGGL(k_add_identity, eg, dim3(256), 0, s, c->d_s1, c->d_s2, n, nn);
+  LRIGW_TRY(zgemm(s, mk(n, n, n, OP_C, c->d_s2, n, nn, OP_N, c->d_s2, n, nn, c->d_s0, n, nn, one, np)));
+  LRIGW_TRY(zgemm(s, mk(n, n, n, OP_C, c->d_s2, n, nn, OP_N, c->d_s1, n, nn, c->d_s3, n, nn, one, np)));
+  // X = G^{-1} R = E^{-1} D
+  LRIGW_TRY(zpotrf_batched(s, c->d_s0, n, n, nn, np, c->d_dinv, c->d_info + 2));
+  LRIGW_TRY(ztrsm_left_lower(s, c->d_s0, n, nn, c->d_dinv, c->d_s3, n, nn, n, n, np));
+  LRIGW_TRY(ztrsm_left_upper_conj(s, c->d_s0, n, nn, c->d_dinv, c->d_s3, n, nn, n, n, np));
+  // W = -L X L^H (T in place of L with V^cut), full
+  if (cut) LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_s3, n, nn, OP_N, c->d_cut, n, 0, c->d_s1, n, nn, one, np)));
+  else LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_s3, n, nn, OP_C, c->d_LV, n, 0, c->d_s1, n, nn, one, np)));
+  if (cut) LRIGW_TRY(zgemm(s, mk(n, n, n, OP_C, c->d_cut, n, 0, OP_N, c->d_s1, n, nn, c->d_s2, n, nn, mone, np)));
+  else LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_LV, n, 0, OP_N, c->d_s1, n, nn, c->d_s2, n, nn, mone, np)));
+  if (c->precision == LRIGW_FP64)
+    hipLaunchKernelGGL(k_herm_part<double>, eg, dim3(256), 0, s, c->d_s2, (double2 *)Wh_out, n, nn);
+  else
+    hipLaunchKernelGGL(k_herm_part<float>, eg, dim3(256), 0, s, c->d_s2, (float2 *)Wh_out, n, nn);
+  LRIGW_TRY(lrigw_launch_check("screen_cplx"));
+  if (c->capturing) {
+    hipLaunchKernelGGL(k_fold_status, dim3(1), dim3(1), 0, s, c->d_info, iq);
+    if (info) *info = -1;
+    return lrigw_launch_check("screen_status");
+  }
+  int h[2];
+  LRIGW_HIP_TRY(hipMemcpyAsync(h, c->d_info + 1, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+  LRIGW_HIP_TRY(hipStreamSynchronize(s));
+  if (info) *info = -1;
+  if (h[0] != INT_MAX) {
+    if (info) *info = -2;
+    return LRIGW_ERR_NOT_HPD;
+  }
+  if (h[1] != INT_MAX) {
+    if (info) *info = h[1];
+    return LRIGW_ERR_NOT_HPD;
+  }
+  return LRIGW_OK;
+}
+
 // out = tmp * w (first direction) or out + tmp * w
 template <typename C>
 __global__ void k_waccum(C *__restrict__ out, const C *__restrict__ tmp, long long n, double w, int first) {

@@ -644,7 +644,11 @@ __global__ __launch_bounds__(256) void k_sigma_splitq(const us16 *__restrict__ x
 #define RES_F 4
 #define RES_MAXI 15
 
-template <int PAD, bool H, int NWV>
+// GX: the per-tile sum X_c += 2 Re(x_mu Z_mu) takes x from the FP32 array in
+// global memory (L2-resident while the column block is worked on) instead of
+// the FP16 parts in LDS: two 16-byte loads and two FMAs per row quadruple
+// instead of four 8-byte LDS reads, four conversions and four FMAs.
+template <int PAD, bool H, int NWV, bool GX = false>
 __global__ __launch_bounds__(64 * NWV) void k_sigma_res(const us16 *__restrict__ xs, const us16 *__restrict__ ws,
                                                    const float2 *__restrict__ x, const float2 *__restrict__ Wall,
                                                    long long Ccols, long long Cpad, int N, int Npad, int Rpad, int n_freq,
@@ -763,7 +767,29 @@ __global__ __launch_bounds__(64 * NWV) void k_sigma_res(const us16 *__restrict__
     // tile's eight terms per lane are summed in FP32, the tiles in FP64
     // the tile holds conj(x) / sx = xr - i xi' with xi' = -Im(x) / sx
     float tz[4] = {0.f, 0.f, 0.f, 0.f};
-    if ((N & 3) == 0) {
+    if (GX && (N & 3) == 0) {
+      // tz in units of x (not x/sx): Re(x Z') = xr zr - xi zi with Z' the
+      // product of the scaled tile; the column scale is applied once below
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int m0 = r0 + 16 * i + 4 * g;
+        const bool ok = m0 >= 0;
+        const int ma = ok ? m0 : 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const long long cc = c0 + 16 * j + col;
+          const long long cs = cc < Ccols ? cc : 0;   // padded columns read column 0 (never stored)
+          const float4 *px = (const float4 *)(x + cs * N + ma);   // 4 consecutive rows, 32-byte aligned
+          const float4 a = px[0], b = px[1];
+          const float xr[4] = {a.x, a.z, b.x, b.z}, xi[4] = {a.y, a.w, b.y, b.w};
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float zrv = ok ? zr[i][j][q] : 0.f, ziv = ok ? zi[i][j][q] : 0.f;
+            tz[j] = fmaf(xr[q], zrv, fmaf(-xi[q], ziv, tz[j]));
+          }
+        }
+      }
+    } else if ((N & 3) == 0) {
       // a lane's four rows 16 i + 4 (lane / 16) + q are consecutive and, with
       // N = 0 (mod 4), start on a multiple of 4 (tiles end at row N - 1): one
       // 8-byte read per plane; a group above row 0 reads row 0 and adds zero
@@ -812,9 +838,9 @@ __global__ __launch_bounds__(64 * NWV) void k_sigma_res(const us16 *__restrict__
 #pragma unroll
     for (int j = 0; j < 4; ++j) psum[j] += 2.0 * (double)fw * (double)tz[j];
   }
-  // x = sx x' and Z = sW sx Z': sx^2
+  // x = sx x' and Z = sW sx Z': sx^2 (sx once when the sum took x itself)
 #pragma unroll
-  for (int j = 0; j < 4; ++j) psum[j] *= (double)fx[j] * (double)fx[j];
+  for (int j = 0; j < 4; ++j) psum[j] *= (GX && (N & 3) == 0) ? (double)fx[j] : (double)fx[j] * (double)fx[j];
   // lanes l, l^16, l^32, l^48 hold the same column
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -1037,9 +1063,10 @@ __global__ __launch_bounds__(64) void k_sigma_freq(const double *__restrict__ X,
 // W prefetched one chunk ahead, wave tile) = (1, yes, 16x64), (2, no, 16x64),
 // (1, no, 16x64), (1, yes, 32x32), (1, no, 32x32), the first one with LDS rows
 // padded to 96 and 112 bytes instead of 80, and the resident-tile form with 8
-// and 4 waves per workgroup and LDS rows padded by 8 or 16 elements (two-part
-// FP16 split, N_aux <= 288 only)
-#define SIGMA_VARIANTS 11
+// and 4 waves per workgroup and LDS rows padded by 8 or 16 elements, 11/12 the
+// 8/4-wave forms whose per-tile sum reads x from global memory (two-part FP16
+// split, N_aux <= 288 only)
+#define SIGMA_VARIANTS 13
 int sigma_variant_snw(int var) { return var == 1 ? 2 : 1; }
 int sigma_variants() { return SIGMA_VARIANTS; }
 int sigma_default_variant(int precision) { return ns_sig(precision) == 2 ? 1 : 0; }
@@ -1131,7 +1158,9 @@ int run_pair_weights(lrigw_ctx *c, const void *x, const void *Wc, int nw, double
       if (var == 7) hipLaunchKernelGGL((k_sigma_res<8, true, 8>), gr, dim3(512), 0, c->stream, RES_ARGS, t8, c->d_sx, c->d_wmax, X);
       else if (var == 8) hipLaunchKernelGGL((k_sigma_res<8, true, 4>), gr, dim3(256), 0, c->stream, RES_ARGS, t4, c->d_sx, c->d_wmax, X);
       else if (var == 9) hipLaunchKernelGGL((k_sigma_res<16, true, 8>), gr, dim3(512), 0, c->stream, RES_ARGS, t8, c->d_sx, c->d_wmax, X);
-      else hipLaunchKernelGGL((k_sigma_res<16, true, 4>), gr, dim3(256), 0, c->stream, RES_ARGS, t4, c->d_sx, c->d_wmax, X);
+      else if (var == 10) hipLaunchKernelGGL((k_sigma_res<16, true, 4>), gr, dim3(256), 0, c->stream, RES_ARGS, t4, c->d_sx, c->d_wmax, X);
+      else if (var == 11) hipLaunchKernelGGL((k_sigma_res<8, true, 8, true>), gr, dim3(512), 0, c->stream, RES_ARGS, t8, c->d_sx, c->d_wmax, X);
+      else hipLaunchKernelGGL((k_sigma_res<8, true, 4, true>), gr, dim3(256), 0, c->stream, RES_ARGS, t4, c->d_sx, c->d_wmax, X);
 #undef RES_ARGS
     } else if (H)
       launch_sigma_split<2, true>(var, gs, c->stream, xs, ws, xf, Wf, Ccols, Cpad, d.n_aux, Npad, Rpad, nw, c->d_sx,

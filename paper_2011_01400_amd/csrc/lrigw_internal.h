@@ -95,8 +95,18 @@ struct lrigw_ctx {
   std::vector<double> h_om2;
   std::vector<float> h_wsc;
   double gap_min = 0.0;          // smallest transition energy of the checked eigenvalues
+  double gap_max = 0.0;          // largest transition energy of the checked eigenvalues
   // real-axis grid w_r = r h, r < n_real (0: none); its buffers
   int n_real = 0;
+  // broadened real grid (real_eta > 0): W^c at w_r + i eta for every w_r, the
+  // response from two weight planes per node (tables of 2 n_real planes: node
+  // r's Re part at 2r, Im part at 2r+1)
+  double real_eta = 0.0;
+  double *d_bom2 = nullptr;      // [2 n_real] eta^2 - w_r^2
+  double2 *d_bcpl = nullptr;     // [2 n_real] (2 w_r eta, part)
+  float *d_bwsc = nullptr;       // [2 n_real] FP16 weight scales
+  std::vector<float> h_bwsc;
+  double bwsc_gap = -1.0, bwsc_gmax = -1.0;   // transition window the scales were made for
   double real_h = 0.0, real_wsc_gap = -1.0;
   void *d_chir = nullptr, *d_wr = nullptr;   // [n_real][N][N] response / W^c (compute type)
   void *d_chir2 = nullptr, *d_wr2 = nullptr; // second pair (the pass screens q while building q+1)
@@ -222,6 +232,17 @@ int run_build_M(lrigw_ctx *c, int iq, int slice, const void *H, const void *evec
 int run_chi0(lrigw_ctx *c, int iq, const void *M, const double *eig, int apply_gamma, void *chi_out);
 int run_chi0_sel(lrigw_ctx *c, int iq, const void *M, const double *eig, int apply_gamma, void *chi_out, const int *wsel,
                  int n_sel, const int *run, bool real_axis = false);
+// per-plane tables of the response kernels (device): signed w^2 (weight
+// 2D/(D^2 + om2)), the FP16 split's weight scale, and for complex-frequency
+// planes (cpl != nullptr) (s, part): the Re (part 0) or Im part of
+// 2D/(D^2 - z^2) with z^2 = -om2 + i s
+struct PlaneTab {
+  const double *om2;
+  const float *wsc;
+  const double2 *cpl;
+};
+int run_chi0_tab(lrigw_ctx *c, int iq, const void *M, const double *eig, int apply_gamma, void *chi_out, const int *wsel,
+                 int n_sel, const int *run, const PlaneTab &tab);
 int surrogate_prepare(lrigw_surrogate *sg);
 int run_chi0_surrogate(lrigw_ctx *c, lrigw_surrogate *sg, int iq, const void *M, const double *eig, int apply_gamma,
                        double threshold, void *chi_out);
@@ -229,10 +250,17 @@ int run_gamma_prepare(lrigw_ctx *c, const void *Vcut0, const void *p, double ome
 // Vcut: the truncated Coulomb matrix of the numerator (nullptr or V: V itself)
 int run_screen(lrigw_ctx *c, int iq, const void *chi, const void *V, const void *Vcut, void *Wc_out, int *info);
 int run_screen_n(lrigw_ctx *c, int iq, const void *chi, const void *V, const void *Vcut, void *Wc_out, int *info, int nw);
+int run_screen_cplx(lrigw_ctx *c, int iq, const void *chi, const void *V, const void *Vcut, void *Wh_out, int *info,
+                    int np);
 int run_sigma_c(lrigw_ctx *c, int iq, const void *x, const void *Wc, const double *eig, void *sigma_acc);
 int run_pair_weights(lrigw_ctx *c, const void *x, const void *Wc, int nw, double *X);
 int sigma_res_prepare_real(lrigw_ctx *c, int n_r);
-int run_set_real_grid(lrigw_ctx *c, int n_r, double omega_max);
+int run_set_real_grid(lrigw_ctx *c, int n_r, double omega_max, double eta);
+int run_cd_pass_broadened(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V,
+                          const void *Vcut, const void *p, double omega_cell, int n_e, const double *E, double *sigma_e,
+                          int *n_bad);
+int cd_newton(lrigw_ctx *c, const double *eig, const double *S, const double *e_static, double delta, double *e_cur,
+              double *z, int first);
 int run_chi0_real(lrigw_ctx *c, int iq, const void *M, const double *eig, int apply_gamma, void *chi_out);
 int run_sigma_cd(lrigw_ctx *c, int iq, const void *x, const void *Wc, const void *Wr, const double *eig, int n_e,
                  const double *E, double *sigma_e);

@@ -35,7 +35,7 @@ EXPORTS = ["lrigw_create", "lrigw_destroy", "lrigw_strerror", "lrigw_get_sizes",
            "lrigw_build_M", "lrigw_chi0", "lrigw_gamma_prepare", "lrigw_screen", "lrigw_sigma_c", "lrigw_sigma_x",
            "lrigw_sigma_x_pass", "lrigw_lri_fit", "lrigw_lri_fit_noalloc", "lrigw_qp",
            "lrigw_set_real_grid", "lrigw_chi0_real", "lrigw_screen_real", "lrigw_sigma_cd", "lrigw_sigma_cd_pass",
-           "lrigw_g0w0_cd", "lrigw_set_gamma_directions", "lrigw_pade_eval", "lrigw_g0w0", "lrigw_set_timing", "lrigw_stage_ms", "lrigw_reset_timing",
+           "lrigw_g0w0_cd", "lrigw_qp_cd", "lrigw_set_gamma_directions", "lrigw_pade_eval", "lrigw_g0w0", "lrigw_set_timing", "lrigw_stage_ms", "lrigw_reset_timing",
            "lrigw_surrogate_create", "lrigw_surrogate_destroy", "lrigw_surrogate_info", "lrigw_surrogate_rule",
            "lrigw_surrogate_params", "lrigw_surrogate_basis", "lrigw_surrogate_add", "lrigw_surrogate_rows",
            "lrigw_surrogate_forward", "lrigw_surrogate_grad", "lrigw_surrogate_train", "lrigw_chi0_surrogate",
@@ -107,7 +107,7 @@ def load(path: Optional[str] = None):
         "lrigw_lri_fit": (i, [vp, i, i, i, i, vp, vp, d, vp, ip]),
         "lrigw_lri_fit_noalloc": (i, [vp, i, i, i, i, vp, vp, d, vp, ip]),
         "lrigw_qp": (i, [vp, vp, vp, vp, i, vp, vp, ip]),
-        "lrigw_set_real_grid": (i, [vp, i, d]),
+        "lrigw_set_real_grid": (i, [vp, i, d, d]),
         "lrigw_set_gamma_directions": (i, [vp, i, vp, dp]),
         "lrigw_pade_eval": (i, [vp, vp, i, i, vp, vp]),
         "lrigw_chi0_real": (i, [vp, i, vp, vp, i, vp]),
@@ -115,6 +115,7 @@ def load(path: Optional[str] = None):
         "lrigw_sigma_cd": (i, [vp, i, vp, vp, vp, vp, i, vp, vp]),
         "lrigw_sigma_cd_pass": (i, [vp, vp, vp, vp, vp, vp, vp, d, i, vp, vp, ip]),
         "lrigw_g0w0_cd": (i, [vp, vp, vp, vp, vp, vp, vp, d, vp, d, vp, vp, vp, ip]),
+        "lrigw_qp_cd": (i, [vp, vp, vp, vp, vp, vp, vp, d, vp, d, i, vp, vp, vp, ip]),
         "lrigw_g0w0": (i, [vp, vp, vp, vp, vp, vp, vp, d, vp, i, i, i, vp, vp, vp, ip]),
         "lrigw_set_timing": (i, [vp, i]),
         "lrigw_stage_ms": (d, [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_longlong)]),
@@ -322,8 +323,8 @@ class Context:
         self._gdirs = p_dirs
 
     # ---- contour deformation (real energies) ---------------------------
-    def set_real_grid(self, n_r, omega_max):
-        self._check(self.lib.lrigw_set_real_grid(self.h, int(n_r), float(omega_max)), "lrigw_set_real_grid")
+    def set_real_grid(self, n_r, omega_max, eta=0.0):
+        self._check(self.lib.lrigw_set_real_grid(self.h, int(n_r), float(omega_max), float(eta)), "lrigw_set_real_grid")
         self.n_real = int(n_r)
 
     def empty_real(self):
@@ -366,6 +367,14 @@ class Context:
                                     float(omega_cell), _ptr(e_static), float(delta), _ptr(sigma3), _ptr(e_qp), _ptr(z),
                                     ctypes.byref(bad))
         self._check(rc, "lrigw_g0w0_cd", allow_warn=True)
+        return rc, bad.value
+
+    def qp_cd(self, H, evec, eig, V, p, omega_cell, e_static, delta, n_iter, e_qp, z, sigma3=None, Vcut=None):
+        bad = ctypes.c_int(0)
+        rc = self.lib.lrigw_qp_cd(self.h, _ptr(H), _ptr(evec), _ptr(eig), _ptr(V), _ptr(Vcut), _ptr(p),
+                                  float(omega_cell), _ptr(e_static), float(delta), int(n_iter), _ptr(sigma3), _ptr(e_qp),
+                                  _ptr(z), ctypes.byref(bad))
+        self._check(rc, "lrigw_qp_cd", allow_warn=True)
         return rc, bad.value
 
     def pade_eval(self, sigma, n_par, E, out):
@@ -587,14 +596,35 @@ class Batch:
             pass
 
 
-def device_inputs(sysm, device="cuda"):
-    """Copy the arrays of a synthetic cell to the device (torch tensors)."""
+def device_inputs(sysm, device="cuda", lri_blocks=None, progress=None):
+    """Copy the arrays of a synthetic cell to the device (torch tensors).  A
+    cell that does not hold its LRI coefficients (lri None) takes them from
+    `lri_blocks`, the atoms' blocks in order, each copied into its slice of
+    the device array as it comes (the host holds one block at a time);
+    progress(A) is called after atom A's block."""
     import torch
     t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt)
+    if sysm.lri is None:
+        if lri_blocks is None:
+            raise ValueError("the cell holds no LRI coefficients: pass lri_blocks")
+        off = np.asarray(sysm.lri_off, dtype=np.int64)
+        lri = torch.empty(int(off[-1]), dtype=torch.float64, device=device)
+        n = 0
+        for A, blk in enumerate(lri_blocks):
+            if A >= len(off) - 1 or blk.size != off[A + 1] - off[A]:
+                raise ValueError(f"LRI block {A} does not match the cell's offsets")
+            lri[int(off[A]):int(off[A + 1])].copy_(torch.from_numpy(np.ascontiguousarray(blk).reshape(-1)))
+            n += 1
+            if progress is not None:
+                progress(A)
+        if n != len(off) - 1:
+            raise ValueError("fewer LRI blocks than atoms")
+    else:
+        lri = t(sysm.lri, torch.float64)
     out = dict(
         eig=t(sysm.eig, torch.float64),
         evec=t(sysm.evec, torch.complex128),
-        lri=t(sysm.lri, torch.float64),
+        lri=lri,
         V=t(sysm.V, torch.complex128),
         p=t(sysm.p, torch.complex128),
         e_static=t(sysm.e_static, torch.float64),

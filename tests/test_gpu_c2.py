@@ -117,37 +117,48 @@ def test_sampled_q_every_sigma_variant(c2, precision):
     ctx.close()
 
 
-def test_full_pass_forms_agree(c2):
-    """Whole pass in every precision form.  Against the plain FP64 path, the QP
-    energies of quasiparticle-like solutions (0.5 <= Z <= 1; Z near 0 marks a
-    root next to a pole of the continued fraction, where the continuation is
-    ill-conditioned) agree within 1 meV for the FP32, three-part and mixed BF16
-    and two-part FP16 forms and within 3 meV for the two-part BF16 form."""
+def test_full_pass_against_oracle_qp(c2):
+    """Whole pass of every precision form against the FP64 oracle's whole pass
+    (tests/golden/c2_qp.npz), per state.  The plain FP64 path meets the
+    oracle to 1e-3 meV on all 1728 states.  The reduced-precision forms carry
+    ~1e-7 relative error in Sigma^c(i w), which the Pade continuation
+    amplifies (tests/test_oracle_c2_conditioning.py); they are held to their
+    bound on the quasiparticle-like states (0.5 <= Z <= 1 in the oracle's
+    pass) and to a looser one on all states, and both maxima are printed.
+    The tuned tiles (the benchmark's configuration) are used for every
+    reduced form."""
+    import os
+    gold = os.path.join(HERE, "golden", "c2_qp.npz")
+    if not os.path.exists(gold):
+        pytest.skip("oracle whole-pass values not written")
     L, s, dev = c2["L"], c2["s"], c2["dev"]
     sp = s.spec
-    out = {}
+    g = np.load(gold)
+    assert int(g["seed"]) == s.seed
+    E_o, S_o = g["E"], g["sigma"]
+    good = (g["Z"] >= 0.5) & (g["Z"] <= 1.0)
+    print(f"\n[gpu c2] {int(good.sum())} of {good.size} states quasiparticle-like in the oracle's pass", flush=True)
+    bounds = {"fp32": (1.0, 5.0), "split3_bf16": (1.0, 5.0), "split_mixed": (1.0, 5.0), "split_f16": (1.0, 5.0),
+              "split_bf16": (3.0, 10.0)}
     for precision in ("fp64", "fp32", "split3_bf16", "split_mixed", "split_f16", "split_bf16"):
         print(f"[gpu c2] full pass {precision}", flush=True)
         ctx = L.Context.from_system(s, precision=precision)
         H = ctx.empty("H")
         ctx.lri_ft(dev["lri"], s.R, dev["evec"], H)
         if precision != "fp64":
-            # the tile and kernel choices the benchmark runs with
             print(f"  tuned: {ctx.tune(H, dev['evec'], dev['eig'])}", flush=True)
         sigma = torch.zeros((s.n_k, sp.n_qp, sp.n_freq), dtype=torch.complex128, device="cuda")
         e = torch.zeros((s.n_k, sp.n_qp), dtype=torch.float64, device="cuda")
         z = torch.zeros_like(e)
         ctx.g0w0(H, dev["evec"], dev["eig"], dev["V"], dev["p"], s.omega_cell, dev["e_static"], 16, sigma, e, z)
-        out[precision] = (sigma.cpu().numpy(), e.cpu().numpy(), z.cpu().numpy())
+        sg, ev = sigma.cpu().numpy(), e.cpu().numpy()
         ctx.close()
-    s64, e64, z64 = out["fp64"]
-    assert np.all(np.isfinite(s64)) and np.all(np.isfinite(e64))
-    reg = (z64 >= 0.5) & (z64 <= 1.0)
-    assert reg.mean() > 0.9
-    for precision, bound in (("fp32", 1.0), ("split3_bf16", 1.0), ("split_mixed", 1.0), ("split_f16", 1.0),
-                             ("split_bf16", 3.0)):
-        sg, e, z = out[precision]
-        d = np.abs(e - e64) * HA_MEV
-        print(f"  {precision} vs fp64: max|dSigma| = {np.max(np.abs(sg - s64)):.3e} Ha, QP max {d.max():.3f} meV, "
-              f"quasiparticle-like max {d[reg].max():.3f} meV, median {np.median(d):.4f} meV", flush=True)
-        assert d[reg].max() < bound
+        ds = np.max(np.abs(sg - S_o)) / np.max(np.abs(S_o))
+        d = np.abs(ev - E_o) * HA_MEV
+        print(f"  {precision} vs oracle: Sigma^c rel {ds:.2e}; QP all states max {d.max():.4f} meV, median "
+              f"{np.median(d):.5f} meV; quasiparticle-like max {d[good].max():.4f} meV, "
+              f"{int((d > 1.0).sum())} states over 1 meV", flush=True)
+        if precision == "fp64":
+            assert ds < 1e-10 and d.max() < 1e-3
+        else:
+            assert ds < 1e-5 and d[good].max() < bounds[precision][0] and d.max() < bounds[precision][1]

@@ -316,3 +316,68 @@ def test_si_like_against_pade_continuation():
           f"max {d.max():.2f} meV (lrigw_pade_eval: max {dd.max():.2f} meV); |Sigma^c(e)| up to "
           f"{np.abs(cd[ok]).max() * HA_MEV:.0f} meV", flush=True)
     assert ok.sum() > 0 and d.max() < 2.0 and dd.max() < 2.0
+
+
+# ---- every state: the broadened real grid (W^c at w_r + i eta)
+ETA = 0.05
+
+
+def _broad_grid(s, E):
+    # every |E - e_m| lies below this
+    top = max(float(E.max() - s.eig.min()), float(s.eig.max() - E.min())) + 0.02
+    h = ETA / 4
+    n_r = int(np.ceil(top / h)) + 1
+    return n_r, (n_r - 1) * h
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("split_f16", 2e-5), ("fp32", 2e-5)])
+def test_broadened_pass_every_state(case, precision, tol):
+    """Sigma^c at energies across every band (residues far above the first
+    transition), whole pass with the broadened grid, against the oracle's
+    contour deformation on the same grid."""
+    s, o, dev, L = case["sys"], case["o"], case["dev"], case["L"]
+    if s.spec.n_freq < 2:
+        pytest.skip("n_freq < 2")
+    E = np.random.default_rng(8).uniform(s.eig.min() - 0.05, s.eig.max() + 0.05, (2, s.n_k, s.spec.n_qp))
+    n_r, wmax = _broad_grid(s, E)
+    print(f"  {case['name']} {precision}: broadened grid {n_r} nodes to {wmax:.3f} Ha", flush=True)
+    ctx = L.Context.from_system(s, precision=precision)
+    ctx.set_real_grid(n_r, wmax, ETA)
+    H = ctx.empty("H")
+    ctx.lri_ft(dev["lri"], s.R, dev["evec"], H)
+    Ed = torch.from_numpy(np.ascontiguousarray(E)).cuda()
+    out = torch.zeros_like(Ed)
+    rc, bad = ctx.sigma_cd_pass(H, dev["evec"], dev["eig"], dev["V"], dev["p"], s.omega_cell, Ed, out)
+    assert rc == L.LRIGW_OK and bad == 0
+    got = out.cpu().numpy()
+    ref = o.sigma_cd(n_r, wmax, E, eta=ETA)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    print(f"    Sigma^c(E) rel. {err:.2e}", flush=True)
+    assert np.all(np.isfinite(got)) and err < tol
+    ctx.close()
+
+
+def test_broadened_qp_newton(case):
+    """lrigw_qp_cd (three Newton steps, broadened grid) against the oracle's
+    Newton steps, every state evaluated (FP64)."""
+    s, o, dev, L = case["sys"], case["o"], case["dev"], case["L"]
+    if s.spec.n_freq < 2:
+        pytest.skip("n_freq < 2")
+    # the Newton iterates stay within 0.6 Ha of the band range
+    span = np.array([s.eig.min() - 0.6, s.eig.max() + 0.6])
+    n_r, wmax = _broad_grid(s, span)
+    ctx = L.Context.from_system(s, precision="fp64")
+    ctx.set_real_grid(n_r, wmax, ETA)
+    H = ctx.empty("H")
+    ctx.lri_ft(dev["lri"], s.R, dev["evec"], H)
+    e = torch.zeros((s.n_k, s.spec.n_qp), dtype=torch.float64, device="cuda")
+    z = torch.zeros_like(e)
+    rc, bad = ctx.qp_cd(H, dev["evec"], dev["eig"], dev["V"], dev["p"], s.omega_cell, dev["e_static"], 0.002, 3, e, z)
+    assert rc == L.LRIGW_OK and bad == 0
+    Eo, Zo, _ = o.qp_cd(n_r, wmax, ETA, 3, delta=0.002)
+    d = np.abs(e.cpu().numpy() - Eo) * HA_MEV
+    print(f"  {case['name']}: QP by Newton on the broadened grid, max {d.max():.2e} meV from the oracle; "
+          f"shifts {np.abs(Eo - s.eig[:, s.spec.qp_lo:s.spec.qp_lo + s.spec.n_qp]).max():.3f} Ha", flush=True)
+    assert np.all(np.isfinite(e.cpu().numpy())) and d.max() < 1e-4
+    assert np.max(np.abs(z.cpu().numpy() - Zo)) < 1e-8
+    ctx.close()

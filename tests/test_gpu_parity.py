@@ -178,7 +178,7 @@ def test_sigma_c_accumulates_per_q(case):
 @pytest.mark.parametrize("precision", ["split_bf16", "split3_bf16", "split_f16"])
 def test_every_tile_variant(case, precision):
     """Each tile choice the tuner may pick (response: frequencies per workgroup
-    x LDS padding; self-energy: every variant, the resident-tile ones (7-10)
+    x LDS padding; self-energy: every variant, the resident-tile ones (7-12)
     for the FP16 form) gives the oracle's chi0 and Sigma^c contribution within
     the form's tolerance."""
     s, o, dev = case["sys"], case["o"], case["dev"]
@@ -196,7 +196,7 @@ def test_every_tile_variant(case, precision):
     n = s.n_aux
     sp = s.spec
     nw_choices = (4, 2)
-    for var in range(11 if precision == "split_f16" else 7):
+    for var in range(ctx.get_tiles()[4] if precision == "split_f16" else 7):
         # the partial-tile buffer of this small cell holds one K split
         nw, pad, splits = nw_choices[var % 2], (8, 16)[(var // 2) % 2], 1
         ctx.set_tiles(nw, splits, pad, var)
