@@ -88,12 +88,19 @@ def mo_triple_per_atom(Lk2, Lmk1, basis_off, aux_off, c1, c2):
 class TripleBuilder:
     """Forms C^mu_{mn}(k1,k2) for any pair of grid points of one cell."""
 
-    def __init__(self, sysm, kfrac, per_atom=False):
+    def __init__(self, sysm, kfrac, per_atom=False, blocks=None):
+        """blocks: the atoms' real-space blocks in order (any iterable, taken
+        one at a time); default the cell's own array."""
         self.sys = sysm
         self.per_atom = per_atom
-        blocks = [sysm.lri_block(A) for A in range(sysm.spec.n_atoms)]
-        self.Lk = lri_bloch(blocks, sysm.R, kfrac)          # at +k
-        self.Lmk = lri_bloch(blocks, sysm.R, -kfrac)        # at -k (own transform)
+        if blocks is None:
+            blocks = (sysm.lri_block(A) for A in range(sysm.spec.n_atoms))
+        self.Lk, self.Lmk = [], []
+        for blk in blocks:
+            self.Lk += lri_bloch([blk], sysm.R, kfrac)      # at +k
+            self.Lmk += lri_bloch([blk], sysm.R, -kfrac)    # at -k (own transform)
+        if len(self.Lk) != sysm.spec.n_atoms:
+            raise ValueError("one block per atom expected")
 
     def ao(self, k1, k2):
         s = self.sys

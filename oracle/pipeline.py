@@ -23,15 +23,16 @@ from . import grids, lri, response, screening, selfenergy, continuation, contour
 
 
 class Oracle:
-    def __init__(self, sysm, n_par=16, per_atom=False):
+    def __init__(self, sysm, n_par=16, per_atom=False, lri_blocks=None):
         self.sys = sysm
         sp = sysm.spec
         self.kint, self.kfrac = grids.kgrid(sp.nk)
         self.kpq, self.kmq, self.minus = grids.kq_tables(sp.nk)
         self.omega, self.weight = grids.frequency_grid(sp.n_freq, sp.x0)
         # per_atom: triples one auxiliary atom at a time (cells too large for
-        # the dense AO tensor); the dense form otherwise
-        self.tb = lri.TripleBuilder(sysm, self.kfrac, per_atom=per_atom)
+        # the dense AO tensor); the dense form otherwise.  lri_blocks: the
+        # coefficients atom by atom when the cell does not hold them
+        self.tb = lri.TripleBuilder(sysm, self.kfrac, per_atom=per_atom, blocks=lri_blocks)
         self.occ = slice(0, sp.n_occ)
         self.unocc = slice(sp.n_occ, sp.n_bands)
         self.qp = slice(sp.qp_lo, sp.qp_lo + sp.n_qp)
@@ -41,10 +42,10 @@ class Oracle:
         self.gamma_dirs = None
 
     # ---- per-q pieces -------------------------------------------------
-    def B(self, q):
-        """C^mu_{ia}(k,k+q): [N_k][N_aux][N_occ][N_unocc]."""
-        return np.stack([self.tb.mo(k, self.kpq[k, q], self.occ, self.unocc)
-                         for k in range(self.sys.n_k)])
+    def B(self, q, ks=None):
+        """C^mu_{ia}(k,k+q): [len(ks)][N_aux][N_occ][N_unocc] (default every k)."""
+        ks = range(self.sys.n_k) if ks is None else ks
+        return np.stack([self.tb.mo(k, self.kpq[k, q], self.occ, self.unocc) for k in ks])
 
     def x(self, q, ks=None):
         """C^mu_{nm}(k,k-q) for QP bands n and all m: [len(ks)][N_aux][N_qp][N_bands]."""
@@ -64,10 +65,13 @@ class Oracle:
         """Sigma^x_n(k) [len(ks)][N_qp], summed over every q."""
         return sum(self.sigma_x_q(q, ks) for q in range(self.sys.n_k))
 
-    def chi0(self, q, B=None, omega=None):
-        B = self.B(q) if B is None else B
+    def chi0(self, q, B=None, omega=None, ks=None):
+        """chi~(q) at `omega` (default the grid).  ks: the k terms of the sum to
+        take (B then holds those rows); the k sum over a partition of the grid
+        adds up to the whole."""
+        B = self.B(q, ks) if B is None else B
         om = self.omega if omega is None else omega
-        return response.chi0_trs(B, self.sys.eig, self.kpq, q, self.sys.n_occ, om)
+        return response.chi0_trs(B, self.sys.eig, self.kpq, q, self.sys.n_occ, om, ks=ks, n_k=self.sys.n_k)
 
     def wc(self, q, chi=None, B=None, gamma=True):
         s = self.sys

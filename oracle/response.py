@@ -43,8 +43,10 @@ def weight(delta, w, real_axis=False, eta=0.0):
     return 2.0 * delta / (delta * delta - z * z)
 
 
-def chi0_trs(B, eig, kpq, q, n_occ, omega, s=SPIN, real_axis=False, eta=0.0):
+def chi0_trs(B, eig, kpq, q, n_occ, omega, s=SPIN, real_axis=False, eta=0.0, ks=None, n_k=None):
     """B: [N_k][N_aux][N_occ][N_unocc] = C^mu_{ia}(k,k+q); returns [N_w][N_aux][N_aux].
+    ks / n_k: B's rows are the k points ks of a grid of n_k points (the terms
+    of those k only; default every k of B).
 
     real_axis: the frequencies are real, w -> -i w in the denominators, so the
     weight is 2D/(D^2 - w^2); with eta = 0 meant for 0 <= w < min D, where it
@@ -53,14 +55,17 @@ def chi0_trs(B, eig, kpq, q, n_occ, omega, s=SPIN, real_axis=False, eta=0.0):
     complex weight makes it a sum of two Hermitian parts, Re and i Im of the
     weight, not Hermitian itself (the broadened response above the first
     transition)."""
-    n_k = B.shape[0]
+    ks = list(range(B.shape[0])) if ks is None else list(ks)
+    n_k = B.shape[0] if n_k is None else n_k
+    if len(ks) != B.shape[0]:
+        raise ValueError("one row of B per k in ks")
     n_aux = B.shape[1]
     cplx = real_axis and eta != 0.0
     out = np.zeros((len(omega), n_aux, n_aux), dtype=np.complex128)
-    for k in range(n_k):
+    for row, k in enumerate(ks):
         kq = kpq[k, q]
         delta = eig[kq][n_occ:][None, :] - eig[k][:n_occ][:, None]     # [occ][unocc]
-        Bk = B[k].reshape(n_aux, -1)
+        Bk = B[row].reshape(n_aux, -1)
         for iw, w in enumerate(omega):
             wt = weight(delta, w, real_axis, eta).reshape(-1)
             out[iw] += (Bk * wt[None, :]) @ Bk.conj().T

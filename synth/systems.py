@@ -108,7 +108,7 @@ class System:
     aux_off: np.ndarray        # int32 [n_atoms+1]
     lattice: np.ndarray        # float64 [3][3], rows = primitive vectors (bohr)
     R: np.ndarray              # int32 [nR][3]
-    lri: np.ndarray            # float64 flat, per atom [nR][naux_A][nb_A][N_b]
+    lri: Optional[np.ndarray]  # float64 flat, per atom [nR][naux_A][nb_A][N_b]; None: not materialised
     lri_off: np.ndarray        # int64 [n_atoms+1] element offsets into lri
     eig: np.ndarray            # float64 [N_k][N_bands]
     evec: np.ndarray           # complex128 [N_k][N_b][N_bands]
@@ -144,6 +144,8 @@ class System:
     def lri_block(self, atom: int) -> np.ndarray:
         """The [nR][naux_A][nb_A][N_b] view of atom `atom`'s coefficients."""
         s = self.spec
+        if self.lri is None:
+            raise ValueError("the coefficients of this cell are not materialised (use lri_blocks)")
         nR = self.R.shape[0]
         na = int(self.aux_off[atom + 1] - self.aux_off[atom])
         nb = int(self.basis_off[atom + 1] - self.basis_off[atom])
@@ -180,9 +182,12 @@ def _inscribed_radius(vectors: np.ndarray) -> float:
 
 
 def make_system(spec: CellSpec, seed: int, *, lri_scale: float = 1.0,
-                p_scale: float = 1.0) -> System:
+                p_scale: float = 1.0, materialize_lri: bool = True) -> System:
     """Draw one synthetic cell.  `lri_scale`/`p_scale` multiply the LRI and
-    momentum arrays (0 gives the zero-coupling limits used in tests)."""
+    momentum arrays (0 gives the zero-coupling limits used in tests).
+    materialize_lri=False leaves `lri` None (the other arrays are unchanged:
+    the coefficients draw from a stream of their own); `lri_blocks` then
+    yields them atom by atom."""
     rng_eig, rng_vec, rng_lri, rng_v, rng_p, _ = np.random.default_rng(seed).spawn(6)
     nk = spec.nk
     n_k, n_b, n_aux, n_occ = spec.n_k, spec.n_b, spec.n_aux, spec.n_occ
@@ -219,21 +224,17 @@ def make_system(spec: CellSpec, seed: int, *, lri_scale: float = 1.0,
                     + 1j * rng_p.normal(0.0, math.sqrt(0.125), (n_occ, n_unocc)))
     p *= p_scale
 
-    # real-space two-centre coefficients, |n_i| <= rmax
-    rr = range(-spec.rmax, spec.rmax + 1)
-    R = np.array([(a, b, c) for a in rr for b in rr for c in rr], dtype=np.int32)
-    nR = R.shape[0]
-    amp = np.exp(-np.linalg.norm(R @ lat, axis=1) / 2.0)
-    blocks = []
+    # real-space two-centre coefficients, |n_i| <= rmax, filled in place atom
+    # by atom (the 16-atom cell's array is 50 GB)
+    R = lattice_vectors(spec)
     lri_off = [0]
     for A in range(spec.n_atoms):
-        na = spec.naux_per_atom
-        nb = spec.nb_per_atom
-        blk = rng_lri.standard_normal((nR, na, nb, n_b))
-        blk *= (amp * (spec.lri_amplitude * lri_scale))[:, None, None, None]
-        blocks.append(blk.reshape(-1))
-        lri_off.append(lri_off[-1] + blk.size)
-    lri = np.concatenate(blocks)
+        lri_off.append(lri_off[-1] + R.shape[0] * spec.naux_per_atom * spec.nb_per_atom * n_b)
+    lri = None
+    if materialize_lri:
+        lri = np.empty(lri_off[-1])
+        for _ in _lri_blocks(spec, rng_lri, lat, lri_scale, lri):
+            pass
 
     # Coulomb matrices
     recip = 2.0 * math.pi * np.linalg.inv(lat).T  # rows = reciprocal vectors
@@ -292,6 +293,34 @@ def truncated_coulomb(sysm: System) -> np.ndarray:
         q2 = float(qc @ qc)
         Vc[q, 0, 0] -= 4.0 * math.pi * math.cos(math.sqrt(q2) * r_cut) / q2
     return Vc
+
+
+def lattice_vectors(spec: CellSpec) -> np.ndarray:
+    """The R of the two-centre coefficients, integer [nR][3], |n_i| <= rmax."""
+    rr = range(-spec.rmax, spec.rmax + 1)
+    return np.array([(a, b, c) for a in rr for b in rr for c in rr], dtype=np.int32)
+
+
+def _lri_blocks(spec: CellSpec, rng, lat, lri_scale=1.0, out=None):
+    """Yield atom A's block [nR][naux_A][nb_A][N_b] of the real-space
+    coefficients in generator order (into `out`, the flat array, if given)."""
+    R = lattice_vectors(spec)
+    nR = R.shape[0]
+    amp = np.exp(-np.linalg.norm(R @ lat, axis=1) / 2.0) * (spec.lri_amplitude * lri_scale)
+    shape = (nR, spec.naux_per_atom, spec.nb_per_atom, spec.n_b)
+    size = int(np.prod(shape))
+    for A in range(spec.n_atoms):
+        blk = out[A * size:(A + 1) * size].reshape(shape) if out is not None else np.empty(shape)
+        rng.standard_normal(out=blk)
+        blk *= amp[:, None, None, None]
+        yield blk
+
+
+def lri_blocks(spec: CellSpec, seed: int, lri_scale: float = 1.0):
+    """Atom by atom, the real-space coefficient blocks make_system(spec, seed)
+    draws, without holding the others (the same generator stream)."""
+    rng_lri = np.random.default_rng(seed).spawn(6)[2]
+    yield from _lri_blocks(spec, rng_lri, _lattice(spec), lri_scale)
 
 
 def momentum_vectors(sysm: System) -> np.ndarray:

@@ -121,3 +121,56 @@ def test_contour_deformation_against_pade(c4):
     print(f"  contour pass {dt:.1f} s, {ok.sum()} band-edge states: |Sigma_CD - Sigma_Pade| median {np.median(d):.3f} "
           f"meV, max {d.max():.3f} meV", flush=True)
     assert rc >= 0 and ok.sum() > 0 and d.max() < 5.0
+
+
+def test_sampled_q_against_oracle(c4):
+    """The tuned FP16 form (the streaming self-energy kernel and the
+    multi-block Cholesky of N_aux 1040) and the plain FP64 path against the
+    oracle's values for two q (q = 0 with the Gamma treatment) written by
+    tests/golden/make_c4_golden.py with the per-atom triples: chi0 and W^c
+    rows at three frequencies, and the Sigma^c contribution at three k."""
+    import os
+    gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c4_sampled.npz")
+    if not os.path.exists(gold):
+        pytest.skip("c4_sampled.npz not written")
+    L, s, dev, ctx_f16, H16 = c4
+    g = np.load(gold)
+    assert int(g["seed"]) == s.seed
+    sp = s.spec
+    n = s.n_aux
+    rows = int(g["ROWS"])
+    widx, kidx = g["W_IDX"], g["K_IDX"]
+
+    def relf(a, b):
+        return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+    for precision, tol in (("split_f16", 1e-5), ("fp64", 1e-10)):
+        if precision == "split_f16":
+            ctx, H = ctx_f16, H16
+        else:
+            ctx = L.Context.from_system(s, precision="fp64")
+            H = ctx.empty("H")
+            ctx.lri_ft(dev["lri"], s.R, dev["evec"], H)
+        ctx.gamma_prepare(dev["V"][0], dev["p"], s.omega_cell)
+        M, x, chi, W = ctx.empty("M"), ctx.empty("x"), ctx.empty("W"), ctx.empty("W")
+        for q in g["Q"]:
+            q = int(q)
+            ctx.build_M(q, 0, H, dev["evec"], M)
+            ctx.chi0(q, M, dev["eig"], chi)
+            c = chi.cpu().numpy().reshape(-1, n, n)[widx, :rows]
+            ec = relf(c, g[f"chi_q{q}"])
+            if q == 0:
+                ctx.chi0(0, M, dev["eig"], chi, apply_gamma=True)
+            ctx.screen(q, chi, dev["V"][q], W)
+            w = W.cpu().numpy().reshape(-1, n, n)[widx, :rows]
+            ew = relf(w, g[f"wc_q{q}"])
+            ctx.build_M(q, 1, H, dev["evec"], x)
+            sig = torch.zeros((s.n_k, sp.n_qp, sp.n_freq), dtype=torch.complex128, device="cuda")
+            ctx.sigma_c(q, x, W, dev["eig"], sig)
+            ref = g[f"sigma_q{q}"]
+            es = np.max(np.abs(sig.cpu().numpy()[kidx] - ref)) / np.max(np.abs(ref))
+            print(f"  c4 q={q} {precision} (tiles {ctx.tiles}): chi {ec:.2e}  Wc {ew:.2e}  Sigma_q {es:.2e}", flush=True)
+            assert ec < tol and ew < 10 * tol and es < 10 * tol
+        del M, x, chi, W
+        if precision == "fp64":
+            ctx.close()

@@ -1,0 +1,109 @@
+"""GPU, the 16-atom stress workload at full size (N_b 624, N_aux 2080, 3x3x3 k,
+32 occupied of 624 bands, 48 frequencies), tuned FP16 form.  The host never
+holds the 50 GB of LRI coefficients: they are drawn atom by atom and copied
+into the device array as they come.  Checks: one sampled q against the
+oracle's values (chi~ and W^c rows at three frequencies, written by
+tests/golden/make_c5_golden.py with triples formed one auxiliary atom at a
+time), and the whole pass by properties that hold at any size (every
+screening positive definite, finite Sigma^c(i w), Sigma^x negative, finite
+QP energies with renormalisation factors in (0, 1]).
+
+The workload takes several minutes (drawing 50 GB of coefficients, then the
+pass), so it runs only when LRIGW_C5=1 is set."""
+import os
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(os.environ.get("LRIGW_C5") != "1", reason="16-atom workload: set LRIGW_C5=1")]
+
+torch = pytest.importorskip("torch")
+
+from synth.systems import lri_blocks, make_config
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c5_sampled.npz")
+
+
+@pytest.fixture(scope="module")
+def c5():
+    from paper_2011_01400_amd import lrigw as L
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L.load()
+    t0 = time.perf_counter()
+    s = make_config(5, materialize_lri=False)
+    print(f"\n[gpu c5] inputs without coefficients (N_aux {s.n_aux}, {s.n_k} k, {s.spec.n_freq} w) in "
+          f"{time.perf_counter() - t0:.1f} s", flush=True)
+    dev = L.device_inputs(s, lri_blocks=lri_blocks(s.spec, s.seed),
+                          progress=lambda A: print(f"  atom {A} on the device after {time.perf_counter() - t0:.1f} s",
+                                                   flush=True))
+    ctx = L.Context.from_system(s, precision="split_f16")
+    H = ctx.empty("H")
+    ctx.lri_ft(dev["lri"], s.R, dev["evec"], H)
+    torch.cuda.synchronize()
+    del dev["lri"]          # 50 GB, needed only by the transform
+    torch.cuda.empty_cache()
+    print(f"  transform done after {time.perf_counter() - t0:.1f} s", flush=True)
+    print(f"  tuned {ctx.tune(H, dev['evec'], dev['eig'])} after {time.perf_counter() - t0:.1f} s", flush=True)
+    return L, s, dev, ctx, H
+
+
+def test_sampled_q_against_oracle(c5):
+    if not os.path.exists(GOLD):
+        pytest.skip("c5_sampled.npz not written")
+    L, s, dev, ctx, H = c5
+    g = np.load(GOLD)
+    assert int(g["seed"]) == s.seed
+    n = s.n_aux
+    q = int(g["Q"])
+    widx, rows = g["W_IDX"], g["ROWS"]
+    M, chi, W = ctx.empty("M"), ctx.empty("W"), ctx.empty("W")
+    ctx.build_M(q, 0, H, dev["evec"], M)
+    ctx.chi0(q, M, dev["eig"], chi)
+    c = chi.cpu().numpy().reshape(-1, n, n)[widx]
+    ctx.screen(q, chi, dev["V"][q], W)
+    w = W.cpu().numpy().reshape(-1, n, n)[widx]
+
+    def relf(a, b):
+        return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+    e = [relf(c[:, rows], g["chi_rows"]), relf(np.einsum("wii->wi", c), g["chi_diag"]),
+         relf(w[:, rows], g["wc_rows"]), relf(np.einsum("wii->wi", w), g["wc_diag"])]
+    print(f"  c5 q={q} split_f16 (tiles {ctx.tiles}): chi rows {e[0]:.2e} diag {e[1]:.2e}; "
+          f"W^c rows {e[2]:.2e} diag {e[3]:.2e}", flush=True)
+    assert max(e[:2]) < 1e-5 and max(e[2:]) < 1e-4
+    del M, chi, W
+
+
+def test_whole_pass(c5):
+    L, s, dev, ctx, H = c5
+    sp = s.spec
+    sx = torch.zeros((s.n_k, sp.n_qp), dtype=torch.float64, device="cuda")
+    ctx.sigma_x_pass(H, dev["evec"], dev["V"], sx)
+    sg = torch.zeros((s.n_k, sp.n_qp, sp.n_freq), dtype=torch.complex128, device="cuda")
+    part = torch.zeros_like(sg)
+    e = torch.zeros((s.n_k, sp.n_qp), dtype=torch.float64, device="cuda")
+    z = torch.zeros_like(e)
+    t0 = time.perf_counter()
+    for q in range(s.n_k):
+        # one q per call (each call sets its output to that q's terms)
+        rc, info = ctx.g0w0(H, dev["evec"], dev["eig"], dev["V"], dev["p"], s.omega_cell, dev["e_static"], 16, part,
+                            e, z, q_first=q, q_last=q + 1)
+        sg += part
+        torch.cuda.synchronize()
+        print(f"  q={q} done after {time.perf_counter() - t0:.1f} s (rc {rc}, info {info})", flush=True)
+        assert rc >= 0
+    dt = time.perf_counter() - t0
+    eps = torch.from_numpy(np.ascontiguousarray(s.eig[:, sp.qp_lo:sp.qp_lo + sp.n_qp])).cuda()
+    rc, info = ctx.qp(sg, eps, dev["e_static"], 16, e, z)
+    sgh, ev, zv, sxv = sg.cpu().numpy(), e.cpu().numpy(), z.cpu().numpy(), sx.cpu().numpy()
+    print(f"  pass {dt:.1f} s, one q per call ({s.n_k * sp.n_freq / dt:.1f} (q, w) pairs/s); QP rc {rc} info {info}; "
+          f"Sigma^x in [{sxv.min():.3f}, {sxv.max():.3f}] Ha; QP shifts up to "
+          f"{np.abs(ev - s.eig[:, sp.qp_lo:sp.qp_lo + sp.n_qp]).max():.3f} Ha, Z in [{zv.min():.3f}, {zv.max():.3f}]",
+          flush=True)
+    assert rc >= 0
+    assert np.all(np.isfinite(sgh)) and np.all(np.isfinite(ev))
+    assert np.all(sxv < 0.0)
+    assert np.all((zv > 0.0) & (zv <= 1.0 + 1e-9))

@@ -153,3 +153,26 @@ def test_per_atom_triples_expand_rig_products_exactly():
             lhs = psi[k1].conj()[:, None, :] * psi[k2][None, :, :]
             rhs = np.einsum("umn,ux->mnx", C, Pq[(k1 - k2) % NK].conj())
             assert np.max(np.abs(lhs - rhs)) < 1e-13
+
+
+def test_streamed_blocks_and_k_partition():
+    """An oracle fed the coefficients atom by atom (the cell not holding them)
+    forms the same triples; chi~ summed over a partition of the k grid is the
+    whole k sum."""
+    from synth.systems import lri_blocks, make_system
+    s = make_custom(n_atoms=2, nb_per_atom=5, naux_per_atom=9, nk=(3, 1, 2), n_occ=3, n_freq=6, seed=17)
+    bare = make_system(s.spec, s.seed, materialize_lri=False)
+    o = Oracle(s, per_atom=True)
+    ob = Oracle(bare, per_atom=True, lri_blocks=lri_blocks(s.spec, s.seed))
+    for q in (0, 4):
+        B = o.B(q)
+        assert np.array_equal(B, ob.B(q))
+        full = o.chi0(q, B)
+        parts = [[0, 3], [1, 4, 5], [2]]
+        tot = sum(ob.chi0(q, ks=ks) for ks in parts)
+        assert np.max(np.abs(tot - full)) < 1e-14 * np.max(np.abs(full))
+        sub = ob.chi0(q, omega=o.omega[[1, 4]], ks=[1, 2])
+        ref = o.chi0(q, B[[1, 2]], omega=o.omega[[1, 4]], ks=[1, 2])
+        assert np.array_equal(sub, ref)
+    with pytest.raises(ValueError):
+        Oracle(bare)
