@@ -529,9 +529,11 @@ int lrigw_tune(lrigw_ctx *ctx, const void *H, const void *evec, const double *ei
 
 /* Set the tile choices lrigw_tune would pick, explicitly: nw = frequencies per
  * response workgroup (the form's default or its alternative: 4/2 in the FP32
- * and split forms, 2/1 in FP64), splits = K splits (the partial-tile buffer
- * must hold them; in the split forms at least ceil(K/4096), K = N_k n_occ
- * n_unocc, so no workgroup sums more than 4096 rows in FP32), pad = LDS row padding of the split-form response kernel (8
+ * and split forms, 2/1 in FP64), splits = K splits, 1..max(1, K/64), K =
+ * N_k n_occ n_unocc (in the split forms at least ceil(K/4096), so no
+ * workgroup sums more than 4096 rows in FP32; splits beyond what the
+ * context's partial-tile buffer of at most 3 GiB holds run in batches whose
+ * results are added up in the output), pad = LDS row padding of the split-form response kernel (8
  * or 16), sigma_variant = split-form self-energy kernel variant (0..12; 7 to
  * 12, the resident-tile form with 8 or 4 waves and LDS rows padded by 8 or
  * 16, or (11, 12) the per-tile sum taking x from global memory, need the

@@ -40,10 +40,6 @@ static int autotune_chi0(lrigw_ctx *c, const lrigw_batch_cell &cell, int *nw_out
   LRIGW_TRY(run_build_M(c, q, 0, cell.H, cell.evec, c->d_M));
   const int nw0 = c->chi_nw, S0 = c->chi_splits;
   std::vector<int> nws = {chi0_default_nw(c->precision), chi0_alt_nw(c->precision)};
-  const int nt = (d.n_aux + 63) / 64;
-  const size_t ntile = (size_t)nt * (nt + 1) / 2;
-  const size_t per = (size_t)d.n_freq * ntile * 64 * 64 * lrigw_csize(c);
-  const long long Smax = std::max<long long>(1, (long long)(c->part_bytes / per));
   double best = INFINITY;
   int bnw = nw0, bS = S0;
   hipEvent_t e0, e1;
@@ -64,7 +60,6 @@ static int autotune_chi0(lrigw_ctx *c, const lrigw_batch_cell &cell, int *nw_out
     std::sort(Ss.begin(), Ss.end());
     Ss.erase(std::unique(Ss.begin(), Ss.end()), Ss.end());
     for (int S : Ss) {
-      if (S > Smax) continue;
       if ((long long)S < chi0_min_splits(c, lrigw_K(c))) continue;
       if ((long long)S > std::max<long long>(1, lrigw_K(c) / 64)) continue;
       c->chi_splits = S;
@@ -274,10 +269,7 @@ int lrigw_set_tiles(lrigw_ctx *c, int nw, int splits, int pad, int sigma_variant
   if (nw != dnw && nw != anw) return LRIGW_ERR_ARG;
   if (pad != 8 && pad != 16) return LRIGW_ERR_ARG;
   if (!sigma_variant_ok(c, sigma_variant)) return LRIGW_ERR_ARG;
-  const Dims &d = c->d;
-  const int nt = (d.n_aux + 63) / 64;
-  const size_t per = (size_t)d.n_freq * ((size_t)nt * (nt + 1) / 2) * 64 * 64 * lrigw_csize(c);
-  if (splits < 1 || (size_t)splits * per > c->part_bytes || (long long)splits > std::max<long long>(1, lrigw_K(c) / 64) ||
+  if (splits < 1 || (long long)splits > std::max<long long>(1, lrigw_K(c) / 64) ||
       (long long)splits < chi0_min_splits(c, lrigw_K(c)))
     return LRIGW_ERR_ARG;
   c->chi_nw = nw;

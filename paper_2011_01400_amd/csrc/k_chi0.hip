@@ -472,11 +472,13 @@ store:
   }
 }
 
-// chi[w][mu][nu] = scale * sum_s part[s][w][tile][..]; upper triangle by Hermitian symmetry.
+// chi[w][mu][nu] = scale * sum_s part[s][w][tile][..] (accumulate: added to
+// chi's lower half as it stands); upper triangle by Hermitian symmetry.
 template <typename T>
 __global__ __launch_bounds__(256) void k_chi0_reduce(const typename c2t<T>::type *__restrict__ part, int S, int n_freq,
                                                      long long ntile, int N, double scale, const int *__restrict__ wsel,
-                                                     const int *__restrict__ run, typename c2t<T>::type *__restrict__ chi) {
+                                                     const int *__restrict__ run, int accumulate,
+                                                     typename c2t<T>::type *__restrict__ chi) {
   // one workgroup per (lower tile, frequency): the K-split partial tiles are
   // summed in FP64 along the tile's rows; the lower half of chi is written
   // along those rows, the mirrored upper half (conjugated) along the tile's
@@ -524,10 +526,16 @@ __global__ __launch_bounds__(256) void k_chi0_reduce(const typename c2t<T>::type
   for (int e = 0; e < E; ++e) {
     const int idx = e * 256 + tid, r = idx >> 6, cc = idx & 63;
     double2 z = mkc(scale * sr[e], scale * si[e]);
+    const bool mine = mu0 + r < N && nu0 + cc < N && (I != J || cc <= r);
+    if (accumulate && mine) {
+      const CT o = dst[(long long)(mu0 + r) * N + nu0 + cc];
+      z.x += (double)o.x;
+      z.y += (double)o.y;
+    }
     if (I == J && r == cc) z.y = 0.0;
     const CT v = to_c<T>(z);
     tr[r][cc] = v;
-    if (mu0 + r < N && nu0 + cc < N && (I != J || cc <= r)) dst[(long long)(mu0 + r) * N + nu0 + cc] = v;
+    if (mine) dst[(long long)(mu0 + r) * N + nu0 + cc] = v;
   }
   __syncthreads();
 #pragma unroll
@@ -542,7 +550,9 @@ __global__ __launch_bounds__(256) void k_chi0_reduce(const typename c2t<T>::type
   }
 }
 
-// Number of K splits: enough workgroups to fill the device, partial buffer <= 2 GiB.
+// Number of K splits: enough workgroups to fill the device; in the split
+// forms at most 2048 rows each.  The partial-tile buffer holds
+// chi0_batch_splits of them; more are taken in batches (run_chi0_tab).
 int chi0_plan_splits(const lrigw_ctx *c, int *splits) {
   const Dims &d = c->d;
   const long long K = lrigw_K(c);
@@ -554,11 +564,18 @@ int chi0_plan_splits(const lrigw_ctx *c, int *splits) {
   long long maxS = std::max<long long>(1, K / 512);
   S = std::min(S, maxS);
   if (ns_chi(c->precision) > 0) S = std::max(S, (K + 2047) / 2048);
-  const size_t cs = lrigw_csize(c);
-  const size_t per = (size_t)d.n_freq * ntile * TILE * TILE * cs;
-  while (S > 1 && (size_t)S * per > (size_t)3 << 30) --S;
   *splits = (int)std::max<long long>(1, S);
   return LRIGW_OK;
+}
+
+// Partial-tile buffer size: S splits of n_freq planes, at most 3 GiB (at
+// least one split).
+size_t chi0_part_bytes(const lrigw_ctx *c, int S) {
+  const Dims &d = c->d;
+  const int nt = (d.n_aux + TILE - 1) / TILE;
+  const size_t per = (size_t)d.n_freq * ((size_t)nt * (nt + 1) / 2) * TILE * TILE * lrigw_csize(c);
+  const size_t cap = std::max<size_t>(per, (size_t)3 << 30);
+  return std::min<size_t>((size_t)S * per, cap / per * per);
 }
 
 static int check_gap(lrigw_ctx *c, const double *eig);
@@ -629,52 +646,74 @@ int run_chi0_tab(lrigw_ctx *c, int iq, const void *M, const double *eig, int app
   const int S = c->chi_splits;
   const long long Ks = ((K + S - 1) / S + KCB - 1) / KCB * KCB;
   const double scale = -2.0 / d.n_k;
-  hipEvent_t ev;
-  stage_begin(c, "chi0_mfma", &ev);
+  // the partial-tile buffer holds Sb splits of these planes: the splits are
+  // taken Sb at a time, each batch on rows k0.. of the operands (k0 a
+  // multiple of KCB) and reduced into chi, the first batch writing it
+  const size_t per = (size_t)n_sel * ntile * TILE * TILE * lrigw_csize(c);
+  const int Sb = (int)std::max<size_t>(1, std::min<size_t>((size_t)S, c->part_bytes / per));
+  if ((size_t)Sb * per > c->part_bytes) return LRIGW_ERR_ARG;   // more planes than the buffer was sized for
   const int NW = c->chi_nw;
-  dim3 grid((unsigned)ntile, (n_sel + NW - 1) / NW, S);
-#define CHI0_ARGS om2t, cplt, wsel, run, K, d.n_aux, n_sel, Ks, ntile
-  if (c->precision == LRIGW_FP64) {
-    if (NW == 2)
-      hipLaunchKernelGGL((k_chi0_mfma<double, 2>), grid, dim3(256), 0, c->stream, (const double2 *)B,
-                         (const double *)c->d_delta, CHI0_ARGS, (double2 *)c->d_part);
-    else
-      hipLaunchKernelGGL((k_chi0_mfma<double, 1>), grid, dim3(256), 0, c->stream, (const double2 *)B,
-                         (const double *)c->d_delta, CHI0_ARGS, (double2 *)c->d_part);
-  } else {
+  const bool split = c->precision != LRIGW_FP64 && c->precision != LRIGW_FP32;
+  const long long Kp = (K + KCB - 1) / KCB * KCB;
+  const int Npad = nt * TILE;
+  hipEvent_t ev;
+  if (split) {
+    stage_begin(c, "chi0_split", &ev);
     const float2 *Bf = (const float2 *)B;
-    const float *Df = (const float *)c->d_delta;
-    float2 *Pf = (float2 *)c->d_part;
-    if (c->precision == LRIGW_FP32) {
-      if (NW == 4) hipLaunchKernelGGL((k_chi0_mfma<float, 4>), grid, dim3(256), 0, c->stream, Bf, Df, CHI0_ARGS, Pf);
-      else hipLaunchKernelGGL((k_chi0_mfma<float, 2>), grid, dim3(256), 0, c->stream, Bf, Df, CHI0_ARGS, Pf);
+    us16 *Apd = (us16 *)c->d_ap;
+    float2 *Btd = (float2 *)c->d_bt;
+    dim3 pg((unsigned)(Kp / 32), (unsigned)(Npad / 32));
+    const int NS = ns_chi(c->precision);
+    const bool H = split_h(c->precision);
+    if (H) {
+      LRIGW_TRY(zero_fill(c->stream, c->d_amax, (size_t)Npad * sizeof(unsigned)));
+      hipLaunchKernelGGL(k_absmax_rows, dim3((unsigned)((K + 63) / 64)), dim3(256), 0, c->stream, Bf, K, d.n_aux, c->d_amax);
+      hipLaunchKernelGGL((k_chi0_presplit<2, true>), pg, dim3(256), 0, c->stream, Bf, K, d.n_aux, Kp, Npad, c->d_amax, Apd,
+                         Btd);
+    } else if (NS == 2) {
+      hipLaunchKernelGGL((k_chi0_presplit<2, false>), pg, dim3(256), 0, c->stream, Bf, K, d.n_aux, Kp, Npad, nullptr, Apd,
+                         Btd);
     } else {
-      const long long Kp = (K + KCB - 1) / KCB * KCB;
-      const int Npad = nt * TILE;
-      us16 *Apd = (us16 *)c->d_ap;
-      float2 *Btd = (float2 *)c->d_bt;
-      dim3 pg((unsigned)(Kp / 32), (unsigned)(Npad / 32));
+      hipLaunchKernelGGL((k_chi0_presplit<3, false>), pg, dim3(256), 0, c->stream, Bf, K, d.n_aux, Kp, Npad, nullptr, Apd,
+                         Btd);
+    }
+    stage_end(c, "chi0_split", ev);
+  }
+  for (int s0 = 0; s0 < S; s0 += Sb) {
+    const long long k0 = (long long)s0 * Ks;
+    if (k0 >= K) break;
+    const int sb = std::min(Sb, S - s0);
+    const long long Kb = K - k0;   // rows from k0 on; split ks of the batch covers [ks Ks, (ks+1) Ks)
+    stage_begin(c, "chi0_mfma", &ev);
+    if (c->precision == LRIGW_FP64) {
+      dim3 grid((unsigned)ntile, (n_sel + NW - 1) / NW, sb);
+      const double2 *Bb = (const double2 *)B + k0 * d.n_aux;
+      const double *Db = (const double *)c->d_delta + k0;
+#define CHI0_ARGS om2t, cplt, wsel, run, Kb, d.n_aux, n_sel, Ks, ntile
+      if (NW == 2)
+        hipLaunchKernelGGL((k_chi0_mfma<double, 2>), grid, dim3(256), 0, c->stream, Bb, Db, CHI0_ARGS, (double2 *)c->d_part);
+      else
+        hipLaunchKernelGGL((k_chi0_mfma<double, 1>), grid, dim3(256), 0, c->stream, Bb, Db, CHI0_ARGS, (double2 *)c->d_part);
+    } else if (c->precision == LRIGW_FP32) {
+      dim3 grid((unsigned)ntile, (n_sel + NW - 1) / NW, sb);
+      const float2 *Bb = (const float2 *)B + k0 * d.n_aux;
+      const float *Db = (const float *)c->d_delta + k0;
+      float2 *Pf = (float2 *)c->d_part;
+      if (NW == 4) hipLaunchKernelGGL((k_chi0_mfma<float, 4>), grid, dim3(256), 0, c->stream, Bb, Db, CHI0_ARGS, Pf);
+      else hipLaunchKernelGGL((k_chi0_mfma<float, 2>), grid, dim3(256), 0, c->stream, Bb, Db, CHI0_ARGS, Pf);
+#undef CHI0_ARGS
+    } else {
+      const us16 *Apb = (const us16 *)c->d_ap + k0;
+      const float2 *Btb = (const float2 *)c->d_bt + k0;
+      const float *Db = (const float *)c->d_delta + k0;
+      float2 *Pf = (float2 *)c->d_part;
       const bool p16 = c->chi_pad == 16;
       const int NS = ns_chi(c->precision);
       const bool H = split_h(c->precision);
-      if (H) {
-        LRIGW_TRY(zero_fill(c->stream, c->d_amax, (size_t)Npad * sizeof(unsigned)));
-        hipLaunchKernelGGL(k_absmax_rows, dim3((unsigned)((K + 63) / 64)), dim3(256), 0, c->stream, Bf, K, d.n_aux, c->d_amax);
-        hipLaunchKernelGGL((k_chi0_presplit<2, true>), pg, dim3(256), 0, c->stream, Bf, K, d.n_aux, Kp, Npad, c->d_amax, Apd,
-                           Btd);
-      } else if (NS == 2) {
-        hipLaunchKernelGGL((k_chi0_presplit<2, false>), pg, dim3(256), 0, c->stream, Bf, K, d.n_aux, Kp, Npad, nullptr, Apd,
-                           Btd);
-      } else {
-        hipLaunchKernelGGL((k_chi0_presplit<3, false>), pg, dim3(256), 0, c->stream, Bf, K, d.n_aux, Kp, Npad, nullptr, Apd,
-                           Btd);
-      }
-      stage_end(c, "chi0_split", ev);
-      stage_begin(c, "chi0_mfma", &ev);
       // 1D over (K split, tile, frequency group), split over the XCDs
-      const long long sitems = (long long)((n_sel + NW - 1) / NW) * ntile * S;
+      const long long sitems = (long long)((n_sel + NW - 1) / NW) * ntile * sb;
       const dim3 sgrid((unsigned)(8 * ((sitems + 7) / 8)));
-#define BF16_ARGS Apd, Btd, Df, om2t, cplt, wsct, wsel, run, K, Kp, Npad, n_sel, Ks, ntile, c->d_amax, d.n_aux, Pf, S
+#define BF16_ARGS Apb, Btb, Db, om2t, cplt, wsct, wsel, run, Kb, Kp, Npad, n_sel, Ks, ntile, c->d_amax, d.n_aux, Pf, sb
 #define SPLIT_LAUNCH(NS_, H_)                                                                                            \
   do {                                                                                                                 \
     if (NW == 4 && p16) hipLaunchKernelGGL((k_chi0_split<NS_, 4, 16, H_>), sgrid, dim3(256), 0, c->stream, BF16_ARGS); \
@@ -688,17 +727,17 @@ int run_chi0_tab(lrigw_ctx *c, int iq, const void *M, const double *eig, int app
 #undef SPLIT_LAUNCH
 #undef BF16_ARGS
     }
+    stage_end(c, "chi0_mfma", ev);
+    LRIGW_TRY(lrigw_launch_check("chi0_mfma"));
+    dim3 rgrid((unsigned)ntile, n_sel);
+    const int acc = s0 > 0;
+    if (c->precision == LRIGW_FP64)
+      hipLaunchKernelGGL(k_chi0_reduce<double>, rgrid, dim3(256), 0, c->stream, (const double2 *)c->d_part, sb, n_sel, ntile,
+                         d.n_aux, scale, wsel, run, acc, (double2 *)chi_out);
+    else
+      hipLaunchKernelGGL(k_chi0_reduce<float>, rgrid, dim3(256), 0, c->stream, (const float2 *)c->d_part, sb, n_sel, ntile,
+                         d.n_aux, scale, wsel, run, acc, (float2 *)chi_out);
   }
-#undef CHI0_ARGS
-  stage_end(c, "chi0_mfma", ev);
-  LRIGW_TRY(lrigw_launch_check("chi0_mfma"));
-  dim3 rgrid((unsigned)ntile, n_sel);
-  if (c->precision == LRIGW_FP64)
-    hipLaunchKernelGGL(k_chi0_reduce<double>, rgrid, dim3(256), 0, c->stream, (const double2 *)c->d_part, S, n_sel, ntile,
-                       d.n_aux, scale, wsel, run, (double2 *)chi_out);
-  else
-    hipLaunchKernelGGL(k_chi0_reduce<float>, rgrid, dim3(256), 0, c->stream, (const float2 *)c->d_part, S, n_sel, ntile,
-                       d.n_aux, scale, wsel, run, (float2 *)chi_out);
   LRIGW_TRY(lrigw_launch_check("chi0_reduce"));
   stage_end(c, "chi0", ev_all);
   return LRIGW_OK;

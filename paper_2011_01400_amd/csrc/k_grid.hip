@@ -140,9 +140,7 @@ int run_grids(lrigw_ctx *c) {
   c->chi_nw = chi0_default_nw(c->precision);
   c->sig_var = sigma_default_variant(c->precision);
   LRIGW_TRY(chi0_plan_splits(c, &c->chi_splits));
-  int nt = (d.n_aux + TILE - 1) / TILE;
-  size_t ntile = (size_t)nt * (nt + 1) / 2;
-  c->part_bytes = (size_t)c->chi_splits * d.n_freq * ntile * TILE * TILE * cs;
+  c->part_bytes = chi0_part_bytes(c, c->chi_splits);
   LRIGW_HIP_TRY(hipMalloc(&c->d_part, c->part_bytes));
   LRIGW_HIP_TRY(hipMalloc(&c->d_X, (size_t)d.n_freq * d.n_k * d.n_qp * d.n_bands * sizeof(double)));
   LRIGW_HIP_TRY(hipMalloc(&c->d_LV, nn * sizeof(double2)));

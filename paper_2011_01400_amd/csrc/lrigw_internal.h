@@ -215,6 +215,7 @@ int run_grids(lrigw_ctx *c);
 int chi0_default_nw(int precision);
 int chi0_alt_nw(int precision);
 int chi0_plan_splits(const lrigw_ctx *c, int *splits);
+size_t chi0_part_bytes(const lrigw_ctx *c, int splits);
 // split forms: the longest K chunk one workgroup may sum in FP32 (the tuner
 // and lrigw_set_tiles keep splits >= ceil(K / CHI0_SPLIT_MAX_ROWS))
 #define CHI0_SPLIT_MAX_ROWS 4096
