@@ -52,7 +52,7 @@ static void free_all(lrigw_ctx *c) {
                   c->d_delta, c->d_part, c->d_X, c->d_LV, c->d_s0, c->d_s1, c->d_s2, c->d_s3, c->d_dinv, c->d_info,
                   c->d_bhat, c->d_x1, c->d_M, c->d_x, c->d_chi, c->d_wc, c->d_epsqp, c->d_xs, c->d_ws, c->d_ap, c->d_bt, c->d_chi2, c->d_wc2,
                   c->d_sx, c->d_wmax, c->d_amax, c->d_sitems, c->d_wd, c->d_xo, c->d_sxa, c->d_sxz, c->d_om2,
-                  c->d_wsc, c->d_chir, c->d_wr, c->d_Xr, c->d_cdE, c->d_cdS, c->d_cdbad, c->d_sitems_r, c->d_chir2, c->d_wr2, c->d_cut, c->d_bom2, c->d_bcpl, c->d_bwsc};
+                  c->d_wsc, c->d_chir, c->d_wr, c->d_Xr, c->d_cdE, c->d_cdS, c->d_cdbad, c->d_sitems_r, c->d_chir2, c->d_wr2, c->d_cut, c->d_bom2, c->d_bcpl, c->d_bwsc, c->d_cf};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &kv : c->stages)
@@ -123,6 +123,9 @@ int run_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, c
   const hipStream_t s2 = overlap ? c->stream2 : s;
   LRIGW_TRY(zero_fill(s, sigma, (size_t)d.n_k * d.n_qp * d.n_freq * sizeof(double2)));
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->d_info + 16, INT_MAX);
+  // V(q) (and V^cut) factors of every q at once (not under graph capture)
+  CoulombScope coulomb_scope(c);
+  if (!c->capturing) LRIGW_TRY(coulomb_factors(c, V, Vcut, q_first, q_last));
   const size_t vstride = (size_t)d.n_aux * d.n_aux;
   // two buffers in either mode: Sigma^c(q-1) is issued after screen(q)
   void *chi[2] = {c->d_chi, c->d_chi2};
@@ -215,6 +218,8 @@ int run_cd_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig
   const hipStream_t s = c->stream, s2 = c->stream2;
   LRIGW_TRY(zero_fill(s, sigma_e, (size_t)n_e * d.n_k * d.n_qp * sizeof(double)));
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->d_info + 16, INT_MAX);
+  CoulombScope coulomb_scope(c);
+  if (!c->capturing) LRIGW_TRY(coulomb_factors(c, V, Vcut, 0, d.n_k));
   const size_t vstride = (size_t)d.n_aux * d.n_aux;
   void *chi[2] = {c->d_chi, c->d_chi2}, *wc[2] = {c->d_wc, c->d_wc2};
   void *chir[2] = {c->d_chir, c->d_chir2}, *wr[2] = {c->d_wr, c->d_wr2};

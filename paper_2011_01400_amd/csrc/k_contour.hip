@@ -343,6 +343,9 @@ int run_cd_pass_broadened(lrigw_ctx *c, const void *H, const void *evec, const d
   const hipStream_t s = c->stream;
   LRIGW_TRY(zero_fill(s, sigma_e, (size_t)n_e * d.n_k * d.n_qp * sizeof(double)));
   hipLaunchKernelGGL(k_cd_set_int, dim3(1), dim3(1), 0, s, c->d_info + 16, INT_MAX);
+  // V(q) factors of every q at once: every chunk of real planes reuses them
+  CoulombScope coulomb_scope(c);
+  if (!c->capturing) LRIGW_TRY(coulomb_factors(c, V, Vcut, 0, d.n_k));
   const size_t vstride = (size_t)d.n_aux * d.n_aux;
   const long long C = (long long)d.n_k * d.n_qp * d.n_bands;
   const int P = d.n_freq / 2;

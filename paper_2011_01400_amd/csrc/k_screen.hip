@@ -177,6 +177,90 @@ static int cut_factor(lrigw_ctx *c, const void *V, const void *Vcut) {
   return ztrsm_left_lower(s, c->d_LV, n, nn, c->d_dinv, c->d_cut, n, nn, n, n, 1);
 }
 
+// d_info[16] = min(d_info[16], q0 + b) for the first batch element b whose
+// factorisation failed (d_info[1]); d_info[1] is reset
+__global__ void k_fold_first(int *info, int q0) {
+  if (threadIdx.x != 0) return;
+  if (info[1] != INT_MAX) {
+    info[16] = min(info[16], q0 + info[1]);
+    info[1] = INT_MAX;
+  }
+}
+
+int coulomb_factors(lrigw_ctx *c, const void *V, const void *Vcut, int q0, int q1) {
+  c->cf_on = false;
+  const int n = c->d.n_aux;
+  const long long nn = (long long)n * n, ds = zdinv_stride(n);
+  const int nq = q1 - q0;
+  if (!V || nq < 1) return LRIGW_ERR_ARG;
+  const bool cut = Vcut != nullptr && Vcut != V;
+  const int qa = std::max(q0, 1), ncut = cut ? std::max(0, q1 - qa) : 0;
+  // root chunks: [V, V^cut] pairs of qc q, roots, workspace (12 qc N^2 + 64), at most 1 GiB
+  const int qc = ncut > 0 ? (int)std::max<long long>(1, std::min<long long>(ncut, ((1ll << 30) / 16 - 64) / (12 * nn))) : 0;
+  const size_t need = ((size_t)nq * nn * (cut ? 2 : 1) + (size_t)nq * ds + (qc > 0 ? (size_t)12 * qc * nn + 64 : 0)) *
+                      sizeof(double2);
+  if (need > c->cf_bytes) {
+    if (c->d_cf) LRIGW_HIP_TRY(hipFree(c->d_cf));
+    c->d_cf = nullptr;
+    c->cf_bytes = 0;
+    LRIGW_HIP_TRY(hipMalloc(&c->d_cf, need));
+    c->cf_bytes = need;
+  }
+  hipStream_t s = c->stream;
+  double2 *L = c->d_cf, *TH = L + (long long)nq * nn, *Dinv = TH + (cut ? (long long)nq * nn : 0);
+  double2 *work = Dinv + (long long)nq * ds;
+  LRIGW_HIP_TRY(hipMemcpyAsync(L, (const double2 *)V + (long long)q0 * nn, (size_t)nq * nn * sizeof(double2),
+                               hipMemcpyDeviceToDevice, s));
+  LRIGW_TRY(zpotrf_batched(s, L, n, n, nn, nq, Dinv, c->d_info + 1));
+  hipLaunchKernelGGL(k_fold_first, dim3(1), dim3(1), 0, s, c->d_info, q0);
+  LRIGW_TRY(lrigw_launch_check("coulomb_factors"));
+  // T^H(q) = L^{-1} S S_c for q > 0, qc q at a time
+  for (int qb = qa; cut && qb < q1; qb += qc) {
+    const int m = std::min(qc, q1 - qb);
+    double2 *A = work, *R = A + 2ll * m * nn, *w = R + 2ll * m * nn;
+    LRIGW_HIP_TRY(hipMemcpyAsync(A, (const double2 *)V + (long long)qb * nn, (size_t)m * nn * sizeof(double2),
+                                 hipMemcpyDeviceToDevice, s));
+    LRIGW_HIP_TRY(hipMemcpyAsync(A + (long long)m * nn, (const double2 *)Vcut + (long long)qb * nn,
+                                 (size_t)m * nn * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    LRIGW_TRY(zsqrt_hpd_batched(s, A, n, 2 * m, R, w));
+    double2 *T = TH + (long long)(qb - q0) * nn;
+    LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, R, n, nn, OP_N, R + (long long)m * nn, n, nn, T, n, nn, mkc(1.0, 0.0), m)));
+    LRIGW_TRY(ztrsm_left_lower(s, L + (long long)(qb - q0) * nn, n, nn, Dinv + (long long)(qb - q0) * ds, T, n, nn, n, n,
+                               m));
+  }
+  c->cf_V = V;
+  c->cf_Vcut = cut ? Vcut : nullptr;
+  c->cf_cut = cut;
+  c->cf_q0 = q0;
+  c->cf_q1 = q1;
+  c->cf_on = true;
+  return LRIGW_OK;
+}
+
+// The factors of the screening of q: L (V = L L^H) and, with V^cut, T^H,
+// from the pass's batched factorisation when it covers these matrices, else
+// computed here (d_LV, d_cut; V's status in d_info[1]).
+static int screen_factors(lrigw_ctx *c, int iq, const void *V, const void *Vcut, const double2 **L, const double2 **TH) {
+  const int n = c->d.n_aux;
+  const long long nn = (long long)n * n;
+  const bool cut = Vcut != nullptr && Vcut != V;
+  if (c->cf_on && iq >= c->cf_q0 && iq < c->cf_q1 && V == (const void *)((const double2 *)c->cf_V + (long long)iq * nn) &&
+      (!cut || (c->cf_cut && iq > 0 && Vcut == (const void *)((const double2 *)c->cf_Vcut + (long long)iq * nn)))) {
+    const int nq = c->cf_q1 - c->cf_q0;
+    *L = c->d_cf + (long long)(iq - c->cf_q0) * nn;
+    *TH = cut ? c->d_cf + (long long)(nq + iq - c->cf_q0) * nn : nullptr;
+    return LRIGW_OK;
+  }
+  hipStream_t s = c->stream;
+  LRIGW_HIP_TRY(hipMemcpyAsync(c->d_LV, V, nn * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  LRIGW_TRY(zpotrf_batched(s, c->d_LV, n, n, nn, 1, c->d_dinv, c->d_info + 1));
+  // T^H = L^{-1} V^{1/2} V^cut^{1/2} (before the dielectric Cholesky reuses d_dinv)
+  if (cut) LRIGW_TRY(cut_factor(c, V, Vcut));
+  *L = c->d_LV;
+  *TH = cut ? c->d_cut : nullptr;
+  return LRIGW_OK;
+}
+
 int run_screen(lrigw_ctx *c, int iq, const void *chi, const void *V, const void *Vcut, void *Wc_out, int *info) {
   return run_screen_n(c, iq, chi, V, Vcut, Wc_out, info, c->d.n_freq);
 }
@@ -188,11 +272,8 @@ int run_screen_n(lrigw_ctx *c, int iq, const void *chi, const void *V, const voi
   const long long nn = (long long)n * n;
   hipStream_t s = c->stream;
   const bool cut = Vcut != nullptr && Vcut != V;
-  // L_V
-  LRIGW_HIP_TRY(hipMemcpyAsync(c->d_LV, V, nn * sizeof(double2), hipMemcpyDeviceToDevice, s));
-  LRIGW_TRY(zpotrf_batched(s, c->d_LV, n, n, nn, 1, c->d_dinv, c->d_info + 1));
-  // T^H = L^{-1} V^{1/2} V^cut^{1/2} (before the dielectric Cholesky reuses d_dinv)
-  if (cut) LRIGW_TRY(cut_factor(c, V, Vcut));
+  const double2 *LV = nullptr, *TH = nullptr;
+  LRIGW_TRY(screen_factors(c, iq, V, Vcut, &LV, &TH));
   // chi in FP64
   const double2 *chiz;
   if (c->precision == LRIGW_FP64) {
@@ -205,8 +286,8 @@ int run_screen_n(lrigw_ctx *c, int iq, const void *chi, const void *V, const voi
   }
   const double2 one = mkc(1.0, 0.0), mone = mkc(-1.0, 0.0);
   // T1 = chi L ; D = -L^H T1 (Hermitian: lower tiles, then mirrored)
-  LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, chiz, n, nn, OP_N, c->d_LV, n, 0, c->d_s0, n, nn, one, nw)));
-  ZGemm gd = mk(n, n, n, OP_C, c->d_LV, n, 0, OP_N, c->d_s0, n, nn, c->d_s1, n, nn, mone, nw);
+  LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, chiz, n, nn, OP_N, LV, n, 0, c->d_s0, n, nn, one, nw)));
+  ZGemm gd = mk(n, n, n, OP_C, LV, n, 0, OP_N, c->d_s0, n, nn, c->d_s1, n, nn, mone, nw);
   gd.lower_only = 1;
   LRIGW_TRY(zgemm(s, gd));
   dim3 eg((unsigned)((nn + 255) / 256), nw);
@@ -219,10 +300,10 @@ int run_screen_n(lrigw_ctx *c, int iq, const void *chi, const void *V, const voi
   LRIGW_TRY(ztrsm_left_upper_conj(s, c->d_s2, n, nn, c->d_dinv, c->d_s1, n, nn, n, n, nw));
   // W = -L (E^{-1} D) L^H (Hermitian: lower tiles; k_hermitize mirrors them);
   // with V^cut, T = (T^H)^H in place of L
-  if (cut) LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_s1, n, nn, OP_N, c->d_cut, n, 0, c->d_s0, n, nn, one, nw)));
-  else LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_s1, n, nn, OP_C, c->d_LV, n, 0, c->d_s0, n, nn, one, nw)));
-  ZGemm gw = cut ? mk(n, n, n, OP_C, c->d_cut, n, 0, OP_N, c->d_s0, n, nn, c->d_s1, n, nn, mone, nw)
-                 : mk(n, n, n, OP_N, c->d_LV, n, 0, OP_N, c->d_s0, n, nn, c->d_s1, n, nn, mone, nw);
+  if (cut) LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_s1, n, nn, OP_N, TH, n, 0, c->d_s0, n, nn, one, nw)));
+  else LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_s1, n, nn, OP_C, LV, n, 0, c->d_s0, n, nn, one, nw)));
+  ZGemm gw = cut ? mk(n, n, n, OP_C, TH, n, 0, OP_N, c->d_s0, n, nn, c->d_s1, n, nn, mone, nw)
+                 : mk(n, n, n, OP_N, LV, n, 0, OP_N, c->d_s0, n, nn, c->d_s1, n, nn, mone, nw);
   gw.lower_only = 1;
   LRIGW_TRY(zgemm(s, gw));
   if (c->precision == LRIGW_FP64)
@@ -292,9 +373,8 @@ int run_screen_cplx(lrigw_ctx *c, int iq, const void *chi, const void *V, const 
   hipStream_t s = c->stream;
   if (np < 1 || np > d.n_freq) return LRIGW_ERR_ARG;
   const bool cut = Vcut != nullptr && Vcut != V;
-  LRIGW_HIP_TRY(hipMemcpyAsync(c->d_LV, V, nn * sizeof(double2), hipMemcpyDeviceToDevice, s));
-  LRIGW_TRY(zpotrf_batched(s, c->d_LV, n, n, nn, 1, c->d_dinv, c->d_info + 1));
-  if (cut) LRIGW_TRY(cut_factor(c, V, Vcut));
+  const double2 *LV = nullptr, *TH = nullptr;
+  LRIGW_TRY(screen_factors(c, iq, V, Vcut, &LV, &TH));
   dim3 eg((unsigned)((nn + 255) / 256), np);
   if (c->precision == LRIGW_FP64)
     hipLaunchKernelGGL(k_combine_planes<double2>, eg, dim3(256), 0, s, (const double2 *)chi, c->d_s3, nn);
@@ -302,8 +382,8 @@ int run_screen_cplx(lrigw_ctx *c, int iq, const void *chi, const void *V, const 
     hipLaunchKernelGGL(k_combine_planes<float2>, eg, dim3(256), 0, s, (const float2 *)chi, c->d_s3, nn);
   const double2 one = mkc(1.0, 0.0), mone = mkc(-1.0, 0.0);
   // T1 = chi L; D = -L^H T1 (full: not Hermitian)
-  LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_s3, n, nn, OP_N, c->d_LV, n, 0, c->d_s0, n, nn, one, np)));
-  LRIGW_TRY(zgemm(s, mk(n, n, n, OP_C, c->d_LV, n, 0, OP_N, c->d_s0, n, nn, c->d_s1, n, nn, mone, np)));
+  LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_s3, n, nn, OP_N, LV, n, 0, c->d_s0, n, nn, one, np)));
+  LRIGW_TRY(zgemm(s, mk(n, n, n, OP_C, LV, n, 0, OP_N, c->d_s0, n, nn, c->d_s1, n, nn, mone, np)));
   // E = I + D; G = E^H E, R = E^H D
   hipLaunchKernelGGL(k_add_identity, eg, dim3(256), 0, s, c->d_s1, c->d_s2, n, nn);
   LRIGW_TRY(zgemm(s, mk(n, n, n, OP_C, c->d_s2, n, nn, OP_N, c->d_s2, n, nn, c->d_s0, n, nn, one, np)));
@@ -313,10 +393,10 @@ int run_screen_cplx(lrigw_ctx *c, int iq, const void *chi, const void *V, const 
   LRIGW_TRY(ztrsm_left_lower(s, c->d_s0, n, nn, c->d_dinv, c->d_s3, n, nn, n, n, np));
   LRIGW_TRY(ztrsm_left_upper_conj(s, c->d_s0, n, nn, c->d_dinv, c->d_s3, n, nn, n, n, np));
   // W = -L X L^H (T in place of L with V^cut), full
-  if (cut) LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_s3, n, nn, OP_N, c->d_cut, n, 0, c->d_s1, n, nn, one, np)));
-  else LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_s3, n, nn, OP_C, c->d_LV, n, 0, c->d_s1, n, nn, one, np)));
-  if (cut) LRIGW_TRY(zgemm(s, mk(n, n, n, OP_C, c->d_cut, n, 0, OP_N, c->d_s1, n, nn, c->d_s2, n, nn, mone, np)));
-  else LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_LV, n, 0, OP_N, c->d_s1, n, nn, c->d_s2, n, nn, mone, np)));
+  if (cut) LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_s3, n, nn, OP_N, TH, n, 0, c->d_s1, n, nn, one, np)));
+  else LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_s3, n, nn, OP_C, LV, n, 0, c->d_s1, n, nn, one, np)));
+  if (cut) LRIGW_TRY(zgemm(s, mk(n, n, n, OP_C, TH, n, 0, OP_N, c->d_s1, n, nn, c->d_s2, n, nn, mone, np)));
+  else LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, LV, n, 0, OP_N, c->d_s1, n, nn, c->d_s2, n, nn, mone, np)));
   if (c->precision == LRIGW_FP64)
     hipLaunchKernelGGL(k_herm_part<double>, eg, dim3(256), 0, s, c->d_s2, (double2 *)Wh_out, n, nn);
   else

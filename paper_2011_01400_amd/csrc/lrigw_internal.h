@@ -126,6 +126,13 @@ struct lrigw_ctx {
   void *d_X = nullptr;           // [N_w][N_k*n_qp*n_bands] pair weights (T)
   double2 *d_LV = nullptr;       // [N][N]
   double2 *d_cut = nullptr;      // truncated-Coulomb screening: L^{-1} V^{1/2} V^cut^{1/2} and workspace (13 N^2)
+  // Coulomb factors of a whole pass (CoulombScope): L(q) with V(q) = L L^H and,
+  // with V^cut, T^H(q) = L^{-1} V^{1/2} V^cut^{1/2}, for q in [cf_q0, cf_q1)
+  double2 *d_cf = nullptr;       // [L(q) ...][T^H(q) ...][diagonal-block inverses][root workspace]
+  size_t cf_bytes = 0;
+  const void *cf_V = nullptr, *cf_Vcut = nullptr;
+  int cf_q0 = 0, cf_q1 = 0;
+  bool cf_on = false, cf_cut = false;
   double2 *d_s0 = nullptr, *d_s1 = nullptr, *d_s2 = nullptr, *d_s3 = nullptr;  // [N_w][N][N]
   double2 *d_dinv = nullptr;     // inverses of 64x64 diagonal Cholesky blocks, [N_w][zdinv_stride(N)]
   int *d_info = nullptr;         // device status words
@@ -190,6 +197,20 @@ struct GapScope {
   ~GapScope() { --c->gap_trusted; }
   GapScope(const GapScope &) = delete;
   GapScope &operator=(const GapScope &) = delete;
+};
+// Factors V(q) = L L^H (and the V^cut factors) of q in [q0, q1) for a whole
+// pass at once, batched over q, on the context stream; while the scope lives
+// the screening takes them when called with V + q N^2 (and V^cut + q N^2 for
+// q > 0).  A V(q) that is not positive definite marks d_info[16] with its q.
+// Not used during graph capture (no allocation there): then each screening
+// factors its own V(q).
+int coulomb_factors(lrigw_ctx *c, const void *V, const void *Vcut, int q0, int q1);
+struct CoulombScope {
+  lrigw_ctx *c;
+  explicit CoulombScope(lrigw_ctx *ctx) : c(ctx) {}
+  ~CoulombScope() { c->cf_on = false; }
+  CoulombScope(const CoulombScope &) = delete;
+  CoulombScope &operator=(const CoulombScope &) = delete;
 };
 // BF16 parts of the response / self-energy operands (0: not a split form)
 inline int ns_chi(int precision) {
