@@ -44,9 +44,11 @@ def parse():
                     help="skip the exchange, coefficient-fit and contour-deformation legs (kernel profiles of the metric)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--n-par", type=int, default=16)
-    ap.add_argument("--workload", default="cell", choices=["cell", "batched", "surrogate"],
+    ap.add_argument("--workload", default="cell", choices=["cell", "batched", "surrogate", "cd_every_state"],
                     help="cell: one cell (--config); batched: the six uneven cells of config 3 in one captured graph; "
-                         "surrogate: the learned frequency surrogate on the 8-atom cell against its exact pass")
+                         "surrogate: the learned frequency surrogate on the 8-atom cell against its exact pass; "
+                         "cd_every_state: every QP state of the Si-like cell by contour deformation on the "
+                         "broadened real grid (Newton steps), against the Pade roots")
     return ap.parse_args()
 
 
@@ -235,6 +237,89 @@ def contour_timing(run, sysm, dev, n_r=16, reps=1):
             "states_evaluated": int(ok.sum()), "states": int(ok.size), "nan_outputs": int(bad),
             "z_range": [round(float(z.cpu().numpy()[ok].min()), 4), round(float(z.cpu().numpy()[ok].max()), 4)]
             if ok.any() else None}
+
+
+def cd_every_state(args, eta=0.05, max_iter=8, tol_mev=0.1, delta=0.002):
+    """Every QP state of the Si-like cell by contour deformation: W^c at
+    w_r + i eta on a uniform real grid of step eta/4 reaching every residue
+    of energies within 0.6 Ha of the band range, Newton steps on the QP
+    equation with Re Sigma^c(E) (lrigw_qp_cd, one step per call continuing
+    from the previous energies, each step one pass over every q) until no
+    state moves by more than tol_mev (at most max_iter steps), against the
+    roots of the Pade continuation of the same form's Sigma^c(i w)
+    (lrigw_g0w0) and, when on file, the oracle's Pade roots."""
+    import torch
+    from paper_2011_01400_amd import lrigw as L
+    from synth.systems import make_config
+    L.load()
+    t_start = time.perf_counter()
+    s = make_config(2)
+    sp = s.spec
+    dev = L.device_inputs(s)
+    run = Run(L, s, dev, args.precision, args.n_par)
+    run.ctx.lri_ft(dev["lri"], s.R, dev["evec"], run.H)
+    tuned = run.ctx.tune(run.H, dev["evec"], dev["eig"])
+    run.step()
+    torch.cuda.synchronize()
+    e_pade, z_pade = run.e_qp.cpu().numpy(), run.z.cpu().numpy()
+    lo, hi = float(s.eig.min()) - 0.6, float(s.eig.max()) + 0.6
+    h = eta / 4.0
+    top = max(hi - float(s.eig.min()), float(s.eig.max()) - lo) + 0.02
+    n_r = int(np.ceil(top / h)) + 1
+    run.ctx.set_real_grid(n_r, (n_r - 1) * h, eta)
+    print(f"# bench cd_every_state: broadened grid of {n_r} nodes to {(n_r - 1) * h:.3f} Ha (eta {eta} Ha)",
+          file=sys.stderr, flush=True)
+    e = torch.zeros((s.n_k, sp.n_qp), dtype=torch.float64, device="cuda")
+    z = torch.zeros_like(e)
+    S3 = torch.zeros((3, s.n_k, sp.n_qp), dtype=torch.float64, device="cuda")
+    steps, times = [], []
+    prev = s.eig[:, sp.qp_lo:sp.qp_lo + sp.n_qp].copy()
+    rc, bad = 0, 0
+    for it in range(max_iter):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, bad = run.ctx.qp_cd(run.H, dev["evec"], dev["eig"], dev["V"], dev["p"], s.omega_cell, dev["e_static"],
+                                delta, 1, e, z, sigma3=S3, warm=it > 0)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        ev = e.cpu().numpy()
+        st = np.abs(ev - prev) * HA_MEV
+        prev = ev.copy()
+        fin = np.isfinite(st)
+        steps.append((float(np.median(st[fin])) if fin.any() else None, float(st[fin].max()) if fin.any() else None,
+                      int((~np.isfinite(ev)).sum())))
+        print(f"# bench cd_every_state: Newton step {it + 1}: {times[-1]:.1f} s, |step| median {steps[-1][0]:.3f} "
+              f"max {steps[-1][1]:.3f} meV, {steps[-1][2]} states off the grid", file=sys.stderr, flush=True)
+        if fin.all() and st.max() <= tol_mev:
+            break
+    ev, zv = e.cpu().numpy(), z.cpu().numpy()
+    ok = np.isfinite(ev)
+    d = np.abs(ev - e_pade) * HA_MEV
+    reg = ok & (z_pade >= 0.5) & (z_pade <= 1.0) & (zv >= 0.5) & (zv <= 1.0)
+    dt = float(np.sum(times))
+    out = {"metric": "contour-deformation QP states per second", "value": round(float(ok.sum()) / dt, 2),
+           "unit": "states/s", "n_gpus": 1, "higher_is_better": True, "dtype": DTYPE[args.precision],
+           "data": "synthetic",
+           "config": {"workload": f"Si-like 2-atom cell: N_aux={s.n_aux}, k grid {'x'.join(map(str, sp.nk))}, every "
+                                  f"QP state; broadened real grid eta={eta} Ha, step eta/4, {n_r} nodes; Newton steps "
+                                  f"(delta {delta} Ha) until no state moves by more than {tol_mev} meV",
+                      "precision_form": args.precision},
+           "seconds": round(dt, 2), "seconds_per_newton_pass": round(dt / len(times), 2), "rc": int(rc),
+           "newton_steps": len(times),
+           "step_mev_median_max_offgrid": [[None if v is None else round(v, 4) for v in st[:2]] + [st[2]] for st in steps],
+           "states_evaluated": int(ok.sum()), "states": int(ok.size), "nan_outputs": int(bad),
+           "vs_pade_mev": {"all_median": round(float(np.median(d[ok])), 3), "all_max": round(float(d[ok].max()), 3),
+                           "quasiparticle_like_states": int(reg.sum()),
+                           "quasiparticle_like_median": round(float(np.median(d[reg])), 3) if reg.any() else None,
+                           "quasiparticle_like_max": round(float(d[reg].max()), 3) if reg.any() else None},
+           "z_range": [round(float(zv[ok].min()), 4), round(float(zv[ok].max()), 4)] if ok.any() else None,
+           "tuned": list(tuned), "wall_s": round(time.perf_counter() - t_start, 1)}
+    gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "c2_qp.npz")
+    if os.path.exists(gold):
+        g = np.load(gold, allow_pickle=False)
+        do = np.abs(ev - g["E"]) * HA_MEV
+        out["vs_oracle_pade_mev"] = {"median": round(float(np.median(do[ok])), 3), "max": round(float(do[ok].max()), 3)}
+    print(json.dumps(out))
 
 
 def lri_fit_timing(run, sysm, reps=2):
@@ -543,6 +628,9 @@ def main():
         return
     if args.workload == "surrogate":
         surrogate_leg(args)
+        return
+    if args.workload == "cd_every_state":
+        cd_every_state(args)
         return
     import torch
     from paper_2011_01400_amd import lrigw as L

@@ -387,13 +387,16 @@ int lrigw_g0w0_cd(lrigw_ctx *ctx, const void *H, const void *evec, const double 
  *   E <- E + Z (e_n + e_static_n + Sigma^c(E) - E),
  *   Z = 1 / (1 - (Sigma^c(E + delta) - Sigma^c(E - delta)) / (2 delta)),
  * n_iter (1..64) steps, each one whole contour-deformation pass at the three
- * energies of every state (n_iter = 1 is lrigw_g0w0_cd).  With the broadened
- * grid (lrigw_set_real_grid, eta > 0) every state is evaluated.  Arguments
- * and errors as lrigw_g0w0_cd; sigma3 holds the last pass's three values,
- * z the Z of the last step. */
+ * energies of every state (n_iter = 1 is lrigw_g0w0_cd).  warm = 0 starts
+ * from E_0 = e_n; warm = 1 continues from the energies e_qp holds on entry
+ * (a call of n steps after one of m gives what one call of m + n steps
+ * gives).  With the broadened grid (lrigw_set_real_grid, eta > 0) every state
+ * is evaluated.  Arguments and errors as lrigw_g0w0_cd (ERR_ARG also for warm
+ * outside 0..1); sigma3 holds the last pass's three values, z the Z of the
+ * last step. */
 int lrigw_qp_cd(lrigw_ctx *ctx, const void *H, const void *evec, const double *eig, const void *V, const void *Vcut,
-                const void *p, double omega_cell, const double *e_static, double delta, int n_iter, double *sigma3,
-                double *e_qp, double *z, int *n_bad);
+                const void *p, double omega_cell, const double *e_static, double delta, int n_iter, int warm,
+                double *sigma3, double *e_qp, double *z, int *n_bad);
 
 /* ---- Learned frequency surrogate of the response (a form the paper does not
  * have; it evaluates Eq. chi0_matrix at every frequency of the grid).

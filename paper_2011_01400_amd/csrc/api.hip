@@ -602,19 +602,20 @@ int lrigw_g0w0_cd(lrigw_ctx *c, const void *H, const void *evec, const double *e
 }
 
 int lrigw_qp_cd(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *Vcut,
-                const void *p, double omega_cell, const double *e_static, double delta, int n_iter, double *sigma3,
-                double *e_qp, double *z, int *n_bad) {
+                const void *p, double omega_cell, const double *e_static, double delta, int n_iter, int warm,
+                double *sigma3, double *e_qp, double *z, int *n_bad) {
   (void)hipGetLastError();
   if (n_bad) *n_bad = 0;
   if (!c || !H || !evec || !eig || !V || !e_qp || !z) return LRIGW_ERR_ARG;
-  if (c->n_real < 4 || !(delta > 0.0) || !std::isfinite(delta) || c->capturing || n_iter < 1 || n_iter > 64)
+  if (c->n_real < 4 || !(delta > 0.0) || !std::isfinite(delta) || c->capturing || n_iter < 1 || n_iter > 64 ||
+      warm < 0 || warm > 1)
     return LRIGW_ERR_ARG;
   if (p && !(omega_cell > 0.0)) return LRIGW_ERR_ARG;
   double *S = sigma3 ? sigma3 : c->d_cdS;
   int rc = LRIGW_OK;
   for (int it = 0; it < n_iter; ++it) {
     // energies E - delta, E, E + delta of the current iterate (E_0 = e_n)
-    LRIGW_TRY(cd_newton(c, eig, nullptr, nullptr, delta, e_qp, nullptr, it == 0));
+    LRIGW_TRY(cd_newton(c, eig, nullptr, nullptr, delta, e_qp, nullptr, it == 0 && !warm));
     rc = c->real_eta > 0.0 ? run_cd_pass_broadened(c, H, evec, eig, V, Vcut, p, omega_cell, 3, c->d_cdE, S, n_bad)
                            : run_cd_pass(c, H, evec, eig, V, Vcut, p, omega_cell, 3, c->d_cdE, S, n_bad);
     if (rc < 0) return rc;

@@ -115,7 +115,7 @@ def load(path: Optional[str] = None):
         "lrigw_sigma_cd": (i, [vp, i, vp, vp, vp, vp, i, vp, vp]),
         "lrigw_sigma_cd_pass": (i, [vp, vp, vp, vp, vp, vp, vp, d, i, vp, vp, ip]),
         "lrigw_g0w0_cd": (i, [vp, vp, vp, vp, vp, vp, vp, d, vp, d, vp, vp, vp, ip]),
-        "lrigw_qp_cd": (i, [vp, vp, vp, vp, vp, vp, vp, d, vp, d, i, vp, vp, vp, ip]),
+        "lrigw_qp_cd": (i, [vp, vp, vp, vp, vp, vp, vp, d, vp, d, i, i, vp, vp, vp, ip]),
         "lrigw_g0w0": (i, [vp, vp, vp, vp, vp, vp, vp, d, vp, i, i, i, vp, vp, vp, ip]),
         "lrigw_set_timing": (i, [vp, i]),
         "lrigw_stage_ms": (d, [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_longlong)]),
@@ -369,11 +369,13 @@ class Context:
         self._check(rc, "lrigw_g0w0_cd", allow_warn=True)
         return rc, bad.value
 
-    def qp_cd(self, H, evec, eig, V, p, omega_cell, e_static, delta, n_iter, e_qp, z, sigma3=None, Vcut=None):
+    def qp_cd(self, H, evec, eig, V, p, omega_cell, e_static, delta, n_iter, e_qp, z, sigma3=None, Vcut=None,
+              warm=False):
+        """warm: continue from the energies e_qp holds (else start at e_n)."""
         bad = ctypes.c_int(0)
         rc = self.lib.lrigw_qp_cd(self.h, _ptr(H), _ptr(evec), _ptr(eig), _ptr(V), _ptr(Vcut), _ptr(p),
-                                  float(omega_cell), _ptr(e_static), float(delta), int(n_iter), _ptr(sigma3), _ptr(e_qp),
-                                  _ptr(z), ctypes.byref(bad))
+                                  float(omega_cell), _ptr(e_static), float(delta), int(n_iter), int(bool(warm)),
+                                  _ptr(sigma3), _ptr(e_qp), _ptr(z), ctypes.byref(bad))
         self._check(rc, "lrigw_qp_cd", allow_warn=True)
         return rc, bad.value
 

@@ -375,6 +375,13 @@ def test_broadened_qp_newton(case):
     rc, bad = ctx.qp_cd(H, dev["evec"], dev["eig"], dev["V"], dev["p"], s.omega_cell, dev["e_static"], 0.002, 3, e, z)
     assert rc == L.LRIGW_OK and bad == 0
     Eo, Zo, _ = o.qp_cd(n_r, wmax, ETA, 3, delta=0.002)
+    # one step, then two more continuing from its energies: the same iterates
+    e1, z1 = torch.zeros_like(e), torch.zeros_like(e)
+    assert ctx.qp_cd(H, dev["evec"], dev["eig"], dev["V"], dev["p"], s.omega_cell, dev["e_static"], 0.002, 1, e1,
+                     z1)[0] == L.LRIGW_OK
+    assert ctx.qp_cd(H, dev["evec"], dev["eig"], dev["V"], dev["p"], s.omega_cell, dev["e_static"], 0.002, 2, e1, z1,
+                     warm=True)[0] == L.LRIGW_OK
+    assert torch.equal(e1, e) and torch.equal(z1, z)
     d = np.abs(e.cpu().numpy() - Eo) * HA_MEV
     print(f"  {case['name']}: QP by Newton on the broadened grid, max {d.max():.2e} meV from the oracle; "
           f"shifts {np.abs(Eo - s.eig[:, s.spec.qp_lo:s.spec.qp_lo + s.spec.n_qp]).max():.3f} Ha", flush=True)
