@@ -44,6 +44,7 @@ def parse():
                     help="skip the exchange, coefficient-fit and contour-deformation legs (kernel profiles of the metric)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--n-par", type=int, default=16)
+    ap.add_argument("--cd-eta", type=float, default=0.05, help="broadening (Ha) of the cd_every_state workload")
     ap.add_argument("--workload", default="cell", choices=["cell", "batched", "surrogate", "cd_every_state"],
                     help="cell: one cell (--config); batched: the six uneven cells of config 3 in one captured graph; "
                          "surrogate: the learned frequency surrogate on the 8-atom cell against its exact pass; "
@@ -630,7 +631,7 @@ def main():
         surrogate_leg(args)
         return
     if args.workload == "cd_every_state":
-        cd_every_state(args)
+        cd_every_state(args, eta=args.cd_eta)
         return
     import torch
     from paper_2011_01400_amd import lrigw as L

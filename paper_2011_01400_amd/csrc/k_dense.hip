@@ -33,6 +33,10 @@ __global__ __launch_bounds__(256) void k_zgemm(ZGemm g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1, col = lane & 15;
   const double2 zero = mkc(0.0, 0.0);
+  // 16x16 blocks of this wave that hold any output (a tile of the last tile
+  // row or column is mostly padding; the others' products are skipped)
+  const bool rin[2] = {m0 + 32 * wr < g.m, m0 + 32 * wr + 16 < g.m};
+  const bool cin[2] = {n0 + 32 * wc < g.n, n0 + 32 * wc + 16 < g.n};
   d4v cr[2][2], ci[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -91,6 +95,7 @@ __global__ __launch_bounds__(256) void k_zgemm(ZGemm g) {
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
+          if (!rin[i] || !cin[j]) continue;
           cr[i][j] = MF::mac(a[i].x, bb[j].x, cr[i][j]);
           ci[i][j] = MF::mac(a[i].x, bb[j].y, ci[i][j]);
         }
@@ -98,6 +103,7 @@ __global__ __launch_bounds__(256) void k_zgemm(ZGemm g) {
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
+          if (!rin[i] || !cin[j]) continue;
           cr[i][j] = MF::mac(-a[i].y, bb[j].y, cr[i][j]);
           ci[i][j] = MF::mac(a[i].y, bb[j].x, ci[i][j]);
         }
