@@ -76,8 +76,15 @@ __global__ __launch_bounds__(256) void k_zgemm(ZGemm g) {
       Bs[kb][nn] = rb[t];
     }
   };
-  fetch(0);
-  for (int k0 = 0; k0 < g.k; k0 += GK) {
+  // K range this tile needs when an operand is triangular (the skipped
+  // products are with stored zeros; both ends are multiples of GT)
+  int k_lo = 0, k_hi = g.k;
+  if (g.tri_b == TRI_LOWER) k_lo = max(k_lo, n0);        // op(B)[k][c] = 0 for k < c
+  if (g.tri_b == TRI_UPPER) k_hi = min(k_hi, n0 + GT);   // op(B)[k][c] = 0 for k > c
+  if (g.tri_a == TRI_UPPER) k_lo = max(k_lo, m0);        // op(A)[r][k] = 0 for k < r
+  if (g.tri_a == TRI_LOWER) k_hi = min(k_hi, m0 + GT);   // op(A)[r][k] = 0 for k > r
+  fetch(k_lo);
+  for (int k0 = k_lo; k0 < k_hi; k0 += GK) {
     __syncthreads();
     stash();
     __syncthreads();

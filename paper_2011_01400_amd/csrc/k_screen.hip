@@ -285,10 +285,15 @@ int run_screen_n(lrigw_ctx *c, int iq, const void *chi, const void *V, const voi
     chiz = c->d_s3;
   }
   const double2 one = mkc(1.0, 0.0), mone = mkc(-1.0, 0.0);
-  // T1 = chi L ; D = -L^H T1 (Hermitian: lower tiles, then mirrored)
-  LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, chiz, n, nn, OP_N, LV, n, 0, c->d_s0, n, nn, one, nw)));
+  // T1 = chi L ; D = -L^H T1 (Hermitian: lower tiles, then mirrored); L is
+  // lower triangular with its upper part zero, so each tile runs only the K
+  // range L or L^H leaves nonzero
+  ZGemm gt = mk(n, n, n, OP_N, chiz, n, nn, OP_N, LV, n, 0, c->d_s0, n, nn, one, nw);
+  gt.tri_b = TRI_LOWER;
+  LRIGW_TRY(zgemm(s, gt));
   ZGemm gd = mk(n, n, n, OP_C, LV, n, 0, OP_N, c->d_s0, n, nn, c->d_s1, n, nn, mone, nw);
   gd.lower_only = 1;
+  gd.tri_a = TRI_UPPER;
   LRIGW_TRY(zgemm(s, gd));
   dim3 eg((unsigned)((nn + 255) / 256), nw);
   hipLaunchKernelGGL(k_mirror_lower, eg, dim3(256), 0, s, c->d_s1, n, nn);
@@ -300,11 +305,17 @@ int run_screen_n(lrigw_ctx *c, int iq, const void *chi, const void *V, const voi
   LRIGW_TRY(ztrsm_left_upper_conj(s, c->d_s2, n, nn, c->d_dinv, c->d_s1, n, nn, n, n, nw));
   // W = -L (E^{-1} D) L^H (Hermitian: lower tiles; k_hermitize mirrors them);
   // with V^cut, T = (T^H)^H in place of L
-  if (cut) LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_s1, n, nn, OP_N, TH, n, 0, c->d_s0, n, nn, one, nw)));
-  else LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_s1, n, nn, OP_C, LV, n, 0, c->d_s0, n, nn, one, nw)));
+  if (cut) {
+    LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_s1, n, nn, OP_N, TH, n, 0, c->d_s0, n, nn, one, nw)));
+  } else {
+    ZGemm g1 = mk(n, n, n, OP_N, c->d_s1, n, nn, OP_C, LV, n, 0, c->d_s0, n, nn, one, nw);
+    g1.tri_b = TRI_UPPER;
+    LRIGW_TRY(zgemm(s, g1));
+  }
   ZGemm gw = cut ? mk(n, n, n, OP_C, TH, n, 0, OP_N, c->d_s0, n, nn, c->d_s1, n, nn, mone, nw)
                  : mk(n, n, n, OP_N, LV, n, 0, OP_N, c->d_s0, n, nn, c->d_s1, n, nn, mone, nw);
   gw.lower_only = 1;
+  if (!cut) gw.tri_a = TRI_LOWER;
   LRIGW_TRY(zgemm(s, gw));
   if (c->precision == LRIGW_FP64)
     hipLaunchKernelGGL(k_hermitize<double>, eg, dim3(256), 0, s, c->d_s1, (double2 *)Wc_out, n, nn);
@@ -382,8 +393,14 @@ int run_screen_cplx(lrigw_ctx *c, int iq, const void *chi, const void *V, const 
     hipLaunchKernelGGL(k_combine_planes<float2>, eg, dim3(256), 0, s, (const float2 *)chi, c->d_s3, nn);
   const double2 one = mkc(1.0, 0.0), mone = mkc(-1.0, 0.0);
   // T1 = chi L; D = -L^H T1 (full: not Hermitian)
-  LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_s3, n, nn, OP_N, LV, n, 0, c->d_s0, n, nn, one, np)));
-  LRIGW_TRY(zgemm(s, mk(n, n, n, OP_C, LV, n, 0, OP_N, c->d_s0, n, nn, c->d_s1, n, nn, mone, np)));
+  {
+    ZGemm gt = mk(n, n, n, OP_N, c->d_s3, n, nn, OP_N, LV, n, 0, c->d_s0, n, nn, one, np);
+    gt.tri_b = TRI_LOWER;
+    LRIGW_TRY(zgemm(s, gt));
+    ZGemm gd = mk(n, n, n, OP_C, LV, n, 0, OP_N, c->d_s0, n, nn, c->d_s1, n, nn, mone, np);
+    gd.tri_a = TRI_UPPER;
+    LRIGW_TRY(zgemm(s, gd));
+  }
   // E = I + D; G = E^H E, R = E^H D
   hipLaunchKernelGGL(k_add_identity, eg, dim3(256), 0, s, c->d_s1, c->d_s2, n, nn);
   LRIGW_TRY(zgemm(s, mk(n, n, n, OP_C, c->d_s2, n, nn, OP_N, c->d_s2, n, nn, c->d_s0, n, nn, one, np)));
@@ -393,10 +410,17 @@ int run_screen_cplx(lrigw_ctx *c, int iq, const void *chi, const void *V, const 
   LRIGW_TRY(ztrsm_left_lower(s, c->d_s0, n, nn, c->d_dinv, c->d_s3, n, nn, n, n, np));
   LRIGW_TRY(ztrsm_left_upper_conj(s, c->d_s0, n, nn, c->d_dinv, c->d_s3, n, nn, n, n, np));
   // W = -L X L^H (T in place of L with V^cut), full
-  if (cut) LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_s3, n, nn, OP_N, TH, n, 0, c->d_s1, n, nn, one, np)));
-  else LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_s3, n, nn, OP_C, LV, n, 0, c->d_s1, n, nn, one, np)));
-  if (cut) LRIGW_TRY(zgemm(s, mk(n, n, n, OP_C, TH, n, 0, OP_N, c->d_s1, n, nn, c->d_s2, n, nn, mone, np)));
-  else LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, LV, n, 0, OP_N, c->d_s1, n, nn, c->d_s2, n, nn, mone, np)));
+  if (cut) {
+    LRIGW_TRY(zgemm(s, mk(n, n, n, OP_N, c->d_s3, n, nn, OP_N, TH, n, 0, c->d_s1, n, nn, one, np)));
+    LRIGW_TRY(zgemm(s, mk(n, n, n, OP_C, TH, n, 0, OP_N, c->d_s1, n, nn, c->d_s2, n, nn, mone, np)));
+  } else {
+    ZGemm g1 = mk(n, n, n, OP_N, c->d_s3, n, nn, OP_C, LV, n, 0, c->d_s1, n, nn, one, np);
+    g1.tri_b = TRI_UPPER;
+    LRIGW_TRY(zgemm(s, g1));
+    ZGemm g2 = mk(n, n, n, OP_N, LV, n, 0, OP_N, c->d_s1, n, nn, c->d_s2, n, nn, mone, np);
+    g2.tri_a = TRI_LOWER;
+    LRIGW_TRY(zgemm(s, g2));
+  }
   if (c->precision == LRIGW_FP64)
     hipLaunchKernelGGL(k_herm_part<double>, eg, dim3(256), 0, s, c->d_s2, (double2 *)Wh_out, n, nn);
   else

@@ -320,7 +320,11 @@ struct ZGemm {
   double2 alpha, beta;
   int batch;
   int lower_only;                          // skip tiles strictly above the diagonal
+  // op(A) / op(B) triangular with zeros stored in the other triangle (TRI_LOWER,
+  // TRI_UPPER): each tile then runs only the K range its rows / columns need
+  int tri_a = 0, tri_b = 0;
 };
+enum { TRI_NONE = 0, TRI_LOWER = 1, TRI_UPPER = 2 };
 int zgemm(hipStream_t s, const ZGemm &g);
 long long zdinv_stride(int n);
 int zpotrf_batched(hipStream_t s, double2 *A, int n, long long lda, long long stride, int batch, double2 *Dinv, int *d_info);
