@@ -52,7 +52,7 @@ static void free_all(lrigw_ctx *c) {
                   c->d_delta, c->d_part, c->d_X, c->d_LV, c->d_s0, c->d_s1, c->d_s2, c->d_s3, c->d_dinv, c->d_info,
                   c->d_bhat, c->d_x1, c->d_M, c->d_x, c->d_chi, c->d_wc, c->d_epsqp, c->d_xs, c->d_ws, c->d_ap, c->d_bt, c->d_chi2, c->d_wc2,
                   c->d_sx, c->d_wmax, c->d_amax, c->d_sitems, c->d_wd, c->d_xo, c->d_sxa, c->d_sxz, c->d_om2,
-                  c->d_wsc, c->d_chir, c->d_wr, c->d_Xr, c->d_cdE, c->d_cdS, c->d_cdbad, c->d_sitems_r, c->d_chir2, c->d_wr2, c->d_cut, c->d_bom2, c->d_bcpl, c->d_bwsc, c->d_cf};
+                  c->d_wsc, c->d_chir, c->d_wr, c->d_Xr, c->d_cdE, c->d_cdS, c->d_cdbad, c->d_sitems_r, c->d_chir2, c->d_wr2, c->d_cut, c->d_bom2, c->d_bcpl, c->d_bwsc, c->d_cf, c->d_grp};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &kv : c->stages)
@@ -110,6 +110,59 @@ int driver_buffers(lrigw_ctx *c) {
 // attached (its per-q work shares the screening workspaces), and under graph
 // capture (the batched form overlaps whole cells on streams of their own
 // instead), the pass runs on `stream` alone.
+// q per screening group: as many as fit 8 GiB of responses, W^c and FP64
+// workspace (at most 8); 1 (no grouping) when one q alone exceeds that
+static int pass_group_size(const lrigw_ctx *c, int nq) {
+  const Dims &d = c->d;
+  const size_t per_q = 4 * (size_t)d.n_freq * d.n_aux * d.n_aux * lrigw_csize(c) +
+                       (size_t)group_ws_elems(c, 1) * sizeof(double2);
+  const size_t fit = ((size_t)8 << 30) / per_q;
+  return (int)std::max<size_t>(1, std::min<size_t>({fit, (size_t)8, (size_t)nq}));
+}
+
+// two sets of G response and G W^c blocks (one group is screened while the
+// next one's responses are built), and the screening workspace of G q
+static int group_buffers(lrigw_ctx *c, int G) {
+  const Dims &d = c->d;
+  const size_t need = 4 * (size_t)G * d.n_freq * d.n_aux * d.n_aux * lrigw_csize(c) +
+                      (size_t)group_ws_elems(c, G) * sizeof(double2);
+  if (need > c->grp_bytes) {
+    if (c->d_grp) LRIGW_HIP_TRY(hipFree(c->d_grp));
+    c->d_grp = nullptr;
+    c->grp_bytes = 0;
+    LRIGW_HIP_TRY(hipMalloc(&c->d_grp, need));
+    c->grp_bytes = need;
+  }
+  c->grp_cap = G;
+  return LRIGW_OK;
+}
+
+// The end of a pass: the screening status (not under capture), then the QP
+// step when every q was done.
+static int pass_finish(lrigw_ctx *c, const double *eig, const double *e_static, int n_par, bool all_q, void *sigma,
+                       double *e_qp, double *z, int *info) {
+  const Dims &d = c->d;
+  const hipStream_t s = c->stream;
+  if (!c->capturing) {
+    int h = INT_MAX;
+    LRIGW_HIP_TRY(hipMemcpyAsync(&h, c->d_info + 16, sizeof(int), hipMemcpyDeviceToHost, s));
+    LRIGW_HIP_TRY(hipStreamSynchronize(s));
+    if (h != INT_MAX) {
+      if (info) *info = h;
+      return LRIGW_ERR_NOT_HPD;
+    }
+  }
+  if (!all_q) return LRIGW_OK;
+  const int nkq = d.n_k * d.n_qp;
+  hipLaunchKernelGGL(k_qp_bands, dim3((nkq + 255) / 256), dim3(256), 0, s, eig, d.n_k, d.n_bands, d.qp_lo, d.n_qp,
+                     c->d_epsqp);
+  LRIGW_TRY(lrigw_launch_check("qp_bands"));
+  int qinfo = 0;
+  const int rc = lrigw_qp(c, sigma, c->d_epsqp, e_static, n_par, e_qp, z, &qinfo);
+  if (info) *info = qinfo;
+  return rc;
+}
+
 int run_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, const void *V, const void *Vcut,
              const void *p, double omega_cell, const double *e_static, int n_par, int q_first, int q_last, void *sigma,
              double *e_qp, double *z, int *info) {
@@ -131,6 +184,76 @@ int run_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, c
   void *chi[2] = {c->d_chi, c->d_chi2};
   void *wc[2] = {c->d_wc, c->d_wc2};
   const bool was_capturing = c->capturing;
+  // Grouped form (not under capture, no surrogate, no direction average): the
+  // q are taken in groups of G, and one screening covers a group's G N_w
+  // planes (wide launches instead of N_q chains of small latency-bound ones).
+  // Per group g, on `stream`: M and the response of each q of g, then x and
+  // Sigma^c of each q of g - 1 (after its screening); the screening of g runs
+  // on stream2 after that self-energy, beside the responses of g + 1, so no
+  // screening runs beside the self-energy kernel.  Buffer sets alternate by
+  // group: a response set is rewritten only after the self-energy of its
+  // group, which waited for the screening that read it; a W^c set is
+  // rewritten by a screening that starts after the self-energy that read it.
+  const int G = (!was_capturing && c->sur == nullptr && c->n_gdir == 0) ? pass_group_size(c, q_last - q_first) : 1;
+  if (G > 1) {
+    LRIGW_TRY(group_buffers(c, G));
+    const size_t cs = lrigw_csize(c), blk = (size_t)d.n_freq * vstride * cs;
+    char *gchi[2] = {(char *)c->d_grp, (char *)c->d_grp + G * blk};
+    char *gwc[2] = {(char *)c->d_grp + 2 * G * blk, (char *)c->d_grp + 3 * G * blk};
+    double2 *gws = (double2 *)((char *)c->d_grp + 4 * G * blk);
+    c->capturing = true;   // device-side status
+    int rc = LRIGW_OK;
+    const int ng = (q_last - q_first + G - 1) / G;
+    for (int g = 0; g <= ng && rc == LRIGW_OK; ++g) {
+      const int q0 = q_first + g * G, nq = g < ng ? std::min(G, q_last - q0) : 0;
+      for (int j = 0; j < nq && rc == LRIGW_OK; ++j) {
+        const int q = q0 + j;
+        if ((rc = lrigw_build_M(c, q, 0, H, evec, c->d_M)) < 0) break;
+        rc = lrigw_chi0(c, q, c->d_M, eig, (p && q == 0) ? 1 : 0, gchi[g & 1] + j * blk);
+      }
+      if (rc < 0) break;
+      if (g > 0) {
+        // Sigma^c of the previous group, after its screening
+        const int pg = g - 1, p0 = q_first + pg * G, pn = std::min(G, q_last - p0);
+        if (hipStreamWaitEvent(s, c->ev_wc[pg & 1], 0) != hipSuccess) {
+          rc = LRIGW_ERR_HIP;
+          break;
+        }
+        for (int j = 0; j < pn && rc == LRIGW_OK; ++j) {
+          const int q = p0 + j;
+          if ((rc = lrigw_build_M(c, q, 1, H, evec, c->d_x)) < 0) break;
+          rc = lrigw_sigma_c(c, q, c->d_x, gwc[pg & 1] + j * blk, eig, sigma);
+        }
+        if (rc < 0) break;
+      }
+      if (nq == 0) break;
+      // the screening of this group on stream2, after everything issued so far
+      if (hipEventRecord(c->ev_chi[g & 1], s) != hipSuccess || hipStreamWaitEvent(s2, c->ev_chi[g & 1], 0) != hipSuccess) {
+        rc = LRIGW_ERR_HIP;
+        break;
+      }
+      c->stream = s2;
+      hipEvent_t ev;
+      stage_begin(c, "screen", &ev);
+      if (Vcut && q0 == 0) {
+        // V[0] is V^cut(0): q = 0 alone, then the rest of the group
+        rc = run_screen_group(c, 0, 1, gchi[g & 1], V, nullptr, gwc[g & 1], gws);
+        if (rc == LRIGW_OK && nq > 1)
+          rc = run_screen_group(c, 1, nq - 1, gchi[g & 1] + blk, (const double2 *)V + vstride,
+                                (const double2 *)Vcut + vstride, gwc[g & 1] + blk, gws);
+      } else {
+        const void *Vcg = Vcut ? (const void *)((const double2 *)Vcut + q0 * vstride) : nullptr;
+        rc = run_screen_group(c, q0, nq, gchi[g & 1], (const double2 *)V + q0 * vstride, Vcg, gwc[g & 1], gws);
+      }
+      stage_end(c, "screen", ev);
+      if (rc == LRIGW_OK && hipEventRecord(c->ev_wc[g & 1], s2) != hipSuccess) rc = LRIGW_ERR_HIP;
+      c->stream = s;
+    }
+    c->stream = s;
+    c->capturing = was_capturing;
+    if (rc < 0) return rc;
+    return pass_finish(c, eig, e_static, n_par, all_q, sigma, e_qp, z, info);
+  }
   c->capturing = true;   // screening: device-side status, no host round trip
   int rc = LRIGW_OK;
   for (int q = q_first; q <= q_last && rc == LRIGW_OK; ++q) {
@@ -181,24 +304,7 @@ int run_pass(lrigw_ctx *c, const void *H, const void *evec, const double *eig, c
   c->stream = s;
   c->capturing = was_capturing;
   if (rc < 0) return rc;
-  if (!was_capturing) {
-    int h = INT_MAX;
-    LRIGW_HIP_TRY(hipMemcpyAsync(&h, c->d_info + 16, sizeof(int), hipMemcpyDeviceToHost, s));
-    LRIGW_HIP_TRY(hipStreamSynchronize(s));
-    if (h != INT_MAX) {
-      if (info) *info = h;
-      return LRIGW_ERR_NOT_HPD;
-    }
-  }
-  if (!all_q) return LRIGW_OK;
-  const int nkq = d.n_k * d.n_qp;
-  hipLaunchKernelGGL(k_qp_bands, dim3((nkq + 255) / 256), dim3(256), 0, s, eig, d.n_k, d.n_bands, d.qp_lo, d.n_qp,
-                     c->d_epsqp);
-  LRIGW_TRY(lrigw_launch_check("qp_bands"));
-  int qinfo = 0;
-  rc = lrigw_qp(c, sigma, c->d_epsqp, e_static, n_par, e_qp, z, &qinfo);
-  if (info) *info = qinfo;
-  return rc;
+  return pass_finish(c, eig, e_static, n_par, all_q, sigma, e_qp, z, info);
 }
 
 // Sigma^c at real energies over every q by contour deformation: per q the

@@ -27,8 +27,8 @@ __global__ __launch_bounds__(256) void k_zgemm(ZGemm g) {
   const int tm = blockIdx.x, tn = blockIdx.y, b = blockIdx.z;
   const int m0 = tm * GT, n0 = tn * GT;
   if (g.lower_only && n0 > m0 + GT - 1) return;
-  const double2 *A = g.A + (long long)b * g.sa;
-  const double2 *B = g.B + (long long)b * g.sb;
+  const double2 *A = g.A + (long long)(b % g.bdiv) * g.sa + (long long)(b / g.bdiv) * g.sa2;
+  const double2 *B = g.B + (long long)(b % g.bdiv) * g.sb + (long long)(b / g.bdiv) * g.sb2;
   double2 *C = g.C + (long long)b * g.sc;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1, col = lane & 15;

@@ -343,6 +343,94 @@ int run_screen_n(lrigw_ctx *c, int iq, const void *chi, const void *V, const voi
   return LRIGW_OK;
 }
 
+// d_info[16] = min(d_info[16], q0 + b / nw) for the first failing batch
+// element b of a grouped eps~ factorisation (d_info[2]); d_info[2] is reset
+__global__ void k_fold_group(int *info, int q0, int nw) {
+  if (threadIdx.x != 0) return;
+  if (info[2] != INT_MAX) {
+    info[16] = min(info[16], q0 + info[2] / nw);
+    info[2] = INT_MAX;
+  }
+}
+
+long long group_ws_elems(const lrigw_ctx *c, int nq) {
+  const long long nn = (long long)c->d.n_aux * c->d.n_aux, nb = (long long)nq * c->d.n_freq;
+  return 4 * nb * nn + nb * zdinv_stride(c->d.n_aux);
+}
+
+int run_screen_group(lrigw_ctx *c, int q0, int nq, const void *chi, const void *V, const void *Vcut, void *Wc_out,
+                     double2 *ws) {
+  const Dims &d = c->d;
+  const int n = d.n_aux, nw = d.n_freq;
+  const long long nn = (long long)n * n, nb = (long long)nq * nw;
+  hipStream_t s = c->stream;
+  const bool cut = Vcut != nullptr && Vcut != V;
+  // the pass's factors: L(q) (and T^H(q)) at a stride of N^2 from q0
+  if (!c->cf_on || q0 < c->cf_q0 || q0 + nq > c->cf_q1 || V != (const void *)((const double2 *)c->cf_V + (long long)q0 * nn) ||
+      (cut && (!c->cf_cut || q0 < 1 || Vcut != (const void *)((const double2 *)c->cf_Vcut + (long long)q0 * nn))))
+    return LRIGW_ERR_ARG;
+  const int nqc = c->cf_q1 - c->cf_q0;
+  const double2 *LV = c->d_cf + (long long)(q0 - c->cf_q0) * nn;
+  const double2 *TH = cut ? c->d_cf + (long long)(nqc + q0 - c->cf_q0) * nn : nullptr;
+  double2 *s0 = ws, *s1 = s0 + nb * nn, *s2 = s1 + nb * nn, *s3 = s2 + nb * nn, *dinv = s3 + nb * nn;
+  const double2 *chiz;
+  if (c->precision == LRIGW_FP64) {
+    chiz = (const double2 *)chi;
+  } else {
+    const long long tot = nb * nn;
+    hipLaunchKernelGGL(k_widen<float2>, dim3((unsigned)std::min<long long>((tot + 255) / 256, 16384)), dim3(256), 0, s,
+                       (const float2 *)chi, s3, tot);
+    chiz = s3;
+  }
+  const double2 one = mkc(1.0, 0.0), mone = mkc(-1.0, 0.0);
+  // the same steps as run_screen_n over nq N_w planes; the factor of plane b
+  // is that of q0 + b / N_w (element b of an operand is read at
+  // (b % N_w) s + (b / N_w) s2: the factor has s = 0, s2 = N^2, the other
+  // operand its plane stride s and s2 = N_w s)
+  auto per_q = [&](ZGemm g, bool a_is_factor) {
+    g.bdiv = nw;
+    if (a_is_factor) {
+      g.sa2 = nn;
+      g.sb2 = (long long)nw * g.sb;
+    } else {
+      g.sb2 = nn;
+      g.sa2 = (long long)nw * g.sa;
+    }
+    return g;
+  };
+  ZGemm gt = per_q(mk(n, n, n, OP_N, chiz, n, nn, OP_N, LV, n, 0, s0, n, nn, one, (int)nb), false);
+  gt.tri_b = TRI_LOWER;
+  LRIGW_TRY(zgemm(s, gt));
+  ZGemm gd = per_q(mk(n, n, n, OP_C, LV, n, 0, OP_N, s0, n, nn, s1, n, nn, mone, (int)nb), true);
+  gd.lower_only = 1;
+  gd.tri_a = TRI_UPPER;
+  LRIGW_TRY(zgemm(s, gd));
+  dim3 eg((unsigned)((nn + 255) / 256), (unsigned)nb);
+  hipLaunchKernelGGL(k_mirror_lower, eg, dim3(256), 0, s, s1, n, nn);
+  hipLaunchKernelGGL(k_add_identity, eg, dim3(256), 0, s, s1, s2, n, nn);
+  LRIGW_TRY(zpotrf_batched(s, s2, n, n, nn, (int)nb, dinv, c->d_info + 2));
+  hipLaunchKernelGGL(k_fold_group, dim3(1), dim3(1), 0, s, c->d_info, q0, nw);
+  LRIGW_TRY(ztrsm_left_lower(s, s2, n, nn, dinv, s1, n, nn, n, n, (int)nb));
+  LRIGW_TRY(ztrsm_left_upper_conj(s, s2, n, nn, dinv, s1, n, nn, n, n, (int)nb));
+  if (cut) {
+    LRIGW_TRY(zgemm(s, per_q(mk(n, n, n, OP_N, s1, n, nn, OP_N, TH, n, 0, s0, n, nn, one, (int)nb), false)));
+  } else {
+    ZGemm g1 = per_q(mk(n, n, n, OP_N, s1, n, nn, OP_C, LV, n, 0, s0, n, nn, one, (int)nb), false);
+    g1.tri_b = TRI_UPPER;
+    LRIGW_TRY(zgemm(s, g1));
+  }
+  ZGemm gw = cut ? per_q(mk(n, n, n, OP_C, TH, n, 0, OP_N, s0, n, nn, s1, n, nn, mone, (int)nb), true)
+                 : per_q(mk(n, n, n, OP_N, LV, n, 0, OP_N, s0, n, nn, s1, n, nn, mone, (int)nb), true);
+  gw.lower_only = 1;
+  if (!cut) gw.tri_a = TRI_LOWER;
+  LRIGW_TRY(zgemm(s, gw));
+  if (c->precision == LRIGW_FP64)
+    hipLaunchKernelGGL(k_hermitize<double>, eg, dim3(256), 0, s, s1, (double2 *)Wc_out, n, nn);
+  else
+    hipLaunchKernelGGL(k_hermitize<float>, eg, dim3(256), 0, s, s1, (float2 *)Wc_out, n, nn);
+  return lrigw_launch_check("screen_group");
+}
+
 // ---------------------------------------------------------------- complex frequencies
 // out[p] = chi[2p] + i chi[2p+1] in FP64 (the Re- and Im-weight planes of the
 // response at w_r + i eta, each a Hermitian matrix)

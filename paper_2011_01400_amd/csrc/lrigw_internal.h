@@ -129,6 +129,11 @@ struct lrigw_ctx {
   // Coulomb factors of a whole pass (CoulombScope): L(q) with V(q) = L L^H and,
   // with V^cut, T^H(q) = L^{-1} V^{1/2} V^cut^{1/2}, for q in [cf_q0, cf_q1)
   double2 *d_cf = nullptr;       // [L(q) ...][T^H(q) ...][diagonal-block inverses][root workspace]
+  // grouped screening (run_pass without graph capture): the responses and
+  // W^c of up to grp_cap q, FP64 workspaces and diagonal-block inverses
+  void *d_grp = nullptr;
+  size_t grp_bytes = 0;
+  int grp_cap = 0;
   size_t cf_bytes = 0;
   const void *cf_V = nullptr, *cf_Vcut = nullptr;
   int cf_q0 = 0, cf_q1 = 0;
@@ -205,6 +210,13 @@ struct GapScope {
 // Not used during graph capture (no allocation there): then each screening
 // factors its own V(q).
 int coulomb_factors(lrigw_ctx *c, const void *V, const void *Vcut, int q0, int q1);
+// Screening of the nq consecutive q from q0 at once (batch nq N_w), with the
+// factors of the live CoulombScope (which must cover them): chi and Wc_out
+// hold nq blocks of N_w planes; ws: FP64 workspace of group_ws_elems(c, nq)
+// complex elements.  Status as in a pass (d_info[16] = first failing q).
+int run_screen_group(lrigw_ctx *c, int q0, int nq, const void *chi, const void *V, const void *Vcut, void *Wc_out,
+                     double2 *ws);
+long long group_ws_elems(const lrigw_ctx *c, int nq);
 struct CoulombScope {
   lrigw_ctx *c;
   explicit CoulombScope(lrigw_ctx *ctx) : c(ctx) {}
@@ -323,6 +335,10 @@ struct ZGemm {
   // op(A) / op(B) triangular with zeros stored in the other triangle (TRI_LOWER,
   // TRI_UPPER): each tile then runs only the K range its rows / columns need
   int tri_a = 0, tri_b = 0;
+  // batch element b reads A at (b % bdiv) sa + (b / bdiv) sa2 (and B alike):
+  // one operand per group of bdiv elements (a factor per q for its frequencies)
+  int bdiv = 1 << 30;
+  long long sa2 = 0, sb2 = 0;
 };
 enum { TRI_NONE = 0, TRI_LOWER = 1, TRI_UPPER = 2 };
 int zgemm(hipStream_t s, const ZGemm &g);
