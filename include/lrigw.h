@@ -272,7 +272,12 @@ int lrigw_pade_eval(lrigw_ctx *ctx, const void *sigma, int n_par, int n_e, const
  * Vcut: complex128 [N_k][N_aux][N_aux] truncated Coulomb matrices V^cut(q) for
  * the numerator of the screening at q != 0 (lrigw_screen), or NULL (V^cut =
  * V); Vcut[0] is not read (V[0] is V^cut(0), used in both places at q = 0).
- * The buffers for M, chi0 and W^c are owned by the context. */
+ * The buffers for M, chi0 and W^c are owned by the context.  The Cholesky
+ * factors of V(q) (and the V^cut factors) of q_first..q_last-1 are computed
+ * once per call, batched.  Without graph capture, a surrogate or a direction
+ * average, the q are screened in groups of up to 8 (as many as 8 GiB of
+ * responses, W^c and FP64 workspace allow; the context keeps those buffers),
+ * each group's screening beside the next group's responses. */
 int lrigw_g0w0(lrigw_ctx *ctx, const void *H, const void *evec, const double *eig, const void *V, const void *Vcut,
                const void *p, double omega_cell, const double *e_static, int n_par, int q_first, int q_last,
                void *sigma, double *e_qp, double *z, int *info);
