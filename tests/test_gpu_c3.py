@@ -2,8 +2,9 @@
 260 to 1040; 4x4x4 and 3x3x3 k; 32 frequencies) in one captured hipGraph,
 FP16 form with the tile autotuner, as `bench.py --workload batched` runs them.
 Checked: every cell's status; each cell's batched result equals its own
-lrigw_g0w0 on the same tuned context; and on the smallest cell one q's Sigma^c
-contribution at sampled k points equals the FP64 oracle's.
+lrigw_g0w0 on the same tuned context; on the smallest cell one q's Sigma^c
+contribution at sampled k points equals the FP64 oracle's; and on the
+largest cell two q against the oracle's sampled values (golden file).
 
 Sigma^c(k) = Sigma^c(-k) does not hold with one direction q_hat. The q -> 0
 head and wings are taken along q_hat, and the wings are odd in p.q_hat. These
@@ -97,13 +98,16 @@ def test_smallest_cell_one_q_against_oracle(batched):
     ctx = it["ctx"]
     q = 1
     dev = L.device_inputs(s)
+    torch.cuda.synchronize()
     M, x, chi, W = ctx.empty("M"), ctx.empty("x"), ctx.empty("W"), ctx.empty("W")
     ctx.build_M(q, 0, it["H"], it["evec"], M)
     ctx.chi0(q, M, it["eig"], chi)
     ctx.screen(q, chi, dev["V"][q], W)
     ctx.build_M(q, 1, it["H"], it["evec"], x)
     sg = torch.zeros((s.n_k, sp.n_qp, sp.n_freq), dtype=torch.complex128, device="cuda")
+    torch.cuda.synchronize()            # the context launches on the batch's stream
     ctx.sigma_c(q, x, W, it["eig"], sg)
+    torch.cuda.synchronize()
     ks = [0, 5, s.n_k - 1]
     t0 = time.perf_counter()
     o = Oracle(s)
@@ -113,6 +117,69 @@ def test_smallest_cell_one_q_against_oracle(batched):
     print(f"  cell {i} (N_aux {s.n_aux}, {s.n_k} k) q={q}: sampled Sigma^c rel {e:.1e} "
           f"(oracle {time.perf_counter() - t0:.1f} s)", flush=True)
     assert e < 2e-5
+
+
+def test_largest_cell_sampled_q_against_oracle(batched):
+    """The largest cell (8 atoms, N_aux 1040, the streaming self-energy kernel
+    and the multi-block Cholesky) with its tuned FP16 tiles, and the plain FP64
+    path, against the oracle's values for two q (q = 0 with the Gamma
+    treatment) written by tests/golden/make_c3_golden.py: chi0 and W^c rows at
+    three frequencies, and the Sigma^c contribution at three k.  Its batched
+    result equals its own pass (test_batched_equals_per_cell_pass)."""
+    import os
+    gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_cell5_sampled.npz")
+    if not os.path.exists(gold):
+        pytest.skip("c3_cell5_sampled.npz not written")
+    L, cells, items, b, st = batched
+    g = np.load(gold)
+    i = int(g["CELL"])
+    s, it = cells[i], items[i]
+    assert int(g["seed"]) == s.seed
+    sp = s.spec
+    n = s.n_aux
+    rows = int(g["ROWS"])
+    widx, kidx = g["W_IDX"], g["K_IDX"]
+    dev = L.device_inputs(s)
+    torch.cuda.synchronize()
+
+    def relf(a, b_):
+        return np.linalg.norm(a - b_) / np.linalg.norm(b_)
+
+    for precision, tol in (("split_f16", 1e-5), ("fp64", 1e-10)):
+        if precision == "split_f16":
+            ctx, H = it["ctx"], it["H"]
+        else:
+            ctx = L.Context.from_system(s, precision="fp64")
+            H = ctx.empty("H")
+            ctx.lri_ft(dev["lri"], s.R, dev["evec"], H)
+        ctx.gamma_prepare(dev["V"][0], dev["p"], s.omega_cell)
+        M, x, chi, W = ctx.empty("M"), ctx.empty("x"), ctx.empty("W"), ctx.empty("W")
+        for q in g["Q"]:
+            q = int(q)
+            # the batched contexts launch on the batch's stream, the copies
+            # below run on the default one: the device is synchronised first
+            ctx.build_M(q, 0, H, dev["evec"], M)
+            ctx.chi0(q, M, dev["eig"], chi)
+            torch.cuda.synchronize()
+            ec = relf(chi.cpu().numpy().reshape(-1, n, n)[widx, :rows], g[f"chi_q{q}"])
+            if q == 0:
+                ctx.chi0(0, M, dev["eig"], chi, apply_gamma=True)
+            ctx.screen(q, chi, dev["V"][q], W)
+            torch.cuda.synchronize()
+            ew = relf(W.cpu().numpy().reshape(-1, n, n)[widx, :rows], g[f"wc_q{q}"])
+            ctx.build_M(q, 1, H, dev["evec"], x)
+            sig = torch.zeros((s.n_k, sp.n_qp, sp.n_freq), dtype=torch.complex128, device="cuda")
+            torch.cuda.synchronize()
+            ctx.sigma_c(q, x, W, dev["eig"], sig)
+            torch.cuda.synchronize()
+            ref = g[f"sigma_q{q}"]
+            es = np.max(np.abs(sig.cpu().numpy()[kidx] - ref)) / np.max(np.abs(ref))
+            print(f"  cell {i} q={q} {precision} (tiles {ctx.tiles}): chi {ec:.2e}  Wc {ew:.2e}  Sigma_q {es:.2e}",
+                  flush=True)
+            assert ec < tol and ew < 10 * tol and es < 10 * tol
+        del M, x, chi, W
+        if precision == "fp64":
+            ctx.close()
 
 
 def test_batched_with_directions_restores_time_reversal(batched):
