@@ -14,6 +14,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -158,6 +159,28 @@ def roofline(sysm, stages, precision, config):
     return {"bound": "mfma", "kernel": name, "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": traffic_for(name, precision, config),
             "avg_launch_ms": round(ms / n, 4), "flops_per_launch": f}
+
+
+def mfma_sustained():
+    """The sustained dense FP16 matrix-core rate of this device, from the
+    calibration program built beside the library (eight independent
+    16x16x32 FP16 MFMA chains per wave on every SIMD, zero and then random
+    operands, with the mean shader clock of each), run in a child process
+    after the timed steps.  With random operands the clock drops below its
+    peak, so the published peak is not reachable with the data the kernels
+    see; the fractions against this rate are reported beside those against
+    the published peak."""
+    exe = os.path.join(ROOT, "paper_2011_01400_amd", "mfma_rate")
+    if not os.path.exists(exe):
+        return {"error": "calibration program not built"}
+    try:
+        r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+        d = json.loads(r.stdout.strip().splitlines()[-1])
+    except (subprocess.TimeoutExpired, ValueError, IndexError) as e:
+        return {"error": str(e)}
+    if r.returncode != 0 and "error" not in d:
+        d["error"] = f"exit status {r.returncode}"
+    return d
 
 
 def other_kernel(sysm, stages, precision, rl):
@@ -696,6 +719,15 @@ def main():
     }
     if tuned:
         out["tuned"] = tuned
+    if args.precision == "split_f16":
+        sus = mfma_sustained()
+        out["mfma_sustained"] = sus
+        if "random" in sus and sus["random"]["pflops"] > 0:
+            ref = sus["random"]["pflops"] * 1e3
+            rl["frac_of_sustained_fp16"] = round(rl["achieved"] / ref, 4)
+            for v in out["other_kernel"].values():
+                v["frac_of_sustained_fp16"] = round(v["achieved"] / ref, 4)
+        print(f"# bench: sustained FP16 MFMA {sus}", file=sys.stderr, flush=True)
     if not args.no_extras:
         out["sigma_x"] = sigma_x_timing(run, sysm, dev)
         out["lri_fit"] = lri_fit_timing(run, sysm)
