@@ -923,6 +923,9 @@ __global__ __launch_bounds__(256) void k_pair_diag(const float2 *__restrict__ x,
 // Tile lists of the resident-tile form: the 32-row tiles with work are shared
 // by the NWV/F' waves of a frequency, largest first to the least loaded wave
 // (cost = number of nu chunks); every frequency slot gets the same lists.
+// With eight waves, waves w and w + 4 share a SIMD (waves are placed on the
+// SIMDs in turn) and their MFMA pipe: the second four take the lists in the
+// opposite order, so that each SIMD runs a heavier and a lighter list.
 static bool sigma_res_plan(int N, int n_freq, int NWV, std::vector<int> &table, int &F) {
   const int Npad = (N + SKB - 1) / SKB * SKB, Rpad = (N + TILE - 1) / TILE * TILE;
   F = (n_freq + 7) / 8;
@@ -946,9 +949,15 @@ static bool sigma_res_plan(int N, int n_freq, int NWV, std::vector<int> &table, 
     load[wv] += pr.first;
     lists[wv].push_back(pr.second);
   }
+  // heaviest list first
+  std::vector<int> order(wpf);
+  for (int v = 0; v < wpf; ++v) order[v] = v;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return load[a] > load[b]; });
   table.assign(NWV * (RES_MAXI + 1), 0);
   for (int wave = 0; wave < NWV; ++wave) {
-    const std::vector<int> &l = lists[wave % wpf];
+    int li = wave % wpf;
+    if (NWV == 8 && wave >= 4) li = wpf <= 4 ? wpf - 1 - li : 11 - wave;
+    const std::vector<int> &l = lists[order[li]];
     if ((int)l.size() > RES_MAXI) return false;
     table[wave * (RES_MAXI + 1)] = (int)l.size();
     for (size_t i = 0; i < l.size(); ++i) table[wave * (RES_MAXI + 1) + 1 + i] = l[i];
