@@ -211,7 +211,9 @@ __device__ inline void splitn(float v, __bf16 *p) {
 // fragments (rows) come from a double-buffered LDS tile filled with 16-byte
 // copies of Ap; the B fragments (the wave's 16 columns) are read from Bt
 // straight into registers, weighted by 2D/(D^2 + w^2) and split into NS parts
-// there, once per element and frequency.
+// there, once per element and frequency.  With four frequencies per workgroup
+// (k_chi0_split8) eight waves share the tile: the B chunk goes through LDS as
+// well, and each chunk of A and B is loaded once for the four frequencies.
 // amax[mu] = max(amax[mu], largest |Re|, |Im| of B[k][mu] over 64 rows k) as
 // float bits; one block per 64 rows of K
 __global__ __launch_bounds__(256) void k_absmax_rows(const float2 *__restrict__ B, long long K, int N, unsigned *__restrict__ amax) {
@@ -271,8 +273,9 @@ __global__ __launch_bounds__(256) void k_chi0_presplit(const float2 *__restrict_
   }
 }
 
-// With NW = 2 the kernel is held to two waves per SIMD (249 registers), so
-// one wave's weighting and splitting overlaps the other's products.
+// Two frequencies per workgroup (NW = 2; four frequencies run in
+// k_chi0_split8): the kernel is held to two waves per SIMD (232 registers),
+// so one wave's weighting and splitting overlaps the other's products.
 // FP16 parts (H): the weight of frequency w is taken times 2^-e_w with
 // 2^e_w >= 1/w, which bounds |2D/(D^2 + w^2)| by 1, so the weighted, row-scaled
 // B side stays below 2^15; the tile is scaled back by s_mu s_nu 2^e_w.
@@ -282,7 +285,7 @@ __global__ __launch_bounds__(256) void k_chi0_presplit(const float2 *__restrict_
 template <int V> struct IntC { static constexpr int value = V; };
 
 template <int NS, int NW, int PAD, bool H>
-__global__ __launch_bounds__(256, NW == 2 ? 2 : 1) void k_chi0_split(const us16 *__restrict__ Ap, const float2 *__restrict__ Bt,
+__global__ __launch_bounds__(256, 2) void k_chi0_split(const us16 *__restrict__ Ap, const float2 *__restrict__ Bt,
                                                     const float *__restrict__ delta, const double *__restrict__ om2tab,
                                                     const double2 *__restrict__ cpltab, const float *__restrict__ wsctab, const int *__restrict__ wsel, const int *__restrict__ run, long long K,
                                                     long long Kp, int Npad, int n_freq, long long Ks, long long ntile,
@@ -457,6 +460,200 @@ store:
     if (w0 + w >= n_freq) continue;
     float2 *dst = part + (((long long)ks * n_freq + w0 + w) * ntile + tile) * (TILE * TILE);
     const int cl = 16 * wave + col;
+    const float fcol = H ? pow2_scale(__uint_as_float(amax[nu0 + cl < N ? nu0 + cl : 0])) / wsc[w] : 1.f;
+#pragma unroll
+    for (int si = 0; si < 4; ++si) {
+      if (16 * si >= N - mu0) break;
+      const f4v r = re[w][si], i = im[w][si];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = 16 * si + Mfma<float>::row(lane, q);
+        const float f = H ? fcol * pow2_scale(__uint_as_float(amax[mu0 + row < N ? mu0 + row : 0])) : 1.f;
+        dst[row * TILE + cl] = mkcf(r[q] * f, i[q] * f);
+      }
+    }
+  }
+}
+
+// Eight waves per workgroup, four frequencies: waves w and w + 4 take the same
+// 16 columns for frequency pairs 0 and 1, so the A and B chunks of a tile are
+// loaded once (by all 512 threads, into double-buffered LDS) for four
+// frequencies instead of two.  The B columns of a wave come from LDS in FP32
+// and are weighted and split per frequency in registers as in k_chi0_split.
+template <int NS, int PAD, bool H>
+__global__ __launch_bounds__(512) void k_chi0_split8(const us16 *__restrict__ Ap, const float2 *__restrict__ Bt,
+                                                     const float *__restrict__ delta, const double *__restrict__ om2tab,
+                                                     const double2 *__restrict__ cpltab, const float *__restrict__ wsctab,
+                                                     const int *__restrict__ wsel, const int *__restrict__ run, long long K,
+                                                     long long Kp, int Npad, int n_freq, long long Ks, long long ntile,
+                                                     const unsigned *__restrict__ amax, int N, float2 *__restrict__ part,
+                                                     int nsplit) {
+  constexpr int NW = 2, NF = 4;
+  if (run && *run == 0) return;
+  __shared__ __attribute__((aligned(16))) us16 As[2][NS * 2][TILE][KCB + PAD];
+  __shared__ __attribute__((aligned(16))) float2 Bs[2][TILE][KCB + BBP];
+  __shared__ __attribute__((aligned(16))) float wtab[2][NF][KCB];
+  const int nfg = (n_freq + NF - 1) / NF;
+  const long long total = (long long)nfg * ntile * nsplit, per = (total + 7) / 8;
+  const long long wi = (long long)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (wi >= total) return;
+  const int fgi = (int)(wi % nfg);
+  const int tile = (int)((wi / nfg) % ntile);
+  const int ks = (int)(wi / ((long long)nfg * ntile));
+  int I, J;
+  tri_decode(tile, I, J);
+  const long long kb = (long long)ks * Ks;
+  const long long ke = min(K, kb + Ks);
+  const int mu0 = I * TILE, nu0 = J * TILE;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, g = lane >> 4;
+  const int wcg = wave & 3, wf = wave >> 2;
+  const int w0 = fgi * NF + wf * NW;
+  const bool cplx = cpltab != nullptr;
+  float om2[NW], wsc[NW];
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const bool in = w0 + w < n_freq;
+    om2[w] = in ? (float)om2tab[wsel[w0 + w]] : 0.f;
+    wsc[w] = (H && in) ? wsctab[wsel[w0 + w]] : 1.f;
+  }
+  // the weight table: thread t < NF * KCB owns frequency fgi * NF + t / KCB and row t % KCB
+  const int tw = tid / KCB, tk = tid % KCB;
+  const bool wown = tw < NF && fgi * NF + tw < n_freq;
+  const int fw_ = wown ? wsel[fgi * NF + tw] : 0;
+  const float tom2 = wown ? (float)om2tab[fw_] : 0.f;
+  const float twsc = (H && wown) ? wsctab[fw_] : 1.f;
+  const double2 tcp = (cplx && wown) ? cpltab[fw_] : mkc(0.0, 0.0);
+  const float tcsv = (float)tcp.x;
+  const bool tcim = tcp.y != 0.0;
+  auto weight = [&](float dd) {
+    if (cplx) {
+      const float a = dd * dd + tom2;
+      return 2.f * dd * (tcim ? tcsv : a) / (a * a + tcsv * tcsv) * twsc;
+    }
+    return 2.f * dd / (dd * dd + tom2) * twsc;
+  };
+  // rows past K are zero in both operands: any finite weight serves
+  auto dload = [&](long long k0) -> float { return delta[min(k0 + tk, K - 1)]; };
+  f4v re[NW][4], im[NW][4];
+#pragma unroll
+  for (int w = 0; w < NW; ++w)
+#pragma unroll
+    for (int si = 0; si < 4; ++si) re[w][si] = im[w][si] = Mfma<float>::zero();
+  const int nch = (int)((ke - kb + KCB - 1) / KCB);
+  if (nch <= 0) goto store;
+  {
+    // A staging: plane parity ap, row arow, 8-k piece ak; B staging: column bc, 4-k piece bk
+    const int ap = tid >> 8, arow = (tid >> 2) & 63, ak = (tid & 3) * 8;
+    const int bc = tid >> 3, bk = (tid & 7) * 4;
+    const long long pstride = (long long)Npad * Kp;
+    const us16 *asrc = Ap + (long long)ap * pstride + (long long)(mu0 + arow) * Kp + kb + ak;
+    const float2 *bsrc = Bt + (long long)(nu0 + bc) * Kp + kb + bk;
+    u32x4 apre[NS], bpre[2];
+    float dnext = 1.f;
+#pragma unroll
+    for (int m = 0; m < NS; ++m) apre[m] = *(const u32x4 *)(asrc + 2 * m * pstride);
+#pragma unroll
+    for (int e = 0; e < 2; ++e) bpre[e] = *(const u32x4 *)(bsrc + 2 * e);
+    if (tw < NF) wtab[0][tw][tk] = weight(dload(kb));
+#pragma unroll
+    for (int m = 0; m < NS; ++m) *(u32x4 *)&As[0][ap + 2 * m][arow][ak] = apre[m];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) *(u32x4 *)&Bs[0][bc][bk + 2 * e] = bpre[e];
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    auto loop = [&](auto nsi_c) {
+      constexpr int NSI = decltype(nsi_c)::value;
+      for (int ch = 0; ch < nch; ++ch) {
+        const int b = ch & 1;
+        {
+          const long long off = (long long)min(ch + 1, nch - 1) * KCB;
+#pragma unroll
+          for (int m = 0; m < NS; ++m) apre[m] = *(const u32x4 *)(asrc + 2 * m * pstride + off);
+#pragma unroll
+          for (int e = 0; e < 2; ++e) bpre[e] = *(const u32x4 *)(bsrc + off + 2 * e);
+          dnext = dload(kb + off);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        // this wave's 16 columns of the chunk, 8 consecutive k per lane
+        float2 bcur[8];
+#pragma unroll
+        for (int e = 0; e < 8; e += 2) *(u32x4 *)&bcur[e] = *(const u32x4 *)&Bs[b][16 * wcg + col][8 * g + e];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          float wt8[8];
+          *(float4 *)&wt8[0] = *(const float4 *)&wtab[b][wf * NW + w][8 * g];
+          *(float4 *)&wt8[4] = *(const float4 *)&wtab[b][wf * NW + w][8 * g + 4];
+          u32x4 br[NS], bi[NS], nbi[NS];
+          if constexpr (H && NS == 2) {
+#pragma unroll
+            for (int e = 0; e < 8; e += 2) {
+              unsigned h, l;
+              split2_h_pair(wt8[e], bcur[e].x, wt8[e + 1], bcur[e + 1].x, h, l);
+              br[0][e / 2] = h;
+              br[1][e / 2] = l;
+              split2_h_pair(wt8[e], bcur[e].y, wt8[e + 1], bcur[e + 1].y, h, l);
+              bi[0][e / 2] = h;
+              bi[1][e / 2] = l;
+            }
+          } else {
+            us16 brs[NS][8], bis[NS][8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const float wt = wt8[e];
+              us16 pr_[NS], pi_[NS];
+              split_n<NS, H>(wt * bcur[e].x, pr_);
+              split_n<NS, H>(wt * bcur[e].y, pi_);
+#pragma unroll
+              for (int p = 0; p < NS; ++p) {
+                brs[p][e] = pr_[p];
+                bis[p][e] = pi_[p];
+              }
+            }
+#pragma unroll
+            for (int p = 0; p < NS; ++p) {
+              br[p] = *(const u32x4 *)brs[p];
+              bi[p] = *(const u32x4 *)bis[p];
+            }
+          }
+#pragma unroll
+          for (int p = 0; p < NS; ++p) nbi[p] = bi[p] ^ 0x80008000u;
+#pragma unroll
+          for (int si = 0; si < NSI; ++si) {
+#pragma unroll
+            for (int p = 0; p < NS; ++p) {
+              const u32x4 ar = *(const u32x4 *)&As[b][2 * p][16 * si + col][8 * g];
+              const u32x4 ai = *(const u32x4 *)&As[b][2 * p + 1][16 * si + col][8 * g];
+#pragma unroll
+              for (int q = 0; q + p < NS; ++q) {
+                re[w][si] = mfma_p<H>(ar, br[q], re[w][si]);
+                re[w][si] = mfma_p<H>(ai, bi[q], re[w][si]);
+                im[w][si] = mfma_p<H>(ai, br[q], im[w][si]);
+                im[w][si] = mfma_p<H>(ar, nbi[q], im[w][si]);
+              }
+            }
+          }
+        }
+        {
+#pragma unroll
+          for (int m = 0; m < NS; ++m) *(u32x4 *)&As[b ^ 1][ap + 2 * m][arow][ak] = apre[m];
+#pragma unroll
+          for (int e = 0; e < 2; ++e) *(u32x4 *)&Bs[b ^ 1][bc][bk + 2 * e] = bpre[e];
+          if (tw < NF) wtab[b ^ 1][tw][tk] = weight(dnext);
+        }
+        __syncthreads();
+      }
+    };
+    const int rem = N - mu0;
+    if (rem > 2 * 16) loop(IntC<4>());
+    else if (rem > 16) loop(IntC<2>());
+    else loop(IntC<1>());
+  }
+store:
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    if (w0 + w >= n_freq) continue;
+    float2 *dst = part + (((long long)ks * n_freq + w0 + w) * ntile + tile) * (TILE * TILE);
+    const int cl = 16 * wcg + col;
     const float fcol = H ? pow2_scale(__uint_as_float(amax[nu0 + cl < N ? nu0 + cl : 0])) / wsc[w] : 1.f;
 #pragma unroll
     for (int si = 0; si < 4; ++si) {
@@ -716,8 +913,8 @@ int run_chi0_tab(lrigw_ctx *c, int iq, const void *M, const double *eig, int app
 #define BF16_ARGS Apb, Btb, Db, om2t, cplt, wsct, wsel, run, Kb, Kp, Npad, n_sel, Ks, ntile, c->d_amax, d.n_aux, Pf, sb
 #define SPLIT_LAUNCH(NS_, H_)                                                                                            \
   do {                                                                                                                 \
-    if (NW == 4 && p16) hipLaunchKernelGGL((k_chi0_split<NS_, 4, 16, H_>), sgrid, dim3(256), 0, c->stream, BF16_ARGS); \
-    else if (NW == 4) hipLaunchKernelGGL((k_chi0_split<NS_, 4, 8, H_>), sgrid, dim3(256), 0, c->stream, BF16_ARGS);   \
+    if (NW == 4 && p16) hipLaunchKernelGGL((k_chi0_split8<NS_, 16, H_>), sgrid, dim3(512), 0, c->stream, BF16_ARGS); \
+    else if (NW == 4) hipLaunchKernelGGL((k_chi0_split8<NS_, 8, H_>), sgrid, dim3(512), 0, c->stream, BF16_ARGS);   \
     else if (p16) hipLaunchKernelGGL((k_chi0_split<NS_, 2, 16, H_>), sgrid, dim3(256), 0, c->stream, BF16_ARGS);      \
     else hipLaunchKernelGGL((k_chi0_split<NS_, 2, 8, H_>), sgrid, dim3(256), 0, c->stream, BF16_ARGS);                \
   } while (0)
