@@ -24,10 +24,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 1 << 30          # calibration copy: 1 GiB read + 1 GiB written
 # the main kernel of each stage (all its variants) and its source file
 FAMILIES = {"sigma_mfma": (("k_sigma_res", "k_sigma_split", "k_sigma_splitq", "k_sigma_mfma"), "k_sigma.hip"),
-            "chi0_mfma": (("k_chi0_split", "k_chi0_mfma"), "k_chi0.hip")}
+            "chi0_mfma": (("k_chi0_split", "k_chi0_split8", "k_chi0_mfma"), "k_chi0.hip")}
 
 
-def run(precision: str, config: int, q: int):
+def run(precision: str, config: int, q: int, chi0_nw: int = 0):
     import torch
     sys.path.insert(0, ROOT)
     from paper_2011_01400_amd import lrigw as L
@@ -47,6 +47,11 @@ def run(precision: str, config: int, q: int):
     H = ctx.empty("H")
     ctx.lri_ft(dev["lri"], s.R, dev["evec"], H)
     ctx.tune(H, dev["evec"], dev["eig"])           # the kernel variants bench.py runs
+    if chi0_nw:
+        # the tuner's choice between the two response kernels is a near-tie
+        # that varies by run: hold the one asked for (tuned splits and padding)
+        nw, sp_, pad, var = ctx.tiles
+        ctx.set_tiles(chi0_nw, sp_, pad, var)
     sigma = torch.zeros((s.n_k, sp.n_qp, sp.n_freq), dtype=torch.complex128, device="cuda")
     e = torch.zeros((s.n_k, sp.n_qp), dtype=torch.float64, device="cuda")
     z = torch.zeros_like(e)
@@ -208,6 +213,8 @@ if __name__ == "__main__":
     ap.add_argument("--counters", nargs="+", metavar="PMC_DIR", help="markdown table of the counters of these runs")
     ap.add_argument("--contour", action="store_true", help="one contour-deformation pass instead of one q")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--chi0-nw", type=int, default=0, help="hold the response kernel at this many frequencies per "
+                    "workgroup after tuning (2 or 4; 0: the tuner's choice)")
     a = ap.parse_args()
     if a.counters:
         summarize_counters(a.counters, f"{a.precision}, config {a.config}")
@@ -216,4 +223,4 @@ if __name__ == "__main__":
     elif a.contour:
         run_contour(a.precision, a.config)
     else:
-        run(a.precision, a.config, a.q)
+        run(a.precision, a.config, a.q, a.chi0_nw)
