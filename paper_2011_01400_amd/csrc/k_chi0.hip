@@ -284,6 +284,98 @@ __global__ __launch_bounds__(256) void k_chi0_presplit(const float2 *__restrict_
 // partial-tile rows are never read).
 template <int V> struct IntC { static constexpr int value = V; };
 
+// One K chunk of a wave's 64 x 16 strip for NW frequencies: the wave's 16
+// columns bcur (8 consecutive k per lane, FP32) are weighted by the rows wt0,
+// wt0 + KCB, ... of the chunk's weight table, split into NS parts and
+// multiplied with the A fragments of the NSI 16-row blocks in the LDS tile
+// Asb: a conj(b), re = ar br + ai bi, im = ai br - ar bi, with the sign taken
+// on the wave's own (weighted) side.
+template <int NS, int NW, int NSI, int PAD, bool H>
+__device__ __forceinline__ void chi0_chunk(const float2 (&bcur)[8], const float *wt0, const us16 (*Asb)[TILE][KCB + PAD],
+                                           int col, int g, f4v (&re)[NW][4], f4v (&im)[NW][4]) {
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    float wt8[8];
+    *(float4 *)&wt8[0] = *(const float4 *)&wt0[w * KCB + 8 * g];
+    *(float4 *)&wt8[4] = *(const float4 *)&wt0[w * KCB + 8 * g + 4];
+    u32x4 br[NS], bi[NS], nbi[NS];
+    if constexpr (H && NS == 2) {
+#pragma unroll
+      for (int e = 0; e < 8; e += 2) {
+        unsigned h, l;
+        split2_h_pair(wt8[e], bcur[e].x, wt8[e + 1], bcur[e + 1].x, h, l);
+        br[0][e / 2] = h;
+        br[1][e / 2] = l;
+        split2_h_pair(wt8[e], bcur[e].y, wt8[e + 1], bcur[e + 1].y, h, l);
+        bi[0][e / 2] = h;
+        bi[1][e / 2] = l;
+      }
+    } else {
+      us16 brs[NS][8], bis[NS][8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float wt = wt8[e];
+        us16 pr_[NS], pi_[NS];
+        split_n<NS, H>(wt * bcur[e].x, pr_);
+        split_n<NS, H>(wt * bcur[e].y, pi_);
+#pragma unroll
+        for (int p = 0; p < NS; ++p) {
+          brs[p][e] = pr_[p];
+          bis[p][e] = pi_[p];
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < NS; ++p) {
+        br[p] = *(const u32x4 *)brs[p];
+        bi[p] = *(const u32x4 *)bis[p];
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < NS; ++p) nbi[p] = bi[p] ^ 0x80008000u;
+#pragma unroll
+    for (int si = 0; si < NSI; ++si) {
+#pragma unroll
+      for (int p = 0; p < NS; ++p) {
+        const u32x4 ar = *(const u32x4 *)&Asb[2 * p][16 * si + col][8 * g];
+        const u32x4 ai = *(const u32x4 *)&Asb[2 * p + 1][16 * si + col][8 * g];
+#pragma unroll
+        for (int q = 0; q + p < NS; ++q) {
+          re[w][si] = mfma_p<H>(ar, br[q], re[w][si]);
+          re[w][si] = mfma_p<H>(ai, bi[q], re[w][si]);
+          im[w][si] = mfma_p<H>(ai, br[q], im[w][si]);
+          im[w][si] = mfma_p<H>(ar, nbi[q], im[w][si]);
+        }
+      }
+    }
+  }
+}
+
+// The wave's partial tiles (64 rows x its 16 columns cl, frequencies w0 ..
+// w0 + NW - 1 of K split ks), scaled back by the row and column powers of two
+// and the frequency's weight scale in the FP16 form.
+template <int NW, bool H>
+__device__ __forceinline__ void chi0_store(const f4v (&re)[NW][4], const f4v (&im)[NW][4], const float (&wsc)[NW], int w0,
+                                           int n_freq, int ks, long long ntile, int tile, int mu0, int nu0, int cl, int N,
+                                           int lane, const unsigned *__restrict__ amax, float2 *__restrict__ part) {
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    if (w0 + w >= n_freq) continue;
+    float2 *dst = part + (((long long)ks * n_freq + w0 + w) * ntile + tile) * (TILE * TILE);
+    const float fcol = H ? pow2_scale(__uint_as_float(amax[nu0 + cl < N ? nu0 + cl : 0])) / wsc[w] : 1.f;
+#pragma unroll
+    for (int si = 0; si < 4; ++si) {
+      if (16 * si >= N - mu0) break;
+      const f4v r = re[w][si], i = im[w][si];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = 16 * si + Mfma<float>::row(lane, q);
+        const float f = H ? fcol * pow2_scale(__uint_as_float(amax[mu0 + row < N ? mu0 + row : 0])) : 1.f;
+        dst[row * TILE + cl] = mkcf(r[q] * f, i[q] * f);
+      }
+    }
+  }
+}
+
 template <int NS, int NW, int PAD, bool H>
 __global__ __launch_bounds__(256, 2) void k_chi0_split(const us16 *__restrict__ Ap, const float2 *__restrict__ Bt,
                                                     const float *__restrict__ delta, const double *__restrict__ om2tab,
@@ -382,63 +474,7 @@ __global__ __launch_bounds__(256, 2) void k_chi0_split(const us16 *__restrict__ 
         dnext = dload(kb + off);
       }
       __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        // this wave's 16 columns, weighted for frequency w and split
-        float wt8[8];
-        *(float4 *)&wt8[0] = *(const float4 *)&wtab[b][w][8 * g];
-        *(float4 *)&wt8[4] = *(const float4 *)&wtab[b][w][8 * g + 4];
-        u32x4 br[NS], bi[NS], nbi[NS];
-        if constexpr (H && NS == 2) {
-#pragma unroll
-          for (int e = 0; e < 8; e += 2) {
-            unsigned h, l;
-            split2_h_pair(wt8[e], bcur[e].x, wt8[e + 1], bcur[e + 1].x, h, l);
-            br[0][e / 2] = h;
-            br[1][e / 2] = l;
-            split2_h_pair(wt8[e], bcur[e].y, wt8[e + 1], bcur[e + 1].y, h, l);
-            bi[0][e / 2] = h;
-            bi[1][e / 2] = l;
-          }
-        } else {
-          us16 brs[NS][8], bis[NS][8];
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const float wt = wt8[e];
-            us16 pr_[NS], pi_[NS];
-            split_n<NS, H>(wt * bcur[e].x, pr_);
-            split_n<NS, H>(wt * bcur[e].y, pi_);
-#pragma unroll
-            for (int p = 0; p < NS; ++p) {
-              brs[p][e] = pr_[p];
-              bis[p][e] = pi_[p];
-            }
-          }
-#pragma unroll
-          for (int p = 0; p < NS; ++p) {
-            br[p] = *(const u32x4 *)brs[p];
-            bi[p] = *(const u32x4 *)bis[p];
-          }
-        }
-#pragma unroll
-        for (int p = 0; p < NS; ++p) nbi[p] = bi[p] ^ 0x80008000u;   // the sign is taken on this wave's own side
-#pragma unroll
-        for (int si = 0; si < NSI; ++si) {
-#pragma unroll
-          for (int p = 0; p < NS; ++p) {
-            const u32x4 ar = *(const u32x4 *)&As[b][2 * p][16 * si + col][8 * g];
-            const u32x4 ai = *(const u32x4 *)&As[b][2 * p + 1][16 * si + col][8 * g];
-            // a conj(b): re = ar br + ai bi, im = ai br - ar bi
-#pragma unroll
-            for (int q = 0; q + p < NS; ++q) {
-              re[w][si] = mfma_p<H>(ar, br[q], re[w][si]);
-              re[w][si] = mfma_p<H>(ai, bi[q], re[w][si]);
-              im[w][si] = mfma_p<H>(ai, br[q], im[w][si]);
-              im[w][si] = mfma_p<H>(ar, nbi[q], im[w][si]);
-            }
-          }
-        }
-      }
+      chi0_chunk<NS, NW, NSI, PAD, H>(bcur, &wtab[b][0][0], As[b], col, g, re, im);
       if (ch + 1 < nch) {
 #pragma unroll
         for (int pr = 0; pr < NS * 2; ++pr) *(u32x4 *)&As[b ^ 1][pr][arow][ak] = apre[pr];
@@ -455,24 +491,7 @@ __global__ __launch_bounds__(256, 2) void k_chi0_split(const us16 *__restrict__ 
     else loop(IntC<1>());
   }
 store:
-#pragma unroll
-  for (int w = 0; w < NW; ++w) {
-    if (w0 + w >= n_freq) continue;
-    float2 *dst = part + (((long long)ks * n_freq + w0 + w) * ntile + tile) * (TILE * TILE);
-    const int cl = 16 * wave + col;
-    const float fcol = H ? pow2_scale(__uint_as_float(amax[nu0 + cl < N ? nu0 + cl : 0])) / wsc[w] : 1.f;
-#pragma unroll
-    for (int si = 0; si < 4; ++si) {
-      if (16 * si >= N - mu0) break;
-      const f4v r = re[w][si], i = im[w][si];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int row = 16 * si + Mfma<float>::row(lane, q);
-        const float f = H ? fcol * pow2_scale(__uint_as_float(amax[mu0 + row < N ? mu0 + row : 0])) : 1.f;
-        dst[row * TILE + cl] = mkcf(r[q] * f, i[q] * f);
-      }
-    }
-  }
+  chi0_store<NW, H>(re, im, wsc, w0, n_freq, ks, ntile, tile, mu0, nu0, 16 * wave + col, N, lane, amax, part);
 }
 
 // Eight waves per workgroup, four frequencies: waves w and w + 4 take the same
@@ -578,61 +597,7 @@ __global__ __launch_bounds__(512) void k_chi0_split8(const us16 *__restrict__ Ap
         float2 bcur[8];
 #pragma unroll
         for (int e = 0; e < 8; e += 2) *(u32x4 *)&bcur[e] = *(const u32x4 *)&Bs[b][16 * wcg + col][8 * g + e];
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-          float wt8[8];
-          *(float4 *)&wt8[0] = *(const float4 *)&wtab[b][wf * NW + w][8 * g];
-          *(float4 *)&wt8[4] = *(const float4 *)&wtab[b][wf * NW + w][8 * g + 4];
-          u32x4 br[NS], bi[NS], nbi[NS];
-          if constexpr (H && NS == 2) {
-#pragma unroll
-            for (int e = 0; e < 8; e += 2) {
-              unsigned h, l;
-              split2_h_pair(wt8[e], bcur[e].x, wt8[e + 1], bcur[e + 1].x, h, l);
-              br[0][e / 2] = h;
-              br[1][e / 2] = l;
-              split2_h_pair(wt8[e], bcur[e].y, wt8[e + 1], bcur[e + 1].y, h, l);
-              bi[0][e / 2] = h;
-              bi[1][e / 2] = l;
-            }
-          } else {
-            us16 brs[NS][8], bis[NS][8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-              const float wt = wt8[e];
-              us16 pr_[NS], pi_[NS];
-              split_n<NS, H>(wt * bcur[e].x, pr_);
-              split_n<NS, H>(wt * bcur[e].y, pi_);
-#pragma unroll
-              for (int p = 0; p < NS; ++p) {
-                brs[p][e] = pr_[p];
-                bis[p][e] = pi_[p];
-              }
-            }
-#pragma unroll
-            for (int p = 0; p < NS; ++p) {
-              br[p] = *(const u32x4 *)brs[p];
-              bi[p] = *(const u32x4 *)bis[p];
-            }
-          }
-#pragma unroll
-          for (int p = 0; p < NS; ++p) nbi[p] = bi[p] ^ 0x80008000u;
-#pragma unroll
-          for (int si = 0; si < NSI; ++si) {
-#pragma unroll
-            for (int p = 0; p < NS; ++p) {
-              const u32x4 ar = *(const u32x4 *)&As[b][2 * p][16 * si + col][8 * g];
-              const u32x4 ai = *(const u32x4 *)&As[b][2 * p + 1][16 * si + col][8 * g];
-#pragma unroll
-              for (int q = 0; q + p < NS; ++q) {
-                re[w][si] = mfma_p<H>(ar, br[q], re[w][si]);
-                re[w][si] = mfma_p<H>(ai, bi[q], re[w][si]);
-                im[w][si] = mfma_p<H>(ai, br[q], im[w][si]);
-                im[w][si] = mfma_p<H>(ar, nbi[q], im[w][si]);
-              }
-            }
-          }
-        }
+        chi0_chunk<NS, NW, NSI, PAD, H>(bcur, &wtab[b][wf * NW][0], As[b], col, g, re, im);
         {
 #pragma unroll
           for (int m = 0; m < NS; ++m) *(u32x4 *)&As[b ^ 1][ap + 2 * m][arow][ak] = apre[m];
@@ -649,24 +614,7 @@ __global__ __launch_bounds__(512) void k_chi0_split8(const us16 *__restrict__ Ap
     else loop(IntC<1>());
   }
 store:
-#pragma unroll
-  for (int w = 0; w < NW; ++w) {
-    if (w0 + w >= n_freq) continue;
-    float2 *dst = part + (((long long)ks * n_freq + w0 + w) * ntile + tile) * (TILE * TILE);
-    const int cl = 16 * wcg + col;
-    const float fcol = H ? pow2_scale(__uint_as_float(amax[nu0 + cl < N ? nu0 + cl : 0])) / wsc[w] : 1.f;
-#pragma unroll
-    for (int si = 0; si < 4; ++si) {
-      if (16 * si >= N - mu0) break;
-      const f4v r = re[w][si], i = im[w][si];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int row = 16 * si + Mfma<float>::row(lane, q);
-        const float f = H ? fcol * pow2_scale(__uint_as_float(amax[mu0 + row < N ? mu0 + row : 0])) : 1.f;
-        dst[row * TILE + cl] = mkcf(r[q] * f, i[q] * f);
-      }
-    }
-  }
+  chi0_store<NW, H>(re, im, wsc, w0, n_freq, ks, ntile, tile, mu0, nu0, 16 * wcg + col, N, lane, amax, part);
 }
 
 // chi[w][mu][nu] = scale * sum_s part[s][w][tile][..] (accumulate: added to
