@@ -529,7 +529,7 @@ int lrigw_batch_destroy(lrigw_batch *b);
  * faster, so near-ties resolve the same way each time (the K split count
  * changes the order of the FP32 sums).
  * H, evec, eig as lrigw_g0w0.  Outputs (host, may be NULL): the chosen
- * response tiles, the self-energy variant (0..10) and the response time of one
+ * response tiles, the self-energy variant (0..13) and the response time of one
  * q (ms).
  * Synchronous. */
 int lrigw_tune(lrigw_ctx *ctx, const void *H, const void *evec, const double *eig, int *nw, int *splits,
@@ -542,10 +542,12 @@ int lrigw_tune(lrigw_ctx *ctx, const void *H, const void *evec, const double *ei
  * workgroup sums more than 4096 rows in FP32; splits beyond what the
  * context's partial-tile buffer of at most 3 GiB holds run in batches whose
  * results are added up in the output), pad = LDS row padding of the split-form response kernel (8
- * or 16), sigma_variant = split-form self-energy kernel variant (0..12; 7 to
- * 12, the resident-tile form with 8 or 4 waves and LDS rows padded by 8 or
- * 16, or (11, 12) the per-tile sum taking x from global memory, need the
- * two-part FP16 split, N_aux <= 288 and at most 32 frequencies).
+ * or 16), sigma_variant = split-form self-energy kernel variant (0..13; 7 to
+ * 13, the resident-tile form with 8 or 4 waves and LDS rows padded by 8 or
+ * 16, (11, 12) the per-tile sum taking x from global memory, or (13) 8 waves
+ * with the frequencies in four sets instead of eight, twice as many per
+ * workgroup, need the two-part FP16 split, N_aux <= 288 and at most 32
+ * frequencies).
  * Errors: ERR_ARG for a choice outside these sets or a variant the cell does
  * not admit. */
 int lrigw_set_tiles(lrigw_ctx *ctx, int nw, int splits, int pad, int sigma_variant);

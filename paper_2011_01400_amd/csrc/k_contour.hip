@@ -215,6 +215,7 @@ static int set_real_grid_broadened(lrigw_ctx *c, int n_r, double omega_max, doub
   if (!c->d_cdbad) LRIGW_HIP_TRY(hipMalloc(&c->d_cdbad, sizeof(int)));
   c->sig_res_nr = 0;   // the chunks take the imaginary planes' self-energy plans or the default form
   c->sig_res_Fr = 0;
+  c->sig_res_Fr4 = 0;
   c->n_real = n_r;
   c->real_h = h;
   c->real_eta = eta;

@@ -632,8 +632,11 @@ __global__ __launch_bounds__(256) void k_sigma_splitq(const us16 *__restrict__ x
 
 // Resident-tile form (two-part FP16 split, N_aux <= RES_NPAD): one workgroup of NWV
 // waves (8: two per SIMD; 4: one per SIMD with the whole register file) per
-// (64 columns, set of F <= RES_F frequencies), the set chosen by the XCD the
-// workgroup runs on.  The split x tile of its columns, every nu, is loaded into
+// (64 columns, set of F frequencies), the set chosen by the XCD the workgroup
+// runs on: with S = 8 sets (F <= RES_F) XCD x takes set x; with S = 4 sets and
+// eight waves (F <= 8, one wave per frequency at 32 frequencies) XCDs x and
+// x + 4 take set x mod 4 and alternate column blocks, so each x tile is loaded
+// by four workgroups instead of eight and serves twice the work.  The split x tile of its columns, every nu, is loaded into
 // LDS once; then NWV/F' waves (F' = F rounded up to 1, 2 or 4) share each
 // frequency, each working through its own list of 32-row tiles (a balanced
 // static assignment built on the host) with its W fragments read one chunk
@@ -652,15 +655,16 @@ template <int PAD, bool H, int NWV, bool GX = false>
 __global__ __launch_bounds__(64 * NWV) void k_sigma_res(const us16 *__restrict__ xs, const us16 *__restrict__ ws,
                                                    const float2 *__restrict__ x, const float2 *__restrict__ Wall,
                                                    long long Ccols, long long Cpad, int N, int Npad, int Rpad, int n_freq,
-                                                   int F, const int *__restrict__ items, const float *__restrict__ sx,
+                                                   int F, int S, const int *__restrict__ items, const float *__restrict__ sx,
                                                    const unsigned *__restrict__ wmax, double *__restrict__ Xall) {
   __shared__ __attribute__((aligned(16))) us16 Xs[4][TILE][RES_NPAD + PAD];   // [part*2 + re/im][column][nu]
-  const int fs = blockIdx.x & 7;
-  const long long c0 = (long long)(blockIdx.x >> 3) * TILE;
+  const int xcd = blockIdx.x & 7;
+  const int fs = xcd % S;
+  const long long c0 = ((long long)(blockIdx.x >> 3) * (8 / S) + xcd / S) * TILE;
   const int f0 = fs * F;
-  if (f0 >= n_freq) return;
+  if (f0 >= n_freq || c0 >= Ccols) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, g = lane >> 4;
-  const int fpad = F <= 1 ? 1 : F <= 2 ? 2 : 4;
+  const int fpad = F <= 1 ? 1 : F <= 2 ? 2 : F <= 4 ? 4 : 8;
   const int wpf = NWV / fpad;               // waves per frequency
   const int fl = wave / wpf;
   const int w = f0 + fl;
@@ -926,11 +930,11 @@ __global__ __launch_bounds__(256) void k_pair_diag(const float2 *__restrict__ x,
 // With eight waves, waves w and w + 4 share a SIMD (waves are placed on the
 // SIMDs in turn) and their MFMA pipe: the second four take the lists in the
 // opposite order, so that each SIMD runs a heavier and a lighter list.
-static bool sigma_res_plan(int N, int n_freq, int NWV, std::vector<int> &table, int &F) {
+static bool sigma_res_plan(int N, int n_freq, int NWV, int sets, std::vector<int> &table, int &F) {
   const int Npad = (N + SKB - 1) / SKB * SKB, Rpad = (N + TILE - 1) / TILE * TILE;
-  F = (n_freq + 7) / 8;
-  if (Npad > RES_NPAD || F > RES_F) return false;
-  const int fpad = F <= 1 ? 1 : F <= 2 ? 2 : 4;
+  F = (n_freq + sets - 1) / sets;
+  if (Npad > RES_NPAD || F > (sets == 8 ? RES_F : NWV)) return false;
+  const int fpad = F <= 1 ? 1 : F <= 2 ? 2 : F <= 4 ? 4 : 8;
   const int wpf = NWV / fpad;
   const int base = N - Rpad;
   std::vector<std::pair<int, int>> its;   // (cost, tile)
@@ -970,15 +974,20 @@ int sigma_res_prepare(lrigw_ctx *c) {
   // the epilogue takes x from the split tile: 22 significand bits with FP16
   // parts, too few with BF16 ones
   if (ns_sig(c->precision) != 2 || !split_h(c->precision)) return LRIGW_OK;
-  std::vector<int> t8, t4;
-  int F = 0;
+  std::vector<int> t8, t4, t84;
+  int F = 0, F4 = 0;
   if (c->d.n_freq > RES_WMAX) return LRIGW_OK;
-  if (!sigma_res_plan(c->d.n_aux, c->d.n_freq, 8, t8, F) || !sigma_res_plan(c->d.n_aux, c->d.n_freq, 4, t4, F)) return LRIGW_OK;
+  if (!sigma_res_plan(c->d.n_aux, c->d.n_freq, 8, 8, t8, F) || !sigma_res_plan(c->d.n_aux, c->d.n_freq, 4, 8, t4, F))
+    return LRIGW_OK;
+  if (!sigma_res_plan(c->d.n_aux, c->d.n_freq, 8, 4, t84, F4)) t84.assign(8 * (RES_MAXI + 1), 0), F4 = 0;
   LRIGW_HIP_TRY(hipMalloc(&c->d_wd, (size_t)c->d.n_aux * RES_WMAX * sizeof(double)));
-  t8.insert(t8.end(), t4.begin(), t4.end());   // the 8-wave lists, then the 4-wave ones
+  // the 8-wave lists, the 4-wave ones, then the 8-wave lists of four sets
+  t8.insert(t8.end(), t4.begin(), t4.end());
+  t8.insert(t8.end(), t84.begin(), t84.end());
   LRIGW_HIP_TRY(hipMalloc(&c->d_sitems, t8.size() * sizeof(int)));
   LRIGW_HIP_TRY(hipMemcpy(c->d_sitems, t8.data(), t8.size() * sizeof(int), hipMemcpyHostToDevice));
   c->sig_res_F = F;
+  c->sig_res_F4 = F4;
   c->sig_res_ok = true;
   return LRIGW_OK;
 }
@@ -988,13 +997,16 @@ int sigma_res_prepare(lrigw_ctx *c) {
 int sigma_res_prepare_real(lrigw_ctx *c, int n_r) {
   c->sig_res_nr = 0;
   if (!c->sig_res_ok || n_r > RES_WMAX) return LRIGW_OK;
-  std::vector<int> t8, t4;
-  int F = 0;
-  if (!sigma_res_plan(c->d.n_aux, n_r, 8, t8, F) || !sigma_res_plan(c->d.n_aux, n_r, 4, t4, F)) return LRIGW_OK;
+  std::vector<int> t8, t4, t84;
+  int F = 0, F4 = 0;
+  if (!sigma_res_plan(c->d.n_aux, n_r, 8, 8, t8, F) || !sigma_res_plan(c->d.n_aux, n_r, 4, 8, t4, F)) return LRIGW_OK;
+  if (!sigma_res_plan(c->d.n_aux, n_r, 8, 4, t84, F4)) t84.assign(8 * (RES_MAXI + 1), 0), F4 = 0;
   t8.insert(t8.end(), t4.begin(), t4.end());
+  t8.insert(t8.end(), t84.begin(), t84.end());
   if (!c->d_sitems_r) LRIGW_HIP_TRY(hipMalloc(&c->d_sitems_r, t8.size() * sizeof(int)));   // fixed size per cell
   LRIGW_HIP_TRY(hipMemcpy(c->d_sitems_r, t8.data(), t8.size() * sizeof(int), hipMemcpyHostToDevice));
   c->sig_res_Fr = F;
+  c->sig_res_Fr4 = F4;
   c->sig_res_nr = n_r;
   return LRIGW_OK;
 }
@@ -1075,13 +1087,13 @@ __global__ __launch_bounds__(64) void k_sigma_freq(const double *__restrict__ X,
 // and 4 waves per workgroup and LDS rows padded by 8 or 16 elements, 11/12 the
 // 8/4-wave forms whose per-tile sum reads x from global memory (two-part FP16
 // split, N_aux <= 288 only)
-#define SIGMA_VARIANTS 13
+#define SIGMA_VARIANTS 14
 int sigma_variant_snw(int var) { return var == 1 ? 2 : 1; }
 int sigma_variants() { return SIGMA_VARIANTS; }
 int sigma_default_variant(int precision) { return ns_sig(precision) == 2 ? 1 : 0; }
 bool sigma_variant_ok(const lrigw_ctx *c, int var) {
   if (var < 0 || var >= SIGMA_VARIANTS) return false;
-  return var < 7 || c->sig_res_ok;
+  return var < 7 || (c->sig_res_ok && (var != 13 || c->sig_res_F4 > 0));
 }
 
 template <int NS, bool H>
@@ -1145,9 +1157,11 @@ int run_pair_weights(lrigw_ctx *c, const void *x, const void *Wc, int nw, double
     // the resident-tile form has plans for the N_w imaginary planes and for
     // the real-axis grid; any other plane count takes the default split form
     const bool plan_w = nw == d.n_freq, plan_r = !plan_w && nw == c->sig_res_nr;
-    const int var = (c->sig_var >= 7 && !plan_w && !plan_r) ? sigma_default_variant(c->precision) : c->sig_var;
+    int var = (c->sig_var >= 7 && !plan_w && !plan_r) ? sigma_default_variant(c->precision) : c->sig_var;
     const int *items = plan_w ? c->d_sitems : c->d_sitems_r;
-    const int Fres = plan_w ? c->sig_res_F : c->sig_res_Fr;
+    int Fres = plan_w ? c->sig_res_F : c->sig_res_Fr;
+    const int F4 = plan_w ? c->sig_res_F4 : c->sig_res_Fr4;
+    if (var == 13 && F4 == 0) var = 7;   // no four-set plan for these planes
     if (var >= 7) {
       if (!c->sig_res_ok) return LRIGW_ERR_ARG;
       // the exact diagonal term first; the resident kernel adds the rest
@@ -1162,15 +1176,18 @@ int run_pair_weights(lrigw_ctx *c, const void *x, const void *Wc, int nw, double
     dim3 gs(xcd_grid((nw + snw - 1) / snw, ncb));
     if (var >= 7) {
       const dim3 gr((unsigned)(8 * ncb));
-      const int *t8 = items, *t4 = items + 8 * (RES_MAXI + 1);
-#define RES_ARGS xs, ws, xf, Wf, Ccols, Cpad, d.n_aux, Npad, Rpad, nw, Fres
+      const int *t8 = items, *t4 = items + 8 * (RES_MAXI + 1), *t84 = items + 12 * (RES_MAXI + 1);
+#define RES_ARGS xs, ws, xf, Wf, Ccols, Cpad, d.n_aux, Npad, Rpad, nw, Fres, 8
       if (var == 7) hipLaunchKernelGGL((k_sigma_res<8, true, 8>), gr, dim3(512), 0, c->stream, RES_ARGS, t8, c->d_sx, c->d_wmax, X);
       else if (var == 8) hipLaunchKernelGGL((k_sigma_res<8, true, 4>), gr, dim3(256), 0, c->stream, RES_ARGS, t4, c->d_sx, c->d_wmax, X);
       else if (var == 9) hipLaunchKernelGGL((k_sigma_res<16, true, 8>), gr, dim3(512), 0, c->stream, RES_ARGS, t8, c->d_sx, c->d_wmax, X);
       else if (var == 10) hipLaunchKernelGGL((k_sigma_res<16, true, 4>), gr, dim3(256), 0, c->stream, RES_ARGS, t4, c->d_sx, c->d_wmax, X);
       else if (var == 11) hipLaunchKernelGGL((k_sigma_res<8, true, 8, true>), gr, dim3(512), 0, c->stream, RES_ARGS, t8, c->d_sx, c->d_wmax, X);
-      else hipLaunchKernelGGL((k_sigma_res<8, true, 4, true>), gr, dim3(256), 0, c->stream, RES_ARGS, t4, c->d_sx, c->d_wmax, X);
+      else if (var == 12) hipLaunchKernelGGL((k_sigma_res<8, true, 4, true>), gr, dim3(256), 0, c->stream, RES_ARGS, t4, c->d_sx, c->d_wmax, X);
 #undef RES_ARGS
+      else
+        hipLaunchKernelGGL((k_sigma_res<8, true, 8>), dim3((unsigned)(8 * ((ncb + 1) / 2))), dim3(512), 0, c->stream, xs, ws,
+                           xf, Wf, Ccols, Cpad, d.n_aux, Npad, Rpad, nw, F4, 4, t84, c->d_sx, c->d_wmax, X);
     } else if (H)
       launch_sigma_split<2, true>(var, gs, c->stream, xs, ws, xf, Wf, Ccols, Cpad, d.n_aux, Npad, Rpad, nw, c->d_sx,
                                   c->d_wmax, X);

@@ -155,9 +155,11 @@ struct lrigw_ctx {
   void *d_sxa = nullptr;         // the same pairs in FP64 (reduced-precision forms)
   void *d_sxz = nullptr;         // V x of those pairs, FP64
   int sig_res_F = 0;             // resident-tile Sigma^c form: frequencies per workgroup
+  int sig_res_F4 = 0;            // the same with four frequency sets (eight waves; 0: no plan)
   bool sig_res_ok = false;       // resident-tile Sigma^c form applies to this cell
   int *d_sitems_r = nullptr;     // resident-tile form: item lists for the real-axis planes (contour deformation)
   int sig_res_Fr = 0, sig_res_nr = 0;   // their frequencies per workgroup and plane count (0: no plan)
+  int sig_res_Fr4 = 0;           // the same with four frequency sets
 
   // q = 0 data
   double2 *d_x1 = nullptr;       // [N_aux]

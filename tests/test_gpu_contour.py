@@ -142,11 +142,12 @@ def test_sigma_cd_per_q_and_pass(case, precision):
     assert e < tol
 
 
-@pytest.mark.parametrize("var", [7, 8, 9, 10])
+@pytest.mark.parametrize("var", [7, 8, 9, 10, 13])
 def test_sigma_cd_resident_variants(case, var):
     """The FP16 form's resident-tile self-energy kernel (8 and 4 waves per
-    workgroup) on both plane sets: the imaginary grid and the real grid, which
-    has item lists of its own."""
+    workgroup; 13: 8 waves with the frequencies in four sets) on both plane
+    sets: the imaginary grid and the real grid, which has item lists of its
+    own."""
     s, o, dev = case["sys"], case["o"], case["dev"]
     sp = s.spec
     ctx, H = _ctx(case, "split_f16")
