@@ -427,13 +427,15 @@ def qp_against_oracle(sysm, config, e_form, e_plain):
     if int(g["seed"]) != sysm.seed:
         return None
     E, Z = g["E"], g["Z"]
-    out = {"states": int(E.size)}
+    reg = (Z >= 0.5) & (Z <= 1.0)   # quasiparticle-like in the oracle's pass
+    out = {"states": int(E.size), "quasiparticle_like_states": int(reg.sum())}
     for name, e in (("form", e_form), ("plain_fp64", e_plain)):
         if e is None:
             continue
         d = np.abs(e - E) * HA_MEV
         out[name] = {"max_mev": round(float(d.max()), 4), "median_mev": round(float(np.median(d)), 5),
-                     "within_1_mev": bool(d.max() <= 1.0), "states_over_1_mev": int((d > 1.0).sum())}
+                     "within_1_mev": bool(d.max() <= 1.0), "states_over_1_mev": int((d > 1.0).sum()),
+                     "max_mev_quasiparticle_like": round(float(d[reg].max()), 4)}
     return out
 
 
