@@ -36,3 +36,25 @@ def test_binding_has_no_host_fallback():
     src = open(os.path.join(ROOT, "paper_2011_01400_amd", "lrigw.py")).read()
     assert "oracle" not in src
     assert "linalg" not in src
+
+
+def test_bench_runs_on_one_gpu_only():
+    """bench.py with more than one GPU exits with status 2 and says so in its
+    JSON line, before it touches a device."""
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    assert d["n_gpus"] == 2 and "one GPU" in d["error"]
+
+
+def test_calibration_program_built_beside_the_library():
+    """The build step also compiles the sustained matrix-core rate program that
+    bench.py runs after its timed steps."""
+    from paper_2011_01400_amd import build, lrigw as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("liblrigw.so not built (run __graft_entry__.build())")
+    assert os.path.isfile(build.RATE_BIN) and os.access(build.RATE_BIN, os.X_OK)
