@@ -110,9 +110,10 @@ class Run:
 
 
 def algorithmic_flops(sysm):
-    """Real flops of one launch of each MFMA kernel (one q, all frequencies):
+    """Real flops of each MFMA kernel stage for one q (all frequencies):
     chi0: 8 N_aux^2 K per (q, w) pair, K = N_k N_occ N_unocc (full Hermitian
-    count); Sigma^c: 8 N_aux^2 N_k N_qp N_bands per pair."""
+    count); Sigma^c: 8 N_aux^2 N_k N_qp N_bands per pair.  One q is one launch
+    unless its K splits run in batches (one launch per batch)."""
     sp = sysm.spec
     n_aux, n_k, nw = sysm.n_aux, sysm.n_k, sp.n_freq
     K = n_k * sp.n_occ * (sp.n_bands - sp.n_occ)
@@ -142,8 +143,10 @@ def traffic_for(kernel, precision, config):
     return r["bytes_per_launch"] if h == r["source_sha256_16"] else None
 
 
-def roofline(sysm, stages, precision, config):
-    """Dominant MFMA kernel: algorithmic flops per launch / average launch time."""
+def roofline(sysm, stages, precision, config, n_q):
+    """Dominant MFMA kernel: algorithmic flops per launch / average launch
+    time, over the n_q q of the recorded passes (flops per launch = their
+    flops over the launches, so K splits run in batches count right)."""
     flops = algorithmic_flops(sysm)
     best = None
     for name, f in flops.items():
@@ -153,12 +156,12 @@ def roofline(sysm, stages, precision, config):
         if best is None or ms > best[1]:
             best = (name, ms, n, f)
     name, ms, n, f = best
-    avg_s = ms / n / 1e3
-    achieved = f / avg_s / 1e12
+    fl = f * n_q / n
+    achieved = fl / (ms / n / 1e3) / 1e12
     peak = PEAK_TFLOPS[precision]
     return {"bound": "mfma", "kernel": name, "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": traffic_for(name, precision, config),
-            "avg_launch_ms": round(ms / n, 4), "flops_per_launch": f}
+            "avg_launch_ms": round(ms / n, 4), "launches_per_q": round(n / n_q, 3), "flops_per_launch": fl}
 
 
 def mfma_sustained():
@@ -183,7 +186,7 @@ def mfma_sustained():
     return d
 
 
-def other_kernel(sysm, stages, precision, rl):
+def other_kernel(sysm, stages, precision, rl, n_q):
     """The same figures for the other MFMA kernel."""
     flops = algorithmic_flops(sysm)
     out = {}
@@ -191,9 +194,9 @@ def other_kernel(sysm, stages, precision, rl):
         if name == rl["kernel"] or name not in stages:
             continue
         ms, n = stages[name]
-        a = f / (ms / n / 1e3) / 1e12
+        a = f * n_q / (ms / 1e3) / 1e12
         out[name] = {"achieved": round(a, 2), "peak": PEAK_TFLOPS[precision], "frac": round(a / PEAK_TFLOPS[precision], 4),
-                     "avg_launch_ms": round(ms / n, 4)}
+                     "avg_launch_ms": round(ms / n, 4), "launches_per_q": round(n / n_q, 3)}
     return out
 
 
@@ -696,14 +699,14 @@ def main():
                  "quasiparticle_like_states": f"{int(reg.sum())} of {reg.size} (0.5 <= Z <= 1 in the plain path)",
                  "within_1_mev_quasiparticle_like": bool(d[reg].max() <= 1.0),
                  "stages_ms_per_step": {k: round(v[0], 3) for k, v in pstages.items()},
-                 "roofline": roofline(sysm, pkern, "fp64", args.config)}
+                 "roofline": roofline(sysm, pkern, "fp64", args.config, sysm.n_k)}
         print(f"# bench: plain fp64 {plain['value']} pairs/s, QP diff {plain['qp_max_err_mev_quasiparticle_like']:.3f} meV "
               f"(quasiparticle-like), {plain['qp_max_err_mev_all_states']:.3f} meV (all)", file=sys.stderr, flush=True)
         prun.ctx.close()
         del prun
     oracle_qp = qp_against_oracle(sysm, args.config, e_form, e_plain if plain else None)
 
-    rl = roofline(sysm, kern, args.precision, args.config)
+    rl = roofline(sysm, kern, args.precision, args.config, args.steps * sysm.n_k)
     out = {
         "metric": "chi0+Sigma^c (q,w)-pairs/s", "value": round(value, 2), "unit": "(q,w)-pairs/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 3),
@@ -717,7 +720,7 @@ def main():
                    "precision_form": args.precision, "pairs_per_step": pairs},
         "stages_ms_per_step": {k: round(v[0], 3) for k, v in stages.items()},
         "roofline": rl,
-        "other_kernel": other_kernel(sysm, kern, args.precision, rl),
+        "other_kernel": other_kernel(sysm, kern, args.precision, rl, args.steps * sysm.n_k),
     }
     if tuned:
         out["tuned"] = tuned
