@@ -283,6 +283,7 @@ __global__ __launch_bounds__(256) void k_chi0_presplit(const float2 *__restrict_
 // runs a copy of the chunk loop without those blocks' products (their
 // partial-tile rows are never read).
 template <int V> struct IntC { static constexpr int value = V; };
+template <bool V> struct BoolC { static constexpr bool value = V; };
 
 // One K chunk of a wave's 64 x 16 strip for NW frequencies: the wave's 16
 // columns bcur (8 consecutive k per lane, FP32) are weighted by the rows wt0,
@@ -374,6 +375,49 @@ __device__ __forceinline__ void chi0_store(const f4v (&re)[NW][4], const f4v (&i
       }
     }
   }
+}
+
+// The same for a swapped tile: the wave holds P[r][c] = sum_k a_r conj(w b_c)
+// with r over 64 rows of column tile J (mu0 = J TILE) and c over the 16 rows
+// of the last tile row (nu0); the tile (I, J) of the partial buffer is
+// conj(P) transposed (the weight is real, so conj(P[r][c]) is the term of
+// row nu0 + c and column mu0 + r).
+template <int NW, bool H>
+__device__ __forceinline__ void chi0_store_swapped(const f4v (&re)[NW][4], const f4v (&im)[NW][4], const float (&wsc)[NW],
+                                                   int w0, int n_freq, int ks, long long ntile, int tile, int mu0,
+                                                   int nu0, int N, int lane, const unsigned *__restrict__ amax,
+                                                   float2 *__restrict__ part) {
+  const int c = lane & 15;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    if (w0 + w >= n_freq) continue;
+    float2 *dst = part + (((long long)ks * n_freq + w0 + w) * ntile + tile) * (TILE * TILE);
+    const float fc = H ? pow2_scale(__uint_as_float(amax[nu0 + c < N ? nu0 + c : 0])) / wsc[w] : 1.f;
+#pragma unroll
+    for (int si = 0; si < 4; ++si) {
+      if (16 * si >= N - mu0) break;
+      const f4v r = re[w][si], i = im[w][si];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = 16 * si + Mfma<float>::row(lane, q);
+        const float f = H ? fc * pow2_scale(__uint_as_float(amax[mu0 + row < N ? mu0 + row : 0])) : 1.f;
+        dst[c * TILE + row] = mkcf(r[q] * f, -i[q] * f);
+      }
+    }
+  }
+}
+
+// Work items of k_chi0_split8 over nt tile rows of N rows: (K split, tile,
+// four frequencies) for every tile, except that a last tile row of at most 16
+// rows is taken as (K split, column tile J, sixteen frequencies) with the roles
+// of rows and columns swapped: such a work item weights and splits the 16 rows
+// of the last tile row instead of the 64 columns of tile J.
+__host__ __device__ inline bool split8_swap(int N, int nt) { return N - (nt - 1) * TILE <= 16; }
+__host__ __device__ inline long long split8_items(int N, int nt, int n_freq, int nsplit) {
+  const long long ntile = (long long)nt * (nt + 1) / 2;
+  const bool sw = split8_swap(N, nt);
+  return (long long)((n_freq + 3) / 4) * (sw ? ntile - nt : ntile) * nsplit +
+         (sw ? (long long)((n_freq + 15) / 16) * nt * nsplit : 0);
 }
 
 template <int NS, int NW, int PAD, bool H>
@@ -499,7 +543,11 @@ store:
 // loaded once (by all 512 threads, into double-buffered LDS) for four
 // frequencies instead of two.  The B columns of a wave come from LDS in FP32
 // and are weighted and split per frequency in registers as in k_chi0_split.
-template <int NS, int PAD, bool H>
+// When the last tile row holds at most 16 rows, its tiles run swapped (see
+// split8_items): the eight waves take sixteen frequencies of the 16 weighted
+// rows against the 64 unweighted rows of tile J, in place of four frequencies
+// of 64 weighted columns against 16 or fewer rows.
+template <int NS, int PAD, bool H, bool SWK>
 __global__ __launch_bounds__(512) void k_chi0_split8(const us16 *__restrict__ Ap, const float2 *__restrict__ Bt,
                                                      const float *__restrict__ delta, const double *__restrict__ om2tab,
                                                      const double2 *__restrict__ cpltab, const float *__restrict__ wsctab,
@@ -507,26 +555,46 @@ __global__ __launch_bounds__(512) void k_chi0_split8(const us16 *__restrict__ Ap
                                                      long long Kp, int Npad, int n_freq, long long Ks, long long ntile,
                                                      const unsigned *__restrict__ amax, int N, float2 *__restrict__ part,
                                                      int nsplit) {
-  constexpr int NW = 2, NF = 4;
+  constexpr int NW = 2, NF = 4, NFS = 16;
   if (run && *run == 0) return;
   __shared__ __attribute__((aligned(16))) us16 As[2][NS * 2][TILE][KCB + PAD];
   __shared__ __attribute__((aligned(16))) float2 Bs[2][TILE][KCB + BBP];
-  __shared__ __attribute__((aligned(16))) float wtab[2][NF][KCB];
-  const int nfg = (n_freq + NF - 1) / NF;
-  const long long total = (long long)nfg * ntile * nsplit, per = (total + 7) / 8;
+  __shared__ __attribute__((aligned(16))) float wtab[2][SWK ? NFS : NF][KCB];
+  // the plain work items first, then those of a swapped last tile row (SWK:
+  // launched for the sizes that have one, split8_swap)
+  const int nt = Npad / TILE;
+  const bool sw = SWK;
+  const long long nplain = sw ? ntile - nt : ntile;
+  const int nfg = (n_freq + NF - 1) / NF, nfgs = (n_freq + NFS - 1) / NFS;
+  const long long tplain = (long long)nfg * nplain * nsplit;
+  const long long total = tplain + (sw ? (long long)nfgs * nt * nsplit : 0), per = (total + 7) / 8;
   const long long wi = (long long)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (wi >= total) return;
-  const int fgi = (int)(wi % nfg);
-  const int tile = (int)((wi / nfg) % ntile);
-  const int ks = (int)(wi / ((long long)nfg * ntile));
-  int I, J;
-  tri_decode(tile, I, J);
+  const bool swp = SWK && wi >= tplain;
+  int fgi, tile, ks, I, J;
+  if (!swp) {
+    fgi = (int)(wi % nfg);
+    tile = (int)((wi / nfg) % nplain);
+    ks = (int)(wi / ((long long)nfg * nplain));
+    tri_decode(tile, I, J);
+  } else {
+    const long long wj = wi - tplain;
+    fgi = (int)(wj % nfgs);
+    J = (int)((wj / nfgs) % nt);
+    ks = (int)(wj / ((long long)nfgs * nt));
+    I = nt - 1;
+    tile = I * (I + 1) / 2 + J;
+  }
   const long long kb = (long long)ks * Ks;
   const long long ke = min(K, kb + Ks);
-  const int mu0 = I * TILE, nu0 = J * TILE;
+  // rows mu0.. take the unweighted (A) side, columns nu0.. the weighted (B) side
+  const int mu0 = (swp ? J : I) * TILE, nu0 = (swp ? I : J) * TILE;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, g = lane >> 4;
-  const int wcg = wave & 3, wf = wave >> 2;
-  const int w0 = fgi * NF + wf * NW;
+  // plain: waves w and w + 4 share 16 columns (two frequencies each);
+  // swapped: all eight waves take the 16 columns, two frequencies each
+  const int nf = swp ? NFS : NF;
+  const int wcg = swp ? 0 : wave & 3, wf = swp ? wave : wave >> 2;
+  const int w0 = fgi * nf + wf * NW;
   const bool cplx = cpltab != nullptr;
   float om2[NW], wsc[NW];
 #pragma unroll
@@ -535,10 +603,10 @@ __global__ __launch_bounds__(512) void k_chi0_split8(const us16 *__restrict__ Ap
     om2[w] = in ? (float)om2tab[wsel[w0 + w]] : 0.f;
     wsc[w] = (H && in) ? wsctab[wsel[w0 + w]] : 1.f;
   }
-  // the weight table: thread t < NF * KCB owns frequency fgi * NF + t / KCB and row t % KCB
+  // the weight table: thread t < nf * KCB owns frequency fgi * nf + t / KCB and row t % KCB
   const int tw = tid / KCB, tk = tid % KCB;
-  const bool wown = tw < NF && fgi * NF + tw < n_freq;
-  const int fw_ = wown ? wsel[fgi * NF + tw] : 0;
+  const bool wown = tw < nf && fgi * nf + tw < n_freq;
+  const int fw_ = wown ? wsel[fgi * nf + tw] : 0;
   const float tom2 = wown ? (float)om2tab[fw_] : 0.f;
   const float twsc = (H && wown) ? wsctab[fw_] : 1.f;
   const double2 tcp = (cplx && wown) ? cpltab[fw_] : mkc(0.0, 0.0);
@@ -564,6 +632,7 @@ __global__ __launch_bounds__(512) void k_chi0_split8(const us16 *__restrict__ Ap
     // A staging: plane parity ap, row arow, 8-k piece ak; B staging: column bc, 4-k piece bk
     const int ap = tid >> 8, arow = (tid >> 2) & 63, ak = (tid & 3) * 8;
     const int bc = tid >> 3, bk = (tid & 7) * 4;
+    const bool bown = !swp || bc < 16;   // a swapped tile stages 16 columns (waves 0 and 1)
     const long long pstride = (long long)Npad * Kp;
     const us16 *asrc = Ap + (long long)ap * pstride + (long long)(mu0 + arow) * Kp + kb + ak;
     const float2 *bsrc = Bt + (long long)(nu0 + bc) * Kp + kb + bk;
@@ -571,25 +640,35 @@ __global__ __launch_bounds__(512) void k_chi0_split8(const us16 *__restrict__ Ap
     float dnext = 1.f;
 #pragma unroll
     for (int m = 0; m < NS; ++m) apre[m] = *(const u32x4 *)(asrc + 2 * m * pstride);
+    if (bown) {
 #pragma unroll
-    for (int e = 0; e < 2; ++e) bpre[e] = *(const u32x4 *)(bsrc + 2 * e);
-    if (tw < NF) wtab[0][tw][tk] = weight(dload(kb));
+      for (int e = 0; e < 2; ++e) bpre[e] = *(const u32x4 *)(bsrc + 2 * e);
+    }
+    if (tw < nf) wtab[0][tw][tk] = weight(dload(kb));
 #pragma unroll
     for (int m = 0; m < NS; ++m) *(u32x4 *)&As[0][ap + 2 * m][arow][ak] = apre[m];
+    if (bown) {
 #pragma unroll
-    for (int e = 0; e < 2; ++e) *(u32x4 *)&Bs[0][bc][bk + 2 * e] = bpre[e];
+      for (int e = 0; e < 2; ++e) *(u32x4 *)&Bs[0][bc][bk + 2 * e] = bpre[e];
+    }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    auto loop = [&](auto nsi_c) {
+    // the chunk loop, compiled apart for plain and swapped tiles
+    auto loop = [&](auto nsi_c, auto swp_c) {
       constexpr int NSI = decltype(nsi_c)::value;
+      constexpr bool SW = decltype(swp_c)::value;
+      const bool bo = !SW || bc < 16;
+      const bool wo = tw < (SW ? NFS : NF);
       for (int ch = 0; ch < nch; ++ch) {
         const int b = ch & 1;
         {
           const long long off = (long long)min(ch + 1, nch - 1) * KCB;
 #pragma unroll
           for (int m = 0; m < NS; ++m) apre[m] = *(const u32x4 *)(asrc + 2 * m * pstride + off);
+          if (bo) {
 #pragma unroll
-          for (int e = 0; e < 2; ++e) bpre[e] = *(const u32x4 *)(bsrc + off + 2 * e);
+            for (int e = 0; e < 2; ++e) bpre[e] = *(const u32x4 *)(bsrc + off + 2 * e);
+          }
           dnext = dload(kb + off);
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -601,20 +680,31 @@ __global__ __launch_bounds__(512) void k_chi0_split8(const us16 *__restrict__ Ap
         {
 #pragma unroll
           for (int m = 0; m < NS; ++m) *(u32x4 *)&As[b ^ 1][ap + 2 * m][arow][ak] = apre[m];
+          if (bo) {
 #pragma unroll
-          for (int e = 0; e < 2; ++e) *(u32x4 *)&Bs[b ^ 1][bc][bk + 2 * e] = bpre[e];
-          if (tw < NF) wtab[b ^ 1][tw][tk] = weight(dnext);
+            for (int e = 0; e < 2; ++e) *(u32x4 *)&Bs[b ^ 1][bc][bk + 2 * e] = bpre[e];
+          }
+          if (wo) wtab[b ^ 1][tw][tk] = weight(dnext);
         }
         __syncthreads();
       }
     };
     const int rem = N - mu0;
-    if (rem > 2 * 16) loop(IntC<4>());
-    else if (rem > 16) loop(IntC<2>());
-    else loop(IntC<1>());
+    if constexpr (SWK) {
+      if (swp) {
+        // rows of a column tile J < nt - 1 fill it; the corner tile has at most 16
+        if (rem > 16) loop(IntC<4>(), BoolC<true>());
+        else loop(IntC<1>(), BoolC<true>());
+        goto store;
+      }
+    }
+    if (rem > 2 * 16) loop(IntC<4>(), BoolC<false>());
+    else if (rem > 16) loop(IntC<2>(), BoolC<false>());
+    else loop(IntC<1>(), BoolC<false>());
   }
 store:
-  chi0_store<NW, H>(re, im, wsc, w0, n_freq, ks, ntile, tile, mu0, nu0, 16 * wcg + col, N, lane, amax, part);
+  if (SWK && swp) chi0_store_swapped<NW, H>(re, im, wsc, w0, n_freq, ks, ntile, tile, mu0, nu0, N, lane, amax, part);
+  else chi0_store<NW, H>(re, im, wsc, w0, n_freq, ks, ntile, tile, mu0, nu0, 16 * wcg + col, N, lane, amax, part);
 }
 
 // chi[w][mu][nu] = scale * sum_s part[s][w][tile][..] (accumulate: added to
@@ -856,13 +946,20 @@ int run_chi0_tab(lrigw_ctx *c, int iq, const void *M, const double *eig, int app
       const int NS = ns_chi(c->precision);
       const bool H = split_h(c->precision);
       // 1D over (K split, tile, frequency group), split over the XCDs
-      const long long sitems = (long long)((n_sel + NW - 1) / NW) * ntile * sb;
+      const long long sitems = NW == 4 ? split8_items(d.n_aux, nt, n_sel, sb) : (long long)((n_sel + NW - 1) / NW) * ntile * sb;
       const dim3 sgrid((unsigned)(8 * ((sitems + 7) / 8)));
 #define BF16_ARGS Apb, Btb, Db, om2t, cplt, wsct, wsel, run, Kb, Kp, Npad, n_sel, Ks, ntile, c->d_amax, d.n_aux, Pf, sb
+      const bool swk = split8_swap(d.n_aux, nt);
 #define SPLIT_LAUNCH(NS_, H_)                                                                                            \
   do {                                                                                                                 \
-    if (NW == 4 && p16) hipLaunchKernelGGL((k_chi0_split8<NS_, 16, H_>), sgrid, dim3(512), 0, c->stream, BF16_ARGS); \
-    else if (NW == 4) hipLaunchKernelGGL((k_chi0_split8<NS_, 8, H_>), sgrid, dim3(512), 0, c->stream, BF16_ARGS);   \
+    if (NW == 4 && swk && p16)                                                                                         \
+      hipLaunchKernelGGL((k_chi0_split8<NS_, 16, H_, true>), sgrid, dim3(512), 0, c->stream, BF16_ARGS);              \
+    else if (NW == 4 && swk)                                                                                           \
+      hipLaunchKernelGGL((k_chi0_split8<NS_, 8, H_, true>), sgrid, dim3(512), 0, c->stream, BF16_ARGS);               \
+    else if (NW == 4 && p16)                                                                                           \
+      hipLaunchKernelGGL((k_chi0_split8<NS_, 16, H_, false>), sgrid, dim3(512), 0, c->stream, BF16_ARGS);             \
+    else if (NW == 4)                                                                                                  \
+      hipLaunchKernelGGL((k_chi0_split8<NS_, 8, H_, false>), sgrid, dim3(512), 0, c->stream, BF16_ARGS);              \
     else if (p16) hipLaunchKernelGGL((k_chi0_split<NS_, 2, 16, H_>), sgrid, dim3(256), 0, c->stream, BF16_ARGS);      \
     else hipLaunchKernelGGL((k_chi0_split<NS_, 2, 8, H_>), sgrid, dim3(256), 0, c->stream, BF16_ARGS);                \
   } while (0)
