@@ -883,39 +883,49 @@ __global__ void k_wdiag(const float2 *__restrict__ W, int N, int n_freq, double 
 }
 // D[w][c] = sum_mu Re W^c_mumu(w) |x_mu(c)|^2 as an FP64 matrix product on the
 // 16x16x4 MFMA (A = W^c_mumu, 16 frequencies x 4 mu; B = |x|^2, 4 mu x 16
-// columns, so each output row is 16 consecutive columns): a wave takes 16
-// columns and all RES_WMAX frequencies (two accumulators); in the k-th product
-// of a 16-mu chunk, lane l holds mu = m0 + 4 (l / 16) + k for frequency l % 16
-// (A) and column l % 16 (B).  Entries past N or C load as zero.  No LDS, no
-// barrier: a wave past the last column leaves at once.
+// columns): a workgroup takes 64 columns, each wave 16 of them and all
+// RES_WMAX frequencies (two accumulators).  The x rows of the 64 columns are
+// read in 64-mu chunks, one row's chunk (512 contiguous bytes) per wave-wide
+// load, and |x|^2 (FP64) and the chunk's W^c diagonal go through LDS into
+// the operand layouts: in the j-th product of a chunk lane l holds
+// mu = m0 + 4 j + l / 16 for frequency l % 16 (A) and column l % 16 (B).
+// Entries past N or C are zero.
 static_assert(RES_WMAX == 32, "two 16-frequency accumulators");
 __global__ __launch_bounds__(256) void k_pair_diag(const float2 *__restrict__ x, long long C, int N, int n_freq,
                                                    const double *__restrict__ wd, double *__restrict__ Xall) {
-  const int lane = threadIdx.x & 63;
-  const long long cb = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
-  if (cb >= C) return;
-  const long long c = cb + (lane & 15);
-  const bool cok = c < C;
-  const int kq = 4 * (lane >> 4), wl = lane & 15;
+  __shared__ double a2s[64][64 + 1];          // [mu - m0][column - c0]
+  __shared__ double wds[64][RES_WMAX + 1];    // [mu - m0][frequency]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const long long c0 = (long long)blockIdx.x * 64;
   Mfma<double>::acc a0 = Mfma<double>::zero(), a1 = Mfma<double>::zero();
-  for (int m0 = 0; m0 < N; m0 += 16) {
-    float2 xv[4];
-    double w0[4], w1[4];
+  for (int m0 = 0; m0 < N; m0 += 64) {
+    const int mu = m0 + lane;
+    float2 v[16];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int mu = m0 + kq + k;
-      xv[k] = ld_or(x, c * N + mu, cok && mu < N, mkcf(0.f, 0.f));
-      w0[k] = ld_or(wd, (long long)mu * RES_WMAX + wl, mu < N, 0.0);
-      w1[k] = ld_or(wd, (long long)mu * RES_WMAX + 16 + wl, mu < N, 0.0);
+    for (int r = 0; r < 16; ++r) {
+      const long long cr = c0 + 16 * wave + r;
+      v[r] = ld_or(x, cr * N + mu, cr < C && mu < N, mkcf(0.f, 0.f));
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const double a2 = (double)xv[k].x * (double)xv[k].x + (double)xv[k].y * (double)xv[k].y;
-      a0 = Mfma<double>::mac(w0[k], a2, a0);
-      a1 = Mfma<double>::mac(w1[k], a2, a1);
+    for (int r = 0; r < 16; ++r) a2s[lane][16 * wave + r] = (double)v[r].x * (double)v[r].x + (double)v[r].y * (double)v[r].y;
+#pragma unroll
+    for (int i = 0; i < 64 * RES_WMAX / 256; ++i) {
+      const int e = tid + 256 * i, m = e / RES_WMAX, w = e % RES_WMAX;
+      wds[m][w] = ld_or(wd, (long long)(m0 + m) * RES_WMAX + w, m0 + m < N, 0.0);
     }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      if (m0 + 4 * j >= N) break;   // the rest of the chunk lies past N (same for the whole workgroup)
+      const int m = 4 * j + (lane >> 4);
+      const double b = a2s[m][16 * wave + (lane & 15)];
+      a0 = Mfma<double>::mac(wds[m][lane & 15], b, a0);
+      a1 = Mfma<double>::mac(wds[m][16 + (lane & 15)], b, a1);
+    }
+    __syncthreads();
   }
-  if (!cok) return;
+  const long long c = c0 + 16 * wave + (lane & 15);
+  if (c >= C) return;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int w = Mfma<double>::row(lane, r);
