@@ -233,42 +233,51 @@ __global__ __launch_bounds__(256) void k_absmax_rows(const float2 *__restrict__ 
   }
 }
 
-// 32 (k) x 32 (mu) tiles through LDS; block 32 x 8 threads.  FP16 parts (H)
-// and the FP32 copy Bt are taken of row mu times the power of two set by its
-// largest magnitude amax[mu].
+// 64 (k) x 32 (mu) tiles through LDS, 256 threads: the loads take 32
+// consecutive mu of a row of B per 32 lanes; the stores, two k per thread,
+// write 64 consecutive k of each mu row (512 bytes of Bt, 128 bytes of each
+// part plane).  FP16 parts (H) and the FP32 copy Bt are taken of row mu times
+// the power of two set by its largest magnitude amax[mu].  Columns k in
+// [K, Kp) are written as zeros; Kp is a multiple of 32, so the last tile
+// stops at Kp.
 template <int NS, bool H>
 __global__ __launch_bounds__(256) void k_chi0_presplit(const float2 *__restrict__ B, long long K, int N, long long Kp,
                                                        int Npad, const unsigned *__restrict__ amax, us16 *__restrict__ Ap,
                                                        float2 *__restrict__ Bt) {
-  __shared__ float2 t[32][33];
-  const long long k0 = (long long)blockIdx.x * 32;
+  __shared__ float2 t[64][33];
+  const long long k0 = (long long)blockIdx.x * 64;
   const int m0 = blockIdx.y * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < 8; ++i) {
     const int kk = ty + 8 * i;
-    const float2 v = ld_or(B, (k0 + kk) * N + m0 + tx, k0 + kk < K && m0 + tx < N, mkcf(0.f, 0.f));
-    t[kk][tx] = v;
+    t[kk][tx] = ld_or(B, (k0 + kk) * N + m0 + tx, k0 + kk < K && m0 + tx < N, mkcf(0.f, 0.f));
   }
   __syncthreads();
+  const long long k = k0 + 2 * tx;
+  if (k >= Kp) return;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int mm = ty + 8 * i;
-    float2 v = t[tx][mm];
+  for (int j = 0; j < 4; ++j) {
+    const int mm = ty + 8 * j;
+    float2 v0 = t[2 * tx][mm], v1 = t[2 * tx + 1][mm];
     if (H) {
       const float inv = m0 + mm < N ? inv_pow2_scale(__uint_as_float(amax[m0 + mm])) : 1.f;
-      v.x *= inv;
-      v.y *= inv;
+      v0.x *= inv;
+      v0.y *= inv;
+      v1.x *= inv;
+      v1.y *= inv;
     }
-    const long long o = (long long)(m0 + mm) * Kp + k0 + tx;
-    Bt[o] = v;
-    us16 a[NS], b[NS];
-    split_n<NS, H>(v.x, a);
-    split_n<NS, H>(v.y, b);
+    const long long o = (long long)(m0 + mm) * Kp + k;   // even: 16-byte aligned in Bt, 4-byte in Ap
+    *(float4 *)&Bt[o] = make_float4(v0.x, v0.y, v1.x, v1.y);
+    us16 a0[NS], b0[NS], a1[NS], b1[NS];
+    split_n<NS, H>(v0.x, a0);
+    split_n<NS, H>(v0.y, b0);
+    split_n<NS, H>(v1.x, a1);
+    split_n<NS, H>(v1.y, b1);
 #pragma unroll
     for (int p = 0; p < NS; ++p) {
-      Ap[(long long)(2 * p) * Npad * Kp + o] = a[p];
-      Ap[(long long)(2 * p + 1) * Npad * Kp + o] = b[p];
+      *(unsigned *)&Ap[(long long)(2 * p) * Npad * Kp + o] = (unsigned)a0[p] | ((unsigned)a1[p] << 16);
+      *(unsigned *)&Ap[(long long)(2 * p + 1) * Npad * Kp + o] = (unsigned)b0[p] | ((unsigned)b1[p] << 16);
     }
   }
 }
@@ -897,7 +906,7 @@ int run_chi0_tab(lrigw_ctx *c, int iq, const void *M, const double *eig, int app
     const float2 *Bf = (const float2 *)B;
     us16 *Apd = (us16 *)c->d_ap;
     float2 *Btd = (float2 *)c->d_bt;
-    dim3 pg((unsigned)(Kp / 32), (unsigned)(Npad / 32));
+    dim3 pg((unsigned)((Kp + 63) / 64), (unsigned)(Npad / 32));
     const int NS = ns_chi(c->precision);
     const bool H = split_h(c->precision);
     if (H) {
